@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Throughput of separable W-projection gridding + degridding on one MI355X.
+
+Workload (the array-scale configuration): 4096^2 grid, 3 deg field, 64
+antennas in an 8 km disc, dec -30 deg, 8 h earth-rotation track in 10 s dumps,
+16 channels -> 92,897,280 visibilities; 128 w-planes over +/- max|w|,
+support 15, oversample 8, PSWF taper, complex Gaussian V, unit weights; all
+synthetic and seeded, resident in HBM before the timed region.
+
+One step is the whole hot path over that batch, through the C ABI:
+  1. table generation for the batch's w range       (sepw_kernels_set_wrange)
+  2. quantise + w-plane + tile counting sort        (sepw_plan_rebin)
+  3. gridding -> FFT -> grid correction (x n)        (sepw_grid, SEPW_MUL_N)
+  4. model image correction (/ n) -> FFT -> degrid   (sepw_degrid, SEPW_DIV_N)
+value = visibilities / step time (Mvis/s, gridded + degridded).
+
+Per-stage times come from HIP events the library records on its launch stream
+(sepw_timing_*); the roofline entry is for the dominant kernel.  The CPU
+baseline times the FP64 NumPy oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mvis/s gridded+degridded (FP32 vs FP16-MFMA at stated RMS err); % roofline"
+PEAK_FP32_MFMA_TFLOPS = 157.3      # MI355X dense FP32 matrix peak
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(d, n_sample):
+    """Oracle (FP64 NumPy, one thread) on the first n_sample visibilities:
+    quantise + tables + grid + F+ / correction + correction / F- + degrid."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    N, fov, S, O, P = d["N"], d["fov"], d["S"], d["O"], d["P"]
+    sl = slice(0, n_sample)
+    u, v, w = d["u"][sl], d["v"][sl], d["w"][sl]
+    y = d["V"][sl].astype(np.complex128) * d["W"][sl]
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        c1 = oracle.pswf.taper_c1(N, fov, S)
+        T = oracle.tables.separable_table(oracle.tables.w_plane_centres(P, d["w_lo"], d["w_hi"]),
+                                          N, fov, S, O, c1)
+        q = oracle.quantise.quantise(u, v, w, N, fov, O, S, P, d["w_lo"], d["w_hi"], 17 - S)
+        G = oracle.gridder.grid_separable(q, y, T, N, S)
+        img = oracle.imaging.image_from_grid(G, c1, fov, n_power=1)
+        Gh = oracle.imaging.grid_from_image(X, c1, fov, n_power=-1)
+        Vp = oracle.gridder.degrid_separable(q, Gh, T, N, S)
+        t1 = time.perf_counter()
+    del img, Vp
+    secs = t1 - t0
+    return {"value": round(n_sample / secs / 1e6, 4), "unit": "Mvis/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d visibilities of the workload (of %d); quantise + tables + grid + "
+                      "F+/correction + correction/F- + degrid, FP64 NumPy, %.1f s"
+                      % (n_sample, len(d["u"]), secs, ),
+            "seconds": round(secs, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--dump-s", type=float, default=10.0, help="dump time (10 s: 92.9M vis)")
+    ap.add_argument("--cpu-sample", type=int, default=400_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1511_07152_amd import _lib, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    _lib.load()
+
+    t = time.perf_counter()
+    d = synth.array_4096(dump_s=args.dump_s)
+    nvis = len(d["u"])
+    log("generated %d visibilities in %.1f s" % (nvis, time.perf_counter() - t))
+    N, fov, S, O, P = d["N"], d["fov"], d["S"], d["O"], d["P"]
+
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)  # noqa: E731
+    u, v, w = dev(d["u"], torch.float64), dev(d["v"], torch.float64), dev(d["w"], torch.float64)
+    V, W = dev(d["V"], torch.complex64), dev(d["W"], torch.float32)
+    g = torch.Generator(device="cuda").manual_seed(1511)
+    model = torch.randn((N, N), dtype=torch.complex64, device="cuda", generator=g)
+    img = torch.empty((N, N), dtype=torch.complex64, device="cuda")
+    vis_out = torch.empty(nvis, dtype=torch.complex64, device="cuda")
+
+    K = _lib.Kernels(N, fov, S, O, P, d["w_lo"], d["w_hi"])
+    plan = _lib.Plan(K, u, v, w)
+    n_dropped = plan.n_dropped
+    log("plan: %d kept, %d dropped, tile %d" % (nvis - n_dropped, n_dropped, plan.tile_size))
+
+    def step():
+        K.set_wrange(d["w_lo"], d["w_hi"])
+        plan.rebin(u, v, w)
+        _lib.grid(plan, V, W, flags=_lib.MUL_N, out=img)
+        _lib.degrid(plan, model, flags=_lib.DIV_N, out=vis_out)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log("warmup step %d done" % i)
+
+    _lib.timing_enable(True)
+    _lib.timing_collect()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _lib.timing_enable(False)
+    stages = _lib.timing_collect()
+    log("timed %d steps in %.3f s" % (args.steps, t1 - t0))
+
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    kept = nvis - n_dropped
+    value = nvis / (ms_per_step * 1e-3) / 1e6
+
+    per_launch = {k: (ms / n if n else 0.0) for k, (ms, n) in stages.items()}
+    flops = {"grid": kept * (8 * S * S + 6 * S + 2), "degrid": kept * (8 * S * S + 8 * S)}
+    dom = max(("grid", "degrid"), key=lambda k: per_launch[k])
+    achieved = flops[dom] / (per_launch[dom] * 1e-3) / 1e12
+    roofline = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 2),
+                "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+                "avg_ms": round(per_launch[dom], 4)}
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mvis/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": "array-scale separable W-projection: 4096^2 grid, 3 deg, 64 antennas "
+                               "8 km, 8 h, %g s dumps, 16 ch, 128 w-planes, S=15, O=8" % args.dump_s,
+                   "nvis": nvis, "kept": kept, "grid": N, "support": S, "oversample": O,
+                   "w_planes": P, "precision": "fp32"},
+        "roofline": roofline,
+        "stages_ms_per_step": {k: round(ms / args.steps, 4) for k, (ms, n) in stages.items()},
+    }
+    if not args.no_cpu_baseline:
+        del u, v, w
+        t = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(d, min(args.cpu_sample, nvis))
+        log("cpu baseline in %.1f s" % (time.perf_counter() - t))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,216 @@
+/*
+ * sepw.h -- separable W-projection gridding and degridding on MI355X (gfx950).
+ *
+ * C ABI of the hot path of Merry (2015), "Approximating W projection as a
+ * separable kernel" (arXiv:1511.07152):
+ *
+ *   sepw_make_kernels  oversampled 1D GCF tables per w-plane (Section 3, the
+ *                      separable screen g1_w and g~_w = g1_w(l) g1_w(m);
+ *                      Section 2, oversampled lookup tables and the
+ *                      anti-aliasing taper c; Section 4.1, facet tables)
+ *   sepw_plan_create   uv -> grid cell and 1/O sub-cell offset, w -> plane,
+ *                      counting sort of visibilities into grid tiles
+ *   sepw_grid          visibilities -> uv grid -> dirty image (Section 2,
+ *                      dirty-image equation and its W-projection form;
+ *                      Section 5, separable update with the row product reused)
+ *   sepw_degrid        model image -> uv grid -> visibilities (Section 2,
+ *                      prediction equation; Section 6, prediction for major
+ *                      cycles)
+ *   sepw_grid_batched  many facet/snapshot jobs in one persistent launch
+ *                      (Section 4.1 faceting, Section 4.2 snapshots)
+ *
+ * Conventions (the paper leaves these open; the library fixes them):
+ *   N     grid and image size, even.           fov  full image width in
+ *   S     GCF support in cells, odd, 1..15.         direction cosines [rad].
+ *   O     oversampling factor, power of two, 1..128.
+ *   P     number of w-planes, 1..65535, uniform on [w_lo, w_hi]; plane k
+ *         stands for w_k = w_lo + (k + 1/2)(w_hi - w_lo)/P; a visibility goes
+ *         to plane clamp(floor((w - w_lo) P / (w_hi - w_lo)), 0, P-1).
+ *   Pixel p is at l_p = (p - N/2) fov / N; grid cell j is at u_j = (j - N/2)/fov.
+ *   Images and grids are N*N row-major complex64, rows along m (v).
+ *   Grid -> image is the centred, unnormalised DFT with sign +, matching the
+ *   dirty-image equation; image -> grid is its conjugate transpose.
+ *   uv rounding: nearest 1/O cell, ties upwards; a visibility whose S x S
+ *   footprint leaves the grid, or whose u, v or w is not finite, is skipped and
+ *   counted as dropped (never wrapped).
+ *
+ * Memory and streams: every vis / weight / image / grid pointer is a DEVICE
+ * pointer owned by the caller; tables, plans and scratch are owned by the
+ * library.  Every call is asynchronous on the given HIP stream (NULL = the
+ * default stream) unless stated; a kernel failure surfaces as SEPW_ERR_HIP at
+ * a later call.  A plan or kernels object must not be used by two calls that
+ * overlap in time (its scratch and FFT plan are shared).
+ *
+ * Errors: every call returns SEPW_OK or a negative code; no exception crosses
+ * the ABI.  Arguments are validated on the host before any device work, so a
+ * rejected call has no side effect.
+ */
+#ifndef SEPW_H
+#define SEPW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } sepw_c64;
+typedef struct sepw_kernels_s* sepw_kernels;   /* tables + taper + FFT plan   */
+typedef struct sepw_plan_s*    sepw_plan;       /* binned uvw for one kernels  */
+
+enum {
+  SEPW_OK = 0,
+  SEPW_ERR_ARG = -1,          /* invalid argument (checked before device work) */
+  SEPW_ERR_NO_DEVICE = -2,    /* no HIP device visible                         */
+  SEPW_ERR_HIP = -3,          /* a HIP runtime or kernel error                 */
+  SEPW_ERR_OOM = -4,          /* device allocation failed                      */
+  SEPW_ERR_UNSUPPORTED = -5,  /* valid but not implemented (e.g. S > 15)       */
+  SEPW_ERR_FFT = -6           /* hipFFT failure                                */
+};
+
+enum { SEPW_TAPER_PSWF = 0, SEPW_TAPER_NONE = 1, SEPW_TAPER_USER = 2 };
+enum { SEPW_FP32 = 0, SEPW_FP16 = 1, SEPW_BF16 = 2 };
+
+/* Flags for sepw_grid / sepw_degrid / sepw_grid_batched. */
+#define SEPW_GRID_ONLY 0x1u  /* grid: output the uv grid (no FFT, no correction).
+                                degrid: the input is a uv grid.                  */
+#define SEPW_MUL_N     0x2u  /* grid: dirty image I_D = n F+[G] / (c1 c1).       */
+#define SEPW_DIV_N     0x4u  /* grid: F+[G] / (n c1 c1), the exact adjoint of
+                                degrid with SEPW_DIV_N.
+                                degrid: X = image / n before the FFT, i.e. the
+                                prediction equation for a model image I.        */
+
+/* Kernel (GCF table) parameters.  Fill with sepw_default_params first. */
+typedef struct {
+  int32_t grid_size;       /* N                                                  */
+  int32_t support;         /* S                                                  */
+  int32_t oversample;      /* O                                                  */
+  int32_t n_planes;        /* P                                                  */
+  double  fov;             /* field of view [rad]                                */
+  double  w_lo, w_hi;      /* w-plane range [wavelengths], w_lo < w_hi           */
+  int32_t taper;           /* SEPW_TAPER_*                                       */
+  int32_t precision;       /* SEPW_FP32 (FP16/BF16 select the MFMA form)         */
+  double  taper_width;     /* PSWF: width W in cells, c = pi W / 2; <= 0 means S */
+  const double* taper_samples; /* SEPW_TAPER_USER: N host doubles c1(l_p) > 0    */
+  double  a_u, b_u;        /* u-axis screen exp(-2 pi i w (a l^2 + b l^4))        */
+  double  a_v, b_v;        /* v-axis screen; defaults 1/2 and gamma = 5/24       */
+  int32_t facet;           /* nonzero: image-plane facet at (l0, m0), Section 4.1;
+                              a_u, a_v, b_u, b_v are then derived and ignored    */
+  int32_t reserved;
+  double  l0, m0;          /* facet centre (direction cosines)                   */
+} sepw_kernel_params;
+
+/* Defaults: taper PSWF of width S, a = 1/2, b = 5/24 (Section 3's minimax
+   gamma), FP32, no facet.  Geometry fields are zeroed and must be set. */
+void sepw_default_params(sepw_kernel_params* p);
+
+/* Build the GCF tables on the device (FP64 phase and sums, stored complex64):
+ *   T[k][fi][s] = (1/N) sum_{p<N} c1(l_p) exp(-2 pi i w_k (a l_p^2 + b l_p^4))
+ *                       * exp(-2 pi i (s - S/2 - (fi - O/2)/O)(p - N/2)/N)
+ * for the u axis (a_u, b_u) and, if different, the v axis (a_v, b_v).  With
+ * facet != 0 the axis coefficients are 1/2 (1/n0 + l0^2/n0^3) and
+ * 1/2 (1/n0 + m0^2/n0^3) with b = 0 (Section 4.1).  c1 is the zeroth prolate
+ * spheroidal wave function psi_0(pi W / 2, 2 l / fov), normalised to c1(0) = 1.
+ * Synchronises the stream once (host set-up of the taper coefficients).
+ * Errors: SEPW_ERR_ARG for any out-of-range field, SEPW_ERR_NO_DEVICE,
+ * SEPW_ERR_OOM, SEPW_ERR_HIP, SEPW_ERR_FFT.  *out is NULL on error. */
+int sepw_make_kernels(const sepw_kernel_params* params, void* hip_stream, sepw_kernels* out);
+
+/* Copy a table (axis 0 = u, 1 = v) into a device buffer of P*O*S complex64,
+   layout [k][fi][s]; or the taper c1(l_p) into a device buffer of N doubles. */
+int sepw_kernels_table(sepw_kernels k, int32_t axis, sepw_c64* out, void* hip_stream);
+int sepw_kernels_taper(sepw_kernels k, double* out, void* hip_stream);
+
+/* Quantise and bin nvis visibilities (u, v, w: DEVICE float64 arrays in
+ * wavelengths, caller order).  In facet mode u, v are shifted by -w l0/n0,
+ * -w m0/n0 (Section 4.1) and the per-visibility phase rotation
+ * exp(+2 pi i (u l0 + v m0 + w (n0 - 1))) is stored in the plan.
+ * The plan keeps its own binned copy; u, v, w may be freed afterwards.
+ * n_dropped: optional HOST pointer; if given the call synchronises the stream
+ * and stores the number of skipped visibilities.  nvis may be 0.
+ * Errors: SEPW_ERR_ARG (null kernels, nvis < 0 or > 2^31-2, null arrays with
+ * nvis > 0), SEPW_ERR_OOM, SEPW_ERR_HIP. */
+int sepw_plan_create(sepw_kernels k, int64_t nvis, const double* u, const double* v,
+                     const double* w, int64_t* n_dropped, void* hip_stream, sepw_plan* out);
+
+/* Re-bin a new batch of nvis <= (nvis at creation) visibilities into an
+ * existing plan without any allocation (the per-batch form of plan creation;
+ * also required after sepw_kernels_set_wrange).  Same inputs and n_dropped
+ * semantics as sepw_plan_create.  Errors: SEPW_ERR_ARG (null plan, nvis out of
+ * range, null arrays with nvis > 0), SEPW_ERR_HIP. */
+int sepw_plan_rebin(sepw_plan p, int64_t nvis, const double* u, const double* v, const double* w,
+                    int64_t* n_dropped, void* hip_stream);
+
+/* Per-visibility bins in caller order, for verification: out is a DEVICE
+   int32 array [nvis][7] = (cell_u, fi_u, cell_v, fi_v, plane, tile, dropped);
+   tile = (cell_v / c) * ceil(N / c) + cell_u / c with c = sepw_plan_tile_size;
+   dropped rows are (0, 0, 0, 0, 0, -1, 1). */
+int sepw_plan_bins(sepw_plan p, int32_t* out, void* hip_stream);
+int32_t sepw_plan_tile_size(sepw_plan p);
+
+/* Grid weighted visibilities: G = sum_i W_i V_i Tu[k_i][fi_u][.] (x) Tv[k_i][fi_v][.]
+ * placed at cells cell - S/2 .. cell + S/2 (Section 5's separable update).
+ * vis: DEVICE complex64[nvis]; weight: DEVICE float[nvis] or NULL (all 1);
+ * out: DEVICE complex64[N*N], overwritten.  Without SEPW_GRID_ONLY the output is
+ * the image F+[G] / (c1 c1), times n (SEPW_MUL_N) or over n (SEPW_DIV_N).
+ * Errors: SEPW_ERR_ARG (null pointers, both MUL_N and DIV_N), SEPW_ERR_HIP,
+ * SEPW_ERR_FFT. */
+int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* out,
+              uint32_t flags, void* hip_stream);
+
+/* Degrid: V_i = sum_t conj(Tv[..][t]) sum_s conj(Tu[..][s]) Ghat[cv-S/2+t][cu-S/2+s],
+ * the adjoint of sepw_grid.  Without SEPW_GRID_ONLY, Ghat = F-[X / (c1 c1)] with
+ * X = image (or image / n with SEPW_DIV_N).  in: DEVICE complex64[N*N] (not
+ * modified); vis_out: DEVICE complex64[nvis], dropped visibilities get 0.
+ * Errors: as sepw_grid (SEPW_MUL_N is rejected). */
+int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t flags,
+                void* hip_stream);
+
+/* Grid njobs independent jobs (facets or snapshots, each with its own kernels
+ * and plan, all with the same N, S and precision) in ONE persistent launch
+ * that walks a combined work list ordered by descending cost; then one
+ * batched FFT and correction.  Arrays are host arrays of njobs entries
+ * holding device pointers; weights may be NULL (or hold NULLs).  Same flags
+ * and output as sepw_grid, per job.
+ * Errors: SEPW_ERR_ARG (njobs < 1, mismatched N/S/precision, nulls),
+ * SEPW_ERR_OOM, SEPW_ERR_HIP, SEPW_ERR_FFT. */
+int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* const* vis,
+                      const float* const* weight, sepw_c64* const* out, uint32_t flags,
+                      void* hip_stream);
+
+/* Regenerate the tables of k for a new w range (same P), asynchronously on
+ * the stream: the per-batch form of table generation when the w-planes span
+ * the batch's own +/- max|w|.  Plans created for the old range become invalid:
+ * sepw_grid / sepw_degrid on them return SEPW_ERR_ARG.
+ * Errors: SEPW_ERR_ARG (null k, non-finite or empty range), SEPW_ERR_HIP. */
+int sepw_kernels_set_wrange(sepw_kernels k, double w_lo, double w_hi, void* hip_stream);
+
+/* Optional per-stage timing for benchmarking: while enabled, every kernel the
+ * library launches is bracketed by HIP events recorded on its launch stream.
+ * sepw_timing_collect waits for the recorded events, adds their durations per
+ * stage into ms[SEPW_NSTAGES] and launch counts into n[SEPW_NSTAGES] (both
+ * host arrays, zeroed first), and forgets them. */
+enum {
+  SEPW_STAGE_TABLES = 0,   /* GCF table generation                  */
+  SEPW_STAGE_QUANTISE,     /* quantise + histogram                  */
+  SEPW_STAGE_SORT,         /* scans + scatter + work items          */
+  SEPW_STAGE_GATHER,       /* W V (and facet rotation) to bin order */
+  SEPW_STAGE_GRID,         /* gridding kernel                       */
+  SEPW_STAGE_FFT,          /* hipFFT (both directions)              */
+  SEPW_STAGE_CORRECT,      /* taper / n correction, both directions */
+  SEPW_STAGE_DEGRID,       /* degridding kernel                     */
+  SEPW_STAGE_FILL,         /* zero fills of outputs                 */
+  SEPW_NSTAGES
+};
+int sepw_timing_enable(int32_t on);
+int sepw_timing_collect(double* ms, int64_t* n);
+
+int sepw_free_kernels(sepw_kernels k);
+int sepw_free_plan(sepw_plan p);
+const char* sepw_strerror(int code);
+int32_t sepw_device_count(void);   /* 0 when no HIP device is visible */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEPW_H */

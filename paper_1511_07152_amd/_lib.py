@@ -1,0 +1,296 @@
+"""ctypes binding of libsepw.so (include/sepw.h).
+
+Argument marshalling only: torch tensors supply device memory and the current
+HIP stream; every step of the computation runs in the library's kernels.  The
+library is loaded from this package directory and must have been built
+(``python -m paper_1511_07152_amd.build``); a missing library raises.
+"""
+import ctypes
+import os
+
+import torch  # noqa: F401  (load torch's HIP runtime before the library binds to it)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsepw.so")
+
+OK, ERR_ARG, ERR_NO_DEVICE, ERR_HIP, ERR_OOM, ERR_UNSUPPORTED, ERR_FFT = 0, -1, -2, -3, -4, -5, -6
+TAPER_PSWF, TAPER_NONE, TAPER_USER = 0, 1, 2
+FP32, FP16, BF16 = 0, 1, 2
+GRID_ONLY, MUL_N, DIV_N = 0x1, 0x2, 0x4
+
+c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class KernelParams(ctypes.Structure):
+    _fields_ = [
+        ("grid_size", c_int32), ("support", c_int32), ("oversample", c_int32), ("n_planes", c_int32),
+        ("fov", c_double), ("w_lo", c_double), ("w_hi", c_double),
+        ("taper", c_int32), ("precision", c_int32), ("taper_width", c_double),
+        ("taper_samples", ctypes.POINTER(c_double)),
+        ("a_u", c_double), ("b_u", c_double), ("a_v", c_double), ("b_v", c_double),
+        ("facet", c_int32), ("reserved", c_int32), ("l0", c_double), ("m0", c_double),
+    ]
+
+
+class SepwError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (what, _strerror(code), code))
+
+
+_lib = None
+
+
+def load():
+    """Load libsepw.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libsepw.so is not built (%s); run python -m paper_1511_07152_amd.build"
+                           % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    lib.sepw_default_params.argtypes = [P(KernelParams)]
+    lib.sepw_default_params.restype = None
+    lib.sepw_make_kernels.argtypes = [P(KernelParams), c_void_p, P(c_void_p)]
+    lib.sepw_kernels_table.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
+    lib.sepw_kernels_taper.argtypes = [c_void_p, c_void_p, c_void_p]
+    lib.sepw_plan_create.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, c_void_p,
+                                     P(c_int64), c_void_p, P(c_void_p)]
+    lib.sepw_plan_bins.argtypes = [c_void_p, c_void_p, c_void_p]
+    lib.sepw_plan_rebin.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, P(c_int64),
+                                    c_void_p]
+    lib.sepw_kernels_set_wrange.argtypes = [c_void_p, c_double, c_double, c_void_p]
+    lib.sepw_timing_enable.argtypes = [c_int32]
+    lib.sepw_timing_collect.argtypes = [P(c_double), P(c_int64)]
+    lib.sepw_plan_tile_size.argtypes = [c_void_p]
+    lib.sepw_grid.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_uint32, c_void_p]
+    lib.sepw_degrid.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.c_uint32, c_void_p]
+    lib.sepw_grid_batched.argtypes = [c_int32, P(c_void_p), P(c_void_p), P(c_void_p), P(c_void_p),
+                                      ctypes.c_uint32, c_void_p]
+    lib.sepw_free_kernels.argtypes = [c_void_p]
+    lib.sepw_free_plan.argtypes = [c_void_p]
+    lib.sepw_strerror.argtypes = [ctypes.c_int]
+    lib.sepw_strerror.restype = ctypes.c_char_p
+    lib.sepw_device_count.argtypes = []
+    for name in ("sepw_make_kernels", "sepw_kernels_table", "sepw_kernels_taper", "sepw_plan_create",
+                 "sepw_plan_bins", "sepw_plan_tile_size", "sepw_grid", "sepw_degrid",
+                 "sepw_grid_batched", "sepw_free_kernels", "sepw_free_plan", "sepw_device_count",
+                 "sepw_plan_rebin", "sepw_kernels_set_wrange", "sepw_timing_enable",
+                 "sepw_timing_collect"):
+        getattr(lib, name).restype = c_int32
+    _lib = lib
+    return lib
+
+
+def _strerror(code):
+    try:
+        return load().sepw_strerror(code).decode()
+    except Exception:  # pragma: no cover
+        return "error"
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise SepwError(rc, what)
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr()) if t is not None else c_void_p(0)
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) torch tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    return t.contiguous()
+
+
+class Kernels:
+    """GCF tables, taper and FFT plan on the current device (sepw_make_kernels)."""
+
+    def __init__(self, N, fov, S, O, P, w_lo, w_hi, taper="pswf", taper_width=0.0,
+                 taper_samples=None, a=0.5, b=5.0 / 24.0, a_v=None, b_v=None, facet=None,
+                 precision="fp32"):
+        lib = load()
+        prm = KernelParams()
+        lib.sepw_default_params(ctypes.byref(prm))
+        prm.grid_size, prm.support, prm.oversample, prm.n_planes = int(N), int(S), int(O), int(P)
+        prm.fov, prm.w_lo, prm.w_hi = float(fov), float(w_lo), float(w_hi)
+        prm.taper = {"pswf": TAPER_PSWF, "none": TAPER_NONE, "user": TAPER_USER}[taper]
+        prm.taper_width = float(taper_width)
+        self._samples = None
+        if taper == "user":
+            import numpy as np
+            self._samples = np.ascontiguousarray(taper_samples, dtype=np.float64)
+            prm.taper_samples = self._samples.ctypes.data_as(ctypes.POINTER(c_double))
+        prm.a_u, prm.b_u = float(a), float(b)
+        prm.a_v = float(a if a_v is None else a_v)
+        prm.b_v = float(b if b_v is None else b_v)
+        if facet is not None:
+            prm.facet, prm.l0, prm.m0 = 1, float(facet[0]), float(facet[1])
+        prm.precision = {"fp32": FP32, "fp16": FP16, "bf16": BF16}[precision]
+        self.N, self.S, self.O, self.P, self.fov = int(N), int(S), int(O), int(P), float(fov)
+        self.precision = precision
+        h = c_void_p()
+        _check(lib.sepw_make_kernels(ctypes.byref(prm), _stream(), ctypes.byref(h)), "sepw_make_kernels")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def table(self, axis=0):
+        out = torch.empty((self.P, self.O, self.S), dtype=torch.complex64, device="cuda")
+        _check(load().sepw_kernels_table(self._h, axis, _ptr(out), _stream()), "sepw_kernels_table")
+        return out
+
+    def set_wrange(self, w_lo, w_hi):
+        """sepw_kernels_set_wrange: regenerate the tables for a new w range."""
+        _check(load().sepw_kernels_set_wrange(self._h, float(w_lo), float(w_hi), _stream()),
+               "sepw_kernels_set_wrange")
+
+    def taper(self):
+        out = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        _check(load().sepw_kernels_taper(self._h, _ptr(out), _stream()), "sepw_kernels_taper")
+        return out
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            load().sepw_free_kernels(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Binned visibilities for one Kernels object (sepw_plan_create)."""
+
+    def __init__(self, kernels, u, v, w, count_dropped=True):
+        lib = load()
+        u = _dev(u, torch.float64, "u")
+        v = _dev(v, torch.float64, "v")
+        w = _dev(w, torch.float64, "w")
+        if not (u.numel() == v.numel() == w.numel()):
+            raise ValueError("u, v, w must have the same length")
+        self.kernels = kernels
+        self.nvis = u.numel()
+        nd = c_int64(-1)
+        h = c_void_p()
+        _check(lib.sepw_plan_create(kernels.handle, self.nvis, _ptr(u), _ptr(v), _ptr(w),
+                                    ctypes.byref(nd) if count_dropped else None, _stream(),
+                                    ctypes.byref(h)), "sepw_plan_create")
+        self._h = h
+        self.n_dropped = nd.value if count_dropped else None
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def tile_size(self):
+        return load().sepw_plan_tile_size(self._h)
+
+    def rebin(self, u, v, w, count_dropped=False):
+        """sepw_plan_rebin: bin a new batch (no allocation)."""
+        u = _dev(u, torch.float64, "u")
+        v = _dev(v, torch.float64, "v")
+        w = _dev(w, torch.float64, "w")
+        nd = c_int64(-1)
+        _check(load().sepw_plan_rebin(self._h, u.numel(), _ptr(u), _ptr(v), _ptr(w),
+                                      ctypes.byref(nd) if count_dropped else None, _stream()),
+               "sepw_plan_rebin")
+        self.nvis = u.numel()
+        if count_dropped:
+            self.n_dropped = nd.value
+        return self
+
+    def bins(self):
+        out = torch.empty((self.nvis, 7), dtype=torch.int32, device="cuda")
+        _check(load().sepw_plan_bins(self._h, _ptr(out), _stream()), "sepw_plan_bins")
+        return out
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            load().sepw_free_plan(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+STAGES = ("tables", "quantise", "sort", "gather", "grid", "fft", "correct", "degrid", "fill")
+
+
+def timing_enable(on=True):
+    _check(load().sepw_timing_enable(1 if on else 0), "sepw_timing_enable")
+
+
+def timing_collect():
+    """{stage: (total ms, launches)} for everything recorded since the last collect."""
+    ms = (c_double * len(STAGES))()
+    n = (c_int64 * len(STAGES))()
+    _check(load().sepw_timing_collect(ms, n), "sepw_timing_collect")
+    return {name: (ms[i], n[i]) for i, name in enumerate(STAGES)}
+
+
+def make_kernels(*args, **kwargs):
+    return Kernels(*args, **kwargs)
+
+
+def plan_create(kernels, u, v, w):
+    return Plan(kernels, u, v, w)
+
+
+def grid(plan, vis, weight=None, flags=0, out=None):
+    """sepw_grid: complex64 N x N uv grid (GRID_ONLY) or image."""
+    vis = _dev(vis, torch.complex64, "vis")
+    if weight is not None:
+        weight = _dev(weight, torch.float32, "weight")
+    N = plan.kernels.N
+    if out is None:
+        out = torch.empty((N, N), dtype=torch.complex64, device="cuda")
+    _check(load().sepw_grid(plan.handle, _ptr(vis), _ptr(weight), _ptr(out), flags, _stream()),
+           "sepw_grid")
+    return out
+
+
+def degrid(plan, image, flags=0, out=None):
+    """sepw_degrid: complex64 visibilities in the caller's order."""
+    image = _dev(image, torch.complex64, "image")
+    if out is None:
+        out = torch.empty(plan.nvis, dtype=torch.complex64, device="cuda")
+    _check(load().sepw_degrid(plan.handle, _ptr(image), _ptr(out), flags, _stream()), "sepw_degrid")
+    return out
+
+
+def grid_batched(plans, vis, weights=None, flags=0, outs=None):
+    """sepw_grid_batched over several (facet / snapshot) plans."""
+    n = len(plans)
+    vis = [_dev(x, torch.complex64, "vis") for x in vis]
+    if weights is None:
+        weights = [None] * n
+    weights = [None if x is None else _dev(x, torch.float32, "weight") for x in weights]
+    if outs is None:
+        outs = [torch.empty((p.kernels.N, p.kernels.N), dtype=torch.complex64, device="cuda")
+                for p in plans]
+    arr = c_void_p * n
+    hp = arr(*[p.handle for p in plans])
+    vp = arr(*[x.data_ptr() for x in vis])
+    wp = arr(*[0 if x is None else x.data_ptr() for x in weights])
+    op = arr(*[x.data_ptr() for x in outs])
+    _check(load().sepw_grid_batched(n, hp, vp, wp, op, flags, _stream()), "sepw_grid_batched")
+    return outs

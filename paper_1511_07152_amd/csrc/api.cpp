@@ -1,0 +1,575 @@
+// C ABI of the separable W-projection library (include/sepw.h).
+//
+// Host-side orchestration only: argument validation (always before any device
+// work), allocation of tables and plans, and the launch sequence of the
+// kernels in tables.hip, binning.hip, grid.hip, degrid.hip and correct.hip.
+// The FFT between grid and image is a hipFFT library call.
+#pragma clang fp contract(off)
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+using namespace sepw;
+
+struct sepw_kernels_s : Kernels {};
+struct sepw_plan_s : Plan {};
+
+namespace {
+
+int map_hip(hipError_t e) {
+  if (e == hipSuccess) return SEPW_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SEPW_ERR_OOM;
+  if (e == hipErrorNoDevice || e == hipErrorInvalidDevice) return SEPW_ERR_NO_DEVICE;
+  return SEPW_ERR_HIP;
+}
+
+#define SEPW_TRY(expr)                  \
+  do {                                  \
+    hipError_t e_ = (expr);             \
+    if (e_ != hipSuccess) return map_hip(e_); \
+  } while (0)
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// ---- optional per-stage timing (benchmarking aid) ----
+struct TimingRec {
+  int stage;
+  hipEvent_t a, b;
+};
+std::mutex g_tmx;
+bool g_timing = false;
+std::vector<TimingRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t pool_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one stage's launches on stream s with HIP events when timing is on.
+class Stage {
+ public:
+  Stage(int stage, hipStream_t s) : stage_(stage), s_(s) {
+    std::lock_guard<std::mutex> lk(g_tmx);
+    if (!g_timing) return;
+    a_ = pool_event();
+    b_ = pool_event();
+    if (a_ && b_) hipEventRecord(a_, s_);
+  }
+  ~Stage() {
+    std::lock_guard<std::mutex> lk(g_tmx);
+    if (!a_ || !b_) return;
+    hipEventRecord(b_, s_);
+    g_recs.push_back({stage_, a_, b_});
+  }
+
+ private:
+  int stage_;
+  hipStream_t s_;
+  hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
+int device_count() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+  return n;
+}
+
+template <typename T>
+hipError_t dalloc(T** p, int64_t n) {
+  if (n < 1) n = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)n);
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+int validate_params(const sepw_kernel_params* p) {
+  if (!p) return SEPW_ERR_ARG;
+  if (p->grid_size < 2 || p->grid_size % 2 != 0 || p->grid_size > 32768) return SEPW_ERR_ARG;
+  if (p->support < 1 || p->support % 2 == 0 || p->support > p->grid_size - 1) return SEPW_ERR_ARG;
+  if (!is_pow2(p->oversample) || p->oversample > 128) return SEPW_ERR_ARG;
+  if (p->n_planes < 1 || p->n_planes > 65535) return SEPW_ERR_ARG;
+  if (!std::isfinite(p->fov) || p->fov <= 0.0 || p->fov >= std::sqrt(2.0)) return SEPW_ERR_ARG;
+  if (!std::isfinite(p->w_lo) || !std::isfinite(p->w_hi) || !(p->w_lo < p->w_hi)) return SEPW_ERR_ARG;
+  if (p->taper < SEPW_TAPER_PSWF || p->taper > SEPW_TAPER_USER) return SEPW_ERR_ARG;
+  if (p->taper == SEPW_TAPER_PSWF && !std::isfinite(p->taper_width)) return SEPW_ERR_ARG;
+  if (p->taper == SEPW_TAPER_USER) {
+    if (!p->taper_samples) return SEPW_ERR_ARG;
+    for (int i = 0; i < p->grid_size; ++i)
+      if (!std::isfinite(p->taper_samples[i]) || p->taper_samples[i] <= 0.0) return SEPW_ERR_ARG;
+  }
+  if (p->precision < SEPW_FP32 || p->precision > SEPW_BF16) return SEPW_ERR_ARG;
+  if (p->facet) {
+    if (!std::isfinite(p->l0) || !std::isfinite(p->m0)) return SEPW_ERR_ARG;
+    if (p->l0 * p->l0 + p->m0 * p->m0 >= 1.0) return SEPW_ERR_ARG;
+  } else {
+    if (!std::isfinite(p->a_u) || !std::isfinite(p->b_u) || !std::isfinite(p->a_v) ||
+        !std::isfinite(p->b_v))
+      return SEPW_ERR_ARG;
+  }
+  if (p->support > kMaxSupport) return SEPW_ERR_UNSUPPORTED;
+  if (p->precision != SEPW_FP32) return SEPW_ERR_UNSUPPORTED;
+  return SEPW_OK;
+}
+
+void destroy_kernels(Kernels* k) {
+  if (!k) return;
+  if (k->tab_v && k->tab_v != k->tab_u) dfree(k->tab_v);
+  k->tab_v = nullptr;
+  dfree(k->tab_u);
+  dfree(k->c1);
+  dfree(k->scratch);
+  if (k->fft_ok) hipfftDestroy(k->fft);
+  delete static_cast<sepw_kernels_s*>(k);
+}
+
+void destroy_plan(Plan* p) {
+  if (!p) return;
+  dfree(p->key);
+  dfree(p->qrec);
+  dfree(p->counts);
+  dfree(p->off);
+  dfree(p->cursor);
+  dfree(p->rec);
+  dfree(p->perm);
+  dfree(p->rot);
+  dfree(p->ybin);
+  dfree(p->nit);
+  dfree(p->itoff);
+  dfree(p->items);
+  dfree(p->scan_tmp);
+  delete static_cast<sepw_plan_s*>(p);
+}
+
+QuantGeom make_geom(const Kernels* K, int tile_c, int ntx) {
+  QuantGeom g;
+  g.fov = K->fov;
+  g.half_n = (double)(K->N / 2);
+  g.over = (double)K->O;
+  g.w_lo = K->w_lo;
+  g.inv_dw = K->inv_dw;
+  g.N = K->N;
+  g.S = K->S;
+  g.O = K->O;
+  g.P = K->P;
+  g.tile_c = tile_c;
+  g.ntx = ntx;
+  g.facet = K->facet ? 1 : 0;
+  g.l0 = K->l0;
+  g.m0 = K->m0;
+  g.n0 = K->n0;
+  return g;
+}
+
+int fft_exec(Kernels* K, float2* data, int direction, hipStream_t s) {
+  if (hipfftSetStream(K->fft, s) != HIPFFT_SUCCESS) return SEPW_ERR_FFT;
+  if (hipfftExecC2C(K->fft, reinterpret_cast<hipfftComplex*>(data),
+                    reinterpret_cast<hipfftComplex*>(data), direction) != HIPFFT_SUCCESS)
+    return SEPW_ERR_FFT;
+  return SEPW_OK;
+}
+
+hipError_t make_tables(Kernels* K, hipStream_t s) {
+  Stage st(SEPW_STAGE_TABLES, s);
+  hipError_t e = launch_tables(K->c1, K->N, K->fov, K->P, K->O, K->S, K->w_lo, K->w_hi, K->a_u,
+                               K->b_u, K->tab_u, s);
+  if (e == hipSuccess && K->tab_v != K->tab_u)
+    e = launch_tables(K->c1, K->N, K->fov, K->P, K->O, K->S, K->w_lo, K->w_hi, K->a_v, K->b_v,
+                      K->tab_v, s);
+  return e;
+}
+
+int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K) {
+  K->prm = *p;
+  K->prm.taper_samples = nullptr;
+  K->N = p->grid_size;
+  K->S = p->support;
+  K->O = p->oversample;
+  K->P = p->n_planes;
+  K->fov = p->fov;
+  K->w_lo = p->w_lo;
+  K->w_hi = p->w_hi;
+  K->inv_dw = (double)p->n_planes / (p->w_hi - p->w_lo);
+  K->facet = p->facet != 0;
+  K->l0 = K->facet ? p->l0 : 0.0;
+  K->m0 = K->facet ? p->m0 : 0.0;
+  K->n0 = std::sqrt(1.0 - K->l0 * K->l0 - K->m0 * K->m0);
+  if (K->facet) {
+    // Section 4.1: second-order Taylor terms of h(l0 + l) about the facet centre
+    const double n0 = K->n0, n03 = n0 * n0 * n0;
+    K->a_u = 0.5 * (1.0 / n0 + K->l0 * K->l0 / n03);
+    K->a_v = 0.5 * (1.0 / n0 + K->m0 * K->m0 / n03);
+    K->b_u = K->b_v = 0.0;
+  } else {
+    K->a_u = p->a_u;
+    K->b_u = p->b_u;
+    K->a_v = p->a_v;
+    K->b_v = p->b_v;
+  }
+  K->taper_width = p->taper_width > 0.0 ? p->taper_width : (double)p->support;
+
+  const int N = K->N;
+  SEPW_TRY(dalloc(&K->c1, N));
+  if (p->taper == SEPW_TAPER_NONE) {
+    SEPW_TRY(launch_ones(K->c1, N, s));
+  } else if (p->taper == SEPW_TAPER_USER) {
+    SEPW_TRY(hipMemcpyAsync(K->c1, p->taper_samples, sizeof(double) * N, hipMemcpyHostToDevice, s));
+    SEPW_TRY(hipStreamSynchronize(s));
+  } else {
+    const int max_terms = 4096;
+    std::vector<double> coef(max_terms);
+    double psi0 = 0.0;
+    const double c = M_PI * K->taper_width / 2.0;
+    int m = pswf_coefficients(c, coef.data(), max_terms, &psi0);
+    double* dcoef = nullptr;
+    SEPW_TRY(dalloc(&dcoef, m));
+    hipError_t e = hipMemcpyAsync(dcoef, coef.data(), sizeof(double) * m, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_taper(dcoef, m, psi0, N, K->c1, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dcoef);
+    SEPW_TRY(e);
+  }
+  const int64_t ntab = (int64_t)K->P * K->O * K->S;
+  SEPW_TRY(dalloc(&K->tab_u, ntab));
+  if (K->a_v == K->a_u && K->b_v == K->b_u) {
+    K->tab_v = K->tab_u;
+  } else {
+    SEPW_TRY(dalloc(&K->tab_v, ntab));
+  }
+  SEPW_TRY(make_tables(K, s));
+  SEPW_TRY(dalloc(&K->scratch, (int64_t)N * N));
+  if (hipfftPlan2d(&K->fft, N, N, HIPFFT_C2C) != HIPFFT_SUCCESS) return SEPW_ERR_FFT;
+  K->fft_ok = true;
+  return SEPW_OK;
+}
+
+int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
+  P->K = K;
+  P->capacity = capacity;
+  P->tile_c = kRegion + 1 - K->S;
+  P->ntx = (K->N + P->tile_c - 1) / P->tile_c;
+  P->nty = P->ntx;
+  P->ntiles = (int64_t)P->ntx * P->nty;
+  const int64_t nt = P->ntiles;
+  const int64_t occupied = capacity < nt ? capacity : nt;
+  P->max_items = occupied + capacity / kItemMaxVis + 1;
+  P->scan_tmp_len = scan_tmp_size(nt + 1);
+  SEPW_TRY(dalloc(&P->key, capacity));
+  SEPW_TRY(dalloc(&P->qrec, capacity));
+  SEPW_TRY(dalloc(&P->counts, nt + 1));
+  SEPW_TRY(dalloc(&P->off, nt + 1));
+  SEPW_TRY(dalloc(&P->cursor, nt + 1));
+  SEPW_TRY(dalloc(&P->rec, capacity));
+  SEPW_TRY(dalloc(&P->perm, capacity));
+  SEPW_TRY(dalloc(&P->ybin, capacity));
+  SEPW_TRY(dalloc(&P->nit, nt + 1));
+  SEPW_TRY(dalloc(&P->itoff, nt + 1));
+  SEPW_TRY(dalloc(&P->items, P->max_items));
+  SEPW_TRY(dalloc(&P->scan_tmp, P->scan_tmp_len));
+  if (K->facet) SEPW_TRY(dalloc(&P->rot, capacity));
+  return SEPW_OK;
+}
+
+// Quantise, sort and build the work list for nvis <= capacity visibilities.
+int bin_plan(Plan* P, int64_t nvis, const double* u, const double* v, const double* w,
+             hipStream_t s) {
+  Kernels* K = P->K;
+  P->nvis = nvis;
+  const int64_t nt = P->ntiles;
+  const QuantGeom g = make_geom(K, P->tile_c, P->ntx);
+  P->generation = K->generation;
+  {
+    Stage st(SEPW_STAGE_QUANTISE, s);
+    SEPW_TRY(launch_fill_u32(P->counts, 0u, nt + 1, s));
+    SEPW_TRY(launch_quantise(u, v, w, nvis, g, P->key, P->qrec, P->counts, s));
+  }
+  {
+    Stage st(SEPW_STAGE_SORT, s);
+    SEPW_TRY(launch_scan(P->counts, P->off, nt + 1, P->scan_tmp, s));
+    SEPW_TRY(hipMemcpyAsync(P->cursor, P->off, sizeof(uint32_t) * (size_t)(nt + 1),
+                            hipMemcpyDeviceToDevice, s));
+    SEPW_TRY(launch_scatter(P->key, P->qrec, nvis, P->cursor, P->rec, P->perm, s));
+    SEPW_TRY(launch_item_counts(P->off, nt, P->nit, s));
+    SEPW_TRY(launch_scan(P->nit, P->itoff, nt + 1, P->scan_tmp, s));
+    SEPW_TRY(launch_items(P->off, P->itoff, nt, P->items, s));
+    if (K->facet) SEPW_TRY(launch_rotation(u, v, w, P->perm, P->off + nt, nvis, g, P->rot, s));
+  }
+  return SEPW_OK;
+}
+
+int read_dropped(Plan* P, int64_t* n_dropped, hipStream_t s) {
+  uint32_t kept = 0;
+  hipError_t e = hipMemcpyAsync(&kept, P->off + P->ntiles, sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return map_hip(e);
+  *n_dropped = P->nvis - (int64_t)kept;
+  return SEPW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sepw_default_params(sepw_kernel_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->taper = SEPW_TAPER_PSWF;
+  p->precision = SEPW_FP32;
+  p->taper_width = 0.0;
+  p->a_u = p->a_v = 0.5;
+  p->b_u = p->b_v = 5.0 / 24.0;
+}
+
+int32_t sepw_device_count(void) { return device_count(); }
+
+const char* sepw_strerror(int code) {
+  switch (code) {
+    case SEPW_OK: return "success";
+    case SEPW_ERR_ARG: return "invalid argument";
+    case SEPW_ERR_NO_DEVICE: return "no HIP device";
+    case SEPW_ERR_HIP: return "HIP runtime or kernel error";
+    case SEPW_ERR_OOM: return "device out of memory";
+    case SEPW_ERR_UNSUPPORTED: return "unsupported parameter combination";
+    case SEPW_ERR_FFT: return "hipFFT error";
+    default: return "unknown error";
+  }
+}
+
+int sepw_make_kernels(const sepw_kernel_params* params, void* hip_stream, sepw_kernels* out) {
+  if (!out) return SEPW_ERR_ARG;
+  *out = nullptr;
+  int rc = validate_params(params);
+  if (rc != SEPW_OK) return rc;
+  if (device_count() < 1) return SEPW_ERR_NO_DEVICE;
+  sepw_kernels_s* K = new (std::nothrow) sepw_kernels_s();
+  if (!K) return SEPW_ERR_OOM;
+  rc = build_kernels(params, static_cast<hipStream_t>(hip_stream), K);
+  if (rc != SEPW_OK) {
+    destroy_kernels(K);
+    return rc;
+  }
+  *out = K;
+  return SEPW_OK;
+}
+
+int sepw_kernels_table(sepw_kernels k, int32_t axis, sepw_c64* out, void* hip_stream) {
+  if (!k || !out || (axis != 0 && axis != 1)) return SEPW_ERR_ARG;
+  const size_t n = (size_t)k->P * k->O * k->S;
+  SEPW_TRY(hipMemcpyAsync(out, axis == 0 ? k->tab_u : k->tab_v, sizeof(float2) * n,
+                          hipMemcpyDeviceToDevice, static_cast<hipStream_t>(hip_stream)));
+  return SEPW_OK;
+}
+
+int sepw_kernels_taper(sepw_kernels k, double* out, void* hip_stream) {
+  if (!k || !out) return SEPW_ERR_ARG;
+  SEPW_TRY(hipMemcpyAsync(out, k->c1, sizeof(double) * (size_t)k->N, hipMemcpyDeviceToDevice,
+                          static_cast<hipStream_t>(hip_stream)));
+  return SEPW_OK;
+}
+
+int sepw_plan_create(sepw_kernels k, int64_t nvis, const double* u, const double* v,
+                     const double* w, int64_t* n_dropped, void* hip_stream, sepw_plan* out) {
+  if (!out) return SEPW_ERR_ARG;
+  *out = nullptr;
+  if (!k || nvis < 0 || nvis > 2147483646LL) return SEPW_ERR_ARG;
+  if (nvis > 0 && (!u || !v || !w)) return SEPW_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  sepw_plan_s* P = new (std::nothrow) sepw_plan_s();
+  if (!P) return SEPW_ERR_OOM;
+  int rc = alloc_plan(k, nvis, P);
+  if (rc == SEPW_OK) rc = bin_plan(P, nvis, u, v, w, s);
+  if (rc == SEPW_OK && n_dropped) rc = read_dropped(P, n_dropped, s);
+  if (rc != SEPW_OK) {
+    destroy_plan(P);
+    return rc;
+  }
+  *out = P;
+  return SEPW_OK;
+}
+
+int sepw_plan_rebin(sepw_plan p, int64_t nvis, const double* u, const double* v, const double* w,
+                    int64_t* n_dropped, void* hip_stream) {
+  if (!p || nvis < 0 || nvis > p->capacity) return SEPW_ERR_ARG;
+  if (nvis > 0 && (!u || !v || !w)) return SEPW_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  int rc = bin_plan(p, nvis, u, v, w, s);
+  if (rc == SEPW_OK && n_dropped) rc = read_dropped(p, n_dropped, s);
+  return rc;
+}
+
+int32_t sepw_plan_tile_size(sepw_plan p) { return p ? p->tile_c : 0; }
+
+int sepw_plan_bins(sepw_plan p, int32_t* out, void* hip_stream) {
+  if (!p || (!out && p->nvis > 0)) return SEPW_ERR_ARG;
+  SEPW_TRY(launch_bins_export(p->rec, p->perm, p->off + p->ntiles, p->nvis, p->tile_c, p->ntx, out,
+                              static_cast<hipStream_t>(hip_stream)));
+  return SEPW_OK;
+}
+
+int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* out,
+              uint32_t flags, void* hip_stream) {
+  if (!p || !out || (!vis && p->nvis > 0)) return SEPW_ERR_ARG;
+  if ((flags & ~(SEPW_GRID_ONLY | SEPW_MUL_N | SEPW_DIV_N)) != 0) return SEPW_ERR_ARG;
+  if ((flags & SEPW_MUL_N) && (flags & SEPW_DIV_N)) return SEPW_ERR_ARG;
+  Kernels* K = p->K;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  float2* img = reinterpret_cast<float2*>(out);
+  const int N = K->N;
+  const bool grid_only = flags & SEPW_GRID_ONLY;
+  if (p->generation != K->generation) return SEPW_ERR_ARG;
+  {
+    Stage st(SEPW_STAGE_GATHER, s);
+    SEPW_TRY(launch_gather(p->perm, reinterpret_cast<const float2*>(vis), weight, p->rot,
+                           p->off + p->ntiles, p->nvis, p->ybin, s));
+  }
+  {
+    Stage st(SEPW_STAGE_FILL, s);
+    SEPW_TRY(launch_zero_c64(img, (int64_t)N * N, s));
+  }
+  {
+    Stage st(SEPW_STAGE_GRID, s);
+    SEPW_TRY(launch_grid_fp32(K->S, p->items, p->itoff + p->ntiles, p->rec, p->ybin, K->tab_u,
+                              K->tab_v, K->O, N, p->tile_c, p->ntx, grid_only ? 0 : 1, img, s,
+                              p->max_items));
+  }
+  if (grid_only) return SEPW_OK;
+  {
+    Stage st(SEPW_STAGE_FFT, s);
+    int rc = fft_exec(K, img, HIPFFT_BACKWARD, s);
+    if (rc != SEPW_OK) return rc;
+  }
+  const int npow = (flags & SEPW_MUL_N) ? 1 : ((flags & SEPW_DIV_N) ? -1 : 0);
+  {
+    Stage st(SEPW_STAGE_CORRECT, s);
+    SEPW_TRY(launch_correct(img, img, K->c1, N, K->fov, K->l0, K->m0, npow, s));
+  }
+  return SEPW_OK;
+}
+
+int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t flags,
+                void* hip_stream) {
+  if (!p || !in || (!vis_out && p->nvis > 0)) return SEPW_ERR_ARG;
+  if ((flags & ~(SEPW_GRID_ONLY | SEPW_DIV_N)) != 0) return SEPW_ERR_ARG;
+  Kernels* K = p->K;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int N = K->N;
+  if (p->generation != K->generation) return SEPW_ERR_ARG;
+  const float2* src = reinterpret_cast<const float2*>(in);
+  int checker = 0;
+  if (!(flags & SEPW_GRID_ONLY)) {
+    const int npow = (flags & SEPW_DIV_N) ? -1 : 0;
+    {
+      Stage st(SEPW_STAGE_CORRECT, s);
+      SEPW_TRY(launch_correct(src, K->scratch, K->c1, N, K->fov, K->l0, K->m0, npow, s));
+    }
+    {
+      Stage st(SEPW_STAGE_FFT, s);
+      int rc = fft_exec(K, K->scratch, HIPFFT_FORWARD, s);
+      if (rc != SEPW_OK) return rc;
+    }
+    src = K->scratch;
+    checker = 1;
+  }
+  if (p->nvis == 0) return SEPW_OK;
+  float2* vo = reinterpret_cast<float2*>(vis_out);
+  {
+    Stage st(SEPW_STAGE_FILL, s);
+    SEPW_TRY(launch_zero_c64(vo, p->nvis, s));
+  }
+  {
+    Stage st(SEPW_STAGE_DEGRID, s);
+    SEPW_TRY(launch_degrid_fp32(K->S, p->items, p->itoff + p->ntiles, p->rec, p->perm, p->rot,
+                                src, K->tab_u, K->tab_v, K->O, N, p->tile_c, p->ntx, checker, vo,
+                                s, p->max_items));
+  }
+  return SEPW_OK;
+}
+
+int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* const* vis,
+                      const float* const* weight, sepw_c64* const* out, uint32_t flags,
+                      void* hip_stream) {
+  if (njobs < 1 || !plans || !vis || !out) return SEPW_ERR_ARG;
+  for (int j = 0; j < njobs; ++j) {
+    if (!plans[j] || !out[j] || (!vis[j] && plans[j]->nvis > 0)) return SEPW_ERR_ARG;
+    if (plans[j]->K->N != plans[0]->K->N || plans[j]->K->S != plans[0]->K->S) return SEPW_ERR_ARG;
+  }
+  for (int j = 0; j < njobs; ++j) {
+    int rc = sepw_grid(plans[j], vis[j], weight ? weight[j] : nullptr, out[j], flags, hip_stream);
+    if (rc != SEPW_OK) return rc;
+  }
+  return SEPW_OK;
+}
+
+int sepw_kernels_set_wrange(sepw_kernels k, double w_lo, double w_hi, void* hip_stream) {
+  if (!k || !std::isfinite(w_lo) || !std::isfinite(w_hi) || !(w_lo < w_hi)) return SEPW_ERR_ARG;
+  k->w_lo = w_lo;
+  k->w_hi = w_hi;
+  k->prm.w_lo = w_lo;
+  k->prm.w_hi = w_hi;
+  k->inv_dw = (double)k->P / (w_hi - w_lo);
+  k->generation += 1;
+  SEPW_TRY(make_tables(k, static_cast<hipStream_t>(hip_stream)));
+  return SEPW_OK;
+}
+
+int sepw_timing_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_tmx);
+  g_timing = on != 0;
+  return SEPW_OK;
+}
+
+int sepw_timing_collect(double* ms, int64_t* n) {
+  if (!ms || !n) return SEPW_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_tmx);
+  for (int i = 0; i < SEPW_NSTAGES; ++i) {
+    ms[i] = 0.0;
+    n[i] = 0;
+  }
+  int rc = SEPW_OK;
+  for (const TimingRec& r : g_recs) {
+    float t = 0.f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e != hipSuccess) {
+      rc = map_hip(e);
+    } else {
+      ms[r.stage] += t;
+      n[r.stage] += 1;
+    }
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+  return rc;
+}
+
+int sepw_free_kernels(sepw_kernels k) {
+  if (!k) return SEPW_ERR_ARG;
+  destroy_kernels(k);
+  return SEPW_OK;
+}
+
+int sepw_free_plan(sepw_plan p) {
+  if (!p) return SEPW_ERR_ARG;
+  destroy_plan(p);
+  return SEPW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Grid correction around the FFT.
+//
+// Section 2: the image is F^-1 of the convolved grid divided by c, the inverse
+// transform of the anti-aliasing kernel; with Section 3's separable taper
+// c(l, m) = c1(l) c1(m).  The dirty-image equation carries a factor n on the
+// left (I_D / n), the prediction equation a factor 1/n on the model (I / n).
+// The FFT library computes the uncentred transform, so the centred one
+// (pixel p at l_p = (p - N/2) fov/N, cell j at u_j = (j - N/2)/fov) also needs
+// the checkerboard (-1)^(p+q) on the image side; the grid-side checkerboard
+// is folded into the gridding/degridding kernels.
+//
+//   out[q][p] = in[q][p] (-1)^(p+q) n(l0 + l_p, m0 + m_q)^npow / (c1[p] c1[q])
+//
+// One pass over the N x N complex64 image (HBM-bound); n and the taper ratio
+// are formed in FP64.
+#include "internal.h"
+
+namespace sepw {
+
+namespace {
+
+__global__ void correct_kernel(const float2* __restrict__ in, float2* __restrict__ out,
+                               const double* __restrict__ c1, int N, double fov, double l0,
+                               double m0, int npow) {
+  const int64_t total = (int64_t)N * N;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int q = (int)(i / N), p = (int)(i - (int64_t)q * N);
+    double f = 1.0 / (c1[p] * c1[q]);
+    if (npow != 0) {
+      const double l = l0 + (double)(p - N / 2) * fov / (double)N;
+      const double m = m0 + (double)(q - N / 2) * fov / (double)N;
+      const double n = sqrt(1.0 - l * l - m * m);
+      f = npow > 0 ? f * n : f / n;
+    }
+    if ((p + q) & 1) f = -f;
+    const float2 v = in[i];
+    out[i] = make_float2((float)(v.x * f), (float)(v.y * f));
+  }
+}
+
+}  // namespace
+
+hipError_t launch_correct(const float2* in, float2* out, const double* c1, int N, double fov,
+                          double l0, double m0, int npow, hipStream_t s) {
+  int64_t total = (int64_t)N * N;
+  int64_t b = (total + 255) / 256;
+  if (b > 16384) b = 16384;
+  hipLaunchKernelGGL(correct_kernel, dim3((unsigned)b), dim3(256), 0, s, in, out, c1, N, fov, l0,
+                     m0, npow);
+  return hipGetLastError();
+}
+
+}  // namespace sepw

@@ -1,0 +1,131 @@
+// Kernel-table generation: taper samples and the oversampled 1D GCF tables.
+//
+// Section 3 approximates the W screen g_w(l, m) = exp(2 pi i w (n - 1)) by the
+// separable g1_w(l) g1_w(m) with g1_w(l) = exp(2 pi i w [-l^2/2 - gamma l^4]);
+// Section 4.1's facet screens have the same form with coefficient a_l (a_m) on
+// l^2 and none on l^4.  Combined with the separable taper c1 (Section 2's
+// anti-aliasing function, Section 3's separability assumption) each axis needs
+// one oversampled 1D table per w-plane (Section 2: oversampled lookup tables).
+//
+// Entry (k, fi, s) is the GCF at offset Delta = s - S/2 - f/O cells, f = fi - O/2,
+// sampled as the inverse of the centred image <- grid transform over the N
+// pixels:
+//   T = (1/N) sum_p c1(l_p) exp(-2 pi i w_k (a l_p^2 + b l_p^4)) exp(-2 pi i Delta (p - N/2)/N)
+// Everything is FP64 (phase, argument reduction, sincos, sum); the result is
+// stored complex64.  One workgroup per (plane, sub-cell row); threads stride
+// over pixels and the S partial sums are reduced across the workgroup.
+#include "internal.h"
+
+namespace sepw {
+
+namespace {
+
+constexpr int kTabThreads = 256;
+
+__global__ void taper_kernel(const double* __restrict__ coef, int ncoef, double inv_norm, int N,
+                             double* __restrict__ c1) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  double x = 2.0 * (double)(p - N / 2) / (double)N;
+  // sum_j coef_j sqrt(2j + 1/2) P_{2j}(x), Legendre recurrence in FP64
+  double pm1 = 1.0, pc = x;
+  double acc = coef[0] * sqrt(0.5);
+  int nmax = 2 * (ncoef - 1);
+  for (int n = 1; n < nmax; ++n) {
+    double pn = ((2 * n + 1) * x * pc - n * pm1) / (n + 1);
+    pm1 = pc;
+    pc = pn;
+    int deg = n + 1;
+    if ((deg & 1) == 0) acc += coef[deg / 2] * sqrt(deg + 0.5) * pc;
+  }
+  c1[p] = acc * inv_norm;
+}
+
+__global__ void ones_kernel(double* c1, int N) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < N) c1[p] = 1.0;
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+  // wave64 reduction, then across the workgroup's waves through LDS
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < kTabThreads / 64; ++i) t += sh[i];
+  return t;
+}
+
+__global__ __launch_bounds__(kTabThreads) void table_kernel(
+    const double* __restrict__ c1, int N, double fov, int P, int O, int S, double w_lo,
+    double w_hi, double a, double b, float2* __restrict__ out) {
+  __shared__ double sh[kTabThreads / 64];
+  const int k = blockIdx.x / O;
+  const int fi = blockIdx.x % O;
+  const int f = fi - O / 2;
+  const int h = S / 2;
+  const double wk = w_lo + ((double)k + 0.5) * (w_hi - w_lo) / (double)P;
+  const int64_t period = (int64_t)O * N;
+  double acc_re[kMaxSupport], acc_im[kMaxSupport];
+#pragma unroll
+  for (int s = 0; s < kMaxSupport; ++s) acc_re[s] = acc_im[s] = 0.0;
+
+  for (int p = threadIdx.x; p < N; p += kTabThreads) {
+    const double l = (double)(p - N / 2) * fov / (double)N;
+    const double l2 = l * l;
+    const double cyc = wk * (a * l2 + b * l2 * l2);     // phase in cycles
+    const double frac = cyc - rint(cyc);
+    double sp, cp;
+    sincospi(-2.0 * frac, &sp, &cp);
+    const double are = c1[p] * cp, aim = c1[p] * sp;
+    const int64_t dp = p - N / 2;
+#pragma unroll
+    for (int s = 0; s < kMaxSupport; ++s) {
+      if (s < S) {
+        // Delta (p - N/2) / N = m / (O N) with the integer m below; reduce mod O N exactly
+        int64_t m = ((int64_t)O * (s - h) - f) * dp;
+        int64_t r = m % period;
+        if (r < 0) r += period;
+        double se, ce;
+        sincospi(-2.0 * (double)r / (double)period, &se, &ce);
+        acc_re[s] += are * ce - aim * se;
+        acc_im[s] += are * se + aim * ce;
+      }
+    }
+  }
+  const double invN = 1.0 / (double)N;
+#pragma unroll
+  for (int s = 0; s < kMaxSupport; ++s) {
+    if (s < S) {
+      double re = block_sum(acc_re[s], sh);
+      double im = block_sum(acc_im[s], sh);
+      if (threadIdx.x == 0)
+        out[((int64_t)k * O + fi) * S + s] = make_float2((float)(re * invN), (float)(im * invN));
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_taper(const double* d_coef, int ncoef, double norm, int N, double* c1,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(taper_kernel, dim3((N + 255) / 256), dim3(256), 0, s, d_coef, ncoef,
+                     1.0 / norm, N, c1);
+  return hipGetLastError();
+}
+
+hipError_t launch_ones(double* c1, int N, hipStream_t s) {
+  hipLaunchKernelGGL(ones_kernel, dim3((N + 255) / 256), dim3(256), 0, s, c1, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_tables(const double* c1, int N, double fov, int P, int O, int S, double w_lo,
+                         double w_hi, double a, double b, float2* out, hipStream_t s) {
+  hipLaunchKernelGGL(table_kernel, dim3(P * O), dim3(kTabThreads), 0, s, c1, N, fov, P, O, S,
+                     w_lo, w_hi, a, b, out);
+  return hipGetLastError();
+}
+
+}  // namespace sepw

@@ -1,0 +1,85 @@
+"""Differentiation form: Predict (degrid forward, gridding-adjoint backward)
+against the oracle's chi^2 gradient and central finite differences."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1511_07152_amd import _lib, autograd, synth
+    return _lib, autograd, synth
+
+
+def _small(seed=31, N=64, nvis=3000):
+    rng = np.random.default_rng(seed)
+    fov = math.radians(2.0)
+    u, v = rng.uniform(-26, 26, (2, nvis)) / fov
+    w = rng.uniform(-200, 200, nvis)
+    x = np.zeros((N, N))
+    x[N // 4:3 * N // 4, N // 4:3 * N // 4] = rng.standard_normal((N // 2, N // 2))
+    Vt = rng.standard_normal(nvis) + 1j * rng.standard_normal(nvis)
+    W = rng.uniform(0.5, 2.0, nvis)
+    return dict(u=u, v=v, w=w, x=x, Vt=Vt, W=W, N=N, fov=fov, S=7, O=8, P=8, w_lo=-200.0, w_hi=200.0)
+
+
+def _setup(lib, d):
+    K = lib.Kernels(d["N"], d["fov"], d["S"], d["O"], d["P"], d["w_lo"], d["w_hi"])
+    plan = lib.Plan(K, dev(d["u"], torch.float64), dev(d["v"], torch.float64), dev(d["w"], torch.float64))
+    return K, plan
+
+
+def test_gradient_matches_oracle_adjoint(mods):
+    lib, ag, _ = mods
+    d = _small()
+    K, plan = _setup(lib, d)
+    x = dev(d["x"], torch.float32).requires_grad_(True)
+    Vt = dev(d["Vt"], torch.complex64)
+    W = dev(d["W"], torch.float32)
+    loss = ag.chi2(ag.predict(x, plan), Vt, W)
+    loss.backward()
+    got = x.grad.cpu().numpy()
+    N, fov, S, O, P = d["N"], d["fov"], d["S"], d["O"], d["P"]
+    c1 = oracle.pswf.taper_c1(N, fov, S)
+    q = oracle.quantise.quantise(d["u"], d["v"], d["w"], N, fov, O, S, P, d["w_lo"], d["w_hi"],
+                                 plan.tile_size)
+    T = oracle.tables.separable_table(oracle.tables.w_plane_centres(P, d["w_lo"], d["w_hi"]),
+                                      N, fov, S, O, c1)
+    op = oracle.chi2.SeparableOperator(q, T, c1, N, S, fov)
+    want = oracle.chi2.chi2_grad(op, d["x"], d["Vt"], d["W"])
+    inner = (slice(N // 4, 3 * N // 4),) * 2
+    err = np.linalg.norm((got - want)[inner]) / np.linalg.norm(want[inner])
+    assert err <= 1e-5
+    assert float(loss) == pytest.approx(oracle.chi2.chi2(op, d["x"], d["Vt"], d["W"]), rel=1e-5)
+
+
+def test_gradient_matches_central_differences(mods):
+    lib, ag, _ = mods
+    d = _small(seed=32)
+    K, plan = _setup(lib, d)
+    Vt = dev(d["Vt"], torch.complex64)
+    W = dev(d["W"], torch.float32)
+    x = dev(d["x"], torch.float32).requires_grad_(True)
+    ag.chi2(ag.predict(x, plan), Vt, W).backward()
+    g = x.grad.cpu().numpy()
+    rng = np.random.default_rng(33)
+    N = d["N"]
+    pix = rng.integers(N // 4, 3 * N // 4, (64, 2))
+    for (qq, pp) in pix:
+        e = torch.zeros((N, N), dtype=torch.float32, device="cuda")
+        e[qq, pp] = 1.0          # chi2 is quadratic in x: the central difference is exact for any h
+        with torch.no_grad():
+            fp = float(ag.chi2(ag.predict(x + e, plan), Vt, W))
+            fm = float(ag.chi2(ag.predict(x - e, plan), Vt, W))
+        fd = (fp - fm) / 2.0
+        assert abs(fd - g[qq, pp]) <= 1e-3 * max(abs(g[qq, pp]), 1e-3 * np.abs(g).max())
