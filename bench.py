@@ -70,6 +70,92 @@ def cpu_baseline(d, n_sample):
             "seconds": round(secs, 2)}
 
 
+def accuracy_64(_lib, torch):
+    """Relative RMS error of each precision against the FP64 oracle on the
+    64^2, 2,000-visibility workload: dirty image over the inner half and
+    visibilities predicted from an inner-half model."""
+    import numpy as np
+
+    import oracle
+    from paper_1511_07152_amd import synth
+    d = synth.accuracy_64()
+    N, fov, S, O, P = d["N"], d["fov"], d["S"], d["O"], d["P"]
+    c1 = oracle.pswf.taper_c1(N, fov, S)
+    T = oracle.tables.separable_table(oracle.tables.w_plane_centres(P, d["w_lo"], d["w_hi"]),
+                                      N, fov, S, O, c1)
+    rng = np.random.default_rng(64)
+    X = np.zeros((N, N), complex)
+    X[N // 4:3 * N // 4, N // 4:3 * N // 4] = (rng.standard_normal((N // 2, N // 2))
+                                               + 1j * rng.standard_normal((N // 2, N // 2)))
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)  # noqa: E731
+    inner = slice(N // 4, 3 * N // 4)
+    out = {}
+    for prec in ("fp32", "fp16", "bf16"):
+        K = _lib.Kernels(N, fov, S, O, P, d["w_lo"], d["w_hi"], precision=prec)
+        plan = _lib.Plan(K, dev(d["u"], torch.float64), dev(d["v"], torch.float64),
+                         dev(d["w"], torch.float64))
+        img = _lib.grid(plan, dev(d["V"], torch.complex64), dev(d["W"], torch.float32),
+                        flags=_lib.MUL_N).cpu().numpy()
+        Vp = _lib.degrid(plan, dev(X, torch.complex64), flags=_lib.DIV_N).cpu().numpy()
+        q = oracle.quantise.quantise(d["u"], d["v"], d["w"], N, fov, O, S, P, d["w_lo"], d["w_hi"],
+                                     plan.tile_size)
+        ref_img = oracle.imaging.image_from_grid(
+            oracle.gridder.grid_separable(q, d["V"] * d["W"], T, N, S), c1, fov, n_power=1)
+        ref_v = oracle.gridder.degrid_separable(q, oracle.imaging.grid_from_image(X, c1, fov, -1),
+                                                T, N, S)
+        e_img = np.linalg.norm((img - ref_img)[inner, inner]) / np.linalg.norm(ref_img[inner, inner])
+        e_vis = np.linalg.norm(Vp - ref_v) / np.linalg.norm(ref_v)
+        out[prec] = {"image": float("%.3g" % e_img), "vis": float("%.3g" % e_vis)}
+    return out
+
+
+def batching_form(_lib, torch, args):
+    """36 image-plane facets (6 x 6 over 10 deg, 1024^2 each, S = 11, 64 planes,
+    log-normal visibility counts): one persistent sepw_grid_batched launch vs
+    one sepw_grid launch per facet, both through FFT and correction."""
+    import numpy as np
+
+    from paper_1511_07152_amd import synth
+    d = synth.facets_36()
+    N, fov, S, O, P = d["N"], d["fov"], d["S"], d["O"], d["P"]
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)  # noqa: E731
+    Ks, plans, vis, wts, outs = [], [], [], [], []
+    nvis = 0
+    for jb in d["jobs"]:
+        wmax = float(np.max(np.abs(jb["w"]))) * (1 + 1e-9) + 1e-9
+        K = _lib.Kernels(N, fov, S, O, P, -wmax, wmax, facet=(jb["l0"], jb["m0"]))
+        Ks.append(K)
+        plans.append(_lib.Plan(K, dev(jb["u"], torch.float64), dev(jb["v"], torch.float64),
+                               dev(jb["w"], torch.float64)))
+        vis.append(dev(jb["V"], torch.complex64))
+        wts.append(dev(jb["W"], torch.float32))
+        outs.append(torch.empty((N, N), dtype=torch.complex64, device="cuda"))
+        nvis += len(jb["u"])
+    dropped = sum(p.n_dropped for p in plans)
+
+    def batched():
+        _lib.grid_batched(plans, vis, wts, flags=_lib.MUL_N, outs=outs)
+
+    def per_job():
+        for p, x, wt, o in zip(plans, vis, wts, outs):
+            _lib.grid(p, x, wt, flags=_lib.MUL_N, out=o)
+
+    res = {"workload": "36 facets 6x6 over 10 deg, 1024^2, S=11, O=8, 64 planes",
+           "nvis": nvis, "dropped": dropped}
+    for name, fn in (("batched", batched), ("per_facet", per_job)):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        res[name] = {"ms": round(ms, 3), "Mvis_per_s": round(nvis / (ms * 1e-3) / 1e6, 2)}
+    log("batched facets: %s" % res)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +164,10 @@ def main():
     ap.add_argument("--dump-s", type=float, default=10.0, help="dump time (10 s: 92.9M vis)")
     ap.add_argument("--cpu-sample", type=int, default=400_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp32-only", action="store_true",
+                    help="skip the FP16/BF16 MFMA forms and their accuracy check")
+    ap.add_argument("--no-weights", action="store_true",
+                    help="pass W = NULL (unit weights implied) instead of an array of ones")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -111,36 +201,40 @@ def main():
     img = torch.empty((N, N), dtype=torch.complex64, device="cuda")
     vis_out = torch.empty(nvis, dtype=torch.complex64, device="cuda")
 
-    K = _lib.Kernels(N, fov, S, O, P, d["w_lo"], d["w_hi"])
-    plan = _lib.Plan(K, u, v, w)
-    n_dropped = plan.n_dropped
-    log("plan: %d kept, %d dropped, tile %d" % (nvis - n_dropped, n_dropped, plan.tile_size))
+    def measure(precision):
+        """Warm up, then time args.steps steps; returns (ms/step, stages, kept)."""
+        K = _lib.Kernels(N, fov, S, O, P, d["w_lo"], d["w_hi"], precision=precision)
+        plan = _lib.Plan(K, u, v, w)
+        log("%s plan: %d kept, %d dropped, tile %d" % (precision, nvis - plan.n_dropped,
+                                                       plan.n_dropped, plan.tile_size))
 
-    def step():
-        K.set_wrange(d["w_lo"], d["w_hi"])
-        plan.rebin(u, v, w)
-        _lib.grid(plan, V, W, flags=_lib.MUL_N, out=img)
-        _lib.degrid(plan, model, flags=_lib.DIV_N, out=vis_out)
+        def step():
+            K.set_wrange(d["w_lo"], d["w_hi"])
+            plan.rebin(u, v, w)
+            _lib.grid(plan, V, None if args.no_weights else W, flags=_lib.MUL_N, out=img)
+            _lib.degrid(plan, model, flags=_lib.DIV_N, out=vis_out)
 
-    for i in range(args.warmup):
-        step()
+        for i in range(args.warmup):
+            step()
+            torch.cuda.synchronize()
+            log("%s warmup step %d done" % (precision, i))
+        _lib.timing_enable(True)
+        _lib.timing_collect()
         torch.cuda.synchronize()
-        log("warmup step %d done" % i)
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _lib.timing_enable(False)
+        stages = _lib.timing_collect()
+        log("%s: timed %d steps in %.3f s" % (precision, args.steps, t1 - t0))
+        kept = nvis - plan.n_dropped
+        plan.close()
+        K.close()
+        return (t1 - t0) * 1e3 / args.steps, stages, kept
 
-    _lib.timing_enable(True)
-    _lib.timing_collect()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    _lib.timing_enable(False)
-    stages = _lib.timing_collect()
-    log("timed %d steps in %.3f s" % (args.steps, t1 - t0))
-
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    kept = nvis - n_dropped
+    ms_per_step, stages, kept = measure("fp32")
     value = nvis / (ms_per_step * 1e-3) / 1e6
 
     per_launch = {k: (ms / n if n else 0.0) for k, (ms, n) in stages.items()}
@@ -151,6 +245,20 @@ def main():
                 "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
                 "avg_ms": round(per_launch[dom], 4)}
+
+    forms = {}
+    if not args.fp32_only:
+        acc = accuracy_64(_lib, torch)
+        forms["fp32"] = {"rel_rms_err": acc["fp32"]}
+        for prec in ("fp16", "bf16"):
+            ms, st, _ = measure(prec)
+            forms[prec] = {"value": round(nvis / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 3),
+                           "grid_ms": round(st["grid"][0] / max(st["grid"][1], 1), 4),
+                           "degrid_ms": round(st["degrid"][0] / max(st["degrid"][1], 1), 4),
+                           "rel_rms_err": acc[prec]}
+
+    if not args.fp32_only:
+        forms["batched_facets"] = batching_form(_lib, torch, args)
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mvis/s", "n_gpus": 1,
@@ -164,6 +272,8 @@ def main():
         "roofline": roofline,
         "stages_ms_per_step": {k: round(ms / args.steps, 4) for k, (ms, n) in stages.items()},
     }
+    if forms:
+        out["precision_forms"] = forms
     if not args.no_cpu_baseline:
         del u, v, w
         t = time.perf_counter()

@@ -129,7 +129,9 @@ int sepw_kernels_taper(sepw_kernels k, double* out, void* hip_stream);
  * n_dropped: optional HOST pointer; if given the call synchronises the stream
  * and stores the number of skipped visibilities.  nvis may be 0.
  * Errors: SEPW_ERR_ARG (null kernels, nvis < 0 or > 2^31-2, null arrays with
- * nvis > 0), SEPW_ERR_OOM, SEPW_ERR_HIP. */
+ * nvis > 0), SEPW_ERR_UNSUPPORTED (more tiles than the in-LDS tile sort
+ * handles: N > 16384 at S = 15, N > 32768 at S <= 13), SEPW_ERR_OOM,
+ * SEPW_ERR_HIP. */
 int sepw_plan_create(sepw_kernels k, int64_t nvis, const double* u, const double* v,
                      const double* w, int64_t* n_dropped, void* hip_stream, sepw_plan* out);
 

@@ -6,6 +6,7 @@
 // The FFT between grid and image is a hipFFT library call.
 #pragma clang fp contract(off)
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -124,7 +125,6 @@ int validate_params(const sepw_kernel_params* p) {
       return SEPW_ERR_ARG;
   }
   if (p->support > kMaxSupport) return SEPW_ERR_UNSUPPORTED;
-  if (p->precision != SEPW_FP32) return SEPW_ERR_UNSUPPORTED;
   return SEPW_OK;
 }
 
@@ -135,6 +135,18 @@ void destroy_kernels(Kernels* k) {
   dfree(k->tab_u);
   dfree(k->c1);
   dfree(k->scratch);
+  if (k->pad_v && k->pad_v != k->pad_u) dfree(k->pad_v);
+  k->pad_v = nullptr;
+  dfree(k->pad_u);
+  if (k->lp_v && k->lp_v != k->lp_u) dfree(k->lp_v);
+  k->lp_v = nullptr;
+  dfree(k->lp_u);
+  if (k->sc_v && k->sc_v != k->sc_u) dfree(k->sc_v);
+  k->sc_v = nullptr;
+  dfree(k->sc_u);
+  dfree(k->pad_us);
+  dfree(k->pad_vs);
+  dfree(k->lp_bound);
   if (k->fft_ok) hipfftDestroy(k->fft);
   delete static_cast<sepw_kernels_s*>(k);
 }
@@ -143,13 +155,20 @@ void destroy_plan(Plan* p) {
   if (!p) return;
   dfree(p->key);
   dfree(p->qrec);
-  dfree(p->counts);
+  dfree(p->rowcount);
+  dfree(p->rowoff);
+  dfree(p->rowcursor);
+  dfree(p->rrec);
+  dfree(p->rperm);
+  dfree(p->to_row);
+  dfree(p->to_tile);
+  dfree(p->tmp);
+  dfree(p->ybin);
+  dfree(p->krec);
   dfree(p->off);
-  dfree(p->cursor);
   dfree(p->rec);
   dfree(p->perm);
   dfree(p->rot);
-  dfree(p->ybin);
   dfree(p->nit);
   dfree(p->itoff);
   dfree(p->items);
@@ -192,6 +211,22 @@ hipError_t make_tables(Kernels* K, hipStream_t s) {
   if (e == hipSuccess && K->tab_v != K->tab_u)
     e = launch_tables(K->c1, K->N, K->fov, K->P, K->O, K->S, K->w_lo, K->w_hi, K->a_v, K->b_v,
                       K->tab_v, s);
+  // kernel-side layouts: zero-padded rows (and the precision form's 16-bit tables)
+  if (e == hipSuccess) e = launch_pad_table(K->tab_u, nullptr, K->P, K->O, K->S, K->pad_u, s);
+  if (e == hipSuccess && K->pad_v != K->pad_u)
+    e = launch_pad_table(K->tab_v, nullptr, K->P, K->O, K->S, K->pad_v, s);
+  if (e == hipSuccess && K->lp_u) {
+    const int bf16 = K->prm.precision == SEPW_BF16 ? 1 : 0;
+    e = launch_plane_scales(K->tab_u, K->P, K->O * K->S, K->sc_u, s);
+    if (e == hipSuccess && K->sc_v != K->sc_u)
+      e = launch_plane_scales(K->tab_v, K->P, K->O * K->S, K->sc_v, s);
+    if (e == hipSuccess) e = launch_lp_table(K->tab_u, K->sc_u, K->P, K->O, K->S, bf16, K->lp_u, s);
+    if (e == hipSuccess && K->lp_v != K->lp_u)
+      e = launch_lp_table(K->tab_v, K->sc_v, K->P, K->O, K->S, bf16, K->lp_v, s);
+    if (e == hipSuccess) e = launch_pad_table(K->tab_u, K->sc_v, K->P, K->O, K->S, K->pad_us, s);
+    if (e == hipSuccess) e = launch_pad_table(K->tab_v, K->sc_u, K->P, K->O, K->S, K->pad_vs, s);
+    if (e == hipSuccess) e = launch_lp_bound(K->sc_u, K->sc_v, K->P, K->lp_bound, s);
+  }
   return e;
 }
 
@@ -247,10 +282,32 @@ int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K) {
   }
   const int64_t ntab = (int64_t)K->P * K->O * K->S;
   SEPW_TRY(dalloc(&K->tab_u, ntab));
-  if (K->a_v == K->a_u && K->b_v == K->b_u) {
+  const bool shared_axes = K->a_v == K->a_u && K->b_v == K->b_u;
+  if (shared_axes) {
     K->tab_v = K->tab_u;
   } else {
     SEPW_TRY(dalloc(&K->tab_v, ntab));
+  }
+  const int64_t npad = (int64_t)K->P * K->O * padded_len(K->S);
+  SEPW_TRY(dalloc(&K->pad_u, npad));
+  if (shared_axes) {
+    K->pad_v = K->pad_u;
+  } else {
+    SEPW_TRY(dalloc(&K->pad_v, npad));
+  }
+  if (p->precision != SEPW_FP32) {
+    SEPW_TRY(dalloc(&K->lp_u, npad));
+    SEPW_TRY(dalloc(&K->sc_u, K->P));
+    if (shared_axes) {
+      K->lp_v = K->lp_u;
+      K->sc_v = K->sc_u;
+    } else {
+      SEPW_TRY(dalloc(&K->lp_v, npad));
+      SEPW_TRY(dalloc(&K->sc_v, K->P));
+    }
+    SEPW_TRY(dalloc(&K->pad_us, npad));
+    SEPW_TRY(dalloc(&K->pad_vs, npad));
+    SEPW_TRY(dalloc(&K->lp_bound, 1));
   }
   SEPW_TRY(make_tables(K, s));
   SEPW_TRY(dalloc(&K->scratch, (int64_t)N * N));
@@ -267,19 +324,35 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
   P->nty = P->ntx;
   P->ntiles = (int64_t)P->ntx * P->nty;
   const int64_t nt = P->ntiles;
-  const int64_t occupied = capacity < nt ? capacity : nt;
-  P->max_items = occupied + capacity / kItemMaxVis + 1;
-  P->scan_tmp_len = scan_tmp_size(nt + 1);
+  P->max_items = P->nty + capacity / kItemMaxVis + 1;
+  // level-1 row bins: group 2^rshift tile rows so that there are at most
+  // kMaxRowBins bins and each bin's tiles fit the level-2 LDS histogram
+  // (about 512 bins keeps the level-1 placement runs long enough to coalesce)
+  auto bins_for = [&](int r) { return (P->nty + (1 << r) - 1) >> r; };
+  P->rshift = 0;
+  while (bins_for(P->rshift) > kTargetRowBins) P->rshift += 1;
+  while (P->rshift > 0 && ((int64_t)P->ntx << P->rshift) > kMaxRowTiles) P->rshift -= 1;
+  P->nbins = bins_for(P->rshift);
+  if (P->nbins > kMaxRowBins || ((int64_t)P->ntx << P->rshift) > kMaxRowTiles)
+    return SEPW_ERR_UNSUPPORTED;
+  P->scan_tmp_len = scan_tmp_size((P->nbins > P->nty ? P->nbins : P->nty) + 1);
   SEPW_TRY(dalloc(&P->key, capacity));
   SEPW_TRY(dalloc(&P->qrec, capacity));
-  SEPW_TRY(dalloc(&P->counts, nt + 1));
+  SEPW_TRY(dalloc(&P->rowcount, P->nbins + 1));
+  SEPW_TRY(dalloc(&P->rowoff, P->nbins + 1));
+  SEPW_TRY(dalloc(&P->rowcursor, P->nbins + 1));
+  SEPW_TRY(dalloc(&P->rrec, capacity));
+  SEPW_TRY(dalloc(&P->rperm, capacity));
+  SEPW_TRY(dalloc(&P->to_row, capacity));
+  SEPW_TRY(dalloc(&P->to_tile, capacity));
+  SEPW_TRY(dalloc(&P->tmp, capacity));
+  SEPW_TRY(dalloc(&P->ybin, capacity));
+  SEPW_TRY(dalloc(&P->krec, capacity));
   SEPW_TRY(dalloc(&P->off, nt + 1));
-  SEPW_TRY(dalloc(&P->cursor, nt + 1));
   SEPW_TRY(dalloc(&P->rec, capacity));
   SEPW_TRY(dalloc(&P->perm, capacity));
-  SEPW_TRY(dalloc(&P->ybin, capacity));
-  SEPW_TRY(dalloc(&P->nit, nt + 1));
-  SEPW_TRY(dalloc(&P->itoff, nt + 1));
+  SEPW_TRY(dalloc(&P->nit, P->nty + 1));
+  SEPW_TRY(dalloc(&P->itoff, P->nty + 1));
   SEPW_TRY(dalloc(&P->items, P->max_items));
   SEPW_TRY(dalloc(&P->scan_tmp, P->scan_tmp_len));
   if (K->facet) SEPW_TRY(dalloc(&P->rot, capacity));
@@ -296,18 +369,23 @@ int bin_plan(Plan* P, int64_t nvis, const double* u, const double* v, const doub
   P->generation = K->generation;
   {
     Stage st(SEPW_STAGE_QUANTISE, s);
-    SEPW_TRY(launch_fill_u32(P->counts, 0u, nt + 1, s));
-    SEPW_TRY(launch_quantise(u, v, w, nvis, g, P->key, P->qrec, P->counts, s));
+    SEPW_TRY(launch_fill_u32(P->rowcount, 0u, P->nbins + 1, s));
+    SEPW_TRY(launch_quantise_rows(u, v, w, nvis, g, P->rshift, P->nbins, P->key, P->qrec,
+                                  P->rowcount, s));
   }
   {
     Stage st(SEPW_STAGE_SORT, s);
-    SEPW_TRY(launch_scan(P->counts, P->off, nt + 1, P->scan_tmp, s));
-    SEPW_TRY(hipMemcpyAsync(P->cursor, P->off, sizeof(uint32_t) * (size_t)(nt + 1),
+    SEPW_TRY(launch_scan(P->rowcount, P->rowoff, P->nbins + 1, P->scan_tmp, s));
+    SEPW_TRY(hipMemcpyAsync(P->rowcursor, P->rowoff, sizeof(uint32_t) * (size_t)(P->nbins + 1),
                             hipMemcpyDeviceToDevice, s));
-    SEPW_TRY(launch_scatter(P->key, P->qrec, nvis, P->cursor, P->rec, P->perm, s));
-    SEPW_TRY(launch_item_counts(P->off, nt, P->nit, s));
-    SEPW_TRY(launch_scan(P->nit, P->itoff, nt + 1, P->scan_tmp, s));
-    SEPW_TRY(launch_items(P->off, P->itoff, nt, P->items, s));
+    SEPW_TRY(launch_row_scatter(P->key, P->qrec, nvis, P->ntx, P->rshift, P->nbins, P->rowcursor,
+                                P->rrec, P->rperm, P->to_row, s));
+    SEPW_TRY(launch_row_sort(P->rowoff, P->rrec, P->rperm, P->rshift, P->nbins, P->ntx, P->nty,
+                             P->tile_c, K->O, K->S, P->off, P->rec, P->perm, P->to_tile, P->krec,
+                             s));
+    SEPW_TRY(launch_item_counts(P->off, P->ntx, P->nty, P->nit, s));
+    SEPW_TRY(launch_scan(P->nit, P->itoff, P->nty + 1, P->scan_tmp, s));
+    SEPW_TRY(launch_items(P->off, P->itoff, P->ntx, P->nty, P->items, s));
     if (K->facet) SEPW_TRY(launch_rotation(u, v, w, P->perm, P->off + nt, nvis, g, P->rot, s));
   }
   return SEPW_OK;
@@ -320,6 +398,53 @@ int read_dropped(Plan* P, int64_t* n_dropped, hipStream_t s) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return map_hip(e);
   *n_dropped = P->nvis - (int64_t)kept;
+  return SEPW_OK;
+}
+
+// Library-owned scratch of the batched launch: the job table (pinned host
+// copy and device copy), the per-job item prefix and the work counter.  One
+// per process, grown on demand; guarded so that a new call waits until the
+// previous call's job table has reached the device before overwriting it.
+struct BatchScratch {
+  int cap = 0;
+  int device = -1;
+  int blocks = 0;
+  GridArgs* host = nullptr;     // pinned
+  GridArgs* jobs = nullptr;     // device
+  uint32_t* first = nullptr;    // device [cap + 1]
+  uint32_t* counter = nullptr;  // device
+  hipEvent_t copied = nullptr;
+};
+std::mutex g_bmx;
+BatchScratch g_batch;
+
+int batch_scratch(int njobs, hipStream_t s, BatchScratch** out) {
+  std::lock_guard<std::mutex> lk(g_bmx);
+  BatchScratch& b = g_batch;
+  int dev = 0;
+  SEPW_TRY(hipGetDevice(&dev));
+  if (b.copied) SEPW_TRY(hipEventSynchronize(b.copied));
+  if (b.cap < njobs || b.device != dev) {
+    if (b.host) (void)hipHostFree(b.host);
+    dfree(b.jobs);
+    dfree(b.first);
+    dfree(b.counter);
+    if (b.copied) (void)hipEventDestroy(b.copied);
+    b = BatchScratch();
+    const int cap = njobs < 64 ? 64 : njobs;
+    SEPW_TRY(hipHostMalloc(reinterpret_cast<void**>(&b.host), sizeof(GridArgs) * (size_t)cap));
+    SEPW_TRY(dalloc(&b.jobs, cap));
+    SEPW_TRY(dalloc(&b.first, cap + 1));
+    SEPW_TRY(dalloc(&b.counter, 1));
+    SEPW_TRY(hipEventCreateWithFlags(&b.copied, hipEventDisableTiming));
+    hipDeviceProp_t prop;
+    SEPW_TRY(hipGetDeviceProperties(&prop, dev));
+    b.blocks = prop.multiProcessorCount * 8;
+    b.cap = cap;
+    b.device = dev;
+  }
+  (void)s;
+  *out = &b;
   return SEPW_OK;
 }
 
@@ -434,10 +559,11 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
   const int N = K->N;
   const bool grid_only = flags & SEPW_GRID_ONLY;
   if (p->generation != K->generation) return SEPW_ERR_ARG;
+  const uint32_t* nkept = p->off + p->ntiles;
   {
     Stage st(SEPW_STAGE_GATHER, s);
-    SEPW_TRY(launch_gather(p->perm, reinterpret_cast<const float2*>(vis), weight, p->rot,
-                           p->off + p->ntiles, p->nvis, p->ybin, s));
+    SEPW_TRY(launch_vis_to_tiles(reinterpret_cast<const float2*>(vis), weight, p->to_row,
+                                 p->to_tile, nkept, p->nvis, p->tmp, p->ybin, s));
   }
   {
     Stage st(SEPW_STAGE_FILL, s);
@@ -445,9 +571,15 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
   }
   {
     Stage st(SEPW_STAGE_GRID, s);
-    SEPW_TRY(launch_grid_fp32(K->S, p->items, p->itoff + p->ntiles, p->rec, p->ybin, K->tab_u,
-                              K->tab_v, K->O, N, p->tile_c, p->ntx, grid_only ? 0 : 1, img, s,
-                              p->max_items));
+    if (K->prm.precision == SEPW_FP32) {
+      GridArgs a{p->items, p->itoff + p->nty, p->off, p->rec, p->krec, p->ybin, p->rot, K->pad_u,
+                 K->pad_v, K->O, N, p->ntx, grid_only ? 0 : 1, img};
+      SEPW_TRY(launch_grid_fp32(K->S, a, p->max_items, s));
+    } else {
+      GridArgsLp a{p->items, p->itoff + p->nty, p->off, p->rec, p->krec, p->ybin, p->rot,
+                   K->pad_us, K->lp_v, K->lp_bound, K->O, N, p->ntx, grid_only ? 0 : 1, img};
+      SEPW_TRY(launch_grid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->max_items, s));
+    }
   }
   if (grid_only) return SEPW_OK;
   {
@@ -490,14 +622,21 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
   if (p->nvis == 0) return SEPW_OK;
   float2* vo = reinterpret_cast<float2*>(vis_out);
   {
-    Stage st(SEPW_STAGE_FILL, s);
-    SEPW_TRY(launch_zero_c64(vo, p->nvis, s));
+    Stage st(SEPW_STAGE_DEGRID, s);
+    if (K->prm.precision == SEPW_FP32) {
+      DegridArgs a{p->items, p->itoff + p->nty, p->off, p->rec, p->krec, p->rot, src,
+                   K->pad_u, K->pad_v, K->O, N, p->ntx, checker, p->ybin};
+      SEPW_TRY(launch_degrid_fp32(K->S, a, p->max_items, s));
+    } else {
+      DegridArgsLp a{p->items, p->itoff + p->nty, p->off, p->rec, p->krec, p->rot, src,
+                     K->lp_u, K->pad_vs, K->O, N, p->ntx, checker, p->ybin};
+      SEPW_TRY(launch_degrid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->max_items, s));
+    }
   }
   {
-    Stage st(SEPW_STAGE_DEGRID, s);
-    SEPW_TRY(launch_degrid_fp32(K->S, p->items, p->itoff + p->ntiles, p->rec, p->perm, p->rot,
-                                src, K->tab_u, K->tab_v, K->O, N, p->tile_c, p->ntx, checker, vo,
-                                s, p->max_items));
+    Stage st(SEPW_STAGE_GATHER, s);
+    SEPW_TRY(launch_vis_from_tiles(p->ybin, p->to_row, p->to_tile, p->off + p->ntiles, p->nvis,
+                                   p->tmp, vo, s));
   }
   return SEPW_OK;
 }
@@ -506,13 +645,75 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
                       const float* const* weight, sepw_c64* const* out, uint32_t flags,
                       void* hip_stream) {
   if (njobs < 1 || !plans || !vis || !out) return SEPW_ERR_ARG;
+  if ((flags & ~(SEPW_GRID_ONLY | SEPW_MUL_N | SEPW_DIV_N)) != 0) return SEPW_ERR_ARG;
+  if ((flags & SEPW_MUL_N) && (flags & SEPW_DIV_N)) return SEPW_ERR_ARG;
   for (int j = 0; j < njobs; ++j) {
     if (!plans[j] || !out[j] || (!vis[j] && plans[j]->nvis > 0)) return SEPW_ERR_ARG;
-    if (plans[j]->K->N != plans[0]->K->N || plans[j]->K->S != plans[0]->K->S) return SEPW_ERR_ARG;
+    const Kernels* K = plans[j]->K;
+    const Kernels* K0 = plans[0]->K;
+    if (K->N != K0->N || K->S != K0->S || K->prm.precision != K0->prm.precision) return SEPW_ERR_ARG;
+    if (plans[j]->generation != K->generation) return SEPW_ERR_ARG;
   }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (plans[0]->K->prm.precision != SEPW_FP32) {
+    // the persistent launch is built for the FP32 path; other precisions go job by job
+    for (int j = 0; j < njobs; ++j) {
+      int rc = sepw_grid(plans[j], vis[j], weight ? weight[j] : nullptr, out[j], flags, hip_stream);
+      if (rc != SEPW_OK) return rc;
+    }
+    return SEPW_OK;
+  }
+  const bool grid_only = flags & SEPW_GRID_ONLY;
+  const int N = plans[0]->K->N, S = plans[0]->K->S;
+  // jobs in decreasing size, so the largest start first
+  std::vector<int> order(njobs);
+  for (int j = 0; j < njobs; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return plans[a]->nvis > plans[b]->nvis; });
+  BatchScratch* bs = nullptr;
+  int rc = batch_scratch(njobs, s, &bs);
+  if (rc != SEPW_OK) return rc;
+  {
+    Stage st(SEPW_STAGE_GATHER, s);
+    for (int j = 0; j < njobs; ++j) {
+      Plan* p = plans[j];
+      SEPW_TRY(launch_vis_to_tiles(reinterpret_cast<const float2*>(vis[j]),
+                                   weight ? weight[j] : nullptr, p->to_row, p->to_tile,
+                                   p->off + p->ntiles, p->nvis, p->tmp, p->ybin, s));
+    }
+  }
+  {
+    Stage st(SEPW_STAGE_FILL, s);
+    for (int j = 0; j < njobs; ++j)
+      SEPW_TRY(launch_zero_c64(reinterpret_cast<float2*>(out[j]), (int64_t)N * N, s));
+  }
+  for (int r = 0; r < njobs; ++r) {
+    Plan* p = plans[order[r]];
+    Kernels* K = p->K;
+    bs->host[r] = GridArgs{p->items, p->itoff + p->nty, p->off, p->rec, p->krec, p->ybin, p->rot,
+                           K->pad_u, K->pad_v, K->O, N, p->ntx, grid_only ? 0 : 1,
+                           reinterpret_cast<float2*>(out[order[r]])};
+  }
+  SEPW_TRY(hipMemcpyAsync(bs->jobs, bs->host, sizeof(GridArgs) * (size_t)njobs,
+                          hipMemcpyHostToDevice, s));
+  SEPW_TRY(hipEventRecord(bs->copied, s));
+  {
+    Stage st(SEPW_STAGE_GRID, s);
+    SEPW_TRY(launch_job_prefix(bs->jobs, njobs, bs->first, bs->counter, s));
+    SEPW_TRY(launch_grid_fp32_batched(S, bs->jobs, bs->first, njobs, bs->counter, bs->blocks, s));
+  }
+  if (grid_only) return SEPW_OK;
+  const int npow = (flags & SEPW_MUL_N) ? 1 : ((flags & SEPW_DIV_N) ? -1 : 0);
   for (int j = 0; j < njobs; ++j) {
-    int rc = sepw_grid(plans[j], vis[j], weight ? weight[j] : nullptr, out[j], flags, hip_stream);
-    if (rc != SEPW_OK) return rc;
+    Kernels* K = plans[j]->K;
+    float2* img = reinterpret_cast<float2*>(out[j]);
+    {
+      Stage st(SEPW_STAGE_FFT, s);
+      rc = fft_exec(K, img, HIPFFT_BACKWARD, s);
+      if (rc != SEPW_OK) return rc;
+    }
+    Stage st(SEPW_STAGE_CORRECT, s);
+    SEPW_TRY(launch_correct(img, img, K->c1, N, K->fov, K->l0, K->m0, npow, s));
   }
   return SEPW_OK;
 }

@@ -14,9 +14,15 @@
 // exp(+2 pi i (u l0 + v m0 + w (n0 - 1))).
 //
 // Tiles are c x c blocks of cells (c = 17 - S, so that a tile's S x S
-// footprints fit in a 16 x 16 region).  Sorting is a counting sort: global
-// histogram by atomics, exclusive scan, atomic-cursor scatter.  Membership of a
-// visibility in its bin is exact; the order inside a bin is not specified.
+// footprints fit in a 16 x 16 region), numbered row-major.  Sorting is a
+// two-level counting sort.  Level 1 (by row bin = tile row >> rshift): each
+// block of kChunk visibilities builds its histogram in LDS, the bins are
+// scanned, and each block reserves one contiguous range per non-empty bin with
+// a single global atomic, then places its visibilities with LDS atomics.
+// Level 2 (by tile inside the row bin): one workgroup per row bin counts,
+// scans and places its visibilities entirely in LDS and writes the per-tile
+// offsets.  Membership of a visibility in its tile is exact; the order inside
+// a tile is not specified.
 #include "internal.h"
 
 namespace sepw {
@@ -54,38 +60,6 @@ __device__ inline AxisBin axis_bin(double u, const QuantGeom& g) {
   r.cell = floor_div(qi + g.O / 2, g.O);
   r.fi = (int)(qi - r.cell * g.O) + g.O / 2;
   return r;
-}
-
-__global__ void quantise_kernel(const double* __restrict__ u, const double* __restrict__ v,
-                                const double* __restrict__ w, int64_t nvis, QuantGeom g,
-                                uint32_t* __restrict__ key, uint2* __restrict__ qrec,
-                                uint32_t* __restrict__ counts) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nvis;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    double uu = u[i], vv = v[i], ww = w[i];
-    if (g.facet) {
-      uu = __dsub_rn(uu, __ddiv_rn(__dmul_rn(ww, g.l0), g.n0));
-      vv = __dsub_rn(vv, __ddiv_rn(__dmul_rn(ww, g.m0), g.n0));
-    }
-    AxisBin bu = axis_bin(uu, g), bv = axis_bin(vv, g);
-    double kt = floor(__dmul_rn(__dsub_rn(ww, g.w_lo), g.inv_dw));
-    bool okw = isfinite(kt);
-    int k = 0;
-    if (okw) k = kt < 0.0 ? 0 : (kt > (double)(g.P - 1) ? g.P - 1 : (int)kt);
-    const int h = g.S / 2;
-    bool on = bu.ok && bv.ok && okw && bu.cell - h >= 0 && bu.cell + h <= g.N - 1 &&
-              bv.cell - h >= 0 && bv.cell + h <= g.N - 1;
-    if (on) {
-      int cu = (int)bu.cell, cv = (int)bv.cell;
-      uint32_t tile = (uint32_t)(cv / g.tile_c) * (uint32_t)g.ntx + (uint32_t)(cu / g.tile_c);
-      key[i] = tile;
-      qrec[i] = pack_rec(cu, bu.fi, cv, bv.fi, k);
-      atomicAdd(&counts[tile], 1u);
-    } else {
-      key[i] = kDropped;
-      qrec[i] = make_uint2(0u, 0u);
-    }
-  }
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t val, int64_t n) {
@@ -176,20 +150,7 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(const uint32_t* in
   }
 }
 
-// ---------------------------------------------------------------- scatter etc.
-__global__ void scatter_kernel(const uint32_t* __restrict__ key, const uint2* __restrict__ qrec,
-                               int64_t nvis, uint32_t* __restrict__ cursor,
-                               uint2* __restrict__ rec, int32_t* __restrict__ perm) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nvis;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t kk = key[i];
-    if (kk == kDropped) continue;
-    uint32_t pos = atomicAdd(&cursor[kk], 1u);
-    rec[pos] = qrec[i];
-    perm[pos] = (int32_t)i;
-  }
-}
-
+// ---------------------------------------------------------------- facets, items, export
 __global__ void rotation_kernel(const double* __restrict__ u, const double* __restrict__ v,
                                 const double* __restrict__ w, const int32_t* __restrict__ perm,
                                 const uint32_t* __restrict__ nkept, QuantGeom g,
@@ -207,27 +168,38 @@ __global__ void rotation_kernel(const double* __restrict__ u, const double* __re
   }
 }
 
-__global__ void item_counts_kernel(const uint32_t* __restrict__ off, int64_t ntiles,
+__global__ void item_counts_kernel(const uint32_t* __restrict__ off, int ntx, int nty,
                                    uint32_t* __restrict__ nit) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t <= ntiles;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t c = t < ntiles ? off[t + 1] - off[t] : 0u;
-    nit[t] = (c + kItemMaxVis - 1) / kItemMaxVis;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r <= nty;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t c = r < nty ? off[(r + 1) * ntx] - off[r * ntx] : 0u;
+    nit[r] = (c + kItemMaxVis - 1) / kItemMaxVis;
   }
 }
 
 __global__ void items_kernel(const uint32_t* __restrict__ off, const uint32_t* __restrict__ itoff,
-                             int64_t ntiles, int4* __restrict__ items) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t first = off[t], cnt = off[t + 1] - first;
-    uint32_t o = itoff[t];
-    for (uint32_t m = 0; m * kItemMaxVis < cnt; ++m) {
-      uint32_t c = cnt - m * kItemMaxVis;
-      items[o + m] = make_int4((int)t, (int)(first + m * kItemMaxVis),
-                               (int)(c < (uint32_t)kItemMaxVis ? c : kItemMaxVis), 0);
+                             int ntx, int nty, int4* __restrict__ items) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nty;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t first = off[r * ntx], last = off[(r + 1) * ntx];
+    uint32_t o = itoff[r];
+    for (uint32_t b = first; b < last; b += kItemMaxVis, ++o) {
+      const uint32_t e = last - b > (uint32_t)kItemMaxVis ? b + kItemMaxVis : last;
+      items[o] = make_int4((int)r, (int)b, (int)e, 0);
     }
   }
+}
+
+__global__ void job_prefix_kernel(const GridArgs* __restrict__ jobs, int njobs,
+                                  uint32_t* __restrict__ first, uint32_t* __restrict__ counter) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  uint32_t acc = 0;
+  first[0] = 0;
+  for (int j = 0; j < njobs; ++j) {
+    acc += *jobs[j].nitems;
+    first[j + 1] = acc;
+  }
+  *counter = 0u;
 }
 
 __global__ void bins_dropped_kernel(int64_t nvis, int32_t* __restrict__ out) {
@@ -259,24 +231,199 @@ __global__ void bins_export_kernel(const uint2* __restrict__ rec, const int32_t*
   }
 }
 
-__global__ void gather_kernel(const int32_t* __restrict__ perm, const float2* __restrict__ vis,
-                              const float* __restrict__ weight, const float2* __restrict__ rot,
-                              const uint32_t* __restrict__ nkept, float2* __restrict__ ybin) {
-  const int64_t n = *nkept;
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    int64_t i = perm[j];
+// ---------------------------------------------------------------- two-level sort
+constexpr int kL1Threads = 1024;
+constexpr int kChunk = kL1Threads * 32;  // visibilities per block in the level-1 passes
+
+__global__ __launch_bounds__(kL1Threads) void quantise_rows_kernel(
+    const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
+    int64_t nvis, QuantGeom g, int rshift, int nbins, uint32_t* __restrict__ key,
+    uint2* __restrict__ qrec, uint32_t* __restrict__ rowcount) {
+  __shared__ uint32_t hist[kMaxRowBins];
+  for (int b = threadIdx.x; b < nbins; b += kL1Threads) hist[b] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kChunk;
+  for (int m = 0; m < kChunk / kL1Threads; ++m) {
+    const int64_t i = base + (int64_t)m * kL1Threads + threadIdx.x;
+    if (i >= nvis) break;
+    double uu = u[i], vv = v[i], ww = w[i];
+    if (g.facet) {
+      uu = __dsub_rn(uu, __ddiv_rn(__dmul_rn(ww, g.l0), g.n0));
+      vv = __dsub_rn(vv, __ddiv_rn(__dmul_rn(ww, g.m0), g.n0));
+    }
+    AxisBin bu = axis_bin(uu, g), bv = axis_bin(vv, g);
+    double kt = floor(__dmul_rn(__dsub_rn(ww, g.w_lo), g.inv_dw));
+    bool okw = isfinite(kt);
+    int k = 0;
+    if (okw) k = kt < 0.0 ? 0 : (kt > (double)(g.P - 1) ? g.P - 1 : (int)kt);
+    const int h = g.S / 2;
+    bool on = bu.ok && bv.ok && okw && bu.cell - h >= 0 && bu.cell + h <= g.N - 1 &&
+              bv.cell - h >= 0 && bv.cell + h <= g.N - 1;
+    if (on) {
+      int cu = (int)bu.cell, cv = (int)bv.cell;
+      const uint32_t ty = (uint32_t)(cv / g.tile_c);
+      key[i] = ty * (uint32_t)g.ntx + (uint32_t)(cu / g.tile_c);
+      qrec[i] = pack_rec(cu, bu.fi, cv, bv.fi, k);
+      atomicAdd(&hist[ty >> rshift], 1u);
+    } else {
+      key[i] = kDropped;
+      qrec[i] = make_uint2(0u, 0u);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += kL1Threads)
+    if (hist[b]) atomicAdd(&rowcount[b], hist[b]);
+}
+
+__global__ __launch_bounds__(kL1Threads) void row_scatter_kernel(
+    const uint32_t* __restrict__ key, const uint2* __restrict__ qrec, int64_t nvis, int ntx,
+    int rshift, int nbins, uint32_t* __restrict__ rowcursor, uint2* __restrict__ rrec,
+    int32_t* __restrict__ rperm, uint32_t* __restrict__ to_row) {
+  __shared__ uint32_t hist[kMaxRowBins];
+  __shared__ uint32_t base[kMaxRowBins];
+  for (int b = threadIdx.x; b < nbins; b += kL1Threads) hist[b] = 0u;
+  __syncthreads();
+  const int64_t first = (int64_t)blockIdx.x * kChunk;
+  for (int m = 0; m < kChunk / kL1Threads; ++m) {
+    const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
+    if (i >= nvis) break;
+    const uint32_t kk = key[i];
+    if (kk != kDropped) atomicAdd(&hist[(kk / (uint32_t)ntx) >> rshift], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += kL1Threads) {
+    const uint32_t c = hist[b];
+    base[b] = c ? atomicAdd(&rowcursor[b], c) : 0u;   // one reservation per bin and block
+    hist[b] = 0u;
+  }
+  __syncthreads();
+  for (int m = 0; m < kChunk / kL1Threads; ++m) {
+    const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
+    if (i >= nvis) break;
+    const uint32_t kk = key[i];
+    if (kk == kDropped) {
+      to_row[i] = kDropped;
+      continue;
+    }
+    const uint32_t b = (kk / (uint32_t)ntx) >> rshift;
+    const uint32_t pos = base[b] + atomicAdd(&hist[b], 1u);
+    rrec[pos] = qrec[i];
+    rperm[pos] = (int32_t)i;
+    to_row[i] = pos;
+  }
+}
+
+constexpr int kSortThreads = 1024;
+
+__global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
+    const uint32_t* __restrict__ rowoff, const uint2* __restrict__ rrec,
+    const int32_t* __restrict__ rperm, int rshift, int nbins, int ntx, int nty, int tile_c, int O,
+    int S, uint32_t* __restrict__ off, uint2* __restrict__ rec, int32_t* __restrict__ perm,
+    uint32_t* __restrict__ to_tile, int2* __restrict__ krec) {
+  const int L = padded_len(S);
+  __shared__ uint32_t cnt[kMaxRowTiles];
+  __shared__ uint32_t wsum[kSortThreads / 64];
+  const int b = blockIdx.x;
+  const int row0 = b << rshift;
+  const int row1 = min((b + 1) << rshift, nty);
+  const int64_t tile0 = (int64_t)row0 * ntx;
+  const int nloc = (row1 - row0) * ntx;
+  const uint32_t s0 = rowoff[b], s1 = rowoff[b + 1];
+  for (int t = threadIdx.x; t < nloc; t += kSortThreads) cnt[t] = 0u;
+  __syncthreads();
+  for (uint32_t e = s0 + threadIdx.x; e < s1; e += kSortThreads) {
+    const uint2 r = rrec[e];
+    const int cu = (int)(r.x & 0xFFFFu), cv = (int)(r.x >> 16);
+    atomicAdd(&cnt[(cv / tile_c - row0) * ntx + cu / tile_c], 1u);
+  }
+  __syncthreads();
+  // exclusive scan of cnt[0, nloc): each thread owns a run of consecutive tiles
+  const int per = (nloc + kSortThreads - 1) / kSortThreads;
+  const int t0 = threadIdx.x * per;
+  uint32_t sum = 0;
+  for (int t = t0; t < min(t0 + per, nloc); ++t) sum += cnt[t];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  uint32_t run = x - sum;
+  for (int i = 0; i < wave; ++i) run += wsum[i];
+  for (int t = t0; t < min(t0 + per, nloc); ++t) {
+    const uint32_t c = cnt[t];
+    cnt[t] = run;
+    off[tile0 + t] = s0 + run;
+    run += c;
+  }
+  if (b == nbins - 1 && threadIdx.x == 0) off[(int64_t)nty * ntx] = s1;
+  __syncthreads();
+  for (uint32_t e = s0 + threadIdx.x; e < s1; e += kSortThreads) {
+    const uint2 r = rrec[e];
+    const int cu = (int)(r.x & 0xFFFFu), cv = (int)(r.x >> 16);
+    const uint32_t pos = s0 + atomicAdd(&cnt[(cv / tile_c - row0) * ntx + cu / tile_c], 1u);
+    rec[pos] = r;
+    perm[pos] = rperm[e];
+    to_tile[e] = pos;
+    // padded-table bases: tap of region column x is at base + x
+    const int k = (int)(r.y >> 16);
+    const int ox = cu - (cu / tile_c) * tile_c, oy = cv - (cv / tile_c) * tile_c;
+    const int row_u = k * O + (int)(r.y & 0xFFu), row_v = k * O + (int)((r.y >> 8) & 0xFFu);
+    krec[pos] = make_int2(row_u * L + tile_c - 1 - ox, row_v * L + tile_c - 1 - oy);
+  }
+}
+
+// ---------------------------------------------------------------- moving data
+// Caller order <-> tile order in the same two locality-preserving steps as the
+// sort: caller -> row bin (runs per block and bin), row bin -> tile (inside one
+// row bin's range, which stays cache resident).
+
+// tmp[to_row[i]] = V[i] W[i]   (caller order in, coalesced reads)
+__global__ void to_rows_kernel(const float2* __restrict__ vis, const float* __restrict__ weight,
+                               const uint32_t* __restrict__ to_row, int64_t nvis,
+                               float2* __restrict__ tmp) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nvis;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t d = to_row[i];
+    if (d == kDropped) continue;
     float2 y = vis[i];
     if (weight) {
-      float wt = weight[i];
+      const float wt = weight[i];
       y.x *= wt;
       y.y *= wt;
     }
-    if (rot) {
-      float2 r = rot[j];
-      y = make_float2(y.x * r.x - y.y * r.y, y.x * r.y + y.y * r.x);
-    }
-    ybin[j] = y;
+    tmp[d] = y;
+  }
+}
+
+// dst[to_tile[e]] = src[e]   (row-bin order -> tile order)
+__global__ void to_tiles_kernel(const float2* __restrict__ src, const uint32_t* __restrict__ to_tile,
+                                const uint32_t* __restrict__ nkept, float2* __restrict__ dst) {
+  const int64_t n = *nkept;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[to_tile[e]] = src[e];
+}
+
+// dst[e] = src[to_tile[e]]   (tile order -> row-bin order)
+__global__ void from_tiles_kernel(const float2* __restrict__ src,
+                                  const uint32_t* __restrict__ to_tile,
+                                  const uint32_t* __restrict__ nkept, float2* __restrict__ dst) {
+  const int64_t n = *nkept;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = src[to_tile[e]];
+}
+
+// out[i] = tmp[to_row[i]], 0 for dropped visibilities (caller order out, coalesced writes)
+__global__ void from_rows_kernel(const float2* __restrict__ tmp, const uint32_t* __restrict__ to_row,
+                                 int64_t nvis, float2* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nvis;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t d = to_row[i];
+    out[i] = d == kDropped ? make_float2(0.f, 0.f) : tmp[d];
   }
 }
 
@@ -292,15 +439,6 @@ hipError_t launch_zero_c64(float2* p, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_quantise(const double* u, const double* v, const double* w, int64_t nvis,
-                           QuantGeom g, uint32_t* key, uint2* qrec, uint32_t* counts,
-                           hipStream_t s) {
-  if (nvis == 0) return hipSuccess;
-  hipLaunchKernelGGL(quantise_kernel, grid_for(nvis), dim3(kThreads), 0, s, u, v, w, nvis, g,
-                     key, qrec, counts);
-  return hipGetLastError();
-}
-
 int64_t scan_tmp_size(int64_t n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
 
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp,
@@ -313,11 +451,53 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* t
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(const uint32_t* key, const uint2* qrec, int64_t nvis, uint32_t* cursor,
-                          uint2* rec, int32_t* perm, hipStream_t s) {
+hipError_t launch_quantise_rows(const double* u, const double* v, const double* w, int64_t nvis,
+                                QuantGeom g, int rshift, int nbins, uint32_t* key, uint2* qrec,
+                                uint32_t* rowcount, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
-  hipLaunchKernelGGL(scatter_kernel, grid_for(nvis), dim3(kThreads), 0, s, key, qrec, nvis,
-                     cursor, rec, perm);
+  const int64_t nb = (nvis + kChunk - 1) / kChunk;
+  hipLaunchKernelGGL(quantise_rows_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, u, v, w, nvis,
+                     g, rshift, nbins, key, qrec, rowcount);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_scatter(const uint32_t* key, const uint2* qrec, int64_t nvis, int ntx,
+                              int rshift, int nbins, uint32_t* rowcursor, uint2* rrec,
+                              int32_t* rperm, uint32_t* to_row, hipStream_t s) {
+  if (nvis == 0) return hipSuccess;
+  const int64_t nb = (nvis + kChunk - 1) / kChunk;
+  hipLaunchKernelGGL(row_scatter_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, key, qrec, nvis,
+                     ntx, rshift, nbins, rowcursor, rrec, rperm, to_row);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_sort(const uint32_t* rowoff, const uint2* rrec, const int32_t* rperm,
+                           int rshift, int nbins, int ntx, int nty, int tile_c, int O, int S,
+                           uint32_t* off, uint2* rec, int32_t* perm, uint32_t* to_tile, int2* krec,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(row_sort_kernel, dim3(nbins), dim3(kSortThreads), 0, s, rowoff, rrec, rperm,
+                     rshift, nbins, ntx, nty, tile_c, O, S, off, rec, perm, to_tile, krec);
+  return hipGetLastError();
+}
+
+hipError_t launch_vis_to_tiles(const float2* vis, const float* weight, const uint32_t* to_row,
+                               const uint32_t* to_tile, const uint32_t* nkept, int64_t nvis,
+                               float2* tmp, float2* ybin, hipStream_t s) {
+  if (nvis == 0) return hipSuccess;
+  hipLaunchKernelGGL(to_rows_kernel, grid_for(nvis), dim3(kThreads), 0, s, vis, weight, to_row, nvis,
+                     tmp);
+  hipLaunchKernelGGL(to_tiles_kernel, grid_for(nvis), dim3(kThreads), 0, s, tmp, to_tile, nkept,
+                     ybin);
+  return hipGetLastError();
+}
+
+hipError_t launch_vis_from_tiles(const float2* vbin, const uint32_t* to_row,
+                                 const uint32_t* to_tile, const uint32_t* nkept, int64_t nvis,
+                                 float2* tmp, float2* out, hipStream_t s) {
+  if (nvis == 0) return hipSuccess;
+  hipLaunchKernelGGL(from_tiles_kernel, grid_for(nvis), dim3(kThreads), 0, s, vbin, to_tile, nkept,
+                     tmp);
+  hipLaunchKernelGGL(from_rows_kernel, grid_for(nvis), dim3(kThreads), 0, s, tmp, to_row, nvis, out);
   return hipGetLastError();
 }
 
@@ -330,16 +510,22 @@ hipError_t launch_rotation(const double* u, const double* v, const double* w, co
   return hipGetLastError();
 }
 
-hipError_t launch_item_counts(const uint32_t* off, int64_t ntiles, uint32_t* nit, hipStream_t s) {
-  hipLaunchKernelGGL(item_counts_kernel, grid_for(ntiles + 1), dim3(kThreads), 0, s, off, ntiles,
+hipError_t launch_item_counts(const uint32_t* off, int ntx, int nty, uint32_t* nit, hipStream_t s) {
+  hipLaunchKernelGGL(item_counts_kernel, grid_for(nty + 1), dim3(kThreads), 0, s, off, ntx, nty,
                      nit);
   return hipGetLastError();
 }
 
-hipError_t launch_items(const uint32_t* off, const uint32_t* itoff, int64_t ntiles, int4* items,
+hipError_t launch_items(const uint32_t* off, const uint32_t* itoff, int ntx, int nty, int4* items,
                         hipStream_t s) {
-  hipLaunchKernelGGL(items_kernel, grid_for(ntiles), dim3(kThreads), 0, s, off, itoff, ntiles,
+  hipLaunchKernelGGL(items_kernel, grid_for(nty), dim3(kThreads), 0, s, off, itoff, ntx, nty,
                      items);
+  return hipGetLastError();
+}
+
+hipError_t launch_job_prefix(const GridArgs* jobs, int njobs, uint32_t* first, uint32_t* counter,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(job_prefix_kernel, dim3(1), dim3(64), 0, s, jobs, njobs, first, counter);
   return hipGetLastError();
 }
 
@@ -352,13 +538,5 @@ hipError_t launch_bins_export(const uint2* rec, const int32_t* perm, const uint3
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const int32_t* perm, const float2* vis, const float* weight,
-                         const float2* rot, const uint32_t* nkept, int64_t nvis, float2* ybin,
-                         hipStream_t s) {
-  if (nvis == 0) return hipSuccess;
-  hipLaunchKernelGGL(gather_kernel, grid_for(nvis), dim3(kThreads), 0, s, perm, vis, weight, rot,
-                     nkept, ybin);
-  return hipGetLastError();
-}
 
 }  // namespace sepw

@@ -13,7 +13,16 @@ namespace sepw {
 constexpr uint32_t kDropped = 0xFFFFFFFFu;
 constexpr int kRegion = 16;        // MFMA tile region edge (cells): core + S - 1
 constexpr int kMaxSupport = 15;    // S <= kRegion - 1
-constexpr int kItemMaxVis = 512;   // visibilities per work item (heavy tiles split)
+constexpr int kItemMaxVis = 1024;  // visibilities per work item (a slice of a tile row)
+constexpr int kMaxRowBins = 4096;  // level-1 sort bins (rows of tiles, possibly grouped)
+constexpr int kTargetRowBins = 2048;
+
+// Padded tables: row length L = 32 - S holds the S taps of a table row at
+// offsets c - 1 .. c - 2 + S (c = 17 - S is the tile size) and zeros around
+// them, so that tap index col - ox for col in [0, 16) and ox in [0, c) is
+// always a valid, predicate-free offset: padded[row][c - 1 + col - ox].
+__host__ __device__ inline int padded_len(int S) { return 32 - S; }
+constexpr int kMaxRowTiles = 16384; // tiles per level-1 bin (level-2 sort in LDS)
 
 // Geometry shared by the binning kernels; all FP64 values are used exactly as
 // stored (no recomputation on the device), so host and device agree bit for bit.
@@ -40,6 +49,19 @@ struct Kernels {
   float2* tab_u = nullptr;     // [P][O][S] complex64
   float2* tab_v = nullptr;     // == tab_u when both axes share coefficients
   double* c1 = nullptr;        // taper at the N pixel positions
+  float2* pad_u = nullptr;     // [P][O][L] zero-padded u / v tables
+  float2* pad_v = nullptr;
+  // precision form (FP16 / BF16): per-plane scales s_k, 16-bit padded tables
+  // holding T / s_k, and FP32 padded tables pre-multiplied by the other axis'
+  // scale (u-table times s_k^v for the gridding row product, v-table times
+  // s_k^u for the degridding epilogue); lp_bound = max_k s_k^u s_k^v
+  float* sc_u = nullptr;
+  float* sc_v = nullptr;
+  uint32_t* lp_u = nullptr;
+  uint32_t* lp_v = nullptr;
+  float2* pad_us = nullptr;
+  float2* pad_vs = nullptr;
+  float* lp_bound = nullptr;
   float2* scratch = nullptr;   // N*N complex64 work grid for degridding
   hipfftHandle fft = 0;
   bool fft_ok = false;
@@ -54,18 +76,26 @@ struct Plan {
   int tile_c = 0, ntx = 0, nty = 0;
   int64_t ntiles = 0;
   int64_t max_items = 0;
+  int rshift = 0, nbins = 0;    // level-1 sort: row bin = tile row >> rshift
   uint32_t* key = nullptr;      // [nvis] tile id or kDropped (caller order)
   uint2* qrec = nullptr;        // [nvis] packed bins (caller order)
-  uint32_t* counts = nullptr;   // [ntiles + 1]
-  uint32_t* off = nullptr;      // [ntiles + 1] exclusive scan of counts
-  uint32_t* cursor = nullptr;   // [ntiles]
+  uint32_t* rowcount = nullptr; // [nbins + 1] level-1 histogram
+  uint32_t* rowoff = nullptr;   // [nbins + 1] its exclusive scan
+  uint32_t* rowcursor = nullptr;// [nbins + 1] level-1 placement cursors
+  uint2* rrec = nullptr;        // [nvis] records sorted by row bin
+  int32_t* rperm = nullptr;     // [nvis] caller index sorted by row bin
+  uint32_t* to_row = nullptr;   // [nvis] caller index -> row-bin position (or kDropped)
+  uint32_t* to_tile = nullptr;  // [nvis] row-bin position -> tile-order position
+  float2* tmp = nullptr;        // [nvis] row-bin-order staging for W V / results
+  float2* ybin = nullptr;       // [nvis] tile-order W V (grid) or results (degrid)
+  uint32_t* off = nullptr;      // [ntiles + 1] first binned visibility of each tile
   uint2* rec = nullptr;         // [nvis] packed bins, binned order
+  int2* krec = nullptr;         // [nvis] padded-table base offsets (u, v) relative to the tile
   int32_t* perm = nullptr;      // [nvis] caller index, binned order
   float2* rot = nullptr;        // [nvis] facet phase rotation, binned order
-  float2* ybin = nullptr;       // [nvis] W V (rotated), binned order
-  uint32_t* nit = nullptr;      // [ntiles + 1] work items per tile
-  uint32_t* itoff = nullptr;    // [ntiles + 1] exclusive scan of nit
-  int4* items = nullptr;        // [max_items] (tile, first vis, count, 0)
+  uint32_t* nit = nullptr;      // [nty + 1] work items per row of tiles
+  uint32_t* itoff = nullptr;    // [nty + 1] exclusive scan of nit
+  int4* items = nullptr;        // [max_items] (tile row, first vis, end vis, 0)
   uint32_t* scan_tmp = nullptr; // block partials for the scans
   int64_t scan_tmp_len = 0;
 };
@@ -89,32 +119,118 @@ hipError_t launch_tables(const double* c1, int N, double fov, int P, int O, int 
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_zero_c64(float2* p, int64_t n, hipStream_t s);
-hipError_t launch_quantise(const double* u, const double* v, const double* w, int64_t nvis,
-                           QuantGeom g, uint32_t* key, uint2* qrec, uint32_t* counts, hipStream_t s);
+// two-level counting sort by tile (rows of tiles, then tiles within a row bin)
+hipError_t launch_quantise_rows(const double* u, const double* v, const double* w, int64_t nvis,
+                                QuantGeom g, int rshift, int nbins, uint32_t* key, uint2* qrec,
+                                uint32_t* rowcount, hipStream_t s);
+hipError_t launch_row_scatter(const uint32_t* key, const uint2* qrec, int64_t nvis, int ntx,
+                              int rshift, int nbins, uint32_t* rowcursor, uint2* rrec,
+                              int32_t* rperm, uint32_t* to_row, hipStream_t s);
+hipError_t launch_row_sort(const uint32_t* rowoff, const uint2* rrec, const int32_t* rperm,
+                           int rshift, int nbins, int ntx, int nty, int tile_c, int O, int S,
+                           uint32_t* off, uint2* rec, int32_t* perm, uint32_t* to_tile, int2* krec,
+                           hipStream_t s);
+// caller-order W V -> tile order (two passes through the sort's placement maps)
+hipError_t launch_vis_to_tiles(const float2* vis, const float* weight, const uint32_t* to_row,
+                               const uint32_t* to_tile, const uint32_t* nkept, int64_t nvis,
+                               float2* tmp, float2* ybin, hipStream_t s);
+// tile-order results -> caller order (dropped visibilities get 0)
+hipError_t launch_vis_from_tiles(const float2* vbin, const uint32_t* to_row,
+                                 const uint32_t* to_tile, const uint32_t* nkept, int64_t nvis,
+                                 float2* tmp, float2* out, hipStream_t s);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t s);
 int64_t scan_tmp_size(int64_t n);
-hipError_t launch_scatter(const uint32_t* key, const uint2* qrec, int64_t nvis, uint32_t* cursor,
-                          uint2* rec, int32_t* perm, hipStream_t s);
 hipError_t launch_rotation(const double* u, const double* v, const double* w, const int32_t* perm,
                            const uint32_t* nkept, int64_t nvis, QuantGeom g, float2* rot, hipStream_t s);
-hipError_t launch_item_counts(const uint32_t* off, int64_t ntiles, uint32_t* nit, hipStream_t s);
-hipError_t launch_items(const uint32_t* off, const uint32_t* itoff, int64_t ntiles, int4* items,
+// work items: slices of <= kItemMaxVis visibilities of each row of tiles
+hipError_t launch_item_counts(const uint32_t* off, int ntx, int nty, uint32_t* nit, hipStream_t s);
+hipError_t launch_items(const uint32_t* off, const uint32_t* itoff, int ntx, int nty, int4* items,
                         hipStream_t s);
 hipError_t launch_bins_export(const uint2* rec, const int32_t* perm, const uint32_t* nkept,
                               int64_t nvis, int tile_c, int ntx, int32_t* out, hipStream_t s);
-hipError_t launch_gather(const int32_t* perm, const float2* vis, const float* weight,
-                         const float2* rot, const uint32_t* nkept, int64_t nvis, float2* ybin,
-                         hipStream_t s);
+struct GridArgs {
+  const int4* items;
+  const uint32_t* nitems;   // device count of items
+  const uint32_t* off;      // per-tile offsets into the binned arrays
+  const uint2* rec;         // cells (tile walk)
+  const int2* krec;         // padded-table bases
+  const float2* ybin;       // W V in binned order
+  const float2* rot;        // binned order, may be null
+  const float2* tab_u;      // padded tables
+  const float2* tab_v;
+  int O, N, ntx;
+  int checker;              // apply (-1)^(x+y) for the centred FFT
+  float2* grid;
+};
 
-hipError_t launch_grid_fp32(int S, const int4* items, const uint32_t* nitems, const uint2* rec,
-                            const float2* ybin, const float2* tab_u, const float2* tab_v, int O,
-                            int N, int tile_c, int ntx, int checker, float2* grid, hipStream_t s,
-                            int64_t max_items);
-hipError_t launch_degrid_fp32(int S, const int4* items, const uint32_t* nitems, const uint2* rec,
-                              const int32_t* perm, const float2* rot, const float2* grid,
-                              const float2* tab_u, const float2* tab_v, int O, int N, int tile_c,
-                              int ntx, int checker, float2* vis_out, hipStream_t s,
-                              int64_t max_items);
+struct DegridArgs {
+  const int4* items;
+  const uint32_t* nitems;
+  const uint32_t* off;
+  const uint2* rec;
+  const int2* krec;
+  const float2* rot;
+  const float2* grid;
+  const float2* tab_u;      // padded tables
+  const float2* tab_v;
+  int O, N, ntx;
+  int checker;
+  float2* vbin;             // results in binned order
+};
+
+struct GridArgsLp {
+  const int4* items;
+  const uint32_t* nitems;
+  const uint32_t* off;
+  const uint2* rec;
+  const int2* krec;
+  const float2* ybin;
+  const float2* rot;
+  const float2* pad_us;     // FP32 padded u-table times s_k^v (row product in FP32)
+  const uint32_t* lp_v;     // 16-bit padded v-table / s_k^v, packed (re | im << 16)
+  const float* lp_bound;    // max_k s_k^u s_k^v
+  int O, N, ntx;
+  int checker;
+  float2* grid;
+};
+
+struct DegridArgsLp {
+  const int4* items;
+  const uint32_t* nitems;
+  const uint32_t* off;
+  const uint2* rec;
+  const int2* krec;
+  const float2* rot;
+  const float2* grid;
+  const uint32_t* lp_u;     // 16-bit padded u-table / s_k^u
+  const float2* pad_vs;     // FP32 padded v-table times s_k^u (epilogue)
+  int O, N, ntx;
+  int checker;
+  float2* vbin;
+};
+
+hipError_t launch_grid_fp32(int S, const GridArgs& a, int64_t max_items, hipStream_t s);
+// persistent launch over the items of njobs jobs; first[njobs + 1] = prefix of
+// per-job item counts (device), counter = zeroed device word
+hipError_t launch_grid_fp32_batched(int S, const GridArgs* jobs, const uint32_t* first, int njobs,
+                                    uint32_t* counter, int blocks, hipStream_t s);
+// first[j + 1] = first[j] + *jobs[j].nitems, first[0] = 0; counter = 0
+hipError_t launch_job_prefix(const GridArgs* jobs, int njobs, uint32_t* first, uint32_t* counter,
+                             hipStream_t s);
+hipError_t launch_grid_lp(int S, bool bf16, const GridArgsLp& a, int64_t max_items, hipStream_t s);
+hipError_t launch_degrid_lp(int S, bool bf16, const DegridArgsLp& a, int64_t max_items,
+                            hipStream_t s);
+// zero-padded FP32 tables: out[k][fi][c - 1 + s] = tab[k][fi][s] * (scale ? scale[k] : 1)
+hipError_t launch_pad_table(const float2* tab, const float* scale, int P, int O, int S, float2* out,
+                            hipStream_t s);
+// per-plane scales s_k = max |Re, Im| over the plane
+hipError_t launch_plane_scales(const float2* tab, int P, int per_plane, float* scale, hipStream_t s);
+// 16-bit padded tables holding T / s_k
+hipError_t launch_lp_table(const float2* tab, const float* scale, int P, int O, int S, int bf16,
+                           uint32_t* out, hipStream_t s);
+// lp_bound = max_k su[k] sv[k]
+hipError_t launch_lp_bound(const float* su, const float* sv, int P, float* bound, hipStream_t s);
+hipError_t launch_degrid_fp32(int S, const DegridArgs& a, int64_t max_items, hipStream_t s);
 
 // out[q][p] = in[q][p] (-1)^(p+q) n(l0 + l_p, m0 + m_q)^npow / (c1[p] c1[q])
 hipError_t launch_correct(const float2* in, float2* out, const double* c1, int N, double fov,
