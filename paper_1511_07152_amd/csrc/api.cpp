@@ -158,16 +158,13 @@ void destroy_plan(Plan* p) {
   dfree(p->rowcount);
   dfree(p->rowoff);
   dfree(p->rowcursor);
+  dfree(p->rowpad);
+  dfree(p->prowoff);
   dfree(p->rrec);
-  dfree(p->rperm);
   dfree(p->to_row);
-  dfree(p->to_tile);
-  dfree(p->tmp);
-  dfree(p->ybin);
+  dfree(p->yrow);
   dfree(p->krec);
-  dfree(p->off);
-  dfree(p->rec);
-  dfree(p->perm);
+  dfree(p->tdesc);
   dfree(p->rot);
   dfree(p->nit);
   dfree(p->itoff);
@@ -311,6 +308,17 @@ int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K) {
   }
   SEPW_TRY(make_tables(K, s));
   SEPW_TRY(dalloc(&K->scratch, (int64_t)N * N));
+  // stage the FP32 tables in LDS when both fit in one workgroup's share
+  K->tab_len = (int)npad;
+  {
+    int dev = 0, max_lds = 0, ncu = 0;
+    SEPW_TRY(hipGetDevice(&dev));
+    SEPW_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    SEPW_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t bytes = (int64_t)sizeof(float2) * npad * (shared_axes ? 1 : 2);
+    K->n_cu = ncu > 0 ? ncu : 1;
+    K->lds_bytes = bytes <= (int64_t)max_lds ? (int)bytes : 0;
+  }
   if (hipfftPlan2d(&K->fft, N, N, HIPFFT_C2C) != HIPFFT_SUCCESS) return SEPW_ERR_FFT;
   K->fft_ok = true;
   return SEPW_OK;
@@ -324,7 +332,6 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
   P->nty = P->ntx;
   P->ntiles = (int64_t)P->ntx * P->nty;
   const int64_t nt = P->ntiles;
-  P->max_items = P->nty + capacity / kItemMaxVis + 1;
   // level-1 row bins: group 2^rshift tile rows so that there are at most
   // kMaxRowBins bins and each bin's tiles fit the level-2 LDS histogram
   // (about 512 bins keeps the level-1 placement runs long enough to coalesce)
@@ -335,22 +342,24 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
   P->nbins = bins_for(P->rshift);
   if (P->nbins > kMaxRowBins || ((int64_t)P->ntx << P->rshift) > kMaxRowTiles)
     return SEPW_ERR_UNSUPPORTED;
+  // tile slots: every visibility plus room to pad each non-empty tile to a
+  // multiple of 4, each row bin's range rounded to 4
+  P->pcap = capacity + 3 * std::min<int64_t>(nt, capacity) + 4 * (int64_t)P->nbins;
+  if (P->pcap > 2147483647LL - 64) return SEPW_ERR_UNSUPPORTED;
+  P->max_items = P->nty + P->pcap / kItemMaxVis + 1;
   P->scan_tmp_len = scan_tmp_size((P->nbins > P->nty ? P->nbins : P->nty) + 1);
   SEPW_TRY(dalloc(&P->key, capacity));
   SEPW_TRY(dalloc(&P->qrec, capacity));
   SEPW_TRY(dalloc(&P->rowcount, P->nbins + 1));
   SEPW_TRY(dalloc(&P->rowoff, P->nbins + 1));
   SEPW_TRY(dalloc(&P->rowcursor, P->nbins + 1));
+  SEPW_TRY(dalloc(&P->rowpad, P->nbins + 1));
+  SEPW_TRY(dalloc(&P->prowoff, P->nbins + 1));
   SEPW_TRY(dalloc(&P->rrec, capacity));
-  SEPW_TRY(dalloc(&P->rperm, capacity));
   SEPW_TRY(dalloc(&P->to_row, capacity));
-  SEPW_TRY(dalloc(&P->to_tile, capacity));
-  SEPW_TRY(dalloc(&P->tmp, capacity));
-  SEPW_TRY(dalloc(&P->ybin, capacity));
-  SEPW_TRY(dalloc(&P->krec, capacity));
-  SEPW_TRY(dalloc(&P->off, nt + 1));
-  SEPW_TRY(dalloc(&P->rec, capacity));
-  SEPW_TRY(dalloc(&P->perm, capacity));
+  SEPW_TRY(dalloc(&P->yrow, capacity + 1));
+  SEPW_TRY(dalloc(&P->krec, P->pcap));
+  SEPW_TRY(dalloc(&P->tdesc, nt));
   SEPW_TRY(dalloc(&P->nit, P->nty + 1));
   SEPW_TRY(dalloc(&P->itoff, P->nty + 1));
   SEPW_TRY(dalloc(&P->items, P->max_items));
@@ -364,7 +373,6 @@ int bin_plan(Plan* P, int64_t nvis, const double* u, const double* v, const doub
              hipStream_t s) {
   Kernels* K = P->K;
   P->nvis = nvis;
-  const int64_t nt = P->ntiles;
   const QuantGeom g = make_geom(K, P->tile_c, P->ntx);
   P->generation = K->generation;
   {
@@ -378,22 +386,25 @@ int bin_plan(Plan* P, int64_t nvis, const double* u, const double* v, const doub
     SEPW_TRY(launch_scan(P->rowcount, P->rowoff, P->nbins + 1, P->scan_tmp, s));
     SEPW_TRY(hipMemcpyAsync(P->rowcursor, P->rowoff, sizeof(uint32_t) * (size_t)(P->nbins + 1),
                             hipMemcpyDeviceToDevice, s));
+    SEPW_TRY(launch_pad_sizes(P->rowcount, P->nbins, P->rshift, P->ntx, P->nty, P->rowpad, s));
+    SEPW_TRY(launch_scan(P->rowpad, P->prowoff, P->nbins + 1, P->scan_tmp, s));
     SEPW_TRY(launch_row_scatter(P->key, P->qrec, nvis, P->ntx, P->rshift, P->nbins, P->rowcursor,
-                                P->rrec, P->rperm, P->to_row, s));
-    SEPW_TRY(launch_row_sort(P->rowoff, P->rrec, P->rperm, P->rshift, P->nbins, P->ntx, P->nty,
-                             P->tile_c, K->O, K->S, P->off, P->rec, P->perm, P->to_tile, P->krec,
-                             s));
-    SEPW_TRY(launch_item_counts(P->off, P->ntx, P->nty, P->nit, s));
+                                P->rrec, P->to_row, s));
+    // padding slots point at yrow[capacity], which nothing writes: keep it 0
+    SEPW_TRY(launch_zero_c64(P->yrow + P->capacity, 1, s));
+    SEPW_TRY(launch_row_sort(P->rowoff, P->prowoff, P->rrec, P->rshift, P->nbins, P->ntx, P->nty,
+                             P->tile_c, K->O, K->S, (uint32_t)P->capacity, P->tdesc, P->krec, s));
+    SEPW_TRY(launch_item_counts(P->tdesc, P->ntx, P->nty, P->nit, s));
     SEPW_TRY(launch_scan(P->nit, P->itoff, P->nty + 1, P->scan_tmp, s));
-    SEPW_TRY(launch_items(P->off, P->itoff, P->ntx, P->nty, P->items, s));
-    if (K->facet) SEPW_TRY(launch_rotation(u, v, w, P->perm, P->off + nt, nvis, g, P->rot, s));
+    SEPW_TRY(launch_items(P->tdesc, P->itoff, P->ntx, P->nty, P->items, s));
+    if (K->facet) SEPW_TRY(launch_rotation(u, v, w, nvis, g, P->rot, s));
   }
   return SEPW_OK;
 }
 
 int read_dropped(Plan* P, int64_t* n_dropped, hipStream_t s) {
   uint32_t kept = 0;
-  hipError_t e = hipMemcpyAsync(&kept, P->off + P->ntiles, sizeof(uint32_t),
+  hipError_t e = hipMemcpyAsync(&kept, P->rowoff + P->nbins, sizeof(uint32_t),
                                 hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return map_hip(e);
@@ -543,7 +554,7 @@ int32_t sepw_plan_tile_size(sepw_plan p) { return p ? p->tile_c : 0; }
 
 int sepw_plan_bins(sepw_plan p, int32_t* out, void* hip_stream) {
   if (!p || (!out && p->nvis > 0)) return SEPW_ERR_ARG;
-  SEPW_TRY(launch_bins_export(p->rec, p->perm, p->off + p->ntiles, p->nvis, p->tile_c, p->ntx, out,
+  SEPW_TRY(launch_bins_export(p->rrec, p->to_row, p->nvis, p->tile_c, p->ntx, out,
                               static_cast<hipStream_t>(hip_stream)));
   return SEPW_OK;
 }
@@ -559,11 +570,10 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
   const int N = K->N;
   const bool grid_only = flags & SEPW_GRID_ONLY;
   if (p->generation != K->generation) return SEPW_ERR_ARG;
-  const uint32_t* nkept = p->off + p->ntiles;
   {
     Stage st(SEPW_STAGE_GATHER, s);
-    SEPW_TRY(launch_vis_to_tiles(reinterpret_cast<const float2*>(vis), weight, p->to_row,
-                                 p->to_tile, nkept, p->nvis, p->tmp, p->ybin, s));
+    SEPW_TRY(launch_vis_to_rows(reinterpret_cast<const float2*>(vis), weight, p->rot, p->to_row,
+                                p->nvis, p->yrow, s));
   }
   {
     Stage st(SEPW_STAGE_FILL, s);
@@ -572,12 +582,12 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
   {
     Stage st(SEPW_STAGE_GRID, s);
     if (K->prm.precision == SEPW_FP32) {
-      GridArgs a{p->items, p->itoff + p->nty, p->off, p->rec, p->krec, p->ybin, p->rot, K->pad_u,
-                 K->pad_v, K->O, N, p->ntx, grid_only ? 0 : 1, img};
+      GridArgs a{p->items, p->itoff + p->nty, p->tdesc, p->krec, p->yrow, K->pad_u, K->pad_v,
+                 K->tab_len, N, p->ntx, grid_only ? 0 : 1, img};
       SEPW_TRY(launch_grid_fp32(K->S, a, p->max_items, s));
     } else {
-      GridArgsLp a{p->items, p->itoff + p->nty, p->off, p->rec, p->krec, p->ybin, p->rot,
-                   K->pad_us, K->lp_v, K->lp_bound, K->O, N, p->ntx, grid_only ? 0 : 1, img};
+      GridArgsLp a{p->items, p->itoff + p->nty, p->tdesc, p->krec, p->yrow, K->pad_us, K->lp_v,
+                   K->lp_bound, N, p->ntx, grid_only ? 0 : 1, img};
       SEPW_TRY(launch_grid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->max_items, s));
     }
   }
@@ -624,19 +634,18 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
   {
     Stage st(SEPW_STAGE_DEGRID, s);
     if (K->prm.precision == SEPW_FP32) {
-      DegridArgs a{p->items, p->itoff + p->nty, p->off, p->rec, p->krec, p->rot, src,
-                   K->pad_u, K->pad_v, K->O, N, p->ntx, checker, p->ybin};
-      SEPW_TRY(launch_degrid_fp32(K->S, a, p->max_items, s));
+      DegridArgs a{p->items, p->itoff + p->nty, p->tdesc, p->krec, src, K->pad_u, K->pad_v,
+                   K->tab_len, N, p->ntx, checker, p->yrow};
+      SEPW_TRY(launch_degrid_fp32(K->S, a, p->max_items, K->lds_bytes, K->n_cu, s));
     } else {
-      DegridArgsLp a{p->items, p->itoff + p->nty, p->off, p->rec, p->krec, p->rot, src,
-                     K->lp_u, K->pad_vs, K->O, N, p->ntx, checker, p->ybin};
+      DegridArgsLp a{p->items, p->itoff + p->nty, p->tdesc, p->krec, src, K->lp_u, K->pad_vs, N,
+                     p->ntx, checker, p->yrow};
       SEPW_TRY(launch_degrid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->max_items, s));
     }
   }
   {
     Stage st(SEPW_STAGE_GATHER, s);
-    SEPW_TRY(launch_vis_from_tiles(p->ybin, p->to_row, p->to_tile, p->off + p->ntiles, p->nvis,
-                                   p->tmp, vo, s));
+    SEPW_TRY(launch_vis_from_rows(p->yrow, p->rot, p->to_row, p->nvis, vo, s));
   }
   return SEPW_OK;
 }
@@ -677,9 +686,9 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
     Stage st(SEPW_STAGE_GATHER, s);
     for (int j = 0; j < njobs; ++j) {
       Plan* p = plans[j];
-      SEPW_TRY(launch_vis_to_tiles(reinterpret_cast<const float2*>(vis[j]),
-                                   weight ? weight[j] : nullptr, p->to_row, p->to_tile,
-                                   p->off + p->ntiles, p->nvis, p->tmp, p->ybin, s));
+      SEPW_TRY(launch_vis_to_rows(reinterpret_cast<const float2*>(vis[j]),
+                                  weight ? weight[j] : nullptr, p->rot, p->to_row, p->nvis, p->yrow,
+                                  s));
     }
   }
   {
@@ -690,8 +699,8 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
   for (int r = 0; r < njobs; ++r) {
     Plan* p = plans[order[r]];
     Kernels* K = p->K;
-    bs->host[r] = GridArgs{p->items, p->itoff + p->nty, p->off, p->rec, p->krec, p->ybin, p->rot,
-                           K->pad_u, K->pad_v, K->O, N, p->ntx, grid_only ? 0 : 1,
+    bs->host[r] = GridArgs{p->items, p->itoff + p->nty, p->tdesc, p->krec, p->yrow, K->pad_u,
+                           K->pad_v, K->tab_len, N, p->ntx, grid_only ? 0 : 1,
                            reinterpret_cast<float2*>(out[order[r]])};
   }
   SEPW_TRY(hipMemcpyAsync(bs->jobs, bs->host, sizeof(GridArgs) * (size_t)njobs,

@@ -20,9 +20,12 @@
 // scanned, and each block reserves one contiguous range per non-empty bin with
 // a single global atomic, then places its visibilities with LDS atomics.
 // Level 2 (by tile inside the row bin): one workgroup per row bin counts,
-// scans and places its visibilities entirely in LDS and writes the per-tile
-// offsets.  Membership of a visibility in its tile is exact; the order inside
-// a tile is not specified.
+// scans and places its visibilities entirely in LDS.  Each row bin owns a
+// reserved range of tile slots; inside it the tiles follow each other in
+// row-major order, each padded to a multiple of 4 slots (the MFMA group size)
+// with zero-weight padding, and tdesc[tile] = (first slot, first slot + count).
+// Membership of a visibility in its tile is exact; the order inside a tile is
+// not specified.
 #include "internal.h"
 
 namespace sepw {
@@ -150,42 +153,61 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(const uint32_t* in
   }
 }
 
+
 // ---------------------------------------------------------------- facets, items, export
+// Facet phase rotation in caller order (Section 4.1), applied to W V on its way
+// into tile order and undone on the way back.
 __global__ void rotation_kernel(const double* __restrict__ u, const double* __restrict__ v,
-                                const double* __restrict__ w, const int32_t* __restrict__ perm,
-                                const uint32_t* __restrict__ nkept, QuantGeom g,
+                                const double* __restrict__ w, int64_t nvis, QuantGeom g,
                                 float2* __restrict__ rot) {
-  const int64_t n = *nkept;
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    int64_t i = perm[j];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nvis;
+       i += (int64_t)gridDim.x * blockDim.x) {
     // phase in cycles, reduced to [-1/2, 1/2] before the FP64 sincos
     double cyc = u[i] * g.l0 + v[i] * g.m0 + w[i] * (g.n0 - 1.0);
     double frac = cyc - rint(cyc);
     double s, c;
     sincospi(2.0 * frac, &s, &c);
-    rot[j] = make_float2((float)c, (float)s);
+    rot[i] = make_float2((float)c, (float)s);
   }
 }
 
-__global__ void item_counts_kernel(const uint32_t* __restrict__ off, int ntx, int nty,
+__device__ inline uint32_t round4(uint32_t n) { return (n + 3u) & ~3u; }
+
+// slot range of row of tiles r: [first slot of its first tile, padded end of its last)
+__device__ inline uint2 row_slots(const uint2* __restrict__ tdesc, int ntx, int64_t r) {
+  const uint2 a = tdesc[r * ntx], b = tdesc[(r + 1) * ntx - 1];
+  return make_uint2(a.x, b.x + round4(b.y - b.x));
+}
+
+__global__ void item_counts_kernel(const uint2* __restrict__ tdesc, int ntx, int nty,
                                    uint32_t* __restrict__ nit) {
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r <= nty;
        r += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t c = r < nty ? off[(r + 1) * ntx] - off[r * ntx] : 0u;
-    nit[r] = (c + kItemMaxVis - 1) / kItemMaxVis;
+    uint32_t c = 0;
+    if (r < nty) {
+      const uint2 rs = row_slots(tdesc, ntx, r);
+      c = (rs.y - rs.x + kItemMaxVis - 1) / kItemMaxVis;
+    }
+    nit[r] = c;
   }
 }
 
-__global__ void items_kernel(const uint32_t* __restrict__ off, const uint32_t* __restrict__ itoff,
+// Item k of row r covers slots [a + k M, min(a + (k + 1) M, e)) of the row's
+// range [a, e); the tile holding its first slot writes it.
+__global__ void items_kernel(const uint2* __restrict__ tdesc, const uint32_t* __restrict__ itoff,
                              int ntx, int nty, int4* __restrict__ items) {
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nty;
-       r += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t first = off[r * ntx], last = off[(r + 1) * ntx];
-    uint32_t o = itoff[r];
-    for (uint32_t b = first; b < last; b += kItemMaxVis, ++o) {
-      const uint32_t e = last - b > (uint32_t)kItemMaxVis ? b + kItemMaxVis : last;
-      items[o] = make_int4((int)r, (int)b, (int)e, 0);
+  const int64_t nt = (int64_t)ntx * nty;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const uint2 d = tdesc[t];
+    if (d.y == d.x) continue;
+    const int64_t r = t / ntx;
+    const uint32_t ps = d.x, pe = d.x + round4(d.y - d.x);
+    const uint2 rs = row_slots(tdesc, ntx, r);
+    uint32_t k = (ps - rs.x + kItemMaxVis - 1) / kItemMaxVis;
+    for (uint32_t b = rs.x + k * kItemMaxVis; b < pe; b += kItemMaxVis, ++k) {
+      const uint32_t e = rs.y - b > (uint32_t)kItemMaxVis ? b + kItemMaxVis : rs.y;
+      items[itoff[r] + k] = make_int4((int)r, (int)b, (int)e, (int)(t - r * ntx));
     }
   }
 }
@@ -202,25 +224,20 @@ __global__ void job_prefix_kernel(const GridArgs* __restrict__ jobs, int njobs,
   *counter = 0u;
 }
 
-__global__ void bins_dropped_kernel(int64_t nvis, int32_t* __restrict__ out) {
+__global__ void bins_export_kernel(const uint2* __restrict__ rrec, const uint32_t* __restrict__ to_row,
+                                   int64_t nvis, int tile_c, int ntx, int32_t* __restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nvis;
        i += (int64_t)gridDim.x * blockDim.x) {
     int32_t* o = out + 7 * i;
-    o[0] = o[1] = o[2] = o[3] = o[4] = 0;
-    o[5] = -1;
-    o[6] = 1;
-  }
-}
-
-__global__ void bins_export_kernel(const uint2* __restrict__ rec, const int32_t* __restrict__ perm,
-                                   const uint32_t* __restrict__ nkept, int tile_c, int ntx,
-                                   int32_t* __restrict__ out) {
-  const int64_t n = *nkept;
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    uint2 r = rec[j];
-    int cu = r.x & 0xFFFF, cv = r.x >> 16;
-    int32_t* o = out + 7 * (int64_t)perm[j];
+    const uint32_t d = to_row[i];
+    if (d == kDropped) {
+      o[0] = o[1] = o[2] = o[3] = o[4] = 0;
+      o[5] = -1;
+      o[6] = 1;
+      continue;
+    }
+    const uint2 r = rrec[d];
+    const int cu = r.x & 0xFFFF, cv = r.x >> 16;
     o[0] = cu;
     o[1] = r.y & 0xFF;
     o[2] = cv;
@@ -275,10 +292,27 @@ __global__ __launch_bounds__(kL1Threads) void quantise_rows_kernel(
     if (hist[b]) atomicAdd(&rowcount[b], hist[b]);
 }
 
+// Slots reserved for row bin b: its visibilities plus room to pad every
+// non-empty tile to a multiple of 4, rounded to 4.
+__global__ void pad_sizes_kernel(const uint32_t* __restrict__ rowcount, int nbins, int rshift,
+                                 int ntx, int nty, uint32_t* __restrict__ rowpad) {
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b <= nbins; b += gridDim.x * blockDim.x) {
+    uint32_t p = 0;
+    if (b < nbins) {
+      const uint32_t c = rowcount[b];
+      const int64_t r0 = (int64_t)b << rshift;
+      const int64_t r1 = min(((int64_t)b + 1) << rshift, (int64_t)nty);
+      const int64_t tiles = (r1 - r0) * ntx;
+      p = round4(c + 3u * (uint32_t)min((int64_t)c, tiles));
+    }
+    rowpad[b] = p;
+  }
+}
+
 __global__ __launch_bounds__(kL1Threads) void row_scatter_kernel(
     const uint32_t* __restrict__ key, const uint2* __restrict__ qrec, int64_t nvis, int ntx,
     int rshift, int nbins, uint32_t* __restrict__ rowcursor, uint2* __restrict__ rrec,
-    int32_t* __restrict__ rperm, uint32_t* __restrict__ to_row) {
+    uint32_t* __restrict__ to_row) {
   __shared__ uint32_t hist[kMaxRowBins];
   __shared__ uint32_t base[kMaxRowBins];
   for (int b = threadIdx.x; b < nbins; b += kL1Threads) hist[b] = 0u;
@@ -308,18 +342,22 @@ __global__ __launch_bounds__(kL1Threads) void row_scatter_kernel(
     const uint32_t b = (kk / (uint32_t)ntx) >> rshift;
     const uint32_t pos = base[b] + atomicAdd(&hist[b], 1u);
     rrec[pos] = qrec[i];
-    rperm[pos] = (int32_t)i;
     to_row[i] = pos;
   }
 }
 
 constexpr int kSortThreads = 1024;
 
+// Level 2: one workgroup per row bin.  Tiles are laid out row-major inside the
+// bin's reserved slot range, each padded to a multiple of 4 slots, and
+// described by tdesc[tile] = (first slot, first slot + count).  A slot holds
+// the padded-table bases of its visibility and the visibility's row-bin
+// position (where the data movement keeps W V); padding slots have table base
+// 0 and point at zero_row, whose W V stays 0.
 __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
-    const uint32_t* __restrict__ rowoff, const uint2* __restrict__ rrec,
-    const int32_t* __restrict__ rperm, int rshift, int nbins, int ntx, int nty, int tile_c, int O,
-    int S, uint32_t* __restrict__ off, uint2* __restrict__ rec, int32_t* __restrict__ perm,
-    uint32_t* __restrict__ to_tile, int2* __restrict__ krec) {
+    const uint32_t* __restrict__ rowoff, const uint32_t* __restrict__ prowoff,
+    const uint2* __restrict__ rrec, int rshift, int ntx, int nty, int tile_c, int O, int S,
+    uint32_t zero_row, uint2* __restrict__ tdesc, int4* __restrict__ krec) {
   const int L = padded_len(S);
   __shared__ uint32_t cnt[kMaxRowTiles];
   __shared__ uint32_t wsum[kSortThreads / 64];
@@ -329,6 +367,7 @@ __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
   const int64_t tile0 = (int64_t)row0 * ntx;
   const int nloc = (row1 - row0) * ntx;
   const uint32_t s0 = rowoff[b], s1 = rowoff[b + 1];
+  const uint32_t pbase = prowoff[b];
   for (int t = threadIdx.x; t < nloc; t += kSortThreads) cnt[t] = 0u;
   __syncthreads();
   for (uint32_t e = s0 + threadIdx.x; e < s1; e += kSortThreads) {
@@ -337,11 +376,11 @@ __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
     atomicAdd(&cnt[(cv / tile_c - row0) * ntx + cu / tile_c], 1u);
   }
   __syncthreads();
-  // exclusive scan of cnt[0, nloc): each thread owns a run of consecutive tiles
+  // exclusive scan of the padded counts: each thread owns a run of consecutive tiles
   const int per = (nloc + kSortThreads - 1) / kSortThreads;
   const int t0 = threadIdx.x * per;
   uint32_t sum = 0;
-  for (int t = t0; t < min(t0 + per, nloc); ++t) sum += cnt[t];
+  for (int t = t0; t < min(t0 + per, nloc); ++t) sum += round4(cnt[t]);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t x = sum;
   for (int o = 1; o < 64; o <<= 1) {
@@ -354,36 +393,36 @@ __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
   for (int i = 0; i < wave; ++i) run += wsum[i];
   for (int t = t0; t < min(t0 + per, nloc); ++t) {
     const uint32_t c = cnt[t];
+    const uint32_t p = pbase + run;
+    tdesc[tile0 + t] = make_uint2(p, p + c);
+    for (uint32_t j = c; j < round4(c); ++j) krec[p + j] = make_int4(0, 0, (int)zero_row, 0);
     cnt[t] = run;
-    off[tile0 + t] = s0 + run;
-    run += c;
+    run += round4(c);
   }
-  if (b == nbins - 1 && threadIdx.x == 0) off[(int64_t)nty * ntx] = s1;
   __syncthreads();
   for (uint32_t e = s0 + threadIdx.x; e < s1; e += kSortThreads) {
     const uint2 r = rrec[e];
     const int cu = (int)(r.x & 0xFFFFu), cv = (int)(r.x >> 16);
-    const uint32_t pos = s0 + atomicAdd(&cnt[(cv / tile_c - row0) * ntx + cu / tile_c], 1u);
-    rec[pos] = r;
-    perm[pos] = rperm[e];
-    to_tile[e] = pos;
+    const uint32_t pos = pbase + atomicAdd(&cnt[(cv / tile_c - row0) * ntx + cu / tile_c], 1u);
     // padded-table bases: tap of region column x is at base + x
     const int k = (int)(r.y >> 16);
     const int ox = cu - (cu / tile_c) * tile_c, oy = cv - (cv / tile_c) * tile_c;
     const int row_u = k * O + (int)(r.y & 0xFFu), row_v = k * O + (int)((r.y >> 8) & 0xFFu);
-    krec[pos] = make_int2(row_u * L + tile_c - 1 - ox, row_v * L + tile_c - 1 - oy);
+    krec[pos] = make_int4(row_u * L + tile_c - 1 - ox, row_v * L + tile_c - 1 - oy, (int)e, 0);
   }
 }
 
 // ---------------------------------------------------------------- moving data
-// Caller order <-> tile order in the same two locality-preserving steps as the
-// sort: caller -> row bin (runs per block and bin), row bin -> tile (inside one
-// row bin's range, which stays cache resident).
+// Caller order <-> row-bin order through the level-1 placement map: reads and
+// writes on the caller side are coalesced, the row-bin side is written (read)
+// in runs per block and bin.  The gridding kernels read W V, and the
+// degridding kernels write their results, at the row-bin positions held in
+// the tile slots.
 
-// tmp[to_row[i]] = V[i] W[i]   (caller order in, coalesced reads)
+// yrow[to_row[i]] = V[i] W[i] rot[i]
 __global__ void to_rows_kernel(const float2* __restrict__ vis, const float* __restrict__ weight,
-                               const uint32_t* __restrict__ to_row, int64_t nvis,
-                               float2* __restrict__ tmp) {
+                               const float2* __restrict__ rot, const uint32_t* __restrict__ to_row,
+                               int64_t nvis, float2* __restrict__ yrow) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nvis;
        i += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t d = to_row[i];
@@ -394,36 +433,30 @@ __global__ void to_rows_kernel(const float2* __restrict__ vis, const float* __re
       y.x *= wt;
       y.y *= wt;
     }
-    tmp[d] = y;
+    if (rot) {
+      const float2 ro = rot[i];
+      y = make_float2(y.x * ro.x - y.y * ro.y, y.x * ro.y + y.y * ro.x);
+    }
+    yrow[d] = y;
   }
 }
 
-// dst[to_tile[e]] = src[e]   (row-bin order -> tile order)
-__global__ void to_tiles_kernel(const float2* __restrict__ src, const uint32_t* __restrict__ to_tile,
-                                const uint32_t* __restrict__ nkept, float2* __restrict__ dst) {
-  const int64_t n = *nkept;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x)
-    dst[to_tile[e]] = src[e];
-}
-
-// dst[e] = src[to_tile[e]]   (tile order -> row-bin order)
-__global__ void from_tiles_kernel(const float2* __restrict__ src,
-                                  const uint32_t* __restrict__ to_tile,
-                                  const uint32_t* __restrict__ nkept, float2* __restrict__ dst) {
-  const int64_t n = *nkept;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x)
-    dst[e] = src[to_tile[e]];
-}
-
-// out[i] = tmp[to_row[i]], 0 for dropped visibilities (caller order out, coalesced writes)
-__global__ void from_rows_kernel(const float2* __restrict__ tmp, const uint32_t* __restrict__ to_row,
-                                 int64_t nvis, float2* __restrict__ out) {
+// out[i] = yrow[to_row[i]] conj(rot[i]), 0 for dropped visibilities
+__global__ void from_rows_kernel(const float2* __restrict__ yrow, const uint32_t* __restrict__ to_row,
+                                 const float2* __restrict__ rot, int64_t nvis,
+                                 float2* __restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nvis;
        i += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t d = to_row[i];
-    out[i] = d == kDropped ? make_float2(0.f, 0.f) : tmp[d];
+    float2 y = make_float2(0.f, 0.f);
+    if (d != kDropped) {
+      y = yrow[d];
+      if (rot) {
+        const float2 ro = rot[i];
+        y = make_float2(y.x * ro.x + y.y * ro.y, y.y * ro.x - y.x * ro.y);
+      }
+    }
+    out[i] = y;
   }
 }
 
@@ -461,65 +494,64 @@ hipError_t launch_quantise_rows(const double* u, const double* v, const double* 
   return hipGetLastError();
 }
 
+hipError_t launch_pad_sizes(const uint32_t* rowcount, int nbins, int rshift, int ntx, int nty,
+                            uint32_t* rowpad, hipStream_t s) {
+  hipLaunchKernelGGL(pad_sizes_kernel, grid_for(nbins + 1), dim3(kThreads), 0, s, rowcount, nbins,
+                     rshift, ntx, nty, rowpad);
+  return hipGetLastError();
+}
+
 hipError_t launch_row_scatter(const uint32_t* key, const uint2* qrec, int64_t nvis, int ntx,
                               int rshift, int nbins, uint32_t* rowcursor, uint2* rrec,
-                              int32_t* rperm, uint32_t* to_row, hipStream_t s) {
+                              uint32_t* to_row, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
   const int64_t nb = (nvis + kChunk - 1) / kChunk;
   hipLaunchKernelGGL(row_scatter_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, key, qrec, nvis,
-                     ntx, rshift, nbins, rowcursor, rrec, rperm, to_row);
+                     ntx, rshift, nbins, rowcursor, rrec, to_row);
   return hipGetLastError();
 }
 
-hipError_t launch_row_sort(const uint32_t* rowoff, const uint2* rrec, const int32_t* rperm,
+hipError_t launch_row_sort(const uint32_t* rowoff, const uint32_t* prowoff, const uint2* rrec,
                            int rshift, int nbins, int ntx, int nty, int tile_c, int O, int S,
-                           uint32_t* off, uint2* rec, int32_t* perm, uint32_t* to_tile, int2* krec,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(row_sort_kernel, dim3(nbins), dim3(kSortThreads), 0, s, rowoff, rrec, rperm,
-                     rshift, nbins, ntx, nty, tile_c, O, S, off, rec, perm, to_tile, krec);
+                           uint32_t zero_row, uint2* tdesc, int4* krec, hipStream_t s) {
+  hipLaunchKernelGGL(row_sort_kernel, dim3(nbins), dim3(kSortThreads), 0, s, rowoff, prowoff, rrec,
+                     rshift, ntx, nty, tile_c, O, S, zero_row, tdesc, krec);
   return hipGetLastError();
 }
 
-hipError_t launch_vis_to_tiles(const float2* vis, const float* weight, const uint32_t* to_row,
-                               const uint32_t* to_tile, const uint32_t* nkept, int64_t nvis,
-                               float2* tmp, float2* ybin, hipStream_t s) {
+hipError_t launch_vis_to_rows(const float2* vis, const float* weight, const float2* rot,
+                              const uint32_t* to_row, int64_t nvis, float2* yrow, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
-  hipLaunchKernelGGL(to_rows_kernel, grid_for(nvis), dim3(kThreads), 0, s, vis, weight, to_row, nvis,
-                     tmp);
-  hipLaunchKernelGGL(to_tiles_kernel, grid_for(nvis), dim3(kThreads), 0, s, tmp, to_tile, nkept,
-                     ybin);
+  hipLaunchKernelGGL(to_rows_kernel, grid_for(nvis), dim3(kThreads), 0, s, vis, weight, rot, to_row,
+                     nvis, yrow);
   return hipGetLastError();
 }
 
-hipError_t launch_vis_from_tiles(const float2* vbin, const uint32_t* to_row,
-                                 const uint32_t* to_tile, const uint32_t* nkept, int64_t nvis,
-                                 float2* tmp, float2* out, hipStream_t s) {
+hipError_t launch_vis_from_rows(const float2* yrow, const float2* rot, const uint32_t* to_row,
+                                int64_t nvis, float2* out, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
-  hipLaunchKernelGGL(from_tiles_kernel, grid_for(nvis), dim3(kThreads), 0, s, vbin, to_tile, nkept,
-                     tmp);
-  hipLaunchKernelGGL(from_rows_kernel, grid_for(nvis), dim3(kThreads), 0, s, tmp, to_row, nvis, out);
+  hipLaunchKernelGGL(from_rows_kernel, grid_for(nvis), dim3(kThreads), 0, s, yrow, to_row, rot,
+                     nvis, out);
   return hipGetLastError();
 }
 
-hipError_t launch_rotation(const double* u, const double* v, const double* w, const int32_t* perm,
-                           const uint32_t* nkept, int64_t nvis, QuantGeom g, float2* rot,
-                           hipStream_t s) {
+hipError_t launch_rotation(const double* u, const double* v, const double* w, int64_t nvis,
+                           QuantGeom g, float2* rot, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
-  hipLaunchKernelGGL(rotation_kernel, grid_for(nvis), dim3(kThreads), 0, s, u, v, w, perm, nkept,
-                     g, rot);
+  hipLaunchKernelGGL(rotation_kernel, grid_for(nvis), dim3(kThreads), 0, s, u, v, w, nvis, g, rot);
   return hipGetLastError();
 }
 
-hipError_t launch_item_counts(const uint32_t* off, int ntx, int nty, uint32_t* nit, hipStream_t s) {
-  hipLaunchKernelGGL(item_counts_kernel, grid_for(nty + 1), dim3(kThreads), 0, s, off, ntx, nty,
+hipError_t launch_item_counts(const uint2* tdesc, int ntx, int nty, uint32_t* nit, hipStream_t s) {
+  hipLaunchKernelGGL(item_counts_kernel, grid_for(nty + 1), dim3(kThreads), 0, s, tdesc, ntx, nty,
                      nit);
   return hipGetLastError();
 }
 
-hipError_t launch_items(const uint32_t* off, const uint32_t* itoff, int ntx, int nty, int4* items,
+hipError_t launch_items(const uint2* tdesc, const uint32_t* itoff, int ntx, int nty, int4* items,
                         hipStream_t s) {
-  hipLaunchKernelGGL(items_kernel, grid_for(nty), dim3(kThreads), 0, s, off, itoff, ntx, nty,
-                     items);
+  hipLaunchKernelGGL(items_kernel, grid_for((int64_t)ntx * nty), dim3(kThreads), 0, s, tdesc,
+                     itoff, ntx, nty, items);
   return hipGetLastError();
 }
 
@@ -529,14 +561,12 @@ hipError_t launch_job_prefix(const GridArgs* jobs, int njobs, uint32_t* first, u
   return hipGetLastError();
 }
 
-hipError_t launch_bins_export(const uint2* rec, const int32_t* perm, const uint32_t* nkept,
-                              int64_t nvis, int tile_c, int ntx, int32_t* out, hipStream_t s) {
+hipError_t launch_bins_export(const uint2* rrec, const uint32_t* to_row, int64_t nvis, int tile_c,
+                              int ntx, int32_t* out, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
-  hipLaunchKernelGGL(bins_dropped_kernel, grid_for(nvis), dim3(kThreads), 0, s, nvis, out);
-  hipLaunchKernelGGL(bins_export_kernel, grid_for(nvis), dim3(kThreads), 0, s, rec, perm, nkept,
+  hipLaunchKernelGGL(bins_export_kernel, grid_for(nvis), dim3(kThreads), 0, s, rrec, to_row, nvis,
                      tile_c, ntx, out);
   return hipGetLastError();
 }
-
 
 }  // namespace sepw

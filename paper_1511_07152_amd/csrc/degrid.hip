@@ -4,22 +4,30 @@
 // Section 6, prediction for major cycles):
 //     V_i = sum_y conj(Tv_i[y - oy_i]) sum_x conj(Tu_i[x - ox_i]) R[y][x]
 // over the 16 x 16 grid region R of the visibility's tile.  The inner sums for
-// 16 visibilities at once are the dense product Z = R conj(A_u)^T (M = 16 rows,
-// N = 16 visibilities, K = 16 columns): four steps of v_mfma_f32_16x16x4f32 per
-// real/imaginary combination.  The outer sum is an S-term dot product per
-// visibility on the vector unit from the accumulator layout, reduced across the
-// four 16-lane groups.
+// a chunk of 16 visibilities of one tile are the dense product Z = R conj(A_u)^T
+// (M = 16 rows, N = 16 visibilities, K = 16 columns): four K-steps of
+// v_mfma_f32_16x16x4f32, each complex product in Gauss's three-multiplication
+// form (with B = conj(Tu)):
+//     P1 += Re R Re Tu,  P2 += Im R Im Tu,  P3 += (Re R + Im R)(Re Tu - Im Tu),
+//     Re Z = P1 + P2,    Im Z = P3 - P1 + P2.
+// The outer sum is an S-term dot product per visibility on the vector unit
+// from the accumulator layout, reduced across the four 16-lane groups.
 //
-// Work item: a slice of <= kItemMaxVis binned visibilities from one row of
-// tiles; the region of each tile is read once per tile (consecutive tiles of a
-// row share 16 - c of their 16 columns, so the reloads hit the caches).  If the
-// grid came from the FFT, the checkerboard (-1)^(x+y) of the centred transform
-// is applied on load.  Results are written in binned order (streaming); the
-// plan's placement maps move them to the caller's order afterwards.  The facet
-// rotation is undone here.
+// Work item: a range of tile slots of one row of tiles, processed in chunks of
+// at most 16 slots that never cross a tile.  K-step q of the product takes
+// region columns x = 4 k + q (k = lane group), so each lane reads four
+// consecutive taps of a table row.  Table taps come from LDS when the tables
+// fit there (staged once per workgroup) or from the caches otherwise.  Loads
+// run ahead of the arithmetic: the slot records of chunk n + 2 and the taps
+// and (on a tile change) the grid region of chunk n + 1 are in flight while
+// chunk n is multiplied.  If the grid came from the FFT, the checkerboard
+// (-1)^(x+y) of the centred transform is applied to the region.  Results of
+// real visibilities go straight to their row-bin positions (held in the slot
+// records); the placement map moves them to the caller's order and undoes the
+// facet rotation afterwards.
 // Lane layout of v_mfma_f32_16x16x4f32: lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; accumulator register r of lane l is D[4 (l / 16) + r][l % 16].
-#include "internal.h"
+#include "walk.h"
 
 namespace sepw {
 
@@ -27,128 +35,213 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kWaves = 4;
 
-__device__ inline int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
+// Region operand for the tile at column tx: lane (col, grp) holds
+// R[y = col][x = 4 grp + q] for the four K-steps q (zero outside the grid).
+// The loads are only issued here; the checkerboard sign is applied by
+// region_sign() once the data is needed, so no wait is forced at the load.
 template <int S>
-__global__ __launch_bounds__(64 * kWaves) void degrid_fp32_kernel(
-    const int4* __restrict__ items, const uint32_t* __restrict__ nitems,
-    const uint32_t* __restrict__ off, const uint2* __restrict__ rec,
-    const int2* __restrict__ krec, const float2* __restrict__ rot,
-    const float2* __restrict__ grid, const float2* __restrict__ tab_u,
-    const float2* __restrict__ tab_v, int N, int ntx, int checker, float2* __restrict__ vbin) {
+__device__ inline void load_region(const float2* __restrict__ grid, int N, int tx, int gy,
+                                   bool row_ok, int grp, float2 (&r)[4]) {
   constexpr int C = kRegion + 1 - S;
   constexpr int H = S / 2;
-  const int lane = threadIdx.x & 63;
-  const int col = lane & 15, grp = lane >> 4;
-  const int n_items = (int)*nitems;
-  const int stride = gridDim.x * kWaves;
-
-  for (int it = uniform(blockIdx.x * kWaves + (threadIdx.x >> 6)); it < n_items; it += stride) {
-    const int4 item = items[it];
-    const int ty = uniform(item.x), je = uniform(item.z);
-    int j = uniform(item.y);
-    const int by = ty * C;
-    const int gy = by - H + col;          // grid row of this lane's A operand
-    const bool row_ok = gy >= 0 && gy < N;
-    while (j < je) {
-      const int tx = uniform((int)(rec[j].x & 0xFFFFu) / C);
-      const int bx = tx * C;
-      const int tend = min(uniform((int)off[ty * ntx + tx + 1]), je);
-      // A operand for step q: R[y = col][x = 4 q + grp]
-      float r_re[4], r_im[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int gx = bx - H + 4 * q + grp;
-        float2 val = make_float2(0.f, 0.f);
-        if (row_ok && gx >= 0 && gx < N) {
-          val = grid[(int64_t)gy * N + gx];
-          if (checker && ((gx + gy) & 1)) val = make_float2(-val.x, -val.y);
-        }
-        r_re[q] = val.x;
-        r_im[q] = val.y;
-      }
-      // 32 visibilities per iteration (two MFMA column blocks); lane (col, grp)
-      // handles visibility v0 + 16 m + col.  Taps come from the padded tables at
-      // base + region index, so no per-tap predicate is needed.
-      for (int v0 = j; v0 < tend; v0 += 32) {
-        int2 kr[2];
-        float2 tu[2][4], tv[2][4];
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          const int v = v0 + 16 * m + col;
-          kr[m] = v < tend ? krec[v] : make_int2(0, 0);
-        }
-#pragma unroll
-        for (int m = 0; m < 2; ++m)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            tu[m][q] = tab_u[kr[m].x + 4 * q + grp];
-            tv[m][q] = tab_v[kr[m].y + 4 * grp + q];
-          }
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          if (v0 + 16 * m >= tend) break;   // uniform
-          const int v = v0 + 16 * m + col;
-          f32x4 z_re = {0.f, 0.f, 0.f, 0.f}, z_im = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            z_re = __builtin_amdgcn_mfma_f32_16x16x4f32(r_re[q], tu[m][q].x, z_re, 0, 0, 0);
-            z_im = __builtin_amdgcn_mfma_f32_16x16x4f32(r_im[q], tu[m][q].x, z_im, 0, 0, 0);
-            z_re = __builtin_amdgcn_mfma_f32_16x16x4f32(r_im[q], tu[m][q].y, z_re, 0, 0, 0);
-            z_im = __builtin_amdgcn_mfma_f32_16x16x4f32(r_re[q], -tu[m][q].y, z_im, 0, 0, 0);
-          }
-          // V = sum_y conj(Tv[y]) Z[y] over this lane's rows y = 4 grp + rr
-          float p_re = 0.f, p_im = 0.f;
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) {
-            p_re += tv[m][rr].x * z_re[rr] + tv[m][rr].y * z_im[rr];
-            p_im += tv[m][rr].x * z_im[rr] - tv[m][rr].y * z_re[rr];
-          }
-          p_re += __shfl_xor(p_re, 16, 64);
-          p_im += __shfl_xor(p_im, 16, 64);
-          p_re += __shfl_xor(p_re, 32, 64);
-          p_im += __shfl_xor(p_im, 32, 64);
-          if (grp == 0 && v < tend) {
-            float2 out = make_float2(p_re, p_im);
-            if (rot) {  // undo the facet phase rotation: multiply by conj(rot)
-              const float2 ro = rot[v];
-              out = make_float2(p_re * ro.x + p_im * ro.y, p_im * ro.x - p_re * ro.y);
-            }
-            vbin[v] = out;
-          }
-        }
-      }
-      j = tend;
-    }
+  for (int q = 0; q < 4; ++q) {
+    const int gx = tx * C - H + 4 * grp + q;
+    float2 val = make_float2(0.f, 0.f);
+    if (row_ok && gx >= 0 && gx < N) val = grid[(int64_t)gy * N + gx];
+    r[q] = val;
   }
 }
 
+// (-1)^(x + y) of the centred transform on the region operand of tile tx
 template <int S>
-hipError_t launch_s(const DegridArgs& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(degrid_fp32_kernel<S>, dim3(blocks), dim3(64 * kWaves), 0, s, a.items,
-                     a.nitems, a.off, a.rec, a.krec, a.rot, a.grid, a.tab_u, a.tab_v, a.N, a.ntx,
-                     a.checker, a.vbin);
+__device__ inline void region_sign(int tx, int gy, int grp, float2 (&r)[4]) {
+  constexpr int C = kRegion + 1 - S;
+  constexpr int H = S / 2;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int gx = tx * C - H + 4 * grp + q;
+    if ((gx + gy) & 1) r[q] = make_float2(-r[q].x, -r[q].y);
+  }
+}
+
+// Operands of one chunk of 16 slots as one lane sees them.
+struct ChunkBuf {
+  int4 k;          // record of the lane's slot (column of Z), two chunks ahead
+  float2 tu[4];    // u-table taps x = 4 grp + q of the lane's visibility
+  float2 tv[4];    // v-table taps y = 4 grp + rr
+  float2 reg[4];   // grid region R[y = col][x = 4 grp + q] of the chunk's tile
+  bool fresh;      // region loaded for this chunk, checkerboard not yet applied
+};
+
+struct DegridCtx {
+  const DegridArgs* a;
+  const float2* tu_tab;
+  const float2* tv_tab;
+  int s_end, gy, col, grp, lane;
+  bool row_ok;
+};
+
+__device__ __forceinline__ void fetch_taps(const DegridCtx& c, ChunkBuf& B) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    B.tu[q] = c.tu_tab[B.k.x + 4 * c.grp + q];
+    B.tv[q] = c.tv_tab[B.k.y + 4 * c.grp + q];
+  }
+}
+
+// One pipeline step: chunk cur from buffer X (taps and region in flight or
+// ready; a region loaded for this chunk gets its checkerboard sign here), while
+// the record of chunk n2 goes into X.k and the taps (and, on a tile change, the
+// region) of chunk n1 (record Y.k, loaded one step earlier) into Y.  Buffers
+// alternate between steps.  Returns false after the item's last chunk.
+template <int S>
+__device__ __forceinline__ bool degrid_step(const DegridCtx& c, TileWalk& tw, ChunkPos& cur,
+                                            ChunkPos& n1, ChunkPos& n2, ChunkBuf& X,
+                                            ChunkBuf& Y) {
+  const DegridArgs& a = *c.a;
+  const int4 kx = X.k;   // this chunk's record (row-bin position of the result)
+  X.k = a.krec[min(n2.c0 + c.col, n2.pe - 1)];
+  fetch_taps(c, Y);
+  if (X.fresh && a.checker) region_sign<S>(cur.tx, c.gy, c.grp, X.reg);
+  Y.fresh = n1.ok && n1.tx != cur.tx;
+  if (Y.fresh) {
+    load_region<S>(a.grid, a.N, n1.tx, c.gy, c.row_ok, c.grp, Y.reg);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Y.reg[q] = X.reg[q];
+  }
+
+  // chunk cur: Z = R conj(Tu)^T on the matrix cores
+  f32x4 p1 = {0.f, 0.f, 0.f, 0.f}, p2 = p1, p3 = p1;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(X.reg[q].x, X.tu[q].x, p1, 0, 0, 0);
+    p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(X.reg[q].y, X.tu[q].y, p2, 0, 0, 0);
+    p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(X.reg[q].x + X.reg[q].y, X.tu[q].x - X.tu[q].y, p3,
+                                              0, 0, 0);
+  }
+  // V = sum_y conj(Tv[y]) Z[y] over this lane's rows y = 4 grp + rr
+  float v_re = 0.f, v_im = 0.f;
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const float z_re = p1[rr] + p2[rr];
+    const float z_im = p3[rr] - p1[rr] + p2[rr];
+    v_re += X.tv[rr].x * z_re + X.tv[rr].y * z_im;
+    v_im += X.tv[rr].x * z_im - X.tv[rr].y * z_re;
+  }
+  v_re += __shfl_xor(v_re, 16, 64);
+  v_im += __shfl_xor(v_im, 16, 64);
+  v_re += __shfl_xor(v_re, 32, 64);
+  v_im += __shfl_xor(v_im, 32, 64);
+  if (c.grp == 0 && cur.c0 + c.col < cur.re) a.yrow[kx.z] = make_float2(v_re, v_im);
+
+  if (!n1.ok) return false;
+  cur = n1;
+  n1 = n2;
+  n2 = next_chunk(n2, tw, c.s_end, c.lane);
+  return true;
+}
+
+template <int S>
+__device__ __forceinline__ void degrid_item(const DegridArgs& a, const float2* tu_tab,
+                                            const float2* tv_tab, int it, int lane, int col,
+                                            int grp) {
+  constexpr int C = kRegion + 1 - S;
+  constexpr int H = S / 2;
+  const int4 item = a.items[it];
+  const int ty = uniform(item.x), s_end = uniform(item.z);
+  DegridCtx c;
+  c.a = &a;
+  c.tu_tab = tu_tab;
+  c.tv_tab = tv_tab;
+  c.s_end = s_end;
+  c.gy = ty * C - H + col;          // grid row of this lane's A operand
+  c.row_ok = c.gy >= 0 && c.gy < a.N;
+  c.col = col;
+  c.grp = grp;
+  c.lane = lane;
+  TileWalk tw;
+  tw.start(a.tdesc + (int64_t)ty * a.ntx, a.ntx, uniform(item.w), lane);
+  ChunkPos cur;
+  cur.c0 = uniform(item.y);
+  cur.pe = min(tw.padded_end(), s_end);
+  cur.re = min(tw.real_end(), s_end);
+  cur.tx = tw.tx;
+  cur.ok = true;
+  ChunkPos n1 = next_chunk(cur, tw, s_end, lane);
+  ChunkPos n2 = next_chunk(n1, tw, s_end, lane);
+
+  // prologue: chunk cur complete in A, record of chunk n1 in B
+  ChunkBuf A, B;
+  A.k = a.krec[min(cur.c0 + col, cur.pe - 1)];
+  fetch_taps(c, A);
+  load_region<S>(a.grid, a.N, cur.tx, c.gy, c.row_ok, grp, A.reg);
+  A.fresh = true;
+  B.k = a.krec[min(n1.c0 + col, n1.pe - 1)];
+  while (degrid_step<S>(c, tw, cur, n1, n2, A, B) && degrid_step<S>(c, tw, cur, n1, n2, B, A)) {
+  }
+}
+
+// Tables staged in LDS (LDS = true, the workgroup owns a CU with 16 waves) or
+// read through the caches.
+template <int S, bool LDS>
+__global__ __launch_bounds__(LDS ? 1024 : 256) void degrid_fp32_kernel(DegridArgs a) {
+  extern __shared__ float2 smem[];
+  constexpr int kW = LDS ? 16 : 4;
+  const float2* tu_tab = a.tab_u;
+  const float2* tv_tab = a.tab_v;
+  if constexpr (LDS) {
+    const int n = a.tab_len;
+    const bool two = a.tab_v != a.tab_u;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) smem[i] = a.tab_u[i];
+    if (two)
+      for (int i = threadIdx.x; i < n; i += blockDim.x) smem[n + i] = a.tab_v[i];
+    __syncthreads();
+    tu_tab = smem;
+    tv_tab = two ? smem + n : smem;
+  }
+  const int lane = threadIdx.x & 63;
+  const int n_items = (int)*a.nitems;
+  const int stride = gridDim.x * kW;
+  for (int it = uniform(blockIdx.x * kW + (threadIdx.x >> 6)); it < n_items; it += stride)
+    degrid_item<S>(a, tu_tab, tv_tab, it, lane, lane & 15, lane >> 4);
+}
+
+template <int S>
+hipError_t launch_s(const DegridArgs& a, int64_t max_items, int lds_bytes, int n_cu,
+                    hipStream_t s) {
+  if (lds_bytes > 0) {
+    int64_t b = (max_items + 15) / 16;
+    if (b > n_cu) b = n_cu;
+    if (b < 1) b = 1;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&degrid_fp32_kernel<S, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    hipLaunchKernelGGL((degrid_fp32_kernel<S, true>), dim3((unsigned)b), dim3(1024), lds_bytes, s,
+                       a);
+  } else {
+    int64_t b = (max_items + 3) / 4;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    hipLaunchKernelGGL((degrid_fp32_kernel<S, false>), dim3((unsigned)b), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_degrid_fp32(int S, const DegridArgs& a, int64_t max_items, hipStream_t s) {
-  int64_t b = (max_items + kWaves - 1) / kWaves;
-  if (b > 8192) b = 8192;
-  if (b < 1) b = 1;
-  const int blocks = (int)b;
+hipError_t launch_degrid_fp32(int S, const DegridArgs& a, int64_t max_items, int lds_bytes,
+                              int n_cu, hipStream_t s) {
   switch (S) {
-    case 1: return launch_s<1>(a, blocks, s);
-    case 3: return launch_s<3>(a, blocks, s);
-    case 5: return launch_s<5>(a, blocks, s);
-    case 7: return launch_s<7>(a, blocks, s);
-    case 9: return launch_s<9>(a, blocks, s);
-    case 11: return launch_s<11>(a, blocks, s);
-    case 13: return launch_s<13>(a, blocks, s);
-    case 15: return launch_s<15>(a, blocks, s);
+    case 1: return launch_s<1>(a, max_items, lds_bytes, n_cu, s);
+    case 3: return launch_s<3>(a, max_items, lds_bytes, n_cu, s);
+    case 5: return launch_s<5>(a, max_items, lds_bytes, n_cu, s);
+    case 7: return launch_s<7>(a, max_items, lds_bytes, n_cu, s);
+    case 9: return launch_s<9>(a, max_items, lds_bytes, n_cu, s);
+    case 11: return launch_s<11>(a, max_items, lds_bytes, n_cu, s);
+    case 13: return launch_s<13>(a, max_items, lds_bytes, n_cu, s);
+    case 15: return launch_s<15>(a, max_items, lds_bytes, n_cu, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -8,20 +8,31 @@
 // an MFMA product with K = visibilities: the B operand carries the row product
 // y_i Tu_i (the paper's reuse), the A operand the v-row Tv_i.  c = 17 - S makes
 // the region exactly 16 cells (c = 2 at S = 15: 225 of 256 MACs useful).
-// Complex arithmetic is four real v_mfma_f32_16x16x4f32 per 4 visibilities.
+// The complex product takes three real v_mfma_f32_16x16x4f32 per 4
+// visibilities (Gauss's three-multiplication form):
+//     P1 += Re A Re B,  P2 += Im A Im B,  P3 += (Re A + Im A)(Re B + Im B),
+//     Re R = P1 - P2,   Im R = P3 - P1 - P2.
 //
-// Work item: a slice of <= kItemMaxVis binned visibilities from one row of
-// tiles (tiles are sorted row-major, so a slice walks left to right).  The
-// region accumulator slides with the tile: moving right by d tiles flushes the
-// d*c columns that leave the region (hardware FP32 atomics; regions of
-// neighbouring tiles overlap by S - 1) and shifts the rest across lanes.  W V
-// arrives already in binned order (moved there by the plan's placement maps),
-// so every operand load is a streaming read; the facet rotation is applied
-// here.
+// Work item: a range of tile slots of one row of tiles, walked left to right.
+// Tiles are padded to multiples of 4 slots (padding carries W V = 0), so each
+// MFMA group of 4 slots belongs to one tile and needs no per-visibility test.
+// Operand traffic is shaped for the memory pipeline: a slot record (table
+// bases and the row-bin position of its W V) and its W V are loaded once, one
+// slot per lane, 64 slots at a time and two batches ahead; ds_bpermute then
+// hands each MFMA lane the record of its group's visibility, and the table
+// taps come through the caches.  Taps for group g + 1 are fetched while group
+// g is multiplied.
+// Region accumulation: when the walk moves to another tile, the 16 x 16
+// region sums are added (plain read-modify-write) into a per-wave ring of 32
+// grid columns x 16 rows in LDS at their absolute columns, and the sums
+// restart from zero.  Ring columns that no later tile of the item can touch
+// are flushed to the grid 16 at a time with hardware FP32 atomics (regions of
+// neighbouring tiles and rows overlap, so other waves add to the same cells),
+// all 64 lanes active and each row segment contiguous.
 // Lane layout of v_mfma_f32_16x16x4f32: lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; accumulator register r of lane l is D[4 (l / 16) + r][l % 16],
 // so region column x = l % 16 and region row y = 4 (l / 16) + r.
-#include "internal.h"
+#include "walk.h"
 
 namespace sepw {
 
@@ -29,118 +40,221 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kWaves = 4;
+constexpr int kWaves = 4;   // waves per workgroup of the cache-table and batched launches
 
-__device__ inline int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+constexpr int kRing = 32;        // ring columns (power of two, >= 2 x 16)
+constexpr int kRingPitch = 34;   // complex entries per ring row (spreads LDS banks)
+constexpr int kRingFloats = 2 * 16 * kRingPitch;
 
-// value of lane (lane + sh) within the same 16-lane row, 0 past the row end
-__device__ inline float shift_cols(float v, int lane, int col, int sh) {
-  float r = __int_as_float(__builtin_amdgcn_ds_bpermute((lane + sh) << 2, __float_as_int(v)));
-  return col + sh < 16 ? r : 0.f;
-}
-
-// Add columns [0, ncols) of the region whose top-left cell is (gx0, gy0).
-__device__ inline void flush_cols(float* g, const f32x4& re, const f32x4& im, int col, int grp,
-                                  int gx0, int gy0, int ncols, int N, int checker) {
-  if (col >= ncols) return;
-  const int gx = gx0 + col;
-  if (gx < 0 || gx >= N) return;
+// Add the region sums (column x0 + col, rows 4 grp + r) into the ring.
+__device__ inline void ring_add(float* ring, const f32x4& re, const f32x4& im, int x0, int col,
+                                int grp) {
+  const int slot = (x0 + col) & (kRing - 1);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int gy = gy0 + 4 * grp + r;
-    if (gy >= 0 && gy < N) {
-      const float sg = (checker && ((gx + gy) & 1)) ? -1.f : 1.f;
-      const int64_t idx = 2 * ((int64_t)gy * N + gx);
-      unsafeAtomicAdd(g + idx, sg * re[r]);
-      unsafeAtomicAdd(g + idx + 1, sg * im[r]);
+    float2* p = reinterpret_cast<float2*>(ring) + (4 * grp + r) * kRingPitch + slot;
+    float2 v = *p;
+    v.x += re[r];
+    v.y += im[r];
+    *p = v;
+  }
+}
+
+// Flush ring columns [fx, fx + 16) (grid rows gy0 .. gy0 + 15) to the grid with
+// atomics and clear them.  Lane L takes float L % 32 of a 16-column row
+// segment (column (L % 32) / 2, real or imaginary part) of rows 2 k + L / 32.
+__device__ inline void ring_flush16(float* ring, int fx, float* g, int gy0, int N, int checker,
+                                    int lane) {
+  const int f = lane & 31, half = lane >> 5;
+  const int gx = fx + (f >> 1);
+  const int slot = gx & (kRing - 1);
+  const bool col_ok = gx >= 0 && gx < N;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int row = 2 * k + half;
+    float* p = ring + 2 * (row * kRingPitch + slot) + (f & 1);
+    const float v = *p;
+    *p = 0.f;
+    const int gy = gy0 + row;
+    if (v != 0.f && col_ok && gy >= 0 && gy < N) {
+      const float sg = (checker && ((gx + gy) & 1)) ? -v : v;
+      unsafeAtomicAdd(g + 2 * ((int64_t)gy * N + gx) + (f & 1), sg);
     }
   }
 }
 
-// One work item (a slice of one row of tiles) of one gridding job.
-template <int S>
-__device__ inline void grid_item(const GridArgs& a, int it, int lane, int col, int grp) {
-  constexpr int C = kRegion + 1 - S;   // tile core
-  constexpr int H = S / 2;
-  const int N = a.N, ntx = a.ntx, checker = a.checker;
-  const int2* __restrict__ krec = a.krec;
-  const float2* __restrict__ ybin = a.ybin;
-  const float2* __restrict__ rot = a.rot;
-  const float2* __restrict__ tab_u = a.tab_u;
-  const float2* __restrict__ tab_v = a.tab_v;
-  float* g = reinterpret_cast<float*>(a.grid);
-  const int4 item = a.items[it];
-  const int ty = uniform(item.x), je = uniform(item.z);
-  int j = uniform(item.y);
-  const int by = ty * C;
-  int tx = uniform((int)(a.rec[j].x & 0xFFFFu) / C);
-  f32x4 acc_re = {0.f, 0.f, 0.f, 0.f}, acc_im = {0.f, 0.f, 0.f, 0.f};
-  while (true) {
-    const int bx = tx * C;
-    const int tend = min(uniform((int)a.off[ty * ntx + tx + 1]), je);
-    // 16 visibilities per iteration, four MFMA groups; lane (col, grp) supplies
-    // region row/column col of visibility v0 + 4 m + grp.  The padded tables
-    // make tap col of a visibility simply base + col.
-    for (int v0 = j; v0 < tend; v0 += 16) {
-      int2 kr[4];
-      float2 yv[4];
+// Operands of one MFMA group (4 slots) as one lane sees them.
+struct GroupOps {
+  float2 y;     // W V of the lane's slot
+  float2 tu;    // u-table tap of the lane's column
+  float2 tv;    // v-table tap of the lane's row
+};
+
+struct GridState {
+  f32x4 p1, p2, p3;   // the three real sums of the region accumulator
+  int tx;             // tile column of the region
+  int pe;             // end of the current tile's slots
+  int fx;             // first grid column not yet flushed from the ring
+};
+
+struct GridCtx {
+  const int4* krec;
+  const float2* yrow;
+  float* grid;
+  float* ring;          // this wave's LDS ring
+  const float2* tu_tab;
+  const float2* tv_tab;
+  int N, checker;
+  int s0, last, ng, by, lane, col, grp;
+};
+
+__device__ inline void region_parts(const GridState& st, f32x4& re, f32x4& im) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int v = v0 + 4 * m + grp;
-        kr[m] = make_int2(0, 0);
-        yv[m] = make_float2(0.f, 0.f);   // padding visibilities carry zero weight
-        if (v < tend) {
-          kr[m] = krec[v];
-          yv[m] = ybin[v];
-          if (rot) {
-            const float2 ro = rot[v];
-            yv[m] = make_float2(yv[m].x * ro.x - yv[m].y * ro.y, yv[m].x * ro.y + yv[m].y * ro.x);
-          }
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const float2 tv = tab_v[kr[m].y + col];
-        const float2 tu = tab_u[kr[m].x + col];
-        const float b_re = yv[m].x * tu.x - yv[m].y * tu.y;   // row product W V Tu
-        const float b_im = yv[m].x * tu.y + yv[m].y * tu.x;
-        if (v0 + 4 * m < tend) {   // uniform: skip all-padding groups
-          acc_re = __builtin_amdgcn_mfma_f32_16x16x4f32(tv.x, b_re, acc_re, 0, 0, 0);
-          acc_im = __builtin_amdgcn_mfma_f32_16x16x4f32(tv.x, b_im, acc_im, 0, 0, 0);
-          acc_re = __builtin_amdgcn_mfma_f32_16x16x4f32(-tv.y, b_im, acc_re, 0, 0, 0);
-          acc_im = __builtin_amdgcn_mfma_f32_16x16x4f32(tv.y, b_re, acc_im, 0, 0, 0);
-        }
-      }
-    }
-    j = tend;
-    if (j >= je) break;
-    // slide the region to the next non-empty tile of the row
-    const int txn = uniform((int)(a.rec[j].x & 0xFFFFu) / C);
-    const int sh = (txn - tx) * C;
-    if (sh >= 16) {
-      flush_cols(g, acc_re, acc_im, col, grp, bx - H, by - H, 16, N, checker);
-      acc_re = f32x4{0.f, 0.f, 0.f, 0.f};
-      acc_im = f32x4{0.f, 0.f, 0.f, 0.f};
-    } else {
-      flush_cols(g, acc_re, acc_im, col, grp, bx - H, by - H, sh, N, checker);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        acc_re[r] = shift_cols(acc_re[r], lane, col, sh);
-        acc_im[r] = shift_cols(acc_im[r], lane, col, sh);
-      }
-    }
-    tx = txn;
+  for (int r = 0; r < 4; ++r) {
+    re[r] = st.p1[r] - st.p2[r];
+    im[r] = st.p3[r] - st.p1[r] - st.p2[r];
   }
-  flush_cols(g, acc_re, acc_im, col, grp, tx * C - H, by - H, 16, N, checker);
+}
+
+__device__ inline float bperm(int addr, float v) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+
+// Operands of group j (slots s0 + 4 j ..): the record of slot 4 (j % 16) + grp
+// of the batch (R, Y), moved to this lane, then its table taps.
+__device__ __forceinline__ void fetch_group(const GridCtx& c, const int4& R, const float2& Y,
+                                            int j, GroupOps& o) {
+  const int src = (4 * (j & 15) + c.grp) << 2;
+  const int kx = __builtin_amdgcn_ds_bpermute(src, R.x);
+  const int ky = __builtin_amdgcn_ds_bpermute(src, R.y);
+  o.y = make_float2(bperm(src, Y.x), bperm(src, Y.y));
+  o.tu = c.tu_tab[kx + c.col];
+  o.tv = c.tv_tab[ky + c.col];
+}
+
+// One pipeline step: group g from cur (taps in flight or ready) while the
+// operands of group g + 1 (from batch registers R, Y) go into nxt.  The fetch
+// is unconditional (past the item's end it reads a harmless repeat), so that
+// every path leaves the same loads in flight.  Buffers alternate.
+template <int S>
+__device__ __forceinline__ void grid_step(const GridCtx& c, int g, const int4& R, const float2& Y,
+                                          TileWalk& tw, GridState& st, const GroupOps& cur,
+                                          GroupOps& nxt) {
+  constexpr int C = kRegion + 1 - S;
+  constexpr int H = S / 2;
+  fetch_group(c, R, Y, g + 1, nxt);
+  if (c.s0 + 4 * g >= st.pe) {
+    // next non-empty tile of the row: bank the region sums in the ring,
+    // flush ring columns the new region cannot reach, restart the sums
+    if (tw.next(c.lane)) {
+      f32x4 re, im;
+      region_parts(st, re, im);
+      ring_add(c.ring, re, im, st.tx * C - H, c.col, c.grp);
+      const int x0 = tw.tx * C - H;
+      if (x0 >= st.fx + kRing) {
+        ring_flush16(c.ring, st.fx, c.grid, c.by - H, c.N, c.checker, c.lane);
+        ring_flush16(c.ring, st.fx + 16, c.grid, c.by - H, c.N, c.checker, c.lane);
+        st.fx = x0;
+      } else if (x0 + 16 > st.fx + kRing) {
+        ring_flush16(c.ring, st.fx, c.grid, c.by - H, c.N, c.checker, c.lane);
+        st.fx += 16;
+      }
+      st.p1 = f32x4{0.f, 0.f, 0.f, 0.f};
+      st.p2 = st.p1;
+      st.p3 = st.p1;
+      st.tx = tw.tx;
+      st.pe = tw.padded_end();
+    }
+  }
+  const float b_re = cur.y.x * cur.tu.x - cur.y.y * cur.tu.y;   // row product W V Tu
+  const float b_im = cur.y.x * cur.tu.y + cur.y.y * cur.tu.x;
+  st.p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.tv.x, b_re, st.p1, 0, 0, 0);
+  st.p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.tv.y, b_im, st.p2, 0, 0, 0);
+  st.p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.tv.x + cur.tv.y, b_re + b_im, st.p3, 0, 0, 0);
+}
+
+// One work item of one gridding job; tu_tab / tv_tab are the padded tables
+// (in LDS or global memory).
+template <int S>
+__device__ __forceinline__ void grid_item(const GridArgs& a, float* ring, int it, int lane,
+                                          int col, int grp) {
+  constexpr int C = kRegion + 1 - S;
+  constexpr int H = S / 2;
+  const int4 item = a.items[it];
+  const int ty = uniform(item.x), s_end = uniform(item.z);
+  GridCtx c;
+  c.krec = a.krec;
+  c.yrow = a.yrow;
+  c.grid = reinterpret_cast<float*>(a.grid);
+  c.ring = ring;
+  c.tu_tab = a.tab_u;
+  c.tv_tab = a.tab_v;
+  c.N = a.N;
+  c.checker = a.checker;
+  c.s0 = uniform(item.y);
+  c.last = s_end - 1;
+  c.ng = (s_end - c.s0) >> 2;
+  c.by = ty * C;
+  c.lane = lane;
+  c.col = col;
+  c.grp = grp;
+  TileWalk tw;
+  tw.start(a.tdesc + (int64_t)ty * a.ntx, a.ntx, uniform(item.w), lane);
+  GridState st;
+  st.tx = tw.tx;
+  st.pe = tw.padded_end();
+  st.fx = st.tx * C - H;
+  st.p1 = f32x4{0.f, 0.f, 0.f, 0.f};
+  st.p2 = st.p1;
+  st.p3 = st.p1;
+
+  // records of batches 0..2 and W V of batches 0 and 1, one slot per lane
+  int4 r0 = c.krec[min(c.s0 + lane, c.last)];
+  int4 r1 = c.krec[min(c.s0 + 64 + lane, c.last)];
+  int4 r2 = c.krec[min(c.s0 + 128 + lane, c.last)];
+  float2 y0 = c.yrow[r0.z];
+  float2 y1 = c.yrow[r1.z];
+  GroupOps A, B;
+  fetch_group(c, r0, y0, 0, A);
+  int g = 0;
+  while (true) {
+    // the 16 groups of one batch; the last one fetches from the next batch
+    for (int p = 0; p < 7; ++p) {
+      grid_step<S>(c, g, r0, y0, tw, st, A, B);
+      if (++g >= c.ng) goto done;
+      grid_step<S>(c, g, r0, y0, tw, st, B, A);
+      if (++g >= c.ng) goto done;
+    }
+    grid_step<S>(c, g, r0, y0, tw, st, A, B);
+    if (++g >= c.ng) goto done;
+    grid_step<S>(c, g, r1, y1, tw, st, B, A);
+    if (++g >= c.ng) goto done;
+    // next batch: W V one batch ahead (its records arrived a batch ago),
+    // records two batches ahead
+    r0 = r1;
+    y0 = y1;
+    r1 = r2;
+    y1 = c.yrow[r1.z];
+    r2 = c.krec[min(c.s0 + 4 * g + 128 + lane, c.last)];
+  }
+done:
+  f32x4 re, im;
+  region_parts(st, re, im);
+  ring_add(c.ring, re, im, st.tx * C - H, col, grp);
+  ring_flush16(c.ring, st.fx, c.grid, c.by - H, c.N, c.checker, lane);
+  ring_flush16(c.ring, st.fx + 16, c.grid, c.by - H, c.N, c.checker, lane);
 }
 
 template <int S>
 __global__ __launch_bounds__(64 * kWaves) void grid_fp32_kernel(GridArgs a) {
-  const int lane = threadIdx.x & 63;
+  __shared__ float rings[kWaves * kRingFloats];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float* ring = rings + wave * kRingFloats;
+  for (int i = lane; i < kRingFloats; i += 64) ring[i] = 0.f;
   const int n_items = (int)*a.nitems;
   const int stride = gridDim.x * kWaves;
-  for (int it = uniform(blockIdx.x * kWaves + (threadIdx.x >> 6)); it < n_items; it += stride)
-    grid_item<S>(a, it, lane, lane & 15, lane >> 4);
+  for (int it = uniform(blockIdx.x * kWaves + wave); it < n_items; it += stride)
+    grid_item<S>(a, ring, it, lane, lane & 15, lane >> 4);
 }
 
 // Persistent launch over the work items of many jobs (facets, snapshots):
@@ -151,7 +265,10 @@ template <int S>
 __global__ __launch_bounds__(64 * kWaves) void grid_fp32_batched_kernel(
     const GridArgs* __restrict__ jobs, const uint32_t* __restrict__ first, int njobs,
     uint32_t* __restrict__ counter) {
+  __shared__ float rings[kWaves * kRingFloats];
   const int lane = threadIdx.x & 63;
+  float* ring = rings + (threadIdx.x >> 6) * kRingFloats;
+  for (int i = lane; i < kRingFloats; i += 64) ring[i] = 0.f;
   const uint32_t total = first[njobs];
   while (true) {
     uint32_t gi = 0;
@@ -164,13 +281,16 @@ __global__ __launch_bounds__(64 * kWaves) void grid_fp32_batched_kernel(
       if (first[mid] <= gi) lo = mid; else hi = mid - 1;
     }
     const int job = uniform(lo);
-    grid_item<S>(jobs[job], (int)(gi - first[job]), lane, lane & 15, lane >> 4);
+    grid_item<S>(jobs[job], ring, (int)(gi - first[job]), lane, lane & 15, lane >> 4);
   }
 }
 
 template <int S>
-hipError_t launch_s(const GridArgs& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(grid_fp32_kernel<S>, dim3(blocks), dim3(64 * kWaves), 0, s, a);
+hipError_t launch_s(const GridArgs& a, int64_t max_items, hipStream_t s) {
+  int64_t b = (max_items + kWaves - 1) / kWaves;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(grid_fp32_kernel<S>, dim3((unsigned)b), dim3(64 * kWaves), 0, s, a);
   return hipGetLastError();
 }
 
@@ -200,19 +320,15 @@ hipError_t launch_grid_fp32_batched(int S, const GridArgs* jobs, const uint32_t*
 }
 
 hipError_t launch_grid_fp32(int S, const GridArgs& a, int64_t max_items, hipStream_t s) {
-  int64_t b = (max_items + kWaves - 1) / kWaves;
-  if (b > 8192) b = 8192;
-  if (b < 1) b = 1;
-  const int blocks = (int)b;
   switch (S) {
-    case 1: return launch_s<1>(a, blocks, s);
-    case 3: return launch_s<3>(a, blocks, s);
-    case 5: return launch_s<5>(a, blocks, s);
-    case 7: return launch_s<7>(a, blocks, s);
-    case 9: return launch_s<9>(a, blocks, s);
-    case 11: return launch_s<11>(a, blocks, s);
-    case 13: return launch_s<13>(a, blocks, s);
-    case 15: return launch_s<15>(a, blocks, s);
+    case 1: return launch_s<1>(a, max_items, s);
+    case 3: return launch_s<3>(a, max_items, s);
+    case 5: return launch_s<5>(a, max_items, s);
+    case 7: return launch_s<7>(a, max_items, s);
+    case 9: return launch_s<9>(a, max_items, s);
+    case 11: return launch_s<11>(a, max_items, s);
+    case 13: return launch_s<13>(a, max_items, s);
+    case 15: return launch_s<15>(a, max_items, s);
     default: return hipErrorInvalidValue;
   }
 }

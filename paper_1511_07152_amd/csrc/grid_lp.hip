@@ -19,10 +19,15 @@
 //     over the tile's region, B = conj(Tu / s_k^u) (16-bit table); the FP32
 //     epilogue uses the v-table pre-multiplied by s_k^u and multiplies by s_R.
 // All tables are zero-padded so that the tap for region index x is base + x.
+// Work items are walked in chunks of at most 16 slots of one tile (walk.h);
+// slots past the tile's end in the last chunk carry zero weight (gridding) or
+// are not written (degridding).  Slot records (table bases and row-bin
+// position) run two chunks ahead of the arithmetic; W V, table rows and grid
+// regions one chunk ahead, in two alternating register buffers.
 // Layout of v_mfma_f32_16x16x16: lane l supplies A[l % 16][4 (l / 16) + m] and
 // B[4 (l / 16) + m][l % 16] for m = 0..3; accumulator register r of lane l is
 // D[4 (l / 16) + r][l % 16].
-#include "internal.h"
+#include "walk.h"
 
 namespace sepw {
 
@@ -33,8 +38,6 @@ typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef short i16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 4;
-
-__device__ inline int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 __device__ inline uint16_t bf16_rne(float x) {
   uint32_t u = __float_as_uint(x);
@@ -100,216 +103,306 @@ __device__ inline void flush_cols(float* g, const f32x4& re, const f32x4& im, fl
   }
 }
 
+__device__ inline ChunkPos first_chunk(const TileWalk& tw, int c0, int s_end) {
+  ChunkPos p;
+  p.c0 = c0;
+  p.pe = min(tw.padded_end(), s_end);
+  p.re = min(tw.real_end(), s_end);
+  p.tx = tw.tx;
+  p.ok = true;
+  return p;
+}
+
+// ---------------------------------------------------------------- gridding
+
+// Operands of one chunk for lane group grp: slots c0 + 4 grp + m.
+struct GridBuf {
+  int4 k[4];       // slot records, two chunks ahead
+  float2 y[4];     // W V
+  uint32_t tv[4];  // 16-bit v-table taps (re | im << 16) of the lane's row
+  float2 tu[4];    // FP32 u-table taps of the lane's column
+};
+
+struct LpCtx {
+  const int4* krec;
+  const float2* yrow;
+  int s_end, lane, col, grp;
+};
+
+__device__ __forceinline__ void load_grid_rec(const LpCtx& c, const ChunkPos& p, GridBuf& B) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) B.k[m] = c.krec[min(p.c0 + 4 * c.grp + m, p.pe - 1)];
+}
+
 template <int S, bool BF16>
-__global__ __launch_bounds__(64 * kWaves) void grid_lp_kernel(
-    const int4* __restrict__ items, const uint32_t* __restrict__ nitems,
-    const uint32_t* __restrict__ off, const uint2* __restrict__ rec,
-    const int2* __restrict__ krec, const float2* __restrict__ ybin,
-    const float2* __restrict__ rot, const float2* __restrict__ pad_us,
-    const uint32_t* __restrict__ lp_v, const float* __restrict__ lp_bound, int N, int ntx,
-    int checker, float2* __restrict__ grid) {
+__device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float bound, int it, int lane,
+                                             int col, int grp) {
   typedef Lp<BF16> L;
   typedef typename L::vec vec;
   constexpr int C = kRegion + 1 - S;
   constexpr int H = S / 2;
-  const int lane = threadIdx.x & 63;
-  const int col = lane & 15, grp = lane >> 4;
-  const int n_items = (int)*nitems;
-  const int stride = gridDim.x * kWaves;
-  const float bound = *lp_bound;
-  float* g = reinterpret_cast<float*>(grid);
+  const int N = a.N, checker = a.checker;
+  const uint32_t* __restrict__ lp_v = a.lp_v + col;
+  const float2* __restrict__ pad_us = a.pad_us + col;
+  float* g = reinterpret_cast<float*>(a.grid);
+  const int4 item = a.items[it];
+  const int ty = uniform(item.x), s_end = uniform(item.z);
+  const int by = ty * C;
+  LpCtx c{a.krec, a.yrow, s_end, lane, col, grp};
+  TileWalk tw;
+  tw.start(a.tdesc + (int64_t)ty * a.ntx, a.ntx, uniform(item.w), lane);
+  ChunkPos cur = first_chunk(tw, uniform(item.y), s_end);
+  ChunkPos n1 = next_chunk(cur, tw, s_end, lane);
+  ChunkPos n2 = next_chunk(n1, tw, s_end, lane);
 
-  for (int it = uniform(blockIdx.x * kWaves + (threadIdx.x >> 6)); it < n_items; it += stride) {
-    const int4 item = items[it];
-    const int ty = uniform(item.x), je = uniform(item.z);
-    int j = uniform(item.y);
-    const int by = ty * C;
-    int tx = uniform((int)(rec[j].x & 0xFFFFu) / C);
-    f32x4 acc_re = {0.f, 0.f, 0.f, 0.f}, acc_im = {0.f, 0.f, 0.f, 0.f};
-    float scale = 0.f;   // accumulator holds (true sum) / scale; 0 = not yet set
-    while (true) {
-      const int bx = tx * C;
-      const int tend = min(uniform((int)off[ty * ntx + tx + 1]), je);
-      for (int v0 = j; v0 < tend; v0 += 16) {
-        // lane's visibilities: v0 + 4 grp + m, m = 0..3 (the K slice it supplies)
-        float bre[4], bim[4], mx = 0.f;
-        vec a_re, a_im, a_nim;
+  int tx = cur.tx;
+  f32x4 acc_re = {0.f, 0.f, 0.f, 0.f}, acc_im = {0.f, 0.f, 0.f, 0.f};
+  float scale = 0.f;   // accumulator holds (true sum) / scale; 0 = not yet set
+
+  // One pipeline step: chunk cur from X while the records of n2 go into X.k
+  // and W V and taps of n1 (records Y.k, loaded one step earlier) into Y.
+  auto step = [&](GridBuf& X, GridBuf& Y) -> bool {
+    // X.k (this chunk's records) was used when its operands were fetched
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int v = v0 + 4 * grp + m;
-          int2 kr = make_int2(0, 0);
-          float2 y = make_float2(0.f, 0.f);
-          if (v < tend) {
-            kr = krec[v];
-            y = ybin[v];
-            if (rot) {
-              const float2 ro = rot[v];
-              y = make_float2(y.x * ro.x - y.y * ro.y, y.x * ro.y + y.y * ro.x);
-            }
-          }
-          const uint32_t tv = lp_v[kr.y + col];
-          const float2 tu = pad_us[kr.x + col];
-          bre[m] = y.x * tu.x - y.y * tu.y;   // row product (u-table times s_k^v)
-          bim[m] = y.x * tu.y + y.y * tu.x;
-          mx = fmaxf(mx, fmaxf(fabsf(y.x), fabsf(y.y)));
-          L::set_bits(a_re, m, (uint16_t)(tv & 0xFFFFu));
-          L::set_bits(a_im, m, (uint16_t)(tv >> 16));
-          L::set_bits(a_nim, m, (uint16_t)((tv >> 16) ^ 0x8000u));
-        }
-        mx = wave_max(mx) * bound;
-        if (mx > 0.f) {
-          const float sn = pow2_ceil(mx);
-          if (scale == 0.f) {
-            scale = sn;                     // accumulator is still zero
-          } else if (sn > scale) {
-            const float f = scale / sn;     // exact: both are powers of two
-            acc_re *= f;
-            acc_im *= f;
-            scale = sn;
-          }
-        }
-        const float inv = scale > 0.f ? 1.f / scale : 0.f;
-        vec b_re, b_im;
+    for (int m = 0; m < 4; ++m) X.k[m] = c.krec[min(n2.c0 + 4 * grp + m, n2.pe - 1)];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          L::set(b_re, m, bre[m] * inv);
-          L::set(b_im, m, bim[m] * inv);
-        }
-        acc_re = L::mfma(a_re, b_re, acc_re);
-        acc_im = L::mfma(a_re, b_im, acc_im);
-        acc_re = L::mfma(a_nim, b_im, acc_re);
-        acc_im = L::mfma(a_im, b_re, acc_im);
-      }
-      j = tend;
-      if (j >= je) break;
-      const int txn = uniform((int)(rec[j].x & 0xFFFFu) / C);
-      const int sh = (txn - tx) * C;
+    for (int m = 0; m < 4; ++m) {
+      Y.y[m] = c.yrow[Y.k[m].z];
+      Y.tv[m] = lp_v[Y.k[m].y];
+      Y.tu[m] = pad_us[Y.k[m].x];
+    }
+    if (cur.tx != tx) {
+      // slide the region to this chunk's tile
+      const int sh = (cur.tx - tx) * C;
+      flush_cols(g, acc_re, acc_im, scale, col, grp, tx * C - H, by - H, sh < 16 ? sh : 16, N,
+                 checker);
       if (sh >= 16) {
-        flush_cols(g, acc_re, acc_im, scale, col, grp, bx - H, by - H, 16, N, checker);
         acc_re = f32x4{0.f, 0.f, 0.f, 0.f};
         acc_im = f32x4{0.f, 0.f, 0.f, 0.f};
         scale = 0.f;
       } else {
-        flush_cols(g, acc_re, acc_im, scale, col, grp, bx - H, by - H, sh, N, checker);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           acc_re[r] = shift_cols(acc_re[r], lane, col, sh);
           acc_im[r] = shift_cols(acc_im[r], lane, col, sh);
         }
       }
-      tx = txn;
+      tx = cur.tx;
     }
-    flush_cols(g, acc_re, acc_im, scale, col, grp, tx * C - H, by - H, 16, N, checker);
+    // lane's visibilities: slots c0 + 4 grp + m (the K slice it supplies)
+    float bre[4], bim[4], mx = 0.f;
+    vec a_re, a_im, a_nim;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const bool in = cur.c0 + 4 * grp + m < cur.pe;   // slots past the tile carry no weight
+      const float2 y = in ? X.y[m] : make_float2(0.f, 0.f);
+      bre[m] = y.x * X.tu[m].x - y.y * X.tu[m].y;   // row product (u-table times s_k^v)
+      bim[m] = y.x * X.tu[m].y + y.y * X.tu[m].x;
+      mx = fmaxf(mx, fmaxf(fabsf(y.x), fabsf(y.y)));
+      L::set_bits(a_re, m, (uint16_t)(X.tv[m] & 0xFFFFu));
+      L::set_bits(a_im, m, (uint16_t)(X.tv[m] >> 16));
+      L::set_bits(a_nim, m, (uint16_t)((X.tv[m] >> 16) ^ 0x8000u));
+    }
+    mx = wave_max(mx) * bound;
+    if (mx > 0.f) {
+      const float sn = pow2_ceil(mx);
+      if (scale == 0.f) {
+        scale = sn;                     // accumulator is still zero
+      } else if (sn > scale) {
+        const float f = scale / sn;     // exact: both are powers of two
+        acc_re *= f;
+        acc_im *= f;
+        scale = sn;
+      }
+    }
+    const float inv = scale > 0.f ? 1.f / scale : 0.f;
+    vec b_re, b_im;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      L::set(b_re, m, bre[m] * inv);
+      L::set(b_im, m, bim[m] * inv);
+    }
+    acc_re = L::mfma(a_re, b_re, acc_re);
+    acc_im = L::mfma(a_re, b_im, acc_im);
+    acc_re = L::mfma(a_nim, b_im, acc_re);
+    acc_im = L::mfma(a_im, b_re, acc_im);
+    if (!n1.ok) return false;
+    cur = n1;
+    n1 = n2;
+    n2 = next_chunk(n2, tw, s_end, lane);
+    return true;
+  };
+
+  GridBuf A, B;
+  load_grid_rec(c, cur, A);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    A.y[m] = c.yrow[A.k[m].z];
+    A.tv[m] = lp_v[A.k[m].y];
+    A.tu[m] = pad_us[A.k[m].x];
   }
+  load_grid_rec(c, n1, B);
+  while (step(A, B) && step(B, A)) {
+  }
+  flush_cols(g, acc_re, acc_im, scale, col, grp, tx * C - H, by - H, 16, N, checker);
 }
 
 template <int S, bool BF16>
-__global__ __launch_bounds__(64 * kWaves) void degrid_lp_kernel(
-    const int4* __restrict__ items, const uint32_t* __restrict__ nitems,
-    const uint32_t* __restrict__ off, const uint2* __restrict__ rec,
-    const int2* __restrict__ krec, const float2* __restrict__ rot,
-    const float2* __restrict__ grid, const uint32_t* __restrict__ lp_u,
-    const float2* __restrict__ pad_vs, int N, int ntx, int checker,
-    float2* __restrict__ vbin) {
+__global__ __launch_bounds__(64 * kWaves) void grid_lp_kernel(GridArgsLp a) {
+  const int lane = threadIdx.x & 63;
+  const int n_items = (int)*a.nitems;
+  const int stride = gridDim.x * kWaves;
+  const float bound = *a.lp_bound;
+  for (int it = uniform(blockIdx.x * kWaves + (threadIdx.x >> 6)); it < n_items; it += stride)
+    grid_lp_item<S, BF16>(a, bound, it, lane, lane & 15, lane >> 4);
+}
+
+// ---------------------------------------------------------------- degridding
+
+// Region operand of the tile at column tx: lane (col, grp) holds
+// R[y = col][x = 4 grp + m] (zero outside the grid).  Only the loads are
+// issued here; the checkerboard sign is applied when the region is converted
+// to the 16-bit operand, so no wait is forced at the load.
+template <int S>
+__device__ inline void load_region_lp(const float2* __restrict__ grid, int N, int tx, int gy,
+                                      bool row_ok, int grp, float2 (&r)[4]) {
+  constexpr int C = kRegion + 1 - S;
+  constexpr int H = S / 2;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int gx = tx * C - H + 4 * grp + m;
+    float2 val = make_float2(0.f, 0.f);
+    if (row_ok && gx >= 0 && gx < N) val = grid[(int64_t)gy * N + gx];
+    r[m] = val;
+  }
+}
+
+struct DegridBuf {
+  int4 k;          // record of the lane's slot, two chunks ahead
+  uint32_t tu[4];  // 16-bit u-table taps x = 4 grp + m
+  float2 tv[4];    // FP32 v-table taps y = 4 grp + m (times s_k^u)
+  float2 reg[4];   // raw grid region of the chunk's tile
+  bool fresh;      // region loaded for this chunk, not yet converted
+};
+
+template <int S, bool BF16>
+__device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, int it, int lane, int col,
+                                               int grp) {
   typedef Lp<BF16> L;
   typedef typename L::vec vec;
   constexpr int C = kRegion + 1 - S;
   constexpr int H = S / 2;
-  const int lane = threadIdx.x & 63;
-  const int col = lane & 15, grp = lane >> 4;
-  const int n_items = (int)*nitems;
-  const int stride = gridDim.x * kWaves;
+  const int N = a.N, checker = a.checker;
+  const uint32_t* __restrict__ lp_u = a.lp_u + 4 * grp;      // taps x = 4 grp + m
+  const float2* __restrict__ pad_vs = a.pad_vs + 4 * grp;    // taps y = 4 grp + m
+  const int4* __restrict__ krec = a.krec;
+  const int4 item = a.items[it];
+  const int ty = uniform(item.x), s_end = uniform(item.z);
+  const int gy = ty * C - H + col;
+  const bool row_ok = gy >= 0 && gy < N;
+  TileWalk tw;
+  tw.start(a.tdesc + (int64_t)ty * a.ntx, a.ntx, uniform(item.w), lane);
+  ChunkPos cur = first_chunk(tw, uniform(item.y), s_end);
+  ChunkPos n1 = next_chunk(cur, tw, s_end, lane);
+  ChunkPos n2 = next_chunk(n1, tw, s_end, lane);
+  float sr = 1.f;
+  vec a_re, a_im;
 
-  for (int it = uniform(blockIdx.x * kWaves + (threadIdx.x >> 6)); it < n_items; it += stride) {
-    const int4 item = items[it];
-    const int ty = uniform(item.x), je = uniform(item.z);
-    int j = uniform(item.y);
-    const int by = ty * C;
-    const int gy = by - H + col;
-    const bool row_ok = gy >= 0 && gy < N;
-    while (j < je) {
-      const int tx = uniform((int)(rec[j].x & 0xFFFFu) / C);
-      const int bx = tx * C;
-      const int tend = min(uniform((int)off[ty * ntx + tx + 1]), je);
-      // A operand: R[y = col][x = 4 grp + m], scaled by a power of two
-      float rre[4], rim[4], mx = 0.f;
+  auto taps = [&](DegridBuf& B) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int gx = bx - H + 4 * grp + m;
-        float2 val = make_float2(0.f, 0.f);
-        if (row_ok && gx >= 0 && gx < N) {
-          val = grid[(int64_t)gy * N + gx];
-          if (checker && ((gx + gy) & 1)) val = make_float2(-val.x, -val.y);
-        }
-        rre[m] = val.x;
-        rim[m] = val.y;
-        mx = fmaxf(mx, fmaxf(fabsf(val.x), fabsf(val.y)));
-      }
-      mx = wave_max(mx);
-      const float sr = mx > 0.f ? pow2_ceil(mx) : 1.f;
-      const float inv = 1.f / sr;
-      vec a_re, a_im;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        L::set(a_re, m, rre[m] * inv);
-        L::set(a_im, m, rim[m] * inv);
-      }
-      for (int v0 = j; v0 < tend; v0 += 16) {
-        const int v = v0 + col;   // this lane's visibility (column of Z)
-        const bool valid = v < tend;
-        const int2 kr = valid ? krec[v] : make_int2(0, 0);
-        vec b_re, b_im, b_nim;
-        float2 tv[4];
+    for (int m = 0; m < 4; ++m) {
+      B.tu[m] = lp_u[B.k.x + m];
+      B.tv[m] = pad_vs[B.k.y + m];
+    }
+  };
+  // One pipeline step: chunk cur from X while the record of n2 goes into X.k
+  // and the taps (and on a tile change the region) of n1 into Y.
+  auto step = [&](DegridBuf& X, DegridBuf& Y) -> bool {
+    const int4 kc = X.k;
+    X.k = krec[min(n2.c0 + col, n2.pe - 1)];
+    taps(Y);
+    if (X.fresh) {
+      // A operand: R (-1)^(x + y) / s_R with s_R a power of two covering the region
+      if (checker) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          const uint32_t tu = lp_u[kr.x + 4 * grp + m];
-          tv[m] = pad_vs[kr.y + 4 * grp + m];
-          L::set_bits(b_re, m, (uint16_t)(tu & 0xFFFFu));
-          L::set_bits(b_im, m, (uint16_t)(tu >> 16));
-          L::set_bits(b_nim, m, (uint16_t)((tu >> 16) ^ 0x8000u));
-        }
-        // Z = R conj(Tu): re = Rre Tre + Rim Tim, im = Rim Tre - Rre Tim
-        f32x4 z_re = {0.f, 0.f, 0.f, 0.f}, z_im = {0.f, 0.f, 0.f, 0.f};
-        z_re = L::mfma(a_re, b_re, z_re);
-        z_im = L::mfma(a_im, b_re, z_im);
-        z_re = L::mfma(a_im, b_im, z_re);
-        z_im = L::mfma(a_re, b_nim, z_im);
-        float p_re = 0.f, p_im = 0.f;
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          p_re += tv[rr].x * z_re[rr] + tv[rr].y * z_im[rr];
-          p_im += tv[rr].x * z_im[rr] - tv[rr].y * z_re[rr];
-        }
-        p_re += __shfl_xor(p_re, 16, 64);
-        p_im += __shfl_xor(p_im, 16, 64);
-        p_re += __shfl_xor(p_re, 32, 64);
-        p_im += __shfl_xor(p_im, 32, 64);
-        if (grp == 0 && valid) {
-          float2 out = make_float2(p_re * sr, p_im * sr);
-          if (rot) {
-            const float2 ro = rot[v];
-            out = make_float2(out.x * ro.x + out.y * ro.y, out.y * ro.x - out.x * ro.y);
-          }
-          vbin[v] = out;
+          const int gx = cur.tx * C - H + 4 * grp + m;
+          if ((gx + gy) & 1) X.reg[m] = make_float2(-X.reg[m].x, -X.reg[m].y);
         }
       }
-      j = tend;
+      float mx = 0.f;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) mx = fmaxf(mx, fmaxf(fabsf(X.reg[m].x), fabsf(X.reg[m].y)));
+      mx = wave_max(mx);
+      sr = mx > 0.f ? pow2_ceil(mx) : 1.f;
+      const float inv = 1.f / sr;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        L::set(a_re, m, X.reg[m].x * inv);
+        L::set(a_im, m, X.reg[m].y * inv);
+      }
     }
+    Y.fresh = n1.ok && n1.tx != cur.tx;
+    if (Y.fresh) load_region_lp<S>(a.grid, N, n1.tx, gy, row_ok, grp, Y.reg);
+    vec b_re, b_im, b_nim;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      L::set_bits(b_re, m, (uint16_t)(X.tu[m] & 0xFFFFu));
+      L::set_bits(b_im, m, (uint16_t)(X.tu[m] >> 16));
+      L::set_bits(b_nim, m, (uint16_t)((X.tu[m] >> 16) ^ 0x8000u));
+    }
+    // Z = R conj(Tu): re = Rre Tre + Rim Tim, im = Rim Tre - Rre Tim
+    f32x4 z_re = {0.f, 0.f, 0.f, 0.f}, z_im = {0.f, 0.f, 0.f, 0.f};
+    z_re = L::mfma(a_re, b_re, z_re);
+    z_im = L::mfma(a_im, b_re, z_im);
+    z_re = L::mfma(a_im, b_im, z_re);
+    z_im = L::mfma(a_re, b_nim, z_im);
+    float p_re = 0.f, p_im = 0.f;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      p_re += X.tv[rr].x * z_re[rr] + X.tv[rr].y * z_im[rr];
+      p_im += X.tv[rr].x * z_im[rr] - X.tv[rr].y * z_re[rr];
+    }
+    p_re += __shfl_xor(p_re, 16, 64);
+    p_im += __shfl_xor(p_im, 16, 64);
+    p_re += __shfl_xor(p_re, 32, 64);
+    p_im += __shfl_xor(p_im, 32, 64);
+    if (grp == 0 && cur.c0 + col < cur.re) a.yrow[kc.z] = make_float2(p_re * sr, p_im * sr);
+    if (!n1.ok) return false;
+    cur = n1;
+    n1 = n2;
+    n2 = next_chunk(n2, tw, s_end, lane);
+    return true;
+  };
+
+  DegridBuf A, B;
+  A.k = krec[min(cur.c0 + col, cur.pe - 1)];
+  taps(A);
+  load_region_lp<S>(a.grid, N, cur.tx, gy, row_ok, grp, A.reg);
+  A.fresh = true;
+  B.k = krec[min(n1.c0 + col, n1.pe - 1)];
+  B.fresh = false;
+  while (step(A, B) && step(B, A)) {
   }
 }
 
 template <int S, bool BF16>
+__global__ __launch_bounds__(64 * kWaves) void degrid_lp_kernel(DegridArgsLp a) {
+  const int lane = threadIdx.x & 63;
+  const int n_items = (int)*a.nitems;
+  const int stride = gridDim.x * kWaves;
+  for (int it = uniform(blockIdx.x * kWaves + (threadIdx.x >> 6)); it < n_items; it += stride)
+    degrid_lp_item<S, BF16>(a, it, lane, lane & 15, lane >> 4);
+}
+
+template <int S, bool BF16>
 void launch_grid_s(const GridArgsLp& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((grid_lp_kernel<S, BF16>), dim3(blocks), dim3(64 * kWaves), 0, s, a.items,
-                     a.nitems, a.off, a.rec, a.krec, a.ybin, a.rot, a.pad_us, a.lp_v, a.lp_bound,
-                     a.N, a.ntx, a.checker, a.grid);
+  hipLaunchKernelGGL((grid_lp_kernel<S, BF16>), dim3(blocks), dim3(64 * kWaves), 0, s, a);
 }
 
 template <int S, bool BF16>
 void launch_degrid_s(const DegridArgsLp& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((degrid_lp_kernel<S, BF16>), dim3(blocks), dim3(64 * kWaves), 0, s, a.items,
-                     a.nitems, a.off, a.rec, a.krec, a.rot, a.grid, a.lp_u, a.pad_vs, a.N, a.ntx,
-                     a.checker, a.vbin);
+  hipLaunchKernelGGL((degrid_lp_kernel<S, BF16>), dim3(blocks), dim3(64 * kWaves), 0, s, a);
 }
 
 int blocks_for(int64_t max_items) {

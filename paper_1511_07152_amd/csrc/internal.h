@@ -63,6 +63,9 @@ struct Kernels {
   float2* pad_vs = nullptr;
   float* lp_bound = nullptr;
   float2* scratch = nullptr;   // N*N complex64 work grid for degridding
+  int tab_len = 0;             // entries of one padded table (P O L)
+  int lds_bytes = 0;           // > 0: the FP32 kernels stage the tables in LDS
+  int n_cu = 0;                // compute units of the device
   hipfftHandle fft = 0;
   bool fft_ok = false;
   uint64_t generation = 0;     // bumped when the tables are regenerated
@@ -73,6 +76,7 @@ struct Plan {
   uint64_t generation = 0;      // K->generation the bins were made for
   int64_t nvis = 0;
   int64_t capacity = 0;         // visibilities the buffers were sized for
+  int64_t pcap = 0;             // tile slots the slot-order buffers were sized for
   int tile_c = 0, ntx = 0, nty = 0;
   int64_t ntiles = 0;
   int64_t max_items = 0;
@@ -80,22 +84,21 @@ struct Plan {
   uint32_t* key = nullptr;      // [nvis] tile id or kDropped (caller order)
   uint2* qrec = nullptr;        // [nvis] packed bins (caller order)
   uint32_t* rowcount = nullptr; // [nbins + 1] level-1 histogram
-  uint32_t* rowoff = nullptr;   // [nbins + 1] its exclusive scan
+  uint32_t* rowoff = nullptr;   // [nbins + 1] its exclusive scan; rowoff[nbins] = kept count
   uint32_t* rowcursor = nullptr;// [nbins + 1] level-1 placement cursors
+  uint32_t* rowpad = nullptr;   // [nbins + 1] tile slots reserved per row bin
+  uint32_t* prowoff = nullptr;  // [nbins + 1] exclusive scan of rowpad
   uint2* rrec = nullptr;        // [nvis] records sorted by row bin
-  int32_t* rperm = nullptr;     // [nvis] caller index sorted by row bin
   uint32_t* to_row = nullptr;   // [nvis] caller index -> row-bin position (or kDropped)
-  uint32_t* to_tile = nullptr;  // [nvis] row-bin position -> tile-order position
-  float2* tmp = nullptr;        // [nvis] row-bin-order staging for W V / results
-  float2* ybin = nullptr;       // [nvis] tile-order W V (grid) or results (degrid)
-  uint32_t* off = nullptr;      // [ntiles + 1] first binned visibility of each tile
-  uint2* rec = nullptr;         // [nvis] packed bins, binned order
-  int2* krec = nullptr;         // [nvis] padded-table base offsets (u, v) relative to the tile
-  int32_t* perm = nullptr;      // [nvis] caller index, binned order
-  float2* rot = nullptr;        // [nvis] facet phase rotation, binned order
+  float2* yrow = nullptr;       // [capacity + 1] row-bin-order W V (grid) or results (degrid);
+                                // yrow[capacity] stays 0 (the padding slots point there)
+  int4* krec = nullptr;         // [pcap] per tile slot: padded-table bases (u, v) relative to
+                                // the tile and the row-bin position of its W V
+  uint2* tdesc = nullptr;       // [ntiles] (first slot, first slot + count) per tile
+  float2* rot = nullptr;        // [nvis] facet phase rotation, caller order
   uint32_t* nit = nullptr;      // [nty + 1] work items per row of tiles
   uint32_t* itoff = nullptr;    // [nty + 1] exclusive scan of nit
-  int4* items = nullptr;        // [max_items] (tile row, first vis, end vis, 0)
+  int4* items = nullptr;        // [max_items] (tile row, first slot, end slot, tile column)
   uint32_t* scan_tmp = nullptr; // block partials for the scans
   int64_t scan_tmp_len = 0;
 };
@@ -123,42 +126,47 @@ hipError_t launch_zero_c64(float2* p, int64_t n, hipStream_t s);
 hipError_t launch_quantise_rows(const double* u, const double* v, const double* w, int64_t nvis,
                                 QuantGeom g, int rshift, int nbins, uint32_t* key, uint2* qrec,
                                 uint32_t* rowcount, hipStream_t s);
+// rowpad[b] = slots reserved for row bin b (count + padding room, multiple of 4)
+hipError_t launch_pad_sizes(const uint32_t* rowcount, int nbins, int rshift, int ntx, int nty,
+                            uint32_t* rowpad, hipStream_t s);
 hipError_t launch_row_scatter(const uint32_t* key, const uint2* qrec, int64_t nvis, int ntx,
                               int rshift, int nbins, uint32_t* rowcursor, uint2* rrec,
-                              int32_t* rperm, uint32_t* to_row, hipStream_t s);
-hipError_t launch_row_sort(const uint32_t* rowoff, const uint2* rrec, const int32_t* rperm,
+                              uint32_t* to_row, hipStream_t s);
+// zero_row: row-bin position the padding slots point to (a W V that stays 0)
+hipError_t launch_row_sort(const uint32_t* rowoff, const uint32_t* prowoff, const uint2* rrec,
                            int rshift, int nbins, int ntx, int nty, int tile_c, int O, int S,
-                           uint32_t* off, uint2* rec, int32_t* perm, uint32_t* to_tile, int2* krec,
-                           hipStream_t s);
-// caller-order W V -> tile order (two passes through the sort's placement maps)
-hipError_t launch_vis_to_tiles(const float2* vis, const float* weight, const uint32_t* to_row,
-                               const uint32_t* to_tile, const uint32_t* nkept, int64_t nvis,
-                               float2* tmp, float2* ybin, hipStream_t s);
-// tile-order results -> caller order (dropped visibilities get 0)
-hipError_t launch_vis_from_tiles(const float2* vbin, const uint32_t* to_row,
-                                 const uint32_t* to_tile, const uint32_t* nkept, int64_t nvis,
-                                 float2* tmp, float2* out, hipStream_t s);
+                           uint32_t zero_row, uint2* tdesc, int4* krec, hipStream_t s);
+// caller-order W V (times the facet rotation) -> row-bin order
+hipError_t launch_vis_to_rows(const float2* vis, const float* weight, const float2* rot,
+                              const uint32_t* to_row, int64_t nvis, float2* yrow, hipStream_t s);
+// row-bin-order results -> caller order, rotation undone (dropped visibilities get 0)
+hipError_t launch_vis_from_rows(const float2* yrow, const float2* rot, const uint32_t* to_row,
+                                int64_t nvis, float2* out, hipStream_t s);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t s);
 int64_t scan_tmp_size(int64_t n);
-hipError_t launch_rotation(const double* u, const double* v, const double* w, const int32_t* perm,
-                           const uint32_t* nkept, int64_t nvis, QuantGeom g, float2* rot, hipStream_t s);
-// work items: slices of <= kItemMaxVis visibilities of each row of tiles
-hipError_t launch_item_counts(const uint32_t* off, int ntx, int nty, uint32_t* nit, hipStream_t s);
-hipError_t launch_items(const uint32_t* off, const uint32_t* itoff, int ntx, int nty, int4* items,
+hipError_t launch_rotation(const double* u, const double* v, const double* w, int64_t nvis,
+                           QuantGeom g, float2* rot, hipStream_t s);
+// work items: slices of <= kItemMaxVis slots of each row of tiles
+hipError_t launch_item_counts(const uint2* tdesc, int ntx, int nty, uint32_t* nit, hipStream_t s);
+hipError_t launch_items(const uint2* tdesc, const uint32_t* itoff, int ntx, int nty, int4* items,
                         hipStream_t s);
-hipError_t launch_bins_export(const uint2* rec, const int32_t* perm, const uint32_t* nkept,
-                              int64_t nvis, int tile_c, int ntx, int32_t* out, hipStream_t s);
+hipError_t launch_bins_export(const uint2* rrec, const uint32_t* to_row, int64_t nvis, int tile_c,
+                              int ntx, int32_t* out, hipStream_t s);
+
+// Arguments shared by the gridding and degridding kernels.  Work item it =
+// items[it] = (tile row, first slot, end slot, tile column of the first slot);
+// the slots of a row of tiles are contiguous, tile by tile, each tile padded
+// to a multiple of 4 slots.
 struct GridArgs {
   const int4* items;
   const uint32_t* nitems;   // device count of items
-  const uint32_t* off;      // per-tile offsets into the binned arrays
-  const uint2* rec;         // cells (tile walk)
-  const int2* krec;         // padded-table bases
-  const float2* ybin;       // W V in binned order
-  const float2* rot;        // binned order, may be null
+  const uint2* tdesc;       // per tile (first slot, first slot + count)
+  const int4* krec;         // per slot (u base, v base, row-bin position, 0)
+  const float2* yrow;       // W V in row-bin order
   const float2* tab_u;      // padded tables
   const float2* tab_v;
-  int O, N, ntx;
+  int tab_len;              // entries of one padded table (P O L)
+  int N, ntx;
   int checker;              // apply (-1)^(x+y) for the centred FFT
   float2* grid;
 };
@@ -166,30 +174,27 @@ struct GridArgs {
 struct DegridArgs {
   const int4* items;
   const uint32_t* nitems;
-  const uint32_t* off;
-  const uint2* rec;
-  const int2* krec;
-  const float2* rot;
+  const uint2* tdesc;
+  const int4* krec;
   const float2* grid;
   const float2* tab_u;      // padded tables
   const float2* tab_v;
-  int O, N, ntx;
+  int tab_len;
+  int N, ntx;
   int checker;
-  float2* vbin;             // results in binned order
+  float2* yrow;             // results in row-bin order (padding slots are not written)
 };
 
 struct GridArgsLp {
   const int4* items;
   const uint32_t* nitems;
-  const uint32_t* off;
-  const uint2* rec;
-  const int2* krec;
-  const float2* ybin;
-  const float2* rot;
+  const uint2* tdesc;
+  const int4* krec;
+  const float2* yrow;
   const float2* pad_us;     // FP32 padded u-table times s_k^v (row product in FP32)
   const uint32_t* lp_v;     // 16-bit padded v-table / s_k^v, packed (re | im << 16)
   const float* lp_bound;    // max_k s_k^u s_k^v
-  int O, N, ntx;
+  int N, ntx;
   int checker;
   float2* grid;
 };
@@ -197,16 +202,14 @@ struct GridArgsLp {
 struct DegridArgsLp {
   const int4* items;
   const uint32_t* nitems;
-  const uint32_t* off;
-  const uint2* rec;
-  const int2* krec;
-  const float2* rot;
+  const uint2* tdesc;
+  const int4* krec;
   const float2* grid;
   const uint32_t* lp_u;     // 16-bit padded u-table / s_k^u
   const float2* pad_vs;     // FP32 padded v-table times s_k^u (epilogue)
-  int O, N, ntx;
+  int N, ntx;
   int checker;
-  float2* vbin;
+  float2* yrow;
 };
 
 hipError_t launch_grid_fp32(int S, const GridArgs& a, int64_t max_items, hipStream_t s);
@@ -230,7 +233,10 @@ hipError_t launch_lp_table(const float2* tab, const float* scale, int P, int O, 
                            uint32_t* out, hipStream_t s);
 // lp_bound = max_k su[k] sv[k]
 hipError_t launch_lp_bound(const float* su, const float* sv, int P, float* bound, hipStream_t s);
-hipError_t launch_degrid_fp32(int S, const DegridArgs& a, int64_t max_items, hipStream_t s);
+// lds_bytes > 0: stage both padded tables (2 tab_len entries, or one table when
+// tab_u == tab_v) in LDS, with workgroups that own a whole CU
+hipError_t launch_degrid_fp32(int S, const DegridArgs& a, int64_t max_items, int lds_bytes,
+                              int n_cu, hipStream_t s);
 
 // out[q][p] = in[q][p] (-1)^(p+q) n(l0 + l_p, m0 + m_q)^npow / (c1[p] c1[q])
 hipError_t launch_correct(const float2* in, float2* out, const double* c1, int N, double fov,

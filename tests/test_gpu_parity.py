@@ -1,8 +1,11 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
-Tolerances (relative RMS unless stated): tables and grids 1e-6, images over
-the inner half (|l|,|m| <= fov/4, where 1/(c1 c1) does not amplify FP32
-rounding) 1e-5, degridded visibilities 1e-5, bins bit-exact.
+Tolerances (relative RMS unless stated): tables 1e-6; grids, images over the
+inner half (|l|,|m| <= fov/4, where 1/(c1 c1) does not amplify FP32 rounding)
+and degridded visibilities 1e-5, the FP32 bound; bins bit-exact.  A grid cell
+sums up to thousands of FP32 products (in the three-multiplication complex
+form), whose rounding alone reaches a few 1e-6 relative on heavy tiles
+(about sqrt(K) 2^-24 for K terms), so grids share the 1e-5 bound.
 """
 import math
 
@@ -120,7 +123,7 @@ def test_grid_only_matches_oracle(lib, nvis):
     G = lib.grid(plan, dev(d["V"], torch.complex64), dev(d["W"], torch.float32),
                  flags=lib.GRID_ONLY).cpu().numpy()
     want = _oracle(d, plan).grid(d["V"], d["W"])
-    assert rel_rms(G, want) <= 1e-6
+    assert rel_rms(G, want) <= 1e-5
 
 
 def test_grid_heavy_tile_and_weights(lib):
@@ -137,7 +140,7 @@ def test_grid_heavy_tile_and_weights(lib):
     K, plan = _make(lib, d)
     G = lib.grid(plan, dev(d["V"], torch.complex64), dev(d["W"], torch.float32),
                  flags=lib.GRID_ONLY).cpu().numpy()
-    assert rel_rms(G, _oracle(d, plan).grid(d["V"], d["W"])) <= 1e-6
+    assert rel_rms(G, _oracle(d, plan).grid(d["V"], d["W"])) <= 1e-5
 
 
 @pytest.mark.parametrize("flags,npow", [(0, 0), ("MUL_N", 1), ("DIV_N", -1)])
@@ -249,7 +252,7 @@ def test_odd_tile_layout(lib):
     o = _oracle(d, plan)
     assert np.array_equal(plan.bins().cpu().numpy().astype(np.int64), o.bins_array())
     G = lib.grid(plan, dev(d["V"], torch.complex64), None, flags=lib.GRID_ONLY).cpu().numpy()
-    assert rel_rms(G, o.grid(d["V"], d["W"])) <= 1e-6
+    assert rel_rms(G, o.grid(d["V"], d["W"])) <= 1e-5
     X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
     V = lib.degrid(plan, dev(X, torch.complex64), flags=lib.GRID_ONLY).cpu().numpy()
     assert rel_rms(V, o.degrid_grid(X)) <= 1e-5
