@@ -158,6 +158,7 @@ void destroy_plan(Plan* p) {
   dfree(p->rowcount);
   dfree(p->rowoff);
   dfree(p->rowcursor);
+  dfree(p->blkbase);
   dfree(p->rowpad);
   dfree(p->prowoff);
   dfree(p->rrec);
@@ -353,6 +354,7 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
   SEPW_TRY(dalloc(&P->rowcount, P->nbins + 1));
   SEPW_TRY(dalloc(&P->rowoff, P->nbins + 1));
   SEPW_TRY(dalloc(&P->rowcursor, P->nbins + 1));
+  SEPW_TRY(dalloc(&P->blkbase, ((capacity + kL1Chunk - 1) / kL1Chunk + 1) * (int64_t)P->nbins));
   SEPW_TRY(dalloc(&P->rowpad, P->nbins + 1));
   SEPW_TRY(dalloc(&P->prowoff, P->nbins + 1));
   SEPW_TRY(dalloc(&P->rrec, capacity));
@@ -389,7 +391,7 @@ int bin_plan(Plan* P, int64_t nvis, const double* u, const double* v, const doub
     SEPW_TRY(launch_pad_sizes(P->rowcount, P->nbins, P->rshift, P->ntx, P->nty, P->rowpad, s));
     SEPW_TRY(launch_scan(P->rowpad, P->prowoff, P->nbins + 1, P->scan_tmp, s));
     SEPW_TRY(launch_row_scatter(P->key, P->qrec, nvis, P->ntx, P->rshift, P->nbins, P->rowcursor,
-                                P->rrec, P->to_row, s));
+                                P->blkbase, P->rrec, P->to_row, s));
     // padding slots point at yrow[capacity], which nothing writes: keep it 0
     SEPW_TRY(launch_zero_c64(P->yrow + P->capacity, 1, s));
     SEPW_TRY(launch_row_sort(P->rowoff, P->prowoff, P->rrec, P->rshift, P->nbins, P->ntx, P->nty,
@@ -572,8 +574,9 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
   if (p->generation != K->generation) return SEPW_ERR_ARG;
   {
     Stage st(SEPW_STAGE_GATHER, s);
-    SEPW_TRY(launch_vis_to_rows(reinterpret_cast<const float2*>(vis), weight, p->rot, p->to_row,
-                                p->nvis, p->yrow, s));
+    SEPW_TRY(launch_vis_to_rows(reinterpret_cast<const float2*>(vis), weight, p->rot, p->key,
+                                p->to_row, p->blkbase, p->nvis, p->ntx, p->rshift, p->nbins,
+                                p->yrow, s));
   }
   {
     Stage st(SEPW_STAGE_FILL, s);
@@ -645,7 +648,8 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
   }
   {
     Stage st(SEPW_STAGE_GATHER, s);
-    SEPW_TRY(launch_vis_from_rows(p->yrow, p->rot, p->to_row, p->nvis, vo, s));
+    SEPW_TRY(launch_vis_from_rows(p->yrow, p->rot, p->key, p->to_row, p->blkbase, p->nvis, p->ntx,
+                                  p->rshift, p->nbins, vo, s));
   }
   return SEPW_OK;
 }
@@ -687,8 +691,8 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
     for (int j = 0; j < njobs; ++j) {
       Plan* p = plans[j];
       SEPW_TRY(launch_vis_to_rows(reinterpret_cast<const float2*>(vis[j]),
-                                  weight ? weight[j] : nullptr, p->rot, p->to_row, p->nvis, p->yrow,
-                                  s));
+                                  weight ? weight[j] : nullptr, p->rot, p->key, p->to_row,
+                                  p->blkbase, p->nvis, p->ntx, p->rshift, p->nbins, p->yrow, s));
     }
   }
   {

@@ -250,7 +250,51 @@ __global__ void bins_export_kernel(const uint2* __restrict__ rrec, const uint32_
 
 // ---------------------------------------------------------------- two-level sort
 constexpr int kL1Threads = 1024;
-constexpr int kChunk = kL1Threads * 32;  // visibilities per block in the level-1 passes
+constexpr int kChunk = kL1Chunk;         // visibilities per block in the level-1 passes
+static_assert(kChunk % kL1Threads == 0, "level-1 chunk must be a multiple of the block size");
+
+// Exclusive scan of a[0, n) (n <= kMaxRowBins) by one 1024-thread workgroup,
+// in place; each thread owns kMaxRowBins / 1024 consecutive entries.
+__device__ inline void block_scan_bins(uint32_t* a, int n, uint32_t* wsum) {
+  constexpr int kPer = kMaxRowBins / kL1Threads;
+  const int t0 = threadIdx.x * kPer;
+  uint32_t v[kPer], sum = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    v[j] = t0 + j < n ? a[t0 + j] : 0u;
+    sum += v[j];
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  uint32_t run = x - sum;
+  for (int w = 0; w < wave; ++w) run += wsum[w];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    if (t0 + j < n) a[t0 + j] = run;
+    run += v[j];
+  }
+  __syncthreads();
+}
+
+// Per-block bin counts of the kept visibilities of chunk [first, first + kChunk).
+__device__ inline void chunk_hist(const uint32_t* __restrict__ key, int64_t first, int64_t nvis,
+                                  int ntx, int rshift, int nbins, uint32_t* cnt) {
+  for (int b = threadIdx.x; b < nbins; b += kL1Threads) cnt[b] = 0u;
+  __syncthreads();
+  for (int m = 0; m < kChunk / kL1Threads; ++m) {
+    const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
+    if (i >= nvis) break;
+    const uint32_t kk = key[i];
+    if (kk != kDropped) atomicAdd(&cnt[(kk / (uint32_t)ntx) >> rshift], 1u);
+  }
+  __syncthreads();
+}
 
 __global__ __launch_bounds__(kL1Threads) void quantise_rows_kernel(
     const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
@@ -309,27 +353,30 @@ __global__ void pad_sizes_kernel(const uint32_t* __restrict__ rowcount, int nbin
   }
 }
 
+// Level-1 placement.  Each block reserves one contiguous run per row bin for
+// its chunk (one global atomic per bin), records the run starts in blkbase,
+// lays its records out in LDS in bin order and then copies each bin's run to
+// the row-bin array as one contiguous piece.
 __global__ __launch_bounds__(kL1Threads) void row_scatter_kernel(
     const uint32_t* __restrict__ key, const uint2* __restrict__ qrec, int64_t nvis, int ntx,
-    int rshift, int nbins, uint32_t* __restrict__ rowcursor, uint2* __restrict__ rrec,
-    uint32_t* __restrict__ to_row) {
-  __shared__ uint32_t hist[kMaxRowBins];
-  __shared__ uint32_t base[kMaxRowBins];
-  for (int b = threadIdx.x; b < nbins; b += kL1Threads) hist[b] = 0u;
-  __syncthreads();
+    int rshift, int nbins, uint32_t* __restrict__ rowcursor, uint32_t* __restrict__ blkbase,
+    uint2* __restrict__ rrec, uint32_t* __restrict__ to_row) {
+  __shared__ uint32_t pre[kMaxRowBins];    // counts, then run starts inside the chunk
+  __shared__ uint32_t cur[kMaxRowBins];    // placement cursors, then run ends
+  __shared__ uint32_t base[kMaxRowBins];   // run starts in the row-bin array
+  __shared__ uint32_t wsum[kL1Threads / 64];
+  __shared__ uint2 stage[kChunk];
+  __shared__ uint16_t binof[kChunk];   // row bin of each staged record
   const int64_t first = (int64_t)blockIdx.x * kChunk;
-  for (int m = 0; m < kChunk / kL1Threads; ++m) {
-    const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
-    if (i >= nvis) break;
-    const uint32_t kk = key[i];
-    if (kk != kDropped) atomicAdd(&hist[(kk / (uint32_t)ntx) >> rshift], 1u);
-  }
-  __syncthreads();
+  chunk_hist(key, first, nvis, ntx, rshift, nbins, pre);
   for (int b = threadIdx.x; b < nbins; b += kL1Threads) {
-    const uint32_t c = hist[b];
-    base[b] = c ? atomicAdd(&rowcursor[b], c) : 0u;   // one reservation per bin and block
-    hist[b] = 0u;
+    const uint32_t c = pre[b];
+    const uint32_t r = c ? atomicAdd(&rowcursor[b], c) : 0u;   // one reservation per bin and block
+    base[b] = r;
+    blkbase[(int64_t)blockIdx.x * nbins + b] = r;
   }
+  block_scan_bins(pre, nbins, wsum);
+  for (int b = threadIdx.x; b < nbins; b += kL1Threads) cur[b] = pre[b];
   __syncthreads();
   for (int m = 0; m < kChunk / kL1Threads; ++m) {
     const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
@@ -340,9 +387,17 @@ __global__ __launch_bounds__(kL1Threads) void row_scatter_kernel(
       continue;
     }
     const uint32_t b = (kk / (uint32_t)ntx) >> rshift;
-    const uint32_t pos = base[b] + atomicAdd(&hist[b], 1u);
-    rrec[pos] = qrec[i];
-    to_row[i] = pos;
+    const uint32_t idx = atomicAdd(&cur[b], 1u);
+    stage[idx] = qrec[i];
+    binof[idx] = (uint16_t)b;
+    to_row[i] = base[b] + (idx - pre[b]);
+  }
+  __syncthreads();
+  // copy out: consecutive lanes take consecutive staged records (runs stay contiguous)
+  const uint32_t kept = cur[nbins - 1];
+  for (uint32_t k = threadIdx.x; k < kept; k += kL1Threads) {
+    const uint32_t b = binof[k];
+    rrec[base[b] + (k - pre[b])] = stage[k];
   }
 }
 
@@ -413,20 +468,47 @@ __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
 }
 
 // ---------------------------------------------------------------- moving data
-// Caller order <-> row-bin order through the level-1 placement map: reads and
-// writes on the caller side are coalesced, the row-bin side is written (read)
-// in runs per block and bin.  The gridding kernels read W V, and the
-// degridding kernels write their results, at the row-bin positions held in
-// the tile slots.
+// Caller order <-> row-bin order through the level-1 placement map.  A
+// workgroup handles the same chunk of kChunk caller positions as the level-1
+// placement, whose visibilities went to one contiguous run per row bin (run
+// starts in blkbase): it stages the chunk in LDS in bin order and moves each
+// run as one contiguous piece, while the caller side stays coalesced.  The
+// gridding kernels read W V, and the degridding kernels write their results,
+// at the row-bin positions held in the tile slots.
+
+// Run starts (row-bin array) and starts inside the chunk of this block's runs.
+__device__ inline void chunk_runs(const uint32_t* __restrict__ key,
+                                  const uint32_t* __restrict__ blkbase, int64_t first,
+                                  int64_t nvis, int ntx, int rshift, int nbins, uint32_t* cnt,
+                                  uint32_t* pre, uint32_t* base, uint32_t* wsum) {
+  chunk_hist(key, first, nvis, ntx, rshift, nbins, cnt);
+  for (int b = threadIdx.x; b < nbins; b += kL1Threads) {
+    pre[b] = cnt[b];
+    base[b] = blkbase[(int64_t)blockIdx.x * nbins + b];
+  }
+  __syncthreads();
+  block_scan_bins(pre, nbins, wsum);
+}
 
 // yrow[to_row[i]] = V[i] W[i] rot[i]
-__global__ void to_rows_kernel(const float2* __restrict__ vis, const float* __restrict__ weight,
-                               const float2* __restrict__ rot, const uint32_t* __restrict__ to_row,
-                               int64_t nvis, float2* __restrict__ yrow) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nvis;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t d = to_row[i];
-    if (d == kDropped) continue;
+__global__ __launch_bounds__(kL1Threads) void to_rows_kernel(
+    const float2* __restrict__ vis, const float* __restrict__ weight,
+    const float2* __restrict__ rot, const uint32_t* __restrict__ key,
+    const uint32_t* __restrict__ to_row, const uint32_t* __restrict__ blkbase, int64_t nvis,
+    int ntx, int rshift, int nbins, float2* __restrict__ yrow) {
+  __shared__ uint32_t cnt[kMaxRowBins], pre[kMaxRowBins], base[kMaxRowBins];
+  __shared__ uint32_t wsum[kL1Threads / 64];
+  __shared__ float2 stage[kChunk];
+  __shared__ uint16_t binof[kChunk];
+  const int64_t first = (int64_t)blockIdx.x * kChunk;
+  chunk_runs(key, blkbase, first, nvis, ntx, rshift, nbins, cnt, pre, base, wsum);
+  for (int m = 0; m < kChunk / kL1Threads; ++m) {
+    const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
+    if (i >= nvis) break;
+    const uint32_t kk = key[i];
+    if (kk == kDropped) continue;
+    const uint32_t b = (kk / (uint32_t)ntx) >> rshift;
+    const uint32_t idx = pre[b] + (to_row[i] - base[b]);
     float2 y = vis[i];
     if (weight) {
       const float wt = weight[i];
@@ -437,20 +519,59 @@ __global__ void to_rows_kernel(const float2* __restrict__ vis, const float* __re
       const float2 ro = rot[i];
       y = make_float2(y.x * ro.x - y.y * ro.y, y.x * ro.y + y.y * ro.x);
     }
-    yrow[d] = y;
+    stage[idx] = y;
+    binof[idx] = (uint16_t)b;
+  }
+  __syncthreads();
+  const uint32_t kept = pre[nbins - 1] + cnt[nbins - 1];
+  for (uint32_t k = threadIdx.x; k < kept; k += kL1Threads) {
+    const uint32_t b = binof[k];
+    yrow[base[b] + (k - pre[b])] = stage[k];
   }
 }
 
 // out[i] = yrow[to_row[i]] conj(rot[i]), 0 for dropped visibilities
-__global__ void from_rows_kernel(const float2* __restrict__ yrow, const uint32_t* __restrict__ to_row,
-                                 const float2* __restrict__ rot, int64_t nvis,
-                                 float2* __restrict__ out) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nvis;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t d = to_row[i];
+__global__ __launch_bounds__(kL1Threads) void from_rows_kernel(
+    const float2* __restrict__ yrow, const uint32_t* __restrict__ key,
+    const uint32_t* __restrict__ to_row, const uint32_t* __restrict__ blkbase,
+    const float2* __restrict__ rot, int64_t nvis, int ntx, int rshift, int nbins,
+    float2* __restrict__ out) {
+  __shared__ uint32_t cnt[kMaxRowBins], pre[kMaxRowBins], base[kMaxRowBins];
+  __shared__ uint32_t wsum[kL1Threads / 64];
+  __shared__ float2 stage[kChunk];
+  __shared__ uint16_t binof[kChunk];
+  const int64_t first = (int64_t)blockIdx.x * kChunk;
+  chunk_runs(key, blkbase, first, nvis, ntx, rshift, nbins, cnt, pre, base, wsum);
+  constexpr int kPer = kChunk / kL1Threads;
+  uint32_t idx[kPer];   // staged position of this thread's visibilities (or kDropped)
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
+    idx[m] = kDropped;
+    if (i < nvis) {
+      const uint32_t kk = key[i];
+      if (kk != kDropped) {
+        const uint32_t b = (kk / (uint32_t)ntx) >> rshift;
+        idx[m] = pre[b] + (to_row[i] - base[b]);
+        binof[idx[m]] = (uint16_t)b;
+      }
+    }
+  }
+  __syncthreads();
+  // read in: consecutive lanes take consecutive records of the runs
+  const uint32_t kept = pre[nbins - 1] + cnt[nbins - 1];
+  for (uint32_t k = threadIdx.x; k < kept; k += kL1Threads) {
+    const uint32_t b = binof[k];
+    stage[k] = yrow[base[b] + (k - pre[b])];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
+    if (i >= nvis) break;
     float2 y = make_float2(0.f, 0.f);
-    if (d != kDropped) {
-      y = yrow[d];
+    if (idx[m] != kDropped) {
+      y = stage[idx[m]];
       if (rot) {
         const float2 ro = rot[i];
         y = make_float2(y.x * ro.x + y.y * ro.y, y.y * ro.x - y.x * ro.y);
@@ -502,12 +623,12 @@ hipError_t launch_pad_sizes(const uint32_t* rowcount, int nbins, int rshift, int
 }
 
 hipError_t launch_row_scatter(const uint32_t* key, const uint2* qrec, int64_t nvis, int ntx,
-                              int rshift, int nbins, uint32_t* rowcursor, uint2* rrec,
-                              uint32_t* to_row, hipStream_t s) {
+                              int rshift, int nbins, uint32_t* rowcursor, uint32_t* blkbase,
+                              uint2* rrec, uint32_t* to_row, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
   const int64_t nb = (nvis + kChunk - 1) / kChunk;
   hipLaunchKernelGGL(row_scatter_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, key, qrec, nvis,
-                     ntx, rshift, nbins, rowcursor, rrec, to_row);
+                     ntx, rshift, nbins, rowcursor, blkbase, rrec, to_row);
   return hipGetLastError();
 }
 
@@ -520,18 +641,23 @@ hipError_t launch_row_sort(const uint32_t* rowoff, const uint32_t* prowoff, cons
 }
 
 hipError_t launch_vis_to_rows(const float2* vis, const float* weight, const float2* rot,
-                              const uint32_t* to_row, int64_t nvis, float2* yrow, hipStream_t s) {
+                              const uint32_t* key, const uint32_t* to_row, const uint32_t* blkbase,
+                              int64_t nvis, int ntx, int rshift, int nbins, float2* yrow,
+                              hipStream_t s) {
   if (nvis == 0) return hipSuccess;
-  hipLaunchKernelGGL(to_rows_kernel, grid_for(nvis), dim3(kThreads), 0, s, vis, weight, rot, to_row,
-                     nvis, yrow);
+  const int64_t nb = (nvis + kChunk - 1) / kChunk;
+  hipLaunchKernelGGL(to_rows_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, vis, weight, rot,
+                     key, to_row, blkbase, nvis, ntx, rshift, nbins, yrow);
   return hipGetLastError();
 }
 
-hipError_t launch_vis_from_rows(const float2* yrow, const float2* rot, const uint32_t* to_row,
-                                int64_t nvis, float2* out, hipStream_t s) {
+hipError_t launch_vis_from_rows(const float2* yrow, const float2* rot, const uint32_t* key,
+                                const uint32_t* to_row, const uint32_t* blkbase, int64_t nvis,
+                                int ntx, int rshift, int nbins, float2* out, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
-  hipLaunchKernelGGL(from_rows_kernel, grid_for(nvis), dim3(kThreads), 0, s, yrow, to_row, rot,
-                     nvis, out);
+  const int64_t nb = (nvis + kChunk - 1) / kChunk;
+  hipLaunchKernelGGL(from_rows_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, yrow, key, to_row,
+                     blkbase, rot, nvis, ntx, rshift, nbins, out);
   return hipGetLastError();
 }
 

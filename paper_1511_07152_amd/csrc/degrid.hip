@@ -37,32 +37,34 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 
 // Region operand for the tile at column tx: lane (col, grp) holds
-// R[y = col][x = 4 grp + q] for the four K-steps q (zero outside the grid).
-// The loads are only issued here; the checkerboard sign is applied by
-// region_sign() once the data is needed, so no wait is forced at the load.
+// R[y = col][x = 4 grp + q] for the four K-steps q.  The loads are issued at
+// clamped (always valid) addresses with no branch; region_fix() later applies
+// the factor (-1)^(x + y) (or 1 without the checkerboard), and 0 outside the
+// grid, once the data is needed, so no wait is forced at the load.
 template <int S>
-__device__ inline void load_region(const float2* __restrict__ grid, int N, int tx, int gy,
-                                   bool row_ok, int grp, float2 (&r)[4]) {
+__device__ inline void load_region(const float2* __restrict__ grid, int N, int tx, int gy, int grp,
+                                   float2 (&r)[4]) {
   constexpr int C = kRegion + 1 - S;
   constexpr int H = S / 2;
+  const int64_t row = (int64_t)min(max(gy, 0), N - 1) * N;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int gx = tx * C - H + 4 * grp + q;
-    float2 val = make_float2(0.f, 0.f);
-    if (row_ok && gx >= 0 && gx < N) val = grid[(int64_t)gy * N + gx];
-    r[q] = val;
+    r[q] = grid[row + min(max(gx, 0), N - 1)];
   }
 }
 
-// (-1)^(x + y) of the centred transform on the region operand of tile tx
 template <int S>
-__device__ inline void region_sign(int tx, int gy, int grp, float2 (&r)[4]) {
+__device__ inline void region_fix(int tx, int gy, int grp, int N, int checker, float2 (&r)[4]) {
   constexpr int C = kRegion + 1 - S;
   constexpr int H = S / 2;
+  const bool row_ok = gy >= 0 && gy < N;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int gx = tx * C - H + 4 * grp + q;
-    if ((gx + gy) & 1) r[q] = make_float2(-r[q].x, -r[q].y);
+    float f = (checker && ((gx + gy) & 1)) ? -1.f : 1.f;
+    if (!row_ok || gx < 0 || gx >= N) f = 0.f;
+    r[q] = make_float2(r[q].x * f, r[q].y * f);
   }
 }
 
@@ -72,7 +74,7 @@ struct ChunkBuf {
   float2 tu[4];    // u-table taps x = 4 grp + q of the lane's visibility
   float2 tv[4];    // v-table taps y = 4 grp + rr
   float2 reg[4];   // grid region R[y = col][x = 4 grp + q] of the chunk's tile
-  bool fresh;      // region loaded for this chunk, checkerboard not yet applied
+  bool fresh;      // region loaded for this chunk, sign / bounds factor not yet applied
 };
 
 struct DegridCtx {
@@ -80,7 +82,6 @@ struct DegridCtx {
   const float2* tu_tab;
   const float2* tv_tab;
   int s_end, gy, col, grp, lane;
-  bool row_ok;
 };
 
 __device__ __forceinline__ void fetch_taps(const DegridCtx& c, ChunkBuf& B) {
@@ -92,7 +93,7 @@ __device__ __forceinline__ void fetch_taps(const DegridCtx& c, ChunkBuf& B) {
 }
 
 // One pipeline step: chunk cur from buffer X (taps and region in flight or
-// ready; a region loaded for this chunk gets its checkerboard sign here), while
+// ready; a region loaded for this chunk gets its sign / bounds factor here), while
 // the record of chunk n2 goes into X.k and the taps (and, on a tile change, the
 // region) of chunk n1 (record Y.k, loaded one step earlier) into Y.  Buffers
 // alternate between steps.  Returns false after the item's last chunk.
@@ -104,10 +105,10 @@ __device__ __forceinline__ bool degrid_step(const DegridCtx& c, TileWalk& tw, Ch
   const int4 kx = X.k;   // this chunk's record (row-bin position of the result)
   X.k = a.krec[min(n2.c0 + c.col, n2.pe - 1)];
   fetch_taps(c, Y);
-  if (X.fresh && a.checker) region_sign<S>(cur.tx, c.gy, c.grp, X.reg);
+  if (X.fresh) region_fix<S>(cur.tx, c.gy, c.grp, a.N, a.checker, X.reg);
   Y.fresh = n1.ok && n1.tx != cur.tx;
   if (Y.fresh) {
-    load_region<S>(a.grid, a.N, n1.tx, c.gy, c.row_ok, c.grp, Y.reg);
+    load_region<S>(a.grid, a.N, n1.tx, c.gy, c.grp, Y.reg);
   } else {
 #pragma unroll
     for (int q = 0; q < 4; ++q) Y.reg[q] = X.reg[q];
@@ -158,7 +159,6 @@ __device__ __forceinline__ void degrid_item(const DegridArgs& a, const float2* t
   c.tv_tab = tv_tab;
   c.s_end = s_end;
   c.gy = ty * C - H + col;          // grid row of this lane's A operand
-  c.row_ok = c.gy >= 0 && c.gy < a.N;
   c.col = col;
   c.grp = grp;
   c.lane = lane;
@@ -177,7 +177,7 @@ __device__ __forceinline__ void degrid_item(const DegridArgs& a, const float2* t
   ChunkBuf A, B;
   A.k = a.krec[min(cur.c0 + col, cur.pe - 1)];
   fetch_taps(c, A);
-  load_region<S>(a.grid, a.N, cur.tx, c.gy, c.row_ok, grp, A.reg);
+  load_region<S>(a.grid, a.N, cur.tx, c.gy, grp, A.reg);
   A.fresh = true;
   B.k = a.krec[min(n1.c0 + col, n1.pe - 1)];
   while (degrid_step<S>(c, tw, cur, n1, n2, A, B) && degrid_step<S>(c, tw, cur, n1, n2, B, A)) {
@@ -203,9 +203,9 @@ __global__ __launch_bounds__(LDS ? 1024 : 256) void degrid_fp32_kernel(DegridArg
     tv_tab = two ? smem + n : smem;
   }
   const int lane = threadIdx.x & 63;
+  int stride;
   const int n_items = (int)*a.nitems;
-  const int stride = gridDim.x * kW;
-  for (int it = uniform(blockIdx.x * kW + (threadIdx.x >> 6)); it < n_items; it += stride)
+  for (int it = uniform(wave_items(kW, &stride)); it < n_items; it += stride)
     degrid_item<S>(a, tu_tab, tv_tab, it, lane, lane & 15, lane >> 4);
 }
 

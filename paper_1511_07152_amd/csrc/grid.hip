@@ -251,9 +251,9 @@ __global__ __launch_bounds__(64 * kWaves) void grid_fp32_kernel(GridArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   float* ring = rings + wave * kRingFloats;
   for (int i = lane; i < kRingFloats; i += 64) ring[i] = 0.f;
+  int stride;
   const int n_items = (int)*a.nitems;
-  const int stride = gridDim.x * kWaves;
-  for (int it = uniform(blockIdx.x * kWaves + wave); it < n_items; it += stride)
+  for (int it = uniform(wave_items(kWaves, &stride)); it < n_items; it += stride)
     grid_item<S>(a, ring, it, lane, lane & 15, lane >> 4);
 }
 

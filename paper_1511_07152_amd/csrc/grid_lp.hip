@@ -251,29 +251,29 @@ template <int S, bool BF16>
 __global__ __launch_bounds__(64 * kWaves) void grid_lp_kernel(GridArgsLp a) {
   const int lane = threadIdx.x & 63;
   const int n_items = (int)*a.nitems;
-  const int stride = gridDim.x * kWaves;
   const float bound = *a.lp_bound;
-  for (int it = uniform(blockIdx.x * kWaves + (threadIdx.x >> 6)); it < n_items; it += stride)
+  int stride;
+  for (int it = uniform(wave_items(kWaves, &stride)); it < n_items; it += stride)
     grid_lp_item<S, BF16>(a, bound, it, lane, lane & 15, lane >> 4);
 }
 
 // ---------------------------------------------------------------- degridding
 
 // Region operand of the tile at column tx: lane (col, grp) holds
-// R[y = col][x = 4 grp + m] (zero outside the grid).  Only the loads are
-// issued here; the checkerboard sign is applied when the region is converted
-// to the 16-bit operand, so no wait is forced at the load.
+// R[y = col][x = 4 grp + m].  The loads are issued at clamped (always valid)
+// addresses with no branch; the checkerboard sign, and 0 outside the grid, are
+// applied when the region is converted to the 16-bit operand, so no wait is
+// forced at the load.
 template <int S>
 __device__ inline void load_region_lp(const float2* __restrict__ grid, int N, int tx, int gy,
-                                      bool row_ok, int grp, float2 (&r)[4]) {
+                                      int grp, float2 (&r)[4]) {
   constexpr int C = kRegion + 1 - S;
   constexpr int H = S / 2;
+  const int64_t row = (int64_t)min(max(gy, 0), N - 1) * N;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const int gx = tx * C - H + 4 * grp + m;
-    float2 val = make_float2(0.f, 0.f);
-    if (row_ok && gx >= 0 && gx < N) val = grid[(int64_t)gy * N + gx];
-    r[m] = val;
+    r[m] = grid[row + min(max(gx, 0), N - 1)];
   }
 }
 
@@ -323,12 +323,12 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, int it, in
     taps(Y);
     if (X.fresh) {
       // A operand: R (-1)^(x + y) / s_R with s_R a power of two covering the region
-      if (checker) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int gx = cur.tx * C - H + 4 * grp + m;
-          if ((gx + gy) & 1) X.reg[m] = make_float2(-X.reg[m].x, -X.reg[m].y);
-        }
+      for (int m = 0; m < 4; ++m) {
+        const int gx = cur.tx * C - H + 4 * grp + m;
+        float f = (checker && ((gx + gy) & 1)) ? -1.f : 1.f;
+        if (!row_ok || gx < 0 || gx >= N) f = 0.f;
+        X.reg[m] = make_float2(X.reg[m].x * f, X.reg[m].y * f);
       }
       float mx = 0.f;
 #pragma unroll
@@ -343,7 +343,7 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, int it, in
       }
     }
     Y.fresh = n1.ok && n1.tx != cur.tx;
-    if (Y.fresh) load_region_lp<S>(a.grid, N, n1.tx, gy, row_ok, grp, Y.reg);
+    if (Y.fresh) load_region_lp<S>(a.grid, N, n1.tx, gy, grp, Y.reg);
     vec b_re, b_im, b_nim;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -378,7 +378,7 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, int it, in
   DegridBuf A, B;
   A.k = krec[min(cur.c0 + col, cur.pe - 1)];
   taps(A);
-  load_region_lp<S>(a.grid, N, cur.tx, gy, row_ok, grp, A.reg);
+  load_region_lp<S>(a.grid, N, cur.tx, gy, grp, A.reg);
   A.fresh = true;
   B.k = krec[min(n1.c0 + col, n1.pe - 1)];
   B.fresh = false;
@@ -390,8 +390,8 @@ template <int S, bool BF16>
 __global__ __launch_bounds__(64 * kWaves) void degrid_lp_kernel(DegridArgsLp a) {
   const int lane = threadIdx.x & 63;
   const int n_items = (int)*a.nitems;
-  const int stride = gridDim.x * kWaves;
-  for (int it = uniform(blockIdx.x * kWaves + (threadIdx.x >> 6)); it < n_items; it += stride)
+  int stride;
+  for (int it = uniform(wave_items(kWaves, &stride)); it < n_items; it += stride)
     degrid_lp_item<S, BF16>(a, it, lane, lane & 15, lane >> 4);
 }
 

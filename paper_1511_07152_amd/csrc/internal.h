@@ -15,6 +15,7 @@ constexpr int kRegion = 16;        // MFMA tile region edge (cells): core + S - 
 constexpr int kMaxSupport = 15;    // S <= kRegion - 1
 constexpr int kItemMaxVis = 1024;  // visibilities per work item (a slice of a tile row)
 constexpr int kMaxRowBins = 4096;  // level-1 sort bins (rows of tiles, possibly grouped)
+constexpr int kL1Chunk = 10240;    // visibilities per workgroup in the level-1 passes
 constexpr int kTargetRowBins = 2048;
 
 // Padded tables: row length L = 32 - S holds the S taps of a table row at
@@ -86,6 +87,7 @@ struct Plan {
   uint32_t* rowcount = nullptr; // [nbins + 1] level-1 histogram
   uint32_t* rowoff = nullptr;   // [nbins + 1] its exclusive scan; rowoff[nbins] = kept count
   uint32_t* rowcursor = nullptr;// [nbins + 1] level-1 placement cursors
+  uint32_t* blkbase = nullptr;  // [level-1 blocks][nbins] start of each block's run per row bin
   uint32_t* rowpad = nullptr;   // [nbins + 1] tile slots reserved per row bin
   uint32_t* prowoff = nullptr;  // [nbins + 1] exclusive scan of rowpad
   uint2* rrec = nullptr;        // [nvis] records sorted by row bin
@@ -129,19 +131,23 @@ hipError_t launch_quantise_rows(const double* u, const double* v, const double* 
 // rowpad[b] = slots reserved for row bin b (count + padding room, multiple of 4)
 hipError_t launch_pad_sizes(const uint32_t* rowcount, int nbins, int rshift, int ntx, int nty,
                             uint32_t* rowpad, hipStream_t s);
+// level-1 placement; blkbase[block][bin] = start of the block's run in the row-bin array
 hipError_t launch_row_scatter(const uint32_t* key, const uint2* qrec, int64_t nvis, int ntx,
-                              int rshift, int nbins, uint32_t* rowcursor, uint2* rrec,
-                              uint32_t* to_row, hipStream_t s);
+                              int rshift, int nbins, uint32_t* rowcursor, uint32_t* blkbase,
+                              uint2* rrec, uint32_t* to_row, hipStream_t s);
 // zero_row: row-bin position the padding slots point to (a W V that stays 0)
 hipError_t launch_row_sort(const uint32_t* rowoff, const uint32_t* prowoff, const uint2* rrec,
                            int rshift, int nbins, int ntx, int nty, int tile_c, int O, int S,
                            uint32_t zero_row, uint2* tdesc, int4* krec, hipStream_t s);
 // caller-order W V (times the facet rotation) -> row-bin order
 hipError_t launch_vis_to_rows(const float2* vis, const float* weight, const float2* rot,
-                              const uint32_t* to_row, int64_t nvis, float2* yrow, hipStream_t s);
+                              const uint32_t* key, const uint32_t* to_row, const uint32_t* blkbase,
+                              int64_t nvis, int ntx, int rshift, int nbins, float2* yrow,
+                              hipStream_t s);
 // row-bin-order results -> caller order, rotation undone (dropped visibilities get 0)
-hipError_t launch_vis_from_rows(const float2* yrow, const float2* rot, const uint32_t* to_row,
-                                int64_t nvis, float2* out, hipStream_t s);
+hipError_t launch_vis_from_rows(const float2* yrow, const float2* rot, const uint32_t* key,
+                                const uint32_t* to_row, const uint32_t* blkbase, int64_t nvis,
+                                int ntx, int rshift, int nbins, float2* out, hipStream_t s);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t s);
 int64_t scan_tmp_size(int64_t n);
 hipError_t launch_rotation(const double* u, const double* v, const double* w, int64_t nvis,

@@ -62,6 +62,14 @@ struct TileWalk {
   }
 };
 
+// Grid-stride assignment of work items to the waves of a launch: returns this
+// wave's first item and sets the stride between its items.  (Giving each XCD
+// a contiguous band of rows of tiles instead was measured slower.)
+__device__ inline int wave_items(int waves_per_block, int* stride) {
+  *stride = gridDim.x * waves_per_block;
+  return blockIdx.x * waves_per_block + (int)(threadIdx.x >> 6);
+}
+
 // Position of one chunk of at most 16 slots inside one tile of a work item.
 struct ChunkPos {
   int c0;    // first slot
