@@ -169,6 +169,7 @@ void destroy_plan(Plan* p) {
   dfree(p->rot);
   dfree(p->nit);
   dfree(p->itoff);
+  dfree(p->qctr);
   dfree(p->items);
   dfree(p->scan_tmp);
   delete static_cast<sepw_plan_s*>(p);
@@ -348,7 +349,8 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
   P->pcap = capacity + 3 * std::min<int64_t>(nt, capacity) + 4 * (int64_t)P->nbins;
   if (P->pcap > 2147483647LL - 64) return SEPW_ERR_UNSUPPORTED;
   P->max_items = P->nty + P->pcap / kItemMaxVis + 1;
-  P->scan_tmp_len = scan_tmp_size((P->nbins > P->nty ? P->nbins : P->nty) + 1);
+  P->r8 = (P->nty + 7) / 8;
+  P->scan_tmp_len = scan_tmp_size(std::max<int64_t>(P->nbins, 8 * (int64_t)P->r8) + 1);
   SEPW_TRY(dalloc(&P->key, capacity));
   SEPW_TRY(dalloc(&P->qrec, capacity));
   SEPW_TRY(dalloc(&P->rowcount, P->nbins + 1));
@@ -362,8 +364,9 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
   SEPW_TRY(dalloc(&P->yrow, capacity + 1));
   SEPW_TRY(dalloc(&P->krec, P->pcap));
   SEPW_TRY(dalloc(&P->tdesc, nt));
-  SEPW_TRY(dalloc(&P->nit, P->nty + 1));
-  SEPW_TRY(dalloc(&P->itoff, P->nty + 1));
+  SEPW_TRY(dalloc(&P->nit, 8 * (int64_t)P->r8 + 1));
+  SEPW_TRY(dalloc(&P->itoff, 8 * (int64_t)P->r8 + 1));
+  SEPW_TRY(dalloc(&P->qctr, 8));
   SEPW_TRY(dalloc(&P->items, P->max_items));
   SEPW_TRY(dalloc(&P->scan_tmp, P->scan_tmp_len));
   if (K->facet) SEPW_TRY(dalloc(&P->rot, capacity));
@@ -396,9 +399,9 @@ int bin_plan(Plan* P, int64_t nvis, const double* u, const double* v, const doub
     SEPW_TRY(launch_zero_c64(P->yrow + P->capacity, 1, s));
     SEPW_TRY(launch_row_sort(P->rowoff, P->prowoff, P->rrec, P->rshift, P->nbins, P->ntx, P->nty,
                              P->tile_c, K->O, K->S, (uint32_t)P->capacity, P->tdesc, P->krec, s));
-    SEPW_TRY(launch_item_counts(P->tdesc, P->ntx, P->nty, P->nit, s));
-    SEPW_TRY(launch_scan(P->nit, P->itoff, P->nty + 1, P->scan_tmp, s));
-    SEPW_TRY(launch_items(P->tdesc, P->itoff, P->ntx, P->nty, P->items, s));
+    SEPW_TRY(launch_item_counts(P->tdesc, P->ntx, P->nty, P->r8, P->nit, s));
+    SEPW_TRY(launch_scan(P->nit, P->itoff, 8 * (int64_t)P->r8 + 1, P->scan_tmp, s));
+    SEPW_TRY(launch_items(P->tdesc, P->itoff, P->ntx, P->nty, P->r8, P->items, s));
     if (K->facet) SEPW_TRY(launch_rotation(u, v, w, nvis, g, P->rot, s));
   }
   return SEPW_OK;
@@ -585,11 +588,13 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
   {
     Stage st(SEPW_STAGE_GRID, s);
     if (K->prm.precision == SEPW_FP32) {
-      GridArgs a{p->items, p->itoff + p->nty, p->tdesc, p->krec, p->yrow, K->pad_u, K->pad_v,
+      GridArgs a{p->items, p->itoff + 8 * p->r8, p->itoff, p->r8, p->qctr, p->tdesc, p->krec,
+                 p->yrow, K->pad_u, K->pad_v,
                  K->tab_len, N, p->ntx, grid_only ? 0 : 1, img};
       SEPW_TRY(launch_grid_fp32(K->S, a, p->max_items, s));
     } else {
-      GridArgsLp a{p->items, p->itoff + p->nty, p->tdesc, p->krec, p->yrow, K->pad_us, K->lp_v,
+      GridArgsLp a{p->items, p->itoff + 8 * p->r8, p->itoff, p->r8, p->qctr, p->tdesc, p->krec,
+                   p->yrow, K->pad_us, K->lp_v,
                    K->lp_bound, N, p->ntx, grid_only ? 0 : 1, img};
       SEPW_TRY(launch_grid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->max_items, s));
     }
@@ -637,11 +642,14 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
   {
     Stage st(SEPW_STAGE_DEGRID, s);
     if (K->prm.precision == SEPW_FP32) {
-      DegridArgs a{p->items, p->itoff + p->nty, p->tdesc, p->krec, src, K->pad_u, K->pad_v,
+      SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8, s));
+      DegridArgs a{p->items, p->itoff + 8 * p->r8, p->itoff, p->r8, p->qctr, p->tdesc, p->krec,
+                   src, K->pad_u, K->pad_v,
                    K->tab_len, N, p->ntx, checker, p->yrow};
       SEPW_TRY(launch_degrid_fp32(K->S, a, p->max_items, K->lds_bytes, K->n_cu, s));
     } else {
-      DegridArgsLp a{p->items, p->itoff + p->nty, p->tdesc, p->krec, src, K->lp_u, K->pad_vs, N,
+      DegridArgsLp a{p->items, p->itoff + 8 * p->r8, p->itoff, p->r8, p->qctr, p->tdesc, p->krec,
+                     src, K->lp_u, K->pad_vs, N,
                      p->ntx, checker, p->yrow};
       SEPW_TRY(launch_degrid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->max_items, s));
     }
@@ -703,7 +711,8 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
   for (int r = 0; r < njobs; ++r) {
     Plan* p = plans[order[r]];
     Kernels* K = p->K;
-    bs->host[r] = GridArgs{p->items, p->itoff + p->nty, p->tdesc, p->krec, p->yrow, K->pad_u,
+    bs->host[r] = GridArgs{p->items, p->itoff + 8 * p->r8, p->itoff, p->r8, p->qctr, p->tdesc,
+                           p->krec, p->yrow, K->pad_u,
                            K->pad_v, K->tab_len, N, p->ntx, grid_only ? 0 : 1,
                            reinterpret_cast<float2*>(out[order[r]])};
   }

@@ -179,23 +179,28 @@ __device__ inline uint2 row_slots(const uint2* __restrict__ tdesc, int ntx, int6
   return make_uint2(a.x, b.x + round4(b.y - b.x));
 }
 
-__global__ void item_counts_kernel(const uint2* __restrict__ tdesc, int ntx, int nty,
+// Rows of tiles go to 8 work lists by r % 8; list entries are indexed
+// (r % 8) r8 + r / 8, so one scan gives every row's first item in list order.
+__device__ inline int64_t list_index(int64_t r, int r8) { return (r % 8) * r8 + r / 8; }
+
+__global__ void item_counts_kernel(const uint2* __restrict__ tdesc, int ntx, int nty, int r8,
                                    uint32_t* __restrict__ nit) {
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r <= nty;
-       r += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= 8 * (int64_t)r8;
+       j += (int64_t)gridDim.x * blockDim.x) {
     uint32_t c = 0;
-    if (r < nty) {
+    const int64_t r = (j % r8) * 8 + j / r8;   // row with list_index(r) == j
+    if (j < 8 * (int64_t)r8 && r < nty) {
       const uint2 rs = row_slots(tdesc, ntx, r);
       c = (rs.y - rs.x + kItemMaxVis - 1) / kItemMaxVis;
     }
-    nit[r] = c;
+    nit[j] = c;
   }
 }
 
 // Item k of row r covers slots [a + k M, min(a + (k + 1) M, e)) of the row's
 // range [a, e); the tile holding its first slot writes it.
 __global__ void items_kernel(const uint2* __restrict__ tdesc, const uint32_t* __restrict__ itoff,
-                             int ntx, int nty, int4* __restrict__ items) {
+                             int ntx, int nty, int r8, int4* __restrict__ items) {
   const int64_t nt = (int64_t)ntx * nty;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -204,10 +209,11 @@ __global__ void items_kernel(const uint2* __restrict__ tdesc, const uint32_t* __
     const int64_t r = t / ntx;
     const uint32_t ps = d.x, pe = d.x + round4(d.y - d.x);
     const uint2 rs = row_slots(tdesc, ntx, r);
+    const uint32_t o = itoff[list_index(r, r8)];
     uint32_t k = (ps - rs.x + kItemMaxVis - 1) / kItemMaxVis;
     for (uint32_t b = rs.x + k * kItemMaxVis; b < pe; b += kItemMaxVis, ++k) {
       const uint32_t e = rs.y - b > (uint32_t)kItemMaxVis ? b + kItemMaxVis : rs.y;
-      items[itoff[r] + k] = make_int4((int)r, (int)b, (int)e, (int)(t - r * ntx));
+      items[o + k] = make_int4((int)r, (int)b, (int)e, (int)(t - r * ntx));
     }
   }
 }
@@ -668,16 +674,17 @@ hipError_t launch_rotation(const double* u, const double* v, const double* w, in
   return hipGetLastError();
 }
 
-hipError_t launch_item_counts(const uint2* tdesc, int ntx, int nty, uint32_t* nit, hipStream_t s) {
-  hipLaunchKernelGGL(item_counts_kernel, grid_for(nty + 1), dim3(kThreads), 0, s, tdesc, ntx, nty,
-                     nit);
+hipError_t launch_item_counts(const uint2* tdesc, int ntx, int nty, int r8, uint32_t* nit,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(item_counts_kernel, grid_for(8 * (int64_t)r8 + 1), dim3(kThreads), 0, s, tdesc,
+                     ntx, nty, r8, nit);
   return hipGetLastError();
 }
 
-hipError_t launch_items(const uint2* tdesc, const uint32_t* itoff, int ntx, int nty, int4* items,
-                        hipStream_t s) {
+hipError_t launch_items(const uint2* tdesc, const uint32_t* itoff, int ntx, int nty, int r8,
+                        int4* items, hipStream_t s) {
   hipLaunchKernelGGL(items_kernel, grid_for((int64_t)ntx * nty), dim3(kThreads), 0, s, tdesc,
-                     itoff, ntx, nty, items);
+                     itoff, ntx, nty, r8, items);
   return hipGetLastError();
 }
 

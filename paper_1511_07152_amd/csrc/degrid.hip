@@ -203,10 +203,10 @@ __global__ __launch_bounds__(LDS ? 1024 : 256) void degrid_fp32_kernel(DegridArg
     tv_tab = two ? smem + n : smem;
   }
   const int lane = threadIdx.x & 63;
-  int stride;
-  const int n_items = (int)*a.nitems;
-  for (int it = uniform(wave_items(kW, &stride)); it < n_items; it += stride)
-    degrid_item<S>(a, tu_tab, tv_tab, it, lane, lane & 15, lane >> 4);
+  // per-XCD work lists: all items of a row of tiles write that row's results
+  // through one L2 (measured faster than grid-stride order for degridding)
+  for_items(a.lists, a.r8, a.qctr, lane,
+            [&](int it) { degrid_item<S>(a, tu_tab, tv_tab, it, lane, lane & 15, lane >> 4); });
 }
 
 template <int S>
@@ -221,8 +221,9 @@ hipError_t launch_s(const DegridArgs& a, int64_t max_items, int lds_bytes, int n
     hipLaunchKernelGGL((degrid_fp32_kernel<S, true>), dim3((unsigned)b), dim3(1024), lds_bytes, s,
                        a);
   } else {
+    // persistent: about as many workgroups as can be resident (waves pull items)
     int64_t b = (max_items + 3) / 4;
-    if (b > 8192) b = 8192;
+    if (b > 4 * (int64_t)n_cu) b = 4 * (int64_t)n_cu;
     if (b < 1) b = 1;
     hipLaunchKernelGGL((degrid_fp32_kernel<S, false>), dim3((unsigned)b), dim3(256), 0, s, a);
   }

@@ -250,9 +250,9 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float bound, i
 template <int S, bool BF16>
 __global__ __launch_bounds__(64 * kWaves) void grid_lp_kernel(GridArgsLp a) {
   const int lane = threadIdx.x & 63;
-  const int n_items = (int)*a.nitems;
   const float bound = *a.lp_bound;
   int stride;
+  const int n_items = (int)*a.nitems;
   for (int it = uniform(wave_items(kWaves, &stride)); it < n_items; it += stride)
     grid_lp_item<S, BF16>(a, bound, it, lane, lane & 15, lane >> 4);
 }
@@ -389,20 +389,10 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, int it, in
 template <int S, bool BF16>
 __global__ __launch_bounds__(64 * kWaves) void degrid_lp_kernel(DegridArgsLp a) {
   const int lane = threadIdx.x & 63;
-  const int n_items = (int)*a.nitems;
   int stride;
+  const int n_items = (int)*a.nitems;
   for (int it = uniform(wave_items(kWaves, &stride)); it < n_items; it += stride)
     degrid_lp_item<S, BF16>(a, it, lane, lane & 15, lane >> 4);
-}
-
-template <int S, bool BF16>
-void launch_grid_s(const GridArgsLp& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((grid_lp_kernel<S, BF16>), dim3(blocks), dim3(64 * kWaves), 0, s, a);
-}
-
-template <int S, bool BF16>
-void launch_degrid_s(const DegridArgsLp& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((degrid_lp_kernel<S, BF16>), dim3(blocks), dim3(64 * kWaves), 0, s, a);
 }
 
 int blocks_for(int64_t max_items) {
@@ -412,24 +402,35 @@ int blocks_for(int64_t max_items) {
   return (int)b;
 }
 
+template <int S, bool BF16>
+void launch_grid_s(const GridArgsLp& a, int64_t max_items, hipStream_t s) {
+  const int blocks = blocks_for(max_items);
+  hipLaunchKernelGGL((grid_lp_kernel<S, BF16>), dim3(blocks), dim3(64 * kWaves), 0, s, a);
+}
+
+template <int S, bool BF16>
+void launch_degrid_s(const DegridArgsLp& a, int64_t max_items, hipStream_t s) {
+  const int blocks = blocks_for(max_items);
+  hipLaunchKernelGGL((degrid_lp_kernel<S, BF16>), dim3(blocks), dim3(64 * kWaves), 0, s, a);
+}
+
 }  // namespace
 
 #define SEPW_LP_CASES(F, A, B, ST)                                                    \
   switch (S) {                                                                     \
-    case 1: F<1, B>(A, blocks, ST); break;                                          \
-    case 3: F<3, B>(A, blocks, ST); break;                                          \
-    case 5: F<5, B>(A, blocks, ST); break;                                          \
-    case 7: F<7, B>(A, blocks, ST); break;                                          \
-    case 9: F<9, B>(A, blocks, ST); break;                                          \
-    case 11: F<11, B>(A, blocks, ST); break;                                        \
-    case 13: F<13, B>(A, blocks, ST); break;                                        \
-    case 15: F<15, B>(A, blocks, ST); break;                                        \
+    case 1: F<1, B>(A, max_items, ST); break;                                       \
+    case 3: F<3, B>(A, max_items, ST); break;                                       \
+    case 5: F<5, B>(A, max_items, ST); break;                                       \
+    case 7: F<7, B>(A, max_items, ST); break;                                       \
+    case 9: F<9, B>(A, max_items, ST); break;                                       \
+    case 11: F<11, B>(A, max_items, ST); break;                                     \
+    case 13: F<13, B>(A, max_items, ST); break;                                     \
+    case 15: F<15, B>(A, max_items, ST); break;                                     \
     default: return hipErrorInvalidValue;                                          \
   }
 
 hipError_t launch_grid_lp(int S, bool bf16, const GridArgsLp& a, int64_t max_items,
                           hipStream_t s) {
-  const int blocks = blocks_for(max_items);
   if (bf16) {
     SEPW_LP_CASES(launch_grid_s, a, true, s)
   } else {
@@ -440,7 +441,6 @@ hipError_t launch_grid_lp(int S, bool bf16, const GridArgsLp& a, int64_t max_ite
 
 hipError_t launch_degrid_lp(int S, bool bf16, const DegridArgsLp& a, int64_t max_items,
                             hipStream_t s) {
-  const int blocks = blocks_for(max_items);
   if (bf16) {
     SEPW_LP_CASES(launch_degrid_s, a, true, s)
   } else {

@@ -98,8 +98,10 @@ struct Plan {
                                 // the tile and the row-bin position of its W V
   uint2* tdesc = nullptr;       // [ntiles] (first slot, first slot + count) per tile
   float2* rot = nullptr;        // [nvis] facet phase rotation, caller order
-  uint32_t* nit = nullptr;      // [nty + 1] work items per row of tiles
-  uint32_t* itoff = nullptr;    // [nty + 1] exclusive scan of nit
+  int r8 = 0;                   // rows of tiles per work list: ceil(nty / 8)
+  uint32_t* nit = nullptr;      // [8 r8 + 1] work items per row, row r at (r % 8) r8 + r / 8
+  uint32_t* itoff = nullptr;    // [8 r8 + 1] exclusive scan of nit: list q = [itoff[q r8], itoff[(q + 1) r8])
+  uint32_t* qctr = nullptr;     // [8] work-list counters of a launch
   int4* items = nullptr;        // [max_items] (tile row, first slot, end slot, tile column)
   uint32_t* scan_tmp = nullptr; // block partials for the scans
   int64_t scan_tmp_len = 0;
@@ -153,9 +155,11 @@ int64_t scan_tmp_size(int64_t n);
 hipError_t launch_rotation(const double* u, const double* v, const double* w, int64_t nvis,
                            QuantGeom g, float2* rot, hipStream_t s);
 // work items: slices of <= kItemMaxVis slots of each row of tiles
-hipError_t launch_item_counts(const uint2* tdesc, int ntx, int nty, uint32_t* nit, hipStream_t s);
-hipError_t launch_items(const uint2* tdesc, const uint32_t* itoff, int ntx, int nty, int4* items,
-                        hipStream_t s);
+// per-row item counts in list order (nit[(r % 8) r8 + r / 8]) and the items in that order
+hipError_t launch_item_counts(const uint2* tdesc, int ntx, int nty, int r8, uint32_t* nit,
+                              hipStream_t s);
+hipError_t launch_items(const uint2* tdesc, const uint32_t* itoff, int ntx, int nty, int r8,
+                        int4* items, hipStream_t s);
 hipError_t launch_bins_export(const uint2* rrec, const uint32_t* to_row, int64_t nvis, int tile_c,
                               int ntx, int32_t* out, hipStream_t s);
 
@@ -166,6 +170,9 @@ hipError_t launch_bins_export(const uint2* rrec, const uint32_t* to_row, int64_t
 struct GridArgs {
   const int4* items;
   const uint32_t* nitems;   // device count of items
+  const uint32_t* lists;    // work lists (itoff of the plan), r8 rows per list
+  int r8;
+  uint32_t* qctr;           // list counters, zero at launch
   const uint2* tdesc;       // per tile (first slot, first slot + count)
   const int4* krec;         // per slot (u base, v base, row-bin position, 0)
   const float2* yrow;       // W V in row-bin order
@@ -180,6 +187,9 @@ struct GridArgs {
 struct DegridArgs {
   const int4* items;
   const uint32_t* nitems;
+  const uint32_t* lists;    // work lists (itoff of the plan), r8 rows per list
+  int r8;
+  uint32_t* qctr;           // list counters, zero at launch
   const uint2* tdesc;
   const int4* krec;
   const float2* grid;
@@ -194,6 +204,9 @@ struct DegridArgs {
 struct GridArgsLp {
   const int4* items;
   const uint32_t* nitems;
+  const uint32_t* lists;    // work lists (itoff of the plan), r8 rows per list
+  int r8;
+  uint32_t* qctr;           // list counters, zero at launch
   const uint2* tdesc;
   const int4* krec;
   const float2* yrow;
@@ -208,6 +221,9 @@ struct GridArgsLp {
 struct DegridArgsLp {
   const int4* items;
   const uint32_t* nitems;
+  const uint32_t* lists;    // work lists (itoff of the plan), r8 rows per list
+  int r8;
+  uint32_t* qctr;           // list counters, zero at launch
   const uint2* tdesc;
   const int4* krec;
   const float2* grid;

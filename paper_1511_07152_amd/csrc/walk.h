@@ -63,11 +63,43 @@ struct TileWalk {
 };
 
 // Grid-stride assignment of work items to the waves of a launch: returns this
-// wave's first item and sets the stride between its items.  (Giving each XCD
-// a contiguous band of rows of tiles instead was measured slower.)
+// wave's first item and sets the stride between its items.
 __device__ inline int wave_items(int waves_per_block, int* stride) {
   *stride = gridDim.x * waves_per_block;
   return blockIdx.x * waves_per_block + (int)(threadIdx.x >> 6);
+}
+
+// Work items are kept in 8 lists, list q holding the items of the rows of
+// tiles r with r % 8 == q (rows interleaved, so the lists carry similar work),
+// list q = items [lists[q r8], lists[(q + 1) r8]).  A wave pulls items from the
+// list of the XCD it runs on (hardware register XCC_ID; each XCD has its own
+// L2, and all items of a row then write that row's row-bin data through one
+// L2) with one atomic counter per list, and once that list is empty from the
+// other lists in turn, so every item is taken exactly once whatever XCD a
+// workgroup lands on.  The counters must be zero at launch; launches use only
+// as many workgroups as can be resident, so that few waves find the lists
+// empty.
+__device__ inline int xcd_id() {
+  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7;   // hwreg(XCC_ID, 0, 4)
+}
+
+template <class F>
+__device__ inline void for_items(const uint32_t* __restrict__ lists, int r8,
+                                 uint32_t* __restrict__ ctr, int lane, F&& body) {
+  const int x = uniform(xcd_id());
+  for (int l = 0; l < 8; ++l) {
+    const int q = (x + l) & 7;
+    const int lo = uniform((int)lists[q * r8]), hi = uniform((int)lists[(q + 1) * r8]);
+    // a plain read first: lists that are already used up cost no atomic
+    if (lo + (int)__atomic_load_n(&ctr[q], __ATOMIC_RELAXED) >= hi) continue;
+    while (true) {
+      int n = 0;
+      if (lane == 0) n = (int)atomicAdd(&ctr[q], 1u);
+      n = uniform(__shfl(n, 0, 64));
+      if (lo + n >= hi) break;
+      body(lo + n);
+    }
+  }
 }
 
 // Position of one chunk of at most 16 slots inside one tile of a work item.
