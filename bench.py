@@ -111,8 +111,9 @@ def accuracy_64(_lib, torch):
 
 def batching_form(_lib, torch, args):
     """36 image-plane facets (6 x 6 over 10 deg, 1024^2 each, S = 11, 64 planes,
-    log-normal visibility counts): one persistent sepw_grid_batched launch vs
-    one sepw_grid launch per facet, both through FFT and correction."""
+    log-normal visibility counts): one persistent sepw_grid_batched launch (its
+    work-item length and launch width picked first by sepw_autotune_batched)
+    vs one sepw_grid launch per facet, both through FFT and correction."""
     import numpy as np
 
     from paper_1511_07152_amd import synth
@@ -140,9 +141,19 @@ def batching_form(_lib, torch, args):
         for p, x, wt, o in zip(plans, vis, wts, outs):
             _lib.grid(p, x, wt, flags=_lib.MUL_N, out=o)
 
+    def item_slots(n):
+        for p in plans:
+            p.set_item_slots(n)
+
+    t0 = time.perf_counter()
+    slots, width = _lib.autotune_batched(plans, vis, wts, outs=outs)
+    tune_s = time.perf_counter() - t0
     res = {"workload": "36 facets 6x6 over 10 deg, 1024^2, S=11, O=8, 64 planes",
-           "nvis": nvis, "dropped": dropped}
+           "nvis": nvis, "dropped": dropped,
+           "autotuned": {"item_slots": slots, "blocks_per_cu": width, "seconds": round(tune_s, 2)}}
     for name, fn in (("batched", batched), ("per_facet", per_job)):
+        if name == "per_facet":
+            item_slots(1024)   # per-facet launches with the default work-item length
         for _ in range(max(args.warmup, 1)):
             fn()
         torch.cuda.synchronize()

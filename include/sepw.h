@@ -17,6 +17,7 @@
  *                      prediction equation; Section 6, prediction for major
  *                      cycles)
  *   sepw_grid_batched  many facet/snapshot jobs in one persistent launch
+ *                      (sepw_autotune_batched picks its launch shape)
  *                      (Section 4.1 faceting, Section 4.2 snapshots)
  *
  * Conventions (the paper leaves these open; the library fixes them):
@@ -179,6 +180,26 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
 int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* const* vis,
                       const float* const* weight, sepw_c64* const* out, uint32_t flags,
                       void* hip_stream);
+
+/* Length of the plan's work items: the number of tile slots (visibilities,
+ * each tile padded to whole groups of 4) of one row of tiles that one wave
+ * processes in order.  Default 1024; must be a multiple of 4 in [64, 8192].
+ * Rebuilds the plan's work list asynchronously on the stream (it waits for the
+ * stream once when the list has to grow); later rebins keep the length.
+ * Errors: SEPW_ERR_ARG (null p, invalid slots), SEPW_ERR_OOM, SEPW_ERR_HIP. */
+int sepw_plan_set_item_slots(sepw_plan p, int32_t slots, void* hip_stream);
+
+/* Autotuner of the batching form's launch shape: times sepw_grid_batched with
+ * SEPW_GRID_ONLY on these jobs (HIP events, one warm-up and two timed runs per
+ * candidate) for every work-item length in {256, 512, 1024, 2048} and every
+ * persistent launch width in {2, 4, 8} workgroups per compute unit, and keeps
+ * the fastest pair: the plans keep that item length, and later batched calls
+ * in this process use that width.  The pair is returned in *item_slots and
+ * *blocks_per_cu (either may be NULL).  out[] is overwritten.  Synchronous.
+ * Errors: as sepw_grid_batched, and those of sepw_plan_set_item_slots. */
+int sepw_autotune_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* const* vis,
+                          const float* const* weight, sepw_c64* const* out, void* hip_stream,
+                          int32_t* item_slots, int32_t* blocks_per_cu);
 
 /* Regenerate the tables of k for a new w range (same P), asynchronously on
  * the stream: the per-batch form of table generation when the w-planes span

@@ -69,6 +69,9 @@ def load():
     lib.sepw_degrid.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.c_uint32, c_void_p]
     lib.sepw_grid_batched.argtypes = [c_int32, P(c_void_p), P(c_void_p), P(c_void_p), P(c_void_p),
                                       ctypes.c_uint32, c_void_p]
+    lib.sepw_plan_set_item_slots.argtypes = [c_void_p, c_int32, c_void_p]
+    lib.sepw_autotune_batched.argtypes = [c_int32, P(c_void_p), P(c_void_p), P(c_void_p),
+                                          P(c_void_p), c_void_p, P(c_int32), P(c_int32)]
     lib.sepw_free_kernels.argtypes = [c_void_p]
     lib.sepw_free_plan.argtypes = [c_void_p]
     lib.sepw_strerror.argtypes = [ctypes.c_int]
@@ -78,7 +81,7 @@ def load():
                  "sepw_plan_bins", "sepw_plan_tile_size", "sepw_grid", "sepw_degrid",
                  "sepw_grid_batched", "sepw_free_kernels", "sepw_free_plan", "sepw_device_count",
                  "sepw_plan_rebin", "sepw_kernels_set_wrange", "sepw_timing_enable",
-                 "sepw_timing_collect"):
+                 "sepw_timing_collect", "sepw_plan_set_item_slots", "sepw_autotune_batched"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -215,6 +218,12 @@ class Plan:
             self.n_dropped = nd.value
         return self
 
+    def set_item_slots(self, slots):
+        """sepw_plan_set_item_slots: work-item length (multiple of 4 in [64, 8192])."""
+        _check(load().sepw_plan_set_item_slots(self._h, int(slots), _stream()),
+               "sepw_plan_set_item_slots")
+        return self
+
     def bins(self):
         out = torch.empty((self.nvis, 7), dtype=torch.int32, device="cuda")
         _check(load().sepw_plan_bins(self._h, _ptr(out), _stream()), "sepw_plan_bins")
@@ -275,6 +284,30 @@ def degrid(plan, image, flags=0, out=None):
         out = torch.empty(plan.nvis, dtype=torch.complex64, device="cuda")
     _check(load().sepw_degrid(plan.handle, _ptr(image), _ptr(out), flags, _stream()), "sepw_degrid")
     return out
+
+
+def _batch_args(plans, vis, weights, outs):
+    n = len(plans)
+    vis = [_dev(x, torch.complex64, "vis") for x in vis]
+    if weights is None:
+        weights = [None] * n
+    weights = [None if x is None else _dev(x, torch.float32, "weight") for x in weights]
+    if outs is None:
+        outs = [torch.empty((p.kernels.N, p.kernels.N), dtype=torch.complex64, device="cuda")
+                for p in plans]
+    arr = c_void_p * n
+    return (n, arr(*[p.handle for p in plans]), arr(*[x.data_ptr() for x in vis]),
+            arr(*[0 if x is None else x.data_ptr() for x in weights]),
+            arr(*[x.data_ptr() for x in outs]), (vis, weights, outs))
+
+
+def autotune_batched(plans, vis, weights=None, outs=None):
+    """sepw_autotune_batched: returns (item_slots, blocks_per_cu) it settled on."""
+    n, hp, vp, wp, op, keep = _batch_args(plans, vis, weights, outs)
+    slots, width = c_int32(0), c_int32(0)
+    _check(load().sepw_autotune_batched(n, hp, vp, wp, op, _stream(), ctypes.byref(slots),
+                                        ctypes.byref(width)), "sepw_autotune_batched")
+    return slots.value, width.value
 
 
 def grid_batched(plans, vis, weights=None, flags=0, outs=None):

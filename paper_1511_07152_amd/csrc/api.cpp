@@ -348,7 +348,8 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
   // multiple of 4, each row bin's range rounded to 4
   P->pcap = capacity + 3 * std::min<int64_t>(nt, capacity) + 4 * (int64_t)P->nbins;
   if (P->pcap > 2147483647LL - 64) return SEPW_ERR_UNSUPPORTED;
-  P->max_items = P->nty + P->pcap / kItemMaxVis + 1;
+  P->item_slots = kItemMaxVis;
+  P->max_items = P->nty + P->pcap / P->item_slots + 1;
   P->r8 = (P->nty + 7) / 8;
   P->scan_tmp_len = scan_tmp_size(std::max<int64_t>(P->nbins, 8 * (int64_t)P->r8) + 1);
   SEPW_TRY(dalloc(&P->key, capacity));
@@ -371,6 +372,31 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
   SEPW_TRY(dalloc(&P->scan_tmp, P->scan_tmp_len));
   if (K->facet) SEPW_TRY(dalloc(&P->rot, capacity));
   return SEPW_OK;
+}
+
+MoveArgs move_args(const Plan* p, const sepw_c64* vis, const float* weight) {
+  MoveArgs m;
+  m.vis = reinterpret_cast<const float2*>(vis);
+  m.weight = weight;
+  m.rot = p->rot;
+  m.key = p->key;
+  m.to_row = p->to_row;
+  m.blkbase = p->blkbase;
+  m.yrow = p->yrow;
+  m.nvis = p->nvis;
+  m.ntx = p->ntx;
+  m.rshift = p->rshift;
+  m.nbins = p->nbins;
+  return m;
+}
+
+// Work list: items of item_slots slots per row of tiles, in 8 lists by row % 8.
+hipError_t build_items(Plan* P, hipStream_t s) {
+  hipError_t e = launch_item_counts(P->tdesc, P->ntx, P->nty, P->r8, P->item_slots, P->nit, s);
+  if (e == hipSuccess) e = launch_scan(P->nit, P->itoff, 8 * (int64_t)P->r8 + 1, P->scan_tmp, s);
+  if (e == hipSuccess)
+    e = launch_items(P->tdesc, P->itoff, P->ntx, P->nty, P->r8, P->item_slots, P->items, s);
+  return e;
 }
 
 // Quantise, sort and build the work list for nvis <= capacity visibilities.
@@ -399,9 +425,7 @@ int bin_plan(Plan* P, int64_t nvis, const double* u, const double* v, const doub
     SEPW_TRY(launch_zero_c64(P->yrow + P->capacity, 1, s));
     SEPW_TRY(launch_row_sort(P->rowoff, P->prowoff, P->rrec, P->rshift, P->nbins, P->ntx, P->nty,
                              P->tile_c, K->O, K->S, (uint32_t)P->capacity, P->tdesc, P->krec, s));
-    SEPW_TRY(launch_item_counts(P->tdesc, P->ntx, P->nty, P->r8, P->nit, s));
-    SEPW_TRY(launch_scan(P->nit, P->itoff, 8 * (int64_t)P->r8 + 1, P->scan_tmp, s));
-    SEPW_TRY(launch_items(P->tdesc, P->itoff, P->ntx, P->nty, P->r8, P->items, s));
+    SEPW_TRY(build_items(P, s));
     if (K->facet) SEPW_TRY(launch_rotation(u, v, w, nvis, g, P->rot, s));
   }
   return SEPW_OK;
@@ -427,12 +451,18 @@ struct BatchScratch {
   int blocks = 0;
   GridArgs* host = nullptr;     // pinned
   GridArgs* jobs = nullptr;     // device
+  MoveArgs* mhost = nullptr;    // pinned movement-pass job table
+  MoveArgs* mjobs = nullptr;    // device
+  uint32_t* mfirst_host = nullptr;  // pinned [cap + 1] first workgroup per job
+  uint32_t* mfirst = nullptr;       // device
   uint32_t* first = nullptr;    // device [cap + 1]
   uint32_t* counter = nullptr;  // device
   hipEvent_t copied = nullptr;
+  int n_cu = 0;
 };
 std::mutex g_bmx;
 BatchScratch g_batch;
+int g_blocks_per_cu = 8;   // persistent batched launch width (set by the autotuner)
 
 int batch_scratch(int njobs, hipStream_t s, BatchScratch** out) {
   std::lock_guard<std::mutex> lk(g_bmx);
@@ -442,24 +472,34 @@ int batch_scratch(int njobs, hipStream_t s, BatchScratch** out) {
   if (b.copied) SEPW_TRY(hipEventSynchronize(b.copied));
   if (b.cap < njobs || b.device != dev) {
     if (b.host) (void)hipHostFree(b.host);
+    if (b.mhost) (void)hipHostFree(b.mhost);
+    if (b.mfirst_host) (void)hipHostFree(b.mfirst_host);
     dfree(b.jobs);
+    dfree(b.mjobs);
+    dfree(b.mfirst);
     dfree(b.first);
     dfree(b.counter);
     if (b.copied) (void)hipEventDestroy(b.copied);
     b = BatchScratch();
     const int cap = njobs < 64 ? 64 : njobs;
     SEPW_TRY(hipHostMalloc(reinterpret_cast<void**>(&b.host), sizeof(GridArgs) * (size_t)cap));
+    SEPW_TRY(hipHostMalloc(reinterpret_cast<void**>(&b.mhost), sizeof(MoveArgs) * (size_t)cap));
+    SEPW_TRY(hipHostMalloc(reinterpret_cast<void**>(&b.mfirst_host),
+                           sizeof(uint32_t) * (size_t)(cap + 1)));
     SEPW_TRY(dalloc(&b.jobs, cap));
+    SEPW_TRY(dalloc(&b.mjobs, cap));
+    SEPW_TRY(dalloc(&b.mfirst, cap + 1));
     SEPW_TRY(dalloc(&b.first, cap + 1));
     SEPW_TRY(dalloc(&b.counter, 1));
     SEPW_TRY(hipEventCreateWithFlags(&b.copied, hipEventDisableTiming));
     hipDeviceProp_t prop;
     SEPW_TRY(hipGetDeviceProperties(&prop, dev));
-    b.blocks = prop.multiProcessorCount * 8;
+    b.n_cu = prop.multiProcessorCount;
     b.cap = cap;
     b.device = dev;
   }
   (void)s;
+  b.blocks = b.n_cu * g_blocks_per_cu;
   *out = &b;
   return SEPW_OK;
 }
@@ -577,9 +617,7 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
   if (p->generation != K->generation) return SEPW_ERR_ARG;
   {
     Stage st(SEPW_STAGE_GATHER, s);
-    SEPW_TRY(launch_vis_to_rows(reinterpret_cast<const float2*>(vis), weight, p->rot, p->key,
-                                p->to_row, p->blkbase, p->nvis, p->ntx, p->rshift, p->nbins,
-                                p->yrow, s));
+    SEPW_TRY(launch_vis_to_rows(move_args(p, vis, weight), s));
   }
   {
     Stage st(SEPW_STAGE_FILL, s);
@@ -694,14 +732,22 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
   BatchScratch* bs = nullptr;
   int rc = batch_scratch(njobs, s, &bs);
   if (rc != SEPW_OK) return rc;
+  // one movement launch for all jobs (job table and workgroup prefix on the host)
+  int64_t mtotal = 0;
+  bs->mfirst_host[0] = 0;
+  for (int j = 0; j < njobs; ++j) {
+    bs->mhost[j] = move_args(plans[j], vis[j], weight ? weight[j] : nullptr);
+    mtotal += move_blocks(plans[j]->nvis);
+    if (mtotal > 0xFFFFFFFFLL) return SEPW_ERR_UNSUPPORTED;
+    bs->mfirst_host[j + 1] = (uint32_t)mtotal;
+  }
+  SEPW_TRY(hipMemcpyAsync(bs->mjobs, bs->mhost, sizeof(MoveArgs) * (size_t)njobs,
+                          hipMemcpyHostToDevice, s));
+  SEPW_TRY(hipMemcpyAsync(bs->mfirst, bs->mfirst_host, sizeof(uint32_t) * (size_t)(njobs + 1),
+                          hipMemcpyHostToDevice, s));
   {
     Stage st(SEPW_STAGE_GATHER, s);
-    for (int j = 0; j < njobs; ++j) {
-      Plan* p = plans[j];
-      SEPW_TRY(launch_vis_to_rows(reinterpret_cast<const float2*>(vis[j]),
-                                  weight ? weight[j] : nullptr, p->rot, p->key, p->to_row,
-                                  p->blkbase, p->nvis, p->ntx, p->rshift, p->nbins, p->yrow, s));
-    }
+    SEPW_TRY(launch_vis_to_rows_batched(bs->mjobs, bs->mfirst, njobs, mtotal, s));
   }
   {
     Stage st(SEPW_STAGE_FILL, s);
@@ -737,6 +783,82 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
     Stage st(SEPW_STAGE_CORRECT, s);
     SEPW_TRY(launch_correct(img, img, K->c1, N, K->fov, K->l0, K->m0, npow, s));
   }
+  return SEPW_OK;
+}
+
+int sepw_plan_set_item_slots(sepw_plan p, int32_t slots, void* hip_stream) {
+  if (!p || slots < kItemMinSlots || slots > kItemMaxSlots || (slots & 3) != 0)
+    return SEPW_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int64_t need = p->nty + p->pcap / slots + 1;
+  if (need > p->max_items) {
+    // the old list may still be read by queued launches on this stream
+    SEPW_TRY(hipStreamSynchronize(s));
+    int4* items = nullptr;
+    SEPW_TRY(dalloc(&items, need));
+    dfree(p->items);
+    p->items = items;
+    p->max_items = need;
+  }
+  p->item_slots = slots;
+  SEPW_TRY(build_items(p, s));
+  return SEPW_OK;
+}
+
+int sepw_autotune_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* const* vis,
+                          const float* const* weight, sepw_c64* const* out, void* hip_stream,
+                          int32_t* item_slots, int32_t* blocks_per_cu) {
+  if (njobs < 1 || !plans) return SEPW_ERR_ARG;
+  for (int j = 0; j < njobs; ++j)
+    if (!plans[j]) return SEPW_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int kSlots[] = {256, 512, 1024, 2048};
+  const int kWidth[] = {2, 4, 8};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  SEPW_TRY(hipEventCreate(&e0));
+  hipError_t he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return map_hip(he);
+  }
+  float best = 0.f;
+  int best_slots = kItemMaxVis, best_width = 8, rc = SEPW_OK;
+  for (int si = 0; si < 4 && rc == SEPW_OK; ++si) {
+    for (int j = 0; j < njobs && rc == SEPW_OK; ++j)
+      rc = sepw_plan_set_item_slots(plans[j], kSlots[si], hip_stream);
+    for (int wi = 0; wi < 3 && rc == SEPW_OK; ++wi) {
+      {
+        std::lock_guard<std::mutex> lk(g_bmx);
+        g_blocks_per_cu = kWidth[wi];
+      }
+      rc = sepw_grid_batched(njobs, plans, vis, weight, out, SEPW_GRID_ONLY, hip_stream);
+      if (rc != SEPW_OK) break;
+      he = hipEventRecord(e0, s);
+      for (int r = 0; r < 2 && rc == SEPW_OK; ++r)
+        rc = sepw_grid_batched(njobs, plans, vis, weight, out, SEPW_GRID_ONLY, hip_stream);
+      if (he == hipSuccess) he = hipEventRecord(e1, s);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he != hipSuccess) rc = map_hip(he);
+      if (rc == SEPW_OK && (best == 0.f || ms < best)) {
+        best = ms;
+        best_slots = kSlots[si];
+        best_width = kWidth[wi];
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  {
+    std::lock_guard<std::mutex> lk(g_bmx);
+    g_blocks_per_cu = best_width;
+  }
+  for (int j = 0; j < njobs && rc == SEPW_OK; ++j)
+    rc = sepw_plan_set_item_slots(plans[j], best_slots, hip_stream);
+  if (rc != SEPW_OK) return rc;
+  if (item_slots) *item_slots = best_slots;
+  if (blocks_per_cu) *blocks_per_cu = best_width;
   return SEPW_OK;
 }
 

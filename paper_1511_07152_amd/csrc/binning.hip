@@ -184,23 +184,25 @@ __device__ inline uint2 row_slots(const uint2* __restrict__ tdesc, int ntx, int6
 __device__ inline int64_t list_index(int64_t r, int r8) { return (r % 8) * r8 + r / 8; }
 
 __global__ void item_counts_kernel(const uint2* __restrict__ tdesc, int ntx, int nty, int r8,
-                                   uint32_t* __restrict__ nit) {
+                                   uint32_t item_slots, uint32_t* __restrict__ nit) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= 8 * (int64_t)r8;
        j += (int64_t)gridDim.x * blockDim.x) {
     uint32_t c = 0;
     const int64_t r = (j % r8) * 8 + j / r8;   // row with list_index(r) == j
     if (j < 8 * (int64_t)r8 && r < nty) {
       const uint2 rs = row_slots(tdesc, ntx, r);
-      c = (rs.y - rs.x + kItemMaxVis - 1) / kItemMaxVis;
+      c = (rs.y - rs.x + item_slots - 1) / item_slots;
     }
     nit[j] = c;
   }
 }
 
 // Item k of row r covers slots [a + k M, min(a + (k + 1) M, e)) of the row's
-// range [a, e); the tile holding its first slot writes it.
+// range [a, e) (M = item_slots, a multiple of 4); the tile holding its first
+// slot writes it.
 __global__ void items_kernel(const uint2* __restrict__ tdesc, const uint32_t* __restrict__ itoff,
-                             int ntx, int nty, int r8, int4* __restrict__ items) {
+                             int ntx, int nty, int r8, uint32_t item_slots,
+                             int4* __restrict__ items) {
   const int64_t nt = (int64_t)ntx * nty;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -210,9 +212,9 @@ __global__ void items_kernel(const uint2* __restrict__ tdesc, const uint32_t* __
     const uint32_t ps = d.x, pe = d.x + round4(d.y - d.x);
     const uint2 rs = row_slots(tdesc, ntx, r);
     const uint32_t o = itoff[list_index(r, r8)];
-    uint32_t k = (ps - rs.x + kItemMaxVis - 1) / kItemMaxVis;
-    for (uint32_t b = rs.x + k * kItemMaxVis; b < pe; b += kItemMaxVis, ++k) {
-      const uint32_t e = rs.y - b > (uint32_t)kItemMaxVis ? b + kItemMaxVis : rs.y;
+    uint32_t k = (ps - rs.x + item_slots - 1) / item_slots;
+    for (uint32_t b = rs.x + k * item_slots; b < pe; b += item_slots, ++k) {
+      const uint32_t e = rs.y - b > item_slots ? b + item_slots : rs.y;
       items[o + k] = make_int4((int)r, (int)b, (int)e, (int)(t - r * ntx));
     }
   }
@@ -482,32 +484,46 @@ __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
 // gridding kernels read W V, and the degridding kernels write their results,
 // at the row-bin positions held in the tile slots.
 
-// Run starts (row-bin array) and starts inside the chunk of this block's runs.
+// Run starts (row-bin array, from this chunk's row of blkbase) and run
+// starts inside the chunk.
 __device__ inline void chunk_runs(const uint32_t* __restrict__ key,
-                                  const uint32_t* __restrict__ blkbase, int64_t first,
+                                  const uint32_t* __restrict__ chunk_base, int64_t first,
                                   int64_t nvis, int ntx, int rshift, int nbins, uint32_t* cnt,
                                   uint32_t* pre, uint32_t* base, uint32_t* wsum) {
   chunk_hist(key, first, nvis, ntx, rshift, nbins, cnt);
   for (int b = threadIdx.x; b < nbins; b += kL1Threads) {
     pre[b] = cnt[b];
-    base[b] = blkbase[(int64_t)blockIdx.x * nbins + b];
+    base[b] = chunk_base[b];
   }
   __syncthreads();
   block_scan_bins(pre, nbins, wsum);
 }
 
-// yrow[to_row[i]] = V[i] W[i] rot[i]
-__global__ __launch_bounds__(kL1Threads) void to_rows_kernel(
-    const float2* __restrict__ vis, const float* __restrict__ weight,
-    const float2* __restrict__ rot, const uint32_t* __restrict__ key,
-    const uint32_t* __restrict__ to_row, const uint32_t* __restrict__ blkbase, int64_t nvis,
-    int ntx, int rshift, int nbins, float2* __restrict__ yrow) {
-  __shared__ uint32_t cnt[kMaxRowBins], pre[kMaxRowBins], base[kMaxRowBins];
-  __shared__ uint32_t wsum[kL1Threads / 64];
-  __shared__ float2 stage[kChunk];
-  __shared__ uint16_t binof[kChunk];
-  const int64_t first = (int64_t)blockIdx.x * kChunk;
-  chunk_runs(key, blkbase, first, nvis, ntx, rshift, nbins, cnt, pre, base, wsum);
+// yrow[to_row[i]] = V[i] W[i] rot[i] for chunk `chunk` of one job
+struct ToRowsLds {
+  uint32_t cnt[kMaxRowBins], pre[kMaxRowBins], base[kMaxRowBins];
+  uint32_t wsum[kL1Threads / 64];
+  float2 stage[kChunk];
+  uint16_t binof[kChunk];
+};
+
+__device__ inline void to_rows_chunk(const MoveArgs& a, int64_t chunk, ToRowsLds& L) {
+  const float2* __restrict__ vis = a.vis;
+  const float* __restrict__ weight = a.weight;
+  const float2* __restrict__ rot = a.rot;
+  const uint32_t* __restrict__ key = a.key;
+  const uint32_t* __restrict__ to_row = a.to_row;
+  float2* __restrict__ yrow = a.yrow;
+  const int64_t nvis = a.nvis;
+  const int ntx = a.ntx, rshift = a.rshift, nbins = a.nbins;
+  uint32_t* cnt = L.cnt;
+  uint32_t* pre = L.pre;
+  uint32_t* base = L.base;
+  float2* stage = L.stage;
+  uint16_t* binof = L.binof;
+  const int64_t first = chunk * kChunk;
+  chunk_runs(key, a.blkbase + chunk * nbins, first, nvis, ntx, rshift, nbins, cnt, pre, base,
+             L.wsum);
   for (int m = 0; m < kChunk / kL1Threads; ++m) {
     const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
     if (i >= nvis) break;
@@ -536,6 +552,25 @@ __global__ __launch_bounds__(kL1Threads) void to_rows_kernel(
   }
 }
 
+__global__ __launch_bounds__(kL1Threads) void to_rows_kernel(MoveArgs a) {
+  __shared__ ToRowsLds L;
+  to_rows_chunk(a, blockIdx.x, L);
+}
+
+// Many jobs in one launch: block b works on chunk b - first[j] of the job j
+// with first[j] <= b < first[j + 1].
+__global__ __launch_bounds__(kL1Threads) void to_rows_batched_kernel(
+    const MoveArgs* __restrict__ jobs, const uint32_t* __restrict__ first, int njobs) {
+  __shared__ ToRowsLds L;
+  const uint32_t b = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  to_rows_chunk(jobs[lo], (int64_t)(b - first[lo]), L);
+}
+
 // out[i] = yrow[to_row[i]] conj(rot[i]), 0 for dropped visibilities
 __global__ __launch_bounds__(kL1Threads) void from_rows_kernel(
     const float2* __restrict__ yrow, const uint32_t* __restrict__ key,
@@ -547,7 +582,8 @@ __global__ __launch_bounds__(kL1Threads) void from_rows_kernel(
   __shared__ float2 stage[kChunk];
   __shared__ uint16_t binof[kChunk];
   const int64_t first = (int64_t)blockIdx.x * kChunk;
-  chunk_runs(key, blkbase, first, nvis, ntx, rshift, nbins, cnt, pre, base, wsum);
+  chunk_runs(key, blkbase + (int64_t)blockIdx.x * nbins, first, nvis, ntx, rshift, nbins, cnt,
+             pre, base, wsum);
   constexpr int kPer = kChunk / kL1Threads;
   uint32_t idx[kPer];   // staged position of this thread's visibilities (or kDropped)
 #pragma unroll
@@ -646,14 +682,20 @@ hipError_t launch_row_sort(const uint32_t* rowoff, const uint32_t* prowoff, cons
   return hipGetLastError();
 }
 
-hipError_t launch_vis_to_rows(const float2* vis, const float* weight, const float2* rot,
-                              const uint32_t* key, const uint32_t* to_row, const uint32_t* blkbase,
-                              int64_t nvis, int ntx, int rshift, int nbins, float2* yrow,
-                              hipStream_t s) {
-  if (nvis == 0) return hipSuccess;
-  const int64_t nb = (nvis + kChunk - 1) / kChunk;
-  hipLaunchKernelGGL(to_rows_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, vis, weight, rot,
-                     key, to_row, blkbase, nvis, ntx, rshift, nbins, yrow);
+hipError_t launch_vis_to_rows(const MoveArgs& a, hipStream_t s) {
+  if (a.nvis == 0) return hipSuccess;
+  const int64_t nb = (a.nvis + kChunk - 1) / kChunk;
+  hipLaunchKernelGGL(to_rows_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, a);
+  return hipGetLastError();
+}
+
+int64_t move_blocks(int64_t nvis) { return (nvis + kChunk - 1) / kChunk; }
+
+hipError_t launch_vis_to_rows_batched(const MoveArgs* jobs, const uint32_t* first, int njobs,
+                                      int64_t total_blocks, hipStream_t s) {
+  if (total_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(to_rows_batched_kernel, dim3((unsigned)total_blocks), dim3(kL1Threads), 0, s,
+                     jobs, first, njobs);
   return hipGetLastError();
 }
 
@@ -674,17 +716,17 @@ hipError_t launch_rotation(const double* u, const double* v, const double* w, in
   return hipGetLastError();
 }
 
-hipError_t launch_item_counts(const uint2* tdesc, int ntx, int nty, int r8, uint32_t* nit,
-                              hipStream_t s) {
+hipError_t launch_item_counts(const uint2* tdesc, int ntx, int nty, int r8, int item_slots,
+                              uint32_t* nit, hipStream_t s) {
   hipLaunchKernelGGL(item_counts_kernel, grid_for(8 * (int64_t)r8 + 1), dim3(kThreads), 0, s, tdesc,
-                     ntx, nty, r8, nit);
+                     ntx, nty, r8, (uint32_t)item_slots, nit);
   return hipGetLastError();
 }
 
 hipError_t launch_items(const uint2* tdesc, const uint32_t* itoff, int ntx, int nty, int r8,
-                        int4* items, hipStream_t s) {
+                        int item_slots, int4* items, hipStream_t s) {
   hipLaunchKernelGGL(items_kernel, grid_for((int64_t)ntx * nty), dim3(kThreads), 0, s, tdesc,
-                     itoff, ntx, nty, r8, items);
+                     itoff, ntx, nty, r8, (uint32_t)item_slots, items);
   return hipGetLastError();
 }
 

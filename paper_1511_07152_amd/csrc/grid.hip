@@ -20,8 +20,9 @@
 // bases and the row-bin position of its W V) and its W V are loaded once, one
 // slot per lane, 64 slots at a time and two batches ahead; ds_bpermute then
 // hands each MFMA lane the record of its group's visibility, and the table
-// taps come through the caches.  Taps for group g + 1 are fetched while group
-// g is multiplied.
+// taps come through the caches as buffer loads with 32-bit offsets.  Each
+// step multiplies group g and then fetches group g + 2 into the registers it
+// just consumed, so taps have two groups' time to arrive.
 // Region accumulation: when the walk moves to another tile, the 16 x 16
 // region sums are added (plain read-modify-write) into a per-wave ring of 32
 // grid columns x 16 rows in LDS at their absolute columns, and the sums
@@ -101,12 +102,26 @@ struct GridCtx {
   const int4* krec;
   const float2* yrow;
   float* grid;
-  float* ring;          // this wave's LDS ring
-  const float2* tu_tab;
-  const float2* tv_tab;
+  float* ring;                  // this wave's LDS ring
+  __amdgpu_buffer_rsrc_t tu;    // padded tables as buffer resources
+  __amdgpu_buffer_rsrc_t tv;
   int N, checker;
   int s0, last, ng, by, lane, col, grp;
+  int col8, grp4;               // col * 8 (tap byte offset), grp * 4 (bpermute lane offset)
 };
+
+// Buffer resource over n bytes at p (raw 32-bit dword loads; reads past n return 0).
+__device__ inline __amdgpu_buffer_rsrc_t table_rsrc(const float2* p, int64_t n_entries) {
+  const int64_t bytes = n_entries * (int64_t)sizeof(float2);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(p), (short)0,
+                                           (int)(bytes < 0x7FFFFFFF ? bytes : 0x7FFFFFFF),
+                                           0x00020000);
+}
+
+__device__ inline float2 tap(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+  return make_float2(__int_as_float(v[0]), __int_as_float(v[1]));
+}
 
 __device__ inline void region_parts(const GridState& st, f32x4& re, f32x4& im) {
 #pragma unroll
@@ -124,25 +139,23 @@ __device__ inline float bperm(int addr, float v) {
 // of the batch (R, Y), moved to this lane, then its table taps.
 __device__ __forceinline__ void fetch_group(const GridCtx& c, const int4& R, const float2& Y,
                                             int j, GroupOps& o) {
-  const int src = (4 * (j & 15) + c.grp) << 2;
+  const int src = c.grp4 + ((j & 15) << 4);
   const int kx = __builtin_amdgcn_ds_bpermute(src, R.x);
   const int ky = __builtin_amdgcn_ds_bpermute(src, R.y);
   o.y = make_float2(bperm(src, Y.x), bperm(src, Y.y));
-  o.tu = c.tu_tab[kx + c.col];
-  o.tv = c.tv_tab[ky + c.col];
+  o.tu = tap(c.tu, (kx << 3) + c.col8);
+  o.tv = tap(c.tv, (ky << 3) + c.col8);
 }
 
-// One pipeline step: group g from cur (taps in flight or ready) while the
-// operands of group g + 1 (from batch registers R, Y) go into nxt.  The fetch
-// is unconditional (past the item's end it reads a harmless repeat), so that
-// every path leaves the same loads in flight.  Buffers alternate.
+// One pipeline step: multiply group g from buf (fetched two steps earlier),
+// then fetch group g + 2 (from batch registers R, Y) into the same registers.
+// The fetch is unconditional (past the item's end it reads harmless repeats of
+// valid records), so that every path leaves the same loads in flight.
 template <int S>
 __device__ __forceinline__ void grid_step(const GridCtx& c, int g, const int4& R, const float2& Y,
-                                          TileWalk& tw, GridState& st, const GroupOps& cur,
-                                          GroupOps& nxt) {
+                                          TileWalk& tw, GridState& st, GroupOps& buf) {
   constexpr int C = kRegion + 1 - S;
   constexpr int H = S / 2;
-  fetch_group(c, R, Y, g + 1, nxt);
   if (c.s0 + 4 * g >= st.pe) {
     // next non-empty tile of the row: bank the region sums in the ring,
     // flush ring columns the new region cannot reach, restart the sums
@@ -166,11 +179,12 @@ __device__ __forceinline__ void grid_step(const GridCtx& c, int g, const int4& R
       st.pe = tw.padded_end();
     }
   }
-  const float b_re = cur.y.x * cur.tu.x - cur.y.y * cur.tu.y;   // row product W V Tu
-  const float b_im = cur.y.x * cur.tu.y + cur.y.y * cur.tu.x;
-  st.p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.tv.x, b_re, st.p1, 0, 0, 0);
-  st.p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.tv.y, b_im, st.p2, 0, 0, 0);
-  st.p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.tv.x + cur.tv.y, b_re + b_im, st.p3, 0, 0, 0);
+  const float b_re = buf.y.x * buf.tu.x - buf.y.y * buf.tu.y;   // row product W V Tu
+  const float b_im = buf.y.x * buf.tu.y + buf.y.y * buf.tu.x;
+  st.p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(buf.tv.x, b_re, st.p1, 0, 0, 0);
+  st.p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(buf.tv.y, b_im, st.p2, 0, 0, 0);
+  st.p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(buf.tv.x + buf.tv.y, b_re + b_im, st.p3, 0, 0, 0);
+  fetch_group(c, R, Y, g + 2, buf);
 }
 
 // One work item of one gridding job; tu_tab / tv_tab are the padded tables
@@ -187,8 +201,8 @@ __device__ __forceinline__ void grid_item(const GridArgs& a, float* ring, int it
   c.yrow = a.yrow;
   c.grid = reinterpret_cast<float*>(a.grid);
   c.ring = ring;
-  c.tu_tab = a.tab_u;
-  c.tv_tab = a.tab_v;
+  c.tu = table_rsrc(a.tab_u, a.tab_len);
+  c.tv = table_rsrc(a.tab_v, a.tab_len);
   c.N = a.N;
   c.checker = a.checker;
   c.s0 = uniform(item.y);
@@ -198,6 +212,8 @@ __device__ __forceinline__ void grid_item(const GridArgs& a, float* ring, int it
   c.lane = lane;
   c.col = col;
   c.grp = grp;
+  c.col8 = col << 3;
+  c.grp4 = grp << 2;
   TileWalk tw;
   tw.start(a.tdesc + (int64_t)ty * a.ntx, a.ntx, uniform(item.w), lane);
   GridState st;
@@ -214,20 +230,21 @@ __device__ __forceinline__ void grid_item(const GridArgs& a, float* ring, int it
   int4 r2 = c.krec[min(c.s0 + 128 + lane, c.last)];
   float2 y0 = c.yrow[r0.z];
   float2 y1 = c.yrow[r1.z];
-  GroupOps A, B;
+  GroupOps A, B;   // groups of even / odd index
   fetch_group(c, r0, y0, 0, A);
+  fetch_group(c, r0, y0, 1, B);
   int g = 0;
   while (true) {
-    // the 16 groups of one batch; the last one fetches from the next batch
+    // the 16 groups of one batch; the last two fetch from the next batch
     for (int p = 0; p < 7; ++p) {
-      grid_step<S>(c, g, r0, y0, tw, st, A, B);
+      grid_step<S>(c, g, r0, y0, tw, st, A);
       if (++g >= c.ng) goto done;
-      grid_step<S>(c, g, r0, y0, tw, st, B, A);
+      grid_step<S>(c, g, r0, y0, tw, st, B);
       if (++g >= c.ng) goto done;
     }
-    grid_step<S>(c, g, r0, y0, tw, st, A, B);
+    grid_step<S>(c, g, r1, y1, tw, st, A);
     if (++g >= c.ng) goto done;
-    grid_step<S>(c, g, r1, y1, tw, st, B, A);
+    grid_step<S>(c, g, r1, y1, tw, st, B);
     if (++g >= c.ng) goto done;
     // next batch: W V one batch ahead (its records arrived a batch ago),
     // records two batches ahead

@@ -13,7 +13,9 @@ namespace sepw {
 constexpr uint32_t kDropped = 0xFFFFFFFFu;
 constexpr int kRegion = 16;        // MFMA tile region edge (cells): core + S - 1
 constexpr int kMaxSupport = 15;    // S <= kRegion - 1
-constexpr int kItemMaxVis = 1024;  // visibilities per work item (a slice of a tile row)
+constexpr int kItemMaxVis = 1024;  // default slots per work item (a slice of a tile row)
+constexpr int kItemMinSlots = 64;  // range of the tunable item length
+constexpr int kItemMaxSlots = 8192;
 constexpr int kMaxRowBins = 4096;  // level-1 sort bins (rows of tiles, possibly grouped)
 constexpr int kL1Chunk = 10240;    // visibilities per workgroup in the level-1 passes
 constexpr int kTargetRowBins = 2048;
@@ -80,7 +82,8 @@ struct Plan {
   int64_t pcap = 0;             // tile slots the slot-order buffers were sized for
   int tile_c = 0, ntx = 0, nty = 0;
   int64_t ntiles = 0;
-  int64_t max_items = 0;
+  int64_t max_items = 0;        // capacity of items (for the smallest item length used so far)
+  int item_slots = kItemMaxVis; // slots per work item (multiple of 4)
   int rshift = 0, nbins = 0;    // level-1 sort: row bin = tile row >> rshift
   uint32_t* key = nullptr;      // [nvis] tile id or kDropped (caller order)
   uint2* qrec = nullptr;        // [nvis] packed bins (caller order)
@@ -142,10 +145,23 @@ hipError_t launch_row_sort(const uint32_t* rowoff, const uint32_t* prowoff, cons
                            int rshift, int nbins, int ntx, int nty, int tile_c, int O, int S,
                            uint32_t zero_row, uint2* tdesc, int4* krec, hipStream_t s);
 // caller-order W V (times the facet rotation) -> row-bin order
-hipError_t launch_vis_to_rows(const float2* vis, const float* weight, const float2* rot,
-                              const uint32_t* key, const uint32_t* to_row, const uint32_t* blkbase,
-                              int64_t nvis, int ntx, int rshift, int nbins, float2* yrow,
-                              hipStream_t s);
+struct MoveArgs {
+  const float2* vis;
+  const float* weight;      // may be null (all 1)
+  const float2* rot;        // may be null
+  const uint32_t* key;
+  const uint32_t* to_row;
+  const uint32_t* blkbase;
+  float2* yrow;
+  int64_t nvis;
+  int ntx, rshift, nbins;
+};
+hipError_t launch_vis_to_rows(const MoveArgs& a, hipStream_t s);
+// workgroups of the movement pass for nvis visibilities
+int64_t move_blocks(int64_t nvis);
+// all jobs in one launch: first[j] = first workgroup of job j (device, njobs + 1 entries)
+hipError_t launch_vis_to_rows_batched(const MoveArgs* jobs, const uint32_t* first, int njobs,
+                                      int64_t total_blocks, hipStream_t s);
 // row-bin-order results -> caller order, rotation undone (dropped visibilities get 0)
 hipError_t launch_vis_from_rows(const float2* yrow, const float2* rot, const uint32_t* key,
                                 const uint32_t* to_row, const uint32_t* blkbase, int64_t nvis,
@@ -154,12 +170,12 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* t
 int64_t scan_tmp_size(int64_t n);
 hipError_t launch_rotation(const double* u, const double* v, const double* w, int64_t nvis,
                            QuantGeom g, float2* rot, hipStream_t s);
-// work items: slices of <= kItemMaxVis slots of each row of tiles
+// work items: slices of <= item_slots slots of each row of tiles
 // per-row item counts in list order (nit[(r % 8) r8 + r / 8]) and the items in that order
-hipError_t launch_item_counts(const uint2* tdesc, int ntx, int nty, int r8, uint32_t* nit,
-                              hipStream_t s);
+hipError_t launch_item_counts(const uint2* tdesc, int ntx, int nty, int r8, int item_slots,
+                              uint32_t* nit, hipStream_t s);
 hipError_t launch_items(const uint2* tdesc, const uint32_t* itoff, int ntx, int nty, int r8,
-                        int4* items, hipStream_t s);
+                        int item_slots, int4* items, hipStream_t s);
 hipError_t launch_bins_export(const uint2* rrec, const uint32_t* to_row, int64_t nvis, int tile_c,
                               int ntx, int32_t* out, hipStream_t s);
 

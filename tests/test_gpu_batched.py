@@ -84,3 +84,45 @@ def test_batched_matches_oracle(lib):
                         plans[j].tile_size, facet=jb["facet"])
         want = o.image(jb["V"], jb["W"], n_power=1)
         assert rel_rms(inner(outs[j].cpu().numpy()), inner(want)) <= 1e-5
+
+
+@pytest.mark.parametrize("slots", [64, 256, 8192])
+def test_item_length_matches_oracle(lib, slots):
+    # work items of 64 .. 8192 slots split the rows of tiles differently; the
+    # grid and the degridded visibilities must not depend on it
+    N, fov, S, O, P = 96, math.radians(1.5), 11, 8, 6
+    jb = _jobs(53, 1, N, fov, [6000])[0]
+    K = lib.Kernels(N, fov, S, O, P, -350.0, 350.0)
+    plan = lib.Plan(K, dev(jb["u"], torch.float64), dev(jb["v"], torch.float64),
+                    dev(jb["w"], torch.float64)).set_item_slots(slots)
+    o = OracleSetup(jb["u"], jb["v"], jb["w"], N, fov, S, O, P, -350.0, 350.0, plan.tile_size)
+    G = lib.grid(plan, dev(jb["V"], torch.complex64), dev(jb["W"], torch.float32),
+                 flags=lib.GRID_ONLY).cpu().numpy()
+    assert rel_rms(G, o.grid(jb["V"], jb["W"])) <= 1e-5
+    X = np.random.default_rng(54).standard_normal((N, N)) + 0j
+    V = lib.degrid(plan, dev(X, torch.complex64), flags=lib.GRID_ONLY).cpu().numpy()
+    assert rel_rms(V, o.degrid_grid(X)) <= 1e-5
+
+
+def test_autotuned_batch_equals_per_job(lib):
+    N, fov, S, O, P = 128, math.radians(1.5), 11, 8, 8
+    counts = [4000, 300, 0, 9000, 1200]
+    jobs = _jobs(55, len(counts), N, fov, counts)
+    plans, Ks = [], []
+    for jb in jobs:
+        K = lib.Kernels(N, fov, S, O, P, -350.0, 350.0, facet=jb["facet"])
+        Ks.append(K)
+        plans.append(lib.Plan(K, dev(jb["u"], torch.float64), dev(jb["v"], torch.float64),
+                              dev(jb["w"], torch.float64)))
+    vis = [dev(jb["V"], torch.complex64) for jb in jobs]
+    wts = [dev(jb["W"], torch.float32) for jb in jobs]
+    slots, width = lib.autotune_batched(plans, vis, wts)
+    assert slots in (256, 512, 1024, 2048) and width in (2, 4, 8)
+    outs = lib.grid_batched(plans, vis, wts, flags=lib.GRID_ONLY)
+    for j, jb in enumerate(jobs):
+        single = lib.grid(plans[j], vis[j], wts[j], flags=lib.GRID_ONLY).cpu().numpy()
+        got = outs[j].cpu().numpy()
+        if counts[j] == 0:
+            assert np.abs(got).max() == 0.0
+        else:
+            assert rel_rms(got, single) <= 1e-6

@@ -272,3 +272,24 @@ def test_facet_grid_and_degrid(lib):
     X = _inner_model(rng, 64)
     V = lib.degrid(plan, dev(X, torch.complex64), flags=lib.DIV_N).cpu().numpy()
     assert rel_rms(V, o.degrid_image(X, n_power=-1)) <= 1e-5
+
+
+# ------------------------------------------------------------------ table placement
+def test_large_tables_cache_path(lib):
+    # P = 256, O = 8, S = 15: one padded table is 256 * 8 * 17 * 8 B = 278 KB,
+    # more than a workgroup's LDS, so degridding reads the taps through the
+    # caches instead of staging them in LDS; both paths must agree with the oracle
+    rng = np.random.default_rng(23)
+    N, fov, S, O, P = 64, math.radians(2.0), 15, 8, 256
+    n = 3000
+    d = dict(u=rng.uniform(-24, 24, n) / fov, v=rng.uniform(-24, 24, n) / fov,
+             w=rng.uniform(-200, 200, n), V=rng.standard_normal(n) + 1j * rng.standard_normal(n),
+             W=rng.uniform(0.5, 2.0, n), N=N, fov=fov, S=S, O=O, P=P, w_lo=-200.0, w_hi=200.0)
+    K, plan = _make(lib, d)
+    o = _oracle(d, plan)
+    G = lib.grid(plan, dev(d["V"], torch.complex64), dev(d["W"], torch.float32),
+                 flags=lib.GRID_ONLY).cpu().numpy()
+    assert rel_rms(G, o.grid(d["V"], d["W"])) <= 1e-5
+    X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    V = lib.degrid(plan, dev(X, torch.complex64), flags=lib.GRID_ONLY).cpu().numpy()
+    assert rel_rms(V, o.degrid_grid(X)) <= 1e-5
