@@ -21,6 +21,7 @@ baseline times the FP64 NumPy oracle on a bounded sample of the same workload.
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -35,6 +36,34 @@ PEAK_HBM_GBS = 8000.0
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_grid_degrid_array4096_fp32.md")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` ("grid" or "degrid") from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary (calibrated against a kernel of known
+    traffic), or None when the kernel's sources have changed since the counters
+    were taken or no summary is present."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    entry = json.loads(m.group(1))["kernels"].get(kernel)
+    if entry is None:
+        return None
+    h = hashlib.sha256()
+    for f in entry["sources"]:
+        try:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        except OSError:
+            return None
+    return entry["bytes_per_launch"] if h.hexdigest() == entry["sources_sha256"] else None
 
 
 def cpu_baseline(d, n_sample):
@@ -254,7 +283,8 @@ def main():
     achieved = flops[dom] / (per_launch[dom] * 1e-3) / 1e12
     roofline = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 2),
                 "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": measured_traffic(dom),
+                "traffic_unit": "bytes/launch",
                 "avg_ms": round(per_launch[dom], 4)}
 
     forms = {}
