@@ -157,12 +157,14 @@ void destroy_plan(Plan* p) {
   dfree(p->qrec);
   dfree(p->rowcount);
   dfree(p->rowoff);
-  dfree(p->rowcursor);
-  dfree(p->blkbase);
+  dfree(p->chist);
+  dfree(p->gsum);
+  dfree(p->delta);
+  dfree(p->ckept);
   dfree(p->rowpad);
   dfree(p->prowoff);
   dfree(p->rrec);
-  dfree(p->to_row);
+  dfree(p->place);
   dfree(p->yrow);
   dfree(p->krec);
   dfree(p->tdesc);
@@ -356,12 +358,16 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
   SEPW_TRY(dalloc(&P->qrec, capacity));
   SEPW_TRY(dalloc(&P->rowcount, P->nbins + 1));
   SEPW_TRY(dalloc(&P->rowoff, P->nbins + 1));
-  SEPW_TRY(dalloc(&P->rowcursor, P->nbins + 1));
-  SEPW_TRY(dalloc(&P->blkbase, ((capacity + kL1Chunk - 1) / kL1Chunk + 1) * (int64_t)P->nbins));
+  const int64_t nch = (capacity + kL1Chunk - 1) / kL1Chunk;
+  const int64_t ngroups = (nch + kGroupChunks - 1) / kGroupChunks;
+  SEPW_TRY(dalloc(&P->chist, std::max<int64_t>(nch, 1) * P->nbins));
+  SEPW_TRY(dalloc(&P->gsum, std::max<int64_t>(ngroups, 1) * P->nbins));
+  SEPW_TRY(dalloc(&P->delta, std::max<int64_t>(nch, 1) * P->nbins));
+  SEPW_TRY(dalloc(&P->ckept, std::max<int64_t>(nch, 1)));
   SEPW_TRY(dalloc(&P->rowpad, P->nbins + 1));
   SEPW_TRY(dalloc(&P->prowoff, P->nbins + 1));
   SEPW_TRY(dalloc(&P->rrec, capacity));
-  SEPW_TRY(dalloc(&P->to_row, capacity));
+  SEPW_TRY(dalloc(&P->place, capacity));
   SEPW_TRY(dalloc(&P->yrow, capacity + 1));
   SEPW_TRY(dalloc(&P->krec, P->pcap));
   SEPW_TRY(dalloc(&P->tdesc, nt));
@@ -379,13 +385,11 @@ MoveArgs move_args(const Plan* p, const sepw_c64* vis, const float* weight) {
   m.vis = reinterpret_cast<const float2*>(vis);
   m.weight = weight;
   m.rot = p->rot;
-  m.key = p->key;
-  m.to_row = p->to_row;
-  m.blkbase = p->blkbase;
+  m.place = p->place;
+  m.delta = p->delta;
+  m.ckept = p->ckept;
   m.yrow = p->yrow;
   m.nvis = p->nvis;
-  m.ntx = p->ntx;
-  m.rshift = p->rshift;
   m.nbins = p->nbins;
   return m;
 }
@@ -408,19 +412,19 @@ int bin_plan(Plan* P, int64_t nvis, const double* u, const double* v, const doub
   P->generation = K->generation;
   {
     Stage st(SEPW_STAGE_QUANTISE, s);
-    SEPW_TRY(launch_fill_u32(P->rowcount, 0u, P->nbins + 1, s));
     SEPW_TRY(launch_quantise_rows(u, v, w, nvis, g, P->rshift, P->nbins, P->key, P->qrec,
-                                  P->rowcount, s));
+                                  P->chist, s));
   }
   {
     Stage st(SEPW_STAGE_SORT, s);
+    SEPW_TRY(launch_level1_counts(P->chist, nvis, P->nbins, P->gsum, P->rowcount, s));
     SEPW_TRY(launch_scan(P->rowcount, P->rowoff, P->nbins + 1, P->scan_tmp, s));
-    SEPW_TRY(hipMemcpyAsync(P->rowcursor, P->rowoff, sizeof(uint32_t) * (size_t)(P->nbins + 1),
-                            hipMemcpyDeviceToDevice, s));
+    SEPW_TRY(launch_chunk_deltas(P->chist, P->gsum, P->rowoff, nvis, P->nbins, P->delta, P->ckept,
+                                 s));
     SEPW_TRY(launch_pad_sizes(P->rowcount, P->nbins, P->rshift, P->ntx, P->nty, P->rowpad, s));
     SEPW_TRY(launch_scan(P->rowpad, P->prowoff, P->nbins + 1, P->scan_tmp, s));
-    SEPW_TRY(launch_row_scatter(P->key, P->qrec, nvis, P->ntx, P->rshift, P->nbins, P->rowcursor,
-                                P->blkbase, P->rrec, P->to_row, s));
+    SEPW_TRY(launch_row_scatter(P->key, P->qrec, nvis, P->ntx, P->rshift, P->nbins, P->chist,
+                                P->delta, P->rrec, P->place, s));
     // padding slots point at yrow[capacity], which nothing writes: keep it 0
     SEPW_TRY(launch_zero_c64(P->yrow + P->capacity, 1, s));
     SEPW_TRY(launch_row_sort(P->rowoff, P->prowoff, P->rrec, P->rshift, P->nbins, P->ntx, P->nty,
@@ -599,8 +603,8 @@ int32_t sepw_plan_tile_size(sepw_plan p) { return p ? p->tile_c : 0; }
 
 int sepw_plan_bins(sepw_plan p, int32_t* out, void* hip_stream) {
   if (!p || (!out && p->nvis > 0)) return SEPW_ERR_ARG;
-  SEPW_TRY(launch_bins_export(p->rrec, p->to_row, p->nvis, p->tile_c, p->ntx, out,
-                              static_cast<hipStream_t>(hip_stream)));
+  SEPW_TRY(launch_bins_export(p->rrec, p->place, p->delta, p->nbins, p->nvis, p->tile_c, p->ntx,
+                              out, static_cast<hipStream_t>(hip_stream)));
   return SEPW_OK;
 }
 
@@ -694,8 +698,8 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
   }
   {
     Stage st(SEPW_STAGE_GATHER, s);
-    SEPW_TRY(launch_vis_from_rows(p->yrow, p->rot, p->key, p->to_row, p->blkbase, p->nvis, p->ntx,
-                                  p->rshift, p->nbins, vo, s));
+    SEPW_TRY(launch_vis_from_rows(p->yrow, p->rot, p->place, p->delta, p->ckept, p->nvis,
+                                  p->nbins, vo, s));
   }
   return SEPW_OK;
 }

@@ -15,10 +15,11 @@
 //
 // Tiles are c x c blocks of cells (c = 17 - S, so that a tile's S x S
 // footprints fit in a 16 x 16 region), numbered row-major.  Sorting is a
-// two-level counting sort.  Level 1 (by row bin = tile row >> rshift): each
-// block of kChunk visibilities builds its histogram in LDS, the bins are
-// scanned, and each block reserves one contiguous range per non-empty bin with
-// a single global atomic, then places its visibilities with LDS atomics.
+// two-level counting sort.  Level 1 (by row bin = tile row >> rshift): the
+// quantiser writes the histogram of each chunk of kChunk visibilities; a scan
+// down the chunks of every bin (chunk groups, then chunks inside a group) gives
+// each chunk one contiguous run per non-empty bin, in chunk order, with no
+// global atomics; each chunk then places its visibilities with LDS atomics.
 // Level 2 (by tile inside the row bin): one workgroup per row bin counts,
 // scans and places its visibilities entirely in LDS.  Each row bin owns a
 // reserved range of tile slots; inside it the tiles follow each other in
@@ -232,18 +233,21 @@ __global__ void job_prefix_kernel(const GridArgs* __restrict__ jobs, int njobs,
   *counter = 0u;
 }
 
-__global__ void bins_export_kernel(const uint2* __restrict__ rrec, const uint32_t* __restrict__ to_row,
-                                   int64_t nvis, int tile_c, int ntx, int32_t* __restrict__ out) {
+__global__ void bins_export_kernel(const uint2* __restrict__ rrec, const uint32_t* __restrict__ place,
+                                   const uint32_t* __restrict__ delta, int nbins, int64_t nvis,
+                                   int tile_c, int ntx, int32_t* __restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nvis;
        i += (int64_t)gridDim.x * blockDim.x) {
     int32_t* o = out + 7 * i;
-    const uint32_t d = to_row[i];
-    if (d == kDropped) {
+    const uint32_t pl = place[i];
+    if (pl == kDropped) {
       o[0] = o[1] = o[2] = o[3] = o[4] = 0;
       o[5] = -1;
       o[6] = 1;
       continue;
     }
+    const uint32_t d =
+        delta[(i / kL1Chunk) * nbins + (pl >> kPlaceShift)] + (pl & kPlaceMask);
     const uint2 r = rrec[d];
     const int cu = r.x & 0xFFFF, cv = r.x >> 16;
     o[0] = cu;
@@ -261,17 +265,12 @@ constexpr int kL1Threads = 1024;
 constexpr int kChunk = kL1Chunk;         // visibilities per block in the level-1 passes
 static_assert(kChunk % kL1Threads == 0, "level-1 chunk must be a multiple of the block size");
 
-// Exclusive scan of a[0, n) (n <= kMaxRowBins) by one 1024-thread workgroup,
-// in place; each thread owns kMaxRowBins / 1024 consecutive entries.
-__device__ inline void block_scan_bins(uint32_t* a, int n, uint32_t* wsum) {
-  constexpr int kPer = kMaxRowBins / kL1Threads;
-  const int t0 = threadIdx.x * kPer;
-  uint32_t v[kPer], sum = 0;
-#pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    v[j] = t0 + j < n ? a[t0 + j] : 0u;
-    sum += v[j];
-  }
+constexpr int kBinsPer = kMaxRowBins / kL1Threads;   // row bins owned by each thread
+
+// Exclusive scan across one 1024-thread workgroup: `sum` is this thread's
+// total (thread t owns bins t kBinsPer .. t kBinsPer + kBinsPer - 1); returns
+// the sum over the threads before it and sets *total to the workgroup's sum.
+__device__ inline uint32_t block_scan_owned(uint32_t sum, uint32_t* wsum, uint32_t* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t x = sum;
   for (int o = 1; o < 64; o <<= 1) {
@@ -280,34 +279,22 @@ __device__ inline void block_scan_bins(uint32_t* a, int n, uint32_t* wsum) {
   }
   if (lane == 63) wsum[wave] = x;
   __syncthreads();
-  uint32_t run = x - sum;
-  for (int w = 0; w < wave; ++w) run += wsum[w];
+  uint32_t run = x - sum, tot = 0;
 #pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    if (t0 + j < n) a[t0 + j] = run;
-    run += v[j];
+  for (int w = 0; w < kL1Threads / 64; ++w) {
+    const uint32_t ws = wsum[w];
+    if (w < wave) run += ws;
+    tot += ws;
   }
-  __syncthreads();
-}
-
-// Per-block bin counts of the kept visibilities of chunk [first, first + kChunk).
-__device__ inline void chunk_hist(const uint32_t* __restrict__ key, int64_t first, int64_t nvis,
-                                  int ntx, int rshift, int nbins, uint32_t* cnt) {
-  for (int b = threadIdx.x; b < nbins; b += kL1Threads) cnt[b] = 0u;
-  __syncthreads();
-  for (int m = 0; m < kChunk / kL1Threads; ++m) {
-    const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
-    if (i >= nvis) break;
-    const uint32_t kk = key[i];
-    if (kk != kDropped) atomicAdd(&cnt[(kk / (uint32_t)ntx) >> rshift], 1u);
-  }
-  __syncthreads();
+  __syncthreads();   // wsum is reused by the next scan
+  *total = tot;
+  return run;
 }
 
 __global__ __launch_bounds__(kL1Threads) void quantise_rows_kernel(
     const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
     int64_t nvis, QuantGeom g, int rshift, int nbins, uint32_t* __restrict__ key,
-    uint2* __restrict__ qrec, uint32_t* __restrict__ rowcount) {
+    uint2* __restrict__ qrec, uint32_t* __restrict__ chist) {
   __shared__ uint32_t hist[kMaxRowBins];
   for (int b = threadIdx.x; b < nbins; b += kL1Threads) hist[b] = 0u;
   __syncthreads();
@@ -340,8 +327,98 @@ __global__ __launch_bounds__(kL1Threads) void quantise_rows_kernel(
     }
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < nbins; b += kL1Threads)
-    if (hist[b]) atomicAdd(&rowcount[b], hist[b]);
+  uint32_t* row = chist + (int64_t)blockIdx.x * nbins;
+  for (int b = threadIdx.x; b < nbins; b += kL1Threads) row[b] = hist[b];
+}
+
+// gsum[b][g] = visibilities of row bin b in the chunks of group g
+__global__ void group_sums_kernel(const uint32_t* __restrict__ chist, int64_t nch, int nbins,
+                                  int ngroups, uint32_t* __restrict__ gsum) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = blockIdx.y;
+  if (b >= nbins) return;
+  const int64_t c0 = (int64_t)g * kGroupChunks;
+  const int64_t c1 = min(c0 + (int64_t)kGroupChunks, nch);
+  uint32_t sum = 0;
+  for (int64_t c = c0; c < c1; ++c) sum += chist[c * nbins + b];
+  gsum[(int64_t)b * ngroups + g] = sum;
+}
+
+// One workgroup per row bin: exclusive scan of gsum[b][.] in place, total to
+// rowcount[b] (and rowcount[nbins] = 0, so that the scan of rowcount ends with
+// the kept count).
+__global__ __launch_bounds__(256) void group_scan_kernel(uint32_t* __restrict__ gsum, int ngroups,
+                                                         int nbins, uint32_t* __restrict__ rowcount) {
+  __shared__ uint32_t wsum[4];
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t* p = gsum + (int64_t)b * ngroups;
+  uint32_t carry = 0;
+  for (int g0 = 0; g0 < ngroups; g0 += 256) {
+    const int g = g0 + (int)threadIdx.x;
+    const uint32_t v = g < ngroups ? p[g] : 0u;
+    uint32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    uint32_t run = carry + x - v, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const uint32_t ws = wsum[w];
+      if (w < wave) run += ws;
+      tot += ws;
+    }
+    __syncthreads();
+    if (g < ngroups) p[g] = run;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    rowcount[b] = carry;
+    if (b == 0) rowcount[nbins] = 0u;
+  }
+}
+
+// One workgroup per chunk group: walks its chunks in order carrying, per row
+// bin, the row-bin position where the next chunk's run starts (rowoff + the
+// group's prefix), and writes delta[c][b] = that position minus the run's
+// start inside chunk c's bin-ordered staging, plus the chunk's kept count.
+__global__ __launch_bounds__(kL1Threads) void chunk_deltas_kernel(
+    const uint32_t* __restrict__ chist, const uint32_t* __restrict__ gpre,
+    const uint32_t* __restrict__ rowoff, int64_t nch, int nbins, int ngroups,
+    uint32_t* __restrict__ delta, uint32_t* __restrict__ ckept) {
+  __shared__ uint32_t wsum[kL1Threads / 64];
+  const int g = blockIdx.x;
+  const int t0 = threadIdx.x * kBinsPer;
+  uint32_t carry[kBinsPer];
+#pragma unroll
+  for (int j = 0; j < kBinsPer; ++j) {
+    const int b = t0 + j;
+    carry[j] = b < nbins ? rowoff[b] + gpre[(int64_t)b * ngroups + g] : 0u;
+  }
+  const int64_t c0 = (int64_t)g * kGroupChunks;
+  const int64_t c1 = min(c0 + (int64_t)kGroupChunks, nch);
+  for (int64_t c = c0; c < c1; ++c) {
+    const uint32_t* row = chist + c * nbins;
+    uint32_t v[kBinsPer], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kBinsPer; ++j) {
+      v[j] = t0 + j < nbins ? row[t0 + j] : 0u;
+      sum += v[j];
+    }
+    uint32_t total;
+    uint32_t run = block_scan_owned(sum, wsum, &total);
+    uint32_t* d = delta + c * nbins;
+#pragma unroll
+    for (int j = 0; j < kBinsPer; ++j) {
+      if (t0 + j < nbins) d[t0 + j] = carry[j] - run;
+      run += v[j];
+      carry[j] += v[j];
+    }
+    if (threadIdx.x == 0) ckept[c] = total;
+  }
 }
 
 // Slots reserved for row bin b: its visibilities plus room to pad every
@@ -361,52 +438,56 @@ __global__ void pad_sizes_kernel(const uint32_t* __restrict__ rowcount, int nbin
   }
 }
 
-// Level-1 placement.  Each block reserves one contiguous run per row bin for
-// its chunk (one global atomic per bin), records the run starts in blkbase,
-// lays its records out in LDS in bin order and then copies each bin's run to
-// the row-bin array as one contiguous piece.
+// Level-1 placement of one chunk: the scan of its histogram gives the start of
+// each bin's run in the chunk's staging; visibilities are laid out in LDS in
+// bin order (LDS atomics), each gets its placement word, and each run is copied
+// to the row-bin array as one contiguous piece (delta gives its position).
 __global__ __launch_bounds__(kL1Threads) void row_scatter_kernel(
     const uint32_t* __restrict__ key, const uint2* __restrict__ qrec, int64_t nvis, int ntx,
-    int rshift, int nbins, uint32_t* __restrict__ rowcursor, uint32_t* __restrict__ blkbase,
-    uint2* __restrict__ rrec, uint32_t* __restrict__ to_row) {
-  __shared__ uint32_t pre[kMaxRowBins];    // counts, then run starts inside the chunk
-  __shared__ uint32_t cur[kMaxRowBins];    // placement cursors, then run ends
-  __shared__ uint32_t base[kMaxRowBins];   // run starts in the row-bin array
+    int rshift, int nbins, const uint32_t* __restrict__ chist, const uint32_t* __restrict__ delta,
+    uint2* __restrict__ rrec, uint32_t* __restrict__ place) {
+  __shared__ uint32_t cur[kMaxRowBins];   // placement cursors in the staging
+  __shared__ uint32_t dl[kMaxRowBins];    // the chunk's row of delta
   __shared__ uint32_t wsum[kL1Threads / 64];
   __shared__ uint2 stage[kChunk];
   __shared__ uint16_t binof[kChunk];   // row bin of each staged record
-  const int64_t first = (int64_t)blockIdx.x * kChunk;
-  chunk_hist(key, first, nvis, ntx, rshift, nbins, pre);
-  for (int b = threadIdx.x; b < nbins; b += kL1Threads) {
-    const uint32_t c = pre[b];
-    const uint32_t r = c ? atomicAdd(&rowcursor[b], c) : 0u;   // one reservation per bin and block
-    base[b] = r;
-    blkbase[(int64_t)blockIdx.x * nbins + b] = r;
+  const int64_t chunk = blockIdx.x;
+  const int64_t first = chunk * kChunk;
+  const int t0 = threadIdx.x * kBinsPer;
+  uint32_t v[kBinsPer], sum = 0;
+#pragma unroll
+  for (int j = 0; j < kBinsPer; ++j) {
+    v[j] = t0 + j < nbins ? chist[chunk * nbins + t0 + j] : 0u;
+    sum += v[j];
   }
-  block_scan_bins(pre, nbins, wsum);
-  for (int b = threadIdx.x; b < nbins; b += kL1Threads) cur[b] = pre[b];
+  uint32_t kept;
+  uint32_t run = block_scan_owned(sum, wsum, &kept);
+#pragma unroll
+  for (int j = 0; j < kBinsPer; ++j) {
+    if (t0 + j < nbins) {
+      cur[t0 + j] = run;
+      dl[t0 + j] = delta[chunk * nbins + t0 + j];
+    }
+    run += v[j];
+  }
   __syncthreads();
   for (int m = 0; m < kChunk / kL1Threads; ++m) {
     const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
     if (i >= nvis) break;
     const uint32_t kk = key[i];
     if (kk == kDropped) {
-      to_row[i] = kDropped;
+      place[i] = kDropped;
       continue;
     }
     const uint32_t b = (kk / (uint32_t)ntx) >> rshift;
     const uint32_t idx = atomicAdd(&cur[b], 1u);
     stage[idx] = qrec[i];
     binof[idx] = (uint16_t)b;
-    to_row[i] = base[b] + (idx - pre[b]);
+    place[i] = (b << kPlaceShift) | idx;
   }
   __syncthreads();
   // copy out: consecutive lanes take consecutive staged records (runs stay contiguous)
-  const uint32_t kept = cur[nbins - 1];
-  for (uint32_t k = threadIdx.x; k < kept; k += kL1Threads) {
-    const uint32_t b = binof[k];
-    rrec[base[b] + (k - pre[b])] = stage[k];
-  }
+  for (uint32_t k = threadIdx.x; k < kept; k += kL1Threads) rrec[dl[binof[k]] + k] = stage[k];
 }
 
 constexpr int kSortThreads = 1024;
@@ -476,84 +557,62 @@ __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
 }
 
 // ---------------------------------------------------------------- moving data
-// Caller order <-> row-bin order through the level-1 placement map.  A
-// workgroup handles the same chunk of kChunk caller positions as the level-1
-// placement, whose visibilities went to one contiguous run per row bin (run
-// starts in blkbase): it stages the chunk in LDS in bin order and moves each
-// run as one contiguous piece, while the caller side stays coalesced.  The
-// gridding kernels read W V, and the degridding kernels write their results,
-// at the row-bin positions held in the tile slots.
+// Caller order <-> row-bin order through the level-1 placement.  A workgroup
+// handles the same chunk of kChunk caller positions as the level-1 placement:
+// the placement words put the chunk's visibilities into LDS in bin order, and
+// each bin's run moves to or from the row-bin array as one contiguous piece
+// (position = delta[chunk][bin] + staged position), while the caller side
+// stays coalesced.  The gridding kernels read W V, and the degridding kernels
+// write their results, at the row-bin positions held in the tile slots.
+constexpr int kPerThread = kChunk / kL1Threads;
 
-// Run starts (row-bin array, from this chunk's row of blkbase) and run
-// starts inside the chunk.
-__device__ inline void chunk_runs(const uint32_t* __restrict__ key,
-                                  const uint32_t* __restrict__ chunk_base, int64_t first,
-                                  int64_t nvis, int ntx, int rshift, int nbins, uint32_t* cnt,
-                                  uint32_t* pre, uint32_t* base, uint32_t* wsum) {
-  chunk_hist(key, first, nvis, ntx, rshift, nbins, cnt);
-  for (int b = threadIdx.x; b < nbins; b += kL1Threads) {
-    pre[b] = cnt[b];
-    base[b] = chunk_base[b];
-  }
-  __syncthreads();
-  block_scan_bins(pre, nbins, wsum);
-}
-
-// yrow[to_row[i]] = V[i] W[i] rot[i] for chunk `chunk` of one job
-struct ToRowsLds {
-  uint32_t cnt[kMaxRowBins], pre[kMaxRowBins], base[kMaxRowBins];
-  uint32_t wsum[kL1Threads / 64];
+struct MoveLds {
+  uint32_t dl[kMaxRowBins];   // the chunk's row of delta
   float2 stage[kChunk];
   uint16_t binof[kChunk];
 };
 
-__device__ inline void to_rows_chunk(const MoveArgs& a, int64_t chunk, ToRowsLds& L) {
-  const float2* __restrict__ vis = a.vis;
-  const float* __restrict__ weight = a.weight;
-  const float2* __restrict__ rot = a.rot;
-  const uint32_t* __restrict__ key = a.key;
-  const uint32_t* __restrict__ to_row = a.to_row;
-  float2* __restrict__ yrow = a.yrow;
-  const int64_t nvis = a.nvis;
-  const int ntx = a.ntx, rshift = a.rshift, nbins = a.nbins;
-  uint32_t* cnt = L.cnt;
-  uint32_t* pre = L.pre;
-  uint32_t* base = L.base;
-  float2* stage = L.stage;
-  uint16_t* binof = L.binof;
+__device__ inline void load_deltas(const uint32_t* __restrict__ delta, int64_t chunk, int nbins,
+                                   uint32_t* dl) {
+  const uint32_t* row = delta + chunk * nbins;
+  for (int b = threadIdx.x; b < nbins; b += kL1Threads) dl[b] = row[b];
+}
+
+// yrow[row-bin position of i] = V[i] W[i] rot[i] for chunk `chunk` of one job
+__device__ inline void to_rows_chunk(const MoveArgs& a, int64_t chunk, MoveLds& L) {
   const int64_t first = chunk * kChunk;
-  chunk_runs(key, a.blkbase + chunk * nbins, first, nvis, ntx, rshift, nbins, cnt, pre, base,
-             L.wsum);
-  for (int m = 0; m < kChunk / kL1Threads; ++m) {
+  load_deltas(a.delta, chunk, a.nbins, L.dl);
+  uint32_t pl[kPerThread];
+  float2 y[kPerThread];
+  float wt[kPerThread];
+  float2 ro[kPerThread];
+  // all loads of the thread first, then the LDS stores
+#pragma unroll
+  for (int m = 0; m < kPerThread; ++m) {
     const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
-    if (i >= nvis) break;
-    const uint32_t kk = key[i];
-    if (kk == kDropped) continue;
-    const uint32_t b = (kk / (uint32_t)ntx) >> rshift;
-    const uint32_t idx = pre[b] + (to_row[i] - base[b]);
-    float2 y = vis[i];
-    if (weight) {
-      const float wt = weight[i];
-      y.x *= wt;
-      y.y *= wt;
-    }
-    if (rot) {
-      const float2 ro = rot[i];
-      y = make_float2(y.x * ro.x - y.y * ro.y, y.x * ro.y + y.y * ro.x);
-    }
-    stage[idx] = y;
-    binof[idx] = (uint16_t)b;
+    const bool in = i < a.nvis;
+    pl[m] = in ? a.place[i] : kDropped;
+    y[m] = in ? a.vis[i] : make_float2(0.f, 0.f);
+    wt[m] = (in && a.weight) ? a.weight[i] : 1.f;
+    ro[m] = (in && a.rot) ? a.rot[i] : make_float2(1.f, 0.f);
+  }
+#pragma unroll
+  for (int m = 0; m < kPerThread; ++m) {
+    if (pl[m] == kDropped) continue;
+    float2 v = make_float2(y[m].x * wt[m], y[m].y * wt[m]);
+    if (a.rot) v = make_float2(v.x * ro[m].x - v.y * ro[m].y, v.x * ro[m].y + v.y * ro[m].x);
+    const uint32_t k = pl[m] & kPlaceMask;
+    L.stage[k] = v;
+    L.binof[k] = (uint16_t)(pl[m] >> kPlaceShift);
   }
   __syncthreads();
-  const uint32_t kept = pre[nbins - 1] + cnt[nbins - 1];
-  for (uint32_t k = threadIdx.x; k < kept; k += kL1Threads) {
-    const uint32_t b = binof[k];
-    yrow[base[b] + (k - pre[b])] = stage[k];
-  }
+  const uint32_t kept = a.ckept[chunk];
+  for (uint32_t k = threadIdx.x; k < kept; k += kL1Threads)
+    a.yrow[L.dl[L.binof[k]] + k] = L.stage[k];
 }
 
 __global__ __launch_bounds__(kL1Threads) void to_rows_kernel(MoveArgs a) {
-  __shared__ ToRowsLds L;
+  __shared__ MoveLds L;
   to_rows_chunk(a, blockIdx.x, L);
 }
 
@@ -561,7 +620,7 @@ __global__ __launch_bounds__(kL1Threads) void to_rows_kernel(MoveArgs a) {
 // with first[j] <= b < first[j + 1].
 __global__ __launch_bounds__(kL1Threads) void to_rows_batched_kernel(
     const MoveArgs* __restrict__ jobs, const uint32_t* __restrict__ first, int njobs) {
-  __shared__ ToRowsLds L;
+  __shared__ MoveLds L;
   const uint32_t b = blockIdx.x;
   int lo = 0, hi = njobs - 1;
   while (lo < hi) {
@@ -571,49 +630,37 @@ __global__ __launch_bounds__(kL1Threads) void to_rows_batched_kernel(
   to_rows_chunk(jobs[lo], (int64_t)(b - first[lo]), L);
 }
 
-// out[i] = yrow[to_row[i]] conj(rot[i]), 0 for dropped visibilities
+// out[i] = yrow[row-bin position of i] conj(rot[i]), 0 for dropped visibilities
 __global__ __launch_bounds__(kL1Threads) void from_rows_kernel(
-    const float2* __restrict__ yrow, const uint32_t* __restrict__ key,
-    const uint32_t* __restrict__ to_row, const uint32_t* __restrict__ blkbase,
-    const float2* __restrict__ rot, int64_t nvis, int ntx, int rshift, int nbins,
-    float2* __restrict__ out) {
-  __shared__ uint32_t cnt[kMaxRowBins], pre[kMaxRowBins], base[kMaxRowBins];
-  __shared__ uint32_t wsum[kL1Threads / 64];
-  __shared__ float2 stage[kChunk];
-  __shared__ uint16_t binof[kChunk];
-  const int64_t first = (int64_t)blockIdx.x * kChunk;
-  chunk_runs(key, blkbase + (int64_t)blockIdx.x * nbins, first, nvis, ntx, rshift, nbins, cnt,
-             pre, base, wsum);
-  constexpr int kPer = kChunk / kL1Threads;
-  uint32_t idx[kPer];   // staged position of this thread's visibilities (or kDropped)
+    const float2* __restrict__ yrow, const uint32_t* __restrict__ place,
+    const uint32_t* __restrict__ delta, const uint32_t* __restrict__ ckept,
+    const float2* __restrict__ rot, int64_t nvis, int nbins, float2* __restrict__ out) {
+  __shared__ MoveLds L;
+  const int64_t chunk = blockIdx.x;
+  const int64_t first = chunk * kChunk;
+  load_deltas(delta, chunk, nbins, L.dl);
+  uint32_t pl[kPerThread];
 #pragma unroll
-  for (int m = 0; m < kPer; ++m) {
+  for (int m = 0; m < kPerThread; ++m) {
     const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
-    idx[m] = kDropped;
-    if (i < nvis) {
-      const uint32_t kk = key[i];
-      if (kk != kDropped) {
-        const uint32_t b = (kk / (uint32_t)ntx) >> rshift;
-        idx[m] = pre[b] + (to_row[i] - base[b]);
-        binof[idx[m]] = (uint16_t)b;
-      }
-    }
+    pl[m] = i < nvis ? place[i] : kDropped;
   }
+#pragma unroll
+  for (int m = 0; m < kPerThread; ++m)
+    if (pl[m] != kDropped) L.binof[pl[m] & kPlaceMask] = (uint16_t)(pl[m] >> kPlaceShift);
   __syncthreads();
   // read in: consecutive lanes take consecutive records of the runs
-  const uint32_t kept = pre[nbins - 1] + cnt[nbins - 1];
-  for (uint32_t k = threadIdx.x; k < kept; k += kL1Threads) {
-    const uint32_t b = binof[k];
-    stage[k] = yrow[base[b] + (k - pre[b])];
-  }
+  const uint32_t kept = ckept[chunk];
+  for (uint32_t k = threadIdx.x; k < kept; k += kL1Threads)
+    L.stage[k] = yrow[L.dl[L.binof[k]] + k];
   __syncthreads();
 #pragma unroll
-  for (int m = 0; m < kPer; ++m) {
+  for (int m = 0; m < kPerThread; ++m) {
     const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
     if (i >= nvis) break;
     float2 y = make_float2(0.f, 0.f);
-    if (idx[m] != kDropped) {
-      y = stage[idx[m]];
+    if (pl[m] != kDropped) {
+      y = L.stage[pl[m] & kPlaceMask];
       if (rot) {
         const float2 ro = rot[i];
         y = make_float2(y.x * ro.x + y.y * ro.y, y.y * ro.x - y.x * ro.y);
@@ -649,11 +696,34 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* t
 
 hipError_t launch_quantise_rows(const double* u, const double* v, const double* w, int64_t nvis,
                                 QuantGeom g, int rshift, int nbins, uint32_t* key, uint2* qrec,
-                                uint32_t* rowcount, hipStream_t s) {
+                                uint32_t* chist, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
   const int64_t nb = (nvis + kChunk - 1) / kChunk;
   hipLaunchKernelGGL(quantise_rows_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, u, v, w, nvis,
-                     g, rshift, nbins, key, qrec, rowcount);
+                     g, rshift, nbins, key, qrec, chist);
+  return hipGetLastError();
+}
+
+hipError_t launch_level1_counts(const uint32_t* chist, int64_t nvis, int nbins, uint32_t* gsum,
+                                uint32_t* rowcount, hipStream_t s) {
+  const int64_t nch = (nvis + kChunk - 1) / kChunk;
+  const int ngroups = (int)((nch + kGroupChunks - 1) / kGroupChunks);
+  if (ngroups == 0) return launch_fill_u32(rowcount, 0u, nbins + 1, s);
+  hipLaunchKernelGGL(group_sums_kernel, dim3((unsigned)((nbins + 255) / 256), (unsigned)ngroups),
+                     dim3(256), 0, s, chist, nch, nbins, ngroups, gsum);
+  hipLaunchKernelGGL(group_scan_kernel, dim3((unsigned)nbins), dim3(256), 0, s, gsum, ngroups, nbins,
+                     rowcount);
+  return hipGetLastError();
+}
+
+hipError_t launch_chunk_deltas(const uint32_t* chist, const uint32_t* gsum,
+                               const uint32_t* rowoff, int64_t nvis, int nbins, uint32_t* delta,
+                               uint32_t* ckept, hipStream_t s) {
+  const int64_t nch = (nvis + kChunk - 1) / kChunk;
+  const int ngroups = (int)((nch + kGroupChunks - 1) / kGroupChunks);
+  if (ngroups == 0) return hipSuccess;
+  hipLaunchKernelGGL(chunk_deltas_kernel, dim3((unsigned)ngroups), dim3(kL1Threads), 0, s, chist,
+                     gsum, rowoff, nch, nbins, ngroups, delta, ckept);
   return hipGetLastError();
 }
 
@@ -665,12 +735,12 @@ hipError_t launch_pad_sizes(const uint32_t* rowcount, int nbins, int rshift, int
 }
 
 hipError_t launch_row_scatter(const uint32_t* key, const uint2* qrec, int64_t nvis, int ntx,
-                              int rshift, int nbins, uint32_t* rowcursor, uint32_t* blkbase,
-                              uint2* rrec, uint32_t* to_row, hipStream_t s) {
+                              int rshift, int nbins, const uint32_t* chist, const uint32_t* delta,
+                              uint2* rrec, uint32_t* place, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
   const int64_t nb = (nvis + kChunk - 1) / kChunk;
   hipLaunchKernelGGL(row_scatter_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, key, qrec, nvis,
-                     ntx, rshift, nbins, rowcursor, blkbase, rrec, to_row);
+                     ntx, rshift, nbins, chist, delta, rrec, place);
   return hipGetLastError();
 }
 
@@ -699,13 +769,13 @@ hipError_t launch_vis_to_rows_batched(const MoveArgs* jobs, const uint32_t* firs
   return hipGetLastError();
 }
 
-hipError_t launch_vis_from_rows(const float2* yrow, const float2* rot, const uint32_t* key,
-                                const uint32_t* to_row, const uint32_t* blkbase, int64_t nvis,
-                                int ntx, int rshift, int nbins, float2* out, hipStream_t s) {
+hipError_t launch_vis_from_rows(const float2* yrow, const float2* rot, const uint32_t* place,
+                                const uint32_t* delta, const uint32_t* ckept, int64_t nvis,
+                                int nbins, float2* out, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
   const int64_t nb = (nvis + kChunk - 1) / kChunk;
-  hipLaunchKernelGGL(from_rows_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, yrow, key, to_row,
-                     blkbase, rot, nvis, ntx, rshift, nbins, out);
+  hipLaunchKernelGGL(from_rows_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, yrow, place, delta,
+                     ckept, rot, nvis, nbins, out);
   return hipGetLastError();
 }
 
@@ -736,11 +806,12 @@ hipError_t launch_job_prefix(const GridArgs* jobs, int njobs, uint32_t* first, u
   return hipGetLastError();
 }
 
-hipError_t launch_bins_export(const uint2* rrec, const uint32_t* to_row, int64_t nvis, int tile_c,
-                              int ntx, int32_t* out, hipStream_t s) {
+hipError_t launch_bins_export(const uint2* rrec, const uint32_t* place, const uint32_t* delta,
+                              int nbins, int64_t nvis, int tile_c, int ntx, int32_t* out,
+                              hipStream_t s) {
   if (nvis == 0) return hipSuccess;
-  hipLaunchKernelGGL(bins_export_kernel, grid_for(nvis), dim3(kThreads), 0, s, rrec, to_row, nvis,
-                     tile_c, ntx, out);
+  hipLaunchKernelGGL(bins_export_kernel, grid_for(nvis), dim3(kThreads), 0, s, rrec, place, delta,
+                     nbins, nvis, tile_c, ntx, out);
   return hipGetLastError();
 }
 

@@ -18,6 +18,14 @@ constexpr int kItemMinSlots = 64;  // range of the tunable item length
 constexpr int kItemMaxSlots = 8192;
 constexpr int kMaxRowBins = 4096;  // level-1 sort bins (rows of tiles, possibly grouped)
 constexpr int kL1Chunk = 10240;    // visibilities per workgroup in the level-1 passes
+constexpr int kGroupChunks = 16;   // level-1 chunks per group of the run-offset scan
+// placement word of a kept visibility: row bin << kPlaceShift | its position in
+// its chunk's bin-ordered staging (kDropped for dropped visibilities)
+constexpr int kPlaceShift = 14;
+constexpr uint32_t kPlaceMask = (1u << kPlaceShift) - 1u;
+static_assert(kL1Chunk <= (1 << kPlaceShift), "chunk positions must fit the placement word");
+static_assert(((uint64_t)kMaxRowBins << kPlaceShift) < 0xFFFFFFFFull,
+              "placement words must stay below kDropped");
 constexpr int kTargetRowBins = 2048;
 
 // Padded tables: row length L = 32 - S holds the S taps of a table row at
@@ -87,14 +95,17 @@ struct Plan {
   int rshift = 0, nbins = 0;    // level-1 sort: row bin = tile row >> rshift
   uint32_t* key = nullptr;      // [nvis] tile id or kDropped (caller order)
   uint2* qrec = nullptr;        // [nvis] packed bins (caller order)
+  uint32_t* chist = nullptr;    // [chunks][nbins] level-1 histogram of each chunk
+  uint32_t* gsum = nullptr;     // [nbins][groups] per-group sums, then their exclusive scan
   uint32_t* rowcount = nullptr; // [nbins + 1] level-1 histogram
   uint32_t* rowoff = nullptr;   // [nbins + 1] its exclusive scan; rowoff[nbins] = kept count
-  uint32_t* rowcursor = nullptr;// [nbins + 1] level-1 placement cursors
-  uint32_t* blkbase = nullptr;  // [level-1 blocks][nbins] start of each block's run per row bin
+  uint32_t* delta = nullptr;    // [chunks][nbins] row-bin position of a chunk's run minus
+                                // the run's start in the chunk's staging
+  uint32_t* ckept = nullptr;    // [chunks] kept visibilities per chunk
   uint32_t* rowpad = nullptr;   // [nbins + 1] tile slots reserved per row bin
   uint32_t* prowoff = nullptr;  // [nbins + 1] exclusive scan of rowpad
   uint2* rrec = nullptr;        // [nvis] records sorted by row bin
-  uint32_t* to_row = nullptr;   // [nvis] caller index -> row-bin position (or kDropped)
+  uint32_t* place = nullptr;    // [nvis] placement word per caller index (or kDropped)
   float2* yrow = nullptr;       // [capacity + 1] row-bin-order W V (grid) or results (degrid);
                                 // yrow[capacity] stays 0 (the padding slots point there)
   int4* krec = nullptr;         // [pcap] per tile slot: padded-table bases (u, v) relative to
@@ -129,17 +140,26 @@ hipError_t launch_tables(const double* c1, int N, double fov, int P, int O, int 
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_zero_c64(float2* p, int64_t n, hipStream_t s);
-// two-level counting sort by tile (rows of tiles, then tiles within a row bin)
+// two-level counting sort by tile (rows of tiles, then tiles within a row bin);
+// chist[chunk][bin] = level-1 histogram of each chunk of kL1Chunk visibilities
 hipError_t launch_quantise_rows(const double* u, const double* v, const double* w, int64_t nvis,
                                 QuantGeom g, int rshift, int nbins, uint32_t* key, uint2* qrec,
+                                uint32_t* chist, hipStream_t s);
+// rowcount[bin] = kept visibilities per row bin (rowcount[nbins] = 0); gsum =
+// [nbins][groups] exclusive scan over the chunk groups of each bin
+hipError_t launch_level1_counts(const uint32_t* chist, int64_t nvis, int nbins, uint32_t* gsum,
                                 uint32_t* rowcount, hipStream_t s);
+// delta[chunk][bin] and ckept[chunk] from the histograms, group scan and rowoff
+hipError_t launch_chunk_deltas(const uint32_t* chist, const uint32_t* gsum,
+                               const uint32_t* rowoff, int64_t nvis, int nbins, uint32_t* delta,
+                               uint32_t* ckept, hipStream_t s);
 // rowpad[b] = slots reserved for row bin b (count + padding room, multiple of 4)
 hipError_t launch_pad_sizes(const uint32_t* rowcount, int nbins, int rshift, int ntx, int nty,
                             uint32_t* rowpad, hipStream_t s);
-// level-1 placement; blkbase[block][bin] = start of the block's run in the row-bin array
+// level-1 placement: records in row-bin order, placement word per visibility
 hipError_t launch_row_scatter(const uint32_t* key, const uint2* qrec, int64_t nvis, int ntx,
-                              int rshift, int nbins, uint32_t* rowcursor, uint32_t* blkbase,
-                              uint2* rrec, uint32_t* to_row, hipStream_t s);
+                              int rshift, int nbins, const uint32_t* chist, const uint32_t* delta,
+                              uint2* rrec, uint32_t* place, hipStream_t s);
 // zero_row: row-bin position the padding slots point to (a W V that stays 0)
 hipError_t launch_row_sort(const uint32_t* rowoff, const uint32_t* prowoff, const uint2* rrec,
                            int rshift, int nbins, int ntx, int nty, int tile_c, int O, int S,
@@ -149,12 +169,12 @@ struct MoveArgs {
   const float2* vis;
   const float* weight;      // may be null (all 1)
   const float2* rot;        // may be null
-  const uint32_t* key;
-  const uint32_t* to_row;
-  const uint32_t* blkbase;
+  const uint32_t* place;
+  const uint32_t* delta;
+  const uint32_t* ckept;
   float2* yrow;
   int64_t nvis;
-  int ntx, rshift, nbins;
+  int nbins;
 };
 hipError_t launch_vis_to_rows(const MoveArgs& a, hipStream_t s);
 // workgroups of the movement pass for nvis visibilities
@@ -163,9 +183,9 @@ int64_t move_blocks(int64_t nvis);
 hipError_t launch_vis_to_rows_batched(const MoveArgs* jobs, const uint32_t* first, int njobs,
                                       int64_t total_blocks, hipStream_t s);
 // row-bin-order results -> caller order, rotation undone (dropped visibilities get 0)
-hipError_t launch_vis_from_rows(const float2* yrow, const float2* rot, const uint32_t* key,
-                                const uint32_t* to_row, const uint32_t* blkbase, int64_t nvis,
-                                int ntx, int rshift, int nbins, float2* out, hipStream_t s);
+hipError_t launch_vis_from_rows(const float2* yrow, const float2* rot, const uint32_t* place,
+                                const uint32_t* delta, const uint32_t* ckept, int64_t nvis,
+                                int nbins, float2* out, hipStream_t s);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t s);
 int64_t scan_tmp_size(int64_t n);
 hipError_t launch_rotation(const double* u, const double* v, const double* w, int64_t nvis,
@@ -176,8 +196,9 @@ hipError_t launch_item_counts(const uint2* tdesc, int ntx, int nty, int r8, int 
                               uint32_t* nit, hipStream_t s);
 hipError_t launch_items(const uint2* tdesc, const uint32_t* itoff, int ntx, int nty, int r8,
                         int item_slots, int4* items, hipStream_t s);
-hipError_t launch_bins_export(const uint2* rrec, const uint32_t* to_row, int64_t nvis, int tile_c,
-                              int ntx, int32_t* out, hipStream_t s);
+hipError_t launch_bins_export(const uint2* rrec, const uint32_t* place, const uint32_t* delta,
+                              int nbins, int64_t nvis, int tile_c, int ntx, int32_t* out,
+                              hipStream_t s);
 
 // Arguments shared by the gridding and degridding kernels.  Work item it =
 // items[it] = (tile row, first slot, end slot, tile column of the first slot);
