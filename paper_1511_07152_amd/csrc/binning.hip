@@ -451,7 +451,7 @@ __global__ __launch_bounds__(kL1Threads) void row_scatter_kernel(
   __shared__ uint32_t wsum[kL1Threads / 64];
   __shared__ uint2 stage[kChunk];
   __shared__ uint16_t binof[kChunk];   // row bin of each staged record
-  const int64_t chunk = blockIdx.x;
+  const int64_t chunk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t first = chunk * kChunk;
   const int t0 = threadIdx.x * kBinsPer;
   uint32_t v[kBinsPer], sum = 0;
@@ -613,7 +613,7 @@ __device__ inline void to_rows_chunk(const MoveArgs& a, int64_t chunk, MoveLds& 
 
 __global__ __launch_bounds__(kL1Threads) void to_rows_kernel(MoveArgs a) {
   __shared__ MoveLds L;
-  to_rows_chunk(a, blockIdx.x, L);
+  to_rows_chunk(a, xcd_block(blockIdx.x, gridDim.x), L);
 }
 
 // Many jobs in one launch: block b works on chunk b - first[j] of the job j
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(kL1Threads) void to_rows_kernel(MoveArgs a) {
 __global__ __launch_bounds__(kL1Threads) void to_rows_batched_kernel(
     const MoveArgs* __restrict__ jobs, const uint32_t* __restrict__ first, int njobs) {
   __shared__ MoveLds L;
-  const uint32_t b = blockIdx.x;
+  const uint32_t b = (uint32_t)xcd_block(blockIdx.x, gridDim.x);
   int lo = 0, hi = njobs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -636,7 +636,7 @@ __global__ __launch_bounds__(kL1Threads) void from_rows_kernel(
     const uint32_t* __restrict__ delta, const uint32_t* __restrict__ ckept,
     const float2* __restrict__ rot, int64_t nvis, int nbins, float2* __restrict__ out) {
   __shared__ MoveLds L;
-  const int64_t chunk = blockIdx.x;
+  const int64_t chunk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t first = chunk * kChunk;
   load_deltas(delta, chunk, nbins, L.dl);
   uint32_t pl[kPerThread];

@@ -121,6 +121,16 @@ struct Plan {
   int64_t scan_tmp_len = 0;
 };
 
+// Workgroups of a launch are dispatched to the 8 XCDs in turn (workgroup b on
+// XCD b % 8).  xcd_block(b, nb) renumbers them so that each XCD takes one
+// contiguous range of [0, nb): neighbouring chunks, whose runs in the row-bin
+// array are adjacent, then meet in one L2 and their partial cache lines merge.
+// A bijection of [0, nb) whatever the actual placement.
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t x = b & 7, j = b >> 3, q = nb >> 3, r = nb & 7;
+  return x * q + (x < r ? x : r) + j;
+}
+
 // packed record: x = cell_u | cell_v << 16 ; y = fi_u | fi_v << 8 | plane << 16
 __host__ __device__ inline uint2 pack_rec(int cu, int fu, int cv, int fv, int k) {
   return make_uint2((uint32_t)cu | ((uint32_t)cv << 16),

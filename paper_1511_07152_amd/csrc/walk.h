@@ -63,7 +63,8 @@ struct TileWalk {
 };
 
 // Grid-stride assignment of work items to the waves of a launch: returns this
-// wave's first item and sets the stride between its items.
+// wave's first item and sets the stride between its items.  (Renumbering the
+// workgroups per XCD, as the movement passes do, was measured slower here.)
 __device__ inline int wave_items(int waves_per_block, int* stride) {
   *stride = gridDim.x * waves_per_block;
   return blockIdx.x * waves_per_block + (int)(threadIdx.x >> 6);
