@@ -163,6 +163,7 @@ void destroy_plan(Plan* p) {
   dfree(p->ckept);
   dfree(p->rowpad);
   dfree(p->prowoff);
+  dfree(p->binperm);
   dfree(p->rrec);
   dfree(p->place);
   dfree(p->yrow);
@@ -366,6 +367,7 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
   SEPW_TRY(dalloc(&P->ckept, std::max<int64_t>(nch, 1)));
   SEPW_TRY(dalloc(&P->rowpad, P->nbins + 1));
   SEPW_TRY(dalloc(&P->prowoff, P->nbins + 1));
+  SEPW_TRY(dalloc(&P->binperm, P->nbins));
   SEPW_TRY(dalloc(&P->rrec, capacity));
   SEPW_TRY(dalloc(&P->place, capacity));
   SEPW_TRY(dalloc(&P->yrow, capacity + 1));
@@ -427,8 +429,9 @@ int bin_plan(Plan* P, int64_t nvis, const double* u, const double* v, const doub
                                 P->delta, P->rrec, P->place, s));
     // padding slots point at yrow[capacity], which nothing writes: keep it 0
     SEPW_TRY(launch_zero_c64(P->yrow + P->capacity, 1, s));
-    SEPW_TRY(launch_row_sort(P->rowoff, P->prowoff, P->rrec, P->rshift, P->nbins, P->ntx, P->nty,
-                             P->tile_c, K->O, K->S, (uint32_t)P->capacity, P->tdesc, P->krec, s));
+    SEPW_TRY(launch_row_sort(P->rowcount, P->rowoff, P->prowoff, P->rrec, P->rshift, P->nbins,
+                             P->ntx, P->nty, P->tile_c, K->O, K->S, (uint32_t)P->capacity,
+                             P->binperm, P->tdesc, P->krec, s));
     SEPW_TRY(build_items(P, s));
     if (K->facet) SEPW_TRY(launch_rotation(u, v, w, nvis, g, P->rot, s));
   }

@@ -492,6 +492,42 @@ __global__ __launch_bounds__(kL1Threads) void row_scatter_kernel(
 
 constexpr int kSortThreads = 1024;
 
+// perm = the row bins by decreasing count (one workgroup, bitonic sort in LDS),
+// so that the level-2 workgroups start with the largest bins and the small
+// ones fill in at the end.
+__global__ __launch_bounds__(kSortThreads) void bin_order_kernel(const uint32_t* __restrict__ rowcount,
+                                                                 int nbins, uint32_t* __restrict__ perm) {
+  __shared__ uint32_t key[kMaxRowBins];
+  __shared__ uint16_t val[kMaxRowBins];
+  int n = 1;
+  while (n < nbins) n <<= 1;
+  for (int i = threadIdx.x; i < n; i += kSortThreads) {
+    key[i] = i < nbins ? rowcount[i] + 1u : 0u;   // padding sorts last
+    val[i] = (uint16_t)i;
+  }
+  __syncthreads();
+  for (int k = 2; k <= n; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n; i += kSortThreads) {
+        const int p = i ^ j;
+        if (p > i) {
+          const bool desc = (i & k) == 0;
+          const uint32_t a = key[i], b = key[p];
+          if (desc ? a < b : a > b) {
+            key[i] = b;
+            key[p] = a;
+            const uint16_t t = val[i];
+            val[i] = val[p];
+            val[p] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < nbins; i += kSortThreads) perm[i] = val[i];
+}
+
 // Level 2: one workgroup per row bin.  Tiles are laid out row-major inside the
 // bin's reserved slot range, each padded to a multiple of 4 slots, and
 // described by tdesc[tile] = (first slot, first slot + count).  A slot holds
@@ -500,12 +536,13 @@ constexpr int kSortThreads = 1024;
 // 0 and point at zero_row, whose W V stays 0.
 __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
     const uint32_t* __restrict__ rowoff, const uint32_t* __restrict__ prowoff,
-    const uint2* __restrict__ rrec, int rshift, int ntx, int nty, int tile_c, int O, int S,
-    uint32_t zero_row, uint2* __restrict__ tdesc, int4* __restrict__ krec) {
+    const uint2* __restrict__ rrec, const uint32_t* __restrict__ perm, int rshift, int ntx,
+    int nty, int tile_c, int O, int S, uint32_t zero_row, uint2* __restrict__ tdesc,
+    SlotRec* __restrict__ krec) {
   const int L = padded_len(S);
   __shared__ uint32_t cnt[kMaxRowTiles];
   __shared__ uint32_t wsum[kSortThreads / 64];
-  const int b = blockIdx.x;
+  const int b = (int)perm[blockIdx.x];
   const int row0 = b << rshift;
   const int row1 = min((b + 1) << rshift, nty);
   const int64_t tile0 = (int64_t)row0 * ntx;
@@ -539,7 +576,7 @@ __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
     const uint32_t c = cnt[t];
     const uint32_t p = pbase + run;
     tdesc[tile0 + t] = make_uint2(p, p + c);
-    for (uint32_t j = c; j < round4(c); ++j) krec[p + j] = make_int4(0, 0, (int)zero_row, 0);
+    for (uint32_t j = c; j < round4(c); ++j) krec[p + j] = SlotRec{0, 0, (int)zero_row};
     cnt[t] = run;
     run += round4(c);
   }
@@ -552,7 +589,7 @@ __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
     const int k = (int)(r.y >> 16);
     const int ox = cu - (cu / tile_c) * tile_c, oy = cv - (cv / tile_c) * tile_c;
     const int row_u = k * O + (int)(r.y & 0xFFu), row_v = k * O + (int)((r.y >> 8) & 0xFFu);
-    krec[pos] = make_int4(row_u * L + tile_c - 1 - ox, row_v * L + tile_c - 1 - oy, (int)e, 0);
+    krec[pos] = SlotRec{row_u * L + tile_c - 1 - ox, row_v * L + tile_c - 1 - oy, (int)e};
   }
 }
 
@@ -744,11 +781,13 @@ hipError_t launch_row_scatter(const uint32_t* key, const uint2* qrec, int64_t nv
   return hipGetLastError();
 }
 
-hipError_t launch_row_sort(const uint32_t* rowoff, const uint32_t* prowoff, const uint2* rrec,
-                           int rshift, int nbins, int ntx, int nty, int tile_c, int O, int S,
-                           uint32_t zero_row, uint2* tdesc, int4* krec, hipStream_t s) {
+hipError_t launch_row_sort(const uint32_t* rowcount, const uint32_t* rowoff,
+                           const uint32_t* prowoff, const uint2* rrec, int rshift, int nbins,
+                           int ntx, int nty, int tile_c, int O, int S, uint32_t zero_row,
+                           uint32_t* perm, uint2* tdesc, SlotRec* krec, hipStream_t s) {
+  hipLaunchKernelGGL(bin_order_kernel, dim3(1), dim3(kSortThreads), 0, s, rowcount, nbins, perm);
   hipLaunchKernelGGL(row_sort_kernel, dim3(nbins), dim3(kSortThreads), 0, s, rowoff, prowoff, rrec,
-                     rshift, ntx, nty, tile_c, O, S, zero_row, tdesc, krec);
+                     perm, rshift, ntx, nty, tile_c, O, S, zero_row, tdesc, krec);
   return hipGetLastError();
 }
 

@@ -70,7 +70,7 @@ __device__ inline void region_fix(int tx, int gy, int grp, int N, int checker, f
 
 // Operands of one chunk of 16 slots as one lane sees them.
 struct ChunkBuf {
-  int4 k;          // record of the lane's slot (column of Z), two chunks ahead
+  SlotRec k;       // record of the lane's slot (column of Z), two chunks ahead
   float2 tu[4];    // u-table taps x = 4 grp + q of the lane's visibility
   float2 tv[4];    // v-table taps y = 4 grp + rr
   float2 reg[4];   // grid region R[y = col][x = 4 grp + q] of the chunk's tile
@@ -102,7 +102,7 @@ __device__ __forceinline__ bool degrid_step(const DegridCtx& c, TileWalk& tw, Ch
                                             ChunkPos& n1, ChunkPos& n2, ChunkBuf& X,
                                             ChunkBuf& Y) {
   const DegridArgs& a = *c.a;
-  const int4 kx = X.k;   // this chunk's record (row-bin position of the result)
+  const SlotRec kx = X.k;   // this chunk's record (row-bin position of the result)
   X.k = a.krec[min(n2.c0 + c.col, n2.pe - 1)];
   fetch_taps(c, Y);
   if (X.fresh) region_fix<S>(cur.tx, c.gy, c.grp, a.N, a.checker, X.reg);

@@ -99,7 +99,7 @@ struct GridState {
 };
 
 struct GridCtx {
-  const int4* krec;
+  const SlotRec* krec;
   const float2* yrow;
   float* grid;
   float* ring;                  // this wave's LDS ring
@@ -137,7 +137,7 @@ __device__ inline float bperm(int addr, float v) {
 
 // Operands of group j (slots s0 + 4 j ..): the record of slot 4 (j % 16) + grp
 // of the batch (R, Y), moved to this lane, then its table taps.
-__device__ __forceinline__ void fetch_group(const GridCtx& c, const int4& R, const float2& Y,
+__device__ __forceinline__ void fetch_group(const GridCtx& c, const SlotRec& R, const float2& Y,
                                             int j, GroupOps& o) {
   const int src = c.grp4 + ((j & 15) << 4);
   const int kx = __builtin_amdgcn_ds_bpermute(src, R.x);
@@ -152,7 +152,7 @@ __device__ __forceinline__ void fetch_group(const GridCtx& c, const int4& R, con
 // The fetch is unconditional (past the item's end it reads harmless repeats of
 // valid records), so that every path leaves the same loads in flight.
 template <int S>
-__device__ __forceinline__ void grid_step(const GridCtx& c, int g, const int4& R, const float2& Y,
+__device__ __forceinline__ void grid_step(const GridCtx& c, int g, const SlotRec& R, const float2& Y,
                                           TileWalk& tw, GridState& st, GroupOps& buf) {
   constexpr int C = kRegion + 1 - S;
   constexpr int H = S / 2;
@@ -225,9 +225,9 @@ __device__ __forceinline__ void grid_item(const GridArgs& a, float* ring, int it
   st.p3 = st.p1;
 
   // records of batches 0..2 and W V of batches 0 and 1, one slot per lane
-  int4 r0 = c.krec[min(c.s0 + lane, c.last)];
-  int4 r1 = c.krec[min(c.s0 + 64 + lane, c.last)];
-  int4 r2 = c.krec[min(c.s0 + 128 + lane, c.last)];
+  SlotRec r0 = c.krec[min(c.s0 + lane, c.last)];
+  SlotRec r1 = c.krec[min(c.s0 + 64 + lane, c.last)];
+  SlotRec r2 = c.krec[min(c.s0 + 128 + lane, c.last)];
   float2 y0 = c.yrow[r0.z];
   float2 y1 = c.yrow[r1.z];
   GroupOps A, B;   // groups of even / odd index

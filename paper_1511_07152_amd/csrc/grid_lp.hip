@@ -117,14 +117,14 @@ __device__ inline ChunkPos first_chunk(const TileWalk& tw, int c0, int s_end) {
 
 // Operands of one chunk for lane group grp: slots c0 + 4 grp + m.
 struct GridBuf {
-  int4 k[4];       // slot records, two chunks ahead
+  SlotRec k[4];    // slot records, two chunks ahead
   float2 y[4];     // W V
   uint32_t tv[4];  // 16-bit v-table taps (re | im << 16) of the lane's row
   float2 tu[4];    // FP32 u-table taps of the lane's column
 };
 
 struct LpCtx {
-  const int4* krec;
+  const SlotRec* krec;
   const float2* yrow;
   int s_end, lane, col, grp;
 };
@@ -278,7 +278,7 @@ __device__ inline void load_region_lp(const float2* __restrict__ grid, int N, in
 }
 
 struct DegridBuf {
-  int4 k;          // record of the lane's slot, two chunks ahead
+  SlotRec k;       // record of the lane's slot, two chunks ahead
   uint32_t tu[4];  // 16-bit u-table taps x = 4 grp + m
   float2 tv[4];    // FP32 v-table taps y = 4 grp + m (times s_k^u)
   float2 reg[4];   // raw grid region of the chunk's tile
@@ -295,7 +295,7 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, int it, in
   const int N = a.N, checker = a.checker;
   const uint32_t* __restrict__ lp_u = a.lp_u + 4 * grp;      // taps x = 4 grp + m
   const float2* __restrict__ pad_vs = a.pad_vs + 4 * grp;    // taps y = 4 grp + m
-  const int4* __restrict__ krec = a.krec;
+  const SlotRec* __restrict__ krec = a.krec;
   const int4 item = a.items[it];
   const int ty = uniform(item.x), s_end = uniform(item.z);
   const int gy = ty * C - H + col;
@@ -318,7 +318,7 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, int it, in
   // One pipeline step: chunk cur from X while the record of n2 goes into X.k
   // and the taps (and on a tile change the region) of n1 into Y.
   auto step = [&](DegridBuf& X, DegridBuf& Y) -> bool {
-    const int4 kc = X.k;
+    const SlotRec kc = X.k;
     X.k = krec[min(n2.c0 + col, n2.pe - 1)];
     taps(Y);
     if (X.fresh) {

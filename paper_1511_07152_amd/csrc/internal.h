@@ -82,6 +82,13 @@ struct Kernels {
   uint64_t generation = 0;     // bumped when the tables are regenerated
 };
 
+// Tile slot record: padded-table bases of the visibility's u and v taps (tap
+// of region column x at base + x) and the row-bin position of its W V.  Twelve
+// bytes, loaded as three dwords.
+struct SlotRec {
+  int x, y, z;
+};
+
 struct Plan {
   Kernels* K = nullptr;
   uint64_t generation = 0;      // K->generation the bins were made for
@@ -104,11 +111,12 @@ struct Plan {
   uint32_t* ckept = nullptr;    // [chunks] kept visibilities per chunk
   uint32_t* rowpad = nullptr;   // [nbins + 1] tile slots reserved per row bin
   uint32_t* prowoff = nullptr;  // [nbins + 1] exclusive scan of rowpad
+  uint32_t* binperm = nullptr;  // [nbins] row bins by decreasing count (level-2 order)
   uint2* rrec = nullptr;        // [nvis] records sorted by row bin
   uint32_t* place = nullptr;    // [nvis] placement word per caller index (or kDropped)
   float2* yrow = nullptr;       // [capacity + 1] row-bin-order W V (grid) or results (degrid);
                                 // yrow[capacity] stays 0 (the padding slots point there)
-  int4* krec = nullptr;         // [pcap] per tile slot: padded-table bases (u, v) relative to
+  SlotRec* krec = nullptr;         // [pcap] per tile slot: padded-table bases (u, v) relative to
                                 // the tile and the row-bin position of its W V
   uint2* tdesc = nullptr;       // [ntiles] (first slot, first slot + count) per tile
   float2* rot = nullptr;        // [nvis] facet phase rotation, caller order
@@ -170,10 +178,12 @@ hipError_t launch_pad_sizes(const uint32_t* rowcount, int nbins, int rshift, int
 hipError_t launch_row_scatter(const uint32_t* key, const uint2* qrec, int64_t nvis, int ntx,
                               int rshift, int nbins, const uint32_t* chist, const uint32_t* delta,
                               uint2* rrec, uint32_t* place, hipStream_t s);
-// zero_row: row-bin position the padding slots point to (a W V that stays 0)
-hipError_t launch_row_sort(const uint32_t* rowoff, const uint32_t* prowoff, const uint2* rrec,
-                           int rshift, int nbins, int ntx, int nty, int tile_c, int O, int S,
-                           uint32_t zero_row, uint2* tdesc, int4* krec, hipStream_t s);
+// zero_row: row-bin position the padding slots point to (a W V that stays 0);
+// perm: [nbins] scratch for the order in which the row bins are sorted
+hipError_t launch_row_sort(const uint32_t* rowcount, const uint32_t* rowoff,
+                           const uint32_t* prowoff, const uint2* rrec, int rshift, int nbins,
+                           int ntx, int nty, int tile_c, int O, int S, uint32_t zero_row,
+                           uint32_t* perm, uint2* tdesc, SlotRec* krec, hipStream_t s);
 // caller-order W V (times the facet rotation) -> row-bin order
 struct MoveArgs {
   const float2* vis;
@@ -221,7 +231,7 @@ struct GridArgs {
   int r8;
   uint32_t* qctr;           // list counters, zero at launch
   const uint2* tdesc;       // per tile (first slot, first slot + count)
-  const int4* krec;         // per slot (u base, v base, row-bin position, 0)
+  const SlotRec* krec;      // per slot (u base, v base, row-bin position)
   const float2* yrow;       // W V in row-bin order
   const float2* tab_u;      // padded tables
   const float2* tab_v;
@@ -238,7 +248,7 @@ struct DegridArgs {
   int r8;
   uint32_t* qctr;           // list counters, zero at launch
   const uint2* tdesc;
-  const int4* krec;
+  const SlotRec* krec;
   const float2* grid;
   const float2* tab_u;      // padded tables
   const float2* tab_v;
@@ -255,7 +265,7 @@ struct GridArgsLp {
   int r8;
   uint32_t* qctr;           // list counters, zero at launch
   const uint2* tdesc;
-  const int4* krec;
+  const SlotRec* krec;
   const float2* yrow;
   const float2* pad_us;     // FP32 padded u-table times s_k^v (row product in FP32)
   const uint32_t* lp_v;     // 16-bit padded v-table / s_k^v, packed (re | im << 16)
@@ -272,7 +282,7 @@ struct DegridArgsLp {
   int r8;
   uint32_t* qctr;           // list counters, zero at launch
   const uint2* tdesc;
-  const int4* krec;
+  const SlotRec* krec;
   const float2* grid;
   const uint32_t* lp_u;     // 16-bit padded u-table / s_k^u
   const float2* pad_vs;     // FP32 padded v-table times s_k^u (epilogue)
