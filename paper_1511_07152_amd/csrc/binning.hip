@@ -27,6 +27,8 @@
 // with zero-weight padding, and tdesc[tile] = (first slot, first slot + count).
 // Membership of a visibility in its tile is exact; the order inside a tile is
 // not specified.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace sepw {
@@ -534,62 +536,138 @@ __global__ __launch_bounds__(kSortThreads) void bin_order_kernel(const uint32_t*
 // the padded-table bases of its visibility and the visibility's row-bin
 // position (where the data movement keeps W V); padding slots have table base
 // 0 and point at zero_row, whose W V stays 0.
+// The bin's tile histogram is built in LDS (eight record loads in flight per
+// thread), scanned into tile starts, and the records are then placed in
+// chunks: a counting sort of each chunk in LDS orders it by destination, so
+// that each tile's share of the chunk is written as one contiguous run.
+// Dynamic LDS: cursor and chunk count per tile (2 nloc words), then the
+// chunk's staged records and their destinations (16 bytes per record).
+constexpr int kSortLoads = 8;
+
+__device__ inline int local_tile(uint2 r, int tile_c, int row0, int ntx) {
+  const int cu = (int)(r.x & 0xFFFFu), cv = (int)(r.x >> 16);
+  return (cv / tile_c - row0) * ntx + cu / tile_c;
+}
+
+// Exclusive scan of a[0, n) in place (each thread owns a run of consecutive
+// entries, f applied to each entry first); returns the total.
+template <class F>
+__device__ inline uint32_t block_scan_tiles(uint32_t* a, int n, uint32_t* wsum, F f) {
+  const int per = (n + kSortThreads - 1) / kSortThreads;
+  const int t0 = threadIdx.x * per, t1 = min(t0 + per, n);
+  uint32_t sum = 0;
+  for (int t = t0; t < t1; ++t) sum += f(a[t]);
+  uint32_t total;
+  uint32_t run = block_scan_owned(sum, wsum, &total);
+  for (int t = t0; t < t1; ++t) {
+    const uint32_t v = f(a[t]);
+    a[t] = run;
+    run += v;
+  }
+  return total;
+}
+
 __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
     const uint32_t* __restrict__ rowoff, const uint32_t* __restrict__ prowoff,
     const uint2* __restrict__ rrec, const uint32_t* __restrict__ perm, int rshift, int ntx,
-    int nty, int tile_c, int O, int S, uint32_t zero_row, uint2* __restrict__ tdesc,
+    int nty, int tile_c, int O, int S, uint32_t zero_row, int chunk, uint2* __restrict__ tdesc,
     SlotRec* __restrict__ krec) {
-  const int L = padded_len(S);
-  __shared__ uint32_t cnt[kMaxRowTiles];
+  extern __shared__ uint32_t lds[];
   __shared__ uint32_t wsum[kSortThreads / 64];
+  const int L = padded_len(S);
   const int b = (int)perm[blockIdx.x];
   const int row0 = b << rshift;
   const int row1 = min((b + 1) << rshift, nty);
   const int64_t tile0 = (int64_t)row0 * ntx;
   const int nloc = (row1 - row0) * ntx;
+  uint32_t* cnt = lds;                 // tile counts, then the next free slot of each tile
+  uint32_t* lc = lds + nloc;           // the chunk's count, then start, per tile
+  SlotRec* stage = reinterpret_cast<SlotRec*>(lds + 2 * nloc);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(stage + chunk);
   const uint32_t s0 = rowoff[b], s1 = rowoff[b + 1];
   const uint32_t pbase = prowoff[b];
-  for (int t = threadIdx.x; t < nloc; t += kSortThreads) cnt[t] = 0u;
-  __syncthreads();
-  for (uint32_t e = s0 + threadIdx.x; e < s1; e += kSortThreads) {
-    const uint2 r = rrec[e];
-    const int cu = (int)(r.x & 0xFFFFu), cv = (int)(r.x >> 16);
-    atomicAdd(&cnt[(cv / tile_c - row0) * ntx + cu / tile_c], 1u);
+  for (int t = threadIdx.x; t < nloc; t += kSortThreads) {
+    cnt[t] = 0u;
+    lc[t] = 0u;
   }
   __syncthreads();
-  // exclusive scan of the padded counts: each thread owns a run of consecutive tiles
-  const int per = (nloc + kSortThreads - 1) / kSortThreads;
-  const int t0 = threadIdx.x * per;
-  uint32_t sum = 0;
-  for (int t = t0; t < min(t0 + per, nloc); ++t) sum += round4(cnt[t]);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t x = sum;
-  for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) wsum[wave] = x;
-  __syncthreads();
-  uint32_t run = x - sum;
-  for (int i = 0; i < wave; ++i) run += wsum[i];
-  for (int t = t0; t < min(t0 + per, nloc); ++t) {
-    const uint32_t c = cnt[t];
-    const uint32_t p = pbase + run;
-    tdesc[tile0 + t] = make_uint2(p, p + c);
-    for (uint32_t j = c; j < round4(c); ++j) krec[p + j] = SlotRec{0, 0, (int)zero_row};
-    cnt[t] = run;
-    run += round4(c);
+  for (uint32_t e0 = s0; e0 < s1; e0 += kSortLoads * kSortThreads) {
+    uint2 r[kSortLoads];
+#pragma unroll
+    for (int j = 0; j < kSortLoads; ++j) {
+      const uint32_t e = e0 + j * kSortThreads + threadIdx.x;
+      r[j] = e < s1 ? rrec[e] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int j = 0; j < kSortLoads; ++j)
+      if (e0 + j * kSortThreads + threadIdx.x < s1)
+        atomicAdd(&cnt[local_tile(r[j], tile_c, row0, ntx)], 1u);
   }
   __syncthreads();
-  for (uint32_t e = s0 + threadIdx.x; e < s1; e += kSortThreads) {
-    const uint2 r = rrec[e];
-    const int cu = (int)(r.x & 0xFFFFu), cv = (int)(r.x >> 16);
-    const uint32_t pos = pbase + atomicAdd(&cnt[(cv / tile_c - row0) * ntx + cu / tile_c], 1u);
-    // padded-table bases: tap of region column x is at base + x
-    const int k = (int)(r.y >> 16);
-    const int ox = cu - (cu / tile_c) * tile_c, oy = cv - (cv / tile_c) * tile_c;
-    const int row_u = k * O + (int)(r.y & 0xFFu), row_v = k * O + (int)((r.y >> 8) & 0xFFu);
-    krec[pos] = SlotRec{row_u * L + tile_c - 1 - ox, row_v * L + tile_c - 1 - oy, (int)e};
+  // tile starts (padded counts scanned), descriptors and padding records
+  {
+    const int per = (nloc + kSortThreads - 1) / kSortThreads;
+    const int t0 = threadIdx.x * per, t1 = min(t0 + per, nloc);
+    uint32_t sum = 0;
+    for (int t = t0; t < t1; ++t) sum += round4(cnt[t]);
+    uint32_t total;
+    uint32_t run = block_scan_owned(sum, wsum, &total);
+    for (int t = t0; t < t1; ++t) {
+      const uint32_t c = cnt[t];
+      const uint32_t p = pbase + run;
+      tdesc[tile0 + t] = make_uint2(p, p + c);
+      for (uint32_t j = c; j < round4(c); ++j) krec[p + j] = SlotRec{0, 0, (int)zero_row};
+      cnt[t] = p;
+      run += round4(c);
+    }
+  }
+  __syncthreads();
+  constexpr int kMaxPer = 4;   // records per thread and chunk (chunk <= 4096)
+  for (uint32_t c0 = s0; c0 < s1; c0 += chunk) {
+    const int n = (int)min((uint32_t)chunk, s1 - c0);
+    uint2 r[kMaxPer];
+    int tl[kMaxPer];
+    uint32_t rk[kMaxPer];
+#pragma unroll
+    for (int j = 0; j < kMaxPer; ++j) {
+      const int k = j * kSortThreads + threadIdx.x;
+      r[j] = k < n ? rrec[c0 + k] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxPer; ++j) {
+      if (j * kSortThreads + (int)threadIdx.x < n) {
+        tl[j] = local_tile(r[j], tile_c, row0, ntx);
+        rk[j] = atomicAdd(&lc[tl[j]], 1u);
+      }
+    }
+    __syncthreads();
+    block_scan_tiles(lc, nloc, wsum, [](uint32_t v) { return v; });
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kMaxPer; ++j) {
+      if (j * kSortThreads + (int)threadIdx.x < n) {
+        const int cu = (int)(r[j].x & 0xFFFFu), cv = (int)(r[j].x >> 16);
+        // padded-table bases: tap of region column x is at base + x
+        const int k = (int)(r[j].y >> 16);
+        const int ox = cu - (cu / tile_c) * tile_c, oy = cv - (cv / tile_c) * tile_c;
+        const int row_u = k * O + (int)(r[j].y & 0xFFu);
+        const int row_v = k * O + (int)((r[j].y >> 8) & 0xFFu);
+        const uint32_t q = lc[tl[j]] + rk[j];
+        stage[q] = SlotRec{row_u * L + tile_c - 1 - ox, row_v * L + tile_c - 1 - oy,
+                           (int)(c0 + j * kSortThreads + threadIdx.x)};
+        dst[q] = cnt[tl[j]] + rk[j];
+      }
+    }
+    __syncthreads();
+    // runs of consecutive staged records go to consecutive slots
+    for (int q = threadIdx.x; q < n; q += kSortThreads) krec[dst[q]] = stage[q];
+    for (int t = threadIdx.x; t < nloc; t += kSortThreads) {
+      const uint32_t next = t + 1 < nloc ? lc[t + 1] : (uint32_t)n;
+      cnt[t] += next - lc[t];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nloc; t += kSortThreads) lc[t] = 0u;
+    __syncthreads();
   }
 }
 
@@ -785,9 +863,19 @@ hipError_t launch_row_sort(const uint32_t* rowcount, const uint32_t* rowoff,
                            const uint32_t* prowoff, const uint2* rrec, int rshift, int nbins,
                            int ntx, int nty, int tile_c, int O, int S, uint32_t zero_row,
                            uint32_t* perm, uint2* tdesc, SlotRec* krec, hipStream_t s) {
+  // chunk length: two workgroups per CU when the tile arrays leave room, else one
+  const int64_t nloc = (int64_t)ntx << rshift;
+  constexpr int64_t kLds = 163840, kStatic = 256;
+  int64_t chunk = (kLds / 2 - kStatic - 8 * nloc) / 16;
+  if (chunk < 1024) chunk = (kLds - kStatic - 8 * nloc) / 16;
+  chunk = std::min<int64_t>(chunk, 4096) & ~63LL;
+  if (chunk < 64) return hipErrorInvalidValue;
+  const int lds = (int)(8 * nloc + 16 * chunk);
   hipLaunchKernelGGL(bin_order_kernel, dim3(1), dim3(kSortThreads), 0, s, rowcount, nbins, perm);
-  hipLaunchKernelGGL(row_sort_kernel, dim3(nbins), dim3(kSortThreads), 0, s, rowoff, prowoff, rrec,
-                     perm, rshift, ntx, nty, tile_c, O, S, zero_row, tdesc, krec);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&row_sort_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  hipLaunchKernelGGL(row_sort_kernel, dim3(nbins), dim3(kSortThreads), lds, s, rowoff, prowoff, rrec,
+                     perm, rshift, ntx, nty, tile_c, O, S, zero_row, (int)chunk, tdesc, krec);
   return hipGetLastError();
 }
 
