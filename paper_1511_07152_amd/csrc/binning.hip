@@ -473,17 +473,27 @@ __global__ __launch_bounds__(kL1Threads) void row_scatter_kernel(
     run += v[j];
   }
   __syncthreads();
-  for (int m = 0; m < kChunk / kL1Threads; ++m) {
+  // all loads of the thread first, then the LDS placement
+  constexpr int kPer = kChunk / kL1Threads;
+  uint32_t kk[kPer];
+  uint2 qr[kPer];
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
+    const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
+    kk[m] = i < nvis ? key[i] : kDropped;
+    qr[m] = i < nvis ? qrec[i] : make_uint2(0u, 0u);
+  }
+#pragma unroll
+  for (int m = 0; m < kPer; ++m) {
     const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
     if (i >= nvis) break;
-    const uint32_t kk = key[i];
-    if (kk == kDropped) {
+    if (kk[m] == kDropped) {
       place[i] = kDropped;
       continue;
     }
-    const uint32_t b = (kk / (uint32_t)ntx) >> rshift;
+    const uint32_t b = (kk[m] / (uint32_t)ntx) >> rshift;
     const uint32_t idx = atomicAdd(&cur[b], 1u);
-    stage[idx] = qrec[i];
+    stage[idx] = qr[m];
     binof[idx] = (uint16_t)b;
     place[i] = (b << kPlaceShift) | idx;
   }

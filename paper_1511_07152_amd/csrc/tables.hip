@@ -81,17 +81,25 @@ __global__ __launch_bounds__(kTabThreads) void table_kernel(
     sincospi(-2.0 * frac, &sp, &cp);
     const double are = c1[p] * cp, aim = c1[p] * sp;
     const int64_t dp = p - N / 2;
+    // Twiddle of tap s: exp(-2 pi i m_s / (O N)) with m_s = (O (s - h) - f) dp.
+    // Consecutive taps differ by the factor exp(-2 pi i dp / N), so only the
+    // first twiddle and that ratio are evaluated (integer arguments reduced
+    // exactly), the others by complex multiplication in FP64.
+    int64_t r0 = (((int64_t)O * (-h) - f) * dp) % period;
+    if (r0 < 0) r0 += period;
+    int64_t q = dp % N;
+    if (q < 0) q += N;
+    double te, tc, rs, rc;
+    sincospi(-2.0 * (double)r0 / (double)period, &te, &tc);
+    sincospi(-2.0 * (double)q / (double)N, &rs, &rc);
 #pragma unroll
     for (int s = 0; s < kMaxSupport; ++s) {
       if (s < S) {
-        // Delta (p - N/2) / N = m / (O N) with the integer m below; reduce mod O N exactly
-        int64_t m = ((int64_t)O * (s - h) - f) * dp;
-        int64_t r = m % period;
-        if (r < 0) r += period;
-        double se, ce;
-        sincospi(-2.0 * (double)r / (double)period, &se, &ce);
-        acc_re[s] += are * ce - aim * se;
-        acc_im[s] += are * se + aim * ce;
+        acc_re[s] += are * tc - aim * te;
+        acc_im[s] += are * te + aim * tc;
+        const double nc = tc * rc - te * rs;
+        te = tc * rs + te * rc;
+        tc = nc;
       }
     }
   }
