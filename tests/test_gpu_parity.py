@@ -293,3 +293,38 @@ def test_large_tables_cache_path(lib):
     X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
     V = lib.degrid(plan, dev(X, torch.complex64), flags=lib.GRID_ONLY).cpu().numpy()
     assert rel_rms(V, o.degrid_grid(X)) <= 1e-5
+
+
+# ------------------------------------------------------------------ grid edges
+@pytest.mark.parametrize("N,S", [(64, 15), (40, 7), (18, 3)])
+def test_grid_and_degrid_at_grid_corners(lib, N, S):
+    # Footprints at all four grid edges and corners: the 16-cell regions of the
+    # edge tiles reach past the grid, and at the first and last cells of the
+    # grid the degridding region loads are moved inside the grid and
+    # re-indexed.  Cells j = h .. N-1-h are the extreme ones whose footprint
+    # stays inside (h = S // 2); sub-cell offsets within +-0.4 keep the cell.
+    rng = np.random.default_rng(29 + N)
+    fov, O, P = math.radians(2.0), 8, 4
+    h = S // 2
+    lo, hi = h, N - 1 - h
+    corners = np.array([(a, b) for a in (lo, hi) for b in (lo, hi)] * 30)
+    edges = np.array([(a, b) for a in (lo, hi) for b in rng.integers(lo, hi + 1, 20)] +
+                     [(b, a) for a in (lo, hi) for b in rng.integers(lo, hi + 1, 20)])
+    inner_ = rng.integers(lo, hi + 1, (300, 2))
+    cells = np.concatenate([corners, edges, inner_]).astype(float)
+    n = len(cells)
+    u = (cells[:, 0] - N // 2 + rng.uniform(-0.4, 0.4, n)) / fov
+    v = (cells[:, 1] - N // 2 + rng.uniform(-0.4, 0.4, n)) / fov
+    d = dict(u=u, v=v, w=rng.uniform(-100, 100, n),
+             V=rng.standard_normal(n) + 1j * rng.standard_normal(n), W=rng.uniform(0.5, 2.0, n),
+             N=N, fov=fov, S=S, O=O, P=P, w_lo=-100.0, w_hi=100.0)
+    K, plan = _make(lib, d)
+    o = _oracle(d, plan)
+    assert np.array_equal(plan.bins().cpu().numpy().astype(np.int64), o.bins_array())
+    assert not o.bins_array()[:, 6].any()   # every footprint inside the grid
+    G = lib.grid(plan, dev(d["V"], torch.complex64), dev(d["W"], torch.float32),
+                 flags=lib.GRID_ONLY).cpu().numpy()
+    assert rel_rms(G, o.grid(d["V"], d["W"])) <= 1e-5
+    X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    V = lib.degrid(plan, dev(X, torch.complex64), flags=lib.GRID_ONLY).cpu().numpy()
+    assert rel_rms(V, o.degrid_grid(X)) <= 1e-5
