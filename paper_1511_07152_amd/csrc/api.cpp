@@ -153,7 +153,7 @@ void destroy_kernels(Kernels* k) {
 
 void destroy_plan(Plan* p) {
   if (!p) return;
-  dfree(p->key);
+  dfree(p->rbin);
   dfree(p->qrec);
   dfree(p->rowcount);
   dfree(p->rowoff);
@@ -355,7 +355,7 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
   P->max_items = P->nty + P->pcap / P->item_slots + 1;
   P->r8 = (P->nty + 7) / 8;
   P->scan_tmp_len = scan_tmp_size(std::max<int64_t>(P->nbins, 8 * (int64_t)P->r8) + 1);
-  SEPW_TRY(dalloc(&P->key, capacity));
+  SEPW_TRY(dalloc(&P->rbin, capacity));
   SEPW_TRY(dalloc(&P->qrec, capacity));
   SEPW_TRY(dalloc(&P->rowcount, P->nbins + 1));
   SEPW_TRY(dalloc(&P->rowoff, P->nbins + 1));
@@ -414,7 +414,7 @@ int bin_plan(Plan* P, int64_t nvis, const double* u, const double* v, const doub
   P->generation = K->generation;
   {
     Stage st(SEPW_STAGE_QUANTISE, s);
-    SEPW_TRY(launch_quantise_rows(u, v, w, nvis, g, P->rshift, P->nbins, P->key, P->qrec,
+    SEPW_TRY(launch_quantise_rows(u, v, w, nvis, g, P->rshift, P->nbins, P->rbin, P->qrec,
                                   P->chist, s));
   }
   {
@@ -425,8 +425,8 @@ int bin_plan(Plan* P, int64_t nvis, const double* u, const double* v, const doub
                                  s));
     SEPW_TRY(launch_pad_sizes(P->rowcount, P->nbins, P->rshift, P->ntx, P->nty, P->rowpad, s));
     SEPW_TRY(launch_scan(P->rowpad, P->prowoff, P->nbins + 1, P->scan_tmp, s));
-    SEPW_TRY(launch_row_scatter(P->key, P->qrec, nvis, P->ntx, P->rshift, P->nbins, P->chist,
-                                P->delta, P->rrec, P->place, s));
+    SEPW_TRY(launch_row_scatter(P->rbin, P->qrec, nvis, P->nbins, P->chist, P->delta, P->rrec,
+                                P->place, s));
     // padding slots point at yrow[capacity], which nothing writes: keep it 0
     SEPW_TRY(launch_zero_c64(P->yrow + P->capacity, 1, s));
     SEPW_TRY(launch_row_sort(P->rowcount, P->rowoff, P->prowoff, P->rrec, P->rshift, P->nbins,

@@ -295,7 +295,7 @@ __device__ inline uint32_t block_scan_owned(uint32_t sum, uint32_t* wsum, uint32
 
 __global__ __launch_bounds__(kL1Threads) void quantise_rows_kernel(
     const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
-    int64_t nvis, QuantGeom g, int rshift, int nbins, uint32_t* __restrict__ key,
+    int64_t nvis, QuantGeom g, int rshift, int nbins, uint32_t* __restrict__ rbin,
     uint2* __restrict__ qrec, uint32_t* __restrict__ chist) {
   __shared__ uint32_t hist[kMaxRowBins];
   for (int b = threadIdx.x; b < nbins; b += kL1Threads) hist[b] = 0u;
@@ -320,11 +320,11 @@ __global__ __launch_bounds__(kL1Threads) void quantise_rows_kernel(
     if (on) {
       int cu = (int)bu.cell, cv = (int)bv.cell;
       const uint32_t ty = (uint32_t)(cv / g.tile_c);
-      key[i] = ty * (uint32_t)g.ntx + (uint32_t)(cu / g.tile_c);
+      rbin[i] = ty >> rshift;
       qrec[i] = pack_rec(cu, bu.fi, cv, bv.fi, k);
       atomicAdd(&hist[ty >> rshift], 1u);
     } else {
-      key[i] = kDropped;
+      rbin[i] = kDropped;
       qrec[i] = make_uint2(0u, 0u);
     }
   }
@@ -445,8 +445,8 @@ __global__ void pad_sizes_kernel(const uint32_t* __restrict__ rowcount, int nbin
 // bin order (LDS atomics), each gets its placement word, and each run is copied
 // to the row-bin array as one contiguous piece (delta gives its position).
 __global__ __launch_bounds__(kL1Threads) void row_scatter_kernel(
-    const uint32_t* __restrict__ key, const uint2* __restrict__ qrec, int64_t nvis, int ntx,
-    int rshift, int nbins, const uint32_t* __restrict__ chist, const uint32_t* __restrict__ delta,
+    const uint32_t* __restrict__ rbin, const uint2* __restrict__ qrec, int64_t nvis, int nbins,
+    const uint32_t* __restrict__ chist, const uint32_t* __restrict__ delta,
     uint2* __restrict__ rrec, uint32_t* __restrict__ place) {
   __shared__ uint32_t cur[kMaxRowBins];   // placement cursors in the staging
   __shared__ uint32_t dl[kMaxRowBins];    // the chunk's row of delta
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(kL1Threads) void row_scatter_kernel(
 #pragma unroll
   for (int m = 0; m < kPer; ++m) {
     const int64_t i = first + (int64_t)m * kL1Threads + threadIdx.x;
-    kk[m] = i < nvis ? key[i] : kDropped;
+    kk[m] = i < nvis ? rbin[i] : kDropped;
     qr[m] = i < nvis ? qrec[i] : make_uint2(0u, 0u);
   }
 #pragma unroll
@@ -491,7 +491,7 @@ __global__ __launch_bounds__(kL1Threads) void row_scatter_kernel(
       place[i] = kDropped;
       continue;
     }
-    const uint32_t b = (kk[m] / (uint32_t)ntx) >> rshift;
+    const uint32_t b = kk[m];
     const uint32_t idx = atomicAdd(&cur[b], 1u);
     stage[idx] = qr[m];
     binof[idx] = (uint16_t)b;
@@ -554,9 +554,10 @@ __global__ __launch_bounds__(kSortThreads) void bin_order_kernel(const uint32_t*
 // chunk's staged records and their destinations (16 bytes per record).
 constexpr int kSortLoads = 8;
 
-__device__ inline int local_tile(uint2 r, int tile_c, int row0, int ntx) {
+template <int C>
+__device__ inline int local_tile(uint2 r, int row0, int ntx) {
   const int cu = (int)(r.x & 0xFFFFu), cv = (int)(r.x >> 16);
-  return (cv / tile_c - row0) * ntx + cu / tile_c;
+  return (cv / C - row0) * ntx + cu / C;
 }
 
 // Exclusive scan of a[0, n) in place (each thread owns a run of consecutive
@@ -577,10 +578,12 @@ __device__ inline uint32_t block_scan_tiles(uint32_t* a, int n, uint32_t* wsum, 
   return total;
 }
 
+// C = tile edge (a template argument, so that the divisions are shifts and multiplications)
+template <int C>
 __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
     const uint32_t* __restrict__ rowoff, const uint32_t* __restrict__ prowoff,
     const uint2* __restrict__ rrec, const uint32_t* __restrict__ perm, int rshift, int ntx,
-    int nty, int tile_c, int O, int S, uint32_t zero_row, int chunk, uint2* __restrict__ tdesc,
+    int nty, int O, int S, uint32_t zero_row, int chunk, uint2* __restrict__ tdesc,
     SlotRec* __restrict__ krec) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t wsum[kSortThreads / 64];
@@ -611,7 +614,7 @@ __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
 #pragma unroll
     for (int j = 0; j < kSortLoads; ++j)
       if (e0 + j * kSortThreads + threadIdx.x < s1)
-        atomicAdd(&cnt[local_tile(r[j], tile_c, row0, ntx)], 1u);
+        atomicAdd(&cnt[local_tile<C>(r[j], row0, ntx)], 1u);
   }
   __syncthreads();
   // tile starts (padded counts scanned), descriptors and padding records
@@ -633,20 +636,30 @@ __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
   }
   __syncthreads();
   constexpr int kMaxPer = 4;   // records per thread and chunk (chunk <= 4096)
+  // records of the next chunk are loaded while the current one is placed
+  uint2 rn[kMaxPer];
+#pragma unroll
+  for (int j = 0; j < kMaxPer; ++j) {
+    const uint32_t e = s0 + j * kSortThreads + threadIdx.x;
+    rn[j] = (j * kSortThreads + (int)threadIdx.x < chunk && e < s1) ? rrec[e] : make_uint2(0u, 0u);
+  }
   for (uint32_t c0 = s0; c0 < s1; c0 += chunk) {
     const int n = (int)min((uint32_t)chunk, s1 - c0);
     uint2 r[kMaxPer];
     int tl[kMaxPer];
     uint32_t rk[kMaxPer];
 #pragma unroll
+    for (int j = 0; j < kMaxPer; ++j) r[j] = rn[j];
+    const uint32_t c1 = c0 + chunk;
+#pragma unroll
     for (int j = 0; j < kMaxPer; ++j) {
-      const int k = j * kSortThreads + threadIdx.x;
-      r[j] = k < n ? rrec[c0 + k] : make_uint2(0u, 0u);
+      const uint32_t e = c1 + j * kSortThreads + threadIdx.x;
+      if (j * kSortThreads + (int)threadIdx.x < chunk && e < s1) rn[j] = rrec[e];
     }
 #pragma unroll
     for (int j = 0; j < kMaxPer; ++j) {
       if (j * kSortThreads + (int)threadIdx.x < n) {
-        tl[j] = local_tile(r[j], tile_c, row0, ntx);
+        tl[j] = local_tile<C>(r[j], row0, ntx);
         rk[j] = atomicAdd(&lc[tl[j]], 1u);
       }
     }
@@ -659,11 +672,11 @@ __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
         const int cu = (int)(r[j].x & 0xFFFFu), cv = (int)(r[j].x >> 16);
         // padded-table bases: tap of region column x is at base + x
         const int k = (int)(r[j].y >> 16);
-        const int ox = cu - (cu / tile_c) * tile_c, oy = cv - (cv / tile_c) * tile_c;
+        const int ox = cu % C, oy = cv % C;
         const int row_u = k * O + (int)(r[j].y & 0xFFu);
         const int row_v = k * O + (int)((r[j].y >> 8) & 0xFFu);
         const uint32_t q = lc[tl[j]] + rk[j];
-        stage[q] = SlotRec{row_u * L + tile_c - 1 - ox, row_v * L + tile_c - 1 - oy,
+        stage[q] = SlotRec{row_u * L + C - 1 - ox, row_v * L + C - 1 - oy,
                            (int)(c0 + j * kSortThreads + threadIdx.x)};
         dst[q] = cnt[tl[j]] + rk[j];
       }
@@ -820,12 +833,12 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* t
 }
 
 hipError_t launch_quantise_rows(const double* u, const double* v, const double* w, int64_t nvis,
-                                QuantGeom g, int rshift, int nbins, uint32_t* key, uint2* qrec,
+                                QuantGeom g, int rshift, int nbins, uint32_t* rbin, uint2* qrec,
                                 uint32_t* chist, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
   const int64_t nb = (nvis + kChunk - 1) / kChunk;
   hipLaunchKernelGGL(quantise_rows_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, u, v, w, nvis,
-                     g, rshift, nbins, key, qrec, chist);
+                     g, rshift, nbins, rbin, qrec, chist);
   return hipGetLastError();
 }
 
@@ -859,13 +872,13 @@ hipError_t launch_pad_sizes(const uint32_t* rowcount, int nbins, int rshift, int
   return hipGetLastError();
 }
 
-hipError_t launch_row_scatter(const uint32_t* key, const uint2* qrec, int64_t nvis, int ntx,
-                              int rshift, int nbins, const uint32_t* chist, const uint32_t* delta,
-                              uint2* rrec, uint32_t* place, hipStream_t s) {
+hipError_t launch_row_scatter(const uint32_t* rbin, const uint2* qrec, int64_t nvis, int nbins,
+                              const uint32_t* chist, const uint32_t* delta, uint2* rrec,
+                              uint32_t* place, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
   const int64_t nb = (nvis + kChunk - 1) / kChunk;
-  hipLaunchKernelGGL(row_scatter_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, key, qrec, nvis,
-                     ntx, rshift, nbins, chist, delta, rrec, place);
+  hipLaunchKernelGGL(row_scatter_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, rbin, qrec, nvis,
+                     nbins, chist, delta, rrec, place);
   return hipGetLastError();
 }
 
@@ -882,11 +895,24 @@ hipError_t launch_row_sort(const uint32_t* rowcount, const uint32_t* rowoff,
   if (chunk < 64) return hipErrorInvalidValue;
   const int lds = (int)(8 * nloc + 16 * chunk);
   hipLaunchKernelGGL(bin_order_kernel, dim3(1), dim3(kSortThreads), 0, s, rowcount, nbins, perm);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&row_sort_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  hipLaunchKernelGGL(row_sort_kernel, dim3(nbins), dim3(kSortThreads), lds, s, rowoff, prowoff, rrec,
-                     perm, rshift, ntx, nty, tile_c, O, S, zero_row, (int)chunk, tdesc, krec);
-  return hipGetLastError();
+  auto run = [&](auto kern) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipLaunchKernelGGL(kern, dim3(nbins), dim3(kSortThreads), lds, s, rowoff, prowoff, rrec, perm,
+                       rshift, ntx, nty, O, S, zero_row, (int)chunk, tdesc, krec);
+    return hipGetLastError();
+  };
+  switch (tile_c) {
+    case 2: return run(&row_sort_kernel<2>);
+    case 4: return run(&row_sort_kernel<4>);
+    case 6: return run(&row_sort_kernel<6>);
+    case 8: return run(&row_sort_kernel<8>);
+    case 10: return run(&row_sort_kernel<10>);
+    case 12: return run(&row_sort_kernel<12>);
+    case 14: return run(&row_sort_kernel<14>);
+    case 16: return run(&row_sort_kernel<16>);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_vis_to_rows(const MoveArgs& a, hipStream_t s) {

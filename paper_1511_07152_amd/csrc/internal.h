@@ -18,7 +18,7 @@ constexpr int kItemMinSlots = 64;  // range of the tunable item length
 constexpr int kItemMaxSlots = 8192;
 constexpr int kMaxRowBins = 4096;  // level-1 sort bins (rows of tiles, possibly grouped)
 constexpr int kL1Chunk = 10240;    // visibilities per workgroup in the level-1 passes
-constexpr int kGroupChunks = 16;   // level-1 chunks per group of the run-offset scan
+constexpr int kGroupChunks = 8;    // level-1 chunks per group of the run-offset scan
 // placement word of a kept visibility: row bin << kPlaceShift | its position in
 // its chunk's bin-ordered staging (kDropped for dropped visibilities)
 constexpr int kPlaceShift = 14;
@@ -100,7 +100,7 @@ struct Plan {
   int64_t max_items = 0;        // capacity of items (for the smallest item length used so far)
   int item_slots = kItemMaxVis; // slots per work item (multiple of 4)
   int rshift = 0, nbins = 0;    // level-1 sort: row bin = tile row >> rshift
-  uint32_t* key = nullptr;      // [nvis] tile id or kDropped (caller order)
+  uint32_t* rbin = nullptr;     // [nvis] row bin or kDropped (caller order)
   uint2* qrec = nullptr;        // [nvis] packed bins (caller order)
   uint32_t* chist = nullptr;    // [chunks][nbins] level-1 histogram of each chunk
   uint32_t* gsum = nullptr;     // [nbins][groups] per-group sums, then their exclusive scan
@@ -161,7 +161,7 @@ hipError_t launch_zero_c64(float2* p, int64_t n, hipStream_t s);
 // two-level counting sort by tile (rows of tiles, then tiles within a row bin);
 // chist[chunk][bin] = level-1 histogram of each chunk of kL1Chunk visibilities
 hipError_t launch_quantise_rows(const double* u, const double* v, const double* w, int64_t nvis,
-                                QuantGeom g, int rshift, int nbins, uint32_t* key, uint2* qrec,
+                                QuantGeom g, int rshift, int nbins, uint32_t* rbin, uint2* qrec,
                                 uint32_t* chist, hipStream_t s);
 // rowcount[bin] = kept visibilities per row bin (rowcount[nbins] = 0); gsum =
 // [nbins][groups] exclusive scan over the chunk groups of each bin
@@ -175,9 +175,9 @@ hipError_t launch_chunk_deltas(const uint32_t* chist, const uint32_t* gsum,
 hipError_t launch_pad_sizes(const uint32_t* rowcount, int nbins, int rshift, int ntx, int nty,
                             uint32_t* rowpad, hipStream_t s);
 // level-1 placement: records in row-bin order, placement word per visibility
-hipError_t launch_row_scatter(const uint32_t* key, const uint2* qrec, int64_t nvis, int ntx,
-                              int rshift, int nbins, const uint32_t* chist, const uint32_t* delta,
-                              uint2* rrec, uint32_t* place, hipStream_t s);
+hipError_t launch_row_scatter(const uint32_t* rbin, const uint2* qrec, int64_t nvis, int nbins,
+                              const uint32_t* chist, const uint32_t* delta, uint2* rrec,
+                              uint32_t* place, hipStream_t s);
 // zero_row: row-bin position the padding slots point to (a W V that stays 0);
 // perm: [nbins] scratch for the order in which the row bins are sorted
 hipError_t launch_row_sort(const uint32_t* rowcount, const uint32_t* rowoff,
