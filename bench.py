@@ -202,7 +202,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--dump-s", type=float, default=10.0, help="dump time (10 s: 92.9M vis)")
-    ap.add_argument("--cpu-sample", type=int, default=400_000)
+    ap.add_argument("--cpu-sample", type=int, default=1_500_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true",
                     help="skip the FP16/BF16 MFMA forms and their accuracy check")
