@@ -181,13 +181,19 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
                       const float* const* weight, sepw_c64* const* out, uint32_t flags,
                       void* hip_stream);
 
-/* Length of the plan's work items: the number of tile slots (visibilities,
- * each tile padded to whole groups of 4) of one row of tiles that one wave
- * processes in order.  Default 1024; must be a multiple of 4 in [64, 8192].
- * Rebuilds the plan's work list asynchronously on the stream (it waits for the
- * stream once when the list has to grow); later rebins keep the length.
+/* Length of the plan's gridding work items: the number of tile slots
+ * (visibilities, each tile padded to whole groups of 4) of one row of tiles
+ * that one wave processes in order.  Default 1024; must be a multiple of 4 in
+ * [64, 8192].  Rebuilds the plan's gridding work list asynchronously on the
+ * stream (it waits for the stream once when the list has to grow); later
+ * rebins keep the length.  Used by sepw_grid and sepw_grid_batched.
  * Errors: SEPW_ERR_ARG (null p, invalid slots), SEPW_ERR_OOM, SEPW_ERR_HIP. */
 int sepw_plan_set_item_slots(sepw_plan p, int32_t slots, void* hip_stream);
+
+/* The same for the degridding work list (sepw_degrid).  Default 448: shorter
+ * items keep fewer rows of scattered results in flight per L2.  Same range,
+ * behaviour and errors as sepw_plan_set_item_slots. */
+int sepw_plan_set_degrid_item_slots(sepw_plan p, int32_t slots, void* hip_stream);
 
 /* Autotuner of the batching form's launch shape: times sepw_grid_batched with
  * SEPW_GRID_ONLY on these jobs (HIP events, one warm-up and two timed runs per

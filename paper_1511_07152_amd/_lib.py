@@ -70,6 +70,7 @@ def load():
     lib.sepw_grid_batched.argtypes = [c_int32, P(c_void_p), P(c_void_p), P(c_void_p), P(c_void_p),
                                       ctypes.c_uint32, c_void_p]
     lib.sepw_plan_set_item_slots.argtypes = [c_void_p, c_int32, c_void_p]
+    lib.sepw_plan_set_degrid_item_slots.argtypes = [c_void_p, c_int32, c_void_p]
     lib.sepw_autotune_batched.argtypes = [c_int32, P(c_void_p), P(c_void_p), P(c_void_p),
                                           P(c_void_p), c_void_p, P(c_int32), P(c_int32)]
     lib.sepw_free_kernels.argtypes = [c_void_p]
@@ -81,7 +82,8 @@ def load():
                  "sepw_plan_bins", "sepw_plan_tile_size", "sepw_grid", "sepw_degrid",
                  "sepw_grid_batched", "sepw_free_kernels", "sepw_free_plan", "sepw_device_count",
                  "sepw_plan_rebin", "sepw_kernels_set_wrange", "sepw_timing_enable",
-                 "sepw_timing_collect", "sepw_plan_set_item_slots", "sepw_autotune_batched"):
+                 "sepw_timing_collect", "sepw_plan_set_item_slots", "sepw_plan_set_degrid_item_slots",
+                 "sepw_autotune_batched"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -222,6 +224,12 @@ class Plan:
         """sepw_plan_set_item_slots: work-item length (multiple of 4 in [64, 8192])."""
         _check(load().sepw_plan_set_item_slots(self._h, int(slots), _stream()),
                "sepw_plan_set_item_slots")
+        return self
+
+    def set_degrid_item_slots(self, slots):
+        """sepw_plan_set_degrid_item_slots: degridding work-item length."""
+        _check(load().sepw_plan_set_degrid_item_slots(self._h, int(slots), _stream()),
+               "sepw_plan_set_degrid_item_slots")
         return self
 
     def bins(self):

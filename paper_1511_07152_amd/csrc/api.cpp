@@ -170,10 +170,12 @@ void destroy_plan(Plan* p) {
   dfree(p->krec);
   dfree(p->tdesc);
   dfree(p->rot);
-  dfree(p->nit);
-  dfree(p->itoff);
+  for (WorkList* l : {&p->gl, &p->dl}) {
+    dfree(l->nit);
+    dfree(l->itoff);
+    dfree(l->items);
+  }
   dfree(p->qctr);
-  dfree(p->items);
   dfree(p->scan_tmp);
   delete static_cast<sepw_plan_s*>(p);
 }
@@ -351,8 +353,8 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
   // multiple of 4, each row bin's range rounded to 4
   P->pcap = capacity + 3 * std::min<int64_t>(nt, capacity) + 4 * (int64_t)P->nbins;
   if (P->pcap > 2147483647LL - 64) return SEPW_ERR_UNSUPPORTED;
-  P->item_slots = kItemMaxVis;
-  P->max_items = P->nty + P->pcap / P->item_slots + 1;
+  P->gl.slots = kItemMaxVis;
+  P->dl.slots = kDegridItemSlots;
   P->r8 = (P->nty + 7) / 8;
   P->scan_tmp_len = scan_tmp_size(std::max<int64_t>(P->nbins, 8 * (int64_t)P->r8) + 1);
   SEPW_TRY(dalloc(&P->rbin, capacity));
@@ -373,10 +375,13 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
   SEPW_TRY(dalloc(&P->yrow, capacity + 1));
   SEPW_TRY(dalloc(&P->krec, P->pcap));
   SEPW_TRY(dalloc(&P->tdesc, nt));
-  SEPW_TRY(dalloc(&P->nit, 8 * (int64_t)P->r8 + 1));
-  SEPW_TRY(dalloc(&P->itoff, 8 * (int64_t)P->r8 + 1));
+  for (WorkList* l : {&P->gl, &P->dl}) {
+    l->max_items = P->nty + P->pcap / l->slots + 1;
+    SEPW_TRY(dalloc(&l->nit, 8 * (int64_t)P->r8 + 1));
+    SEPW_TRY(dalloc(&l->itoff, 8 * (int64_t)P->r8 + 1));
+    SEPW_TRY(dalloc(&l->items, l->max_items));
+  }
   SEPW_TRY(dalloc(&P->qctr, 8));
-  SEPW_TRY(dalloc(&P->items, P->max_items));
   SEPW_TRY(dalloc(&P->scan_tmp, P->scan_tmp_len));
   if (K->facet) SEPW_TRY(dalloc(&P->rot, capacity));
   return SEPW_OK;
@@ -396,13 +401,37 @@ MoveArgs move_args(const Plan* p, const sepw_c64* vis, const float* weight) {
   return m;
 }
 
-// Work list: items of item_slots slots per row of tiles, in 8 lists by row % 8.
-hipError_t build_items(Plan* P, hipStream_t s) {
-  hipError_t e = launch_item_counts(P->tdesc, P->ntx, P->nty, P->r8, P->item_slots, P->nit, s);
-  if (e == hipSuccess) e = launch_scan(P->nit, P->itoff, 8 * (int64_t)P->r8 + 1, P->scan_tmp, s);
+// Work list: items of l.slots slots per row of tiles, in 8 lists by row % 8.
+hipError_t build_list(Plan* P, WorkList& l, hipStream_t s) {
+  hipError_t e = launch_item_counts(P->tdesc, P->ntx, P->nty, P->r8, l.slots, l.nit, s);
+  if (e == hipSuccess) e = launch_scan(l.nit, l.itoff, 8 * (int64_t)P->r8 + 1, P->scan_tmp, s);
   if (e == hipSuccess)
-    e = launch_items(P->tdesc, P->itoff, P->ntx, P->nty, P->r8, P->item_slots, P->items, s);
+    e = launch_items(P->tdesc, l.itoff, P->ntx, P->nty, P->r8, l.slots, l.items, s);
   return e;
+}
+
+hipError_t build_items(Plan* P, hipStream_t s) {
+  hipError_t e = build_list(P, P->gl, s);
+  if (e == hipSuccess) e = build_list(P, P->dl, s);
+  return e;
+}
+
+// New length of one work list (the list grows when needed).
+int set_list_slots(Plan* p, WorkList& l, int32_t slots, hipStream_t s) {
+  if (slots < kItemMinSlots || slots > kItemMaxSlots || (slots & 3) != 0) return SEPW_ERR_ARG;
+  const int64_t need = p->nty + p->pcap / slots + 1;
+  if (need > l.max_items) {
+    // the old list may still be read by queued launches on this stream
+    SEPW_TRY(hipStreamSynchronize(s));
+    int4* items = nullptr;
+    SEPW_TRY(dalloc(&items, need));
+    dfree(l.items);
+    l.items = items;
+    l.max_items = need;
+  }
+  l.slots = slots;
+  SEPW_TRY(build_list(p, l, s));
+  return SEPW_OK;
 }
 
 // Quantise, sort and build the work list for nvis <= capacity visibilities.
@@ -633,15 +662,15 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
   {
     Stage st(SEPW_STAGE_GRID, s);
     if (K->prm.precision == SEPW_FP32) {
-      GridArgs a{p->items, p->itoff + 8 * p->r8, p->itoff, p->r8, p->qctr, p->tdesc, p->krec,
+      GridArgs a{p->gl.items, p->gl.itoff + 8 * p->r8, p->gl.itoff, p->r8, p->qctr, p->tdesc, p->krec,
                  p->yrow, K->pad_u, K->pad_v,
                  K->tab_len, N, p->ntx, grid_only ? 0 : 1, img};
-      SEPW_TRY(launch_grid_fp32(K->S, a, p->max_items, s));
+      SEPW_TRY(launch_grid_fp32(K->S, a, p->gl.max_items, s));
     } else {
-      GridArgsLp a{p->items, p->itoff + 8 * p->r8, p->itoff, p->r8, p->qctr, p->tdesc, p->krec,
+      GridArgsLp a{p->gl.items, p->gl.itoff + 8 * p->r8, p->gl.itoff, p->r8, p->qctr, p->tdesc, p->krec,
                    p->yrow, K->pad_us, K->lp_v,
                    K->lp_bound, N, p->ntx, grid_only ? 0 : 1, img};
-      SEPW_TRY(launch_grid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->max_items, s));
+      SEPW_TRY(launch_grid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->gl.max_items, s));
     }
   }
   if (grid_only) return SEPW_OK;
@@ -688,15 +717,15 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
     Stage st(SEPW_STAGE_DEGRID, s);
     if (K->prm.precision == SEPW_FP32) {
       SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8, s));
-      DegridArgs a{p->items, p->itoff + 8 * p->r8, p->itoff, p->r8, p->qctr, p->tdesc, p->krec,
+      DegridArgs a{p->dl.items, p->dl.itoff + 8 * p->r8, p->dl.itoff, p->r8, p->qctr, p->tdesc, p->krec,
                    src, K->pad_u, K->pad_v,
                    K->tab_len, N, p->ntx, checker, p->yrow};
-      SEPW_TRY(launch_degrid_fp32(K->S, a, p->max_items, K->lds_bytes, K->n_cu, s));
+      SEPW_TRY(launch_degrid_fp32(K->S, a, p->dl.max_items, K->lds_bytes, K->n_cu, s));
     } else {
-      DegridArgsLp a{p->items, p->itoff + 8 * p->r8, p->itoff, p->r8, p->qctr, p->tdesc, p->krec,
+      DegridArgsLp a{p->dl.items, p->dl.itoff + 8 * p->r8, p->dl.itoff, p->r8, p->qctr, p->tdesc, p->krec,
                      src, K->lp_u, K->pad_vs, N,
                      p->ntx, checker, p->yrow};
-      SEPW_TRY(launch_degrid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->max_items, s));
+      SEPW_TRY(launch_degrid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->dl.max_items, s));
     }
   }
   {
@@ -764,7 +793,7 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
   for (int r = 0; r < njobs; ++r) {
     Plan* p = plans[order[r]];
     Kernels* K = p->K;
-    bs->host[r] = GridArgs{p->items, p->itoff + 8 * p->r8, p->itoff, p->r8, p->qctr, p->tdesc,
+    bs->host[r] = GridArgs{p->gl.items, p->gl.itoff + 8 * p->r8, p->gl.itoff, p->r8, p->qctr, p->tdesc,
                            p->krec, p->yrow, K->pad_u,
                            K->pad_v, K->tab_len, N, p->ntx, grid_only ? 0 : 1,
                            reinterpret_cast<float2*>(out[order[r]])};
@@ -794,22 +823,13 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
 }
 
 int sepw_plan_set_item_slots(sepw_plan p, int32_t slots, void* hip_stream) {
-  if (!p || slots < kItemMinSlots || slots > kItemMaxSlots || (slots & 3) != 0)
-    return SEPW_ERR_ARG;
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  const int64_t need = p->nty + p->pcap / slots + 1;
-  if (need > p->max_items) {
-    // the old list may still be read by queued launches on this stream
-    SEPW_TRY(hipStreamSynchronize(s));
-    int4* items = nullptr;
-    SEPW_TRY(dalloc(&items, need));
-    dfree(p->items);
-    p->items = items;
-    p->max_items = need;
-  }
-  p->item_slots = slots;
-  SEPW_TRY(build_items(p, s));
-  return SEPW_OK;
+  if (!p) return SEPW_ERR_ARG;
+  return set_list_slots(p, p->gl, slots, static_cast<hipStream_t>(hip_stream));
+}
+
+int sepw_plan_set_degrid_item_slots(sepw_plan p, int32_t slots, void* hip_stream) {
+  if (!p) return SEPW_ERR_ARG;
+  return set_list_slots(p, p->dl, slots, static_cast<hipStream_t>(hip_stream));
 }
 
 int sepw_autotune_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* const* vis,

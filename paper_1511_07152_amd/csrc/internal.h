@@ -13,7 +13,8 @@ namespace sepw {
 constexpr uint32_t kDropped = 0xFFFFFFFFu;
 constexpr int kRegion = 16;        // MFMA tile region edge (cells): core + S - 1
 constexpr int kMaxSupport = 15;    // S <= kRegion - 1
-constexpr int kItemMaxVis = 1024;  // default slots per work item (a slice of a tile row)
+constexpr int kItemMaxVis = 1024;  // default slots per gridding work item (a slice of a tile row)
+constexpr int kDegridItemSlots = 448;  // default slots per degridding work item
 constexpr int kItemMinSlots = 64;  // range of the tunable item length
 constexpr int kItemMaxSlots = 8192;
 constexpr int kMaxRowBins = 4096;  // level-1 sort bins (rows of tiles, possibly grouped)
@@ -89,6 +90,16 @@ struct SlotRec {
   int x, y, z;
 };
 
+// Work items of at most `slots` tile slots of one row of tiles, in 8 lists by
+// row % 8 (list q = items [itoff[q r8], itoff[(q + 1) r8])).
+struct WorkList {
+  int slots = kItemMaxVis;     // slots per item (multiple of 4)
+  int64_t max_items = 0;       // capacity of items (for the shortest length used so far)
+  uint32_t* nit = nullptr;     // [8 r8 + 1] items per row, row r at (r % 8) r8 + r / 8
+  uint32_t* itoff = nullptr;   // [8 r8 + 1] exclusive scan of nit
+  int4* items = nullptr;       // [max_items] (tile row, first slot, end slot, tile column)
+};
+
 struct Plan {
   Kernels* K = nullptr;
   uint64_t generation = 0;      // K->generation the bins were made for
@@ -97,8 +108,6 @@ struct Plan {
   int64_t pcap = 0;             // tile slots the slot-order buffers were sized for
   int tile_c = 0, ntx = 0, nty = 0;
   int64_t ntiles = 0;
-  int64_t max_items = 0;        // capacity of items (for the smallest item length used so far)
-  int item_slots = kItemMaxVis; // slots per work item (multiple of 4)
   int rshift = 0, nbins = 0;    // level-1 sort: row bin = tile row >> rshift
   uint32_t* rbin = nullptr;     // [nvis] row bin or kDropped (caller order)
   uint2* qrec = nullptr;        // [nvis] packed bins (caller order)
@@ -121,10 +130,9 @@ struct Plan {
   uint2* tdesc = nullptr;       // [ntiles] (first slot, first slot + count) per tile
   float2* rot = nullptr;        // [nvis] facet phase rotation, caller order
   int r8 = 0;                   // rows of tiles per work list: ceil(nty / 8)
-  uint32_t* nit = nullptr;      // [8 r8 + 1] work items per row, row r at (r % 8) r8 + r / 8
-  uint32_t* itoff = nullptr;    // [8 r8 + 1] exclusive scan of nit: list q = [itoff[q r8], itoff[(q + 1) r8])
   uint32_t* qctr = nullptr;     // [8] work-list counters of a launch
-  int4* items = nullptr;        // [max_items] (tile row, first slot, end slot, tile column)
+  WorkList gl;                  // gridding work items
+  WorkList dl;                  // degridding work items (shorter: fewer rows of results in flight)
   uint32_t* scan_tmp = nullptr; // block partials for the scans
   int64_t scan_tmp_len = 0;
 };

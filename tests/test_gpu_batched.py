@@ -88,13 +88,14 @@ def test_batched_matches_oracle(lib):
 
 @pytest.mark.parametrize("slots", [64, 256, 8192])
 def test_item_length_matches_oracle(lib, slots):
-    # work items of 64 .. 8192 slots split the rows of tiles differently; the
-    # grid and the degridded visibilities must not depend on it
+    # work items of 64 .. 8192 slots (both work lists) split the rows of tiles
+    # differently; the grid and the degridded visibilities must not depend on it
     N, fov, S, O, P = 96, math.radians(1.5), 11, 8, 6
     jb = _jobs(53, 1, N, fov, [6000])[0]
     K = lib.Kernels(N, fov, S, O, P, -350.0, 350.0)
     plan = lib.Plan(K, dev(jb["u"], torch.float64), dev(jb["v"], torch.float64),
                     dev(jb["w"], torch.float64)).set_item_slots(slots)
+    plan.set_degrid_item_slots(slots)
     o = OracleSetup(jb["u"], jb["v"], jb["w"], N, fov, S, O, P, -350.0, 350.0, plan.tile_size)
     G = lib.grid(plan, dev(jb["V"], torch.complex64), dev(jb["W"], torch.float32),
                  flags=lib.GRID_ONLY).cpu().numpy()
