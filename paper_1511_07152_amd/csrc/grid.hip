@@ -64,23 +64,27 @@ __device__ inline void ring_add(float* ring, const f32x4& re, const f32x4& im, i
 // Flush ring columns [fx, fx + 16) (grid rows gy0 .. gy0 + 15) to the grid with
 // atomics and clear them.  Lane L takes float L % 32 of a 16-column row
 // segment (column (L % 32) / 2, real or imaginary part) of rows 2 k + L / 32.
+// All eight ring reads are issued before the first use; the lane's rows all
+// have the parity of gy0 + L / 32, so its checkerboard sign is computed once.
 __device__ inline void ring_flush16(float* ring, int fx, float* g, int gy0, int N, int checker,
                                     int lane) {
   const int f = lane & 31, half = lane >> 5;
   const int gx = fx + (f >> 1);
   const int slot = gx & (kRing - 1);
   const bool col_ok = gx >= 0 && gx < N;
+  float* p = ring + 2 * (half * kRingPitch + slot) + (f & 1);   // row half, then 2 rows apart
+  float v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = p[4 * k * kRingPitch];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) p[4 * k * kRingPitch] = 0.f;
+  const float sg = (checker && ((gx + gy0 + half) & 1)) ? -1.f : 1.f;
+  float* gp = g + 2 * ((int64_t)(gy0 + half) * N + gx) + (f & 1);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const int row = 2 * k + half;
-    float* p = ring + 2 * (row * kRingPitch + slot) + (f & 1);
-    const float v = *p;
-    *p = 0.f;
-    const int gy = gy0 + row;
-    if (v != 0.f && col_ok && gy >= 0 && gy < N) {
-      const float sg = (checker && ((gx + gy) & 1)) ? -v : v;
-      unsafeAtomicAdd(g + 2 * ((int64_t)gy * N + gx) + (f & 1), sg);
-    }
+    const int gy = gy0 + 2 * k + half;
+    if (v[k] != 0.f && col_ok && gy >= 0 && gy < N)
+      unsafeAtomicAdd(gp + (int64_t)4 * k * N, sg * v[k]);
   }
 }
 
