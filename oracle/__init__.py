@@ -26,8 +26,10 @@ by eye against the paper:
 * ``imaging``    grid correction by the taper and the factor n around F+ / F-
 * ``chi2``       chi-squared data misfit of a predicted model and its image
                  gradient through the gridding adjoint (Section 6, major cycles)
+* ``wstack``     W-stacking hybrid: w-slices corrected in image space, residual
+                 w by separable W projection (Section 4.3)
 
 Readings of points the paper leaves open are documented at each function.
 """
 
-from . import geometry, pswf, tables, quantise, gridder, dft, phase_error, facet, imaging, chi2  # noqa: F401
+from . import geometry, pswf, tables, quantise, gridder, dft, phase_error, facet, imaging, chi2, wstack  # noqa: F401,E501

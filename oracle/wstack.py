@@ -1,0 +1,105 @@
+"""W-stacking hybrid: w-slices corrected in image space, residual w by
+separable W projection (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Section 4.3: visibilities are partitioned by w; within each partition the
+partition's w is corrected in image space by a phase factor, and the residual
+w by (here separable) W projection.  Splitting w_i = w_s + dw_i in the
+dirty-image equation of Section 2,
+
+    exp(2 pi i w_i (n - 1)) = exp(2 pi i w_s (n - 1)) exp(2 pi i dw_i (n - 1)),
+
+so with D_s the separable W-projection image of slice s on its residual w
+(gridding, F+, division by the taper, factor n as in ``imaging``),
+
+    D = sum_s exp(2 pi i w_s (n - 1)) D_s .
+
+Prediction is the adjoint: slice s degrids the model times
+exp(-2 pi i w_s (n - 1)) on its residual w.
+
+Readings (the paper fixes none of these):
+
+* slices are uniform on [w_lo, w_hi]: slice s = clamp(floor((w - w_lo) n_s /
+  (w_hi - w_lo)), 0, n_s - 1), centre w_s = w_lo + (s + 1/2)(w_hi - w_lo)/n_s
+  (the same rule as the w-planes; Section 4.3 takes evenly spaced slices);
+* the residual w - w_s of every slice is binned into P uniform planes on
+  [-h, h], h = (w_hi - w_lo) / (2 n_s), one table set shared by all slices;
+* n - 1 is evaluated as -(l^2 + m^2) / (1 + n), which equals it exactly and
+  avoids the cancellation of n - 1 near the centre.
+"""
+import numpy as np
+
+from . import geometry, gridder, imaging, quantise, tables
+
+
+def slice_of(w, n_slices, w_lo, w_hi):
+    """Slice index, slice centres and residual w - w_s of each visibility
+    (non-finite w goes to slice 0 with a non-finite residual, which the
+    plane quantiser then drops)."""
+    s, _ = quantise.plane_index(w, n_slices, w_lo, w_hi)
+    ws = tables.w_plane_centres(n_slices, w_lo, w_hi)
+    return s, ws, np.asarray(w, np.float64) - ws[s]
+
+
+def residual_range(n_slices, w_lo, w_hi):
+    h = (np.float64(w_hi) - np.float64(w_lo)) / (2 * n_slices)
+    return -h, h
+
+
+def slice_phase(N, fov, w_s, sign):
+    """exp(sign 2 pi i w_s (n - 1)) at the pixels, indexed [q][p]."""
+    l = geometry.pixel_l(N, fov)
+    r2 = l[None, :] ** 2 + l[:, None] ** 2
+    n = np.sqrt(1.0 - r2)
+    return np.exp(sign * 2j * np.pi * w_s * (-r2 / (1.0 + n)))
+
+
+def _bins(u, v, w, N, fov, O, S, P, w_lo, w_hi):
+    return quantise.quantise(u, v, w, N, fov, O, S, P, w_lo, w_hi, 1)
+
+
+def residual_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a=0.5, b=5.0 / 24.0):
+    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi)
+    return tables.separable_table(tables.w_plane_centres(P, r_lo, r_hi), N, fov, S, O, c1, a=a, b=b)
+
+
+def image(u, v, w, y, N, fov, S, O, P, n_slices, w_lo, w_hi, c1, n_power=0, a=0.5,
+          b=5.0 / 24.0, bins=_bins, wrap=False):
+    """Sum over slices of exp(2 pi i w_s (n - 1)) times the slice's corrected image."""
+    s, ws, dw = slice_of(w, n_slices, w_lo, w_hi)
+    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi)
+    T = residual_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a, b)
+    D = np.zeros((N, N), dtype=np.complex128)
+    for k in range(n_slices):
+        idx = np.flatnonzero(s == k)
+        if len(idx) == 0:
+            continue
+        q = bins(u[idx], v[idx], dw[idx], N, fov, O, S, P, r_lo, r_hi)
+        G = gridder.grid_separable(q, y[idx], T, N, S, wrap=wrap)
+        D += slice_phase(N, fov, ws[k], +1) * imaging.image_from_grid(G, c1, fov, n_power)
+    return D
+
+
+def predict(u, v, w, X, N, fov, S, O, P, n_slices, w_lo, w_hi, c1, n_power=0, a=0.5,
+            b=5.0 / 24.0, bins=_bins, wrap=False):
+    """Visibilities of model X: slice s degrids X exp(-2 pi i w_s (n - 1))."""
+    s, ws, dw = slice_of(w, n_slices, w_lo, w_hi)
+    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi)
+    T = residual_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a, b)
+    V = np.zeros(len(u), dtype=np.complex128)
+    for k in range(n_slices):
+        idx = np.flatnonzero(s == k)
+        if len(idx) == 0:
+            continue
+        q = bins(u[idx], v[idx], dw[idx], N, fov, O, S, P, r_lo, r_hi)
+        G = imaging.grid_from_image(X * slice_phase(N, fov, ws[k], -1), c1, fov, n_power)
+        V[idx] = gridder.degrid_separable(q, G, T, N, S, wrap=wrap)
+    return V
+
+
+def bins(u, v, w, N, fov, O, S, P, n_slices, w_lo, w_hi):
+    """Bins of every visibility in caller order (residual w, residual planes)."""
+    _, _, dw = slice_of(w, n_slices, w_lo, w_hi)
+    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi)
+    return quantise.quantise(u, v, dw, N, fov, O, S, P, r_lo, r_hi, 1)
