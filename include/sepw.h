@@ -19,6 +19,8 @@
  *   sepw_grid_batched  many facet/snapshot jobs in one persistent launch
  *                      (sepw_autotune_batched picks its launch shape)
  *                      (Section 4.1 faceting, Section 4.2 snapshots)
+ *   sepw_wstack_*      W-stacking hybrid: w-slices corrected in image space,
+ *                      residual w by separable W projection (Section 4.3)
  *
  * Conventions (the paper leaves these open; the library fixes them):
  *   N     grid and image size, even.           fov  full image width in
@@ -58,6 +60,7 @@ extern "C" {
 typedef struct { float re, im; } sepw_c64;
 typedef struct sepw_kernels_s* sepw_kernels;   /* tables + taper + FFT plan   */
 typedef struct sepw_plan_s*    sepw_plan;       /* binned uvw for one kernels  */
+typedef struct sepw_wstack_s*  sepw_wstack;     /* W-stacking slices + plans   */
 
 enum {
   SEPW_OK = 0,
@@ -181,6 +184,42 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
                       const float* const* weight, sepw_c64* const* out, uint32_t flags,
                       void* hip_stream);
 
+/* W-stacking hybrid (Section 4.3): the visibilities are partitioned into
+ * n_slices uniform w-slices on [w_lo, w_hi] (slice s = clamp(floor((w - w_lo)
+ * n_slices / (w_hi - w_lo)), 0, n_slices - 1), centre w_s = w_lo + (s + 1/2)
+ * (w_hi - w_lo) / n_slices); slice s is imaged with the separable W-projection
+ * path on its residual w - w_s, and its image is multiplied by the exact
+ * phase exp(2 pi i w_s (n - 1)) before the slice images are summed.  k holds
+ * the residual tables: plain (non-facet) kernels whose planes span exactly
+ * [-h, h], h = (w_hi - w_lo) / (2 n_slices).  u, v, w: DEVICE float64[nvis],
+ * read during the call only.  *n_dropped (host, may be NULL) counts
+ * visibilities whose footprint leaves the grid or whose w is not finite.
+ * Synchronises the stream (the slice sizes come to the host).
+ * Errors: SEPW_ERR_ARG (null k or out, facet kernels, n_slices outside
+ * [1, 4096], w_lo >= w_hi, kernels' w range not [-h, h], nvis out of range),
+ * SEPW_ERR_OOM, SEPW_ERR_HIP. */
+int sepw_wstack_create(sepw_kernels k, int32_t n_slices, double w_lo, double w_hi, int64_t nvis,
+                       const double* u, const double* v, const double* w, int64_t* n_dropped,
+                       void* hip_stream, sepw_wstack* out);
+
+/* Dirty image of the W-stacking hybrid: sum over slices of
+ * exp(2 pi i w_s (n - 1)) times the slice's image (sepw_grid without
+ * SEPW_GRID_ONLY, same flags SEPW_MUL_N / SEPW_DIV_N).  vis, weight: DEVICE,
+ * caller order (weight may be NULL); image_out: DEVICE complex64[N*N].
+ * Errors: SEPW_ERR_ARG (null pointers, SEPW_GRID_ONLY or both n flags), and
+ * those of sepw_grid. */
+int sepw_wstack_grid(sepw_wstack ws, const sepw_c64* vis, const float* weight, sepw_c64* image_out,
+                     uint32_t flags, void* hip_stream);
+
+/* Prediction, the adjoint of sepw_wstack_grid: slice s degrids
+ * image exp(-2 pi i w_s (n - 1)) (with SEPW_DIV_N: image / n) on its residual
+ * w.  image: DEVICE complex64[N*N]; vis_out: DEVICE complex64[nvis], caller
+ * order, 0 for dropped visibilities.
+ * Errors: SEPW_ERR_ARG (null pointers, flags other than SEPW_DIV_N), and those
+ * of sepw_degrid. */
+int sepw_wstack_degrid(sepw_wstack ws, const sepw_c64* image, sepw_c64* vis_out, uint32_t flags,
+                       void* hip_stream);
+
 /* Length of the plan's gridding work items: the number of tile slots
  * (visibilities, each tile padded to whole groups of 4) of one row of tiles
  * that one wave processes in order.  Default 1024; must be a multiple of 4 in
@@ -236,6 +275,7 @@ int sepw_timing_collect(double* ms, int64_t* n);
 
 int sepw_free_kernels(sepw_kernels k);
 int sepw_free_plan(sepw_plan p);
+int sepw_free_wstack(sepw_wstack ws);
 const char* sepw_strerror(int code);
 int32_t sepw_device_count(void);   /* 0 when no HIP device is visible */
 

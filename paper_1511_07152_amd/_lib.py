@@ -73,6 +73,12 @@ def load():
     lib.sepw_plan_set_degrid_item_slots.argtypes = [c_void_p, c_int32, c_void_p]
     lib.sepw_autotune_batched.argtypes = [c_int32, P(c_void_p), P(c_void_p), P(c_void_p),
                                           P(c_void_p), c_void_p, P(c_int32), P(c_int32)]
+    lib.sepw_wstack_create.argtypes = [c_void_p, c_int32, c_double, c_double, c_int64, c_void_p,
+                                       c_void_p, c_void_p, P(c_int64), c_void_p, P(c_void_p)]
+    lib.sepw_wstack_grid.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_uint32,
+                                     c_void_p]
+    lib.sepw_wstack_degrid.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.c_uint32, c_void_p]
+    lib.sepw_free_wstack.argtypes = [c_void_p]
     lib.sepw_free_kernels.argtypes = [c_void_p]
     lib.sepw_free_plan.argtypes = [c_void_p]
     lib.sepw_strerror.argtypes = [ctypes.c_int]
@@ -83,7 +89,8 @@ def load():
                  "sepw_grid_batched", "sepw_free_kernels", "sepw_free_plan", "sepw_device_count",
                  "sepw_plan_rebin", "sepw_kernels_set_wrange", "sepw_timing_enable",
                  "sepw_timing_collect", "sepw_plan_set_item_slots", "sepw_plan_set_degrid_item_slots",
-                 "sepw_autotune_batched"):
+                 "sepw_autotune_batched", "sepw_wstack_create", "sepw_wstack_grid",
+                 "sepw_wstack_degrid", "sepw_free_wstack"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -240,6 +247,66 @@ class Plan:
     def close(self):
         if self._h is not None and self._h.value:
             load().sepw_free_plan(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class WStack:
+    """sepw_wstack_create: W-stacking hybrid over n_slices uniform w-slices on
+    [w_lo, w_hi]; ``kernels`` hold the residual tables (planes on [-h, h],
+    h = (w_hi - w_lo) / (2 n_slices))."""
+
+    def __init__(self, kernels, n_slices, w_lo, w_hi, u, v, w, count_dropped=True):
+        lib = load()
+        u = _dev(u, torch.float64, "u")
+        v = _dev(v, torch.float64, "v")
+        w = _dev(w, torch.float64, "w")
+        if not (u.numel() == v.numel() == w.numel()):
+            raise ValueError("u, v, w must have the same length")
+        self.kernels = kernels
+        self.nvis = u.numel()
+        nd = c_int64(-1)
+        h = c_void_p()
+        _check(lib.sepw_wstack_create(kernels.handle, int(n_slices), float(w_lo), float(w_hi),
+                                      self.nvis, _ptr(u), _ptr(v), _ptr(w),
+                                      ctypes.byref(nd) if count_dropped else None, _stream(),
+                                      ctypes.byref(h)), "sepw_wstack_create")
+        self._h = h
+        self.n_dropped = nd.value if count_dropped else None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def grid(self, vis, weight=None, flags=0, out=None):
+        """sepw_wstack_grid: complex64 N x N image."""
+        vis = _dev(vis, torch.complex64, "vis")
+        if weight is not None:
+            weight = _dev(weight, torch.float32, "weight")
+        N = self.kernels.N
+        if out is None:
+            out = torch.empty((N, N), dtype=torch.complex64, device="cuda")
+        _check(load().sepw_wstack_grid(self._h, _ptr(vis), _ptr(weight), _ptr(out), flags,
+                                       _stream()), "sepw_wstack_grid")
+        return out
+
+    def degrid(self, image, flags=0, out=None):
+        """sepw_wstack_degrid: complex64 visibilities in the caller's order."""
+        image = _dev(image, torch.complex64, "image")
+        if out is None:
+            out = torch.empty(self.nvis, dtype=torch.complex64, device="cuda")
+        _check(load().sepw_wstack_degrid(self._h, _ptr(image), _ptr(out), flags, _stream()),
+               "sepw_wstack_degrid")
+        return out
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            load().sepw_free_wstack(self._h)
         self._h = None
 
     def __del__(self):

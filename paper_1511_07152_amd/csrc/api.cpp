@@ -21,6 +21,20 @@ using namespace sepw;
 struct sepw_kernels_s : Kernels {};
 struct sepw_plan_s : Plan {};
 
+// W-stacking hybrid (Section 4.3): one plan per non-empty w-slice over the
+// slice's residual w, the visibilities in slice order, and one image buffer.
+struct sepw_wstack_s {
+  Kernels* K = nullptr;
+  int ns = 0;
+  int64_t nvis = 0;
+  std::vector<double> centre;    // slice centres w_s
+  std::vector<int64_t> off;      // [ns + 1] slice offsets in slice order
+  std::vector<Plan*> plans;      // [ns], null for empty slices
+  uint32_t* order = nullptr;     // [nvis] slice-ordered position -> caller index
+  float2* vis = nullptr;         // [nvis] slice-ordered W V (gridding) or results (degridding)
+  float2* img = nullptr;         // [N N] one slice's image
+};
+
 namespace {
 
 int map_hip(hipError_t e) {
@@ -540,6 +554,86 @@ int batch_scratch(int njobs, hipStream_t s, BatchScratch** out) {
   return SEPW_OK;
 }
 
+void destroy_wstack(sepw_wstack_s* W) {
+  if (!W) return;
+  for (Plan* p : W->plans) destroy_plan(p);
+  dfree(W->order);
+  dfree(W->vis);
+  dfree(W->img);
+  delete W;
+}
+
+// Partition into slices (count, offsets, scatter with residual w), one plan
+// per non-empty slice.  Synchronises the stream (slice sizes come to the host).
+int wstack_build(sepw_wstack_s* W, Kernels* K, int ns, double w_lo, double w_hi, int64_t nvis,
+                 const double* u, const double* v, const double* w, int64_t* n_dropped,
+                 hipStream_t s) {
+  W->K = K;
+  W->ns = ns;
+  W->nvis = nvis;
+  W->centre.resize(ns);
+  for (int j = 0; j < ns; ++j) W->centre[j] = w_lo + ((j + 0.5) * (w_hi - w_lo)) / ns;
+  const double inv_ds = (double)ns / (w_hi - w_lo);
+  W->off.assign(ns + 1, 0);
+  W->plans.assign(ns, nullptr);
+  SEPW_TRY(dalloc(&W->order, std::max<int64_t>(nvis, 1)));
+  SEPW_TRY(dalloc(&W->vis, std::max<int64_t>(nvis, 1)));
+  SEPW_TRY(dalloc(&W->img, (int64_t)K->N * K->N));
+  uint32_t* count = nullptr;
+  double *cdev = nullptr, *us = nullptr, *vs = nullptr, *wsr = nullptr;
+  auto cleanup = [&]() {
+    dfree(count);
+    dfree(cdev);
+    dfree(us);
+    dfree(vs);
+    dfree(wsr);
+  };
+  auto run = [&]() -> int {
+    SEPW_TRY(dalloc(&count, ns));
+    SEPW_TRY(dalloc(&cdev, ns));
+    SEPW_TRY(dalloc(&us, std::max<int64_t>(nvis, 1)));
+    SEPW_TRY(dalloc(&vs, std::max<int64_t>(nvis, 1)));
+    SEPW_TRY(dalloc(&wsr, std::max<int64_t>(nvis, 1)));
+    SEPW_TRY(launch_fill_u32(count, 0u, ns, s));
+    SEPW_TRY(launch_slice_count(w, nvis, w_lo, inv_ds, ns, count, s));
+    std::vector<uint32_t> hc(ns);
+    SEPW_TRY(hipMemcpyAsync(hc.data(), count, sizeof(uint32_t) * ns, hipMemcpyDeviceToHost, s));
+    SEPW_TRY(hipStreamSynchronize(s));
+    std::vector<uint32_t> cur(ns);
+    for (int j = 0; j < ns; ++j) {
+      cur[j] = (uint32_t)W->off[j];
+      W->off[j + 1] = W->off[j] + hc[j];
+    }
+    SEPW_TRY(hipMemcpyAsync(count, cur.data(), sizeof(uint32_t) * ns, hipMemcpyHostToDevice, s));
+    SEPW_TRY(hipMemcpyAsync(cdev, W->centre.data(), sizeof(double) * ns, hipMemcpyHostToDevice, s));
+    SEPW_TRY(launch_slice_scatter(u, v, w, nvis, w_lo, inv_ds, ns, cdev, count, W->order, us, vs,
+                                  wsr, s));
+    int64_t dropped = 0;
+    for (int j = 0; j < ns; ++j) {
+      const int64_t n = W->off[j + 1] - W->off[j];
+      if (n == 0) continue;
+      sepw_plan_s* P = new (std::nothrow) sepw_plan_s();
+      if (!P) return SEPW_ERR_OOM;
+      W->plans[j] = P;
+      int rc = alloc_plan(K, n, P);
+      if (rc == SEPW_OK) rc = bin_plan(P, n, us + W->off[j], vs + W->off[j], wsr + W->off[j], s);
+      if (rc == SEPW_OK && n_dropped) {
+        int64_t d = 0;
+        rc = read_dropped(P, &d, s);
+        dropped += d;
+      }
+      if (rc != SEPW_OK) return rc;
+    }
+    if (n_dropped) *n_dropped = dropped;
+    // the plans hold their own bins: the slice-ordered coordinates can go
+    SEPW_TRY(hipStreamSynchronize(s));
+    return SEPW_OK;
+  };
+  const int rc = run();
+  cleanup();
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -941,6 +1035,91 @@ int sepw_free_kernels(sepw_kernels k) {
 int sepw_free_plan(sepw_plan p) {
   if (!p) return SEPW_ERR_ARG;
   destroy_plan(p);
+  return SEPW_OK;
+}
+
+int sepw_free_wstack(sepw_wstack ws) {
+  if (!ws) return SEPW_ERR_ARG;
+  destroy_wstack(ws);
+  return SEPW_OK;
+}
+
+int sepw_wstack_create(sepw_kernels k, int32_t n_slices, double w_lo, double w_hi, int64_t nvis,
+                       const double* u, const double* v, const double* w, int64_t* n_dropped,
+                       void* hip_stream, sepw_wstack* out) {
+  if (!out) return SEPW_ERR_ARG;
+  *out = nullptr;
+  if (!k || k->facet || n_slices < 1 || n_slices > kMaxSlices) return SEPW_ERR_ARG;
+  if (!std::isfinite(w_lo) || !std::isfinite(w_hi) || !(w_lo < w_hi)) return SEPW_ERR_ARG;
+  if (nvis < 0 || nvis > 2147483646LL) return SEPW_ERR_ARG;
+  if (nvis > 0 && (!u || !v || !w)) return SEPW_ERR_ARG;
+  // the kernels' planes must span the residual range [-h, h] of one slice
+  const double h = (w_hi - w_lo) / (2.0 * n_slices);
+  if (std::fabs(k->w_lo + h) > 1e-12 * h || std::fabs(k->w_hi - h) > 1e-12 * h)
+    return SEPW_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  sepw_wstack_s* W = new (std::nothrow) sepw_wstack_s();
+  if (!W) return SEPW_ERR_OOM;
+  int rc = wstack_build(W, k, n_slices, w_lo, w_hi, nvis, u, v, w, n_dropped, s);
+  if (rc != SEPW_OK) {
+    destroy_wstack(W);
+    return rc;
+  }
+  *out = W;
+  return SEPW_OK;
+}
+
+int sepw_wstack_grid(sepw_wstack ws, const sepw_c64* vis, const float* weight, sepw_c64* image_out,
+                     uint32_t flags, void* hip_stream) {
+  if (!ws || !image_out || (!vis && ws->nvis > 0)) return SEPW_ERR_ARG;
+  if ((flags & ~(SEPW_MUL_N | SEPW_DIV_N)) != 0) return SEPW_ERR_ARG;
+  if ((flags & SEPW_MUL_N) && (flags & SEPW_DIV_N)) return SEPW_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  Kernels* K = ws->K;
+  float2* out = reinterpret_cast<float2*>(image_out);
+  if (ws->nvis > 0) {
+    Stage st(SEPW_STAGE_GATHER, s);
+    SEPW_TRY(launch_slice_gather(reinterpret_cast<const float2*>(vis), weight, ws->order, ws->nvis,
+                                 ws->vis, s));
+  }
+  bool first = true;
+  for (int j = 0; j < ws->ns; ++j) {
+    if (!ws->plans[j]) continue;
+    int rc = sepw_grid(static_cast<sepw_plan_s*>(ws->plans[j]),
+                       reinterpret_cast<const sepw_c64*>(ws->vis + ws->off[j]), nullptr,
+                       reinterpret_cast<sepw_c64*>(ws->img), flags, hip_stream);
+    if (rc != SEPW_OK) return rc;
+    Stage st(SEPW_STAGE_CORRECT, s);
+    SEPW_TRY(launch_slice_phase(ws->img, out, K->N, K->fov, ws->centre[j], +1, !first, s));
+    first = false;
+  }
+  if (first) SEPW_TRY(launch_zero_c64(out, (int64_t)K->N * K->N, s));
+  return SEPW_OK;
+}
+
+int sepw_wstack_degrid(sepw_wstack ws, const sepw_c64* image, sepw_c64* vis_out, uint32_t flags,
+                       void* hip_stream) {
+  if (!ws || !image || (!vis_out && ws->nvis > 0)) return SEPW_ERR_ARG;
+  if ((flags & ~SEPW_DIV_N) != 0) return SEPW_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  Kernels* K = ws->K;
+  for (int j = 0; j < ws->ns; ++j) {
+    if (!ws->plans[j]) continue;
+    {
+      Stage st(SEPW_STAGE_CORRECT, s);
+      SEPW_TRY(launch_slice_phase(reinterpret_cast<const float2*>(image), ws->img, K->N, K->fov,
+                                  ws->centre[j], -1, false, s));
+    }
+    int rc = sepw_degrid(static_cast<sepw_plan_s*>(ws->plans[j]),
+                         reinterpret_cast<const sepw_c64*>(ws->img),
+                         reinterpret_cast<sepw_c64*>(ws->vis + ws->off[j]), flags, hip_stream);
+    if (rc != SEPW_OK) return rc;
+  }
+  if (ws->nvis > 0) {
+    Stage st(SEPW_STAGE_GATHER, s);
+    SEPW_TRY(launch_slice_return(ws->vis, ws->order, ws->nvis, reinterpret_cast<float2*>(vis_out),
+                                 s));
+  }
   return SEPW_OK;
 }
 

@@ -19,6 +19,7 @@ constexpr int kItemMinSlots = 64;  // range of the tunable item length
 constexpr int kItemMaxSlots = 8192;
 constexpr int kMaxRowBins = 4096;  // level-1 sort bins (rows of tiles, possibly grouped)
 constexpr int kL1Chunk = 10240;    // visibilities per workgroup in the level-1 passes
+constexpr int kMaxSlices = 4096;   // w-slices of the W-stacking hybrid
 constexpr int kGroupChunks = 8;    // level-1 chunks per group of the run-offset scan
 // placement word of a kept visibility: row bin << kPlaceShift | its position in
 // its chunk's bin-ordered staging (kDropped for dropped visibilities)
@@ -224,6 +225,21 @@ hipError_t launch_item_counts(const uint2* tdesc, int ntx, int nty, int r8, int 
                               uint32_t* nit, hipStream_t s);
 hipError_t launch_items(const uint2* tdesc, const uint32_t* itoff, int ntx, int nty, int r8,
                         int item_slots, int4* items, hipStream_t s);
+// W-stacking hybrid (wstack.hip): slice partition, movement and image phase
+hipError_t launch_slice_count(const double* w, int64_t nvis, double w_lo, double inv_ds, int ns,
+                              uint32_t* count, hipStream_t s);
+hipError_t launch_slice_scatter(const double* u, const double* v, const double* w, int64_t nvis,
+                                double w_lo, double inv_ds, int ns, const double* centre,
+                                uint32_t* cursor, uint32_t* order, double* us, double* vs,
+                                double* ws, hipStream_t s);
+hipError_t launch_slice_gather(const float2* vis, const float* weight, const uint32_t* order,
+                               int64_t nvis, float2* out, hipStream_t s);
+hipError_t launch_slice_return(const float2* in, const uint32_t* order, int64_t nvis, float2* out,
+                               hipStream_t s);
+// out (+)= in exp(sign 2 pi i w_s (n - 1)) over the N x N pixels
+hipError_t launch_slice_phase(const float2* in, float2* out, int N, double fov, double w_s,
+                              int sign, bool accumulate, hipStream_t s);
+
 hipError_t launch_bins_export(const uint2* rrec, const uint32_t* place, const uint32_t* delta,
                               int nbins, int64_t nvis, int tile_c, int ntx, int32_t* out,
                               hipStream_t s);

@@ -1,0 +1,116 @@
+"""GPU parity of the W-stacking hybrid (Section 4.3) against the oracle.
+
+The library's slices, residual-w plans, per-slice imaging and image-space
+phase are compared with oracle.wstack on the same seeded inputs: images over
+the inner half and predicted visibilities within the FP32 bound 1e-5
+(relative RMS), the adjoint identity within 1e-5, dropped counts exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import dev, inner, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1511_07152_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def _case(seed, N=64, n=2500, ns=5, w_lo=-2000.0, w_hi=2000.0, cells=25):
+    rng = np.random.default_rng(seed)
+    fov = math.radians(3.0)
+    d = dict(u=rng.uniform(-cells, cells, n) / fov, v=rng.uniform(-cells, cells, n) / fov,
+             w=rng.uniform(w_lo, w_hi, n), V=rng.standard_normal(n) + 1j * rng.standard_normal(n),
+             W=rng.uniform(0.5, 2.0, n), N=N, fov=fov, S=7, O=8, P=4, ns=ns, w_lo=w_lo, w_hi=w_hi)
+    return rng, d
+
+
+def _make(lib, d):
+    h = (d["w_hi"] - d["w_lo"]) / (2 * d["ns"])
+    K = lib.Kernels(d["N"], d["fov"], d["S"], d["O"], d["P"], -h, h)
+    ws = lib.WStack(K, d["ns"], d["w_lo"], d["w_hi"], dev(d["u"], torch.float64),
+                    dev(d["v"], torch.float64), dev(d["w"], torch.float64))
+    return K, ws
+
+
+def _args(d):
+    c1 = oracle.pswf.taper_c1(d["N"], d["fov"], d["S"])
+    return (d["N"], d["fov"], d["S"], d["O"], d["P"], d["ns"], d["w_lo"], d["w_hi"], c1)
+
+
+def test_wstack_image_matches_oracle(lib):
+    rng, d = _case(61)
+    K, ws = _make(lib, d)
+    img = ws.grid(dev(d["V"], torch.complex64), dev(d["W"], torch.float32), flags=lib.MUL_N)
+    want = oracle.wstack.image(d["u"], d["v"], d["w"], d["V"] * d["W"], *_args(d), n_power=1)
+    assert rel_rms(inner(img.cpu().numpy()), inner(want)) <= 1e-5
+
+
+def test_wstack_predict_matches_oracle(lib):
+    rng, d = _case(62)
+    K, ws = _make(lib, d)
+    X = np.zeros((d["N"], d["N"]), complex)
+    q = slice(d["N"] // 4, 3 * d["N"] // 4)
+    X[q, q] = rng.standard_normal((d["N"] // 2, d["N"] // 2))
+    V = ws.degrid(dev(X, torch.complex64), flags=lib.DIV_N).cpu().numpy()
+    want = oracle.wstack.predict(d["u"], d["v"], d["w"], X, *_args(d), n_power=-1)
+    assert rel_rms(V, want) <= 1e-5
+
+
+def test_wstack_grid_and_degrid_are_adjoint(lib):
+    rng, d = _case(63, ns=3)
+    K, ws = _make(lib, d)
+    y = d["V"]
+    # model on the inner half only: towards the edges 1 / (c1 c1) amplifies the
+    # FP32 rounding of the image far beyond the identity's scale (as in the
+    # plain path's adjoint test)
+    N = d["N"]
+    X = np.zeros((N, N), complex)
+    q = slice(N // 4, 3 * N // 4)
+    X[q, q] = rng.standard_normal((N // 2, N // 2)) + 1j * rng.standard_normal((N // 2, N // 2))
+    D = ws.grid(dev(y, torch.complex64), None, flags=lib.DIV_N).cpu().numpy().astype(complex)
+    V = ws.degrid(dev(X, torch.complex64), flags=lib.DIV_N).cpu().numpy().astype(complex)
+    lhs, rhs = np.vdot(X, D), np.vdot(V, y)
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(D) * np.linalg.norm(X)
+
+
+def test_wstack_dropped_count_and_empty_slices(lib):
+    # w only in two of eight slices; some footprints leave the grid
+    rng, d = _case(64, ns=8, cells=31)
+    d["w"] = np.where(rng.random(len(d["w"])) < 0.5, -1900.0, 1100.0) + rng.uniform(-50, 50, len(d["w"]))
+    K, ws = _make(lib, d)
+    q = oracle.wstack.bins(d["u"], d["v"], d["w"], d["N"], d["fov"], d["O"], d["S"], d["P"],
+                           d["ns"], d["w_lo"], d["w_hi"])
+    assert ws.n_dropped == int(q["dropped"].sum()) and ws.n_dropped > 0
+    img = ws.grid(dev(d["V"], torch.complex64), None).cpu().numpy()
+    want = oracle.wstack.image(d["u"], d["v"], d["w"], d["V"], *_args(d))
+    assert rel_rms(inner(img), inner(want)) <= 1e-5
+    V = ws.degrid(dev(want, torch.complex64)).cpu().numpy()
+    assert np.all(V[q["dropped"]] == 0)
+
+
+def test_wstack_arguments_checked(lib):
+    rng, d = _case(65, n=100)
+    h = (d["w_hi"] - d["w_lo"]) / (2 * d["ns"])
+    u, v, w = (dev(d[k], torch.float64) for k in ("u", "v", "w"))
+    wrong = lib.Kernels(d["N"], d["fov"], d["S"], d["O"], d["P"], -2 * h, 2 * h)
+    with pytest.raises(lib.SepwError):
+        lib.WStack(wrong, d["ns"], d["w_lo"], d["w_hi"], u, v, w)
+    K, ws = _make(lib, d)
+    with pytest.raises(lib.SepwError):
+        ws.grid(dev(d["V"], torch.complex64), None, flags=lib.GRID_ONLY)
+    z = torch.zeros(0, dtype=torch.float64, device="cuda")
+    empty = lib.WStack(K, d["ns"], d["w_lo"], d["w_hi"], z, z, z)
+    img = empty.grid(torch.zeros(0, dtype=torch.complex64, device="cuda"), None)
+    assert float(img.abs().max()) == 0.0

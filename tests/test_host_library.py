@@ -100,5 +100,10 @@ def test_null_handles_rejected(lib):
     assert lib.sepw_plan_set_item_slots(None, 256, None) == -1
     assert lib.sepw_plan_set_degrid_item_slots(None, 256, None) == -1
     assert lib.sepw_autotune_batched(0, None, None, None, None, None, None, None) == -1
+    assert lib.sepw_wstack_create(None, 4, -1.0, 1.0, 10, None, None, None, None, None,
+                                  ctypes.byref(h)) == -1
+    assert lib.sepw_wstack_grid(None, None, None, None, 0, None) == -1
+    assert lib.sepw_wstack_degrid(None, None, None, 0, None) == -1
+    assert lib.sepw_free_wstack(None) == -1
     assert lib.sepw_free_kernels(None) == -1 and lib.sepw_free_plan(None) == -1
     assert lib.sepw_strerror(-1) == b"invalid argument"
