@@ -15,7 +15,9 @@ One step is the whole hot path over that batch, through the C ABI:
 value = visibilities / step time (Mvis/s, gridded + degridded).
 
 Per-stage times come from HIP events the library records on its launch stream
-(sepw_timing_*); the roofline entry is for the dominant kernel.  The CPU
+(sepw_timing_*); the roofline entry is for the dominant kernel.  The other
+forms (FP16 / BF16 operands, the batched facet launch, the W-stacking hybrid)
+are reported beside the FP32 line, each with its error against the oracle.  The CPU
 baseline times the FP64 NumPy oracle on a bounded sample of the same workload.
 """
 import argparse
@@ -136,6 +138,64 @@ def accuracy_64(_lib, torch):
         e_vis = np.linalg.norm(Vp - ref_v) / np.linalg.norm(ref_v)
         out[prec] = {"image": float("%.3g" % e_img), "vis": float("%.3g" % e_vis)}
     return out
+
+
+def wstack_form(_lib, torch, d, u, v, w, V, W, model, steps):
+    """W-stacking hybrid (Section 4.3) on the array-scale workload: 16 uniform
+    w-slices over the same w range, 8 residual planes per slice (the plain
+    path's plane density), grid (x n) + degrid (/ n) per step; plus its parity
+    with the oracle on the 64^2 accuracy workload (4 slices, 2 residual planes)."""
+    import numpy as np
+
+    import oracle
+    from paper_1511_07152_amd import synth
+    N, fov, S, O = d["N"], d["fov"], d["S"], d["O"]
+    ns, P = 16, 8
+    h = (d["w_hi"] - d["w_lo"]) / (2 * ns)
+    K = _lib.Kernels(N, fov, S, O, P, -h, h)
+    t = time.perf_counter()
+    ws = _lib.WStack(K, ns, d["w_lo"], d["w_hi"], u, v, w)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t
+    img = torch.empty((N, N), dtype=torch.complex64, device="cuda")
+    vis_out = torch.empty(ws.nvis, dtype=torch.complex64, device="cuda")
+
+    def step():
+        ws.grid(V, W, flags=_lib.MUL_N, out=img)
+        ws.degrid(model, flags=_lib.DIV_N, out=vis_out)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    res = {"workload": "array-scale, %d w-slices x %d residual planes, S=%d, O=%d" % (ns, P, S, O),
+           "slices": ns, "residual_planes": P, "ms_per_step": round(ms, 3),
+           "Mvis_per_s": round(ws.nvis / (ms * 1e-3) / 1e6, 2), "create_s": round(t_create, 3)}
+    ws.close()
+    K.close()
+    # parity with the oracle at 64^2
+    a = synth.accuracy_64()
+    N2, fov2, S2, O2 = a["N"], a["fov"], a["S"], a["O"]
+    ns2, P2 = 4, 2
+    h2 = (a["w_hi"] - a["w_lo"]) / (2 * ns2)
+    dev = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x)).to("cuda", dt)  # noqa: E731
+    K2 = _lib.Kernels(N2, fov2, S2, O2, P2, -h2, h2)
+    ws2 = _lib.WStack(K2, ns2, a["w_lo"], a["w_hi"], dev(a["u"], torch.float64),
+                      dev(a["v"], torch.float64), dev(a["w"], torch.float64))
+    got = ws2.grid(dev(a["V"], torch.complex64), dev(a["W"], torch.float32),
+                   flags=_lib.MUL_N).cpu().numpy()
+    c1 = oracle.pswf.taper_c1(N2, fov2, S2)
+    want = oracle.wstack.image(a["u"], a["v"], a["w"], a["V"] * a["W"], N2, fov2, S2, O2, P2, ns2,
+                               a["w_lo"], a["w_hi"], c1, n_power=1)
+    q = slice(N2 // 4, 3 * N2 // 4)
+    res["rel_rms_err_image_64"] = float("%.3g" % (np.linalg.norm((got - want)[q, q])
+                                                  / np.linalg.norm(want[q, q])))
+    ws2.close()
+    K2.close()
+    return res
 
 
 def batching_form(_lib, torch, args):
@@ -300,6 +360,8 @@ def main():
 
     if not args.fp32_only:
         forms["batched_facets"] = batching_form(_lib, torch, args)
+        forms["w_stacking"] = wstack_form(_lib, torch, d, u, v, w, V, W, model, min(args.steps, 5))
+        log("w-stacking: %s" % forms["w_stacking"])
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mvis/s", "n_gpus": 1,
