@@ -28,8 +28,10 @@ by eye against the paper:
                  gradient through the gridding adjoint (Section 6, major cycles)
 * ``wstack``     W-stacking hybrid: w-slices corrected in image space, residual
                  w by separable W projection (Section 4.3)
+* ``correction`` the 2D correction table F_w - F~_w applied beside the
+                 separable GCF (Section 6)
 
 Readings of points the paper leaves open are documented at each function.
 """
 
-from . import geometry, pswf, tables, quantise, gridder, dft, phase_error, facet, imaging, chi2, wstack  # noqa: F401,E501
+from . import geometry, pswf, tables, quantise, gridder, dft, phase_error, facet, imaging, chi2, wstack, correction  # noqa: F401,E501
