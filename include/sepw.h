@@ -21,6 +21,9 @@
  *                      (Section 4.1 faceting, Section 4.2 snapshots)
  *   sepw_wstack_*      W-stacking hybrid: w-slices corrected in image space,
  *                      residual w by separable W projection (Section 4.3)
+ *   sepw_kernels_set_correction
+ *                      the 2D correction table F_w - F~_w applied beside the
+ *                      separable GCF by grid and degrid (Section 6)
  *
  * Conventions (the paper leaves these open; the library fixes them):
  *   N     grid and image size, even.           fov  full image width in
@@ -124,6 +127,37 @@ int sepw_make_kernels(const sepw_kernel_params* params, void* hip_stream, sepw_k
    layout [k][fi][s]; or the taper c1(l_p) into a device buffer of N doubles. */
 int sepw_kernels_table(sepw_kernels k, int32_t axis, sepw_c64* out, void* hip_stream);
 int sepw_kernels_taper(sepw_kernels k, double* out, void* hip_stream);
+
+/* Section 6 (the correction F_w - F~_w stored as a small full 2D table):
+ * attach to k a correction table with odd support Sc = support and
+ * oversampling Oc = oversample, or remove it (support = 0).  While attached,
+ * sepw_grid, sepw_degrid, sepw_grid_batched and the W-stacking calls on plans
+ * of k add, beside every separable footprint, the 2D footprint
+ *   y_i C[k_i][fu][fv][sv][su] at cell (cv_c - Sc/2 + sv, cu_c - Sc/2 + su)
+ * (degridding: its adjoint, the sum of G conj(C) over the same cells), where
+ *   C[k][fu][fv][su][sv] = (1/N^2) sum_{q,p} c1(l_p) c1(m_q)
+ *       [exp(2 pi i w_k (n - 1)) - exp(-2 pi i w_k (phi_u(l_p) + phi_v(m_q)))]
+ *       exp(-2 pi i [Du (p - N/2) + Dv (q - N/2)] / N),
+ *   phi(l) = a l^2 + b l^4 per axis, Du = su - Sc/2 - (fu - Oc/2)/Oc (Dv alike),
+ * i.e. the exact 2D table minus the outer product of the separable ones,
+ * sampled at the correction's own support and rate; and (cu_c, fu) is the
+ * point of the 1/Oc lattice nearest to the visibility's quantised position
+ * cu + (fi_u - O/2)/O, ties upwards (cu_c is cu or cu + 1).  With Sc = S and
+ * Oc = O gridding is then exactly gridding with the exact 2D GCF.  The table
+ * is generated now (FP64, stored complex64) and again by
+ * sepw_kernels_set_wrange; existing plans stay valid.  Synchronises the
+ * stream once (taper check).
+ * Errors: SEPW_ERR_ARG (null k; support even, negative or above S; oversample
+ * not a power of two or above O; support above S - 2 when 1 < oversample < O,
+ * where the coarse cell can be the next one), SEPW_ERR_UNSUPPORTED (facet
+ * kernels; a taper not symmetric about the image centre; (Sc/2) Oc + Oc/2
+ * above 63), SEPW_ERR_OOM, SEPW_ERR_HIP. */
+int sepw_kernels_set_correction(sepw_kernels k, int32_t support, int32_t oversample,
+                                void* hip_stream);
+/* Copy the attached correction table into a device buffer of P*Oc*Oc*Sc*Sc
+ * complex64, layout [k][fu][fv][sv][su] (su fastest).
+ * Errors: SEPW_ERR_ARG (null pointers, no correction attached), SEPW_ERR_HIP. */
+int sepw_kernels_correction_table(sepw_kernels k, sepw_c64* out, void* hip_stream);
 
 /* Quantise and bin nvis visibilities (u, v, w: DEVICE float64 arrays in
  * wavelengths, caller order).  In facet mode u, v are shifted by -w l0/n0,
@@ -268,6 +302,8 @@ enum {
   SEPW_STAGE_CORRECT,      /* taper / n correction, both directions */
   SEPW_STAGE_DEGRID,       /* degridding kernel                     */
   SEPW_STAGE_FILL,         /* zero fills of outputs                 */
+  SEPW_STAGE_CORR_TABLE,   /* correction table generation           */
+  SEPW_STAGE_CORR_APPLY,   /* correction passes of grid / degrid    */
   SEPW_NSTAGES
 };
 int sepw_timing_enable(int32_t on);

@@ -56,6 +56,8 @@ def load():
     lib.sepw_make_kernels.argtypes = [P(KernelParams), c_void_p, P(c_void_p)]
     lib.sepw_kernels_table.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
     lib.sepw_kernels_taper.argtypes = [c_void_p, c_void_p, c_void_p]
+    lib.sepw_kernels_set_correction.argtypes = [c_void_p, c_int32, c_int32, c_void_p]
+    lib.sepw_kernels_correction_table.argtypes = [c_void_p, c_void_p, c_void_p]
     lib.sepw_plan_create.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, c_void_p,
                                      P(c_int64), c_void_p, P(c_void_p)]
     lib.sepw_plan_bins.argtypes = [c_void_p, c_void_p, c_void_p]
@@ -90,7 +92,8 @@ def load():
                  "sepw_plan_rebin", "sepw_kernels_set_wrange", "sepw_timing_enable",
                  "sepw_timing_collect", "sepw_plan_set_item_slots", "sepw_plan_set_degrid_item_slots",
                  "sepw_autotune_batched", "sepw_wstack_create", "sepw_wstack_grid",
-                 "sepw_wstack_degrid", "sepw_free_wstack"):
+                 "sepw_wstack_degrid", "sepw_free_wstack", "sepw_kernels_set_correction",
+                 "sepw_kernels_correction_table"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -167,6 +170,23 @@ class Kernels:
         """sepw_kernels_set_wrange: regenerate the tables for a new w range."""
         _check(load().sepw_kernels_set_wrange(self._h, float(w_lo), float(w_hi), _stream()),
                "sepw_kernels_set_wrange")
+
+    def set_correction(self, support, oversample):
+        """sepw_kernels_set_correction: attach the 2D correction table F_w - F~_w
+        (support 0 removes it)."""
+        _check(load().sepw_kernels_set_correction(self._h, int(support), int(oversample), _stream()),
+               "sepw_kernels_set_correction")
+        self.corr = (int(support), int(oversample)) if support else None
+
+    def correction_table(self):
+        """The attached correction table, [P][Oc][Oc][Sc(v)][Sc(u)] complex64."""
+        if not getattr(self, "corr", None):
+            raise ValueError("no correction table attached")
+        Sc, Oc = self.corr
+        out = torch.empty((self.P, Oc, Oc, Sc, Sc), dtype=torch.complex64, device="cuda")
+        _check(load().sepw_kernels_correction_table(self._h, _ptr(out), _stream()),
+               "sepw_kernels_correction_table")
+        return out
 
     def taper(self):
         out = torch.empty(self.N, dtype=torch.float64, device="cuda")
@@ -316,7 +336,8 @@ class WStack:
             pass
 
 
-STAGES = ("tables", "quantise", "sort", "gather", "grid", "fft", "correct", "degrid", "fill")
+STAGES = ("tables", "quantise", "sort", "gather", "grid", "fft", "correct", "degrid", "fill",
+          "corr_table", "corr_apply")
 
 
 def timing_enable(on=True):

@@ -161,6 +161,8 @@ void destroy_kernels(Kernels* k) {
   dfree(k->pad_us);
   dfree(k->pad_vs);
   dfree(k->lp_bound);
+  dfree(k->corr);
+  dfree(k->corr_tmp);
   if (k->fft_ok) hipfftDestroy(k->fft);
   delete static_cast<sepw_kernels_s*>(k);
 }
@@ -222,7 +224,7 @@ int fft_exec(Kernels* K, float2* data, int direction, hipStream_t s) {
   return SEPW_OK;
 }
 
-hipError_t make_tables(Kernels* K, hipStream_t s) {
+hipError_t make_separable_tables(Kernels* K, hipStream_t s) {
   Stage st(SEPW_STAGE_TABLES, s);
   hipError_t e = launch_tables(K->c1, K->N, K->fov, K->P, K->O, K->S, K->w_lo, K->w_hi, K->a_u,
                                K->b_u, K->tab_u, s);
@@ -246,6 +248,52 @@ hipError_t make_tables(Kernels* K, hipStream_t s) {
     if (e == hipSuccess) e = launch_lp_bound(K->sc_u, K->sc_v, K->P, K->lp_bound, s);
   }
   return e;
+}
+
+hipError_t make_corr_table(Kernels* K, hipStream_t s) {
+  if (!K->corr) return hipSuccess;
+  Stage st(SEPW_STAGE_CORR_TABLE, s);
+  return launch_corr_tables(K->c1, K->N, K->fov, K->P, K->w_lo, K->w_hi, K->a_u, K->b_u, K->a_v,
+                            K->b_v, K->corr_S, K->corr_O, K->corr_nkb, K->corr_tmp, K->corr, s);
+}
+
+// every table of the kernel set for its current w range
+hipError_t make_tables(Kernels* K, hipStream_t s) {
+  hipError_t e = make_separable_tables(K, s);
+  if (e == hipSuccess) e = make_corr_table(K, s);
+  return e;
+}
+
+int ilog2(int x) {
+  int l = 0;
+  while ((1 << l) < x) ++l;
+  return l;
+}
+
+// Correction pass over one plan's work list (the correction table must exist).
+CorrArgs corr_args(const Plan* p, const WorkList& l, float2* grid, int checker) {
+  const Kernels* K = p->K;
+  CorrArgs a;
+  a.items = l.items;
+  a.nitems = l.itoff + 8 * p->r8;
+  a.tdesc = p->tdesc;
+  a.krec = p->krec;
+  a.yrow = p->yrow;
+  a.tab = K->corr;
+  a.g.O = K->O;
+  a.g.lo = ilog2(K->O);
+  a.g.Oc = K->corr_O;
+  a.g.lr = ilog2(K->O / K->corr_O);
+  a.g.Sc = K->corr_S;
+  a.g.hc = K->corr_S / 2;
+  a.g.T2 = K->corr_S * K->corr_S;
+  a.g.lt = ilog2(a.g.T2);
+  a.g.inv_sc = 1.0f / (float)K->corr_S;
+  a.N = K->N;
+  a.ntx = p->ntx;
+  a.checker = checker;
+  a.grid = grid;
+  return a;
 }
 
 int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K) {
@@ -695,6 +743,58 @@ int sepw_kernels_taper(sepw_kernels k, double* out, void* hip_stream) {
   return SEPW_OK;
 }
 
+int sepw_kernels_set_correction(sepw_kernels k, int32_t support, int32_t oversample,
+                                void* hip_stream) {
+  if (!k) return SEPW_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (support == 0) {
+    if (k->corr) SEPW_TRY(hipStreamSynchronize(s));
+    dfree(k->corr);
+    dfree(k->corr_tmp);
+    k->corr_S = k->corr_O = k->corr_nkb = 0;
+    return SEPW_OK;
+  }
+  if (support < 1 || support % 2 == 0 || support > k->S) return SEPW_ERR_ARG;
+  if (!is_pow2(oversample) || oversample > k->O) return SEPW_ERR_ARG;
+  // the footprint about the coarse cell (possibly the next cell) stays inside the separable one
+  if (oversample != k->O && oversample != 1 && support > k->S - 2) return SEPW_ERR_ARG;
+  if (corr_dmax(support, oversample) + 1 > kCorrMaxD) return SEPW_ERR_UNSUPPORTED;
+  if (k->facet) return SEPW_ERR_UNSUPPORTED;
+  // the generation folds the screen about the image centre: the taper must be symmetric
+  const int N = k->N;
+  std::vector<double> c1(N);
+  SEPW_TRY(hipMemcpyAsync(c1.data(), k->c1, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+  SEPW_TRY(hipStreamSynchronize(s));
+  for (int c = 1; c < N / 2; ++c)
+    if (c1[N / 2 + c] != c1[N / 2 - c]) return SEPW_ERR_UNSUPPORTED;
+  dfree(k->corr);
+  dfree(k->corr_tmp);
+  k->corr_S = k->corr_O = k->corr_nkb = 0;
+  // planes per generation batch: FP64 work space of at most 2^25 doubles beyond the weights
+  const int64_t one = corr_tmp_doubles(N, support, oversample, 1) - corr_tmp_doubles(N, support, oversample, 0);
+  int64_t nkb = ((int64_t)1 << 25) / std::max<int64_t>(one, 1);
+  nkb = std::max<int64_t>(1, std::min<int64_t>(nkb, k->P));
+  SEPW_TRY(dalloc(&k->corr, (int64_t)k->P * oversample * oversample * support * support));
+  hipError_t e = dalloc(&k->corr_tmp, corr_tmp_doubles(N, support, oversample, (int)nkb));
+  if (e != hipSuccess) {
+    dfree(k->corr);
+    return map_hip(e);
+  }
+  k->corr_S = support;
+  k->corr_O = oversample;
+  k->corr_nkb = (int)nkb;
+  SEPW_TRY(make_corr_table(k, s));
+  return SEPW_OK;
+}
+
+int sepw_kernels_correction_table(sepw_kernels k, sepw_c64* out, void* hip_stream) {
+  if (!k || !out || !k->corr) return SEPW_ERR_ARG;
+  const size_t n = (size_t)k->P * k->corr_O * k->corr_O * k->corr_S * k->corr_S;
+  SEPW_TRY(hipMemcpyAsync(out, k->corr, sizeof(float2) * n, hipMemcpyDeviceToDevice,
+                          static_cast<hipStream_t>(hip_stream)));
+  return SEPW_OK;
+}
+
 int sepw_plan_create(sepw_kernels k, int64_t nvis, const double* u, const double* v,
                      const double* w, int64_t* n_dropped, void* hip_stream, sepw_plan* out) {
   if (!out) return SEPW_ERR_ARG;
@@ -767,6 +867,10 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
       SEPW_TRY(launch_grid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->gl.max_items, s));
     }
   }
+  if (K->corr) {
+    Stage st(SEPW_STAGE_CORR_APPLY, s);
+    SEPW_TRY(launch_corr_grid(K->S, corr_args(p, p->gl, img, grid_only ? 0 : 1), p->gl.max_items, s));
+  }
   if (grid_only) return SEPW_OK;
   {
     Stage st(SEPW_STAGE_FFT, s);
@@ -821,6 +925,11 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
                      p->ntx, checker, p->yrow};
       SEPW_TRY(launch_degrid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->dl.max_items, s));
     }
+  }
+  if (K->corr) {
+    Stage st(SEPW_STAGE_CORR_APPLY, s);
+    SEPW_TRY(launch_corr_degrid(K->S, corr_args(p, p->dl, const_cast<float2*>(src), checker),
+                                p->dl.max_items, s));
   }
   {
     Stage st(SEPW_STAGE_GATHER, s);
@@ -899,6 +1008,13 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
     Stage st(SEPW_STAGE_GRID, s);
     SEPW_TRY(launch_job_prefix(bs->jobs, njobs, bs->first, bs->counter, s));
     SEPW_TRY(launch_grid_fp32_batched(S, bs->jobs, bs->first, njobs, bs->counter, bs->blocks, s));
+  }
+  for (int j = 0; j < njobs; ++j) {
+    Plan* p = plans[j];
+    if (!p->K->corr) continue;
+    Stage st(SEPW_STAGE_CORR_APPLY, s);
+    SEPW_TRY(launch_corr_grid(S, corr_args(p, p->gl, reinterpret_cast<float2*>(out[j]), grid_only ? 0 : 1),
+                              p->gl.max_items, s));
   }
   if (grid_only) return SEPW_OK;
   const int npow = (flags & SEPW_MUL_N) ? 1 : ((flags & SEPW_DIV_N) ? -1 : 0);

@@ -33,6 +33,7 @@
 // Lane layout of v_mfma_f32_16x16x4f32: lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; accumulator register r of lane l is D[4 (l / 16) + r][l % 16],
 // so region column x = l % 16 and region row y = 4 (l / 16) + r.
+#include "ring.h"
 #include "walk.h"
 
 namespace sepw {
@@ -42,10 +43,6 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 4;   // waves per workgroup of the cache-table and batched launches
-
-constexpr int kRing = 32;        // ring columns (power of two, >= 2 x 16)
-constexpr int kRingPitch = 34;   // complex entries per ring row (spreads LDS banks)
-constexpr int kRingFloats = 2 * 16 * kRingPitch;
 
 // Add the region sums (column x0 + col, rows 4 grp + r) into the ring.
 __device__ inline void ring_add(float* ring, const f32x4& re, const f32x4& im, int x0, int col,
@@ -58,33 +55,6 @@ __device__ inline void ring_add(float* ring, const f32x4& re, const f32x4& im, i
     v.x += re[r];
     v.y += im[r];
     *p = v;
-  }
-}
-
-// Flush ring columns [fx, fx + 16) (grid rows gy0 .. gy0 + 15) to the grid with
-// atomics and clear them.  Lane L takes float L % 32 of a 16-column row
-// segment (column (L % 32) / 2, real or imaginary part) of rows 2 k + L / 32.
-// All eight ring reads are issued before the first use; the lane's rows all
-// have the parity of gy0 + L / 32, so its checkerboard sign is computed once.
-__device__ inline void ring_flush16(float* ring, int fx, float* g, int gy0, int N, int checker,
-                                    int lane) {
-  const int f = lane & 31, half = lane >> 5;
-  const int gx = fx + (f >> 1);
-  const int slot = gx & (kRing - 1);
-  const bool col_ok = gx >= 0 && gx < N;
-  float* p = ring + 2 * (half * kRingPitch + slot) + (f & 1);   // row half, then 2 rows apart
-  float v[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) v[k] = p[4 * k * kRingPitch];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) p[4 * k * kRingPitch] = 0.f;
-  const float sg = (checker && ((gx + gy0 + half) & 1)) ? -1.f : 1.f;
-  float* gp = g + 2 * ((int64_t)(gy0 + half) * N + gx) + (f & 1);
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int gy = gy0 + 2 * k + half;
-    if (v[k] != 0.f && col_ok && gy >= 0 && gy < N)
-      unsafeAtomicAdd(gp + (int64_t)4 * k * N, sg * v[k]);
   }
 }
 

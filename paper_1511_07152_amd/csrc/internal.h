@@ -29,6 +29,7 @@ static_assert(kL1Chunk <= (1 << kPlaceShift), "chunk positions must fit the plac
 static_assert(((uint64_t)kMaxRowBins << kPlaceShift) < 0xFFFFFFFFull,
               "placement words must stay below kDropped");
 constexpr int kTargetRowBins = 2048;
+constexpr int kCorrMaxD = 64;      // correction table: max tap offset |d| (1/O_c cells) + 1
 
 // Padded tables: row length L = 32 - S holds the S taps of a table row at
 // offsets c - 1 .. c - 2 + S (c = 17 - S is the tile size) and zeros around
@@ -82,6 +83,11 @@ struct Kernels {
   hipfftHandle fft = 0;
   bool fft_ok = false;
   uint64_t generation = 0;     // bumped when the tables are regenerated
+  // correction table F_w - F~_w (0 support = none): [P][Oc][Oc][Sc][Sc] complex64,
+  // taps (sv, su) with su fastest; corr_tmp = FP64 work space of its generation
+  int corr_S = 0, corr_O = 0, corr_nkb = 0;
+  float2* corr = nullptr;
+  double* corr_tmp = nullptr;
 };
 
 // Tile slot record: padded-table bases of the visibility's u and v taps (tap
@@ -344,5 +350,41 @@ hipError_t launch_degrid_fp32(int S, const DegridArgs& a, int64_t max_items, int
 // out[q][p] = in[q][p] (-1)^(p+q) n(l0 + l_p, m0 + m_q)^npow / (c1[p] c1[q])
 hipError_t launch_correct(const float2* in, float2* out, const double* c1, int N, double fov,
                           double l0, double m0, int npow, hipStream_t s);
+
+// ---- correction table F_w - F~_w (corr_tables.hip, corr_apply.hip) ----
+// largest tap offset |d| in 1/Oc cells of an Sc-tap table
+int corr_dmax(int Sc, int Oc);
+// FP64 work space of the generation for nkb planes per batch
+int64_t corr_tmp_doubles(int N, int Sc, int Oc, int nkb);
+// out[k][fu][fv][sv][su] for all P planes (symmetric taper c1 required)
+hipError_t launch_corr_tables(const double* c1, int N, double fov, int P, double w_lo, double w_hi,
+                              double a_u, double b_u, double a_v, double b_v, int Sc, int Oc,
+                              int nkb, double* tmp, float2* out, hipStream_t s);
+
+struct CorrGeom {
+  int O, lo;        // oversampling of the separable tables and log2 O
+  int Oc, lr;       // correction oversampling and log2(O / Oc)
+  int Sc, hc, T2;   // correction support, Sc / 2, Sc^2
+  int lt;           // log2 of the lanes per visibility (Sc^2 rounded up to a power of two)
+  float inv_sc;     // 1 / Sc
+};
+
+// Correction passes over a plan's work items: gridding adds into grid (which
+// already holds the separable gridding), degridding adds into yrow (which
+// already holds the separable results).
+struct CorrArgs {
+  const int4* items;
+  const uint32_t* nitems;
+  const uint2* tdesc;
+  const SlotRec* krec;
+  float2* yrow;             // W V (gridding) or results (degridding), row-bin order
+  const float2* tab;        // correction table
+  CorrGeom g;
+  int N, ntx;
+  int checker;              // (-1)^(x+y) on grid values, as the separable kernels
+  float2* grid;             // gridding: output grid; degridding: input grid
+};
+hipError_t launch_corr_grid(int S, const CorrArgs& a, int64_t max_items, hipStream_t s);
+hipError_t launch_corr_degrid(int S, const CorrArgs& a, int64_t max_items, hipStream_t s);
 
 }  // namespace sepw

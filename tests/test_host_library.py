@@ -105,5 +105,8 @@ def test_null_handles_rejected(lib):
     assert lib.sepw_wstack_grid(None, None, None, None, 0, None) == -1
     assert lib.sepw_wstack_degrid(None, None, None, 0, None) == -1
     assert lib.sepw_free_wstack(None) == -1
+    assert lib.sepw_kernels_set_correction(None, 5, 8, None) == -1
+    assert lib.sepw_kernels_set_correction(None, 0, 0, None) == -1
+    assert lib.sepw_kernels_correction_table(None, None, None) == -1
     assert lib.sepw_free_kernels(None) == -1 and lib.sepw_free_plan(None) == -1
     assert lib.sepw_strerror(-1) == b"invalid argument"
