@@ -16,9 +16,10 @@ value = visibilities / step time (Mvis/s, gridded + degridded).
 
 Per-stage times come from HIP events the library records on its launch stream
 (sepw_timing_*); the roofline entry is for the dominant kernel.  The other
-forms (FP16 / BF16 operands, the batched facet launch, the W-stacking hybrid)
-are reported beside the FP32 line, each with its error against the oracle.  The CPU
-baseline times the FP64 NumPy oracle on a bounded sample of the same workload.
+forms (FP16 / BF16 operands, the batched facet launch, the W-stacking hybrid,
+the 2D correction table) are reported beside the FP32 line, each with its
+error against the oracle.  The CPU baseline times the FP64 NumPy oracle on a
+bounded sample of the same workload.
 """
 import argparse
 import json
@@ -198,6 +199,84 @@ def wstack_form(_lib, torch, d, u, v, w, V, W, model, steps):
     return res
 
 
+def correction_form(_lib, torch, d, u, v, w, V, W, model, steps, Sc=13, Oc=8):
+    """The correction table F_w - F~_w (Section 6) attached to the array-scale
+    kernels (S_c = 13, O_c = 8): its FP64 generation for the 128 planes, then
+    grid (x n) + degrid (/ n) per step with the correction passes; plus, on a
+    wide-field 64^2 case (fov 0.4, |w| <= 20, S = 15, 300 visibilities), the
+    GPU image's error against the exact DFT with and without the correction and
+    its parity with the oracle."""
+    import numpy as np
+
+    import oracle
+    N, fov, S, O, P = d["N"], d["fov"], d["S"], d["O"], d["P"]
+    K = _lib.Kernels(N, fov, S, O, P, d["w_lo"], d["w_hi"])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    K.set_correction(Sc, Oc)
+    torch.cuda.synchronize()
+    table_ms = (time.perf_counter() - t) * 1e3
+    plan = _lib.Plan(K, u, v, w)
+    img = torch.empty((N, N), dtype=torch.complex64, device="cuda")
+    vis_out = torch.empty(plan.nvis, dtype=torch.complex64, device="cuda")
+
+    def step():
+        _lib.grid(plan, V, W, flags=_lib.MUL_N, out=img)
+        _lib.degrid(plan, model, flags=_lib.DIV_N, out=vis_out)
+
+    step()
+    torch.cuda.synchronize()
+    _lib.timing_enable(True)
+    _lib.timing_collect()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    _lib.timing_enable(False)
+    st = _lib.timing_collect()
+    res = {"workload": "array-scale, correction S_c=%d O_c=%d beside S=%d O=%d, %d planes"
+                       % (Sc, Oc, S, O, P),
+           "table_generation_ms": round(table_ms, 2), "ms_per_step": round(ms, 3),
+           "Mvis_per_s": round(plan.nvis / (ms * 1e-3) / 1e6, 2),
+           "stages_ms_per_step": {k: round(v_ / steps, 4) for k, (v_, n) in st.items() if n}}
+    plan.close()
+    K.close()
+    # wide field at 64^2: error against the exact DFT, and oracle parity
+    n2, fov2, S2, O2, P2, wmax = 64, 0.4, 15, 8, 4, 20.0
+    rng = np.random.default_rng(3)
+    cells = n2 / 2 - S2
+    u2 = rng.uniform(-cells, cells, 300) / fov2
+    v2 = rng.uniform(-cells, cells, 300) / fov2
+    w2 = rng.uniform(-wmax, wmax, 300)
+    y2 = rng.standard_normal(300) + 1j * rng.standard_normal(300)
+    dev = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x)).to("cuda", dt)  # noqa: E731
+    K2 = _lib.Kernels(n2, fov2, S2, O2, P2, -wmax, wmax)
+    p2 = _lib.Plan(K2, dev(u2, torch.float64), dev(v2, torch.float64), dev(w2, torch.float64))
+    sep = _lib.grid(p2, dev(y2, torch.complex64)).cpu().numpy()
+    K2.set_correction(Sc, Oc)
+    cor = _lib.grid(p2, dev(y2, torch.complex64)).cpu().numpy()
+    c1 = oracle.pswf.taper_c1(n2, fov2, S2)
+    q = oracle.quantise.quantise(u2, v2, w2, n2, fov2, O2, S2, P2, -wmax, wmax, p2.tile_size)
+    wc = oracle.tables.w_plane_centres(P2, -wmax, wmax)
+    keep = ~q["dropped"]
+    uh, vh = oracle.quantise.dequantised(q, n2, fov2, O2)
+    ref = oracle.dft.dirty(uh[keep], vh[keep], wc[q["k"][keep]], y2[keep], n2, fov2,
+                           oracle.dft.phase_screen(n2, fov2, "exact"))
+    T = oracle.tables.separable_table(wc, n2, fov2, S2, O2, c1)
+    C = oracle.correction.correction_table(wc, n2, fov2, Sc, Oc, c1)
+    want = oracle.imaging.image_from_grid(oracle.correction.grid(q, y2, T, C, n2, S2, O2, Sc, Oc),
+                                          c1, fov2)
+    i = slice(n2 // 4, 3 * n2 // 4)
+    err = lambda a, b: float("%.3g" % (np.linalg.norm((a - b)[i, i]) / np.linalg.norm(b[i, i])))  # noqa: E731
+    res["wide_field_64"] = {"err_vs_exact_dft_separable": err(sep, ref),
+                            "err_vs_exact_dft_corrected": err(cor, ref),
+                            "rel_rms_err_vs_oracle": err(cor, want)}
+    p2.close()
+    K2.close()
+    return res
+
+
 def batching_form(_lib, torch, args):
     """36 image-plane facets (6 x 6 over 10 deg, 1024^2 each, S = 11, 64 planes,
     log-normal visibility counts): one persistent sepw_grid_batched launch (its
@@ -362,6 +441,9 @@ def main():
         forms["batched_facets"] = batching_form(_lib, torch, args)
         forms["w_stacking"] = wstack_form(_lib, torch, d, u, v, w, V, W, model, min(args.steps, 5))
         log("w-stacking: %s" % forms["w_stacking"])
+        forms["correction_table"] = correction_form(_lib, torch, d, u, v, w, V, W, model,
+                                                    min(args.steps, 5))
+        log("correction table: %s" % forms["correction_table"])
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mvis/s", "n_gpus": 1,

@@ -287,8 +287,9 @@ CorrArgs corr_args(const Plan* p, const WorkList& l, float2* grid, int checker) 
   a.g.Sc = K->corr_S;
   a.g.hc = K->corr_S / 2;
   a.g.T2 = K->corr_S * K->corr_S;
-  a.g.lt = ilog2(a.g.T2);
-  a.g.inv_sc = 1.0f / (float)K->corr_S;
+  // footprints about cell or (1 < Oc < O) cell + 1 of the tile's C cells
+  const bool may_move = K->corr_O != K->O && K->corr_O != 1;
+  a.g.win = (kRegion + 1 - K->S) + K->corr_S - (may_move ? 0 : 1);
   a.N = K->N;
   a.ntx = p->ntx;
   a.checker = checker;

@@ -13,16 +13,21 @@
 // items exactly like the separable kernels and decode everything from the
 // slot records (plane, sub-cell rows and position in the tile).
 //
-// Lane layout: the S_c^2 taps of a visibility occupy an aligned group of Tp
-// lanes (S_c^2 rounded up to a power of two): with Tp <= 64 one pass over the
-// wave covers 64 / Tp visibilities, with Tp > 64 a visibility takes Tp / 64
-// passes.  Table reads of a group are contiguous.
-// Gridding adds y_i C into the wave's LDS ring of grid columns with LDS float
-// atomics (taps of different visibilities of one pass can meet in a cell) and
-// flushes the ring to the grid as the separable kernel does.  Degridding
-// multiplies each tap's grid value by the conjugate table entry, sums the
-// group's lanes with butterflies and adds the sum to the visibility's result,
-// which the separable degridding kernel has already written.
+// Lane layout: every correction footprint of a tile's visibilities lies in a
+// W x W window of the tile's region (W = C + S_c, or C + S_c - 1 when the
+// coarse cell never moves), and each lane owns up to four fixed cells of that
+// window, as the matrix-core kernels own their accumulator cells.  The slot
+// records of a batch of up to 64 visibilities are decoded one per lane; then
+// the visibilities go through one at a time (their data broadcast from the
+// decoding lane with readlane), two at a time with all table loads issued
+// before the first use, and every lane handles the taps that fall on its
+// cells.  Gridding accumulates in registers and adds the window into the
+// wave's LDS ring of grid columns when the walk leaves the tile (each lane
+// its own cells, so no atomics), flushing the ring to the grid as the
+// separable kernel does.  Degridding loads the window from the grid once per
+// tile, multiplies each tap's value by the conjugate table entry, sums over
+// the wave with DPP row operations and adds the sum to the visibility's
+// result (already written by the separable degridding kernel) once per batch.
 #include "ring.h"
 #include "walk.h"
 
@@ -59,34 +64,109 @@ __device__ inline TapPos decode(const SlotRec& r, const CorrGeom& g) {
   return t;
 }
 
-__device__ inline int bperm_i(int src_lane, int v) {
-  return __builtin_amdgcn_ds_bpermute(src_lane << 2, v);
-}
-__device__ inline float bperm_f(int src_lane, float v) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute(src_lane << 2, __float_as_int(v)));
+constexpr int kUnroll = 2;   // visibilities whose table loads are in flight together (more costs occupancy)
+constexpr int kCells = 4;    // window cells per lane (W^2 <= 256)
+
+// x + (x of the lane the DPP control selects), disabled rows adding 0
+template <int CTRL, int ROWS>
+__device__ inline float dpp_add(float x) {
+  return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xF, true));
 }
 
-// Tap t of a group -> (sv, su); t < T2 <= 225, so the float quotient is exact.
-__device__ inline void tap_rc(int t, const CorrGeom& g, int& sv, int& su) {
-  sv = (int)(((float)t + 0.5f) * g.inv_sc);
-  su = t - sv * g.Sc;
+// Sum over the wave, ending in lane 63 (inclusive scans within rows of 16,
+// then row broadcasts).
+__device__ inline float wave_sum63(float x) {
+  x = dpp_add<0x111, 0xF>(x);   // row_shr:1
+  x = dpp_add<0x112, 0xF>(x);   // row_shr:2
+  x = dpp_add<0x114, 0xF>(x);   // row_shr:4
+  x = dpp_add<0x118, 0xF>(x);   // row_shr:8
+  x = dpp_add<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
+  x = dpp_add<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+  return x;
 }
 
-// Tiles of one work item: calls body(tx, c0, re) for the real slots [c0, re)
-// of each non-empty tile in order, and on_move(x0) before each tile after the first.
-template <int S, class Body, class Move>
-__device__ inline void walk_item(const int4& item, const uint2* tdesc, int ntx, int lane, Body&& body,
-                                 Move&& on_move) {
-  const int ty = uniform(item.x), s_end = uniform(item.z);
-  TileWalk tw;
-  tw.start(tdesc + (int64_t)ty * ntx, ntx, uniform(item.w), lane);
-  int c0 = uniform(item.y);
-  while (true) {
-    const int pe = min(tw.padded_end(), s_end);
-    body(tw.tx, c0, min(tw.real_end(), s_end));
-    if (pe >= s_end || !tw.next(lane)) break;
-    on_move(tw.tx);
-    c0 = tw.first_slot();
+// The lane's window cells: cell c = lane + 64 r, at (c % W, c / W).
+struct Cells {
+  int wx[kCells], wy[kCells];
+  bool ok[kCells];
+  __device__ void init(int lane, int W) {
+#pragma unroll
+    for (int r = 0; r < kCells; ++r) {
+      const int c = lane + 64 * r;
+      ok[r] = c < W * W;
+      wy[r] = c / W;
+      wx[r] = c - wy[r] * W;
+    }
+  }
+};
+
+// Per-visibility data of a batch, one visibility per lane: footprint origin in
+// window coordinates (column | row << 8), table block, and W V or result slot.
+struct VisData {
+  int pc, tb, a, b;
+};
+
+template <int S>
+__device__ inline VisData load_vis(const CorrArgs& args, int slot, bool with_y) {
+  const SlotRec r = args.krec[slot];
+  const TapPos t = decode<S>(r, args.g);
+  constexpr int H = S / 2;
+  const int wo = H - args.g.hc;   // window origin in region coordinates
+  VisData d;
+  d.pc = (t.col - wo) | ((t.row - wo) << 8);
+  d.tb = t.tb;
+  if (with_y) {
+    const float2 y = args.yrow[r.z];
+    d.a = __float_as_int(y.x);
+    d.b = __float_as_int(y.y);
+  } else {
+    d.a = r.z;
+    d.b = 0;
+  }
+  return d;
+}
+
+__device__ inline int rl(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+// Table taps of the group of kUnroll visibilities starting at v0 that fall on
+// the lane's window cells (cells r < R only; R is uniform).
+struct Group {
+  float2 cv[kUnroll][kCells];
+  bool in[kUnroll][kCells];
+};
+
+__device__ inline void fetch_group(const CorrArgs& a, const Cells& cl, int R, const VisData& mine,
+                                   int v0, int nb, Group& gr) {
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    const int v = min(v0 + u, nb - 1);
+    const int pc = rl(mine.pc, v), tb = rl(mine.tb, v);
+#pragma unroll
+    for (int r = 0; r < kCells; ++r) {
+      gr.in[u][r] = false;
+      if (r < R) {
+        const int su = cl.wx[r] - (pc & 0xFF), sv = cl.wy[r] - (pc >> 8);
+        gr.in[u][r] = cl.ok[r] && (unsigned)su < (unsigned)a.g.Sc && (unsigned)sv < (unsigned)a.g.Sc;
+        if (gr.in[u][r]) gr.cv[u][r] = a.tab[tb + sv * a.g.Sc + su];
+      }
+    }
+  }
+}
+
+// acc += y_v C over the group's taps on the lane's cells
+__device__ inline void accumulate(const Group& gr, const VisData& mine, int v0, int nb, int R,
+                                  float* acc_re, float* acc_im) {
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    const int v = min(v0 + u, nb - 1);
+    const float yr = v0 + u < nb ? __int_as_float(rl(mine.a, v)) : 0.f;
+    const float yi = v0 + u < nb ? __int_as_float(rl(mine.b, v)) : 0.f;
+#pragma unroll
+    for (int r = 0; r < kCells; ++r)
+      if (r < R && gr.in[u][r]) {
+        acc_re[r] += yr * gr.cv[u][r].x - yi * gr.cv[u][r].y;
+        acc_im[r] += yr * gr.cv[u][r].y + yi * gr.cv[u][r].x;
+      }
   }
 }
 
@@ -99,59 +179,87 @@ __global__ __launch_bounds__(64 * kCorrWaves) void corr_grid_kernel(CorrArgs a) 
   for (int i = lane; i < kRingFloats; i += 64) ring[i] = 0.f;
   float* grid = reinterpret_cast<float*>(a.grid);
   const CorrGeom g = a.g;
-  const int tp = 1 << g.lt;
+  const int wo = H - g.hc;
+  Cells cl;
+  cl.init(lane, g.win);
+  const int R = (g.win * g.win + 63) >> 6;   // window cells per lane in use
   const int n_items = (int)*a.nitems;
   int stride;
   for (int it = uniform(wave_items(kCorrWaves, &stride)); it < n_items; it += stride) {
     const int4 item = a.items[it];
-    const int by = uniform(item.x) * C - H;
-    int fx = uniform(item.w) * C - H;
-    walk_item<S>(
-        item, a.tdesc, a.ntx, lane,
-        [&](int tx, int c0, int re) {
-          const int x0 = tx * C - H;
-          for (int b0 = c0; b0 < re; b0 += 64) {
-            const int nb = min(64, re - b0);
-            TapPos mine{0, 0, 0};
-            float2 y = make_float2(0.f, 0.f);
-            if (lane < nb) {
-              const SlotRec r = a.krec[b0 + lane];
-              mine = decode<S>(r, g);
-              y = a.yrow[r.z];
-            }
-            const int passes = (nb * tp + 63) >> 6;
-            for (int p = 0; p < passes; ++p) {
-              const int f = (p << 6) + lane;
-              const int v = f >> g.lt, t = f & (tp - 1);
-              const int src = v & 63;
-              const int col = bperm_i(src, mine.col), row = bperm_i(src, mine.row);
-              const int tb = bperm_i(src, mine.tb);
-              const float yr = bperm_f(src, y.x), yi = bperm_f(src, y.y);
-              if (v < nb && t < g.T2) {
-                int sv, su;
-                tap_rc(t, g, sv, su);
-                const float2 cv = a.tab[tb + t];
-                float* cell = ring + 2 * ((row + sv) * kRingPitch + ((x0 + col + su) & (kRing - 1)));
-                atomicAdd(cell, yr * cv.x - yi * cv.y);
-                atomicAdd(cell + 1, yr * cv.y + yi * cv.x);
-              }
-            }
-          }
-        },
-        [&](int tx) {
-          // ring columns [fx, fx + kRing) hold the band; make room for [x0, x0 + 16)
-          const int x0 = tx * C - H;
-          if (x0 >= fx + kRing) {
-            ring_flush16(ring, fx, grid, by, a.N, a.checker, lane);
-            ring_flush16(ring, fx + 16, grid, by, a.N, a.checker, lane);
-            fx = x0;
-          } else if (x0 + 16 > fx + kRing) {
-            ring_flush16(ring, fx, grid, by, a.N, a.checker, lane);
-            fx += 16;
-          }
-        });
+    const int ty = uniform(item.x), s_end = uniform(item.z);
+    const int by = ty * C - H;
+    TileWalk tw;
+    tw.start(a.tdesc + (int64_t)ty * a.ntx, a.ntx, uniform(item.w), lane);
+    int fx = tw.tx * C - H;
+    int c0 = uniform(item.y);
+    float acc_re[kCells], acc_im[kCells];
+    while (true) {
+      const int x0 = tw.tx * C - H;
+      const int re = min(tw.real_end(), s_end), pe = min(tw.padded_end(), s_end);
+#pragma unroll
+      for (int r = 0; r < kCells; ++r) acc_re[r] = acc_im[r] = 0.f;
+      for (int b0 = c0; b0 < re; b0 += 64) {
+        const int nb = min(64, re - b0);
+        VisData mine{0, 0, 0, 0};
+        if (lane < nb) mine = load_vis<S>(a, b0 + lane, true);
+        for (int v0 = 0; v0 < nb; v0 += kUnroll) {
+          Group gr;
+          fetch_group(a, cl, R, mine, v0, nb, gr);
+          accumulate(gr, mine, v0, nb, R, acc_re, acc_im);
+        }
+      }
+      // bank the tile's window in the ring (each lane its own cells)
+#pragma unroll
+      for (int r = 0; r < kCells; ++r) {
+        if (r >= R || !cl.ok[r]) continue;
+        float2* p = reinterpret_cast<float2*>(ring) + (wo + cl.wy[r]) * kRingPitch +
+                    ((x0 + wo + cl.wx[r]) & (kRing - 1));
+        float2 o = *p;
+        o.x += acc_re[r];
+        o.y += acc_im[r];
+        *p = o;
+      }
+      if (pe >= s_end || !tw.next(lane)) break;
+      // ring columns [fx, fx + kRing) hold the band; make room for the next region
+      const int nx0 = tw.tx * C - H;
+      if (nx0 >= fx + kRing) {
+        ring_flush16(ring, fx, grid, by, a.N, a.checker, lane);
+        ring_flush16(ring, fx + 16, grid, by, a.N, a.checker, lane);
+        fx = nx0;
+      } else if (nx0 + 16 > fx + kRing) {
+        ring_flush16(ring, fx, grid, by, a.N, a.checker, lane);
+        fx += 16;
+      }
+      c0 = tw.first_slot();
+    }
     ring_flush16(ring, fx, grid, by, a.N, a.checker, lane);
     ring_flush16(ring, fx + 16, grid, by, a.N, a.checker, lane);
+  }
+}
+
+// Lane v0 + u of the batch receives sum over the wave of G conj(C) for its
+// visibility (each lane's cells of the window G).
+__device__ inline void reduce_group(const Group& gr, const float2* gw, int v0, int nb, int R,
+                                    int lane, float& res_re, float& res_im) {
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    if (v0 + u >= nb) break;
+    float pr = 0.f, pi = 0.f;
+#pragma unroll
+    for (int r = 0; r < kCells; ++r)
+      if (r < R && gr.in[u][r]) {
+        pr += gw[r].x * gr.cv[u][r].x + gw[r].y * gr.cv[u][r].y;
+        pi += gw[r].y * gr.cv[u][r].x - gw[r].x * gr.cv[u][r].y;
+      }
+    pr = wave_sum63(pr);
+    pi = wave_sum63(pi);
+    const float sr = __int_as_float(rl(__float_as_int(pr), 63));
+    const float si = __int_as_float(rl(__float_as_int(pi), 63));
+    if (lane == v0 + u) {
+      res_re = sr;
+      res_im = si;
+    }
   }
 }
 
@@ -160,64 +268,53 @@ __global__ __launch_bounds__(64 * kCorrWaves) void corr_degrid_kernel(CorrArgs a
   constexpr int C = 17 - S, H = S / 2;
   const int lane = threadIdx.x & 63;
   const CorrGeom g = a.g;
-  const int tp = 1 << g.lt;
-  const int gl = tp < 64 ? tp : 64;                 // lanes reduced together
-  const int pv = tp > 64 ? tp >> 6 : 1;             // passes per visibility
+  const int wo = H - g.hc;
+  Cells cl;
+  cl.init(lane, g.win);
+  const int R = (g.win * g.win + 63) >> 6;
   const int n_items = (int)*a.nitems;
   const float2* grid = a.grid;
   int stride;
   for (int it = uniform(wave_items(kCorrWaves, &stride)); it < n_items; it += stride) {
     const int4 item = a.items[it];
-    const int by = uniform(item.x) * C - H;
-    walk_item<S>(
-        item, a.tdesc, a.ntx, lane,
-        [&](int tx, int c0, int re) {
-          const int x0 = tx * C - H;
-          for (int b0 = c0; b0 < re; b0 += 64) {
-            const int nb = min(64, re - b0);
-            TapPos mine{0, 0, 0};
-            int z = 0;
-            if (lane < nb) {
-              const SlotRec r = a.krec[b0 + lane];
-              mine = decode<S>(r, g);
-              z = r.z;
-            }
-            const int passes = (nb * tp + 63) >> 6;
-            float sre = 0.f, sim = 0.f;
-            for (int p = 0; p < passes; ++p) {
-              const int f = (p << 6) + lane;
-              const int v = f >> g.lt, t = f & (tp - 1);
-              const int src = v & 63;
-              const int col = bperm_i(src, mine.col), row = bperm_i(src, mine.row);
-              const int tb = bperm_i(src, mine.tb);
-              if (v < nb && t < g.T2) {
-                int sv, su;
-                tap_rc(t, g, sv, su);
-                const int gx = x0 + col + su, gy = by + row + sv;
-                float2 gv = grid[(int64_t)gy * a.N + gx];
-                if (a.checker && ((gx + gy) & 1)) gv = make_float2(-gv.x, -gv.y);
-                const float2 cv = a.tab[tb + t];
-                sre += gv.x * cv.x + gv.y * cv.y;   // G conj(C)
-                sim += gv.y * cv.x - gv.x * cv.y;
-              }
-              if ((p + 1) % pv == 0) {
-                for (int o = gl >> 1; o > 0; o >>= 1) {
-                  sre += __shfl_xor(sre, o, 64);
-                  sim += __shfl_xor(sim, o, 64);
-                }
-                const int zv = bperm_i(src, z);
-                if ((lane & (gl - 1)) == 0 && v < nb) {
-                  float2* o = a.yrow + zv;
-                  const float2 old = *o;
-                  *o = make_float2(old.x + sre, old.y + sim);
-                }
-                sre = 0.f;
-                sim = 0.f;
-              }
-            }
-          }
-        },
-        [](int) {});
+    const int ty = uniform(item.x), s_end = uniform(item.z);
+    const int gy0 = ty * C - H + wo;     // grid row of window row 0
+    TileWalk tw;
+    tw.start(a.tdesc + (int64_t)ty * a.ntx, a.ntx, uniform(item.w), lane);
+    int c0 = uniform(item.y);
+    while (true) {
+      const int gx0 = tw.tx * C - H + wo;   // grid column of window column 0
+      const int re = min(tw.real_end(), s_end), pe = min(tw.padded_end(), s_end);
+      // the tile's window, signed for the centred transform (cells off the grid read 0)
+      float2 gw[kCells];
+#pragma unroll
+      for (int r = 0; r < kCells; ++r) {
+        const int gx = gx0 + cl.wx[r], gy = gy0 + cl.wy[r];
+        gw[r] = make_float2(0.f, 0.f);
+        if (r < R && cl.ok[r] && gx >= 0 && gx < a.N && gy >= 0 && gy < a.N) {
+          gw[r] = grid[(int64_t)gy * a.N + gx];
+          if (a.checker && ((gx + gy) & 1)) gw[r] = make_float2(-gw[r].x, -gw[r].y);
+        }
+      }
+      for (int b0 = c0; b0 < re; b0 += 64) {
+        const int nb = min(64, re - b0);
+        VisData mine{0, 0, 0, 0};
+        if (lane < nb) mine = load_vis<S>(a, b0 + lane, false);
+        float res_re = 0.f, res_im = 0.f;   // lane v: result of visibility v of the batch
+        for (int v0 = 0; v0 < nb; v0 += kUnroll) {
+          Group gr;
+          fetch_group(a, cl, R, mine, v0, nb, gr);
+          reduce_group(gr, gw, v0, nb, R, lane, res_re, res_im);
+        }
+        if (lane < nb) {
+          float2* o = a.yrow + mine.a;
+          const float2 old = *o;
+          *o = make_float2(old.x + res_re, old.y + res_im);
+        }
+      }
+      if (pe >= s_end || !tw.next(lane)) break;
+      c0 = tw.first_slot();
+    }
   }
 }
 

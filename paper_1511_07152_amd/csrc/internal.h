@@ -365,8 +365,7 @@ struct CorrGeom {
   int O, lo;        // oversampling of the separable tables and log2 O
   int Oc, lr;       // correction oversampling and log2(O / Oc)
   int Sc, hc, T2;   // correction support, Sc / 2, Sc^2
-  int lt;           // log2 of the lanes per visibility (Sc^2 rounded up to a power of two)
-  float inv_sc;     // 1 / Sc
+  int win;          // edge of the window holding a tile's correction footprints (<= 16)
 };
 
 // Correction passes over a plan's work items: gridding adds into grid (which
