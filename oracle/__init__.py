@@ -30,8 +30,10 @@ by eye against the paper:
                  w by separable W projection (Section 4.3)
 * ``correction`` the 2D correction table F_w - F~_w applied beside the
                  separable GCF (Section 6)
+* ``wsnap``      W snapshots: per-snapshot plane fit, residual w by separable
+                 W projection, image reprojection (Section 4.2)
 
 Readings of points the paper leaves open are documented at each function.
 """
 
-from . import geometry, pswf, tables, quantise, gridder, dft, phase_error, facet, imaging, chi2, wstack, correction  # noqa: F401,E501
+from . import geometry, pswf, tables, quantise, gridder, dft, phase_error, facet, imaging, chi2, wstack, correction, wsnap  # noqa: F401,E501
