@@ -17,9 +17,10 @@ value = visibilities / step time (Mvis/s, gridded + degridded).
 Per-stage times come from HIP events the library records on its launch stream
 (sepw_timing_*); the roofline entry is for the dominant kernel.  The other
 forms (FP16 / BF16 operands, the batched facet launch, the W-stacking hybrid,
-the 2D correction table) are reported beside the FP32 line, each with its
-error against the oracle.  The CPU baseline times the FP64 NumPy oracle on a
-bounded sample of the same workload.
+the 2D correction table, channel-shared coordinates, W snapshots) are
+reported beside the FP32 line, each with its error against the oracle.  The
+CPU baseline times the FP64 NumPy oracle on a bounded sample of the same
+workload.
 """
 import argparse
 import json
@@ -277,6 +278,116 @@ def correction_form(_lib, torch, d, u, v, w, V, W, model, steps, Sc=13, Oc=8):
     return res
 
 
+def channel_form(_lib, torch, d, u, v, w, V, W, model, steps):
+    """Channel-shared coordinates on the array-scale workload: the same step as
+    the FP32 line (tables, rebin, grid x n, degrid / n) with the plan rebinned
+    from uvw per (baseline, time) row in metres and the 16 channel
+    frequencies (24 / 16 B of coordinates per visibility instead of 24), and
+    the difference of its image from the per-visibility plan's."""
+    import numpy as np
+    N, fov, S, O, P = d["N"], d["fov"], d["S"], d["O"], d["P"]
+    uvw = torch.as_tensor(np.ascontiguousarray(d["uvw_m"])).to("cuda", torch.float64)
+    freq = torch.as_tensor(np.ascontiguousarray(d["freqs"])).to("cuda", torch.float64)
+    K = _lib.Kernels(N, fov, S, O, P, d["w_lo"], d["w_hi"])
+    plan = _lib.Plan.from_channels(K, uvw, freq)
+    img = torch.empty((N, N), dtype=torch.complex64, device="cuda")
+    vis_out = torch.empty(plan.nvis, dtype=torch.complex64, device="cuda")
+
+    def step():
+        K.set_wrange(d["w_lo"], d["w_hi"])
+        plan.rebin_channels(uvw, freq)
+        _lib.grid(plan, V, W, flags=_lib.MUL_N, out=img)
+        _lib.degrid(plan, model, flags=_lib.DIV_N, out=vis_out)
+
+    step()
+    torch.cuda.synchronize()
+    _lib.timing_enable(True)
+    _lib.timing_collect()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    _lib.timing_enable(False)
+    st = _lib.timing_collect()
+    ref_plan = _lib.Plan(K, u, v, w)
+    ref = _lib.grid(ref_plan, V, W, flags=_lib.MUL_N)
+    diff = float((torch.linalg.norm(img - ref) / torch.linalg.norm(ref)).item())
+    res = {"workload": "array-scale, uvw per row (%d rows x %d channels)"
+                       % (uvw.shape[0], freq.numel()),
+           "ms_per_step": round(ms, 3), "Mvis_per_s": round(plan.nvis / (ms * 1e-3) / 1e6, 2),
+           "quantise_ms": round(st["quantise"][0] / steps, 4),
+           "image_rel_diff_vs_per_visibility_plan": float("%.3g" % diff),
+           "dropped": plan.n_dropped, "dropped_per_visibility_plan": ref_plan.n_dropped}
+    ref_plan.close()
+    plan.close()
+    K.close()
+    return res
+
+
+def wsnap_form(_lib, torch, d, u, v, w, V, W, model, steps, n_snap=16, planes=16):
+    """W snapshots (Section 4.2) on the array-scale workload: 16 snapshots of
+    30 min (contiguous in the time-ordered data), a plane fitted per snapshot,
+    16 residual planes, grid (x n) + degrid (/ n) per step; plus parity with
+    the oracle on a 64^2 case whose five snapshots tilt by up to 2.5."""
+    import numpy as np
+
+    import oracle
+    N, fov, S, O = d["N"], d["fov"], d["S"], d["O"]
+    nvis = len(d["u"])
+    offs = [nvis * i // n_snap for i in range(n_snap + 1)]
+    K = _lib.Kernels(N, fov, S, O, planes, -1.0, 1.0)
+    t = time.perf_counter()
+    ws = _lib.WSnap(K, offs, u, v, w)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t
+    img = torch.empty((N, N), dtype=torch.complex64, device="cuda")
+    vis_out = torch.empty(nvis, dtype=torch.complex64, device="cuda")
+
+    def step():
+        ws.grid(V, W, flags=_lib.MUL_N, out=img)
+        ws.degrid(model, flags=_lib.DIV_N, out=vis_out)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    h = ws.plane(0)[1]
+    res = {"workload": "array-scale, %d snapshots x %d residual planes, S=%d, O=%d" % (n_snap, planes, S, O),
+           "ms_per_step": round(ms, 3), "Mvis_per_s": round(nvis / (ms * 1e-3) / 1e6, 2),
+           "create_s": round(t_create, 3), "residual_w_max": round(h, 2),
+           "full_w_max": round(float(d["w_hi"]), 2), "dropped": ws.n_dropped}
+    ws.close()
+    K.close()
+    # parity with the oracle at 64^2
+    rng = np.random.default_rng(64_000)
+    n2, fov2, S2, O2, P2, sizes = 64, 0.4, 7, 8, 4, (700, 0, 1, 900, 500)
+    cells = n2 / 2 - 6
+    parts = []
+    for n in sizes:
+        dd = rng.uniform(-2.5, 2.5, 2)
+        a = rng.uniform(-cells, cells, (2, n)) / fov2
+        parts.append((a[0], a[1], dd[0] * a[0] + dd[1] * a[1] + rng.normal(0, 2.0, n)))
+    u2, v2, w2 = (np.concatenate([p_[k] for p_ in parts]) for k in range(3))
+    y2 = rng.standard_normal(len(u2)) + 1j * rng.standard_normal(len(u2))
+    offs2 = [0] + list(np.cumsum(sizes))
+    dev = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x)).to("cuda", dt)  # noqa: E731
+    K2 = _lib.Kernels(n2, fov2, S2, O2, P2, -1.0, 1.0)
+    ws2 = _lib.WSnap(K2, offs2, dev(u2, torch.float64), dev(v2, torch.float64), dev(w2, torch.float64))
+    got = ws2.grid(dev(y2, torch.complex64), flags=_lib.MUL_N).cpu().numpy()
+    c1 = oracle.pswf.taper_c1(n2, fov2, S2)
+    want = oracle.wsnap.image(u2, v2, w2, y2, offs2, n2, fov2, S2, O2, P2, c1, n_power=1)
+    q = slice(n2 // 4, 3 * n2 // 4)
+    res["rel_rms_err_image_64"] = float("%.3g" % (np.linalg.norm((got - want)[q, q])
+                                                  / np.linalg.norm(want[q, q])))
+    ws2.close()
+    K2.close()
+    return res
+
+
 def batching_form(_lib, torch, args):
     """36 image-plane facets (6 x 6 over 10 deg, 1024^2 each, S = 11, 64 planes,
     log-normal visibility counts): one persistent sepw_grid_batched launch (its
@@ -444,6 +555,10 @@ def main():
         forms["correction_table"] = correction_form(_lib, torch, d, u, v, w, V, W, model,
                                                     min(args.steps, 5))
         log("correction table: %s" % forms["correction_table"])
+        forms["channel_shared"] = channel_form(_lib, torch, d, u, v, w, V, W, model, args.steps)
+        log("channel-shared coordinates: %s" % forms["channel_shared"])
+        forms["w_snapshots"] = wsnap_form(_lib, torch, d, u, v, w, V, W, model, min(args.steps, 5))
+        log("w-snapshots: %s" % forms["w_snapshots"])
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mvis/s", "n_gpus": 1,

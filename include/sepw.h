@@ -10,6 +10,8 @@
  *                      anti-aliasing taper c; Section 4.1, facet tables)
  *   sepw_plan_create   uv -> grid cell and 1/O sub-cell offset, w -> plane,
  *                      counting sort of visibilities into grid tiles
+ *                      (sepw_plan_create_channels: uvw in metres per row,
+ *                      scaled per channel)
  *   sepw_grid          visibilities -> uv grid -> dirty image (Section 2,
  *                      dirty-image equation and its W-projection form;
  *                      Section 5, separable update with the row product reused)
@@ -21,6 +23,8 @@
  *                      (Section 4.1 faceting, Section 4.2 snapshots)
  *   sepw_wstack_*      W-stacking hybrid: w-slices corrected in image space,
  *                      residual w by separable W projection (Section 4.3)
+ *   sepw_wsnap_*       W snapshots: per-snapshot plane fit, residual w by
+ *                      separable W projection, image reprojection (Section 4.2)
  *   sepw_kernels_set_correction
  *                      the 2D correction table F_w - F~_w applied beside the
  *                      separable GCF by grid and degrid (Section 6)
@@ -64,6 +68,7 @@ typedef struct { float re, im; } sepw_c64;
 typedef struct sepw_kernels_s* sepw_kernels;   /* tables + taper + FFT plan   */
 typedef struct sepw_plan_s*    sepw_plan;       /* binned uvw for one kernels  */
 typedef struct sepw_wstack_s*  sepw_wstack;     /* W-stacking slices + plans   */
+typedef struct sepw_wsnap_s*   sepw_wsnap;      /* W-snapshot planes + plans   */
 
 enum {
   SEPW_OK = 0,
@@ -180,6 +185,26 @@ int sepw_plan_create(sepw_kernels k, int64_t nvis, const double* u, const double
  * range, null arrays with nvis > 0), SEPW_ERR_HIP. */
 int sepw_plan_rebin(sepw_plan p, int64_t nvis, const double* u, const double* v, const double* w,
                     int64_t* n_dropped, void* hip_stream);
+
+/* Channel-shared coordinates: the plan of nrows * nchan visibilities whose
+ * u, v, w are given once per (baseline, time) row in metres and scaled per
+ * channel, visibility i = row * nchan + ch (caller order of vis, weight and
+ * results) at
+ *   u_i = uvw[row][0] * (freq[ch] / c),   c = 299,792,458 m/s,
+ * (likewise v, w) -- one IEEE division, then one IEEE multiplication, so the
+ * bins equal those of sepw_plan_create on u, v, w formed that way.  Section 2
+ * works in wavelengths; this layout reads 24 / nchan bytes of coordinates per
+ * visibility instead of 24.  uvw: DEVICE float64 [nrows][3]; freq: DEVICE
+ * float64 [nchan] in Hz.  Everything else as sepw_plan_create /
+ * sepw_plan_rebin (facet mode included).
+ * Errors: SEPW_ERR_ARG (null pointers, nrows < 0, nchan < 1, nrows * nchan
+ * above 2^31 - 2 or, for rebin, above the plan's capacity), and those of
+ * sepw_plan_create. */
+int sepw_plan_create_channels(sepw_kernels k, int64_t nrows, int32_t nchan, const double* uvw,
+                              const double* freq, int64_t* n_dropped, void* hip_stream,
+                              sepw_plan* out);
+int sepw_plan_rebin_channels(sepw_plan p, int64_t nrows, int32_t nchan, const double* uvw,
+                             const double* freq, int64_t* n_dropped, void* hip_stream);
 
 /* Per-visibility bins in caller order, for verification: out is a DEVICE
    int32 array [nvis][7] = (cell_u, fi_u, cell_v, fi_v, plane, tile, dropped);
@@ -312,6 +337,42 @@ int sepw_timing_collect(double* ms, int64_t* n);
 int sepw_free_kernels(sepw_kernels k);
 int sepw_free_plan(sepw_plan p);
 int sepw_free_wstack(sepw_wstack ws);
+
+/* W snapshots (Section 4.2).  The caller's visibilities form n_snap snapshots,
+ * contiguous in caller order: snapshot s is [offsets[s], offsets[s + 1])
+ * (offsets: HOST int64 [n_snap + 1], offsets[0] = 0, non-decreasing; empty
+ * snapshots allowed; u, v, w: DEVICE float64 [offsets[n_snap]] in
+ * wavelengths).  Per snapshot the plane w ~ d_u u + d_v v is fitted by least
+ * squares through the origin over its visibilities with finite u, v, w (by
+ * Cramer's rule on Suu, Suv, Svv, Suw, Svw; d0 = 0 unless det > 1e-12 Suu Svv),
+ * and the snapshot is binned on its residual w' = w - (d_u u + d_v v) into the
+ * P planes of k, whose w range create sets to [-h, h], h = max |w'| (1 + 2^-20)
+ * (1 if every w' is 0; k's tables are regenerated, so plans made earlier from
+ * k become invalid).  Synchronises the stream.
+ * sepw_wsnap_grid: image_out (DEVICE complex64 [N N]) = sum over snapshots of
+ *   R_s[F+[G_s] / (c1 c1)], times n (SEPW_MUL_N) or over n (SEPW_DIV_N), where
+ *   G_s is the snapshot's separable gridding on w' and R_s the reprojection:
+ *   output pixel l takes the snapshot image at l^s = l + d0 (n(l) - 1),
+ *   sampled at pixel x = l^s N / fov + N/2 (y alike) by separable cubic
+ *   convolution (Keys, a = -1/2) over the 4 x 4 nearest pixels, pixels off the
+ *   image counting 0.
+ * sepw_wsnap_degrid: its adjoint: per snapshot the transposed reprojection of
+ *   image (times 1/n with SEPW_DIV_N), then separable degridding on w' into
+ *   vis_out (DEVICE complex64 [nvis], caller order).
+ * sepw_wsnap_plane: d0 (host double[2]) of a snapshot and h (host, may be NULL).
+ * Errors: SEPW_ERR_ARG (null pointers, n_snap outside [1, 2^20], offsets not
+ * starting at 0 or decreasing, more than 2^31 - 2 visibilities, flags other
+ * than the n flags (grid) or SEPW_DIV_N (degrid)), SEPW_ERR_UNSUPPORTED (facet
+ * kernels), SEPW_ERR_NO_DEVICE, SEPW_ERR_OOM, SEPW_ERR_HIP, SEPW_ERR_FFT. */
+int sepw_wsnap_create(sepw_kernels k, int32_t n_snap, const int64_t* offsets, const double* u,
+                      const double* v, const double* w, int64_t* n_dropped, void* hip_stream,
+                      sepw_wsnap* out);
+int sepw_wsnap_grid(sepw_wsnap ws, const sepw_c64* vis, const float* weight, sepw_c64* image_out,
+                    uint32_t flags, void* hip_stream);
+int sepw_wsnap_degrid(sepw_wsnap ws, const sepw_c64* image, sepw_c64* vis_out, uint32_t flags,
+                      void* hip_stream);
+int sepw_wsnap_plane(sepw_wsnap ws, int32_t snapshot, double* d0, double* h);
+int sepw_free_wsnap(sepw_wsnap ws);
 const char* sepw_strerror(int code);
 int32_t sepw_device_count(void);   /* 0 when no HIP device is visible */
 

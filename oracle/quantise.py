@@ -24,6 +24,20 @@ the readings used here are:
 import numpy as np
 
 
+SPEED_OF_LIGHT = 299792458.0   # m/s
+
+
+def channel_coordinates(uvw_m, freq_hz):
+    """u, v, w in wavelengths (Section 2's units) of every (row, channel) pair,
+    row-major (visibility row * nchan + ch): u = u_m * (f / c), the division
+    first and then the multiplication, each one IEEE double operation (the
+    reading that makes a channel-shared layout reproduce the same bins)."""
+    uvw_m = np.asarray(uvw_m, np.float64).reshape(-1, 3)
+    scale = np.asarray(freq_hz, np.float64) / np.float64(SPEED_OF_LIGHT)   # [nchan]
+    out = uvw_m[:, None, :] * scale[None, :, None]                          # [row][ch][3]
+    return out[..., 0].ravel(), out[..., 1].ravel(), out[..., 2].ravel()
+
+
 def plane_index(w, P, w_lo, w_hi):
     inv_dw = np.float64(P) / (np.float64(w_hi) - np.float64(w_lo))
     with np.errstate(invalid='ignore'):

@@ -61,6 +61,10 @@ def load():
     lib.sepw_plan_create.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, c_void_p,
                                      P(c_int64), c_void_p, P(c_void_p)]
     lib.sepw_plan_bins.argtypes = [c_void_p, c_void_p, c_void_p]
+    lib.sepw_plan_create_channels.argtypes = [c_void_p, c_int64, c_int32, c_void_p, c_void_p,
+                                              P(c_int64), c_void_p, P(c_void_p)]
+    lib.sepw_plan_rebin_channels.argtypes = [c_void_p, c_int64, c_int32, c_void_p, c_void_p,
+                                             P(c_int64), c_void_p]
     lib.sepw_plan_rebin.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, P(c_int64),
                                     c_void_p]
     lib.sepw_kernels_set_wrange.argtypes = [c_void_p, c_double, c_double, c_void_p]
@@ -81,6 +85,12 @@ def load():
                                      c_void_p]
     lib.sepw_wstack_degrid.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.c_uint32, c_void_p]
     lib.sepw_free_wstack.argtypes = [c_void_p]
+    lib.sepw_wsnap_create.argtypes = [c_void_p, c_int32, P(c_int64), c_void_p, c_void_p, c_void_p,
+                                      P(c_int64), c_void_p, P(c_void_p)]
+    lib.sepw_wsnap_grid.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_uint32, c_void_p]
+    lib.sepw_wsnap_degrid.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.c_uint32, c_void_p]
+    lib.sepw_wsnap_plane.argtypes = [c_void_p, c_int32, P(c_double), P(c_double)]
+    lib.sepw_free_wsnap.argtypes = [c_void_p]
     lib.sepw_free_kernels.argtypes = [c_void_p]
     lib.sepw_free_plan.argtypes = [c_void_p]
     lib.sepw_strerror.argtypes = [ctypes.c_int]
@@ -93,7 +103,9 @@ def load():
                  "sepw_timing_collect", "sepw_plan_set_item_slots", "sepw_plan_set_degrid_item_slots",
                  "sepw_autotune_batched", "sepw_wstack_create", "sepw_wstack_grid",
                  "sepw_wstack_degrid", "sepw_free_wstack", "sepw_kernels_set_correction",
-                 "sepw_kernels_correction_table"):
+                 "sepw_kernels_correction_table", "sepw_plan_create_channels",
+                 "sepw_plan_rebin_channels", "sepw_wsnap_create", "sepw_wsnap_grid",
+                 "sepw_wsnap_degrid", "sepw_wsnap_plane", "sepw_free_wsnap"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -229,6 +241,40 @@ class Plan:
     def handle(self):
         return self._h
 
+    @classmethod
+    def from_channels(cls, kernels, uvw, freq, count_dropped=True):
+        """sepw_plan_create_channels: uvw [nrows][3] in metres (float64), freq
+        [nchan] in Hz (float64); visibility i = row * nchan + ch."""
+        lib = load()
+        uvw = _dev(uvw, torch.float64, "uvw")
+        freq = _dev(freq, torch.float64, "freq")
+        if uvw.dim() != 2 or uvw.shape[1] != 3:
+            raise ValueError("uvw must be [nrows][3]")
+        self = cls.__new__(cls)
+        self.kernels = kernels
+        self.nvis = uvw.shape[0] * freq.numel()
+        nd = c_int64(-1)
+        h = c_void_p()
+        _check(lib.sepw_plan_create_channels(kernels.handle, uvw.shape[0], freq.numel(), _ptr(uvw),
+                                             _ptr(freq), ctypes.byref(nd) if count_dropped else None,
+                                             _stream(), ctypes.byref(h)), "sepw_plan_create_channels")
+        self._h = h
+        self.n_dropped = nd.value if count_dropped else None
+        return self
+
+    def rebin_channels(self, uvw, freq, count_dropped=False):
+        """sepw_plan_rebin_channels: bin a new batch of channel-shared rows."""
+        uvw = _dev(uvw, torch.float64, "uvw")
+        freq = _dev(freq, torch.float64, "freq")
+        nd = c_int64(-1)
+        _check(load().sepw_plan_rebin_channels(self._h, uvw.shape[0], freq.numel(), _ptr(uvw),
+                                               _ptr(freq), ctypes.byref(nd) if count_dropped else None,
+                                               _stream()), "sepw_plan_rebin_channels")
+        self.nvis = uvw.shape[0] * freq.numel()
+        if count_dropped:
+            self.n_dropped = nd.value
+        return self
+
     @property
     def tile_size(self):
         return load().sepw_plan_tile_size(self._h)
@@ -358,6 +404,67 @@ def make_kernels(*args, **kwargs):
 
 def plan_create(kernels, u, v, w):
     return Plan(kernels, u, v, w)
+
+
+class WSnap:
+    """sepw_wsnap_create: W snapshots over contiguous snapshots of the caller's
+    visibilities (offsets: n_snap + 1 host integers); ``kernels`` get the
+    residual w range."""
+
+    def __init__(self, kernels, offsets, u, v, w, count_dropped=True):
+        lib = load()
+        u = _dev(u, torch.float64, "u")
+        v = _dev(v, torch.float64, "v")
+        w = _dev(w, torch.float64, "w")
+        offs = (c_int64 * len(offsets))(*[int(x) for x in offsets])
+        self.kernels = kernels
+        self.n_snap = len(offsets) - 1
+        self.offsets = [int(x) for x in offsets]
+        self.nvis = self.offsets[-1]
+        nd = c_int64(-1)
+        h = c_void_p()
+        _check(lib.sepw_wsnap_create(kernels.handle, self.n_snap, offs, _ptr(u), _ptr(v), _ptr(w),
+                                     ctypes.byref(nd) if count_dropped else None, _stream(),
+                                     ctypes.byref(h)), "sepw_wsnap_create")
+        self._h = h
+        self.n_dropped = nd.value if count_dropped else None
+
+    def plane(self, s):
+        """(d_u, d_v) of snapshot s and the residual range h."""
+        d = (c_double * 2)()
+        h = c_double()
+        _check(load().sepw_wsnap_plane(self._h, int(s), d, ctypes.byref(h)), "sepw_wsnap_plane")
+        return (d[0], d[1]), h.value
+
+    def grid(self, vis, weight=None, flags=0, out=None):
+        vis = _dev(vis, torch.complex64, "vis")
+        if weight is not None:
+            weight = _dev(weight, torch.float32, "weight")
+        N = self.kernels.N
+        if out is None:
+            out = torch.empty((N, N), dtype=torch.complex64, device="cuda")
+        _check(load().sepw_wsnap_grid(self._h, _ptr(vis), _ptr(weight), _ptr(out), flags, _stream()),
+               "sepw_wsnap_grid")
+        return out
+
+    def degrid(self, image, flags=0, out=None):
+        image = _dev(image, torch.complex64, "image")
+        if out is None:
+            out = torch.empty(self.nvis, dtype=torch.complex64, device="cuda")
+        _check(load().sepw_wsnap_degrid(self._h, _ptr(image), _ptr(out), flags, _stream()),
+               "sepw_wsnap_degrid")
+        return out
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            load().sepw_free_wsnap(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def grid(plan, vis, weight=None, flags=0, out=None):

@@ -35,6 +35,19 @@ struct sepw_wstack_s {
   float2* img = nullptr;         // [N N] one slice's image
 };
 
+// W snapshots (Section 4.2): per snapshot (a contiguous range of the caller's
+// visibilities) its fitted plane d0 and a plan over its residual w.
+struct sepw_wsnap_s {
+  Kernels* K = nullptr;
+  int ns = 0;
+  int64_t nvis = 0;
+  std::vector<int64_t> off;      // [ns + 1]
+  std::vector<double> d0;        // [2 ns]
+  std::vector<Plan*> plans;      // [ns], null for empty snapshots
+  double h = 0.0;                // residual w range [-h, h]
+  float2* img = nullptr;         // [N N] one snapshot's image
+};
+
 namespace {
 
 int map_hip(hipError_t e) {
@@ -206,6 +219,8 @@ QuantGeom make_geom(const Kernels* K, int tile_c, int ntx) {
   g.N = K->N;
   g.S = K->S;
   g.O = K->O;
+  g.lo = 0;
+  while ((1 << g.lo) < K->O) ++g.lo;
   g.P = K->P;
   g.tile_c = tile_c;
   g.ntx = ntx;
@@ -498,16 +513,22 @@ int set_list_slots(Plan* p, WorkList& l, int32_t slots, hipStream_t s) {
 }
 
 // Quantise, sort and build the work list for nvis <= capacity visibilities.
-int bin_plan(Plan* P, int64_t nvis, const double* u, const double* v, const double* w,
-             hipStream_t s) {
+Coords plain_coords(const double* u, const double* v, const double* w) {
+  Coords c;
+  c.u = u;
+  c.v = v;
+  c.w = w;
+  return c;
+}
+
+int bin_plan(Plan* P, int64_t nvis, const Coords& src, hipStream_t s) {
   Kernels* K = P->K;
   P->nvis = nvis;
   const QuantGeom g = make_geom(K, P->tile_c, P->ntx);
   P->generation = K->generation;
   {
     Stage st(SEPW_STAGE_QUANTISE, s);
-    SEPW_TRY(launch_quantise_rows(u, v, w, nvis, g, P->rshift, P->nbins, P->rbin, P->qrec,
-                                  P->chist, s));
+    SEPW_TRY(launch_quantise_rows(src, nvis, g, P->rshift, P->nbins, P->rbin, P->qrec, P->chist, s));
   }
   {
     Stage st(SEPW_STAGE_SORT, s);
@@ -525,7 +546,7 @@ int bin_plan(Plan* P, int64_t nvis, const double* u, const double* v, const doub
                              P->ntx, P->nty, P->tile_c, K->O, K->S, (uint32_t)P->capacity,
                              P->binperm, P->tdesc, P->krec, s));
     SEPW_TRY(build_items(P, s));
-    if (K->facet) SEPW_TRY(launch_rotation(u, v, w, nvis, g, P->rot, s));
+    if (K->facet) SEPW_TRY(launch_rotation(src, nvis, g, P->rot, s));
   }
   return SEPW_OK;
 }
@@ -665,7 +686,7 @@ int wstack_build(sepw_wstack_s* W, Kernels* K, int ns, double w_lo, double w_hi,
       if (!P) return SEPW_ERR_OOM;
       W->plans[j] = P;
       int rc = alloc_plan(K, n, P);
-      if (rc == SEPW_OK) rc = bin_plan(P, n, us + W->off[j], vs + W->off[j], wsr + W->off[j], s);
+      if (rc == SEPW_OK) rc = bin_plan(P, n, plain_coords(us + W->off[j], vs + W->off[j], wsr + W->off[j]), s);
       if (rc == SEPW_OK && n_dropped) {
         int64_t d = 0;
         rc = read_dropped(P, &d, s);
@@ -679,6 +700,101 @@ int wstack_build(sepw_wstack_s* W, Kernels* K, int ns, double w_lo, double w_hi,
     return SEPW_OK;
   };
   const int rc = run();
+  cleanup();
+  return rc;
+}
+
+void destroy_wsnap(sepw_wsnap_s* ws) {
+  if (!ws) return;
+  for (Plan* p : ws->plans) destroy_plan(p);
+  dfree(ws->img);
+  delete ws;
+}
+
+constexpr int64_t kSnapBlock = 65536;   // visibilities per block of the plane fit
+
+// Fit the planes, form the residual w, set the kernels' range to it and bin
+// each snapshot.
+int wsnap_build(sepw_wsnap_s* W, const double* u, const double* v, const double* w, hipStream_t s) {
+  Kernels* K = W->K;
+  const int ns = W->ns;
+  std::vector<int64_t> range;
+  std::vector<int> snap, first(ns + 1, 0);
+  for (int i = 0; i < ns; ++i) {
+    first[i] = (int)snap.size();
+    for (int64_t a = W->off[i]; a < W->off[i + 1]; a += kSnapBlock) {
+      range.push_back(a);
+      range.push_back(std::min(a + kSnapBlock, W->off[i + 1]));
+      snap.push_back(i);
+    }
+  }
+  first[ns] = (int)snap.size();
+  const int nb = (int)snap.size();
+  int64_t* d_range = nullptr;
+  int *d_snap = nullptr, *d_first = nullptr;
+  double *d_part = nullptr, *d_wr = nullptr;
+  double2* d_d0 = nullptr;
+  uint32_t* d_max = nullptr;
+  auto cleanup = [&]() {
+    dfree(d_range);
+    dfree(d_snap);
+    dfree(d_first);
+    dfree(d_part);
+    dfree(d_wr);
+    dfree(d_d0);
+    dfree(d_max);
+  };
+  hipError_t e = dalloc(&d_range, 2 * (int64_t)nb);
+  if (e == hipSuccess) e = dalloc(&d_snap, nb);
+  if (e == hipSuccess) e = dalloc(&d_first, ns + 1);
+  if (e == hipSuccess) e = dalloc(&d_part, 5 * (int64_t)nb);
+  if (e == hipSuccess) e = dalloc(&d_wr, W->nvis);
+  if (e == hipSuccess) e = dalloc(&d_d0, ns);
+  if (e == hipSuccess) e = dalloc(&d_max, 2);
+  if (e == hipSuccess && nb > 0)
+    e = hipMemcpyAsync(d_range, range.data(), sizeof(int64_t) * range.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && nb > 0)
+    e = hipMemcpyAsync(d_snap, snap.data(), sizeof(int) * snap.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_first, first.data(), sizeof(int) * first.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_fill_u32(d_max, 0u, 2, s);
+  if (e == hipSuccess)
+    e = launch_snap_fit(u, v, w, d_range, d_snap, d_first, nb, ns, d_part, d_d0, d_wr,
+                        reinterpret_cast<unsigned long long*>(d_max), s);
+  uint64_t maxbits = 0;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(W->d0.data(), d_d0, sizeof(double2) * ns, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&maxbits, d_max, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    cleanup();
+    return map_hip(e);
+  }
+  double m = 0.0;
+  std::memcpy(&m, &maxbits, sizeof(m));
+  W->h = m > 0.0 ? m * (1.0 + 0x1p-20) : 1.0;
+  // the kernels' planes span the residual range
+  K->w_lo = -W->h;
+  K->w_hi = W->h;
+  K->prm.w_lo = -W->h;
+  K->prm.w_hi = W->h;
+  K->inv_dw = (double)K->P / (K->w_hi - K->w_lo);
+  K->generation += 1;
+  int rc = map_hip(make_tables(K, s));
+  for (int i = 0; i < ns && rc == SEPW_OK; ++i) {
+    const int64_t n = W->off[i + 1] - W->off[i];
+    if (n == 0) continue;
+    Plan* P = new (std::nothrow) sepw_plan_s();
+    if (!P) {
+      rc = SEPW_ERR_OOM;
+      break;
+    }
+    W->plans[i] = P;
+    rc = alloc_plan(K, n, P);
+    if (rc == SEPW_OK)
+      rc = bin_plan(P, n, plain_coords(u + W->off[i], v + W->off[i], d_wr + W->off[i]), s);
+  }
+  if (rc == SEPW_OK) rc = map_hip(hipStreamSynchronize(s));
   cleanup();
   return rc;
 }
@@ -806,7 +922,7 @@ int sepw_plan_create(sepw_kernels k, int64_t nvis, const double* u, const double
   sepw_plan_s* P = new (std::nothrow) sepw_plan_s();
   if (!P) return SEPW_ERR_OOM;
   int rc = alloc_plan(k, nvis, P);
-  if (rc == SEPW_OK) rc = bin_plan(P, nvis, u, v, w, s);
+  if (rc == SEPW_OK) rc = bin_plan(P, nvis, plain_coords(u, v, w), s);
   if (rc == SEPW_OK && n_dropped) rc = read_dropped(P, n_dropped, s);
   if (rc != SEPW_OK) {
     destroy_plan(P);
@@ -821,7 +937,49 @@ int sepw_plan_rebin(sepw_plan p, int64_t nvis, const double* u, const double* v,
   if (!p || nvis < 0 || nvis > p->capacity) return SEPW_ERR_ARG;
   if (nvis > 0 && (!u || !v || !w)) return SEPW_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  int rc = bin_plan(p, nvis, u, v, w, s);
+  int rc = bin_plan(p, nvis, plain_coords(u, v, w), s);
+  if (rc == SEPW_OK && n_dropped) rc = read_dropped(p, n_dropped, s);
+  return rc;
+}
+
+int sepw_plan_create_channels(sepw_kernels k, int64_t nrows, int32_t nchan, const double* uvw,
+                              const double* freq, int64_t* n_dropped, void* hip_stream,
+                              sepw_plan* out) {
+  if (!out) return SEPW_ERR_ARG;
+  *out = nullptr;
+  if (!k || nrows < 0 || nrows > 2147483646LL || nchan < 1 || nrows * (int64_t)nchan > 2147483646LL)
+    return SEPW_ERR_ARG;
+  if (nrows > 0 && (!uvw || !freq)) return SEPW_ERR_ARG;
+  const int64_t nvis = nrows * (int64_t)nchan;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  sepw_plan_s* P = new (std::nothrow) sepw_plan_s();
+  if (!P) return SEPW_ERR_OOM;
+  Coords c;
+  c.uvw = uvw;
+  c.freq = freq;
+  c.nchan = nchan;
+  int rc = alloc_plan(k, nvis, P);
+  if (rc == SEPW_OK) rc = bin_plan(P, nvis, c, s);
+  if (rc == SEPW_OK && n_dropped) rc = read_dropped(P, n_dropped, s);
+  if (rc != SEPW_OK) {
+    destroy_plan(P);
+    return rc;
+  }
+  *out = P;
+  return SEPW_OK;
+}
+
+int sepw_plan_rebin_channels(sepw_plan p, int64_t nrows, int32_t nchan, const double* uvw,
+                             const double* freq, int64_t* n_dropped, void* hip_stream) {
+  if (!p || nrows < 0 || nrows > 2147483646LL || nchan < 1 || nrows * (int64_t)nchan > p->capacity)
+    return SEPW_ERR_ARG;
+  if (nrows > 0 && (!uvw || !freq)) return SEPW_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  Coords c;
+  c.uvw = uvw;
+  c.freq = freq;
+  c.nchan = nchan;
+  int rc = bin_plan(p, nrows * (int64_t)nchan, c, s);
   if (rc == SEPW_OK && n_dropped) rc = read_dropped(p, n_dropped, s);
   return rc;
 }
@@ -1236,6 +1394,119 @@ int sepw_wstack_degrid(sepw_wstack ws, const sepw_c64* image, sepw_c64* vis_out,
     Stage st(SEPW_STAGE_GATHER, s);
     SEPW_TRY(launch_slice_return(ws->vis, ws->order, ws->nvis, reinterpret_cast<float2*>(vis_out),
                                  s));
+  }
+  return SEPW_OK;
+}
+
+int sepw_free_wsnap(sepw_wsnap ws) {
+  if (!ws) return SEPW_ERR_ARG;
+  destroy_wsnap(ws);
+  return SEPW_OK;
+}
+
+int sepw_wsnap_create(sepw_kernels k, int32_t n_snap, const int64_t* offsets, const double* u,
+                      const double* v, const double* w, int64_t* n_dropped, void* hip_stream,
+                      sepw_wsnap* out) {
+  if (!out) return SEPW_ERR_ARG;
+  *out = nullptr;
+  if (!k || n_snap < 1 || n_snap > (1 << 20) || !offsets) return SEPW_ERR_ARG;
+  if (offsets[0] != 0) return SEPW_ERR_ARG;
+  for (int i = 0; i < n_snap; ++i)
+    if (offsets[i + 1] < offsets[i]) return SEPW_ERR_ARG;
+  const int64_t nvis = offsets[n_snap];
+  if (nvis > 2147483646LL) return SEPW_ERR_ARG;
+  if (nvis > 0 && (!u || !v || !w)) return SEPW_ERR_ARG;
+  if (k->facet) return SEPW_ERR_UNSUPPORTED;
+  if (device_count() < 1) return SEPW_ERR_NO_DEVICE;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  sepw_wsnap_s* W = new (std::nothrow) sepw_wsnap_s();
+  if (!W) return SEPW_ERR_OOM;
+  W->K = k;
+  W->ns = n_snap;
+  W->nvis = nvis;
+  W->off.assign(offsets, offsets + n_snap + 1);
+  W->d0.assign(2 * (size_t)n_snap, 0.0);
+  W->plans.assign(n_snap, nullptr);
+  int rc = map_hip(dalloc(&W->img, (int64_t)k->N * k->N));
+  if (rc == SEPW_OK) rc = wsnap_build(W, u, v, w, s);
+  int64_t dropped = 0;
+  for (int i = 0; i < n_snap && rc == SEPW_OK && n_dropped; ++i) {
+    if (!W->plans[i]) continue;
+    int64_t d = 0;
+    rc = read_dropped(W->plans[i], &d, s);
+    dropped += d;
+  }
+  if (rc != SEPW_OK) {
+    destroy_wsnap(W);
+    return rc;
+  }
+  if (n_dropped) *n_dropped = dropped;
+  *out = W;
+  return SEPW_OK;
+}
+
+int sepw_wsnap_plane(sepw_wsnap ws, int32_t snapshot, double* d0, double* h) {
+  if (!ws || snapshot < 0 || snapshot >= ws->ns || !d0) return SEPW_ERR_ARG;
+  d0[0] = ws->d0[2 * (size_t)snapshot];
+  d0[1] = ws->d0[2 * (size_t)snapshot + 1];
+  if (h) *h = ws->h;
+  return SEPW_OK;
+}
+
+int sepw_wsnap_grid(sepw_wsnap ws, const sepw_c64* vis, const float* weight, sepw_c64* image_out,
+                    uint32_t flags, void* hip_stream) {
+  if (!ws || !image_out || (!vis && ws->nvis > 0)) return SEPW_ERR_ARG;
+  if ((flags & ~(SEPW_MUL_N | SEPW_DIV_N)) != 0) return SEPW_ERR_ARG;
+  if ((flags & SEPW_MUL_N) && (flags & SEPW_DIV_N)) return SEPW_ERR_ARG;
+  Kernels* K = ws->K;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int N = K->N;
+  float2* out = reinterpret_cast<float2*>(image_out);
+  {
+    Stage st(SEPW_STAGE_FILL, s);
+    SEPW_TRY(launch_zero_c64(out, (int64_t)N * N, s));
+  }
+  for (int i = 0; i < ws->ns; ++i) {
+    Plan* p = ws->plans[i];
+    if (!p) continue;
+    const int64_t o = ws->off[i];
+    int rc = sepw_grid(static_cast<sepw_plan>(p), vis + o, weight ? weight + o : nullptr,
+                       reinterpret_cast<sepw_c64*>(ws->img), 0u, hip_stream);
+    if (rc != SEPW_OK) return rc;
+    Stage st(SEPW_STAGE_CORRECT, s);
+    SEPW_TRY(launch_snap_reproject(ws->img, out, N, K->fov, ws->d0[2 * (size_t)i],
+                                   ws->d0[2 * (size_t)i + 1], true, s));
+  }
+  const int npow = (flags & SEPW_MUL_N) ? 1 : ((flags & SEPW_DIV_N) ? -1 : 0);
+  if (npow) {
+    Stage st(SEPW_STAGE_CORRECT, s);
+    SEPW_TRY(launch_snap_npow(out, N, K->fov, npow, s));
+  }
+  return SEPW_OK;
+}
+
+int sepw_wsnap_degrid(sepw_wsnap ws, const sepw_c64* image, sepw_c64* vis_out, uint32_t flags,
+                      void* hip_stream) {
+  if (!ws || !image || (!vis_out && ws->nvis > 0)) return SEPW_ERR_ARG;
+  if ((flags & ~SEPW_DIV_N) != 0) return SEPW_ERR_ARG;
+  Kernels* K = ws->K;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int N = K->N;
+  const int npow = (flags & SEPW_DIV_N) ? -1 : 0;
+  for (int i = 0; i < ws->ns; ++i) {
+    Plan* p = ws->plans[i];
+    if (!p) continue;
+    {
+      Stage st(SEPW_STAGE_CORRECT, s);
+      SEPW_TRY(launch_zero_c64(ws->img, (int64_t)N * N, s));
+      SEPW_TRY(launch_snap_reproject_adjoint(reinterpret_cast<const float2*>(image), ws->img, N,
+                                             K->fov, ws->d0[2 * (size_t)i],
+                                             ws->d0[2 * (size_t)i + 1], npow, s));
+    }
+    int rc = sepw_degrid(static_cast<sepw_plan>(p), reinterpret_cast<const sepw_c64*>(ws->img),
+                         vis_out + ws->off[i], 0u,
+                         hip_stream);
+    if (rc != SEPW_OK) return rc;
   }
   return SEPW_OK;
 }

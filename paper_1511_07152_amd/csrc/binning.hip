@@ -44,12 +44,6 @@ inline dim3 grid_for(int64_t n, int64_t per_block = kThreads) {
   return dim3((unsigned)b);
 }
 
-__device__ inline int64_t floor_div(int64_t a, int64_t b) {  // b > 0
-  int64_t q = a / b;
-  if ((a % b != 0) && (a < 0)) --q;
-  return q;
-}
-
 struct AxisBin {
   int64_t cell;
   int fi;
@@ -63,8 +57,10 @@ __device__ inline AxisBin axis_bin(double u, const QuantGeom& g) {
   double q = floor(__dadd_rn(t, 0.5));
   r.ok = isfinite(q) && fabs(q) < 1099511627776.0;  // 2^40
   int64_t qi = r.ok ? (int64_t)q : 0;
-  r.cell = floor_div(qi + g.O / 2, g.O);
-  r.fi = (int)(qi - r.cell * g.O) + g.O / 2;
+  // O is a power of two: floor((q + O/2) / O) is an arithmetic shift, and
+  // f + O/2 = q - cell O + O/2 the low bits of q + O/2
+  r.cell = (qi + g.O / 2) >> g.lo;
+  r.fi = (int)((qi + g.O / 2) & (int64_t)(g.O - 1));
   return r;
 }
 
@@ -160,13 +156,13 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(const uint32_t* in
 // ---------------------------------------------------------------- facets, items, export
 // Facet phase rotation in caller order (Section 4.1), applied to W V on its way
 // into tile order and undone on the way back.
-__global__ void rotation_kernel(const double* __restrict__ u, const double* __restrict__ v,
-                                const double* __restrict__ w, int64_t nvis, QuantGeom g,
-                                float2* __restrict__ rot) {
+__global__ void rotation_kernel(Coords src, int64_t nvis, QuantGeom g, float2* __restrict__ rot) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nvis;
        i += (int64_t)gridDim.x * blockDim.x) {
+    double uu, vv, ww;
+    coords_at(src, i, uu, vv, ww);
     // phase in cycles, reduced to [-1/2, 1/2] before the FP64 sincos
-    double cyc = u[i] * g.l0 + v[i] * g.m0 + w[i] * (g.n0 - 1.0);
+    double cyc = uu * g.l0 + vv * g.m0 + ww * (g.n0 - 1.0);
     double frac = cyc - rint(cyc);
     double s, c;
     sincospi(2.0 * frac, &s, &c);
@@ -265,6 +261,7 @@ __global__ void bins_export_kernel(const uint2* __restrict__ rrec, const uint32_
 // ---------------------------------------------------------------- two-level sort
 constexpr int kL1Threads = 1024;
 constexpr int kChunk = kL1Chunk;         // visibilities per block in the level-1 passes
+constexpr int kLdsChannels = 1024;      // channel scales held in LDS (more: divided per visibility)
 static_assert(kChunk % kL1Threads == 0, "level-1 chunk must be a multiple of the block size");
 
 constexpr int kBinsPer = kMaxRowBins / kL1Threads;   // row bins owned by each thread
@@ -294,17 +291,48 @@ __device__ inline uint32_t block_scan_owned(uint32_t sum, uint32_t* wsum, uint32
 }
 
 __global__ __launch_bounds__(kL1Threads) void quantise_rows_kernel(
-    const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
-    int64_t nvis, QuantGeom g, int rshift, int nbins, uint32_t* __restrict__ rbin,
+    Coords src, int64_t nvis, QuantGeom g, int rshift, int nbins, uint32_t* __restrict__ rbin,
     uint2* __restrict__ qrec, uint32_t* __restrict__ chist) {
   __shared__ uint32_t hist[kMaxRowBins];
+  __shared__ double cscale[kLdsChannels];
   for (int b = threadIdx.x; b < nbins; b += kL1Threads) hist[b] = 0u;
+  // channel-shared rows: the channel scales f / c once per workgroup, and
+  // (row, channel) of this thread's visibilities advanced without divisions
+  const bool rows = src.uvw != nullptr;
+  const bool lds_scale = rows && src.nchan <= kLdsChannels;
+  if (lds_scale)
+    for (int c = threadIdx.x; c < (int)src.nchan; c += kL1Threads)
+      cscale[c] = __ddiv_rn(src.freq[c], kLightSpeed);
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kChunk;
+  int64_t row = 0, ch = 0, drow = 0, dch = 0;
+  if (rows) {
+    const int64_t i0 = base + threadIdx.x;
+    row = i0 / src.nchan;
+    ch = i0 - row * src.nchan;
+    drow = kL1Threads / src.nchan;
+    dch = kL1Threads - drow * src.nchan;
+  }
   for (int m = 0; m < kChunk / kL1Threads; ++m) {
     const int64_t i = base + (int64_t)m * kL1Threads + threadIdx.x;
     if (i >= nvis) break;
-    double uu = u[i], vv = v[i], ww = w[i];
+    double uu, vv, ww;
+    if (rows) {
+      const double sc = lds_scale ? cscale[ch] : __ddiv_rn(src.freq[ch], kLightSpeed);
+      uu = __dmul_rn(src.uvw[3 * row], sc);
+      vv = __dmul_rn(src.uvw[3 * row + 1], sc);
+      ww = __dmul_rn(src.uvw[3 * row + 2], sc);
+      row += drow;
+      ch += dch;
+      if (ch >= src.nchan) {
+        ch -= src.nchan;
+        row += 1;
+      }
+    } else {
+      uu = src.u[i];
+      vv = src.v[i];
+      ww = src.w[i];
+    }
     if (g.facet) {
       uu = __dsub_rn(uu, __ddiv_rn(__dmul_rn(ww, g.l0), g.n0));
       vv = __dsub_rn(vv, __ddiv_rn(__dmul_rn(ww, g.m0), g.n0));
@@ -329,8 +357,8 @@ __global__ __launch_bounds__(kL1Threads) void quantise_rows_kernel(
     }
   }
   __syncthreads();
-  uint32_t* row = chist + (int64_t)blockIdx.x * nbins;
-  for (int b = threadIdx.x; b < nbins; b += kL1Threads) row[b] = hist[b];
+  uint32_t* hrow = chist + (int64_t)blockIdx.x * nbins;
+  for (int b = threadIdx.x; b < nbins; b += kL1Threads) hrow[b] = hist[b];
 }
 
 // gsum[b][g] = visibilities of row bin b in the chunks of group g
@@ -832,13 +860,12 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* t
   return hipGetLastError();
 }
 
-hipError_t launch_quantise_rows(const double* u, const double* v, const double* w, int64_t nvis,
-                                QuantGeom g, int rshift, int nbins, uint32_t* rbin, uint2* qrec,
-                                uint32_t* chist, hipStream_t s) {
+hipError_t launch_quantise_rows(const Coords& src, int64_t nvis, QuantGeom g, int rshift, int nbins,
+                                uint32_t* rbin, uint2* qrec, uint32_t* chist, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
   const int64_t nb = (nvis + kChunk - 1) / kChunk;
-  hipLaunchKernelGGL(quantise_rows_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, u, v, w, nvis,
-                     g, rshift, nbins, rbin, qrec, chist);
+  hipLaunchKernelGGL(quantise_rows_kernel, dim3((unsigned)nb), dim3(kL1Threads), 0, s, src, nvis, g,
+                     rshift, nbins, rbin, qrec, chist);
   return hipGetLastError();
 }
 
@@ -942,10 +969,10 @@ hipError_t launch_vis_from_rows(const float2* yrow, const float2* rot, const uin
   return hipGetLastError();
 }
 
-hipError_t launch_rotation(const double* u, const double* v, const double* w, int64_t nvis,
-                           QuantGeom g, float2* rot, hipStream_t s) {
+hipError_t launch_rotation(const Coords& src, int64_t nvis, QuantGeom g, float2* rot,
+                           hipStream_t s) {
   if (nvis == 0) return hipSuccess;
-  hipLaunchKernelGGL(rotation_kernel, grid_for(nvis), dim3(kThreads), 0, s, u, v, w, nvis, g, rot);
+  hipLaunchKernelGGL(rotation_kernel, grid_for(nvis), dim3(kThreads), 0, s, src, nvis, g, rot);
   return hipGetLastError();
 }
 

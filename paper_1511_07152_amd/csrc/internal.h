@@ -47,6 +47,7 @@ struct QuantGeom {
   double w_lo;
   double inv_dw;     // P / (w_hi - w_lo), computed once on the host
   int32_t N, S, O, P;
+  int32_t lo;        // log2 O
   int32_t tile_c, ntx;
   int32_t facet;
   double l0, m0, n0; // facet centre and n0 = sqrt(1 - l0^2 - m0^2)
@@ -165,6 +166,34 @@ __host__ __device__ inline uint2 pack_rec(int cu, int fu, int cv, int fv, int k)
 // and psi_0(c, 0) from the same series.  Returns the number of coefficients.
 int pswf_coefficients(double c, double* d, int max_terms, double* psi_at_0);
 
+// Visibility coordinates in wavelengths, caller order: either three arrays
+// (u[i], v[i], w[i]) or, channel-shared, rows of metres uvw[row][3] with
+// visibility i = row * nchan + ch at u = u_m * (freq[ch] / c) (one IEEE
+// division, then one IEEE multiplication per coordinate).
+constexpr double kLightSpeed = 299792458.0;   // m/s
+struct Coords {
+  const double* u = nullptr;
+  const double* v = nullptr;
+  const double* w = nullptr;
+  const double* uvw = nullptr;    // channel-shared rows (metres), or null
+  const double* freq = nullptr;   // [nchan] Hz
+  int64_t nchan = 1;
+};
+
+__device__ inline void coords_at(const Coords& c, int64_t i, double& u, double& v, double& w) {
+  if (c.uvw) {
+    const int64_t row = i / c.nchan;
+    const double s = __ddiv_rn(c.freq[i - row * c.nchan], kLightSpeed);
+    u = __dmul_rn(c.uvw[3 * row], s);
+    v = __dmul_rn(c.uvw[3 * row + 1], s);
+    w = __dmul_rn(c.uvw[3 * row + 2], s);
+  } else {
+    u = c.u[i];
+    v = c.v[i];
+    w = c.w[i];
+  }
+}
+
 // ---- launchers (return hipError_t of the launch) ----
 hipError_t launch_taper(const double* d_coef, int ncoef, double norm, int N, double* c1, hipStream_t s);
 hipError_t launch_ones(double* c1, int N, hipStream_t s);
@@ -175,9 +204,8 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_zero_c64(float2* p, int64_t n, hipStream_t s);
 // two-level counting sort by tile (rows of tiles, then tiles within a row bin);
 // chist[chunk][bin] = level-1 histogram of each chunk of kL1Chunk visibilities
-hipError_t launch_quantise_rows(const double* u, const double* v, const double* w, int64_t nvis,
-                                QuantGeom g, int rshift, int nbins, uint32_t* rbin, uint2* qrec,
-                                uint32_t* chist, hipStream_t s);
+hipError_t launch_quantise_rows(const Coords& src, int64_t nvis, QuantGeom g, int rshift, int nbins,
+                                uint32_t* rbin, uint2* qrec, uint32_t* chist, hipStream_t s);
 // rowcount[bin] = kept visibilities per row bin (rowcount[nbins] = 0); gsum =
 // [nbins][groups] exclusive scan over the chunk groups of each bin
 hipError_t launch_level1_counts(const uint32_t* chist, int64_t nvis, int nbins, uint32_t* gsum,
@@ -223,8 +251,8 @@ hipError_t launch_vis_from_rows(const float2* yrow, const float2* rot, const uin
                                 int nbins, float2* out, hipStream_t s);
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t s);
 int64_t scan_tmp_size(int64_t n);
-hipError_t launch_rotation(const double* u, const double* v, const double* w, int64_t nvis,
-                           QuantGeom g, float2* rot, hipStream_t s);
+hipError_t launch_rotation(const Coords& src, int64_t nvis, QuantGeom g, float2* rot,
+                           hipStream_t s);
 // work items: slices of <= item_slots slots of each row of tiles
 // per-row item counts in list order (nit[(r % 8) r8 + r / 8]) and the items in that order
 hipError_t launch_item_counts(const uint2* tdesc, int ntx, int nty, int r8, int item_slots,
@@ -245,6 +273,16 @@ hipError_t launch_slice_return(const float2* in, const uint32_t* order, int64_t 
 // out (+)= in exp(sign 2 pi i w_s (n - 1)) over the N x N pixels
 hipError_t launch_slice_phase(const float2* in, float2* out, int N, double fov, double w_s,
                               int sign, bool accumulate, hipStream_t s);
+
+// W snapshots (wsnap.hip): plane fit and residual w, reprojection and its transpose
+hipError_t launch_snap_fit(const double* u, const double* v, const double* w, const int64_t* range,
+                           const int* snap, const int* first, int nblocks, int ns, double* part,
+                           double2* d0, double* wr, unsigned long long* maxbits, hipStream_t s);
+hipError_t launch_snap_reproject(const float2* in, float2* out, int N, double fov, double du,
+                                 double dv, bool accumulate, hipStream_t s);
+hipError_t launch_snap_reproject_adjoint(const float2* X, float2* out, int N, double fov, double du,
+                                         double dv, int npow, hipStream_t s);
+hipError_t launch_snap_npow(float2* out, int N, double fov, int npow, hipStream_t s);
 
 hipError_t launch_bins_export(const uint2* rrec, const uint32_t* place, const uint32_t* delta,
                               int nbins, int64_t nvis, int tile_c, int ntx, int32_t* out,

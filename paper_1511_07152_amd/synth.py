@@ -58,8 +58,10 @@ def uvw_metres(b_xyz, ha, dec):
     return np.stack([u, v, w], axis=-1)
 
 
-def track(rng, n_ant, radius_m, lat, dec, ha_hours, dump_s, freqs_hz, time_slice=None):
-    """uvw in wavelengths, measurement-set order (time, baseline, channel)."""
+def track(rng, n_ant, radius_m, lat, dec, ha_hours, dump_s, freqs_hz, time_slice=None,
+          rows=False):
+    """uvw in wavelengths, measurement-set order (time, baseline, channel);
+    with rows=True also the per-row metres [ntime * nbl][3] they scale from."""
     enu = disc_antennas(rng, n_ant, radius_m)
     bxyz = enu_to_xyz(baselines(enu), lat)
     h0, h1 = ha_hours
@@ -70,7 +72,11 @@ def track(rng, n_ant, radius_m, lat, dec, ha_hours, dump_s, freqs_hz, time_slice
     scale = np.asarray(freqs_hz, np.float64) / C0           # [nchan]
     uvw = uvw_m[:, :, None, :] * scale[None, None, :, None]  # [nt][nbl][nchan][3]
     uvw = uvw.reshape(-1, 3)
-    return np.ascontiguousarray(uvw[:, 0]), np.ascontiguousarray(uvw[:, 1]), np.ascontiguousarray(uvw[:, 2])
+    out = (np.ascontiguousarray(uvw[:, 0]), np.ascontiguousarray(uvw[:, 1]),
+           np.ascontiguousarray(uvw[:, 2]))
+    if rows:
+        return out + (np.ascontiguousarray(uvw_m.reshape(-1, 3)),)
+    return out
 
 
 def gaussian_vis(rng, n):
@@ -113,11 +119,12 @@ def array_4096(dump_s=10.0, channels=16):
     128 w-planes over +/- max|w|, support 15, oversample 8 (92,897,280 vis)."""
     rng = np.random.default_rng(SEED0 + 2)
     freqs = 600e6 + 8e6 * np.arange(channels)
-    u, v, w = track(rng, 64, 8000.0, deg(-30.7), deg(-30.0), (-4.0, 4.0), dump_s, freqs)
+    u, v, w, uvw_m = track(rng, 64, 8000.0, deg(-30.7), deg(-30.0), (-4.0, 4.0), dump_s, freqs,
+                           rows=True)
     V = gaussian_vis(rng, len(u)).astype(np.complex64)
     w_lo, w_hi = _w_range(w)
     return dict(u=u, v=v, w=w, V=V, W=np.ones(len(u), np.float32), N=4096, fov=deg(3.0),
-                P=128, w_lo=w_lo, w_hi=w_hi, S=15, O=8)
+                P=128, w_lo=w_lo, w_hi=w_hi, S=15, O=8, uvw_m=uvw_m, freqs=freqs)
 
 
 def model_2048():

@@ -108,5 +108,12 @@ def test_null_handles_rejected(lib):
     assert lib.sepw_kernels_set_correction(None, 5, 8, None) == -1
     assert lib.sepw_kernels_set_correction(None, 0, 0, None) == -1
     assert lib.sepw_kernels_correction_table(None, None, None) == -1
+    assert lib.sepw_plan_create_channels(None, 10, 4, None, None, None, None, ctypes.byref(h)) == -1
+    assert lib.sepw_plan_rebin_channels(None, 10, 4, None, None, None, None) == -1
+    assert lib.sepw_wsnap_create(None, 2, None, None, None, None, None, None, ctypes.byref(h)) == -1
+    assert lib.sepw_wsnap_grid(None, None, None, None, 0, None) == -1
+    assert lib.sepw_wsnap_degrid(None, None, None, 0, None) == -1
+    assert lib.sepw_wsnap_plane(None, 0, None, None) == -1
+    assert lib.sepw_free_wsnap(None) == -1
     assert lib.sepw_free_kernels(None) == -1 and lib.sepw_free_plan(None) == -1
     assert lib.sepw_strerror(-1) == b"invalid argument"

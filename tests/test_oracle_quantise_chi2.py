@@ -43,6 +43,29 @@ def test_hand_worked_cases(u, cell, fi):
     assert ok[0] and c[0] == cell and f[0] == fi
 
 
+def test_channel_coordinates_order_and_rounding():
+    # visibility row * nchan + ch; u = u_m * (f / c) with the division first
+    rng = np.random.default_rng(77)
+    uvw = rng.uniform(-5e3, 5e3, (40, 3))
+    f = 1e9 + 7.3e6 * np.arange(5)
+    u, v, w = quantise.channel_coordinates(uvw, f)
+    c = 299792458.0
+    for r in (0, 17, 39):
+        for ch in range(5):
+            i = r * 5 + ch
+            s = f[ch] / c
+            assert (u[i], v[i], w[i]) == (uvw[r, 0] * s, uvw[r, 1] * s, uvw[r, 2] * s)
+    # the order is observable: find a row where u_m f / c rounds differently
+    diff = [(x, ff) for x in uvw[:, 0] for ff in f if (x * ff) / c != x * (ff / c)]
+    assert diff, "no case separates the two orders"
+    x, ff = diff[0]
+    got, _, _ = quantise.channel_coordinates([[x, 0.0, 0.0]], [ff])
+    assert got[0] == x * (ff / c) and got[0] != (x * ff) / c
+    # at f = c the scale is exactly 1
+    uc, vc, wc = quantise.channel_coordinates(uvw[:3], [c])
+    assert np.array_equal(np.stack([uc, vc, wc], 1), uvw[:3])
+
+
 def test_plane_index_rules():
     w = np.array([-100.0, -99.999, -50.0, -0.001, 0.0, 49.999, 50.0, 99.999, 100.0, 1e9, -1e9, np.nan])
     k, ok = quantise.plane_index(w, 4, -100.0, 100.0)
