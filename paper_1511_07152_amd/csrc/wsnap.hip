@@ -13,7 +13,11 @@
 // Reprojection samples the snapshot image at the fractional pixel
 // x = l^s N / fov + N/2 (y alike) by separable cubic convolution (Keys,
 // a = -1/2) over the 4 x 4 nearest pixels (pixels off the image count 0);
-// its transpose scatters each pixel back with the same weights (FP32 atomics).
+// its transpose sends each pixel back with the same weights (a gather when the
+// warp is close to the identity, FP32 atomics otherwise).
+#include <algorithm>
+#include <cmath>
+
 #include "internal.h"
 
 namespace sepw {
@@ -212,6 +216,90 @@ __global__ void snap_reproject_adjoint_kernel(const float2* __restrict__ X, floa
   }
 }
 
+// Gather form of the transpose, for warps close to the identity.  Snapshot
+// pixel j receives w(x_b - j_x) w(y_b - j_y) X'_b from every output pixel b
+// whose sample point (x_b, y_b) lies within 2 pixels of j on both axes (the
+// same weights as the forward sampling).  A workgroup takes 16 x 16 snapshot
+// pixels: the pre-image p* of the tile centre c under the warp g comes from
+// the fixed-point iteration p <- p + (c - g(p)); the sample points and values
+// of the 32 x 32 output pixels around p* go to LDS; each pixel then scans the
+// 9 x 9 output pixels around j - (c - p*).  With the warp's Jacobian within
+// eps <= 0.1 of the identity (max-norm) every contributor lies within
+// (2 + 8 eps) / (1 - eps) + 1/2 < 4 pixels of that point, inside the scanned
+// window and the box; the launcher checks the bound and otherwise uses the
+// scatter kernel above.
+constexpr int kGTile = 16, kGBox = 32, kGRad = 4;
+
+__device__ inline void warp_at(double p, double q, int N, double fov, double du, double dv,
+                               double& x, double& y) {
+  const double step = fov / (double)N;
+  const double l = (p - (double)(N / 2)) * step, m = (q - (double)(N / 2)) * step;
+  const double r2 = l * l + m * m;
+  const double nm1 = -r2 / (1.0 + sqrt(1.0 - r2));
+  x = (l + du * nm1) * (double)N / fov + (double)(N / 2);
+  y = (m + dv * nm1) * (double)N / fov + (double)(N / 2);
+}
+
+__global__ __launch_bounds__(kGTile * kGTile) void snap_adjoint_gather_kernel(
+    const float2* __restrict__ X, float2* __restrict__ out, int N, double fov, double du, double dv,
+    int npow) {
+  __shared__ double sx[kGBox * kGBox], sy[kGBox * kGBox];
+  __shared__ float2 sv[kGBox * kGBox];
+  const int tx0 = blockIdx.x * kGTile, ty0 = blockIdx.y * kGTile;
+  const double cx = tx0 + 0.5 * (kGTile - 1), cy = ty0 + 0.5 * (kGTile - 1);
+  double px = cx, py = cy;
+  for (int it = 0; it < 8; ++it) {
+    double x, y;
+    warp_at(px, py, N, fov, du, dv, x, y);
+    px += cx - x;
+    py += cy - y;
+  }
+  const int ox = (int)floor(px) - 12, oy = (int)floor(py) - 12;   // box origin
+  for (int e = threadIdx.x; e < kGBox * kGBox; e += kGTile * kGTile) {
+    const int bp = ox + (e % kGBox), bq = oy + (e / kGBox);
+    double x = 1e300, y = 1e300;
+    float2 val = make_float2(0.f, 0.f);
+    if (bp >= 0 && bp < N && bq >= 0 && bq < N) {
+      double n;
+      sample_point(bp, bq, N, fov, du, dv, x, y, n);
+      if (fabs(x) < 4.0 * N && fabs(y) < 4.0 * N) {
+        val = X[(int64_t)bq * N + bp];
+        if (npow) {
+          const float s = (float)(npow > 0 ? n : 1.0 / n);
+          val = make_float2(val.x * s, val.y * s);
+        }
+      } else {
+        x = y = 1e300;
+      }
+    }
+    sx[e] = x;
+    sy[e] = y;
+    sv[e] = val;
+  }
+  __syncthreads();
+  const int jx = tx0 + (threadIdx.x % kGTile), jy = ty0 + (threadIdx.x / kGTile);
+  if (jx >= N || jy >= N) return;
+  const int cp = (int)rint((double)jx - (cx - px)) - ox, cq = (int)rint((double)jy - (cy - py)) - oy;
+  float ar = 0.f, ai = 0.f;
+  for (int b = -kGRad; b <= kGRad; ++b) {
+    const int qq = cq + b;
+    if (qq < 0 || qq >= kGBox) continue;
+    for (int a = -kGRad; a <= kGRad; ++a) {
+      const int pp = cp + a;
+      if (pp < 0 || pp >= kGBox) continue;
+      const int e = qq * kGBox + pp;
+      const double dx = sx[e] - (double)jx, dy = sy[e] - (double)jy;
+      if (fabs(dx) < 2.0 && fabs(dy) < 2.0) {
+        const float wgt = (float)keys(dy) * (float)keys(dx);
+        ar += wgt * sv[e].x;
+        ai += wgt * sv[e].y;
+      }
+    }
+  }
+  const float2 o = out[(int64_t)jy * N + jx];
+  out[(int64_t)jy * N + jx] = make_float2(o.x + ar, o.y + ai);
+}
+
 // out *= n^npow
 __global__ void snap_npow_kernel(float2* __restrict__ out, int N, double fov, int npow) {
   const int64_t total = (int64_t)N * N;
@@ -255,8 +343,17 @@ hipError_t launch_snap_reproject(const float2* in, float2* out, int N, double fo
 
 hipError_t launch_snap_reproject_adjoint(const float2* X, float2* out, int N, double fov, double du,
                                          double dv, int npow, hipStream_t s) {
-  hipLaunchKernelGGL(snap_reproject_adjoint_kernel, grid_for((int64_t)N * N), dim3(kThreads), 0, s,
-                     X, out, N, fov, du, dv, npow);
+  // bound on the warp's deviation from the identity: max |d| (|l| + |m|) / n
+  // over the image, |l|, |m| <= fov / 2
+  const double eps = std::max(std::fabs(du), std::fabs(dv)) * fov / std::sqrt(1.0 - 0.5 * fov * fov);
+  if (eps <= 0.1) {
+    const unsigned nt = (unsigned)((N + kGTile - 1) / kGTile);
+    hipLaunchKernelGGL(snap_adjoint_gather_kernel, dim3(nt, nt), dim3(kGTile * kGTile), 0, s, X, out,
+                       N, fov, du, dv, npow);
+  } else {
+    hipLaunchKernelGGL(snap_reproject_adjoint_kernel, grid_for((int64_t)N * N), dim3(kThreads), 0, s,
+                       X, out, N, fov, du, dv, npow);
+  }
   return hipGetLastError();
 }
 

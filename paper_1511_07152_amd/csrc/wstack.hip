@@ -52,17 +52,31 @@ __global__ __launch_bounds__(kThreads) void slice_count_kernel(const double* __r
 
 // Slice order: order[j] = caller index of slice-ordered position j; the
 // coordinates in slice order with w replaced by its residual.  cursor starts
-// at the slice offsets.
+// at the slice offsets.  Each workgroup counts its chunk per slice in LDS,
+// reserves each slice's run with one global atomic, then places its
+// visibilities with LDS atomics (one global atomic per visibility on a few
+// slice cursors serialised on those cursors).
+constexpr int kScatterChunk = 16 * kThreads;
 __global__ __launch_bounds__(kThreads) void slice_scatter_kernel(
     const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
     int64_t nvis, double w_lo, double inv_ds, int ns, const double* __restrict__ centre,
     uint32_t* __restrict__ cursor, uint32_t* __restrict__ order, double* __restrict__ us,
     double* __restrict__ vs, double* __restrict__ ws) {
-  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < nvis;
-       i += (int64_t)gridDim.x * kThreads) {
+  __shared__ uint32_t cnt[kMaxSlices];
+  const int64_t i0 = (int64_t)blockIdx.x * kScatterChunk;
+  const int64_t i1 = min(i0 + (int64_t)kScatterChunk, nvis);
+  for (int s = threadIdx.x; s < ns; s += kThreads) cnt[s] = 0u;
+  __syncthreads();
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads)
+    atomicAdd(&cnt[slice_of(w[i], w_lo, inv_ds, ns)], 1u);
+  __syncthreads();
+  for (int s = threadIdx.x; s < ns; s += kThreads)
+    if (cnt[s]) cnt[s] = atomicAdd(&cursor[s], cnt[s]);   // this chunk's first position
+  __syncthreads();
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) {
     const double wi = w[i];
     const int s = slice_of(wi, w_lo, inv_ds, ns);
-    const uint32_t j = atomicAdd(&cursor[s], 1u);
+    const uint32_t j = atomicAdd(&cnt[s], 1u);
     order[j] = (uint32_t)i;
     us[j] = u[i];
     vs[j] = v[i];
@@ -135,8 +149,9 @@ hipError_t launch_slice_scatter(const double* u, const double* v, const double* 
                                 uint32_t* cursor, uint32_t* order, double* us, double* vs,
                                 double* ws, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
-  hipLaunchKernelGGL(slice_scatter_kernel, grid_for(nvis), dim3(kThreads), 0, s, u, v, w, nvis, w_lo,
-                     inv_ds, ns, centre, cursor, order, us, vs, ws);
+  const int64_t nb = (nvis + kScatterChunk - 1) / kScatterChunk;
+  hipLaunchKernelGGL(slice_scatter_kernel, dim3((unsigned)nb), dim3(kThreads), 0, s, u, v, w, nvis,
+                     w_lo, inv_ds, ns, centre, cursor, order, us, vs, ws);
   return hipGetLastError();
 }
 

@@ -4,8 +4,10 @@ The library's per-snapshot planes (FP64, block-ordered sums) are compared with
 oracle.wsnap.fit_plane within 1e-12 relative; images (inner half) and
 predicted visibilities with oracle.wsnap.image / predict within the FP32
 bound 1e-5 (relative RMS), on snapshots whose planes tilt enough that the
-reprojection moves the image by several pixels at the edges; the adjoint
-identity within 1e-5; empty and degenerate snapshots; argument checks.
+reprojection moves the image by several pixels at the edges (the scatter form
+of the transposed reprojection) and on mildly tilted ones (its gather form);
+the adjoint identity within 1e-5; empty and degenerate snapshots; argument
+checks.
 """
 import numpy as np
 import pytest
@@ -27,12 +29,17 @@ def lib():
     return _lib
 
 
-def _case(seed, N=64, fov=0.4, sizes=(700, 0, 1, 900, 500)):
+# geometries: a strong tilt (the transposed reprojection scatters with
+# atomics) and a mild one (warp within 0.1 of the identity: the gather form)
+GEOMETRIES = {"scatter": dict(fov=0.4, dmax=2.5), "gather": dict(fov=0.05, dmax=1.5)}
+
+
+def _case(seed, N=64, fov=0.4, sizes=(700, 0, 1, 900, 500), dmax=2.5):
     rng = np.random.default_rng(seed)
     cells = N / 2 - 6
     us, vs, ws = [], [], []
     for n in sizes:
-        d = rng.uniform(-2.5, 2.5, 2)                 # each snapshot its own plane
+        d = rng.uniform(-dmax, dmax, 2)               # each snapshot its own plane
         u = rng.uniform(-cells, cells, n) / fov
         v = rng.uniform(-cells, cells, n) / fov
         us.append(u)
@@ -69,9 +76,10 @@ def test_planes_match_oracle(lib):
     assert ws.plane(1)[0] == (0.0, 0.0) and ws.plane(2)[0] == (0.0, 0.0)   # empty, single
 
 
+@pytest.mark.parametrize("geom", ["scatter", "gather"])
 @pytest.mark.parametrize("flags,npow", [(0, 0), ("MUL_N", 1), ("DIV_N", -1)])
-def test_wsnap_image_matches_oracle(lib, flags, npow):
-    _, d = _case(72)
+def test_wsnap_image_matches_oracle(lib, flags, npow, geom):
+    _, d = _case(72, **GEOMETRIES[geom])
     K, ws = _make(lib, d)
     f = getattr(lib, flags) if flags else 0
     img = ws.grid(dev(d["V"], torch.complex64), dev(d["W"], torch.float32), flags=f).cpu().numpy()
@@ -79,8 +87,9 @@ def test_wsnap_image_matches_oracle(lib, flags, npow):
     assert rel_rms(inner(img), inner(want)) <= 1e-5
 
 
-def test_wsnap_predict_matches_oracle(lib):
-    rng, d = _case(73)
+@pytest.mark.parametrize("geom", ["scatter", "gather"])
+def test_wsnap_predict_matches_oracle(lib, geom):
+    rng, d = _case(73, **GEOMETRIES[geom])
     K, ws = _make(lib, d)
     N = d["N"]
     X = np.zeros((N, N), complex)
@@ -90,8 +99,9 @@ def test_wsnap_predict_matches_oracle(lib):
     assert rel_rms(V, want) <= 1e-5
 
 
-def test_wsnap_grid_and_degrid_are_adjoint(lib):
-    rng, d = _case(74)
+@pytest.mark.parametrize("geom", ["scatter", "gather"])
+def test_wsnap_grid_and_degrid_are_adjoint(lib, geom):
+    rng, d = _case(74, **GEOMETRIES[geom])
     K, ws = _make(lib, d)
     N = d["N"]
     X = np.zeros((N, N), complex)
