@@ -17,10 +17,10 @@ value = visibilities / step time (Mvis/s, gridded + degridded).
 Per-stage times come from HIP events the library records on its launch stream
 (sepw_timing_*); the roofline entry is for the dominant kernel.  The other
 forms (FP16 / BF16 operands, the batched facet launch, the W-stacking hybrid,
-the 2D correction table, channel-shared coordinates, W snapshots) are
-reported beside the FP32 line, each with its error against the oracle.  The
-CPU baseline times the FP64 NumPy oracle on a bounded sample of the same
-workload.
+the 2D correction table, channel-shared coordinates, W snapshots, the
+differentiable prediction) are reported beside the FP32 line, each with its
+error against the oracle.  The CPU baseline times the FP64 NumPy oracle on a
+bounded sample of the same workload.
 """
 import argparse
 import json
@@ -388,6 +388,74 @@ def wsnap_form(_lib, torch, d, u, v, w, V, W, model, steps, n_snap=16, planes=16
     return res
 
 
+def differentiation_form(_lib, torch, steps):
+    """The differentiation workload: a 2048^2 real model, 4,285,440 visibilities
+    (32 antennas, 4 km, 6 h in 20 s dumps, 8 channels), 64 planes, S = 15:
+    V_t = A x_true + complex noise of 0.1 rms(A x_true); one step is
+    chi^2(Predict(x)) and its gradient (degrid forward, gridding adjoint
+    backward) at x = 0.9 x_true; plus the gradient's parity with the oracle's
+    on a 64^2 case."""
+    import numpy as np
+
+    import oracle
+    from paper_1511_07152_amd import autograd, synth
+    d = synth.model_2048()
+    N, fov, S, O, P = d["N"], d["fov"], d["S"], d["O"], d["P"]
+    dev = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x)).to("cuda", dt)  # noqa: E731
+    K = _lib.Kernels(N, fov, S, O, P, d["w_lo"], d["w_hi"])
+    plan = _lib.Plan(K, dev(d["u"], torch.float64), dev(d["v"], torch.float64),
+                     dev(d["w"], torch.float64))
+    xt = dev(d["x"], torch.float32)
+    with torch.no_grad():
+        v0 = autograd.predict(xt, plan)
+        sigma = float(torch.sqrt(torch.mean(torch.abs(v0) ** 2)).item()) * 0.1
+        Vt = v0 + sigma * dev(d["noise"], torch.complex64) / np.sqrt(2.0)
+    W = dev(d["W"], torch.float32)
+
+    def step():
+        x = (0.9 * xt).requires_grad_(True)
+        loss = autograd.chi2(autograd.predict(x, plan), Vt, W)
+        loss.backward()
+        return x.grad
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    res = {"workload": "2048^2 model, %d visibilities, %d planes, S=%d, O=%d" % (plan.nvis, P, S, O),
+           "ms_per_step": round(ms, 3), "Mvis_per_s": round(plan.nvis / (ms * 1e-3) / 1e6, 2)}
+    plan.close()
+    K.close()
+    # gradient parity at 64^2
+    rng = np.random.default_rng(64_001)
+    n2, fov2, S2, O2, P2, nv = 64, float(np.radians(2.0)), 7, 8, 8, 3000
+    u2, v2 = rng.uniform(-26, 26, (2, nv)) / fov2
+    w2 = rng.uniform(-200, 200, nv)
+    x2 = np.zeros((n2, n2))
+    x2[n2 // 4:3 * n2 // 4, n2 // 4:3 * n2 // 4] = rng.standard_normal((n2 // 2, n2 // 2))
+    Vt2 = rng.standard_normal(nv) + 1j * rng.standard_normal(nv)
+    W2 = rng.uniform(0.5, 2.0, nv)
+    K2 = _lib.Kernels(n2, fov2, S2, O2, P2, -200.0, 200.0)
+    p2 = _lib.Plan(K2, dev(u2, torch.float64), dev(v2, torch.float64), dev(w2, torch.float64))
+    x = dev(x2, torch.float32).requires_grad_(True)
+    autograd.chi2(autograd.predict(x, p2), dev(Vt2, torch.complex64), dev(W2, torch.float32)).backward()
+    c1 = oracle.pswf.taper_c1(n2, fov2, S2)
+    q = oracle.quantise.quantise(u2, v2, w2, n2, fov2, O2, S2, P2, -200.0, 200.0, p2.tile_size)
+    T = oracle.tables.separable_table(oracle.tables.w_plane_centres(P2, -200.0, 200.0), n2, fov2,
+                                      S2, O2, c1)
+    want = oracle.chi2.chi2_grad(oracle.chi2.SeparableOperator(q, T, c1, n2, S2, fov2), x2, Vt2, W2)
+    got = x.grad.cpu().numpy()
+    i = slice(n2 // 4, 3 * n2 // 4)
+    res["rel_rms_err_gradient_64"] = float("%.3g" % (np.linalg.norm((got - want)[i, i])
+                                                     / np.linalg.norm(want[i, i])))
+    p2.close()
+    K2.close()
+    return res
+
+
 def batching_form(_lib, torch, args):
     """36 image-plane facets (6 x 6 over 10 deg, 1024^2 each, S = 11, 64 planes,
     log-normal visibility counts): one persistent sepw_grid_batched launch (its
@@ -559,6 +627,8 @@ def main():
         log("channel-shared coordinates: %s" % forms["channel_shared"])
         forms["w_snapshots"] = wsnap_form(_lib, torch, d, u, v, w, V, W, model, min(args.steps, 5))
         log("w-snapshots: %s" % forms["w_snapshots"])
+        forms["differentiation"] = differentiation_form(_lib, torch, args.steps)
+        log("differentiation: %s" % forms["differentiation"])
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mvis/s", "n_gpus": 1,
@@ -571,6 +641,10 @@ def main():
                    "w_planes": P, "precision": "fp32"},
         "roofline": roofline,
         "stages_ms_per_step": {k: round(ms / args.steps, 4) for k, (ms, n) in stages.items()},
+        # context: visibilities over the gridding + degridding kernel time alone
+        # (binning, tables, FFT and correction left out)
+        "grid_degrid_kernels_Mvis_per_s": round(
+            nvis / ((per_launch["grid"] + per_launch["degrid"]) * 1e-3) / 1e6, 2),
     }
     if forms:
         out["precision_forms"] = forms
