@@ -89,3 +89,19 @@ def degrid(q, G, T, C, N, S, O, Sc, Oc, wrap=False):
     """Adjoint of ``grid``: separable degridding plus the correction's."""
     V = gridder.degrid_separable(q, G, T, N, S, wrap=wrap)
     return V + gridder.degrid_exact(coarse_bins(q, O, Oc), G, C, N, Sc, wrap=wrap)
+
+
+def grid_cells(q, y, T, C, N, S, O, Sc, Oc, cells):
+    """Selected grid cells of ``grid``: each the separable sum plus the
+    correction sum over every kept visibility whose footprint covers it (used
+    to check full-size gridding at sampled outputs)."""
+    out = gridder.grid_cells(q, y, T, N, S, cells)
+    qc = coarse_bins(q, O, Oc)
+    h = Sc // 2
+    keep = ~qc['dropped']
+    for n, (jv, ju) in enumerate(cells):
+        su = ju - qc['cell_u'] + h
+        sv = jv - qc['cell_v'] + h
+        i = np.flatnonzero(keep & (su >= 0) & (su < Sc) & (sv >= 0) & (sv < Sc))
+        out[n] += np.sum(y[i] * C[qc['k'][i], qc['fi_u'][i], qc['fi_v'][i], su[i], sv[i]])
+    return out

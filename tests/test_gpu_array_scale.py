@@ -5,7 +5,10 @@ The oracle cannot grid 92.9M visibilities in seconds, so it checks sampled
 outputs it can compute one by one: the bins of a random subset of
 visibilities (bit-exact), a set of grid cells (each summed over every
 visibility whose footprint covers it), degridded visibilities of a random
-subset from a seeded grid, and the adjoint identity through the FFT path.
+subset from a seeded grid, and the adjoint identity through the FFT path;
+also the bins of the same workload given as channel-shared rows (bit-exact)
+and grid cells with the 2D correction table attached (8 planes, so that the
+oracle's table takes seconds).
 """
 import numpy as np
 import pytest
@@ -99,3 +102,55 @@ def test_full_size_adjoint_identity(setup):
     lhs = np.vdot(X, Gy)
     rhs = np.vdot(AX, y.astype(complex))
     assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(Gy[N // 4:3 * N // 4, N // 4:3 * N // 4]) * np.linalg.norm(X)
+
+
+def test_sampled_channel_shared_bins(setup):
+    # the same workload given as uvw rows in metres and 16 channel frequencies
+    lib, d, K, plan, c1, T = setup
+    nchan = len(d["freqs"])
+    pc = lib.Plan.from_channels(K, dev(d["uvw_m"], torch.float64), dev(d["freqs"], torch.float64))
+    assert pc.nvis == len(d["u"]) and pc.n_dropped == 0
+    rng = np.random.default_rng(26)
+    rows = np.sort(rng.choice(len(d["uvw_m"]), 12_500, replace=False))
+    idx = (rows[:, None] * nchan + np.arange(nchan)[None, :]).ravel()
+    got = pc.bins()[torch.as_tensor(idx, device="cuda")].cpu().numpy().astype(np.int64)
+    u, v, w = oracle.quantise.channel_coordinates(d["uvw_m"][rows], d["freqs"])
+    q = oracle.quantise.quantise(u, v, w, d["N"], d["fov"], d["O"], d["S"], d["P"], d["w_lo"],
+                                 d["w_hi"], pc.tile_size)
+    want = np.stack([q['cell_u'], q['fi_u'], q['cell_v'], q['fi_v'], q['k'], q['tile'],
+                     q['dropped'].astype(np.int64)], axis=1)
+    assert np.array_equal(got, want)
+    pc.close()
+
+
+def test_sampled_correction_cells(setup):
+    # the correction table (S_c = 13, O_c = 8) at the full grid and visibility
+    # count, with 8 planes so that the oracle's table takes seconds, not minutes
+    lib, d, K, plan, c1, T = setup
+    N, S, O, P, Sc, Oc = d["N"], d["S"], d["O"], 8, 13, 8
+    K8 = lib.Kernels(N, d["fov"], S, O, P, d["w_lo"], d["w_hi"])
+    K8.set_correction(Sc, Oc)
+    p8 = lib.Plan(K8, dev(d["u"], torch.float64), dev(d["v"], torch.float64),
+                  dev(d["w"], torch.float64))
+    G = lib.grid(p8, dev(d["V"], torch.complex64), dev(d["W"], torch.float32), flags=lib.GRID_ONLY)
+    rng = np.random.default_rng(27)
+    cells = [(N // 2, N // 2), (N // 2 - 3, N // 2 + 2), (N // 2 + 25, N // 2 - 61)]
+    cells += [tuple(int(x) for x in rng.integers(N // 2 - 1500, N // 2 + 1500, 2)) for _ in range(9)]
+    got = np.array([complex(G[a, b].item()) for a, b in cells])
+    q = oracle.quantise.quantise(d["u"], d["v"], d["w"], N, d["fov"], O, S, P, d["w_lo"], d["w_hi"],
+                                 p8.tile_size)
+    wc = oracle.tables.w_plane_centres(P, d["w_lo"], d["w_hi"])
+    T8 = oracle.tables.separable_table(wc, N, d["fov"], S, O, c1)
+    C = oracle.correction.correction_table(wc, N, d["fov"], Sc, Oc, c1)
+    y = d["V"].astype(complex) * d["W"]
+    want = oracle.correction.grid_cells(q, y, T8, C, N, S, O, Sc, Oc, cells)
+    err = rel_rms(got, want)
+    plain = oracle.gridder.grid_cells(q, y, T8, N, S, cells)
+    print("sampled corrected cells: rel RMS %.3e (correction %.3e of the cells)"
+          % (err, rel_rms(plain, want)), flush=True)
+    assert err <= 1e-5
+    # at a 3 deg field the correction is a few 1e-6 of these cells: the match
+    # must be well below that, or the cells could lack the correction
+    assert err < 0.2 * rel_rms(plain, want)
+    p8.close()
+    K8.close()

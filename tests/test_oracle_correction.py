@@ -14,7 +14,8 @@
   (the error falls with S_c and at S_c = S - 2 is within 2x of the exact 2D
   kernel's; with O_c = 2 it still removes most of the separable error), which
   is what the correction is for.
-* Gridding and degridding with the correction are adjoint (FP64).
+* Gridding and degridding with the correction are adjoint (FP64), and the
+  per-cell evaluation used for full-size checks equals the full grid.
 """
 import math
 
@@ -137,3 +138,17 @@ def test_corrected_gridding_and_degridding_are_adjoint(n_power):
     D = imaging.image_from_grid(correction.grid(q, y, T, C, N, S, O, 7, 4), c1, fov, n_power)
     V = correction.degrid(q, imaging.grid_from_image(X, c1, fov, n_power), T, C, N, S, O, 7, 4)
     assert abs(np.vdot(X, D) - np.vdot(V, y)) <= 1e-12 * np.linalg.norm(D) * np.linalg.norm(X)
+
+
+def test_grid_cells_match_the_full_corrected_grid():
+    N, fov, S, O, P, Sc, Oc = 48, 0.5, 7, 8, 3, 5, 4
+    _, u, v, w, y = _vis(61, N, fov, 500, 18, 50.0)
+    c1 = pswf.taper_c1(N, fov, S)
+    q = quantise.quantise(u, v, w, N, fov, O, S, P, -50.0, 50.0, 1)
+    wc = tables.w_plane_centres(P, -50.0, 50.0)
+    T = tables.separable_table(wc, N, fov, S, O, c1)
+    C = correction.correction_table(wc, N, fov, Sc, Oc, c1)
+    G = correction.grid(q, y, T, C, N, S, O, Sc, Oc)
+    cells = [(24, 24), (10, 30), (33, 7), (20, 21), (0, 0)]
+    got = correction.grid_cells(q, y, T, C, N, S, O, Sc, Oc, cells)
+    assert np.max(np.abs(got - np.array([G[a, b] for a, b in cells]))) <= 1e-13 * np.max(np.abs(G))
