@@ -117,21 +117,25 @@ __device__ inline ChunkPos first_chunk(const TileWalk& tw, int c0, int s_end) {
 
 // Operands of one chunk for lane group grp: slots c0 + 4 grp + m.
 struct GridBuf {
-  SlotRec k[4];    // slot records, two chunks ahead
-  float2 y[4];     // W V
+  float2 y[4];     // W V (0 past the chunk's tile)
   uint32_t tv[4];  // 16-bit v-table taps (re | im << 16) of the lane's row
   float2 tu[4];    // FP32 u-table taps of the lane's column
 };
 
-struct LpCtx {
-  const SlotRec* krec;
-  const float2* yrow;
-  int s_end, lane, col, grp;
+// Slot records and W V of the item's slots, one slot per lane, in batches of
+// 64 from the item's first slot: batch A (the one holding the chunk being
+// fetched), A + 1 (a chunk can reach into it) and the records of A + 2.
+// ds_bpermute hands each lane the slots its group supplies, so every record
+// and W V is loaded once instead of once per column lane.
+struct Batches {
+  SlotRec r0, r1, r2;
+  float2 y0, y1;
+  int a;           // batch index of r0
 };
 
-__device__ __forceinline__ void load_grid_rec(const LpCtx& c, const ChunkPos& p, GridBuf& B) {
-#pragma unroll
-  for (int m = 0; m < 4; ++m) B.k[m] = c.krec[min(p.c0 + 4 * c.grp + m, p.pe - 1)];
+__device__ inline int bperm_i(int addr, int v) { return __builtin_amdgcn_ds_bpermute(addr, v); }
+__device__ inline float bperm_f(int addr, float v) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
 }
 
 template <int S, bool BF16>
@@ -144,33 +148,68 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float bound, i
   const int N = a.N, checker = a.checker;
   const uint32_t* __restrict__ lp_v = a.lp_v + col;
   const float2* __restrict__ pad_us = a.pad_us + col;
+  const SlotRec* __restrict__ krec = a.krec;
+  const float2* __restrict__ yrow = a.yrow;
   float* g = reinterpret_cast<float*>(a.grid);
   const int4 item = a.items[it];
   const int ty = uniform(item.x), s_end = uniform(item.z);
+  const int s0 = uniform(item.y), last = s_end - 1;
   const int by = ty * C;
-  LpCtx c{a.krec, a.yrow, s_end, lane, col, grp};
   TileWalk tw;
   tw.start(a.tdesc + (int64_t)ty * a.ntx, a.ntx, uniform(item.w), lane);
-  ChunkPos cur = first_chunk(tw, uniform(item.y), s_end);
+  ChunkPos cur = first_chunk(tw, s0, s_end);
   ChunkPos n1 = next_chunk(cur, tw, s_end, lane);
-  ChunkPos n2 = next_chunk(n1, tw, s_end, lane);
+
+  Batches bt;
+  bt.a = 0;
+  bt.r0 = krec[min(s0 + lane, last)];
+  bt.r1 = krec[min(s0 + 64 + lane, last)];
+  bt.r2 = krec[min(s0 + 128 + lane, last)];
+  bt.y0 = yrow[bt.r0.z];
+  bt.y1 = yrow[bt.r1.z];
+
+  // operands of chunk p into Bf (batches advance monotonically with p)
+  auto fetch = [&](const ChunkPos& p, GridBuf& Bf) {
+    const int bl = (p.c0 - s0) >> 6;
+    while (bl > bt.a) {
+      bt.r0 = bt.r1;
+      bt.y0 = bt.y1;
+      bt.r1 = bt.r2;
+      bt.y1 = yrow[bt.r1.z];
+      bt.a += 1;
+      bt.r2 = krec[min(s0 + 64 * (bt.a + 2) + lane, last)];
+    }
+    const bool straddle = ((min(p.c0 + 15, p.pe - 1) - s0) >> 6) > bt.a;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int s = p.c0 + 4 * grp + m;
+      const int addr = ((s - s0) & 63) << 2;
+      int kx = bperm_i(addr, bt.r0.x), ky = bperm_i(addr, bt.r0.y);
+      float yr = bperm_f(addr, bt.y0.x), yi = bperm_f(addr, bt.y0.y);
+      if (straddle) {
+        const int kx1 = bperm_i(addr, bt.r1.x), ky1 = bperm_i(addr, bt.r1.y);
+        const float yr1 = bperm_f(addr, bt.y1.x), yi1 = bperm_f(addr, bt.y1.y);
+        if (((s - s0) >> 6) > bt.a) {
+          kx = kx1;
+          ky = ky1;
+          yr = yr1;
+          yi = yi1;
+        }
+      }
+      const bool in = s < p.pe;   // slots past the chunk's tile carry no weight
+      Bf.y[m] = in ? make_float2(yr, yi) : make_float2(0.f, 0.f);
+      Bf.tv[m] = lp_v[ky];
+      Bf.tu[m] = pad_us[kx];
+    }
+  };
 
   int tx = cur.tx;
   f32x4 acc_re = {0.f, 0.f, 0.f, 0.f}, acc_im = {0.f, 0.f, 0.f, 0.f};
   float scale = 0.f;   // accumulator holds (true sum) / scale; 0 = not yet set
 
-  // One pipeline step: chunk cur from X while the records of n2 go into X.k
-  // and W V and taps of n1 (records Y.k, loaded one step earlier) into Y.
+  // One pipeline step: chunk cur from X while the operands of n1 go into Y.
   auto step = [&](GridBuf& X, GridBuf& Y) -> bool {
-    // X.k (this chunk's records) was used when its operands were fetched
-#pragma unroll
-    for (int m = 0; m < 4; ++m) X.k[m] = c.krec[min(n2.c0 + 4 * grp + m, n2.pe - 1)];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      Y.y[m] = c.yrow[Y.k[m].z];
-      Y.tv[m] = lp_v[Y.k[m].y];
-      Y.tu[m] = pad_us[Y.k[m].x];
-    }
+    fetch(n1, Y);
     if (cur.tx != tx) {
       // slide the region to this chunk's tile
       const int sh = (cur.tx - tx) * C;
@@ -194,8 +233,7 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float bound, i
     vec a_re, a_im, a_nim;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const bool in = cur.c0 + 4 * grp + m < cur.pe;   // slots past the tile carry no weight
-      const float2 y = in ? X.y[m] : make_float2(0.f, 0.f);
+      const float2 y = X.y[m];
       bre[m] = y.x * X.tu[m].x - y.y * X.tu[m].y;   // row product (u-table times s_k^v)
       bim[m] = y.x * X.tu[m].y + y.y * X.tu[m].x;
       mx = fmaxf(mx, fmaxf(fabsf(y.x), fabsf(y.y)));
@@ -228,20 +266,12 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float bound, i
     acc_im = L::mfma(a_im, b_re, acc_im);
     if (!n1.ok) return false;
     cur = n1;
-    n1 = n2;
-    n2 = next_chunk(n2, tw, s_end, lane);
+    n1 = next_chunk(n1, tw, s_end, lane);
     return true;
   };
 
   GridBuf A, B;
-  load_grid_rec(c, cur, A);
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    A.y[m] = c.yrow[A.k[m].z];
-    A.tv[m] = lp_v[A.k[m].y];
-    A.tu[m] = pad_us[A.k[m].x];
-  }
-  load_grid_rec(c, n1, B);
+  fetch(cur, A);
   while (step(A, B) && step(B, A)) {
   }
   flush_cols(g, acc_re, acc_im, scale, col, grp, tx * C - H, by - H, 16, N, checker);
