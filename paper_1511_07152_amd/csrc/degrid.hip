@@ -103,7 +103,7 @@ __device__ __forceinline__ bool degrid_step(const DegridCtx& c, TileWalk& tw, Ch
                                             ChunkBuf& Y) {
   const DegridArgs& a = *c.a;
   const SlotRec kx = X.k;   // this chunk's record (row-bin position of the result)
-  X.k = a.krec[min(n2.c0 + c.col, n2.pe - 1)];
+  X.k = load_rec(a.krec + min(n2.c0 + c.col, n2.pe - 1));
   fetch_taps(c, Y);
   if (X.fresh) region_fix<S>(cur.tx, c.gy, c.grp, a.N, a.checker, X.reg);
   Y.fresh = n1.ok && n1.tx != cur.tx;
@@ -175,11 +175,11 @@ __device__ __forceinline__ void degrid_item(const DegridArgs& a, const float2* t
 
   // prologue: chunk cur complete in A, record of chunk n1 in B
   ChunkBuf A, B;
-  A.k = a.krec[min(cur.c0 + col, cur.pe - 1)];
+  A.k = load_rec(a.krec + min(cur.c0 + col, cur.pe - 1));
   fetch_taps(c, A);
   load_region<S>(a.grid, a.N, cur.tx, c.gy, grp, A.reg);
   A.fresh = true;
-  B.k = a.krec[min(n1.c0 + col, n1.pe - 1)];
+  B.k = load_rec(a.krec + min(n1.c0 + col, n1.pe - 1));
   while (degrid_step<S>(c, tw, cur, n1, n2, A, B) && degrid_step<S>(c, tw, cur, n1, n2, B, A)) {
   }
 }

@@ -199,9 +199,9 @@ __device__ __forceinline__ void grid_item(const GridArgs& a, float* ring, int it
   st.p3 = st.p1;
 
   // records of batches 0..2 and W V of batches 0 and 1, one slot per lane
-  SlotRec r0 = c.krec[min(c.s0 + lane, c.last)];
-  SlotRec r1 = c.krec[min(c.s0 + 64 + lane, c.last)];
-  SlotRec r2 = c.krec[min(c.s0 + 128 + lane, c.last)];
+  SlotRec r0 = load_rec(c.krec + min(c.s0 + lane, c.last));
+  SlotRec r1 = load_rec(c.krec + min(c.s0 + 64 + lane, c.last));
+  SlotRec r2 = load_rec(c.krec + min(c.s0 + 128 + lane, c.last));
   float2 y0 = c.yrow[r0.z];
   float2 y1 = c.yrow[r1.z];
   GroupOps A, B;   // groups of even / odd index
@@ -226,7 +226,7 @@ __device__ __forceinline__ void grid_item(const GridArgs& a, float* ring, int it
     y0 = y1;
     r1 = r2;
     y1 = c.yrow[r1.z];
-    r2 = c.krec[min(c.s0 + 4 * g + 128 + lane, c.last)];
+    r2 = load_rec(c.krec + min(c.s0 + 4 * g + 128 + lane, c.last));
   }
 done:
   f32x4 re, im;

@@ -16,6 +16,16 @@ namespace sepw {
 __device__ inline int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ inline int round4i(int n) { return (n + 3) & ~3; }
 
+// Slot record load marked non-temporal: records are read once per launch, and
+// the hint keeps them from displacing grid, W V and result lines in the L2
+// (measured: gridding 2.72 -> 2.67 ms, degridding 3.23 -> 3.21 ms at array
+// scale).
+__device__ inline SlotRec load_rec(const SlotRec* p) {
+  const int* q = reinterpret_cast<const int*>(p);
+  return SlotRec{__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1),
+                 __builtin_nontemporal_load(q + 2)};
+}
+
 struct TileWalk {
   const uint2* row;   // descriptors of the row of tiles
   int ntx;            // tiles in the row
