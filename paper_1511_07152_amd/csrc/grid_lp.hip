@@ -11,10 +11,11 @@
 //   * gridding: A = Tv / s_k^v (16-bit table), B = W V (s_k^v Tu) / s formed in
 //     FP32 from the u-table pre-multiplied by s_k^v, with s a power of two at
 //     least max |Re, Im| (W V) times max_k s_k^u s_k^v over the visibilities
-//     gridded into the region so far (it only grows while the region slides,
-//     and restarts when the region is flushed whole); when s grows the FP32
-//     accumulator is rescaled by the exact power of two s_old / s_new, and
-//     flushes multiply by s;
+//     gridded into the tile so far (a per-tile scale: it restarts with each
+//     tile); when s grows the FP32 accumulator is rescaled by the exact power
+//     of two s_old / s_new, and the tile's region sums are multiplied by s
+//     when they are added into the per-wave LDS ring of grid columns (ring.h),
+//     which reaches the grid with atomics 16 columns at a time;
 //   * degridding: A = R / s_R with s_R a power of two at least max |Re, Im|
 //     over the tile's region, B = conj(Tu / s_k^u) (16-bit table); the FP32
 //     epilogue uses the v-table pre-multiplied by s_k^u and multiplies by s_R.
@@ -27,6 +28,7 @@
 // Layout of v_mfma_f32_16x16x16: lane l supplies A[l % 16][4 (l / 16) + m] and
 // B[4 (l / 16) + m][l % 16] for m = 0..3; accumulator register r of lane l is
 // D[4 (l / 16) + r][l % 16].
+#include "ring.h"
 #include "walk.h"
 
 namespace sepw {
@@ -80,29 +82,6 @@ __device__ inline float pow2_ceil(float x) {
   return ldexpf(1.f, f == 0.5f ? e - 1 : e);
 }
 
-__device__ inline float shift_cols(float v, int lane, int col, int sh) {
-  float r = __int_as_float(__builtin_amdgcn_ds_bpermute((lane + sh) << 2, __float_as_int(v)));
-  return col + sh < 16 ? r : 0.f;
-}
-
-__device__ inline void flush_cols(float* g, const f32x4& re, const f32x4& im, float scale,
-                                  int col, int grp, int gx0, int gy0, int ncols, int N,
-                                  int checker) {
-  if (col >= ncols) return;
-  const int gx = gx0 + col;
-  if (gx < 0 || gx >= N) return;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int gy = gy0 + 4 * grp + r;
-    if (gy >= 0 && gy < N) {
-      const float sg = (checker && ((gx + gy) & 1)) ? -scale : scale;
-      const int64_t idx = 2 * ((int64_t)gy * N + gx);
-      unsafeAtomicAdd(g + idx, sg * re[r]);
-      unsafeAtomicAdd(g + idx + 1, sg * im[r]);
-    }
-  }
-}
-
 __device__ inline ChunkPos first_chunk(const TileWalk& tw, int c0, int s_end) {
   ChunkPos p;
   p.c0 = c0;
@@ -138,9 +117,23 @@ __device__ inline float bperm_f(int addr, float v) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
 }
 
+// Add the tile's region sums times s (column x0 + col, rows 4 grp + r) into the ring.
+__device__ inline void ring_add_scaled(float* ring, const f32x4& re, const f32x4& im, float s,
+                                       int x0, int col, int grp) {
+  const int slot = (x0 + col) & (kRing - 1);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    float2* p = reinterpret_cast<float2*>(ring) + (4 * grp + r) * kRingPitch + slot;
+    float2 v = *p;
+    v.x += s * re[r];
+    v.y += s * im[r];
+    *p = v;
+  }
+}
+
 template <int S, bool BF16>
-__device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float bound, int it, int lane,
-                                             int col, int grp) {
+__device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float* ring, float bound, int it,
+                                             int lane, int col, int grp) {
   typedef Lp<BF16> L;
   typedef typename L::vec vec;
   constexpr int C = kRegion + 1 - S;
@@ -204,6 +197,7 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float bound, i
   };
 
   int tx = cur.tx;
+  int fx = tx * C - H;   // first grid column held by the ring
   f32x4 acc_re = {0.f, 0.f, 0.f, 0.f}, acc_im = {0.f, 0.f, 0.f, 0.f};
   float scale = 0.f;   // accumulator holds (true sum) / scale; 0 = not yet set
 
@@ -211,21 +205,21 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float bound, i
   auto step = [&](GridBuf& X, GridBuf& Y) -> bool {
     fetch(n1, Y);
     if (cur.tx != tx) {
-      // slide the region to this chunk's tile
-      const int sh = (cur.tx - tx) * C;
-      flush_cols(g, acc_re, acc_im, scale, col, grp, tx * C - H, by - H, sh < 16 ? sh : 16, N,
-                 checker);
-      if (sh >= 16) {
-        acc_re = f32x4{0.f, 0.f, 0.f, 0.f};
-        acc_im = f32x4{0.f, 0.f, 0.f, 0.f};
-        scale = 0.f;
-      } else {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          acc_re[r] = shift_cols(acc_re[r], lane, col, sh);
-          acc_im[r] = shift_cols(acc_im[r], lane, col, sh);
-        }
+      // the finished tile's region goes into the ring; ring columns no later
+      // tile of the item can reach go to the grid
+      ring_add_scaled(ring, acc_re, acc_im, scale, tx * C - H, col, grp);
+      const int x0 = cur.tx * C - H;
+      if (x0 >= fx + kRing) {
+        ring_flush16(ring, fx, g, by - H, N, checker, lane);
+        ring_flush16(ring, fx + 16, g, by - H, N, checker, lane);
+        fx = x0;
+      } else if (x0 + 16 > fx + kRing) {
+        ring_flush16(ring, fx, g, by - H, N, checker, lane);
+        fx += 16;
       }
+      acc_re = f32x4{0.f, 0.f, 0.f, 0.f};
+      acc_im = f32x4{0.f, 0.f, 0.f, 0.f};
+      scale = 0.f;
       tx = cur.tx;
     }
     // lane's visibilities: slots c0 + 4 grp + m (the K slice it supplies)
@@ -241,7 +235,10 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float bound, i
       L::set_bits(a_im, m, (uint16_t)(X.tv[m] >> 16));
       L::set_bits(a_nim, m, (uint16_t)((X.tv[m] >> 16) ^ 0x8000u));
     }
-    mx = wave_max(mx) * bound;
+    // the 16 lanes of a group hold the same four visibilities: the maximum
+    // over the chunk needs only the exchanges between groups
+    mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+    mx = __int_as_float(uniform(__float_as_int(fmaxf(mx, __shfl_xor(mx, 32, 64))))) * bound;
     if (mx > 0.f) {
       const float sn = pow2_ceil(mx);
       if (scale == 0.f) {
@@ -274,17 +271,22 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float bound, i
   fetch(cur, A);
   while (step(A, B) && step(B, A)) {
   }
-  flush_cols(g, acc_re, acc_im, scale, col, grp, tx * C - H, by - H, 16, N, checker);
+  ring_add_scaled(ring, acc_re, acc_im, scale, tx * C - H, col, grp);
+  ring_flush16(ring, fx, g, by - H, N, checker, lane);
+  ring_flush16(ring, fx + 16, g, by - H, N, checker, lane);
 }
 
 template <int S, bool BF16>
 __global__ __launch_bounds__(64 * kWaves) void grid_lp_kernel(GridArgsLp a) {
-  const int lane = threadIdx.x & 63;
+  __shared__ float rings[kWaves * kRingFloats];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float* ring = rings + wave * kRingFloats;
+  for (int i = lane; i < kRingFloats; i += 64) ring[i] = 0.f;
   const float bound = *a.lp_bound;
   int stride;
   const int n_items = (int)*a.nitems;
   for (int it = uniform(wave_items(kWaves, &stride)); it < n_items; it += stride)
-    grid_lp_item<S, BF16>(a, bound, it, lane, lane & 15, lane >> 4);
+    grid_lp_item<S, BF16>(a, ring, bound, it, lane, lane & 15, lane >> 4);
 }
 
 // ---------------------------------------------------------------- degridding
