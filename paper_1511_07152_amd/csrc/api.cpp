@@ -403,6 +403,8 @@ int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K) {
     const int64_t bytes = (int64_t)sizeof(float2) * npad * (shared_axes ? 1 : 2);
     K->n_cu = ncu > 0 ? ncu : 1;
     K->lds_bytes = bytes <= (int64_t)max_lds ? (int)bytes : 0;
+    const int64_t vs_bytes = (int64_t)sizeof(float2) * npad;
+    K->lds_bytes_vs = vs_bytes <= (int64_t)max_lds ? (int)vs_bytes : 0;
   }
   if (hipfftPlan2d(&K->fft, N, N, HIPFFT_C2C) != HIPFFT_SUCCESS) return SEPW_ERR_FFT;
   K->fft_ok = true;
@@ -1072,17 +1074,18 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
   float2* vo = reinterpret_cast<float2*>(vis_out);
   {
     Stage st(SEPW_STAGE_DEGRID, s);
+    SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8, s));
     if (K->prm.precision == SEPW_FP32) {
-      SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8, s));
       DegridArgs a{p->dl.items, p->dl.itoff + 8 * p->r8, p->dl.itoff, p->r8, p->qctr, p->tdesc, p->krec,
                    src, K->pad_u, K->pad_v,
                    K->tab_len, N, p->ntx, checker, p->yrow};
       SEPW_TRY(launch_degrid_fp32(K->S, a, p->dl.max_items, K->lds_bytes, K->n_cu, s));
     } else {
       DegridArgsLp a{p->dl.items, p->dl.itoff + 8 * p->r8, p->dl.itoff, p->r8, p->qctr, p->tdesc, p->krec,
-                     src, K->lp_u, K->pad_vs, N,
+                     src, K->lp_u, K->pad_vs, K->tab_len, N,
                      p->ntx, checker, p->yrow};
-      SEPW_TRY(launch_degrid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->dl.max_items, s));
+      SEPW_TRY(launch_degrid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->dl.max_items,
+                                K->lds_bytes_vs, K->n_cu, s));
     }
   }
   if (K->corr) {

@@ -318,15 +318,15 @@ struct DegridBuf {
 };
 
 template <int S, bool BF16>
-__device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, int it, int lane, int col,
-                                               int grp) {
+__device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, const float2* vs_tab, int it,
+                                               int lane, int col, int grp) {
   typedef Lp<BF16> L;
   typedef typename L::vec vec;
   constexpr int C = kRegion + 1 - S;
   constexpr int H = S / 2;
   const int N = a.N, checker = a.checker;
   const uint32_t* __restrict__ lp_u = a.lp_u + 4 * grp;      // taps x = 4 grp + m
-  const float2* __restrict__ pad_vs = a.pad_vs + 4 * grp;    // taps y = 4 grp + m
+  const float2* __restrict__ pad_vs = vs_tab + 4 * grp;      // taps y = 4 grp + m
   const SlotRec* __restrict__ krec = a.krec;
   const int4 item = a.items[it];
   const int ty = uniform(item.x), s_end = uniform(item.z);
@@ -418,13 +418,24 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, int it, in
   }
 }
 
-template <int S, bool BF16>
-__global__ __launch_bounds__(64 * kWaves) void degrid_lp_kernel(DegridArgsLp a) {
+// FP32 v-table staged in LDS (LDS = true: one 16-wave workgroup per CU, work
+// items from the per-XCD lists, as in the FP32 path) or read through the caches.
+template <int S, bool BF16, bool LDS>
+__global__ __launch_bounds__(LDS ? 1024 : 64 * kWaves) void degrid_lp_kernel(DegridArgsLp a) {
+  extern __shared__ float2 vs_lds[];
   const int lane = threadIdx.x & 63;
-  int stride;
-  const int n_items = (int)*a.nitems;
-  for (int it = uniform(wave_items(kWaves, &stride)); it < n_items; it += stride)
-    degrid_lp_item<S, BF16>(a, it, lane, lane & 15, lane >> 4);
+  if constexpr (LDS) {
+    for (int i = threadIdx.x; i < a.tab_len; i += blockDim.x) vs_lds[i] = a.pad_vs[i];
+    __syncthreads();
+    for_items(a.lists, a.r8, a.qctr, lane, [&](int it) {
+      degrid_lp_item<S, BF16>(a, vs_lds, it, lane, lane & 15, lane >> 4);
+    });
+  } else {
+    int stride;
+    const int n_items = (int)*a.nitems;
+    for (int it = uniform(wave_items(kWaves, &stride)); it < n_items; it += stride)
+      degrid_lp_item<S, BF16>(a, a.pad_vs, it, lane, lane & 15, lane >> 4);
+  }
 }
 
 int blocks_for(int64_t max_items) {
@@ -441,23 +452,35 @@ void launch_grid_s(const GridArgsLp& a, int64_t max_items, hipStream_t s) {
 }
 
 template <int S, bool BF16>
-void launch_degrid_s(const DegridArgsLp& a, int64_t max_items, hipStream_t s) {
-  const int blocks = blocks_for(max_items);
-  hipLaunchKernelGGL((degrid_lp_kernel<S, BF16>), dim3(blocks), dim3(64 * kWaves), 0, s, a);
+void launch_degrid_s(const DegridArgsLp& a, int64_t max_items, int lds_bytes, int n_cu,
+                     hipStream_t s) {
+  if (lds_bytes > 0) {
+    int64_t b = (max_items + 15) / 16;
+    if (b > n_cu) b = n_cu;
+    if (b < 1) b = 1;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&degrid_lp_kernel<S, BF16, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    hipLaunchKernelGGL((degrid_lp_kernel<S, BF16, true>), dim3((unsigned)b), dim3(1024), lds_bytes,
+                       s, a);
+  } else {
+    const int blocks = blocks_for(max_items);
+    hipLaunchKernelGGL((degrid_lp_kernel<S, BF16, false>), dim3(blocks), dim3(64 * kWaves), 0, s,
+                       a);
+  }
 }
 
 }  // namespace
 
-#define SEPW_LP_CASES(F, A, B, ST)                                                    \
+#define SEPW_LP_CASES(F, A, B, ...)                                                \
   switch (S) {                                                                     \
-    case 1: F<1, B>(A, max_items, ST); break;                                       \
-    case 3: F<3, B>(A, max_items, ST); break;                                       \
-    case 5: F<5, B>(A, max_items, ST); break;                                       \
-    case 7: F<7, B>(A, max_items, ST); break;                                       \
-    case 9: F<9, B>(A, max_items, ST); break;                                       \
-    case 11: F<11, B>(A, max_items, ST); break;                                     \
-    case 13: F<13, B>(A, max_items, ST); break;                                     \
-    case 15: F<15, B>(A, max_items, ST); break;                                     \
+    case 1: F<1, B>(A, max_items, __VA_ARGS__); break;                             \
+    case 3: F<3, B>(A, max_items, __VA_ARGS__); break;                             \
+    case 5: F<5, B>(A, max_items, __VA_ARGS__); break;                             \
+    case 7: F<7, B>(A, max_items, __VA_ARGS__); break;                             \
+    case 9: F<9, B>(A, max_items, __VA_ARGS__); break;                             \
+    case 11: F<11, B>(A, max_items, __VA_ARGS__); break;                           \
+    case 13: F<13, B>(A, max_items, __VA_ARGS__); break;                           \
+    case 15: F<15, B>(A, max_items, __VA_ARGS__); break;                           \
     default: return hipErrorInvalidValue;                                          \
   }
 
@@ -472,11 +495,11 @@ hipError_t launch_grid_lp(int S, bool bf16, const GridArgsLp& a, int64_t max_ite
 }
 
 hipError_t launch_degrid_lp(int S, bool bf16, const DegridArgsLp& a, int64_t max_items,
-                            hipStream_t s) {
+                            int lds_bytes, int n_cu, hipStream_t s) {
   if (bf16) {
-    SEPW_LP_CASES(launch_degrid_s, a, true, s)
+    SEPW_LP_CASES(launch_degrid_s, a, true, lds_bytes, n_cu, s)
   } else {
-    SEPW_LP_CASES(launch_degrid_s, a, false, s)
+    SEPW_LP_CASES(launch_degrid_s, a, false, lds_bytes, n_cu, s)
   }
   return hipGetLastError();
 }

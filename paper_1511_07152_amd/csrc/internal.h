@@ -80,6 +80,7 @@ struct Kernels {
   float2* scratch = nullptr;   // N*N complex64 work grid for degridding
   int tab_len = 0;             // entries of one padded table (P O L)
   int lds_bytes = 0;           // > 0: the FP32 kernels stage the tables in LDS
+  int lds_bytes_vs = 0;        // > 0: the 16-bit degridding kernels stage the FP32 v-table in LDS
   int n_cu = 0;                // compute units of the device
   hipfftHandle fft = 0;
   bool fft_ok = false;
@@ -354,6 +355,7 @@ struct DegridArgsLp {
   const float2* grid;
   const uint32_t* lp_u;     // 16-bit padded u-table / s_k^u
   const float2* pad_vs;     // FP32 padded v-table times s_k^u (epilogue)
+  int tab_len;              // entries of the padded tables
   int N, ntx;
   int checker;
   float2* yrow;
@@ -368,8 +370,9 @@ hipError_t launch_grid_fp32_batched(int S, const GridArgs* jobs, const uint32_t*
 hipError_t launch_job_prefix(const GridArgs* jobs, int njobs, uint32_t* first, uint32_t* counter,
                              hipStream_t s);
 hipError_t launch_grid_lp(int S, bool bf16, const GridArgsLp& a, int64_t max_items, hipStream_t s);
+// lds_bytes > 0: the FP32 v-table (a.tab_len entries) is staged in LDS
 hipError_t launch_degrid_lp(int S, bool bf16, const DegridArgsLp& a, int64_t max_items,
-                            hipStream_t s);
+                            int lds_bytes, int n_cu, hipStream_t s);
 // zero-padded FP32 tables: out[k][fi][c - 1 + s] = tab[k][fi][s] * (scale ? scale[k] : 1)
 hipError_t launch_pad_table(const float2* tab, const float* scale, int P, int O, int S, float2* out,
                             hipStream_t s);
