@@ -113,3 +113,27 @@ def test_heavy_tile_fp16(lib):
     G = lib.grid(plan, dev(d["V"], torch.complex64), dev(d["W"], torch.float32),
                  flags=lib.GRID_ONLY).cpu().numpy()
     assert rel_rms(G, o.grid(d["V"], d["W"])) <= TOL
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_large_tables_cache_path(lib, precision):
+    # P = 256, O = 8, S = 15: the FP32 v-table of the degridding epilogue is
+    # 256 * 8 * 17 * 8 B = 278 KB, more than a workgroup's LDS, so the 16-bit
+    # degridding kernel reads it through the caches (grid-stride items) instead
+    # of staging it in LDS (per-XCD lists); both launches must match the oracle
+    rng = np.random.default_rng(47)
+    N, fov, S, O, P = 64, np.radians(2.0), 15, 8, 256
+    n = 3000
+    d = dict(u=rng.uniform(-24, 24, n) / fov, v=rng.uniform(-24, 24, n) / fov,
+             w=rng.uniform(-200, 200, n), N=N, fov=fov, S=S, O=O, P=P, w_lo=-200.0, w_hi=200.0)
+    V = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    W = rng.uniform(0.5, 2.0, n)
+    K, plan, o = _make(lib, d, precision)
+    G = lib.grid(plan, dev(V, torch.complex64), dev(W, torch.float32),
+                 flags=lib.GRID_ONLY).cpu().numpy()
+    e_grid = rel_rms(G, o.grid(V, W))
+    X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    Vg = lib.degrid(plan, dev(X, torch.complex64), flags=lib.GRID_ONLY).cpu().numpy()
+    e_deg = rel_rms(Vg, o.degrid_grid(X))
+    print("%s, P = 256: grid %.2e degrid %.2e" % (precision, e_grid, e_deg))
+    assert e_grid <= TOL and e_deg <= TOL
