@@ -75,13 +75,6 @@ __device__ inline float wave_max(float x) {
   return x;
 }
 
-// smallest power of two >= x (x > 0)
-__device__ inline float pow2_ceil(float x) {
-  int e;
-  float f = frexpf(x, &e);   // x = f 2^e, f in [0.5, 1)
-  return ldexpf(1.f, f == 0.5f ? e - 1 : e);
-}
-
 __device__ inline ChunkPos first_chunk(const TileWalk& tw, int c0, int s_end) {
   ChunkPos p;
   p.c0 = c0;
@@ -199,7 +192,10 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float* ring, f
   int tx = cur.tx;
   int fx = tx * C - H;   // first grid column held by the ring
   f32x4 acc_re = {0.f, 0.f, 0.f, 0.f}, acc_im = {0.f, 0.f, 0.f, 0.f};
-  float scale = 0.f;   // accumulator holds (true sum) / scale; 0 = not yet set
+  // the accumulator holds (true sum) / scale, scale = 2^es (0 = not yet set);
+  // inv = 1 / scale, kept beside it so that no chunk divides
+  float scale = 0.f, inv = 0.f;
+  int es = 0;
 
   // One pipeline step: chunk cur from X while the operands of n1 go into Y.
   auto step = [&](GridBuf& X, GridBuf& Y) -> bool {
@@ -220,6 +216,7 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float* ring, f
       acc_re = f32x4{0.f, 0.f, 0.f, 0.f};
       acc_im = f32x4{0.f, 0.f, 0.f, 0.f};
       scale = 0.f;
+      inv = 0.f;
       tx = cur.tx;
     }
     // lane's visibilities: slots c0 + 4 grp + m (the K slice it supplies)
@@ -240,17 +237,21 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float* ring, f
     mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
     mx = __int_as_float(uniform(__float_as_int(fmaxf(mx, __shfl_xor(mx, 32, 64))))) * bound;
     if (mx > 0.f) {
-      const float sn = pow2_ceil(mx);
-      if (scale == 0.f) {
-        scale = sn;                     // accumulator is still zero
-      } else if (sn > scale) {
-        const float f = scale / sn;     // exact: both are powers of two
-        acc_re *= f;
-        acc_im *= f;
-        scale = sn;
+      // smallest power of two 2^e >= mx (e kept within +-100, so that 2^-e is finite)
+      int e;
+      const float fm = frexpf(mx, &e);   // mx = fm 2^e, fm in [0.5, 1)
+      e = uniform(min(max(fm == 0.5f ? e - 1 : e, -100), 100));
+      if (scale == 0.f || e > es) {
+        if (scale != 0.f) {
+          const float f = ldexpf(1.f, es - e);   // exact power of two
+          acc_re *= f;
+          acc_im *= f;
+        }
+        es = e;
+        scale = ldexpf(1.f, e);
+        inv = ldexpf(1.f, -e);
       }
     }
-    const float inv = scale > 0.f ? 1.f / scale : 0.f;
     vec b_re, b_im;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -366,8 +367,15 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, const floa
 #pragma unroll
       for (int m = 0; m < 4; ++m) mx = fmaxf(mx, fmaxf(fabsf(X.reg[m].x), fabsf(X.reg[m].y)));
       mx = wave_max(mx);
-      sr = mx > 0.f ? pow2_ceil(mx) : 1.f;
-      const float inv = 1.f / sr;
+      // s_R: the smallest power of two 2^e >= mx (1 for an empty region;
+      // e within +-100, so that 2^-e is finite)
+      int e = 0;
+      if (mx > 0.f) {
+        const float fm = frexpf(mx, &e);
+        e = min(max(fm == 0.5f ? e - 1 : e, -100), 100);
+      }
+      sr = ldexpf(1.f, e);
+      const float inv = ldexpf(1.f, -e);
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         L::set(a_re, m, X.reg[m].x * inv);
