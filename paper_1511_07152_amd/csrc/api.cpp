@@ -1501,7 +1501,6 @@ int sepw_wsnap_degrid(sepw_wsnap ws, const sepw_c64* image, sepw_c64* vis_out, u
     if (!p) continue;
     {
       Stage st(SEPW_STAGE_CORRECT, s);
-      SEPW_TRY(launch_zero_c64(ws->img, (int64_t)N * N, s));
       SEPW_TRY(launch_snap_reproject_adjoint(reinterpret_cast<const float2*>(image), ws->img, N,
                                              K->fov, ws->d0[2 * (size_t)i],
                                              ws->d0[2 * (size_t)i + 1], npow, s));

@@ -281,6 +281,7 @@ hipError_t launch_snap_fit(const double* u, const double* v, const double* w, co
                            double2* d0, double* wr, unsigned long long* maxbits, hipStream_t s);
 hipError_t launch_snap_reproject(const float2* in, float2* out, int N, double fov, double du,
                                  double dv, bool accumulate, hipStream_t s);
+// out = the transposed reprojection of X n^npow (written in full)
 hipError_t launch_snap_reproject_adjoint(const float2* X, float2* out, int N, double fov, double du,
                                          double dv, int npow, hipStream_t s);
 hipError_t launch_snap_npow(float2* out, int N, double fov, int npow, hipStream_t s);

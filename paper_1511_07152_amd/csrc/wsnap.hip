@@ -218,17 +218,23 @@ __global__ void snap_reproject_adjoint_kernel(const float2* __restrict__ X, floa
 
 // Gather form of the transpose, for warps close to the identity.  Snapshot
 // pixel j receives w(x_b - j_x) w(y_b - j_y) X'_b from every output pixel b
-// whose sample point (x_b, y_b) lies within 2 pixels of j on both axes (the
-// same weights as the forward sampling).  A workgroup takes 16 x 16 snapshot
-// pixels: the pre-image p* of the tile centre c under the warp g comes from
-// the fixed-point iteration p <- p + (c - g(p)); the sample points and values
-// of the 32 x 32 output pixels around p* go to LDS; each pixel then scans the
-// 9 x 9 output pixels around j - (c - p*).  With the warp's Jacobian within
-// eps <= 0.1 of the identity (max-norm) every contributor lies within
-// (2 + 8 eps) / (1 - eps) + 1/2 < 4 pixels of that point, inside the scanned
-// window and the box; the launcher checks the bound and otherwise uses the
+// whose sample point (x_b, y_b) = g(b) lies within 2 pixels of j on both axes
+// (the same weights as the forward sampling), and is written (not added).  A
+// workgroup takes 16 x 16 snapshot pixels: the pre-image p* of the tile centre
+// c comes from the fixed-point iteration p <- p + (c - g(p)); the sample
+// points and values of the 32 x 32 output pixels around p* go to LDS.  Each
+// pixel then refines its own pre-image by one more iteration from
+// p* + (j - c), and scans the 5 x 5 output pixels from ceil(q - 2.32).
+// With the warp's Jacobian within eps <= 0.1 of the identity (max-norm):
+// |g(b) - g(p_j)| >= (1 - eps) |b - p_j|, so every contributor lies within
+// 2 / (1 - eps) < 2.223 of p_j; the start p* + (j - c) is within
+// eps |j - c| / (1 - eps) < 0.84 of p_j and the iteration shrinks the error
+// by eps, so the refined q is within 0.084 of p_j: every contributor lies in
+// [q - 2.307, q + 2.307], whose integers (at most five) are the ones scanned.
+// All of them lie within 8.4 + 2.8 < 12 pixels of p*, inside the box.  The
+// launcher checks the bound and otherwise zeroes the output and uses the
 // scatter kernel above.
-constexpr int kGTile = 16, kGBox = 32, kGRad = 4;
+constexpr int kGTile = 16, kGBox = 32, kGScan = 5;
 
 __device__ inline void warp_at(double p, double q, int N, double fov, double du, double dv,
                                double& x, double& y) {
@@ -279,12 +285,20 @@ __global__ __launch_bounds__(kGTile * kGTile) void snap_adjoint_gather_kernel(
   __syncthreads();
   const int jx = tx0 + (threadIdx.x % kGTile), jy = ty0 + (threadIdx.x / kGTile);
   if (jx >= N || jy >= N) return;
-  const int cp = (int)rint((double)jx - (cx - px)) - ox, cq = (int)rint((double)jy - (cy - py)) - oy;
+  // this pixel's pre-image, from the tile's translation and one iteration
+  double qx = px + (jx - cx), qy = py + (jy - cy);
+  {
+    double x, y;
+    warp_at(qx, qy, N, fov, du, dv, x, y);
+    qx += jx - x;
+    qy += jy - y;
+  }
+  const int cp = (int)ceil(qx - 2.32) - ox, cq = (int)ceil(qy - 2.32) - oy;
   float ar = 0.f, ai = 0.f;
-  for (int b = -kGRad; b <= kGRad; ++b) {
+  for (int b = 0; b < kGScan; ++b) {
     const int qq = cq + b;
     if (qq < 0 || qq >= kGBox) continue;
-    for (int a = -kGRad; a <= kGRad; ++a) {
+    for (int a = 0; a < kGScan; ++a) {
       const int pp = cp + a;
       if (pp < 0 || pp >= kGBox) continue;
       const int e = qq * kGBox + pp;
@@ -296,8 +310,7 @@ __global__ __launch_bounds__(kGTile * kGTile) void snap_adjoint_gather_kernel(
       }
     }
   }
-  const float2 o = out[(int64_t)jy * N + jx];
-  out[(int64_t)jy * N + jx] = make_float2(o.x + ar, o.y + ai);
+  out[(int64_t)jy * N + jx] = make_float2(ar, ai);
 }
 
 // out *= n^npow
@@ -351,6 +364,8 @@ hipError_t launch_snap_reproject_adjoint(const float2* X, float2* out, int N, do
     hipLaunchKernelGGL(snap_adjoint_gather_kernel, dim3(nt, nt), dim3(kGTile * kGTile), 0, s, X, out,
                        N, fov, du, dv, npow);
   } else {
+    hipError_t e = launch_zero_c64(out, (int64_t)N * N, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(snap_reproject_adjoint_kernel, grid_for((int64_t)N * N), dim3(kThreads), 0, s,
                        X, out, N, fov, du, dv, npow);
   }
