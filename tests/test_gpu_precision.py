@@ -137,3 +137,33 @@ def test_large_tables_cache_path(lib, precision):
     e_deg = rel_rms(Vg, o.degrid_grid(X))
     print("%s, P = 256: grid %.2e degrid %.2e" % (precision, e_grid, e_deg))
     assert e_grid <= TOL and e_deg <= TOL
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+@pytest.mark.parametrize("N,S", [(64, 15), (40, 7)])
+def test_grid_corners(lib, precision, N, S):
+    # Footprints at all four grid edges and corners with the 16-bit kernels:
+    # the edge tiles' regions reach past the grid, so the ring flushes and the
+    # region loads clip there (cells h .. N-1-h keep every footprint inside)
+    rng = np.random.default_rng(53 + N)
+    fov, O, P = np.radians(2.0), 8, 4
+    h = S // 2
+    lo, hi = h, N - 1 - h
+    corners = np.array([(a, b) for a in (lo, hi) for b in (lo, hi)] * 30)
+    edges = np.array([(a, b) for a in (lo, hi) for b in rng.integers(lo, hi + 1, 20)] +
+                     [(b, a) for a in (lo, hi) for b in rng.integers(lo, hi + 1, 20)])
+    cells = np.concatenate([corners, edges, rng.integers(lo, hi + 1, (300, 2))]).astype(float)
+    n = len(cells)
+    d = dict(u=(cells[:, 0] - N // 2 + rng.uniform(-0.4, 0.4, n)) / fov,
+             v=(cells[:, 1] - N // 2 + rng.uniform(-0.4, 0.4, n)) / fov,
+             w=rng.uniform(-100, 100, n), N=N, fov=fov, S=S, O=O, P=P, w_lo=-100.0, w_hi=100.0)
+    V = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    W = rng.uniform(0.5, 2.0, n)
+    K, plan, o = _make(lib, d, precision)
+    G = lib.grid(plan, dev(V, torch.complex64), dev(W, torch.float32),
+                 flags=lib.GRID_ONLY).cpu().numpy()
+    X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    Vg = lib.degrid(plan, dev(X, torch.complex64), flags=lib.GRID_ONLY).cpu().numpy()
+    e_grid, e_deg = rel_rms(G, o.grid(V, W)), rel_rms(Vg, o.degrid_grid(X))
+    print("%s, N = %d, S = %d corners: grid %.2e degrid %.2e" % (precision, N, S, e_grid, e_deg))
+    assert e_grid <= TOL and e_deg <= TOL
