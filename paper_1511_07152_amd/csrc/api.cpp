@@ -45,7 +45,8 @@ struct sepw_wsnap_s {
   std::vector<double> d0;        // [2 ns]
   std::vector<Plan*> plans;      // [ns], null for empty snapshots
   double h = 0.0;                // residual w range [-h, h]
-  float2* img = nullptr;         // [N N] one snapshot's image
+  float2* img = nullptr;         // [nimg N N] snapshot images (gridded nimg at a time)
+  int nimg = 1;
 };
 
 namespace {
@@ -714,6 +715,7 @@ void destroy_wsnap(sepw_wsnap_s* ws) {
 }
 
 constexpr int64_t kSnapBlock = 65536;   // visibilities per block of the plane fit
+constexpr int64_t kSnapImageBytes = 4ll << 30;   // snapshot images gridded in one batch
 
 // Fit the planes, form the residual w, set the kernels' range to it and bin
 // each snapshot.
@@ -1430,7 +1432,10 @@ int sepw_wsnap_create(sepw_kernels k, int32_t n_snap, const int64_t* offsets, co
   W->off.assign(offsets, offsets + n_snap + 1);
   W->d0.assign(2 * (size_t)n_snap, 0.0);
   W->plans.assign(n_snap, nullptr);
-  int rc = map_hip(dalloc(&W->img, (int64_t)k->N * k->N));
+  // images for batched gridding: as many snapshots as fit in kSnapImageBytes
+  const int64_t img_bytes = (int64_t)sizeof(float2) * k->N * k->N;
+  W->nimg = (int)std::max<int64_t>(1, std::min<int64_t>(n_snap, kSnapImageBytes / img_bytes));
+  int rc = map_hip(dalloc(&W->img, (int64_t)W->nimg * k->N * k->N));
   if (rc == SEPW_OK) rc = wsnap_build(W, u, v, w, s);
   int64_t dropped = 0;
   for (int i = 0; i < n_snap && rc == SEPW_OK && n_dropped; ++i) {
@@ -1469,16 +1474,37 @@ int sepw_wsnap_grid(sepw_wsnap ws, const sepw_c64* vis, const float* weight, sep
     Stage st(SEPW_STAGE_FILL, s);
     SEPW_TRY(launch_zero_c64(out, (int64_t)N * N, s));
   }
-  for (int i = 0; i < ws->ns; ++i) {
-    Plan* p = ws->plans[i];
-    if (!p) continue;
-    const int64_t o = ws->off[i];
-    int rc = sepw_grid(static_cast<sepw_plan>(p), vis + o, weight ? weight + o : nullptr,
-                       reinterpret_cast<sepw_c64*>(ws->img), 0u, hip_stream);
+  // the snapshots' images, up to nimg of them in one batched gridding launch
+  // (independent jobs on the same tables), each then reprojected into out
+  std::vector<sepw_plan> plans;
+  std::vector<const sepw_c64*> vs;
+  std::vector<const float*> ws_;
+  std::vector<sepw_c64*> imgs;
+  std::vector<int> idx;
+  for (int i0 = 0; i0 < ws->ns;) {
+    plans.clear();
+    vs.clear();
+    ws_.clear();
+    imgs.clear();
+    idx.clear();
+    for (; i0 < ws->ns && (int)idx.size() < ws->nimg; ++i0) {
+      if (!ws->plans[i0]) continue;
+      const int64_t o = ws->off[i0];
+      plans.push_back(static_cast<sepw_plan>(ws->plans[i0]));
+      vs.push_back(vis + o);
+      ws_.push_back(weight ? weight + o : nullptr);
+      imgs.push_back(reinterpret_cast<sepw_c64*>(ws->img + (int64_t)idx.size() * N * N));
+      idx.push_back(i0);
+    }
+    if (idx.empty()) break;
+    int rc = sepw_grid_batched((int32_t)idx.size(), plans.data(), vs.data(), ws_.data(),
+                               imgs.data(), 0u, hip_stream);
     if (rc != SEPW_OK) return rc;
     Stage st(SEPW_STAGE_CORRECT, s);
-    SEPW_TRY(launch_snap_reproject(ws->img, out, N, K->fov, ws->d0[2 * (size_t)i],
-                                   ws->d0[2 * (size_t)i + 1], true, s));
+    for (size_t j = 0; j < idx.size(); ++j)
+      SEPW_TRY(launch_snap_reproject(reinterpret_cast<const float2*>(imgs[j]), out, N, K->fov,
+                                     ws->d0[2 * (size_t)idx[j]], ws->d0[2 * (size_t)idx[j] + 1],
+                                     true, s));
   }
   const int npow = (flags & SEPW_MUL_N) ? 1 : ((flags & SEPW_DIV_N) ? -1 : 0);
   if (npow) {
