@@ -348,7 +348,10 @@ int sepw_free_wstack(sepw_wstack ws);
  * and the snapshot is binned on its residual w' = w - (d_u u + d_v v) into the
  * P planes of k, whose w range create sets to [-h, h], h = max |w'| (1 + 2^-20)
  * (1 if every w' is 0; k's tables are regenerated, so plans made earlier from
- * k become invalid).  Synchronises the stream.
+ * k become invalid).  Synchronises the stream.  The object holds, besides a
+ * plan per snapshot, as many N x N complex64 snapshot images as fit in 4 GiB
+ * (at least one, at most n_snap): sepw_wsnap_grid grids that many snapshots
+ * in one batched launch (sepw_grid_batched).
  * sepw_wsnap_grid: image_out (DEVICE complex64 [N N]) = sum over snapshots of
  *   R_s[F+[G_s] / (c1 c1)], times n (SEPW_MUL_N) or over n (SEPW_DIV_N), where
  *   G_s is the snapshot's separable gridding on w' and R_s the reprojection:
