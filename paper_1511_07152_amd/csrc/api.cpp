@@ -578,6 +578,8 @@ struct BatchScratch {
   MoveArgs* mjobs = nullptr;    // device
   uint32_t* mfirst_host = nullptr;  // pinned [cap + 1] first workgroup per job
   uint32_t* mfirst = nullptr;       // device
+  DegridArgs* dhost = nullptr;  // pinned degridding job table
+  DegridArgs* djobs = nullptr;  // device
   uint32_t* first = nullptr;    // device [cap + 1]
   uint32_t* counter = nullptr;  // device
   hipEvent_t copied = nullptr;
@@ -597,6 +599,8 @@ int batch_scratch(int njobs, hipStream_t s, BatchScratch** out) {
     if (b.host) (void)hipHostFree(b.host);
     if (b.mhost) (void)hipHostFree(b.mhost);
     if (b.mfirst_host) (void)hipHostFree(b.mfirst_host);
+    if (b.dhost) (void)hipHostFree(b.dhost);
+    dfree(b.djobs);
     dfree(b.jobs);
     dfree(b.mjobs);
     dfree(b.mfirst);
@@ -609,6 +613,8 @@ int batch_scratch(int njobs, hipStream_t s, BatchScratch** out) {
     SEPW_TRY(hipHostMalloc(reinterpret_cast<void**>(&b.mhost), sizeof(MoveArgs) * (size_t)cap));
     SEPW_TRY(hipHostMalloc(reinterpret_cast<void**>(&b.mfirst_host),
                            sizeof(uint32_t) * (size_t)(cap + 1)));
+    SEPW_TRY(hipHostMalloc(reinterpret_cast<void**>(&b.dhost), sizeof(DegridArgs) * (size_t)cap));
+    SEPW_TRY(dalloc(&b.djobs, cap));
     SEPW_TRY(dalloc(&b.jobs, cap));
     SEPW_TRY(dalloc(&b.mjobs, cap));
     SEPW_TRY(dalloc(&b.mfirst, cap + 1));
@@ -1522,19 +1528,77 @@ int sepw_wsnap_degrid(sepw_wsnap ws, const sepw_c64* image, sepw_c64* vis_out, u
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const int N = K->N;
   const int npow = (flags & SEPW_DIV_N) ? -1 : 0;
-  for (int i = 0; i < ws->ns; ++i) {
-    Plan* p = ws->plans[i];
-    if (!p) continue;
-    {
-      Stage st(SEPW_STAGE_CORRECT, s);
-      SEPW_TRY(launch_snap_reproject_adjoint(reinterpret_cast<const float2*>(image), ws->img, N,
-                                             K->fov, ws->d0[2 * (size_t)i],
-                                             ws->d0[2 * (size_t)i + 1], npow, s));
+  if (K->prm.precision != SEPW_FP32 || ws->nimg < 2) {
+    for (int i = 0; i < ws->ns; ++i) {
+      Plan* p = ws->plans[i];
+      if (!p) continue;
+      {
+        Stage st(SEPW_STAGE_CORRECT, s);
+        SEPW_TRY(launch_snap_reproject_adjoint(reinterpret_cast<const float2*>(image), ws->img, N,
+                                               K->fov, ws->d0[2 * (size_t)i],
+                                               ws->d0[2 * (size_t)i + 1], npow, s));
+      }
+      int rc = sepw_degrid(static_cast<sepw_plan>(p), reinterpret_cast<const sepw_c64*>(ws->img),
+                           vis_out + ws->off[i], 0u, hip_stream);
+      if (rc != SEPW_OK) return rc;
     }
-    int rc = sepw_degrid(static_cast<sepw_plan>(p), reinterpret_cast<const sepw_c64*>(ws->img),
-                         vis_out + ws->off[i], 0u,
-                         hip_stream);
+    return SEPW_OK;
+  }
+  // FP32: per snapshot the transposed reprojection, correction and FFT into
+  // its own grid, then the snapshots' degridding in one batched launch (up to
+  // nimg at a time; all share the residual tables), then per snapshot the
+  // correction pass and the move to caller order
+  std::vector<int> idx;
+  for (int i0 = 0; i0 < ws->ns;) {
+    idx.clear();
+    for (; i0 < ws->ns && (int)idx.size() < ws->nimg; ++i0)
+      if (ws->plans[i0]) idx.push_back(i0);
+    if (idx.empty()) break;
+    const int nj = (int)idx.size();
+    for (int j = 0; j < nj; ++j) {
+      const int i = idx[j];
+      float2* g = ws->img + (int64_t)j * N * N;
+      {
+        Stage st(SEPW_STAGE_CORRECT, s);
+        SEPW_TRY(launch_snap_reproject_adjoint(reinterpret_cast<const float2*>(image), g, N, K->fov,
+                                               ws->d0[2 * (size_t)i], ws->d0[2 * (size_t)i + 1],
+                                               npow, s));
+        SEPW_TRY(launch_correct(g, g, K->c1, N, K->fov, K->l0, K->m0, 0, s));
+      }
+      Stage st(SEPW_STAGE_FFT, s);
+      int rc = fft_exec(K, g, HIPFFT_FORWARD, s);
+      if (rc != SEPW_OK) return rc;
+    }
+    BatchScratch* bs = nullptr;
+    int rc = batch_scratch(nj, s, &bs);
     if (rc != SEPW_OK) return rc;
+    for (int j = 0; j < nj; ++j) {
+      Plan* p = ws->plans[idx[j]];
+      bs->dhost[j] = DegridArgs{p->dl.items, p->dl.itoff + 8 * p->r8, p->dl.itoff, p->r8, p->qctr,
+                                p->tdesc, p->krec, ws->img + (int64_t)j * N * N, K->pad_u,
+                                K->pad_v, K->tab_len, N, p->ntx, 1, p->yrow};
+    }
+    SEPW_TRY(hipMemcpyAsync(bs->djobs, bs->dhost, sizeof(DegridArgs) * (size_t)nj,
+                            hipMemcpyHostToDevice, s));
+    SEPW_TRY(hipEventRecord(bs->copied, s));
+    {
+      Stage st(SEPW_STAGE_DEGRID, s);
+      SEPW_TRY(launch_job_prefix(bs->djobs, nj, bs->first, bs->counter, s));
+      SEPW_TRY(launch_degrid_fp32_batched(K->S, bs->djobs, bs->first, nj, bs->counter,
+                                          K->lds_bytes, K->n_cu, s));
+    }
+    for (int j = 0; j < nj; ++j) {
+      Plan* p = ws->plans[idx[j]];
+      float2* g = ws->img + (int64_t)j * N * N;
+      if (K->corr) {
+        Stage st(SEPW_STAGE_CORR_APPLY, s);
+        SEPW_TRY(launch_corr_degrid(K->S, corr_args(p, p->dl, g, 1), p->dl.max_items, s));
+      }
+      Stage st(SEPW_STAGE_GATHER, s);
+      SEPW_TRY(launch_vis_from_rows(p->yrow, p->rot, p->place, p->delta, p->ckept, p->nvis,
+                                    p->nbins, reinterpret_cast<float2*>(vis_out + ws->off[idx[j]]),
+                                    s));
+    }
   }
   return SEPW_OK;
 }

@@ -219,7 +219,8 @@ __global__ void items_kernel(const uint2* __restrict__ tdesc, const uint32_t* __
   }
 }
 
-__global__ void job_prefix_kernel(const GridArgs* __restrict__ jobs, int njobs,
+template <class Args>
+__global__ void job_prefix_kernel(const Args* __restrict__ jobs, int njobs,
                                   uint32_t* __restrict__ first, uint32_t* __restrict__ counter) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   uint32_t acc = 0;
@@ -1005,7 +1006,15 @@ hipError_t launch_items(const uint2* tdesc, const uint32_t* itoff, int ntx, int 
 
 hipError_t launch_job_prefix(const GridArgs* jobs, int njobs, uint32_t* first, uint32_t* counter,
                              hipStream_t s) {
-  hipLaunchKernelGGL(job_prefix_kernel, dim3(1), dim3(64), 0, s, jobs, njobs, first, counter);
+  hipLaunchKernelGGL(job_prefix_kernel<GridArgs>, dim3(1), dim3(64), 0, s, jobs, njobs, first,
+                     counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_job_prefix(const DegridArgs* jobs, int njobs, uint32_t* first, uint32_t* counter,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(job_prefix_kernel<DegridArgs>, dim3(1), dim3(64), 0, s, jobs, njobs, first,
+                     counter);
   return hipGetLastError();
 }
 

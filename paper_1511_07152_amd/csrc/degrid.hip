@@ -209,6 +209,57 @@ __global__ __launch_bounds__(LDS ? 1024 : 256) void degrid_fp32_kernel(DegridArg
             [&](int it) { degrid_item<S>(a, tu_tab, tv_tab, it, lane, lane & 15, lane >> 4); });
 }
 
+// Many jobs with the same tables in one launch: a wave takes global item gi,
+// the item gi - first[job] of the job with first[job] <= gi < first[job + 1].
+template <int S, bool LDS>
+__global__ __launch_bounds__(LDS ? 1024 : 256) void degrid_fp32_batched_kernel(
+    const DegridArgs* __restrict__ jobs, const uint32_t* __restrict__ first, int njobs,
+    uint32_t* __restrict__ counter) {
+  extern __shared__ float2 smem[];
+  const float2* tu_tab = jobs[0].tab_u;
+  const float2* tv_tab = jobs[0].tab_v;
+  if constexpr (LDS) {
+    const int n = jobs[0].tab_len;
+    const bool two = tv_tab != tu_tab;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) smem[i] = tu_tab[i];
+    if (two)
+      for (int i = threadIdx.x; i < n; i += blockDim.x) smem[n + i] = tv_tab[i];
+    __syncthreads();
+    tv_tab = two ? smem + n : smem;
+    tu_tab = smem;
+  }
+  const int lane = threadIdx.x & 63;
+  const uint32_t total = first[njobs];
+  while (true) {
+    uint32_t gi = 0;
+    if (lane == 0) gi = atomicAdd(counter, 1u);
+    gi = (uint32_t)uniform((int)__shfl(gi, 0, 64));
+    if (gi >= total) break;
+    int lo = 0, hi = njobs - 1;   // last job with first[job] <= gi
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (first[mid] <= gi) lo = mid; else hi = mid - 1;
+    }
+    const int job = uniform(lo);
+    degrid_item<S>(jobs[job], tu_tab, tv_tab, (int)(gi - first[job]), lane, lane & 15, lane >> 4);
+  }
+}
+
+template <int S>
+hipError_t launch_batched_s(const DegridArgs* jobs, const uint32_t* first, int njobs,
+                            uint32_t* counter, int lds_bytes, int n_cu, hipStream_t s) {
+  if (lds_bytes > 0) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&degrid_fp32_batched_kernel<S, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    hipLaunchKernelGGL((degrid_fp32_batched_kernel<S, true>), dim3((unsigned)n_cu), dim3(1024),
+                       lds_bytes, s, jobs, first, njobs, counter);
+  } else {
+    hipLaunchKernelGGL((degrid_fp32_batched_kernel<S, false>), dim3((unsigned)(4 * n_cu)),
+                       dim3(256), 0, s, jobs, first, njobs, counter);
+  }
+  return hipGetLastError();
+}
+
 template <int S>
 hipError_t launch_s(const DegridArgs& a, int64_t max_items, int lds_bytes, int n_cu,
                     hipStream_t s) {
@@ -231,6 +282,22 @@ hipError_t launch_s(const DegridArgs& a, int64_t max_items, int lds_bytes, int n
 }
 
 }  // namespace
+
+hipError_t launch_degrid_fp32_batched(int S, const DegridArgs* jobs, const uint32_t* first,
+                                      int njobs, uint32_t* counter, int lds_bytes, int n_cu,
+                                      hipStream_t s) {
+  switch (S) {
+    case 1: return launch_batched_s<1>(jobs, first, njobs, counter, lds_bytes, n_cu, s);
+    case 3: return launch_batched_s<3>(jobs, first, njobs, counter, lds_bytes, n_cu, s);
+    case 5: return launch_batched_s<5>(jobs, first, njobs, counter, lds_bytes, n_cu, s);
+    case 7: return launch_batched_s<7>(jobs, first, njobs, counter, lds_bytes, n_cu, s);
+    case 9: return launch_batched_s<9>(jobs, first, njobs, counter, lds_bytes, n_cu, s);
+    case 11: return launch_batched_s<11>(jobs, first, njobs, counter, lds_bytes, n_cu, s);
+    case 13: return launch_batched_s<13>(jobs, first, njobs, counter, lds_bytes, n_cu, s);
+    case 15: return launch_batched_s<15>(jobs, first, njobs, counter, lds_bytes, n_cu, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_degrid_fp32(int S, const DegridArgs& a, int64_t max_items, int lds_bytes,
                               int n_cu, hipStream_t s) {

@@ -370,6 +370,8 @@ hipError_t launch_grid_fp32_batched(int S, const GridArgs* jobs, const uint32_t*
 // first[j + 1] = first[j] + *jobs[j].nitems, first[0] = 0; counter = 0
 hipError_t launch_job_prefix(const GridArgs* jobs, int njobs, uint32_t* first, uint32_t* counter,
                              hipStream_t s);
+hipError_t launch_job_prefix(const DegridArgs* jobs, int njobs, uint32_t* first, uint32_t* counter,
+                             hipStream_t s);
 hipError_t launch_grid_lp(int S, bool bf16, const GridArgsLp& a, int64_t max_items, hipStream_t s);
 // lds_bytes > 0: the FP32 v-table (a.tab_len entries) is staged in LDS
 hipError_t launch_degrid_lp(int S, bool bf16, const DegridArgsLp& a, int64_t max_items,
@@ -388,6 +390,12 @@ hipError_t launch_lp_bound(const float* su, const float* sv, int P, float* bound
 // tab_u == tab_v) in LDS, with workgroups that own a whole CU
 hipError_t launch_degrid_fp32(int S, const DegridArgs& a, int64_t max_items, int lds_bytes,
                               int n_cu, hipStream_t s);
+// persistent launch over the items of njobs jobs that share one set of tables
+// (jobs[0]'s, staged in LDS when lds_bytes > 0); first[njobs + 1] = prefix of
+// per-job item counts (device), counter = zeroed device word
+hipError_t launch_degrid_fp32_batched(int S, const DegridArgs* jobs, const uint32_t* first,
+                                      int njobs, uint32_t* counter, int lds_bytes, int n_cu,
+                                      hipStream_t s);
 
 // out[q][p] = in[q][p] (-1)^(p+q) n(l0 + l_p, m0 + m_q)^npow / (c1[p] c1[q])
 hipError_t launch_correct(const float2* in, float2* out, const double* c1, int N, double fov,
