@@ -32,7 +32,8 @@ struct sepw_wstack_s {
   std::vector<Plan*> plans;      // [ns], null for empty slices
   uint32_t* order = nullptr;     // [nvis] slice-ordered position -> caller index
   float2* vis = nullptr;         // [nvis] slice-ordered W V (gridding) or results (degridding)
-  float2* img = nullptr;         // [N N] one slice's image
+  float2* img = nullptr;         // [nimg N N] slice images (gridded or degridded nimg at a time)
+  int nimg = 1;
 };
 
 // W snapshots (Section 4.2): per snapshot (a contiguous range of the caller's
@@ -633,6 +634,64 @@ int batch_scratch(int njobs, hipStream_t s, BatchScratch** out) {
   return SEPW_OK;
 }
 
+// Degridding of nj FP32 plans on the same kernels K from images held in
+// grids (N x N each, consecutive): per plan the correction (times n^npow) and
+// the FFT in place, then ONE batched persistent degridding launch over the
+// plans' items, then per plan the correction-table pass and the move of its
+// results into vis[j] (its caller order).
+int degrid_images_batched(Kernels* K, Plan* const* plans, int nj, float2* grids, int npow,
+                          float2* const* vis, hipStream_t s) {
+  const int N = K->N;
+  for (int j = 0; j < nj; ++j) {
+    float2* g = grids + (int64_t)j * N * N;
+    {
+      Stage st(SEPW_STAGE_CORRECT, s);
+      SEPW_TRY(launch_correct(g, g, K->c1, N, K->fov, K->l0, K->m0, npow, s));
+    }
+    Stage st(SEPW_STAGE_FFT, s);
+    int rc = fft_exec(K, g, HIPFFT_FORWARD, s);
+    if (rc != SEPW_OK) return rc;
+  }
+  BatchScratch* bs = nullptr;
+  int rc = batch_scratch(nj, s, &bs);
+  if (rc != SEPW_OK) return rc;
+  for (int j = 0; j < nj; ++j) {
+    const Plan* p = plans[j];
+    bs->dhost[j] = DegridArgs{p->dl.items, p->dl.itoff + 8 * p->r8, p->dl.itoff, p->r8, p->qctr,
+                              p->tdesc, p->krec, grids + (int64_t)j * N * N, K->pad_u, K->pad_v,
+                              K->tab_len, N, p->ntx, 1, p->yrow};
+  }
+  SEPW_TRY(hipMemcpyAsync(bs->djobs, bs->dhost, sizeof(DegridArgs) * (size_t)nj,
+                          hipMemcpyHostToDevice, s));
+  SEPW_TRY(hipEventRecord(bs->copied, s));
+  {
+    Stage st(SEPW_STAGE_DEGRID, s);
+    SEPW_TRY(launch_job_prefix(bs->djobs, nj, bs->first, bs->counter, s));
+    SEPW_TRY(launch_degrid_fp32_batched(K->S, bs->djobs, bs->first, nj, bs->counter, K->lds_bytes,
+                                        K->n_cu, s));
+  }
+  for (int j = 0; j < nj; ++j) {
+    Plan* p = plans[j];
+    if (K->corr) {
+      Stage st(SEPW_STAGE_CORR_APPLY, s);
+      SEPW_TRY(launch_corr_degrid(K->S, corr_args(p, p->dl, grids + (int64_t)j * N * N, 1),
+                                  p->dl.max_items, s));
+    }
+    Stage st(SEPW_STAGE_GATHER, s);
+    SEPW_TRY(launch_vis_from_rows(p->yrow, p->rot, p->place, p->delta, p->ckept, p->nvis,
+                                  p->nbins, vis[j], s));
+  }
+  return SEPW_OK;
+}
+
+// Images gridded or degridded in one batch by the multi-plan hybrids: as many
+// N x N complex64 images as fit in kBatchImageBytes (at least 1, at most n).
+constexpr int64_t kBatchImageBytes = 4ll << 30;
+int batch_images(int N, int n) {
+  const int64_t img_bytes = (int64_t)sizeof(float2) * N * N;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(n, kBatchImageBytes / img_bytes));
+}
+
 void destroy_wstack(sepw_wstack_s* W) {
   if (!W) return;
   for (Plan* p : W->plans) destroy_plan(p);
@@ -657,7 +716,8 @@ int wstack_build(sepw_wstack_s* W, Kernels* K, int ns, double w_lo, double w_hi,
   W->plans.assign(ns, nullptr);
   SEPW_TRY(dalloc(&W->order, std::max<int64_t>(nvis, 1)));
   SEPW_TRY(dalloc(&W->vis, std::max<int64_t>(nvis, 1)));
-  SEPW_TRY(dalloc(&W->img, (int64_t)K->N * K->N));
+  W->nimg = batch_images(K->N, ns);
+  SEPW_TRY(dalloc(&W->img, (int64_t)W->nimg * K->N * K->N));
   uint32_t* count = nullptr;
   double *cdev = nullptr, *us = nullptr, *vs = nullptr, *wsr = nullptr;
   auto cleanup = [&]() {
@@ -721,7 +781,6 @@ void destroy_wsnap(sepw_wsnap_s* ws) {
 }
 
 constexpr int64_t kSnapBlock = 65536;   // visibilities per block of the plane fit
-constexpr int64_t kSnapImageBytes = 4ll << 30;   // snapshot images gridded in one batch
 
 // Fit the planes, form the residual w, set the kernels' range to it and bin
 // each snapshot.
@@ -1368,16 +1427,39 @@ int sepw_wstack_grid(sepw_wstack ws, const sepw_c64* vis, const float* weight, s
     SEPW_TRY(launch_slice_gather(reinterpret_cast<const float2*>(vis), weight, ws->order, ws->nvis,
                                  ws->vis, s));
   }
+  // the slices' images, up to nimg of them in one batched gridding launch,
+  // each then phase-corrected into out
   bool first = true;
-  for (int j = 0; j < ws->ns; ++j) {
-    if (!ws->plans[j]) continue;
-    int rc = sepw_grid(static_cast<sepw_plan_s*>(ws->plans[j]),
-                       reinterpret_cast<const sepw_c64*>(ws->vis + ws->off[j]), nullptr,
-                       reinterpret_cast<sepw_c64*>(ws->img), flags, hip_stream);
+  const int64_t nn = (int64_t)K->N * K->N;
+  std::vector<sepw_plan> plans;
+  std::vector<const sepw_c64*> vs;
+  std::vector<const float*> wts;
+  std::vector<sepw_c64*> imgs;
+  std::vector<int> idx;
+  for (int j0 = 0; j0 < ws->ns;) {
+    plans.clear();
+    vs.clear();
+    wts.clear();
+    imgs.clear();
+    idx.clear();
+    for (; j0 < ws->ns && (int)idx.size() < ws->nimg; ++j0) {
+      if (!ws->plans[j0]) continue;
+      plans.push_back(static_cast<sepw_plan>(ws->plans[j0]));
+      vs.push_back(reinterpret_cast<const sepw_c64*>(ws->vis + ws->off[j0]));
+      wts.push_back(nullptr);
+      imgs.push_back(reinterpret_cast<sepw_c64*>(ws->img + (int64_t)idx.size() * nn));
+      idx.push_back(j0);
+    }
+    if (idx.empty()) break;
+    int rc = sepw_grid_batched((int32_t)idx.size(), plans.data(), vs.data(), wts.data(),
+                               imgs.data(), flags, hip_stream);
     if (rc != SEPW_OK) return rc;
     Stage st(SEPW_STAGE_CORRECT, s);
-    SEPW_TRY(launch_slice_phase(ws->img, out, K->N, K->fov, ws->centre[j], +1, !first, s));
-    first = false;
+    for (size_t k = 0; k < idx.size(); ++k) {
+      SEPW_TRY(launch_slice_phase(reinterpret_cast<const float2*>(imgs[k]), out, K->N, K->fov,
+                                  ws->centre[idx[k]], +1, !first, s));
+      first = false;
+    }
   }
   if (first) SEPW_TRY(launch_zero_c64(out, (int64_t)K->N * K->N, s));
   return SEPW_OK;
@@ -1389,17 +1471,43 @@ int sepw_wstack_degrid(sepw_wstack ws, const sepw_c64* image, sepw_c64* vis_out,
   if ((flags & ~SEPW_DIV_N) != 0) return SEPW_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   Kernels* K = ws->K;
-  for (int j = 0; j < ws->ns; ++j) {
-    if (!ws->plans[j]) continue;
-    {
-      Stage st(SEPW_STAGE_CORRECT, s);
-      SEPW_TRY(launch_slice_phase(reinterpret_cast<const float2*>(image), ws->img, K->N, K->fov,
-                                  ws->centre[j], -1, false, s));
+  if (K->prm.precision != SEPW_FP32 || ws->nimg < 2) {
+    for (int j = 0; j < ws->ns; ++j) {
+      if (!ws->plans[j]) continue;
+      {
+        Stage st(SEPW_STAGE_CORRECT, s);
+        SEPW_TRY(launch_slice_phase(reinterpret_cast<const float2*>(image), ws->img, K->N, K->fov,
+                                    ws->centre[j], -1, false, s));
+      }
+      int rc = sepw_degrid(static_cast<sepw_plan_s*>(ws->plans[j]),
+                           reinterpret_cast<const sepw_c64*>(ws->img),
+                           reinterpret_cast<sepw_c64*>(ws->vis + ws->off[j]), flags, hip_stream);
+      if (rc != SEPW_OK) return rc;
     }
-    int rc = sepw_degrid(static_cast<sepw_plan_s*>(ws->plans[j]),
-                         reinterpret_cast<const sepw_c64*>(ws->img),
-                         reinterpret_cast<sepw_c64*>(ws->vis + ws->off[j]), flags, hip_stream);
-    if (rc != SEPW_OK) return rc;
+  } else {
+    // FP32: per slice the phase correction into its own image, then the
+    // slices' degridding in batches of up to nimg
+    const int64_t nn = (int64_t)K->N * K->N;
+    const int npow = (flags & SEPW_DIV_N) ? -1 : 0;
+    std::vector<Plan*> plans;
+    std::vector<float2*> outs;
+    for (int j0 = 0; j0 < ws->ns;) {
+      plans.clear();
+      outs.clear();
+      for (; j0 < ws->ns && (int)plans.size() < ws->nimg; ++j0) {
+        if (!ws->plans[j0]) continue;
+        Stage st(SEPW_STAGE_CORRECT, s);
+        SEPW_TRY(launch_slice_phase(reinterpret_cast<const float2*>(image),
+                                    ws->img + (int64_t)plans.size() * nn, K->N, K->fov,
+                                    ws->centre[j0], -1, false, s));
+        plans.push_back(ws->plans[j0]);
+        outs.push_back(ws->vis + ws->off[j0]);
+      }
+      if (plans.empty()) break;
+      int rc = degrid_images_batched(K, plans.data(), (int)plans.size(), ws->img, npow,
+                                     outs.data(), s);
+      if (rc != SEPW_OK) return rc;
+    }
   }
   if (ws->nvis > 0) {
     Stage st(SEPW_STAGE_GATHER, s);
@@ -1438,9 +1546,7 @@ int sepw_wsnap_create(sepw_kernels k, int32_t n_snap, const int64_t* offsets, co
   W->off.assign(offsets, offsets + n_snap + 1);
   W->d0.assign(2 * (size_t)n_snap, 0.0);
   W->plans.assign(n_snap, nullptr);
-  // images for batched gridding: as many snapshots as fit in kSnapImageBytes
-  const int64_t img_bytes = (int64_t)sizeof(float2) * k->N * k->N;
-  W->nimg = (int)std::max<int64_t>(1, std::min<int64_t>(n_snap, kSnapImageBytes / img_bytes));
+  W->nimg = batch_images(k->N, n_snap);
   int rc = map_hip(dalloc(&W->img, (int64_t)W->nimg * k->N * k->N));
   if (rc == SEPW_OK) rc = wsnap_build(W, u, v, w, s);
   int64_t dropped = 0;
@@ -1544,61 +1650,30 @@ int sepw_wsnap_degrid(sepw_wsnap ws, const sepw_c64* image, sepw_c64* vis_out, u
     }
     return SEPW_OK;
   }
-  // FP32: per snapshot the transposed reprojection, correction and FFT into
-  // its own grid, then the snapshots' degridding in one batched launch (up to
-  // nimg at a time; all share the residual tables), then per snapshot the
-  // correction pass and the move to caller order
+  // FP32: per snapshot the transposed reprojection into its own image, then
+  // the snapshots' degridding in batches of up to nimg
   std::vector<int> idx;
+  std::vector<Plan*> plans;
+  std::vector<float2*> outs;
   for (int i0 = 0; i0 < ws->ns;) {
     idx.clear();
     for (; i0 < ws->ns && (int)idx.size() < ws->nimg; ++i0)
       if (ws->plans[i0]) idx.push_back(i0);
     if (idx.empty()) break;
-    const int nj = (int)idx.size();
-    for (int j = 0; j < nj; ++j) {
+    plans.clear();
+    outs.clear();
+    for (size_t j = 0; j < idx.size(); ++j) {
       const int i = idx[j];
-      float2* g = ws->img + (int64_t)j * N * N;
-      {
-        Stage st(SEPW_STAGE_CORRECT, s);
-        SEPW_TRY(launch_snap_reproject_adjoint(reinterpret_cast<const float2*>(image), g, N, K->fov,
-                                               ws->d0[2 * (size_t)i], ws->d0[2 * (size_t)i + 1],
-                                               npow, s));
-        SEPW_TRY(launch_correct(g, g, K->c1, N, K->fov, K->l0, K->m0, 0, s));
-      }
-      Stage st(SEPW_STAGE_FFT, s);
-      int rc = fft_exec(K, g, HIPFFT_FORWARD, s);
-      if (rc != SEPW_OK) return rc;
+      Stage st(SEPW_STAGE_CORRECT, s);
+      SEPW_TRY(launch_snap_reproject_adjoint(reinterpret_cast<const float2*>(image),
+                                             ws->img + (int64_t)j * N * N, N, K->fov,
+                                             ws->d0[2 * (size_t)i], ws->d0[2 * (size_t)i + 1],
+                                             npow, s));
+      plans.push_back(ws->plans[i]);
+      outs.push_back(reinterpret_cast<float2*>(vis_out + ws->off[i]));
     }
-    BatchScratch* bs = nullptr;
-    int rc = batch_scratch(nj, s, &bs);
+    int rc = degrid_images_batched(K, plans.data(), (int)idx.size(), ws->img, 0, outs.data(), s);
     if (rc != SEPW_OK) return rc;
-    for (int j = 0; j < nj; ++j) {
-      Plan* p = ws->plans[idx[j]];
-      bs->dhost[j] = DegridArgs{p->dl.items, p->dl.itoff + 8 * p->r8, p->dl.itoff, p->r8, p->qctr,
-                                p->tdesc, p->krec, ws->img + (int64_t)j * N * N, K->pad_u,
-                                K->pad_v, K->tab_len, N, p->ntx, 1, p->yrow};
-    }
-    SEPW_TRY(hipMemcpyAsync(bs->djobs, bs->dhost, sizeof(DegridArgs) * (size_t)nj,
-                            hipMemcpyHostToDevice, s));
-    SEPW_TRY(hipEventRecord(bs->copied, s));
-    {
-      Stage st(SEPW_STAGE_DEGRID, s);
-      SEPW_TRY(launch_job_prefix(bs->djobs, nj, bs->first, bs->counter, s));
-      SEPW_TRY(launch_degrid_fp32_batched(K->S, bs->djobs, bs->first, nj, bs->counter,
-                                          K->lds_bytes, K->n_cu, s));
-    }
-    for (int j = 0; j < nj; ++j) {
-      Plan* p = ws->plans[idx[j]];
-      float2* g = ws->img + (int64_t)j * N * N;
-      if (K->corr) {
-        Stage st(SEPW_STAGE_CORR_APPLY, s);
-        SEPW_TRY(launch_corr_degrid(K->S, corr_args(p, p->dl, g, 1), p->dl.max_items, s));
-      }
-      Stage st(SEPW_STAGE_GATHER, s);
-      SEPW_TRY(launch_vis_from_rows(p->yrow, p->rot, p->place, p->delta, p->ckept, p->nvis,
-                                    p->nbins, reinterpret_cast<float2*>(vis_out + ws->off[idx[j]]),
-                                    s));
-    }
   }
   return SEPW_OK;
 }
