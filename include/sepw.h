@@ -253,7 +253,11 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
  * [-h, h], h = (w_hi - w_lo) / (2 n_slices).  u, v, w: DEVICE float64[nvis],
  * read during the call only.  *n_dropped (host, may be NULL) counts
  * visibilities whose footprint leaves the grid or whose w is not finite.
- * Synchronises the stream (the slice sizes come to the host).
+ * Synchronises the stream (the slice sizes come to the host).  The object
+ * holds, besides a plan per slice, as many N x N complex64 slice images as fit
+ * in 4 GiB (at least one, at most n_slices): the slices are gridded that many
+ * at a time in one batched launch (sepw_grid_batched) and, in FP32, degridded
+ * likewise.
  * Errors: SEPW_ERR_ARG (null k or out, facet kernels, n_slices outside
  * [1, 4096], w_lo >= w_hi, kernels' w range not [-h, h], nvis out of range),
  * SEPW_ERR_OOM, SEPW_ERR_HIP. */
@@ -351,7 +355,8 @@ int sepw_free_wstack(sepw_wstack ws);
  * k become invalid).  Synchronises the stream.  The object holds, besides a
  * plan per snapshot, as many N x N complex64 snapshot images as fit in 4 GiB
  * (at least one, at most n_snap): sepw_wsnap_grid grids that many snapshots
- * in one batched launch (sepw_grid_batched).
+ * in one batched launch (sepw_grid_batched) and, in FP32, degrids them
+ * likewise.
  * sepw_wsnap_grid: image_out (DEVICE complex64 [N N]) = sum over snapshots of
  *   R_s[F+[G_s] / (c1 c1)], times n (SEPW_MUL_N) or over n (SEPW_DIV_N), where
  *   G_s is the snapshot's separable gridding on w' and R_s the reprojection:
