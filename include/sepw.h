@@ -49,7 +49,10 @@
  * library.  Every call is asynchronous on the given HIP stream (NULL = the
  * default stream) unless stated; a kernel failure surfaces as SEPW_ERR_HIP at
  * a later call.  A plan or kernels object must not be used by two calls that
- * overlap in time (its scratch and FFT plan are shared).
+ * overlap in time (its scratch and FFT plan are shared).  The batched calls
+ * (sepw_grid_batched, sepw_autotune_batched and the W-stacking and W-snapshot
+ * grid and degrid calls) share one job table and work counter per process:
+ * calls of them that overlap in time on different streams race.
  *
  * Errors: every call returns SEPW_OK or a negative code; no exception crosses
  * the ABI.  Arguments are validated on the host before any device work, so a
