@@ -222,7 +222,8 @@ __global__ void snap_reproject_adjoint_kernel(const float2* __restrict__ X, floa
 // (the same weights as the forward sampling), and is written (not added).  A
 // workgroup takes 16 x 16 snapshot pixels: the pre-image p* of the tile centre
 // c comes from the fixed-point iteration p <- p + (c - g(p)); the sample
-// points and values of the 32 x 32 output pixels around p* go to LDS.  Each
+// points and values of the 26 x 26 output pixels from floor(p*) - 12 go to
+// LDS.  Each
 // pixel then refines its own pre-image by one more iteration from
 // p* + (j - c), and scans the 5 x 5 output pixels from ceil(q - 2.32).
 // With the warp's Jacobian within eps <= 0.1 of the identity (max-norm):
@@ -231,10 +232,10 @@ __global__ void snap_reproject_adjoint_kernel(const float2* __restrict__ X, floa
 // eps |j - c| / (1 - eps) < 0.84 of p_j and the iteration shrinks the error
 // by eps, so the refined q is within 0.084 of p_j: every contributor lies in
 // [q - 2.307, q + 2.307], whose integers (at most five) are the ones scanned.
-// All of them lie within 8.4 + 2.8 < 12 pixels of p*, inside the box.  The
+// All of them lie in [p* - 10.8, p* + 11.2], inside the box.  The
 // launcher checks the bound and otherwise zeroes the output and uses the
 // scatter kernel above.
-constexpr int kGTile = 16, kGBox = 32, kGScan = 5;
+constexpr int kGTile = 16, kGBox = 26, kGScan = 5;
 
 __device__ inline void warp_at(double p, double q, int N, double fov, double du, double dv,
                                double& x, double& y) {
