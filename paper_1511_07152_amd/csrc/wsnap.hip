@@ -135,16 +135,19 @@ __device__ inline Taps taps(double x, int N) {
   return t;
 }
 
-// Fractional pixel coordinates of l^s, m^s for output pixel (p, q), and n.
+// Fractional pixel coordinates of l^s, m^s for output pixel (p, q), and n:
+// x = l^s N / fov + N/2 = p + d_u (n - 1) N / fov (y alike).  step and pix do
+// not depend on the pixel (the compiler hoists them out of pixel loops), so a
+// sample point costs one square root and one division.
 __device__ inline void sample_point(int p, int q, int N, double fov, double du, double dv,
                                     double& x, double& y, double& n) {
-  const double step = fov / (double)N;
+  const double step = fov / (double)N, pix = (double)N / fov;
   const double l = (double)(p - N / 2) * step, m = (double)(q - N / 2) * step;
   const double r2 = l * l + m * m;
   n = sqrt(1.0 - r2);
   const double nm1 = -r2 / (1.0 + n);
-  x = (l + du * nm1) * (double)N / fov + (double)(N / 2);
-  y = (m + dv * nm1) * (double)N / fov + (double)(N / 2);
+  x = (double)p + du * nm1 * pix;
+  y = (double)q + dv * nm1 * pix;
 }
 
 // out (+)= the snapshot image sampled at l^s
@@ -239,12 +242,12 @@ constexpr int kGTile = 16, kGBox = 26, kGScan = 5;
 
 __device__ inline void warp_at(double p, double q, int N, double fov, double du, double dv,
                                double& x, double& y) {
-  const double step = fov / (double)N;
+  const double step = fov / (double)N, pix = (double)N / fov;
   const double l = (p - (double)(N / 2)) * step, m = (q - (double)(N / 2)) * step;
   const double r2 = l * l + m * m;
   const double nm1 = -r2 / (1.0 + sqrt(1.0 - r2));
-  x = (l + du * nm1) * (double)N / fov + (double)(N / 2);
-  y = (m + dv * nm1) * (double)N / fov + (double)(N / 2);
+  x = p + du * nm1 * pix;
+  y = q + dv * nm1 * pix;
 }
 
 __global__ __launch_bounds__(kGTile * kGTile) void snap_adjoint_gather_kernel(
