@@ -23,13 +23,15 @@ __global__ void correct_kernel(const float2* __restrict__ in, float2* __restrict
                                const double* __restrict__ c1, int N, double fov, double l0,
                                double m0, int npow) {
   const int64_t total = (int64_t)N * N;
+  const double step = fov / (double)N;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int q = (int)(i / N), p = (int)(i - (int64_t)q * N);
+    const uint32_t ui = (uint32_t)i;   // N <= 32768: pixel indices fit 32 bits
+    const int q = (int)(ui / (uint32_t)N), p = (int)(ui - (uint32_t)q * (uint32_t)N);
     double f = 1.0 / (c1[p] * c1[q]);
     if (npow != 0) {
-      const double l = l0 + (double)(p - N / 2) * fov / (double)N;
-      const double m = m0 + (double)(q - N / 2) * fov / (double)N;
+      const double l = l0 + (double)(p - N / 2) * step;
+      const double m = m0 + (double)(q - N / 2) * step;
       const double n = sqrt(1.0 - l * l - m * m);
       f = npow > 0 ? f * n : f / n;
     }

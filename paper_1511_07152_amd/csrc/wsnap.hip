@@ -156,7 +156,8 @@ __global__ void snap_reproject_kernel(const float2* __restrict__ in, float2* __r
   const int64_t total = (int64_t)N * N;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int q = (int)(e / N), p = (int)(e - (int64_t)q * N);
+    const uint32_t ue = (uint32_t)e;   // N <= 32768: pixel indices fit 32 bits
+    const int q = (int)(ue / (uint32_t)N), p = (int)(ue - (uint32_t)q * (uint32_t)N);
     double x, y, n;
     sample_point(p, q, N, fov, du, dv, x, y, n);
     float sr = 0.f, si = 0.f;
@@ -194,7 +195,8 @@ __global__ void snap_reproject_adjoint_kernel(const float2* __restrict__ X, floa
   float* o = reinterpret_cast<float*>(out);
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int q = (int)(e / N), p = (int)(e - (int64_t)q * N);
+    const uint32_t ue = (uint32_t)e;   // N <= 32768: pixel indices fit 32 bits
+    const int q = (int)(ue / (uint32_t)N), p = (int)(ue - (uint32_t)q * (uint32_t)N);
     double x, y, n;
     sample_point(p, q, N, fov, du, dv, x, y, n);
     if (!(fabs(x) < 4.0 * N && fabs(y) < 4.0 * N)) continue;
@@ -322,7 +324,8 @@ __global__ void snap_npow_kernel(float2* __restrict__ out, int N, double fov, in
   const int64_t total = (int64_t)N * N;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int q = (int)(e / N), p = (int)(e - (int64_t)q * N);
+    const uint32_t ue = (uint32_t)e;   // N <= 32768: pixel indices fit 32 bits
+    const int q = (int)(ue / (uint32_t)N), p = (int)(ue - (uint32_t)q * (uint32_t)N);
     double x, y, n;
     sample_point(p, q, N, fov, 0.0, 0.0, x, y, n);
     const float s = (float)(npow > 0 ? n : 1.0 / n);

@@ -112,11 +112,13 @@ __global__ void slice_return_kernel(const float2* __restrict__ in, const uint32_
 __global__ void slice_phase_kernel(const float2* __restrict__ in, float2* __restrict__ out, int N,
                                    double fov, double w_s, int sign, int accumulate) {
   const int64_t total = (int64_t)N * N;
+  const double step = fov / (double)N;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int q = (int)(i / N), p = (int)(i - (int64_t)q * N);
-    const double l = (double)(p - N / 2) * fov / (double)N;
-    const double m = (double)(q - N / 2) * fov / (double)N;
+    const uint32_t ui = (uint32_t)i;   // N <= 32768: pixel indices fit 32 bits
+    const int q = (int)(ui / (uint32_t)N), p = (int)(ui - (uint32_t)q * (uint32_t)N);
+    const double l = (double)(p - N / 2) * step;
+    const double m = (double)(q - N / 2) * step;
     const double r2 = l * l + m * m;
     const double n = sqrt(1.0 - r2);
     const double cyc = w_s * (-r2 / (1.0 + n));
