@@ -36,17 +36,3 @@ def facet_rotate(u, v, w, y, l0, m0):
     y2 = y * np.exp(2j * np.pi * (u * l0 + v * m0 + w * (n0 - 1.0)))
     return u - w * l0 / n0, v - w * m0 / n0, w, y2
 
-
-def facet_dirty_exact(u, v, w, y, N, fov, l0, m0, chunk=256):
-    """Exact dirty image divided by n over the facet's pixels:
-    sum_i y_i exp(2 pi i (u_i (l0+l_p) + v_i (m0+m_q) + w_i (n - 1)))."""
-    from .geometry import pixel_l
-    l = pixel_l(N, fov)
-    L, M = l0 + l[None, :], m0 + l[:, None]
-    n = np.sqrt(1.0 - L * L - M * M)
-    D = np.zeros((N, N), dtype=np.complex128)
-    for c0 in range(0, len(u), chunk):
-        sl = slice(c0, c0 + chunk)
-        ph = u[sl, None, None] * L[None] + v[sl, None, None] * M[None] + w[sl, None, None] * (n[None] - 1.0)
-        D += np.einsum('i,iqp->qp', y[sl], np.exp(2j * np.pi * ph))
-    return D
