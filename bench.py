@@ -70,9 +70,47 @@ def measured_traffic(kernel):
     return entry["bytes_per_launch"] if h.hexdigest() == entry["sources_sha256"] else None
 
 
-def cpu_baseline(d, n_sample):
-    """Oracle (FP64 NumPy, one thread) on the first n_sample visibilities:
-    quantise + tables + grid + F+ / correction + correction / F- + degrid."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_worker(args):
+    """One worker of the CPU baseline: quantise, grid (private FP64 grid) and
+    degrid (from the shared pre-corrected grid) one chunk of visibilities."""
+    import numpy as np
+    from multiprocessing import shared_memory
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    u, v, w, y, T, g = args
+    with threadpool_limits(limits=1):
+        N, fov, S, O, P, w_lo, w_hi, shm_name = g
+        shm = shared_memory.SharedMemory(name=shm_name)
+        try:
+            Gh = np.ndarray((N, N), np.complex128, buffer=shm.buf)
+            q = oracle.quantise.quantise(u, v, w, N, fov, O, S, P, w_lo, w_hi, 17 - S)
+            G = oracle.gridder.grid_separable(q, y, T, N, S)
+            Vp = oracle.gridder.degrid_separable(q, Gh, T, N, S)
+            del Gh
+        finally:
+            shm.close()
+    return G, len(Vp)
+
+
+def cpu_baseline(d, n_sample, workers):
+    """Oracle (FP64 NumPy) on the first n_sample visibilities, over a pool of
+    worker processes: tables and both FFT corrections in the parent, the
+    visibilities in equal chunks, each worker quantising, gridding into a
+    private grid and degridding its chunk; the grids summed at the end."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -83,23 +121,39 @@ def cpu_baseline(d, n_sample):
     y = d["V"][sl].astype(np.complex128) * d["W"][sl]
     rng = np.random.default_rng(7)
     X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        c1 = oracle.pswf.taper_c1(N, fov, S)
-        T = oracle.tables.separable_table(oracle.tables.w_plane_centres(P, d["w_lo"], d["w_hi"]),
-                                          N, fov, S, O, c1)
-        q = oracle.quantise.quantise(u, v, w, N, fov, O, S, P, d["w_lo"], d["w_hi"], 17 - S)
-        G = oracle.gridder.grid_separable(q, y, T, N, S)
-        img = oracle.imaging.image_from_grid(G, c1, fov, n_power=1)
-        Gh = oracle.imaging.grid_from_image(X, c1, fov, n_power=-1)
-        Vp = oracle.gridder.degrid_separable(q, Gh, T, N, S)
-        t1 = time.perf_counter()
-    del img, Vp
+    ctx = mp.get_context("spawn")   # fresh interpreters: the parent holds the GPU
+    shm = shared_memory.SharedMemory(create=True, size=N * N * 16)
+    try:
+        with ctx.Pool(workers) as pool:
+            pool.map(abs, range(workers))           # workers started before the clock
+            with threadpool_limits(limits=1):
+                t0 = time.perf_counter()
+                c1 = oracle.pswf.taper_c1(N, fov, S)
+                T = oracle.tables.separable_table(
+                    oracle.tables.w_plane_centres(P, d["w_lo"], d["w_hi"]), N, fov, S, O, c1)
+                Gh = np.ndarray((N, N), np.complex128, buffer=shm.buf)
+                Gh[...] = oracle.imaging.grid_from_image(X, c1, fov, n_power=-1)
+                del Gh
+                g = (N, fov, S, O, P, d["w_lo"], d["w_hi"], shm.name)
+                bounds = np.linspace(0, n_sample, workers + 1).astype(np.int64)
+                jobs = [(u[a:b], v[a:b], w[a:b], y[a:b], T, g)
+                        for a, b in zip(bounds[:-1], bounds[1:])]
+                G = None
+                for Gw, _ in pool.imap_unordered(_oracle_worker, jobs):
+                    G = Gw if G is None else G + Gw
+                img = oracle.imaging.image_from_grid(G, c1, fov, n_power=1)
+                t1 = time.perf_counter()
+    finally:
+        shm.close()
+        shm.unlink()
+    del img
     secs = t1 - t0
-    return {"value": round(n_sample / secs / 1e6, 4), "unit": "Mvis/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d visibilities of the workload (of %d); quantise + tables + grid + "
-                      "F+/correction + correction/F- + degrid, FP64 NumPy, %.1f s"
-                      % (n_sample, len(d["u"]), secs, ),
+    return {"value": round(n_sample / secs / 1e6, 4), "unit": "Mvis/s", "cores": workers,
+            "kind": "oracle", "cpu": _cpu_model(), "cpu_count": os.cpu_count(),
+            "sample": "first %d visibilities of the workload (of %d); tables + F-/correction, then "
+                      "quantise + grid + degrid in %d worker processes (private FP64 grids, "
+                      "summed), F+/correction; FP64 NumPy, %.1f s"
+                      % (n_sample, len(d["u"]), workers, secs),
             "seconds": round(secs, 2)}
 
 
@@ -520,7 +574,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--dump-s", type=float, default=10.0, help="dump time (10 s: 92.9M vis)")
-    ap.add_argument("--cpu-sample", type=int, default=1_500_000)
+    ap.add_argument("--cpu-sample", type=int, default=12_000_000)
+    ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="worker processes of the CPU baseline (at most the host's CPU share)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true",
                     help="skip the FP16/BF16 MFMA forms and their accuracy check")
@@ -651,7 +707,7 @@ def main():
     if not args.no_cpu_baseline:
         del u, v, w
         t = time.perf_counter()
-        out["cpu_baseline"] = cpu_baseline(d, min(args.cpu_sample, nvis))
+        out["cpu_baseline"] = cpu_baseline(d, min(args.cpu_sample, nvis), args.cpu_workers)
         log("cpu baseline in %.1f s" % (time.perf_counter() - t))
     print(json.dumps(out), flush=True)
 

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -66,6 +67,16 @@ int map_hip(hipError_t e) {
   } while (0)
 
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// work distribution of the LDS gridding kernel (0: one counter over all
+// items, 1: per-XCD lists); SEPW_GRID_SCHED overrides the default
+int grid_sched() {
+  static const int v = [] {
+    const char* e = std::getenv("SEPW_GRID_SCHED");
+    return e ? std::atoi(e) : 0;
+  }();
+  return v;
+}
 
 // ---- optional per-stage timing (benchmarking aid) ----
 struct TimingRec {
@@ -167,6 +178,9 @@ void destroy_kernels(Kernels* k) {
   if (k->pad_v && k->pad_v != k->pad_u) dfree(k->pad_v);
   k->pad_v = nullptr;
   dfree(k->pad_u);
+  if (k->pad_sv && k->pad_sv != k->pad_su) dfree(k->pad_sv);
+  k->pad_sv = nullptr;
+  dfree(k->pad_su);
   if (k->lp_v && k->lp_v != k->lp_u) dfree(k->lp_v);
   k->lp_v = nullptr;
   dfree(k->lp_u);
@@ -252,6 +266,9 @@ hipError_t make_separable_tables(Kernels* K, hipStream_t s) {
   if (e == hipSuccess) e = launch_pad_table(K->tab_u, nullptr, K->P, K->O, K->S, K->pad_u, s);
   if (e == hipSuccess && K->pad_v != K->pad_u)
     e = launch_pad_table(K->tab_v, nullptr, K->P, K->O, K->S, K->pad_v, s);
+  if (e == hipSuccess) e = launch_pad_table(K->tab_u, nullptr, K->P, K->O, K->S, K->pad_su, s, true);
+  if (e == hipSuccess && K->pad_sv != K->pad_su)
+    e = launch_pad_table(K->tab_v, nullptr, K->P, K->O, K->S, K->pad_sv, s, true);
   if (e == hipSuccess && K->lp_u) {
     const int bf16 = K->prm.precision == SEPW_BF16 ? 1 : 0;
     e = launch_plane_scales(K->tab_u, K->P, K->O * K->S, K->sc_u, s);
@@ -374,10 +391,13 @@ int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K) {
   }
   const int64_t npad = (int64_t)K->P * K->O * padded_len(K->S);
   SEPW_TRY(dalloc(&K->pad_u, npad));
+  SEPW_TRY(dalloc(&K->pad_su, npad));
   if (shared_axes) {
     K->pad_v = K->pad_u;
+    K->pad_sv = K->pad_su;
   } else {
     SEPW_TRY(dalloc(&K->pad_v, npad));
+    SEPW_TRY(dalloc(&K->pad_sv, npad));
   }
   if (p->precision != SEPW_FP32) {
     SEPW_TRY(dalloc(&K->lp_u, npad));
@@ -658,7 +678,7 @@ int degrid_images_batched(Kernels* K, Plan* const* plans, int nj, float2* grids,
   for (int j = 0; j < nj; ++j) {
     const Plan* p = plans[j];
     bs->dhost[j] = DegridArgs{p->dl.items, p->dl.itoff + 8 * p->r8, p->dl.itoff, p->r8, p->qctr,
-                              p->tdesc, p->krec, grids + (int64_t)j * N * N, K->pad_u, K->pad_v,
+                              p->tdesc, p->krec, grids + (int64_t)j * N * N, K->pad_su, K->pad_sv,
                               K->tab_len, N, p->ntx, 1, p->yrow};
   }
   SEPW_TRY(hipMemcpyAsync(bs->djobs, bs->dhost, sizeof(DegridArgs) * (size_t)nj,
@@ -1086,8 +1106,13 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
     if (K->prm.precision == SEPW_FP32) {
       GridArgs a{p->gl.items, p->gl.itoff + 8 * p->r8, p->gl.itoff, p->r8, p->qctr, p->tdesc, p->krec,
                  p->yrow, K->pad_u, K->pad_v,
-                 K->tab_len, N, p->ntx, grid_only ? 0 : 1, img};
-      SEPW_TRY(launch_grid_fp32(K->S, a, p->gl.max_items, s));
+                 K->tab_len, N, p->ntx, grid_only ? 0 : 1, img, grid_sched()};
+      if (K->lds_bytes > 0) {
+        SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8, s));
+        SEPW_TRY(launch_grid_fp32_lds(K->S, a, K->lds_bytes, K->n_cu, s));
+      } else {
+        SEPW_TRY(launch_grid_fp32(K->S, a, p->gl.max_items, s));
+      }
     } else {
       GridArgsLp a{p->gl.items, p->gl.itoff + 8 * p->r8, p->gl.itoff, p->r8, p->qctr, p->tdesc, p->krec,
                    p->yrow, K->pad_us, K->lp_v,
@@ -1144,7 +1169,7 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
     SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8, s));
     if (K->prm.precision == SEPW_FP32) {
       DegridArgs a{p->dl.items, p->dl.itoff + 8 * p->r8, p->dl.itoff, p->r8, p->qctr, p->tdesc, p->krec,
-                   src, K->pad_u, K->pad_v,
+                   src, checker ? K->pad_su : K->pad_u, checker ? K->pad_sv : K->pad_v,
                    K->tab_len, N, p->ntx, checker, p->yrow};
       SEPW_TRY(launch_degrid_fp32(K->S, a, p->dl.max_items, K->lds_bytes, K->n_cu, s));
     } else {

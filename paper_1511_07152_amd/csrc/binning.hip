@@ -710,7 +710,8 @@ __global__ __launch_bounds__(kSortThreads) void row_sort_kernel(
         const int row_v = k * O + (int)((r[j].y >> 8) & 0xFFu);
         const uint32_t q = lc[tl[j]] + rk[j];
         stage[q] = SlotRec{row_u * L + C - 1 - ox, row_v * L + C - 1 - oy,
-                           (int)(c0 + j * kSortThreads + threadIdx.x)};
+                           (int)((c0 + j * kSortThreads + threadIdx.x) |
+                                 ((uint32_t)((cu + cv) & 1) << 31))};
         dst[q] = cnt[tl[j]] + rk[j];
       }
     }

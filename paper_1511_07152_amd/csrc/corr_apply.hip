@@ -116,11 +116,11 @@ __device__ inline VisData load_vis(const CorrArgs& args, int slot, bool with_y) 
   d.pc = (t.col - wo) | ((t.row - wo) << 8);
   d.tb = t.tb;
   if (with_y) {
-    const float2 y = args.yrow[r.z];
+    const float2 y = args.yrow[rec_pos(r)];
     d.a = __float_as_int(y.x);
     d.b = __float_as_int(y.y);
   } else {
-    d.a = r.z;
+    d.a = rec_pos(r);
     d.b = 0;
   }
   return d;

@@ -19,9 +19,10 @@ namespace sepw {
 
 namespace {
 
-__global__ void correct_kernel(const float2* __restrict__ in, float2* __restrict__ out,
-                               const double* __restrict__ c1, int N, double fov, double l0,
-                               double m0, int npow) {
+// in and out may be the same array (in-place correction): each element is
+// read once and then written by the same thread, so neither is __restrict__.
+__global__ void correct_kernel(const float2* in, float2* out, const double* __restrict__ c1,
+                               int N, double fov, double l0, double m0, int npow) {
   const int64_t total = (int64_t)N * N;
   const double step = fov / (double)N;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;

@@ -37,34 +37,52 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 
 // Region operand for the tile at column tx: lane (col, grp) holds
-// R[y = col][x = 4 grp + q] for the four K-steps q.  The loads are issued at
-// clamped (always valid) addresses with no branch; region_fix() later applies
-// the factor (-1)^(x + y) (or 1 without the checkerboard), and 0 outside the
-// grid, once the data is needed, so no wait is forced at the load.
+// R[y = col][x = 4 grp + q], four consecutive cells of the lane's grid row.
+// A region inside the grid is read as two 16-byte loads (8-byte aligned).  A
+// region that reaches past a grid edge is read at clamped (always valid)
+// addresses, and region_zero() sets its cells outside the grid to 0 once the
+// data is needed (the taps there are 0, but a non-finite edge cell times 0
+// would not be).  The checkerboard of the centred FFT is not applied here: the
+// tables carry (-1)^s per tap and the result (-1)^(cu+cv) per visibility.
+typedef float f4u __attribute__((ext_vector_type(4), aligned(8)));
+
 template <int S>
-__device__ inline void load_region(const float2* __restrict__ grid, int N, int tx, int gy, int grp,
-                                   float2 (&r)[4]) {
+__device__ inline bool edge_region(int tx, int y0, int N) {
   constexpr int C = kRegion + 1 - S;
   constexpr int H = S / 2;
-  const int64_t row = (int64_t)min(max(gy, 0), N - 1) * N;
+  const int x0 = tx * C - H;
+  return x0 < 0 || x0 + kRegion > N || y0 < 0 || y0 + kRegion > N;
+}
+
+template <int S>
+__device__ inline void load_region(const float2* __restrict__ grid, int N, int tx, int gy, int grp,
+                                   bool edge, float2 (&r)[4]) {
+  constexpr int C = kRegion + 1 - S;
+  constexpr int H = S / 2;
+  const int x0 = tx * C - H + 4 * grp;
+  if (!edge) {
+    const f4u* p = reinterpret_cast<const f4u*>(grid + (int64_t)gy * N + x0);
+    const f4u a = p[0], b = p[1];
+    r[0] = make_float2(a[0], a[1]);
+    r[1] = make_float2(a[2], a[3]);
+    r[2] = make_float2(b[0], b[1]);
+    r[3] = make_float2(b[2], b[3]);
+  } else {
+    const int64_t row = (int64_t)min(max(gy, 0), N - 1) * N;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int gx = tx * C - H + 4 * grp + q;
-    r[q] = grid[row + min(max(gx, 0), N - 1)];
+    for (int q = 0; q < 4; ++q) r[q] = grid[row + min(max(x0 + q, 0), N - 1)];
   }
 }
 
 template <int S>
-__device__ inline void region_fix(int tx, int gy, int grp, int N, int checker, float2 (&r)[4]) {
+__device__ inline void region_zero(int tx, int gy, int grp, int N, float2 (&r)[4]) {
   constexpr int C = kRegion + 1 - S;
   constexpr int H = S / 2;
   const bool row_ok = gy >= 0 && gy < N;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int gx = tx * C - H + 4 * grp + q;
-    float f = (checker && ((gx + gy) & 1)) ? -1.f : 1.f;
-    if (!row_ok || gx < 0 || gx >= N) f = 0.f;
-    r[q] = make_float2(r[q].x * f, r[q].y * f);
+    if (!row_ok || gx < 0 || gx >= N) r[q] = make_float2(0.f, 0.f);
   }
 }
 
@@ -74,14 +92,16 @@ struct ChunkBuf {
   float2 tu[4];    // u-table taps x = 4 grp + q of the lane's visibility
   float2 tv[4];    // v-table taps y = 4 grp + rr
   float2 reg[4];   // grid region R[y = col][x = 4 grp + q] of the chunk's tile
-  bool fresh;      // region loaded for this chunk, sign / bounds factor not yet applied
+  bool fresh;      // region loaded for this chunk (edge regions: cells off the grid not yet zeroed)
+  bool edge;       // the region reaches past a grid edge
 };
 
 struct DegridCtx {
   const DegridArgs* a;
   const float2* tu_tab;
   const float2* tv_tab;
-  int s_end, gy, col, grp, lane;
+  int s_end, y0, gy, col, grp, lane;
+  uint32_t smask;   // kRecSign when the result takes the record's sign (-1)^(cu+cv)
 };
 
 __device__ __forceinline__ void fetch_taps(const DegridCtx& c, ChunkBuf& B) {
@@ -105,11 +125,13 @@ __device__ __forceinline__ bool degrid_step(const DegridCtx& c, TileWalk& tw, Ch
   const SlotRec kx = X.k;   // this chunk's record (row-bin position of the result)
   X.k = load_rec(a.krec + min(n2.c0 + c.col, n2.pe - 1));
   fetch_taps(c, Y);
-  if (X.fresh) region_fix<S>(cur.tx, c.gy, c.grp, a.N, a.checker, X.reg);
+  if (X.fresh && X.edge) region_zero<S>(cur.tx, c.gy, c.grp, a.N, X.reg);
   Y.fresh = n1.ok && n1.tx != cur.tx;
   if (Y.fresh) {
-    load_region<S>(a.grid, a.N, n1.tx, c.gy, c.grp, Y.reg);
+    Y.edge = edge_region<S>(n1.tx, c.y0, a.N);
+    load_region<S>(a.grid, a.N, n1.tx, c.gy, c.grp, Y.edge, Y.reg);
   } else {
+    Y.edge = X.edge;
 #pragma unroll
     for (int q = 0; q < 4; ++q) Y.reg[q] = X.reg[q];
   }
@@ -136,7 +158,11 @@ __device__ __forceinline__ bool degrid_step(const DegridCtx& c, TileWalk& tw, Ch
   v_im += __shfl_xor(v_im, 16, 64);
   v_re += __shfl_xor(v_re, 32, 64);
   v_im += __shfl_xor(v_im, 32, 64);
-  if (c.grp == 0 && cur.c0 + c.col < cur.re) a.yrow[kx.z] = make_float2(v_re, v_im);
+  if (c.grp == 0 && cur.c0 + c.col < cur.re) {
+    const uint32_t sg = (uint32_t)kx.z & c.smask;
+    a.yrow[rec_pos(kx)] = make_float2(__uint_as_float(__float_as_uint(v_re) ^ sg),
+                                      __uint_as_float(__float_as_uint(v_im) ^ sg));
+  }
 
   if (!n1.ok) return false;
   cur = n1;
@@ -158,7 +184,9 @@ __device__ __forceinline__ void degrid_item(const DegridArgs& a, const float2* t
   c.tu_tab = tu_tab;
   c.tv_tab = tv_tab;
   c.s_end = s_end;
-  c.gy = ty * C - H + col;          // grid row of this lane's A operand
+  c.y0 = ty * C - H;                // first grid row of the item's regions
+  c.gy = c.y0 + col;                // grid row of this lane's A operand
+  c.smask = a.checker ? kRecSign : 0u;
   c.col = col;
   c.grp = grp;
   c.lane = lane;
@@ -177,7 +205,8 @@ __device__ __forceinline__ void degrid_item(const DegridArgs& a, const float2* t
   ChunkBuf A, B;
   A.k = load_rec(a.krec + min(cur.c0 + col, cur.pe - 1));
   fetch_taps(c, A);
-  load_region<S>(a.grid, a.N, cur.tx, c.gy, grp, A.reg);
+  A.edge = edge_region<S>(cur.tx, c.y0, a.N);
+  load_region<S>(a.grid, a.N, cur.tx, c.gy, grp, A.edge, A.reg);
   A.fresh = true;
   B.k = load_rec(a.krec + min(n1.c0 + col, n1.pe - 1));
   while (degrid_step<S>(c, tw, cur, n1, n2, A, B) && degrid_step<S>(c, tw, cur, n1, n2, B, A)) {

@@ -202,8 +202,8 @@ __device__ __forceinline__ void grid_item(const GridArgs& a, float* ring, int it
   SlotRec r0 = load_rec(c.krec + min(c.s0 + lane, c.last));
   SlotRec r1 = load_rec(c.krec + min(c.s0 + 64 + lane, c.last));
   SlotRec r2 = load_rec(c.krec + min(c.s0 + 128 + lane, c.last));
-  float2 y0 = c.yrow[r0.z];
-  float2 y1 = c.yrow[r1.z];
+  float2 y0 = c.yrow[rec_pos(r0)];
+  float2 y1 = c.yrow[rec_pos(r1)];
   GroupOps A, B;   // groups of even / odd index
   fetch_group(c, r0, y0, 0, A);
   fetch_group(c, r0, y0, 1, B);
@@ -225,7 +225,7 @@ __device__ __forceinline__ void grid_item(const GridArgs& a, float* ring, int it
     r0 = r1;
     y0 = y1;
     r1 = r2;
-    y1 = c.yrow[r1.z];
+    y1 = c.yrow[rec_pos(r1)];
     r2 = load_rec(c.krec + min(c.s0 + 4 * g + 128 + lane, c.last));
   }
 done:
@@ -277,6 +277,312 @@ __global__ __launch_bounds__(64 * kWaves) void grid_fp32_batched_kernel(
   }
 }
 
+// ------------------------------------------------ tables in LDS, ring in registers
+//
+// When the padded tables fit in LDS, one workgroup of 16 waves per CU stages
+// them there and the table taps become LDS reads instead of buffer loads
+// (whose per-lane address processing bounds the cache-table kernel above).
+// The LDS then has no room for the accumulation rings, so each wave keeps its
+// ring in registers.  That works because the accumulator's columns are tied
+// to absolute grid columns modulo 16: lane column c holds the region column
+// whose grid column x satisfies x = c (mod 16), i.e. region column
+// rc = (c - x0) mod 16 for a region whose first column is x0.  A lane's sums
+// therefore always belong to the same two ring columns (x mod 32 is c or
+// c + 16), and banking a tile's sums is an add into one of two register
+// halves, with no data exchanged between lanes.  The ring holds two aligned
+// blocks of 16 grid columns (block b in half b & 1); when the walk reaches a
+// region that starts in a later block, the blocks it has left are added to
+// the grid with FP32 atomics.  The B operand of lane c for a group of tile T
+// is y Tu at region column rc_T, so the operand fetch, two groups ahead of
+// the arithmetic, walks the tiles as well (a second TileWalk) to know each
+// group's x0; the tap address is then one add.
+
+constexpr int kLdsWaves = 16;
+
+// The ring: block blk (lo) and block blk + 1 (hi) of 16 grid columns; lane
+// column c holds grid column 16 blk + c (lo) and 16 (blk + 1) + c (hi), rows
+// 4 grp + r of the item's 16 rows.
+struct RegRing {
+  f32x4 lo_re, lo_im, hi_re, hi_im;
+  int blk;
+};
+
+struct LdsState {
+  f32x4 p1, p2, p3;   // region sums of the current tile (three real products)
+  int x0;             // first grid column of the current region
+  int pe;             // end of the current tile's slots
+};
+
+struct FetchPos {
+  int pe;             // end of the slots of the tile the tap reads are in
+  int rc8;            // byte offset of this lane's region column in that tile: ((c - x0) & 15) * 8
+};
+
+struct LdsCtx {
+  const float2* yrow;
+  const char* tu;     // LDS tables (byte addressing)
+  const char* tv;
+  float* grid;
+  int N, checker;
+  int s0, last, ng, y0, lane, col, grp;
+  int col8, grp4;
+};
+
+// Add the ring's lo block (grid columns 16 blk + c, rows y0 + 4 grp + r) to the
+// grid with atomics ((-1)^(x+y) when the grid feeds the centred FFT), then
+// move hi down to lo and clear hi.
+__device__ inline void ring_shift(RegRing& rg, const LdsCtx& c) {
+  const int gx = 16 * rg.blk + c.col;
+  if (gx >= 0 && gx < c.N) {
+    const int gy0 = c.y0 + 4 * c.grp;
+    float sg = (c.checker && ((gx + gy0) & 1)) ? -1.f : 1.f;
+    float* p = c.grid + 2 * ((int64_t)gy0 * c.N + gx);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gy = gy0 + r;
+      if (gy >= 0 && gy < c.N) {
+        if (rg.lo_re[r] != 0.f) unsafeAtomicAdd(p, sg * rg.lo_re[r]);
+        if (rg.lo_im[r] != 0.f) unsafeAtomicAdd(p + 1, sg * rg.lo_im[r]);
+      }
+      p += 2 * (int64_t)c.N;
+      if (c.checker) sg = -sg;
+    }
+  }
+  rg.lo_re = rg.hi_re;
+  rg.lo_im = rg.hi_im;
+  rg.hi_re = f32x4{0.f, 0.f, 0.f, 0.f};
+  rg.hi_im = rg.hi_re;
+  rg.blk += 1;
+}
+
+// Bank the current tile's region sums into the ring block of this lane's column.
+__device__ inline void ring_bank(RegRing& rg, const LdsState& st, int col) {
+  const int xa = st.x0 + ((col - st.x0) & 15);
+  f32x4 re, im;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    re[r] = st.p1[r] - st.p2[r];
+    im[r] = st.p3[r] - st.p1[r] - st.p2[r];
+  }
+  // selects, not a branch: each lane adds to one block and 0 to the other
+  const bool hi = (xa >> 4) != rg.blk;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    rg.hi_re[r] += hi ? re[r] : 0.f;
+    rg.hi_im[r] += hi ? im[r] : 0.f;
+    rg.lo_re[r] += hi ? 0.f : re[r];
+    rg.lo_im[r] += hi ? 0.f : im[r];
+  }
+}
+
+// Record of group j (table bases and W V of slot 4 (j % 16) + grp of the
+// batch R, Y) moved to this lane.
+struct GroupKey {
+  int kx, ky;
+  float2 y;
+};
+
+__device__ __forceinline__ void key_group(const LdsCtx& c, const SlotRec& R, const float2& Y, int j,
+                                          GroupKey& k) {
+  const int src = c.grp4 + ((j & 15) << 4);
+  k.kx = __builtin_amdgcn_ds_bpermute(src, R.x);
+  k.ky = __builtin_amdgcn_ds_bpermute(src, R.y);
+  k.y = make_float2(bperm(src, Y.x), bperm(src, Y.y));
+}
+
+// Taps of group j from the LDS tables, with its record k moved to this lane
+// one step earlier.  The read position enters a new tile exactly when j
+// reaches that tile's first group.
+template <int S>
+__device__ __forceinline__ void taps_group(const LdsCtx& c, const GroupKey& k, int j, TileWalk& fw,
+                                           FetchPos& f, GroupOps& o) {
+  constexpr int C = kRegion + 1 - S;
+  constexpr int H = S / 2;
+  if (c.s0 + 4 * j >= f.pe && fw.next(c.lane)) {
+    const int x0 = fw.tx * C - H;
+    f.pe = fw.padded_end();
+    f.rc8 = ((c.col - x0) & 15) << 3;
+  }
+  o.y = k.y;
+  o.tu = *reinterpret_cast<const float2*>(c.tu + (k.kx << 3) + f.rc8);
+  o.tv = *reinterpret_cast<const float2*>(c.tv + (k.ky << 3) + c.col8);
+}
+
+// Slot records and W V of the item, one slot per lane, in batches of 64:
+// batch a (records ra, W V ya) holds the group whose record is moved next,
+// batch a + 1 (rb, yb) follows, and the records of batch a + 2 (rc) are in
+// flight.
+struct Batches {
+  SlotRec ra, rb, rc;
+  float2 ya, yb;
+  int nb;             // batch index of rc
+};
+
+// One pipeline step: multiply group g (operands in buf, read two steps
+// earlier), move the record of group g + 3 to the lanes, then read the taps of
+// group g + 2 (record moved one step earlier) into buf.  The record exchange
+// is issued before the tap reads, so that its wait in the next step does not
+// also wait for these reads (LDS operations complete in order).
+template <int S>
+__device__ __forceinline__ void grid_step_lds(const GridArgs& a, const LdsCtx& c, int g,
+                                              Batches& bt, TileWalk& tw, TileWalk& fw,
+                                              FetchPos& f, GroupKey& key, LdsState& st,
+                                              RegRing& rg, GroupOps& buf) {
+  constexpr int C = kRegion + 1 - S;
+  constexpr int H = S / 2;
+  bool first = false;
+  if (c.s0 + 4 * g >= st.pe && tw.next(c.lane)) {
+    // next non-empty tile of the row: bank the sums, flush the ring blocks
+    // the new region has left behind, restart the sums
+    ring_bank(rg, st, c.col);
+    const int x0 = tw.tx * C - H;
+    const int b = x0 >> 4;   // floor(x0 / 16), also for x0 < 0
+    if (b > rg.blk) {
+      ring_shift(rg, c);
+      if (b > rg.blk) {
+        ring_shift(rg, c);
+        rg.blk = b;
+      }
+    }
+    st.x0 = x0;
+    st.pe = tw.padded_end();
+    first = true;
+  }
+  const float b_re = buf.y.x * buf.tu.x - buf.y.y * buf.tu.y;   // row product W V Tu
+  const float b_im = buf.y.x * buf.tu.y + buf.y.y * buf.tu.x;
+  const float a_s = buf.tv.x + buf.tv.y, b_s = b_re + b_im;
+  if (first) {
+    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    st.p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(buf.tv.x, b_re, z, 0, 0, 0);
+    st.p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(buf.tv.y, b_im, z, 0, 0, 0);
+    st.p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a_s, b_s, z, 0, 0, 0);
+  } else {
+    st.p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(buf.tv.x, b_re, st.p1, 0, 0, 0);
+    st.p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(buf.tv.y, b_im, st.p2, 0, 0, 0);
+    st.p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a_s, b_s, st.p3, 0, 0, 0);
+  }
+  if (((g + 3) & 15) == 0) {
+    // group g + 3 opens the next batch: W V one batch ahead (its records
+    // arrived a batch ago), records two batches ahead
+    bt.ra = bt.rb;
+    bt.ya = bt.yb;
+    bt.rb = bt.rc;
+    bt.yb = c.yrow[rec_pos(bt.rb)];
+    bt.nb += 1;
+    bt.rc = load_rec(a.krec + min(c.s0 + 64 * bt.nb + c.lane, c.last));
+  }
+  GroupKey next;
+  key_group(c, bt.ra, bt.ya, g + 3, next);
+  taps_group<S>(c, key, g + 2, fw, f, buf);
+  key = next;
+}
+
+template <int S>
+__device__ __forceinline__ void grid_item_lds(const GridArgs& a, const char* tu, const char* tv,
+                                              int it, int lane) {
+  constexpr int C = kRegion + 1 - S;
+  constexpr int H = S / 2;
+  const int4 item = a.items[it];
+  const int ty = uniform(item.x), s_end = uniform(item.z);
+  LdsCtx c;
+  c.yrow = a.yrow;
+  c.tu = tu;
+  c.tv = tv;
+  c.grid = reinterpret_cast<float*>(a.grid);
+  c.N = a.N;
+  c.checker = a.checker;
+  c.s0 = uniform(item.y);
+  c.last = s_end - 1;
+  c.ng = (s_end - c.s0) >> 2;
+  c.y0 = ty * C - H;
+  c.lane = lane;
+  c.col = lane & 15;
+  c.grp = lane >> 4;
+  c.col8 = c.col << 3;
+  c.grp4 = c.grp << 2;
+  const int last = c.last;
+  TileWalk tw;
+  tw.start(a.tdesc + (int64_t)ty * a.ntx, a.ntx, uniform(item.w), lane);
+  TileWalk fw = tw;
+  LdsState st;
+  st.x0 = tw.tx * C - H;
+  st.pe = tw.padded_end();
+  st.p1 = f32x4{0.f, 0.f, 0.f, 0.f};
+  st.p2 = st.p1;
+  st.p3 = st.p1;
+  FetchPos f;
+  f.pe = st.pe;
+  f.rc8 = ((c.col - st.x0) & 15) << 3;
+  RegRing rg;
+  rg.lo_re = st.p1;
+  rg.lo_im = st.p1;
+  rg.hi_re = st.p1;
+  rg.hi_im = st.p1;
+  rg.blk = st.x0 >> 4;
+
+  Batches bt;
+  bt.ra = load_rec(a.krec + min(c.s0 + lane, last));
+  bt.rb = load_rec(a.krec + min(c.s0 + 64 + lane, last));
+  bt.rc = load_rec(a.krec + min(c.s0 + 128 + lane, last));
+  bt.nb = 2;
+  bt.ya = c.yrow[rec_pos(bt.ra)];
+  bt.yb = c.yrow[rec_pos(bt.rb)];
+  GroupOps A, B;   // groups of even / odd index
+  GroupKey key;
+  key_group(c, bt.ra, bt.ya, 0, key);
+  taps_group<S>(c, key, 0, fw, f, A);
+  key_group(c, bt.ra, bt.ya, 1, key);
+  taps_group<S>(c, key, 1, fw, f, B);
+  key_group(c, bt.ra, bt.ya, 2, key);
+  for (int g = 0;;) {
+    grid_step_lds<S>(a, c, g, bt, tw, fw, f, key, st, rg, A);
+    if (++g >= c.ng) break;
+    grid_step_lds<S>(a, c, g, bt, tw, fw, f, key, st, rg, B);
+    if (++g >= c.ng) break;
+  }
+  ring_bank(rg, st, c.col);
+  ring_shift(rg, c);
+  ring_shift(rg, c);
+}
+
+// One workgroup of 16 waves per CU with the tables in LDS; waves take work
+// items from one counter over all items (sched 0) or from the list of the XCD
+// they run on (sched 1).
+template <int S>
+__global__ __launch_bounds__(64 * kLdsWaves) void grid_fp32_lds_kernel(GridArgs a) {
+  extern __shared__ float2 smem[];
+  const int n = a.tab_len;
+  const bool two = a.tab_v != a.tab_u;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) smem[i] = a.tab_u[i];
+  if (two)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) smem[n + i] = a.tab_v[i];
+  __syncthreads();
+  const char* tu = reinterpret_cast<const char*>(smem);
+  const char* tv = reinterpret_cast<const char*>(two ? smem + n : smem);
+  const int lane = threadIdx.x & 63;
+  if (a.sched) {
+    for_items(a.lists, a.r8, a.qctr, lane, [&](int it) { grid_item_lds<S>(a, tu, tv, it, lane); });
+  } else {
+    const int n_items = uniform((int)*a.nitems);
+    while (true) {
+      int it = 0;
+      if (lane == 0) it = (int)atomicAdd(a.qctr, 1u);
+      it = uniform(__shfl(it, 0, 64));
+      if (it >= n_items) break;
+      grid_item_lds<S>(a, tu, tv, it, lane);
+    }
+  }
+}
+
+template <int S>
+hipError_t launch_lds_s(const GridArgs& a, int lds_bytes, int n_cu, hipStream_t s) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&grid_fp32_lds_kernel<S>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  hipLaunchKernelGGL(grid_fp32_lds_kernel<S>, dim3((unsigned)n_cu), dim3(64 * kLdsWaves),
+                     lds_bytes, s, a);
+  return hipGetLastError();
+}
+
 template <int S>
 hipError_t launch_s(const GridArgs& a, int64_t max_items, hipStream_t s) {
   int64_t b = (max_items + kWaves - 1) / kWaves;
@@ -307,6 +613,21 @@ hipError_t launch_grid_fp32_batched(int S, const GridArgs* jobs, const uint32_t*
     case 11: return launch_batched_s<11>(jobs, first, njobs, counter, blocks, s);
     case 13: return launch_batched_s<13>(jobs, first, njobs, counter, blocks, s);
     case 15: return launch_batched_s<15>(jobs, first, njobs, counter, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_grid_fp32_lds(int S, const GridArgs& a, int lds_bytes, int n_cu,
+                                hipStream_t s) {
+  switch (S) {
+    case 1: return launch_lds_s<1>(a, lds_bytes, n_cu, s);
+    case 3: return launch_lds_s<3>(a, lds_bytes, n_cu, s);
+    case 5: return launch_lds_s<5>(a, lds_bytes, n_cu, s);
+    case 7: return launch_lds_s<7>(a, lds_bytes, n_cu, s);
+    case 9: return launch_lds_s<9>(a, lds_bytes, n_cu, s);
+    case 11: return launch_lds_s<11>(a, lds_bytes, n_cu, s);
+    case 13: return launch_lds_s<13>(a, lds_bytes, n_cu, s);
+    case 15: return launch_lds_s<15>(a, lds_bytes, n_cu, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -151,8 +151,8 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float* ring, f
   bt.r0 = krec[min(s0 + lane, last)];
   bt.r1 = krec[min(s0 + 64 + lane, last)];
   bt.r2 = krec[min(s0 + 128 + lane, last)];
-  bt.y0 = yrow[bt.r0.z];
-  bt.y1 = yrow[bt.r1.z];
+  bt.y0 = yrow[rec_pos(bt.r0)];
+  bt.y1 = yrow[rec_pos(bt.r1)];
 
   // operands of chunk p into Bf (batches advance monotonically with p)
   auto fetch = [&](const ChunkPos& p, GridBuf& Bf) {
@@ -161,7 +161,7 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, float* ring, f
       bt.r0 = bt.r1;
       bt.y0 = bt.y1;
       bt.r1 = bt.r2;
-      bt.y1 = yrow[bt.r1.z];
+      bt.y1 = yrow[rec_pos(bt.r1)];
       bt.a += 1;
       bt.r2 = krec[min(s0 + 64 * (bt.a + 2) + lane, last)];
     }
@@ -407,7 +407,7 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, const floa
     p_im += __shfl_xor(p_im, 16, 64);
     p_re += __shfl_xor(p_re, 32, 64);
     p_im += __shfl_xor(p_im, 32, 64);
-    if (grp == 0 && cur.c0 + col < cur.re) a.yrow[kc.z] = make_float2(p_re * sr, p_im * sr);
+    if (grp == 0 && cur.c0 + col < cur.re) a.yrow[rec_pos(kc)] = make_float2(p_re * sr, p_im * sr);
     if (!n1.ok) return false;
     cur = n1;
     n1 = n2;

@@ -66,6 +66,8 @@ struct Kernels {
   double* c1 = nullptr;        // taper at the N pixel positions
   float2* pad_u = nullptr;     // [P][O][L] zero-padded u / v tables
   float2* pad_v = nullptr;
+  float2* pad_su = nullptr;    // the same with tap s times (-1)^s (degridding from the FFT)
+  float2* pad_sv = nullptr;
   // precision form (FP16 / BF16): per-plane scales s_k, 16-bit padded tables
   // holding T / s_k, and FP32 padded tables pre-multiplied by the other axis'
   // scale (u-table times s_k^v for the gridding row product, v-table times
@@ -94,10 +96,15 @@ struct Kernels {
 
 // Tile slot record: padded-table bases of the visibility's u and v taps (tap
 // of region column x at base + x) and the row-bin position of its W V.  Twelve
-// bytes, loaded as three dwords.
+// bytes, loaded as three dwords.  Bit 31 of z holds the parity of
+// cell_u + cell_v (the sign (-1)^(cu+cv) that, with the tap signs (-1)^(s+t)
+// of the signed tables, makes up the grid-side checkerboard (-1)^(x+y) of the
+// centred FFT); rec_pos() is the row-bin position alone.
 struct SlotRec {
   int x, y, z;
 };
+constexpr uint32_t kRecSign = 0x80000000u;
+__host__ __device__ inline int rec_pos(const SlotRec& r) { return r.z & 0x7FFFFFFF; }
 
 // Work items of at most `slots` tile slots of one row of tiles, in 8 lists by
 // row % 8 (list q = items [itoff[q r8], itoff[(q + 1) r8])).
@@ -309,6 +316,7 @@ struct GridArgs {
   int N, ntx;
   int checker;              // apply (-1)^(x+y) for the centred FFT
   float2* grid;
+  int sched;                // LDS kernel: 0 = one counter over all items, 1 = per-XCD lists
 };
 
 struct DegridArgs {
@@ -320,11 +328,11 @@ struct DegridArgs {
   const uint2* tdesc;
   const SlotRec* krec;
   const float2* grid;
-  const float2* tab_u;      // padded tables
+  const float2* tab_u;      // padded tables; with checker, the signed tables (tap s times (-1)^s)
   const float2* tab_v;
   int tab_len;
   int N, ntx;
-  int checker;
+  int checker;              // the grid comes from the centred FFT: results times (-1)^(cu+cv)
   float2* yrow;             // results in row-bin order (padding slots are not written)
 };
 
@@ -363,6 +371,10 @@ struct DegridArgsLp {
 };
 
 hipError_t launch_grid_fp32(int S, const GridArgs& a, int64_t max_items, hipStream_t s);
+// tables staged in LDS (lds_bytes of them), one 16-wave workgroup per CU; the
+// work-list counters (a.qctr) must be zero at launch
+hipError_t launch_grid_fp32_lds(int S, const GridArgs& a, int lds_bytes, int n_cu,
+                                hipStream_t s);
 // persistent launch over the items of njobs jobs; first[njobs + 1] = prefix of
 // per-job item counts (device), counter = zeroed device word
 hipError_t launch_grid_fp32_batched(int S, const GridArgs* jobs, const uint32_t* first, int njobs,
@@ -376,9 +388,10 @@ hipError_t launch_grid_lp(int S, bool bf16, const GridArgsLp& a, int64_t max_ite
 // lds_bytes > 0: the FP32 v-table (a.tab_len entries) is staged in LDS
 hipError_t launch_degrid_lp(int S, bool bf16, const DegridArgsLp& a, int64_t max_items,
                             int lds_bytes, int n_cu, hipStream_t s);
-// zero-padded FP32 tables: out[k][fi][c - 1 + s] = tab[k][fi][s] * (scale ? scale[k] : 1)
+// zero-padded FP32 tables: out[k][fi][c - 1 + s] = tab[k][fi][s] * (scale ? scale[k] : 1),
+// times (-1)^s when alternate
 hipError_t launch_pad_table(const float2* tab, const float* scale, int P, int O, int S, float2* out,
-                            hipStream_t s);
+                            hipStream_t s, bool alternate = false);
 // per-plane scales s_k = max |Re, Im| over the plane
 hipError_t launch_plane_scales(const float2* tab, int P, int per_plane, float* scale, hipStream_t s);
 // 16-bit padded tables holding T / s_k

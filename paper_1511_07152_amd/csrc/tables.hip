@@ -118,15 +118,16 @@ __global__ __launch_bounds__(kTabThreads) void table_kernel(
 // ---- derived layouts of the tables (same values, kernel-friendly storage) ----
 
 __global__ void pad_table_kernel(const float2* __restrict__ tab, const float* __restrict__ scale,
-                                 int O, int S, float2* __restrict__ out) {
+                                 int O, int S, int alternate, float2* __restrict__ out) {
   // one block per (plane, sub-cell row): out row of L entries
   const int L = padded_len(S), c = kRegion + 1 - S;
   const int row = blockIdx.x, k = row / O;
-  const float f = scale ? scale[k] : 1.f;
+  const float f0 = scale ? scale[k] : 1.f;
   for (int x = threadIdx.x; x < L; x += blockDim.x) {
     const int s = x - (c - 1);
     float2 v = make_float2(0.f, 0.f);
     if (s >= 0 && s < S) {
+      const float f = (alternate && (s & 1)) ? -f0 : f0;
       v = tab[(int64_t)row * S + s];
       v.x *= f;
       v.y *= f;
@@ -202,8 +203,9 @@ hipError_t launch_ones(double* c1, int N, hipStream_t s) {
 }
 
 hipError_t launch_pad_table(const float2* tab, const float* scale, int P, int O, int S, float2* out,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(pad_table_kernel, dim3(P * O), dim3(32), 0, s, tab, scale, O, S, out);
+                            hipStream_t s, bool alternate) {
+  hipLaunchKernelGGL(pad_table_kernel, dim3(P * O), dim3(32), 0, s, tab, scale, O, S,
+                     alternate ? 1 : 0, out);
   return hipGetLastError();
 }
 

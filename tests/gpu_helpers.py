@@ -1,6 +1,8 @@
 """Shared helpers for the GPU parity tests: device transfer, oracle pipelines
 for the same inputs, and error measures.  Inputs come from the seeded
 generators; expected values come from the oracle only."""
+import math
+
 import numpy as np
 
 import oracle
@@ -21,6 +23,30 @@ def inner(a):
     N = a.shape[0]
     s = slice(N // 4, 3 * N // 4)
     return a[s, s]
+
+
+def coverage_max(q, N, S):
+    """Largest number of kept footprints (S x S cells at cell - S//2 ..) that
+    cover one cell of the N x N grid: the number of FP32 terms summed into the
+    heaviest cell."""
+    keep = ~q['dropped']
+    if not keep.any():
+        return 0
+    h = S // 2
+    cu, cv = q['cell_u'][keep], q['cell_v'][keep]
+    d = np.zeros((N + 1, N + 1), np.int64)
+    np.add.at(d, (cv - h, cu - h), 1)
+    np.add.at(d, (cv - h, cu + h + 1), -1)
+    np.add.at(d, (cv + h + 1, cu - h), -1)
+    np.add.at(d, (cv + h + 1, cu + h + 1), 1)
+    return int(d.cumsum(0).cumsum(1).max())
+
+
+def grid_bound(kmax):
+    """FP32 gridding bound, relative RMS: 1e-6, or sqrt(K) 2^-24 where the
+    heaviest cell sums K terms and that is larger (the rounding of a K-term
+    FP32 sum with random signs grows as sqrt(K) times the unit roundoff)."""
+    return max(1e-6, math.sqrt(kmax) * 2.0 ** -24)
 
 
 class OracleSetup:
@@ -85,6 +111,13 @@ class OracleSetup:
             n = np.sqrt(1 - (l0 + l[None, :]) ** 2 - (m0 + l[:, None]) ** 2)
             Y = Y * n ** n_power
         return self.degrid_grid(oracle.geometry.fminus(Y))
+
+    def coverage_max(self):
+        """Largest number of kept footprints that cover one grid cell."""
+        return coverage_max(self.q, self.N, self.S)
+
+    def grid_bound(self):
+        return grid_bound(self.coverage_max())
 
     def bins_array(self):
         q = self.q

@@ -83,3 +83,43 @@ def test_gradient_matches_central_differences(mods):
             fm = float(ag.chi2(ag.predict(x - e, plan), Vt, W))
         fd = (fp - fm) / 2.0
         assert abs(fd - g[qq, pp]) <= 1e-3 * max(abs(g[qq, pp]), 1e-3 * np.abs(g).max())
+
+
+def test_gradient_at_differentiation_kernels(mods):
+    # the differentiation workload's kernels (S = 15, 64 planes, O = 8) and
+    # array on a reduced model: 512^2 pixels over 0.8 deg (the 4 km array's
+    # baselines stay on the grid), every 8th of the 1,080 dumps (535,680
+    # visibilities)
+    lib, ag, synth = mods
+    d = synth.model_2048(N=512, fov_deg=0.8, time_slice=(0, 1080, 8))
+    N, fov, S, O, P = d["N"], d["fov"], d["S"], d["O"], d["P"]
+    assert (S, O, P) == (15, 8, 64)
+    K, plan = _setup(lib, d)
+    assert plan.n_dropped == 0
+    c1 = oracle.pswf.taper_c1(N, fov, S)
+    q = oracle.quantise.quantise(d["u"], d["v"], d["w"], N, fov, O, S, P, d["w_lo"], d["w_hi"],
+                                 plan.tile_size)
+    T = oracle.tables.separable_table(oracle.tables.w_plane_centres(P, d["w_lo"], d["w_hi"]),
+                                      N, fov, S, O, c1)
+    op = oracle.chi2.SeparableOperator(q, T, c1, N, S, fov)
+    # the model's sources inside the inner half (|l|, |m| <= fov / 4): further
+    # out the taper correction 1 / (c1 c1) grows to ~6e7 at 0.4 fov (S = 15),
+    # and FP32 prediction of such sources is dominated by rounding
+    xm = np.zeros_like(d["x"])
+    inner = (slice(N // 4, 3 * N // 4),) * 2
+    xm[inner] = d["x"][inner]
+    # target: noise at a tenth of the model's visibility RMS, so that neither
+    # residual below (-Vt at x = 0, A x - Vt at the model) is a near
+    # cancellation whose relative error would be the FP32 error of A x
+    # divided by the residual's relative size
+    Vm = op.forward(xm)
+    Vt = 0.1 * np.sqrt(np.mean(np.abs(Vm) ** 2)) * d["noise"][:len(Vm)]
+    for xe in (np.zeros_like(xm), xm):       # gradient at x = 0 and at the model
+        x = dev(xe, torch.float32).requires_grad_(True)
+        loss = ag.chi2(ag.predict(x, plan), dev(Vt, torch.complex64), dev(d["W"], torch.float32))
+        loss.backward()
+        got = x.grad.cpu().numpy()
+        want = oracle.chi2.chi2_grad(op, xe, Vt, d["W"])
+        err = np.linalg.norm((got - want)[inner]) / np.linalg.norm(want[inner])
+        print("gradient at S = 15, P = 64, %d visibilities: rel %.2e" % (len(Vt), err), flush=True)
+        assert err <= 1e-5

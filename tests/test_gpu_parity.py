@@ -1,11 +1,11 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
-Tolerances (relative RMS unless stated): tables 1e-6; grids, images over the
-inner half (|l|,|m| <= fov/4, where 1/(c1 c1) does not amplify FP32 rounding)
-and degridded visibilities 1e-5, the FP32 bound; bins bit-exact.  A grid cell
-sums up to thousands of FP32 products (in the three-multiplication complex
-form), whose rounding alone reaches a few 1e-6 relative on heavy tiles
-(about sqrt(K) 2^-24 for K terms), so grids share the 1e-5 bound.
+Tolerances (relative RMS unless stated): tables 1e-6; grids 1e-6, or
+sqrt(K) 2^-24 where the heaviest cell sums K > 2^8 footprints (the rounding of
+a K-term FP32 sum with random signs; only the 3,000-visibility tile reaches
+it here); images over the inner half (|l|,|m| <= fov/4, where 1/(c1 c1) does
+not amplify FP32 rounding) and degridded visibilities 1e-5, the FP32 bound;
+bins bit-exact.
 """
 import math
 
@@ -122,8 +122,8 @@ def test_grid_only_matches_oracle(lib, nvis):
     K, plan = _make(lib, d)
     G = lib.grid(plan, dev(d["V"], torch.complex64), dev(d["W"], torch.float32),
                  flags=lib.GRID_ONLY).cpu().numpy()
-    want = _oracle(d, plan).grid(d["V"], d["W"])
-    assert rel_rms(G, want) <= 1e-5
+    o = _oracle(d, plan)
+    assert rel_rms(G, o.grid(d["V"], d["W"])) <= o.grid_bound() == 1e-6
 
 
 def test_grid_heavy_tile_and_weights(lib):
@@ -140,7 +140,9 @@ def test_grid_heavy_tile_and_weights(lib):
     K, plan = _make(lib, d)
     G = lib.grid(plan, dev(d["V"], torch.complex64), dev(d["W"], torch.float32),
                  flags=lib.GRID_ONLY).cpu().numpy()
-    assert rel_rms(G, _oracle(d, plan).grid(d["V"], d["W"])) <= 1e-5
+    o = _oracle(d, plan)
+    assert o.coverage_max() > 3000
+    assert rel_rms(G, o.grid(d["V"], d["W"])) <= o.grid_bound()
 
 
 @pytest.mark.parametrize("flags,npow", [(0, 0), ("MUL_N", 1), ("DIV_N", -1)])
@@ -252,7 +254,7 @@ def test_odd_tile_layout(lib):
     o = _oracle(d, plan)
     assert np.array_equal(plan.bins().cpu().numpy().astype(np.int64), o.bins_array())
     G = lib.grid(plan, dev(d["V"], torch.complex64), None, flags=lib.GRID_ONLY).cpu().numpy()
-    assert rel_rms(G, o.grid(d["V"], d["W"])) <= 1e-5
+    assert rel_rms(G, o.grid(d["V"], d["W"])) <= o.grid_bound()
     X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
     V = lib.degrid(plan, dev(X, torch.complex64), flags=lib.GRID_ONLY).cpu().numpy()
     assert rel_rms(V, o.degrid_grid(X)) <= 1e-5
@@ -289,7 +291,7 @@ def test_large_tables_cache_path(lib):
     o = _oracle(d, plan)
     G = lib.grid(plan, dev(d["V"], torch.complex64), dev(d["W"], torch.float32),
                  flags=lib.GRID_ONLY).cpu().numpy()
-    assert rel_rms(G, o.grid(d["V"], d["W"])) <= 1e-5
+    assert rel_rms(G, o.grid(d["V"], d["W"])) <= o.grid_bound()
     X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
     V = lib.degrid(plan, dev(X, torch.complex64), flags=lib.GRID_ONLY).cpu().numpy()
     assert rel_rms(V, o.degrid_grid(X)) <= 1e-5
@@ -324,7 +326,7 @@ def test_grid_and_degrid_at_grid_corners(lib, N, S):
     assert not o.bins_array()[:, 6].any()   # every footprint inside the grid
     G = lib.grid(plan, dev(d["V"], torch.complex64), dev(d["W"], torch.float32),
                  flags=lib.GRID_ONLY).cpu().numpy()
-    assert rel_rms(G, o.grid(d["V"], d["W"])) <= 1e-5
+    assert rel_rms(G, o.grid(d["V"], d["W"])) <= o.grid_bound()
     X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
     V = lib.degrid(plan, dev(X, torch.complex64), flags=lib.GRID_ONLY).cpu().numpy()
     assert rel_rms(V, o.degrid_grid(X)) <= 1e-5
