@@ -127,13 +127,16 @@ def array_4096(dump_s=10.0, channels=16):
                 P=128, w_lo=w_lo, w_hi=w_hi, S=15, O=8, uvw_m=uvw_m, freqs=freqs)
 
 
-def model_2048():
+def model_2048(N=2048, fov_deg=3.0, time_slice=None):
     """Differentiation workload: 2048^2 real model (500 point sources inside
     |l|,|m| <= 0.4 fov, flux log-uniform in [1e-3, 1], plus N(0, 1e-4^2) noise),
     3 deg field, 32 antennas in a 4 km disc, 6 h track in 20 s dumps, 8 channels
-    at 600 + 8c MHz, 64 w-planes, support 15, oversample 8 (4,285,440 vis)."""
+    at 600 + 8c MHz, 64 w-planes, support 15, oversample 8 (4,285,440 vis).
+    A reduced model (smaller N, a narrower field so that the same baselines
+    stay on the grid, a slice of the dumps) keeps the array, the kernels
+    (S = 15, 64 planes, O = 8) and the recipe."""
     rng = np.random.default_rng(SEED0 + 4)
-    N, fov = 2048, deg(3.0)
+    fov = deg(fov_deg)
     lim = int(0.4 * N)                       # 0.4 fov in pixels from the centre
     x = np.zeros((N, N), np.float64)
     px = rng.integers(N // 2 - lim, N // 2 + lim + 1, 500)
@@ -142,7 +145,8 @@ def model_2048():
     np.add.at(x, (py, px), flux)
     x += rng.normal(0.0, 1e-4, (N, N))
     freqs = 600e6 + 8e6 * np.arange(8)
-    u, v, w = track(rng, 32, 4000.0, deg(-30.7), deg(-30.0), (-3.0, 3.0), 20.0, freqs)
+    u, v, w = track(rng, 32, 4000.0, deg(-30.7), deg(-30.0), (-3.0, 3.0), 20.0, freqs,
+                    time_slice=time_slice)
     noise = gaussian_vis(rng, len(u))
     w_lo, w_hi = _w_range(w)
     return dict(x=x, u=u, v=v, w=w, W=np.ones(len(u)), noise=noise, N=N, fov=fov,
