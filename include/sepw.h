@@ -246,6 +246,21 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
                       const float* const* weight, sepw_c64* const* out, uint32_t flags,
                       void* hip_stream);
 
+/* sepw_grid_batched for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same jobs, flags, output and errors, but the job tables, the per-job work
+ * prefix and the work counter live in one static device array of the library
+ * (about 48 KB; each GPU the library runs on holds its own copy until the
+ * process ends), written by a small kernel from kernel arguments, so the call
+ * makes no hipMalloc, hipFree, pinned-host or other allocating call.  At most
+ * 256 jobs: njobs > 256 returns SEPW_ERR_UNSUPPORTED with no device work.
+ * The plans and the caller's outputs must already exist.  Every call on one
+ * GPU shares that GPU's array, which keeps the last call's contents: calls
+ * that overlap in time on one GPU (different streams or threads) race. */
+int sepw_grid_batched_noalloc(int32_t njobs, const sepw_plan* plans, const sepw_c64* const* vis,
+                              const float* const* weight, sepw_c64* const* out, uint32_t flags,
+                              void* hip_stream);
+
 /* W-stacking hybrid (Section 4.3): the visibilities are partitioned into
  * n_slices uniform w-slices on [w_lo, w_hi] (slice s = clamp(floor((w - w_lo)
  * n_slices / (w_hi - w_lo)), 0, n_slices - 1), centre w_s = w_lo + (s + 1/2)

@@ -75,6 +75,7 @@ def load():
     lib.sepw_degrid.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.c_uint32, c_void_p]
     lib.sepw_grid_batched.argtypes = [c_int32, P(c_void_p), P(c_void_p), P(c_void_p), P(c_void_p),
                                       ctypes.c_uint32, c_void_p]
+    lib.sepw_grid_batched_noalloc.argtypes = lib.sepw_grid_batched.argtypes
     lib.sepw_plan_set_item_slots.argtypes = [c_void_p, c_int32, c_void_p]
     lib.sepw_plan_set_degrid_item_slots.argtypes = [c_void_p, c_int32, c_void_p]
     lib.sepw_autotune_batched.argtypes = [c_int32, P(c_void_p), P(c_void_p), P(c_void_p),
@@ -98,7 +99,8 @@ def load():
     lib.sepw_device_count.argtypes = []
     for name in ("sepw_make_kernels", "sepw_kernels_table", "sepw_kernels_taper", "sepw_plan_create",
                  "sepw_plan_bins", "sepw_plan_tile_size", "sepw_grid", "sepw_degrid",
-                 "sepw_grid_batched", "sepw_free_kernels", "sepw_free_plan", "sepw_device_count",
+                 "sepw_grid_batched", "sepw_grid_batched_noalloc", "sepw_free_kernels",
+                 "sepw_free_plan", "sepw_device_count",
                  "sepw_plan_rebin", "sepw_kernels_set_wrange", "sepw_timing_enable",
                  "sepw_timing_collect", "sepw_plan_set_item_slots", "sepw_plan_set_degrid_item_slots",
                  "sepw_autotune_batched", "sepw_wstack_create", "sepw_wstack_grid",
@@ -513,8 +515,9 @@ def autotune_batched(plans, vis, weights=None, outs=None):
     return slots.value, width.value
 
 
-def grid_batched(plans, vis, weights=None, flags=0, outs=None):
-    """sepw_grid_batched over several (facet / snapshot) plans."""
+def grid_batched(plans, vis, weights=None, flags=0, outs=None, noalloc=False):
+    """sepw_grid_batched over several (facet / snapshot) plans
+    (sepw_grid_batched_noalloc with noalloc=True)."""
     n = len(plans)
     vis = [_dev(x, torch.complex64, "vis") for x in vis]
     if weights is None:
@@ -528,5 +531,6 @@ def grid_batched(plans, vis, weights=None, flags=0, outs=None):
     vp = arr(*[x.data_ptr() for x in vis])
     wp = arr(*[0 if x is None else x.data_ptr() for x in weights])
     op = arr(*[x.data_ptr() for x in outs])
-    _check(load().sepw_grid_batched(n, hp, vp, wp, op, flags, _stream()), "sepw_grid_batched")
+    fn = "sepw_grid_batched_noalloc" if noalloc else "sepw_grid_batched"
+    _check(getattr(load(), fn)(n, hp, vp, wp, op, flags, _stream()), fn)
     return outs

@@ -107,12 +107,12 @@ class Stage {
     if (!g_timing) return;
     a_ = pool_event();
     b_ = pool_event();
-    if (a_ && b_) hipEventRecord(a_, s_);
+    if (a_ && b_) (void)hipEventRecord(a_, s_);
   }
   ~Stage() {
     std::lock_guard<std::mutex> lk(g_tmx);
     if (!a_ || !b_) return;
-    hipEventRecord(b_, s_);
+    (void)hipEventRecord(b_, s_);
     g_recs.push_back({stage_, a_, b_});
   }
 
@@ -888,7 +888,89 @@ int wsnap_build(sepw_wsnap_s* W, const double* u, const double* v, const double*
   return rc;
 }
 
+// ---- batched gridding that allocates nothing ----
+// The job tables of sepw_grid_batched_noalloc live in one static device array
+// (each GPU the library runs on holds its own copy until the process ends);
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for the current device, never through the array's name.
+constexpr int kNoAllocMaxJobs = 256;
+struct NoAllocArea {
+  GridArgs jobs[kNoAllocMaxJobs];      // gridding jobs, largest first
+  MoveArgs mjobs[kNoAllocMaxJobs];     // movement jobs, caller order
+  uint32_t first[kNoAllocMaxJobs + 1];   // prefix of work items per job
+  uint32_t mfirst[kNoAllocMaxJobs + 1];  // first movement workgroup per job
+  uint32_t counter;                    // work counter of the persistent launch
+};
+
 }  // namespace
+
+static __device__ __align__(256) unsigned char scratch[sizeof(NoAllocArea)];
+
+namespace {
+
+// Up to kStoreJobs entries of the job tables, passed by value as a kernel
+// argument and written into the area by one small kernel (no host copy).
+constexpr int kStoreJobs = 8;
+struct JobBlock {
+  GridArgs g[kStoreJobs];
+  MoveArgs m[kStoreJobs];
+  uint32_t mfirst[kStoreJobs + 1];
+  int base, n;
+  int last;                            // write mfirst[base + n] too
+};
+
+__global__ void store_jobs_kernel(JobBlock b, NoAllocArea* area) {
+  const int t = threadIdx.x;
+  if (t < b.n) {
+    area->jobs[b.base + t] = b.g[t];
+    area->mjobs[b.base + t] = b.m[t];
+    area->mfirst[b.base + t] = b.mfirst[t];
+  }
+  if (b.last && t == b.n) area->mfirst[b.base + b.n] = b.mfirst[b.n];
+}
+
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_namx;
+NoAllocArea* g_na_ptr[kNoAllocMaxDevices] = {};
+
+// The area of the current device: its address is looked up once per device,
+// with that device current.
+int noalloc_area(NoAllocArea** out) {
+  int dev = 0;
+  SEPW_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return SEPW_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_namx);
+  if (!g_na_ptr[dev]) {
+    void* ptr = nullptr;
+    SEPW_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return SEPW_ERR_HIP;
+    g_na_ptr[dev] = static_cast<NoAllocArea*>(ptr);
+  }
+  *out = g_na_ptr[dev];
+  return SEPW_OK;
+}
+
+int store_job_tables(NoAllocArea* area, int njobs, const GridArgs* g, const MoveArgs* m,
+                     const uint32_t* mfirst, hipStream_t s) {
+  for (int b0 = 0; b0 < njobs; b0 += kStoreJobs) {
+    JobBlock b;
+    b.base = b0;
+    b.n = std::min(kStoreJobs, njobs - b0);
+    b.last = b0 + b.n == njobs ? 1 : 0;
+    for (int t = 0; t < b.n; ++t) {
+      b.g[t] = g[b0 + t];
+      b.m[t] = m[b0 + t];
+      b.mfirst[t] = mfirst[b0 + t];
+    }
+    b.mfirst[b.n] = mfirst[b0 + b.n];
+    hipLaunchKernelGGL(store_jobs_kernel, dim3(1), dim3(64), 0, s, b, area);
+    SEPW_TRY(hipGetLastError());
+  }
+  return SEPW_OK;
+}
+
+}  // namespace
+
 
 extern "C" {
 
@@ -1281,6 +1363,88 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
       if (rc != SEPW_OK) return rc;
     }
     Stage st(SEPW_STAGE_CORRECT, s);
+    SEPW_TRY(launch_correct(img, img, K->c1, N, K->fov, K->l0, K->m0, npow, s));
+  }
+  return SEPW_OK;
+}
+
+int sepw_grid_batched_noalloc(int32_t njobs, const sepw_plan* plans, const sepw_c64* const* vis,
+                              const float* const* weight, sepw_c64* const* out, uint32_t flags,
+                              void* hip_stream) {
+  if (njobs < 1 || !plans || !vis || !out) return SEPW_ERR_ARG;
+  if (njobs > kNoAllocMaxJobs) return SEPW_ERR_UNSUPPORTED;   // the static job tables' size
+  if ((flags & ~(SEPW_GRID_ONLY | SEPW_MUL_N | SEPW_DIV_N)) != 0) return SEPW_ERR_ARG;
+  if ((flags & SEPW_MUL_N) && (flags & SEPW_DIV_N)) return SEPW_ERR_ARG;
+  for (int j = 0; j < njobs; ++j) {
+    if (!plans[j] || !out[j] || (!vis[j] && plans[j]->nvis > 0)) return SEPW_ERR_ARG;
+    const Kernels* K = plans[j]->K;
+    const Kernels* K0 = plans[0]->K;
+    if (K->N != K0->N || K->S != K0->S || K->prm.precision != K0->prm.precision) return SEPW_ERR_ARG;
+    if (plans[j]->generation != K->generation) return SEPW_ERR_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (plans[0]->K->prm.precision != SEPW_FP32) {
+    // job by job, as sepw_grid_batched does (sepw_grid allocates nothing)
+    for (int j = 0; j < njobs; ++j) {
+      int rc = sepw_grid(plans[j], vis[j], weight ? weight[j] : nullptr, out[j], flags, hip_stream);
+      if (rc != SEPW_OK) return rc;
+    }
+    return SEPW_OK;
+  }
+  NoAllocArea* area = nullptr;
+  int rc = noalloc_area(&area);
+  if (rc != SEPW_OK) return rc;
+  const bool grid_only = flags & SEPW_GRID_ONLY;
+  const int N = plans[0]->K->N, S = plans[0]->K->S;
+  // jobs in decreasing size (stable), so the largest start first
+  int order[kNoAllocMaxJobs];
+  for (int j = 0; j < njobs; ++j) {
+    int i = j;
+    while (i > 0 && plans[order[i - 1]]->nvis < plans[j]->nvis) {
+      order[i] = order[i - 1];
+      --i;
+    }
+    order[i] = j;
+  }
+  GridArgs g[kNoAllocMaxJobs];
+  MoveArgs m[kNoAllocMaxJobs];
+  uint32_t mfirst[kNoAllocMaxJobs + 1];
+  int64_t mtotal = 0;
+  mfirst[0] = 0;
+  for (int j = 0; j < njobs; ++j) {
+    m[j] = move_args(plans[j], vis[j], weight ? weight[j] : nullptr);
+    mtotal += move_blocks(plans[j]->nvis);
+    if (mtotal > 0xFFFFFFFFLL) return SEPW_ERR_UNSUPPORTED;
+    mfirst[j + 1] = (uint32_t)mtotal;
+  }
+  for (int r = 0; r < njobs; ++r) {
+    Plan* p = plans[order[r]];
+    Kernels* K = p->K;
+    g[r] = GridArgs{p->gl.items, p->gl.itoff + 8 * p->r8, p->gl.itoff, p->r8, p->qctr, p->tdesc,
+                    p->krec, p->yrow, K->pad_u, K->pad_v, K->tab_len, N, p->ntx,
+                    grid_only ? 0 : 1, reinterpret_cast<float2*>(out[order[r]]), 0};
+  }
+  rc = store_job_tables(area, njobs, g, m, mfirst, s);
+  if (rc != SEPW_OK) return rc;
+  SEPW_TRY(launch_vis_to_rows_batched(area->mjobs, area->mfirst, njobs, mtotal, s));
+  for (int j = 0; j < njobs; ++j)
+    SEPW_TRY(launch_zero_c64(reinterpret_cast<float2*>(out[j]), (int64_t)N * N, s));
+  SEPW_TRY(launch_job_prefix(area->jobs, njobs, area->first, &area->counter, s));
+  SEPW_TRY(launch_grid_fp32_batched(S, area->jobs, area->first, njobs, &area->counter,
+                                    plans[0]->K->n_cu * g_blocks_per_cu, s));
+  for (int j = 0; j < njobs; ++j) {
+    Plan* p = plans[j];
+    if (!p->K->corr) continue;
+    SEPW_TRY(launch_corr_grid(S, corr_args(p, p->gl, reinterpret_cast<float2*>(out[j]), grid_only ? 0 : 1),
+                              p->gl.max_items, s));
+  }
+  if (grid_only) return SEPW_OK;
+  const int npow = (flags & SEPW_MUL_N) ? 1 : ((flags & SEPW_DIV_N) ? -1 : 0);
+  for (int j = 0; j < njobs; ++j) {
+    Kernels* K = plans[j]->K;
+    float2* img = reinterpret_cast<float2*>(out[j]);
+    rc = fft_exec(K, img, HIPFFT_BACKWARD, s);
+    if (rc != SEPW_OK) return rc;
     SEPW_TRY(launch_correct(img, img, K->c1, N, K->fov, K->l0, K->m0, npow, s));
   }
   return SEPW_OK;
