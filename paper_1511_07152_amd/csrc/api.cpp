@@ -68,16 +68,6 @@ int map_hip(hipError_t e) {
 
 bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
-// work distribution of the LDS gridding kernel (0: one counter over all
-// items, 1: per-XCD lists); SEPW_GRID_SCHED overrides the default
-int grid_sched() {
-  static const int v = [] {
-    const char* e = std::getenv("SEPW_GRID_SCHED");
-    return e ? std::atoi(e) : 0;
-  }();
-  return v;
-}
-
 // ---- optional per-stage timing (benchmarking aid) ----
 struct TimingRec {
   int stage;
@@ -184,12 +174,6 @@ void destroy_kernels(Kernels* k) {
   if (k->lp_v && k->lp_v != k->lp_u) dfree(k->lp_v);
   k->lp_v = nullptr;
   dfree(k->lp_u);
-  if (k->sc_v && k->sc_v != k->sc_u) dfree(k->sc_v);
-  k->sc_v = nullptr;
-  dfree(k->sc_u);
-  dfree(k->pad_us);
-  dfree(k->pad_vs);
-  dfree(k->lp_bound);
   dfree(k->corr);
   dfree(k->corr_tmp);
   if (k->fft_ok) hipfftDestroy(k->fft);
@@ -221,6 +205,7 @@ void destroy_plan(Plan* p) {
     dfree(l->items);
   }
   dfree(p->qctr);
+  dfree(p->lp_max);
   dfree(p->scan_tmp);
   delete static_cast<sepw_plan_s*>(p);
 }
@@ -271,15 +256,9 @@ hipError_t make_separable_tables(Kernels* K, hipStream_t s) {
     e = launch_pad_table(K->tab_v, nullptr, K->P, K->O, K->S, K->pad_sv, s, true);
   if (e == hipSuccess && K->lp_u) {
     const int bf16 = K->prm.precision == SEPW_BF16 ? 1 : 0;
-    e = launch_plane_scales(K->tab_u, K->P, K->O * K->S, K->sc_u, s);
-    if (e == hipSuccess && K->sc_v != K->sc_u)
-      e = launch_plane_scales(K->tab_v, K->P, K->O * K->S, K->sc_v, s);
-    if (e == hipSuccess) e = launch_lp_table(K->tab_u, K->sc_u, K->P, K->O, K->S, bf16, K->lp_u, s);
+    e = launch_lp_table(K->tab_u, K->P, K->O, K->S, bf16, K->tab_len, K->lp_u, s);
     if (e == hipSuccess && K->lp_v != K->lp_u)
-      e = launch_lp_table(K->tab_v, K->sc_v, K->P, K->O, K->S, bf16, K->lp_v, s);
-    if (e == hipSuccess) e = launch_pad_table(K->tab_u, K->sc_v, K->P, K->O, K->S, K->pad_us, s);
-    if (e == hipSuccess) e = launch_pad_table(K->tab_v, K->sc_u, K->P, K->O, K->S, K->pad_vs, s);
-    if (e == hipSuccess) e = launch_lp_bound(K->sc_u, K->sc_v, K->P, K->lp_bound, s);
+      e = launch_lp_table(K->tab_v, K->P, K->O, K->S, bf16, K->tab_len, K->lp_v, s);
   }
   return e;
 }
@@ -399,24 +378,20 @@ int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K) {
     SEPW_TRY(dalloc(&K->pad_v, npad));
     SEPW_TRY(dalloc(&K->pad_sv, npad));
   }
+  // the 16-bit tables: (Re, Im) dwords, BF16 high then low parts
+  const int64_t nlp = npad * (p->precision == SEPW_BF16 ? 2 : 1);
+  K->tab_len = (int)npad;
   if (p->precision != SEPW_FP32) {
-    SEPW_TRY(dalloc(&K->lp_u, npad));
-    SEPW_TRY(dalloc(&K->sc_u, K->P));
+    SEPW_TRY(dalloc(&K->lp_u, nlp));
     if (shared_axes) {
       K->lp_v = K->lp_u;
-      K->sc_v = K->sc_u;
     } else {
-      SEPW_TRY(dalloc(&K->lp_v, npad));
-      SEPW_TRY(dalloc(&K->sc_v, K->P));
+      SEPW_TRY(dalloc(&K->lp_v, nlp));
     }
-    SEPW_TRY(dalloc(&K->pad_us, npad));
-    SEPW_TRY(dalloc(&K->pad_vs, npad));
-    SEPW_TRY(dalloc(&K->lp_bound, 1));
   }
   SEPW_TRY(make_tables(K, s));
   SEPW_TRY(dalloc(&K->scratch, (int64_t)N * N));
   // stage the FP32 tables in LDS when both fit in one workgroup's share
-  K->tab_len = (int)npad;
   {
     int dev = 0, max_lds = 0, ncu = 0;
     SEPW_TRY(hipGetDevice(&dev));
@@ -425,8 +400,8 @@ int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K) {
     const int64_t bytes = (int64_t)sizeof(float2) * npad * (shared_axes ? 1 : 2);
     K->n_cu = ncu > 0 ? ncu : 1;
     K->lds_bytes = bytes <= (int64_t)max_lds ? (int)bytes : 0;
-    const int64_t vs_bytes = (int64_t)sizeof(float2) * npad;
-    K->lds_bytes_vs = vs_bytes <= (int64_t)max_lds ? (int)vs_bytes : 0;
+    const int64_t lp_bytes = (int64_t)sizeof(uint32_t) * nlp * (shared_axes ? 1 : 2);
+    K->lds_bytes_lp = lp_bytes <= (int64_t)max_lds ? (int)lp_bytes : 0;
   }
   if (hipfftPlan2d(&K->fft, N, N, HIPFFT_C2C) != HIPFFT_SUCCESS) return SEPW_ERR_FFT;
   K->fft_ok = true;
@@ -484,6 +459,7 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
     SEPW_TRY(dalloc(&l->items, l->max_items));
   }
   SEPW_TRY(dalloc(&P->qctr, 8));
+  SEPW_TRY(dalloc(&P->lp_max, 2));
   SEPW_TRY(dalloc(&P->scan_tmp, P->scan_tmp_len));
   if (K->facet) SEPW_TRY(dalloc(&P->rot, capacity));
   return SEPW_OK;
@@ -500,6 +476,7 @@ MoveArgs move_args(const Plan* p, const sepw_c64* vis, const float* weight) {
   m.yrow = p->yrow;
   m.nvis = p->nvis;
   m.nbins = p->nbins;
+  m.vmax = nullptr;
   return m;
 }
 
@@ -1177,7 +1154,12 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
   if (p->generation != K->generation) return SEPW_ERR_ARG;
   {
     Stage st(SEPW_STAGE_GATHER, s);
-    SEPW_TRY(launch_vis_to_rows(move_args(p, vis, weight), s));
+    MoveArgs m = move_args(p, vis, weight);
+    if (K->prm.precision == SEPW_FP16) {
+      SEPW_TRY(launch_fill_u32(p->lp_max, 0u, 1, s));
+      m.vmax = p->lp_max;
+    }
+    SEPW_TRY(launch_vis_to_rows(m, s));
   }
   {
     Stage st(SEPW_STAGE_FILL, s);
@@ -1188,7 +1170,7 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
     if (K->prm.precision == SEPW_FP32) {
       GridArgs a{p->gl.items, p->gl.itoff + 8 * p->r8, p->gl.itoff, p->r8, p->qctr, p->tdesc, p->krec,
                  p->yrow, K->pad_u, K->pad_v,
-                 K->tab_len, N, p->ntx, grid_only ? 0 : 1, img, grid_sched()};
+                 K->tab_len, N, p->ntx, grid_only ? 0 : 1, img};
       if (K->lds_bytes > 0) {
         SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8, s));
         SEPW_TRY(launch_grid_fp32_lds(K->S, a, K->lds_bytes, K->n_cu, s));
@@ -1196,10 +1178,10 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
         SEPW_TRY(launch_grid_fp32(K->S, a, p->gl.max_items, s));
       }
     } else {
-      GridArgsLp a{p->gl.items, p->gl.itoff + 8 * p->r8, p->gl.itoff, p->r8, p->qctr, p->tdesc, p->krec,
-                   p->yrow, K->pad_us, K->lp_v,
-                   K->lp_bound, N, p->ntx, grid_only ? 0 : 1, img};
-      SEPW_TRY(launch_grid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->gl.max_items, s));
+      GridArgsLp a{p->gl.items, p->gl.itoff + 8 * p->r8, p->tdesc, p->krec, p->yrow, K->pad_u,
+                   K->pad_v, K->tab_len, p->lp_max, p->qctr, N, p->ntx, grid_only ? 0 : 1, img};
+      SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8, s));
+      SEPW_TRY(launch_grid_lp(K->S, K->prm.precision == SEPW_BF16, a, K->lds_bytes, K->n_cu, s));
     }
   }
   if (K->corr) {
@@ -1255,11 +1237,14 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
                    K->tab_len, N, p->ntx, checker, p->yrow};
       SEPW_TRY(launch_degrid_fp32(K->S, a, p->dl.max_items, K->lds_bytes, K->n_cu, s));
     } else {
-      DegridArgsLp a{p->dl.items, p->dl.itoff + 8 * p->r8, p->dl.itoff, p->r8, p->qctr, p->tdesc, p->krec,
-                     src, K->lp_u, K->pad_vs, K->tab_len, N,
-                     p->ntx, checker, p->yrow};
-      SEPW_TRY(launch_degrid_lp(K->S, K->prm.precision == SEPW_BF16, a, p->dl.max_items,
-                                K->lds_bytes_vs, K->n_cu, s));
+      const bool bf16 = K->prm.precision == SEPW_BF16;
+      if (!bf16) {
+        SEPW_TRY(launch_fill_u32(p->lp_max + 1, 0u, 1, s));
+        SEPW_TRY(launch_absmax(src, (int64_t)N * N, p->lp_max + 1, s));
+      }
+      DegridArgsLp a{p->dl.items, p->dl.itoff, p->r8, p->qctr, p->tdesc, p->krec, src, K->lp_u,
+                     K->lp_v, K->tab_len, p->lp_max + 1, N, p->ntx, checker, p->yrow};
+      SEPW_TRY(launch_degrid_lp(K->S, bf16, a, K->lds_bytes_lp, K->n_cu, s));
     }
   }
   if (K->corr) {
@@ -1422,7 +1407,7 @@ int sepw_grid_batched_noalloc(int32_t njobs, const sepw_plan* plans, const sepw_
     Kernels* K = p->K;
     g[r] = GridArgs{p->gl.items, p->gl.itoff + 8 * p->r8, p->gl.itoff, p->r8, p->qctr, p->tdesc,
                     p->krec, p->yrow, K->pad_u, K->pad_v, K->tab_len, N, p->ntx,
-                    grid_only ? 0 : 1, reinterpret_cast<float2*>(out[order[r]]), 0};
+                    grid_only ? 0 : 1, reinterpret_cast<float2*>(out[order[r]])};
   }
   rc = store_job_tables(area, njobs, g, m, mfirst, s);
   if (rc != SEPW_OK) return rc;

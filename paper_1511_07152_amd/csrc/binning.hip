@@ -748,6 +748,7 @@ struct MoveLds {
   uint32_t dl[kMaxRowBins];   // the chunk's row of delta
   float2 stage[kChunk];
   uint16_t binof[kChunk];
+  float wmax[kL1Threads / 64];
 };
 
 __device__ inline void load_deltas(const uint32_t* __restrict__ delta, int64_t chunk, int nbins,
@@ -774,6 +775,7 @@ __device__ inline void to_rows_chunk(const MoveArgs& a, int64_t chunk, MoveLds& 
     wt[m] = (in && a.weight) ? __builtin_nontemporal_load(a.weight + i) : 1.f;
     ro[m] = (in && a.rot) ? a.rot[i] : make_float2(1.f, 0.f);
   }
+  float mx = 0.f;   // max |Re, Im| of the placed values (fmaxf skips NaN)
 #pragma unroll
   for (int m = 0; m < kPerThread; ++m) {
     if (pl[m] == kDropped) continue;
@@ -782,11 +784,22 @@ __device__ inline void to_rows_chunk(const MoveArgs& a, int64_t chunk, MoveLds& 
     const uint32_t k = pl[m] & kPlaceMask;
     L.stage[k] = v;
     L.binof[k] = (uint16_t)(pl[m] >> kPlaceShift);
+    mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
   }
   __syncthreads();
   const uint32_t kept = a.ckept[chunk];
   for (uint32_t k = threadIdx.x; k < kept; k += kL1Threads)
     a.yrow[L.dl[L.binof[k]] + k] = L.stage[k];
+  if (a.vmax) {
+    // one atomic maximum per workgroup (non-negative floats order as their bits)
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) L.wmax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < kL1Threads / 64; ++w) mx = fmaxf(mx, L.wmax[w]);
+      if (mx > 0.f) atomicMax(a.vmax, __float_as_uint(mx));
+    }
+  }
 }
 
 __global__ __launch_bounds__(kL1Threads) void to_rows_kernel(MoveArgs a) {

@@ -299,14 +299,6 @@ __global__ __launch_bounds__(64 * kWaves) void grid_fp32_batched_kernel(
 
 constexpr int kLdsWaves = 16;
 
-// The ring: block blk (lo) and block blk + 1 (hi) of 16 grid columns; lane
-// column c holds grid column 16 blk + c (lo) and 16 (blk + 1) + c (hi), rows
-// 4 grp + r of the item's 16 rows.
-struct RegRing {
-  f32x4 lo_re, lo_im, hi_re, hi_im;
-  int blk;
-};
-
 struct LdsState {
   f32x4 p1, p2, p3;   // region sums of the current tile (three real products)
   int x0;             // first grid column of the current region
@@ -328,51 +320,19 @@ struct LdsCtx {
   int col8, grp4;
 };
 
-// Add the ring's lo block (grid columns 16 blk + c, rows y0 + 4 grp + r) to the
-// grid with atomics ((-1)^(x+y) when the grid feeds the centred FFT), then
-// move hi down to lo and clear hi.
 __device__ inline void ring_shift(RegRing& rg, const LdsCtx& c) {
-  const int gx = 16 * rg.blk + c.col;
-  if (gx >= 0 && gx < c.N) {
-    const int gy0 = c.y0 + 4 * c.grp;
-    float sg = (c.checker && ((gx + gy0) & 1)) ? -1.f : 1.f;
-    float* p = c.grid + 2 * ((int64_t)gy0 * c.N + gx);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int gy = gy0 + r;
-      if (gy >= 0 && gy < c.N) {
-        if (rg.lo_re[r] != 0.f) unsafeAtomicAdd(p, sg * rg.lo_re[r]);
-        if (rg.lo_im[r] != 0.f) unsafeAtomicAdd(p + 1, sg * rg.lo_im[r]);
-      }
-      p += 2 * (int64_t)c.N;
-      if (c.checker) sg = -sg;
-    }
-  }
-  rg.lo_re = rg.hi_re;
-  rg.lo_im = rg.hi_im;
-  rg.hi_re = f32x4{0.f, 0.f, 0.f, 0.f};
-  rg.hi_im = rg.hi_re;
-  rg.blk += 1;
+  reg_ring_shift(rg, c.grid, c.N, c.checker, c.y0, c.col, c.grp, 1.f);
 }
 
 // Bank the current tile's region sums into the ring block of this lane's column.
 __device__ inline void ring_bank(RegRing& rg, const LdsState& st, int col) {
-  const int xa = st.x0 + ((col - st.x0) & 15);
   f32x4 re, im;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     re[r] = st.p1[r] - st.p2[r];
     im[r] = st.p3[r] - st.p1[r] - st.p2[r];
   }
-  // selects, not a branch: each lane adds to one block and 0 to the other
-  const bool hi = (xa >> 4) != rg.blk;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    rg.hi_re[r] += hi ? re[r] : 0.f;
-    rg.hi_im[r] += hi ? im[r] : 0.f;
-    rg.lo_re[r] += hi ? 0.f : re[r];
-    rg.lo_im[r] += hi ? 0.f : im[r];
-  }
+  reg_ring_add(rg, re, im, st.x0, col);
 }
 
 // Record of group j (table bases and W V of slot 4 (j % 16) + grp of the
@@ -436,14 +396,7 @@ __device__ __forceinline__ void grid_step_lds(const GridArgs& a, const LdsCtx& c
     // the new region has left behind, restart the sums
     ring_bank(rg, st, c.col);
     const int x0 = tw.tx * C - H;
-    const int b = x0 >> 4;   // floor(x0 / 16), also for x0 < 0
-    if (b > rg.blk) {
-      ring_shift(rg, c);
-      if (b > rg.blk) {
-        ring_shift(rg, c);
-        rg.blk = b;
-      }
-    }
+    reg_ring_advance(rg, x0, c.grid, c.N, c.checker, c.y0, c.col, c.grp, 1.f);
     st.x0 = x0;
     st.pe = tw.padded_end();
     first = true;
@@ -546,8 +499,8 @@ __device__ __forceinline__ void grid_item_lds(const GridArgs& a, const char* tu,
 }
 
 // One workgroup of 16 waves per CU with the tables in LDS; waves take work
-// items from one counter over all items (sched 0) or from the list of the XCD
-// they run on (sched 1).
+// items from one counter over all items (measured faster here than the
+// per-XCD lists: 2.49 vs 2.83 ms at array scale).
 template <int S>
 __global__ __launch_bounds__(64 * kLdsWaves) void grid_fp32_lds_kernel(GridArgs a) {
   extern __shared__ float2 smem[];
@@ -560,17 +513,13 @@ __global__ __launch_bounds__(64 * kLdsWaves) void grid_fp32_lds_kernel(GridArgs 
   const char* tu = reinterpret_cast<const char*>(smem);
   const char* tv = reinterpret_cast<const char*>(two ? smem + n : smem);
   const int lane = threadIdx.x & 63;
-  if (a.sched) {
-    for_items(a.lists, a.r8, a.qctr, lane, [&](int it) { grid_item_lds<S>(a, tu, tv, it, lane); });
-  } else {
-    const int n_items = uniform((int)*a.nitems);
-    while (true) {
-      int it = 0;
-      if (lane == 0) it = (int)atomicAdd(a.qctr, 1u);
-      it = uniform(__shfl(it, 0, 64));
-      if (it >= n_items) break;
-      grid_item_lds<S>(a, tu, tv, it, lane);
-    }
+  const int n_items = uniform((int)*a.nitems);
+  while (true) {
+    int it = 0;
+    if (lane == 0) it = (int)atomicAdd(a.qctr, 1u);
+    it = uniform(__shfl(it, 0, 64));
+    if (it >= n_items) break;
+    grid_item_lds<S>(a, tu, tv, it, lane);
   }
 }
 

@@ -68,21 +68,14 @@ struct Kernels {
   float2* pad_v = nullptr;
   float2* pad_su = nullptr;    // the same with tap s times (-1)^s (degridding from the FFT)
   float2* pad_sv = nullptr;
-  // precision form (FP16 / BF16): per-plane scales s_k, 16-bit padded tables
-  // holding T / s_k, and FP32 padded tables pre-multiplied by the other axis'
-  // scale (u-table times s_k^v for the gridding row product, v-table times
-  // s_k^u for the degridding epilogue); lp_bound = max_k s_k^u s_k^v
-  float* sc_u = nullptr;
-  float* sc_v = nullptr;
+  // precision form (FP16 / BF16): 16-bit padded tables for degridding
+  // (gridding uses the FP32 padded tables)
   uint32_t* lp_u = nullptr;
   uint32_t* lp_v = nullptr;
-  float2* pad_us = nullptr;
-  float2* pad_vs = nullptr;
-  float* lp_bound = nullptr;
   float2* scratch = nullptr;   // N*N complex64 work grid for degridding
   int tab_len = 0;             // entries of one padded table (P O L)
   int lds_bytes = 0;           // > 0: the FP32 kernels stage the tables in LDS
-  int lds_bytes_vs = 0;        // > 0: the 16-bit degridding kernels stage the FP32 v-table in LDS
+  int lds_bytes_lp = 0;        // > 0: the 16-bit degridding kernels stage their tables in LDS
   int n_cu = 0;                // compute units of the device
   hipfftHandle fft = 0;
   bool fft_ok = false;
@@ -147,6 +140,8 @@ struct Plan {
   float2* rot = nullptr;        // [nvis] facet phase rotation, caller order
   int r8 = 0;                   // rows of tiles per work list: ceil(nty / 8)
   uint32_t* qctr = nullptr;     // [8] work-list counters of a launch
+  uint32_t* lp_max = nullptr;   // [2] FP16 scales of the current call: max |Re, Im| of W V
+                                // (gridding) and of the grid (degridding), as float bits
   WorkList gl;                  // gridding work items
   WorkList dl;                  // degridding work items (shorter: fewer rows of results in flight)
   uint32_t* scan_tmp = nullptr; // block partials for the scans
@@ -246,6 +241,8 @@ struct MoveArgs {
   float2* yrow;
   int64_t nvis;
   int nbins;
+  uint32_t* vmax;           // may be null: atomic maximum of max |Re, Im| of the placed
+                            // W V (float bits), for the FP16 gridding scale
 };
 hipError_t launch_vis_to_rows(const MoveArgs& a, hipStream_t s);
 // workgroups of the movement pass for nvis visibilities
@@ -316,7 +313,6 @@ struct GridArgs {
   int N, ntx;
   int checker;              // apply (-1)^(x+y) for the centred FFT
   float2* grid;
-  int sched;                // LDS kernel: 0 = one counter over all items, 1 = per-XCD lists
 };
 
 struct DegridArgs {
@@ -336,18 +332,20 @@ struct DegridArgs {
   float2* yrow;             // results in row-bin order (padding slots are not written)
 };
 
+// Precision form (FP16 / BF16).  Gridding reads the FP32 padded tables;
+// degridding reads 16-bit padded tables holding the taps as (Re, Im) pairs
+// (FP16, or for BF16 the high parts followed by the low parts at + tab_len).
 struct GridArgsLp {
   const int4* items;
   const uint32_t* nitems;
-  const uint32_t* lists;    // work lists (itoff of the plan), r8 rows per list
-  int r8;
-  uint32_t* qctr;           // list counters, zero at launch
   const uint2* tdesc;
   const SlotRec* krec;
   const float2* yrow;
-  const float2* pad_us;     // FP32 padded u-table times s_k^v (row product in FP32)
-  const uint32_t* lp_v;     // 16-bit padded v-table / s_k^v, packed (re | im << 16)
-  const float* lp_bound;    // max_k s_k^u s_k^v
+  const float2* tab_u;      // FP32 padded tables
+  const float2* tab_v;
+  int tab_len;
+  const uint32_t* vmax;     // FP16: bits of max |Re, Im| of W V over the call
+  uint32_t* qctr;           // item counter, zero at launch
   int N, ntx;
   int checker;
   float2* grid;
@@ -355,18 +353,18 @@ struct GridArgsLp {
 
 struct DegridArgsLp {
   const int4* items;
-  const uint32_t* nitems;
   const uint32_t* lists;    // work lists (itoff of the plan), r8 rows per list
   int r8;
   uint32_t* qctr;           // list counters, zero at launch
   const uint2* tdesc;
   const SlotRec* krec;
   const float2* grid;
-  const uint32_t* lp_u;     // 16-bit padded u-table / s_k^u
-  const float2* pad_vs;     // FP32 padded v-table times s_k^u (epilogue)
-  int tab_len;              // entries of the padded tables
+  const uint32_t* lp_u;     // 16-bit padded tables
+  const uint32_t* lp_v;
+  int tab_len;
+  const uint32_t* gmax;     // FP16: bits of max |Re, Im| of the grid
   int N, ntx;
-  int checker;
+  int checker;              // the grid comes from the centred FFT: region times (-1)^(x+y)
   float2* yrow;
 };
 
@@ -384,21 +382,23 @@ hipError_t launch_job_prefix(const GridArgs* jobs, int njobs, uint32_t* first, u
                              hipStream_t s);
 hipError_t launch_job_prefix(const DegridArgs* jobs, int njobs, uint32_t* first, uint32_t* counter,
                              hipStream_t s);
-hipError_t launch_grid_lp(int S, bool bf16, const GridArgsLp& a, int64_t max_items, hipStream_t s);
-// lds_bytes > 0: the FP32 v-table (a.tab_len entries) is staged in LDS
-hipError_t launch_degrid_lp(int S, bool bf16, const DegridArgsLp& a, int64_t max_items,
-                            int lds_bytes, int n_cu, hipStream_t s);
+// lds_bytes > 0: the FP32 tables (gridding) or the 16-bit tables (degridding)
+// are staged in LDS by one 16-wave workgroup per CU; else 4 workgroups of 4
+// waves per CU read them through the caches.  Counters must be zero at launch.
+hipError_t launch_grid_lp(int S, bool bf16, const GridArgsLp& a, int lds_bytes, int n_cu,
+                          hipStream_t s);
+hipError_t launch_degrid_lp(int S, bool bf16, const DegridArgsLp& a, int lds_bytes, int n_cu,
+                            hipStream_t s);
+// atomic maximum of max |Re, Im| over n complex values into *out (float bits)
+hipError_t launch_absmax(const float2* g, int64_t n, uint32_t* out, hipStream_t s);
 // zero-padded FP32 tables: out[k][fi][c - 1 + s] = tab[k][fi][s] * (scale ? scale[k] : 1),
 // times (-1)^s when alternate
 hipError_t launch_pad_table(const float2* tab, const float* scale, int P, int O, int S, float2* out,
                             hipStream_t s, bool alternate = false);
-// per-plane scales s_k = max |Re, Im| over the plane
-hipError_t launch_plane_scales(const float2* tab, int P, int per_plane, float* scale, hipStream_t s);
-// 16-bit padded tables holding T / s_k
-hipError_t launch_lp_table(const float2* tab, const float* scale, int P, int O, int S, int bf16,
+// 16-bit padded tables (rows of L = 32 - S taps as in the FP32 padded tables):
+// FP16 (Re, Im) pairs, or BF16 high parts then low parts at + tab_len
+hipError_t launch_lp_table(const float2* tab, int P, int O, int S, int bf16, int tab_len,
                            uint32_t* out, hipStream_t s);
-// lp_bound = max_k su[k] sv[k]
-hipError_t launch_lp_bound(const float* su, const float* sv, int P, float* bound, hipStream_t s);
 // lds_bytes > 0: stage both padded tables (2 tab_len entries, or one table when
 // tab_u == tab_v) in LDS, with workgroups that own a whole CU
 hipError_t launch_degrid_fp32(int S, const DegridArgs& a, int64_t max_items, int lds_bytes,

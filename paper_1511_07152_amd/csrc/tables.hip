@@ -136,56 +136,34 @@ __global__ void pad_table_kernel(const float2* __restrict__ tab, const float* __
   }
 }
 
-__device__ inline float block_max256(float v, float* sh) {
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  return fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
-}
-
-__global__ __launch_bounds__(256) void plane_scale_kernel(const float2* __restrict__ tab,
-                                                          int per_plane, float* __restrict__ scale) {
-  __shared__ float sh[4];
-  const float2* t = tab + (int64_t)blockIdx.x * per_plane;
-  float mx = 0.f;
-  for (int i = threadIdx.x; i < per_plane; i += 256) mx = fmaxf(mx, fmaxf(fabsf(t[i].x), fabsf(t[i].y)));
-  mx = block_max256(mx, sh);
-  if (threadIdx.x == 0) scale[blockIdx.x] = mx > 0.f ? mx : 1.f;
-}
-
-__device__ inline uint32_t to16(float x, int bf16) {
-  if (bf16) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
-    return u >> 16;
-  }
+// 16-bit padded tables: row of L dwords per (plane, sub-cell row), tap s of
+// the row at c - 1 + s as (Re, Im) rounded to nearest even (FP16, or BF16 high
+// parts); BF16 low parts, bf16(x - hi), at + tab_len.
+__device__ inline uint32_t f16_bits(float x) {
   return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)x);
 }
+__device__ inline uint32_t bf16_bits(float x) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x);
+}
+__device__ inline float bf16_value(uint32_t b) { return __uint_as_float(b << 16); }
 
-__global__ void lp_table_kernel(const float2* __restrict__ tab, const float* __restrict__ scale,
-                                int O, int S, int bf16, uint32_t* __restrict__ out) {
+__global__ void lp_table_kernel(const float2* __restrict__ tab, int S, int bf16, int tab_len,
+                                uint32_t* __restrict__ out) {
   const int L = padded_len(S), c = kRegion + 1 - S;
-  const int row = blockIdx.x, k = row / O;
-  const float inv = 1.f / scale[k];
+  const int row = blockIdx.x;
   for (int x = threadIdx.x; x < L; x += blockDim.x) {
     const int s = x - (c - 1);
-    uint32_t v = 0u;
-    if (s >= 0 && s < S) {
-      const float2 t = tab[(int64_t)row * S + s];
-      v = to16(t.x * inv, bf16) | (to16(t.y * inv, bf16) << 16);
+    float2 t = make_float2(0.f, 0.f);
+    if (s >= 0 && s < S) t = tab[(int64_t)row * S + s];
+    const int64_t i = (int64_t)row * L + x;
+    if (bf16) {
+      const uint32_t hr = bf16_bits(t.x), hi = bf16_bits(t.y);
+      out[i] = hr | (hi << 16);
+      out[i + tab_len] = bf16_bits(t.x - bf16_value(hr)) | (bf16_bits(t.y - bf16_value(hi)) << 16);
+    } else {
+      out[i] = f16_bits(t.x) | (f16_bits(t.y) << 16);
     }
-    out[(int64_t)row * L + x] = v;
   }
-}
-
-__global__ __launch_bounds__(256) void lp_bound_kernel(const float* __restrict__ su,
-                                                       const float* __restrict__ sv, int P,
-                                                       float* __restrict__ bound) {
-  __shared__ float sh[4];
-  float mx = 0.f;
-  for (int k = threadIdx.x; k < P; k += 256) mx = fmaxf(mx, su[k] * sv[k]);
-  mx = block_max256(mx, sh);
-  if (threadIdx.x == 0) *bound = mx;
 }
 
 }  // namespace
@@ -209,19 +187,9 @@ hipError_t launch_pad_table(const float2* tab, const float* scale, int P, int O,
   return hipGetLastError();
 }
 
-hipError_t launch_plane_scales(const float2* tab, int P, int per_plane, float* scale, hipStream_t s) {
-  hipLaunchKernelGGL(plane_scale_kernel, dim3(P), dim3(256), 0, s, tab, per_plane, scale);
-  return hipGetLastError();
-}
-
-hipError_t launch_lp_table(const float2* tab, const float* scale, int P, int O, int S, int bf16,
+hipError_t launch_lp_table(const float2* tab, int P, int O, int S, int bf16, int tab_len,
                            uint32_t* out, hipStream_t s) {
-  hipLaunchKernelGGL(lp_table_kernel, dim3(P * O), dim3(32), 0, s, tab, scale, O, S, bf16, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_lp_bound(const float* su, const float* sv, int P, float* bound, hipStream_t s) {
-  hipLaunchKernelGGL(lp_bound_kernel, dim3(1), dim3(256), 0, s, su, sv, P, bound);
+  hipLaunchKernelGGL(lp_table_kernel, dim3(P * O), dim3(32), 0, s, tab, S, bf16, tab_len, out);
   return hipGetLastError();
 }
 

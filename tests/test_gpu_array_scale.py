@@ -127,39 +127,6 @@ def test_sampled_degrid(setup):
     assert rel_rms(got, want) <= 1e-5
 
 
-def _round16(x, bf16):
-    """Round float32 values to BF16 (round to nearest even) or FP16."""
-    x = np.asarray(x, np.float32)
-    if bf16:
-        u = x.view(np.uint32).astype(np.uint64)
-        u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
-        return u.astype(np.uint32).view(np.float32).astype(np.float64)
-    return x.astype(np.float16).astype(np.float64)
-
-
-def _cells_16bit_model(q, y, T, N, S, cells, bf16):
-    """Rounding model of the 16-bit gridding operands at selected cells: the
-    A operand is the v-table tap over its plane's scale s_k = max |Re, Im|,
-    the B operand y (s_k Tu) formed in FP32, each part rounded to 16 bits;
-    products and sums exact.  (The per-tile power-of-two scale does not change
-    the rounding.)"""
-    T32 = T.astype(np.complex64)
-    sk = np.max(np.maximum(np.abs(T32.real), np.abs(T32.imag)), axis=(1, 2)).astype(np.float32)
-    h = S // 2
-    out = np.zeros(len(cells), complex)
-    for n, (jv, ju) in enumerate(cells):
-        s = ju - q['cell_u'] + h
-        t = jv - q['cell_v'] + h
-        i = np.flatnonzero(~q['dropped'] & (s >= 0) & (s < S) & (t >= 0) & (t < S))
-        k = q['k'][i]
-        tu = T32[k, q['fi_u'][i], s[i]]
-        tv = T32[k, q['fi_v'][i], t[i]]
-        a = _round16(tv.real / sk[k], bf16) + 1j * _round16(tv.imag / sk[k], bf16)
-        b = y[i].astype(np.complex64) * (tu * sk[k])
-        out[n] = np.sum(a * (_round16(b.real, bf16) + 1j * _round16(b.imag, bf16)))
-    return out
-
-
 @pytest.mark.parametrize("precision", ["fp16", "bf16"])
 def test_sampled_16bit_forms(setup, q_all, precision):
     # the precision form as the benchmark runs it: 16-bit gridding (per-tile
@@ -183,18 +150,12 @@ def test_sampled_16bit_forms(setup, q_all, precision):
     got_v = V[torch.as_tensor(idx, device="cuda")].cpu().numpy()
     q = _subset_bins(d, idx, plan.tile_size)
     e_deg = rel_rms(got_v, oracle.gridder.degrid_separable(q, Gn.astype(complex), T, N, S))
-    # The dense cells sum >10^4 footprints with partial cancellation, so the
-    # error of the 16-bit operands at the sampled cells exceeds the 3e-3 of the
-    # 64^2 accuracy workload for BF16: the rounding model alone gives about
-    # 1.2e-2 (BF16) and 5.6e-4 (FP16) there.  The kernels must stay within 25 %
-    # of the model (or 3e-3).
-    e_model = rel_rms(_cells_16bit_model(q_all, d["V"].astype(complex) * d["W"], T, N, S, cells,
-                                         precision == "bf16"), want)
-    print("%s at full size: sampled cells %.2e (rounding model %.2e), sampled visibilities %.2e"
-          % (precision, e_grid, e_model, e_deg))
+    print("%s at full size: sampled cells %.2e, sampled visibilities %.2e"
+          % (precision, e_grid, e_deg))
     plan.close()
     K.close()
-    assert e_grid <= max(3e-3, 1.25 * e_model) and e_deg <= 3e-3
+    # the 16-bit tolerance of the precision form (BF16 splits its operands hi/lo)
+    assert e_grid <= 3e-3 and e_deg <= 3e-3
 
 
 def test_full_size_adjoint_identity(setup):
