@@ -303,14 +303,14 @@ int sepw_wstack_degrid(sepw_wstack ws, const sepw_c64* image, sepw_c64* vis_out,
 
 /* Length of the plan's gridding work items: the number of tile slots
  * (visibilities, each tile padded to whole groups of 4) of one row of tiles
- * that one wave processes in order.  Default 1024; must be a multiple of 4 in
+ * that one wave processes in order.  Default 2048; must be a multiple of 4 in
  * [64, 8192].  Rebuilds the plan's gridding work list asynchronously on the
  * stream (it waits for the stream once when the list has to grow); later
  * rebins keep the length.  Used by sepw_grid and sepw_grid_batched.
  * Errors: SEPW_ERR_ARG (null p, invalid slots), SEPW_ERR_OOM, SEPW_ERR_HIP. */
 int sepw_plan_set_item_slots(sepw_plan p, int32_t slots, void* hip_stream);
 
-/* The same for the degridding work list (sepw_degrid).  Default 448: shorter
+/* The same for the degridding work list (sepw_degrid).  Default 224: shorter
  * items keep fewer rows of scattered results in flight per L2.  Same range,
  * behaviour and errors as sepw_plan_set_item_slots. */
 int sepw_plan_set_degrid_item_slots(sepw_plan p, int32_t slots, void* hip_stream);

@@ -458,7 +458,7 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
     SEPW_TRY(dalloc(&l->itoff, 8 * (int64_t)P->r8 + 1));
     SEPW_TRY(dalloc(&l->items, l->max_items));
   }
-  SEPW_TRY(dalloc(&P->qctr, 8));
+  SEPW_TRY(dalloc(&P->qctr, 8 * kCtrStride));
   SEPW_TRY(dalloc(&P->lp_max, 2));
   SEPW_TRY(dalloc(&P->scan_tmp, P->scan_tmp_len));
   if (K->facet) SEPW_TRY(dalloc(&P->rot, capacity));
@@ -876,7 +876,7 @@ struct NoAllocArea {
   MoveArgs mjobs[kNoAllocMaxJobs];     // movement jobs, caller order
   uint32_t first[kNoAllocMaxJobs + 1];   // prefix of work items per job
   uint32_t mfirst[kNoAllocMaxJobs + 1];  // first movement workgroup per job
-  uint32_t counter;                    // work counter of the persistent launch
+  alignas(256) uint32_t counter;       // work counter of the persistent launch (own cache line)
 };
 
 }  // namespace
@@ -1172,7 +1172,7 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
                  p->yrow, K->pad_u, K->pad_v,
                  K->tab_len, N, p->ntx, grid_only ? 0 : 1, img};
       if (K->lds_bytes > 0) {
-        SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8, s));
+        SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8 * kCtrStride, s));
         SEPW_TRY(launch_grid_fp32_lds(K->S, a, K->lds_bytes, K->n_cu, s));
       } else {
         SEPW_TRY(launch_grid_fp32(K->S, a, p->gl.max_items, s));
@@ -1180,7 +1180,7 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
     } else {
       GridArgsLp a{p->gl.items, p->gl.itoff + 8 * p->r8, p->tdesc, p->krec, p->yrow, K->pad_u,
                    K->pad_v, K->tab_len, p->lp_max, p->qctr, N, p->ntx, grid_only ? 0 : 1, img};
-      SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8, s));
+      SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8 * kCtrStride, s));
       SEPW_TRY(launch_grid_lp(K->S, K->prm.precision == SEPW_BF16, a, K->lds_bytes, K->n_cu, s));
     }
   }
@@ -1230,7 +1230,7 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
   float2* vo = reinterpret_cast<float2*>(vis_out);
   {
     Stage st(SEPW_STAGE_DEGRID, s);
-    SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8, s));
+    SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8 * kCtrStride, s));
     if (K->prm.precision == SEPW_FP32) {
       DegridArgs a{p->dl.items, p->dl.itoff + 8 * p->r8, p->dl.itoff, p->r8, p->qctr, p->tdesc, p->krec,
                    src, checker ? K->pad_su : K->pad_u, checker ? K->pad_sv : K->pad_v,
@@ -1238,12 +1238,18 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
       SEPW_TRY(launch_degrid_fp32(K->S, a, p->dl.max_items, K->lds_bytes, K->n_cu, s));
     } else {
       const bool bf16 = K->prm.precision == SEPW_BF16;
+      // the 16-bit degridding kernel addresses records and results through
+      // 32-bit buffer offsets
+      if (p->pcap * (int64_t)sizeof(SlotRec) > 0x7FFFFFFFLL ||
+          (p->capacity + 1) * (int64_t)sizeof(float2) > 0x7FFFFFFFLL)
+        return SEPW_ERR_UNSUPPORTED;
       if (!bf16) {
         SEPW_TRY(launch_fill_u32(p->lp_max + 1, 0u, 1, s));
         SEPW_TRY(launch_absmax(src, (int64_t)N * N, p->lp_max + 1, s));
       }
       DegridArgsLp a{p->dl.items, p->dl.itoff, p->r8, p->qctr, p->tdesc, p->krec, src, K->lp_u,
-                     K->lp_v, K->tab_len, p->lp_max + 1, N, p->ntx, checker, p->yrow};
+                     K->lp_v, K->tab_len, p->lp_max + 1, N, p->ntx, checker, p->yrow,
+                     p->pcap, p->capacity + 1};
       SEPW_TRY(launch_degrid_lp(K->S, bf16, a, K->lds_bytes_lp, K->n_cu, s));
     }
   }

@@ -258,12 +258,7 @@ __global__ __launch_bounds__(LDS ? 1024 : 256) void degrid_fp32_batched_kernel(
     tu_tab = smem;
   }
   const int lane = threadIdx.x & 63;
-  const uint32_t total = first[njobs];
-  while (true) {
-    uint32_t gi = 0;
-    if (lane == 0) gi = atomicAdd(counter, 1u);
-    gi = (uint32_t)uniform((int)__shfl(gi, 0, 64));
-    if (gi >= total) break;
+  for_counter(counter, first[njobs], lane, [&](uint32_t gi) {
     int lo = 0, hi = njobs - 1;   // last job with first[job] <= gi
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -271,7 +266,7 @@ __global__ __launch_bounds__(LDS ? 1024 : 256) void degrid_fp32_batched_kernel(
     }
     const int job = uniform(lo);
     degrid_item<S>(jobs[job], tu_tab, tv_tab, (int)(gi - first[job]), lane, lane & 15, lane >> 4);
-  }
+  });
 }
 
 template <int S>

@@ -261,12 +261,7 @@ __global__ __launch_bounds__(64 * kWaves) void grid_fp32_batched_kernel(
   const int lane = threadIdx.x & 63;
   float* ring = rings + (threadIdx.x >> 6) * kRingFloats;
   for (int i = lane; i < kRingFloats; i += 64) ring[i] = 0.f;
-  const uint32_t total = first[njobs];
-  while (true) {
-    uint32_t gi = 0;
-    if (lane == 0) gi = atomicAdd(counter, 1u);
-    gi = (uint32_t)uniform((int)__shfl(gi, 0, 64));
-    if (gi >= total) break;
+  for_counter(counter, first[njobs], lane, [&](uint32_t gi) {
     int lo = 0, hi = njobs - 1;   // last job with first[job] <= gi
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -274,7 +269,7 @@ __global__ __launch_bounds__(64 * kWaves) void grid_fp32_batched_kernel(
     }
     const int job = uniform(lo);
     grid_item<S>(jobs[job], ring, (int)(gi - first[job]), lane, lane & 15, lane >> 4);
-  }
+  });
 }
 
 // ------------------------------------------------ tables in LDS, ring in registers
@@ -513,14 +508,8 @@ __global__ __launch_bounds__(64 * kLdsWaves) void grid_fp32_lds_kernel(GridArgs 
   const char* tu = reinterpret_cast<const char*>(smem);
   const char* tv = reinterpret_cast<const char*>(two ? smem + n : smem);
   const int lane = threadIdx.x & 63;
-  const int n_items = uniform((int)*a.nitems);
-  while (true) {
-    int it = 0;
-    if (lane == 0) it = (int)atomicAdd(a.qctr, 1u);
-    it = uniform(__shfl(it, 0, 64));
-    if (it >= n_items) break;
-    grid_item_lds<S>(a, tu, tv, it, lane);
-  }
+  for_counter(a.qctr, (uint32_t)uniform((int)*a.nitems), lane,
+              [&](uint32_t it) { grid_item_lds<S>(a, tu, tv, (int)it, lane); });
 }
 
 template <int S>

@@ -208,9 +208,9 @@ struct GKeys {
   float2 y[4];
 };
 
-// Taps and W V of one chunk, with its position.
+// Taps of one chunk, with its position (its W V stays in the keys it came with).
 struct GOps {
-  float2 tu[4], tv[4], y[4];
+  float2 tu[4], tv[4];
   int x0;
   bool first;
 };
@@ -225,21 +225,31 @@ struct GCtx {
   float ys;         // FP16: scale of W V
 };
 
+// W V times the FP16 scale (applied when a batch moves up, a batch after its
+// load was issued)
+template <bool BF16>
+__device__ __forceinline__ float2 yscaled(const GCtx& c, float2 y) {
+  if constexpr (BF16) return y;
+  return make_float2(y.x * c.ys, y.y * c.ys);
+}
+
+template <bool BF16>
 __device__ __forceinline__ void gbatch_next(const GCtx& c, GBatch& bt) {
   bt.ra = bt.rb;
   bt.rb = bt.rc;
   bt.rc = bt.rd;
   bt.ya = bt.yb;
-  bt.yb = bt.yc;
+  bt.yb = yscaled<BF16>(c, bt.yc);
   bt.yc = c.yrow[rec_pos(bt.rc)];
   bt.a += 1;
   bt.rd = load_rec(c.krec + min(c.s0 + 64 * (bt.a + 3) + c.lane, c.last));
 }
 
-// Move the records and W V of chunk k's slots c0 + 4 grp + m to this lane.
+// Move the records and W V (scaled) of chunk k's slots c0 + 4 grp + m to this lane.
+template <bool BF16>
 __device__ __forceinline__ void gkeys(const GCtx& c, const GChunk& k, GBatch& bt, GKeys& K) {
   const int r = k.c0 - c.s0;
-  while ((r >> 6) > bt.a) gbatch_next(c, bt);
+  while ((r >> 6) > bt.a) gbatch_next<BF16>(c, bt);
   const int off = r & 63;   // the chunk is window [off, off + 16) of batches a, a + 1
   int sx = bt.ra.x, sy = bt.ra.y;
   float yr = bt.ya.x, yi = bt.ya.y;
@@ -266,12 +276,12 @@ __device__ __forceinline__ void gkeys(const GCtx& c, const GChunk& k, GBatch& bt
 }
 
 __device__ __forceinline__ void gtaps(const GCtx& c, const GKeys& K, const GChunk& k, GOps& X) {
-  const int rc8 = ((c.col - k.x0) & 15) << 3;   // lane's region column in this tile
+  const char* tu = c.tu + (((c.col - k.x0) & 15) << 3);   // lane's region column in this tile
+  const char* tv = c.tv + c.col8;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    X.tu[m] = *reinterpret_cast<const float2*>(c.tu + (K.kx[m] << 3) + rc8);
-    X.tv[m] = *reinterpret_cast<const float2*>(c.tv + (K.ky[m] << 3) + c.col8);
-    X.y[m] = K.y[m];
+    X.tu[m] = *reinterpret_cast<const float2*>(tu + (K.kx[m] << 3));
+    X.tv[m] = *reinterpret_cast<const float2*>(tv + (K.ky[m] << 3));
   }
   X.x0 = k.x0;
   X.first = k.first;
@@ -302,32 +312,29 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, const GCtx& c0
   bt.rb = load_rec(c.krec + min(c.s0 + 64 + c.lane, c.last));
   bt.rc = load_rec(c.krec + min(c.s0 + 128 + c.lane, c.last));
   bt.rd = load_rec(c.krec + min(c.s0 + 192 + c.lane, c.last));
-  bt.ya = c.yrow[rec_pos(bt.ra)];
-  bt.yb = c.yrow[rec_pos(bt.rb)];
+  bt.ya = yscaled<BF16>(c, c.yrow[rec_pos(bt.ra)]);
+  bt.yb = yscaled<BF16>(c, c.yrow[rec_pos(bt.rb)]);
   bt.yc = c.yrow[rec_pos(bt.rc)];
 
   RegRing rg;
-  f32x4 acc_re = {0.f, 0.f, 0.f, 0.f}, acc_ni = acc_re;   // acc_ni: minus the imaginary sums
-  rg.lo_re = acc_re;
-  rg.lo_im = acc_re;
-  rg.hi_re = acc_re;
-  rg.hi_im = acc_re;
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  f32x4 acc_re = zero, acc_ni = zero;   // acc_ni: minus the imaginary sums
+  rg.lo_re = zero;
+  rg.lo_im = zero;
+  rg.hi_re = zero;
+  rg.hi_im = zero;
   rg.blk = f.x0 >> 4;
   int x0 = f.x0;
   const float back = 1.f / c.ys;   // exact: c.ys is a power of two
 
-  // chunk in X: operands, then the two products (a new tile first banks the
-  // finished region and makes the ring hold the new one)
-  auto process = [&](const GOps& X) {
+  // chunk in X (W V in K): operands, then the two products; a new tile first
+  // banks the finished region and makes the ring hold the new one
+  auto process = [&](const GOps& X, const GKeys& K) {
     Opnd A, Bre, Bni;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       set_one<BF16>(A, m, X.tv[m].x, X.tv[m].y);
-      float yx = X.y[m].x, yy = X.y[m].y;
-      if constexpr (!BF16) {
-        yx *= c.ys;
-        yy *= c.ys;
-      }
+      const float yx = K.y[m].x, yy = K.y[m].y;
       const float br = yx * X.tu[m].x - yy * X.tu[m].y;   // row product y Tu
       const float bi = yx * X.tu[m].y + yy * X.tu[m].x;
       set_pair<BF16>(Bre, Bni, m, br, -bi);   // (br, -bi) and (-bi, -br)
@@ -339,28 +346,31 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, const GCtx& c0
       reg_ring_add(rg, acc_re, im, x0, c.col);
       x0 = X.x0;
       reg_ring_advance(rg, x0, c.grid, c.N, c.checker, c.y0, c.col, c.grp, back);
-      const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-      acc_re = mma<BF16>(A, Bre, z);
-      acc_ni = mma<BF16>(A, Bni, z);
-    } else {
-      acc_re = mma<BF16>(A, Bre, acc_re);
-      acc_ni = mma<BF16>(A, Bni, acc_ni);
+      acc_re = zero;
+      acc_ni = zero;
     }
+    acc_re = mma<BF16>(A, Bre, acc_re);
+    acc_ni = mma<BF16>(A, Bni, acc_ni);
   };
 
-  // X holds chunk n (taps read), K the records of chunk n + 1 (= f)
-  GKeys K;
-  GOps X;
-  gkeys(c, f, bt, K);
-  gtaps(c, K, f, X);
-  f = next_gchunk<S>(f, fw, s_end, c.lane);
-  if (f.ok) gkeys(c, f, bt, K);
-  while (true) {
-    process(X);
-    if (!f.ok) break;
-    gtaps(c, K, f, X);
+  // Ping-pong: X holds chunk n (its W V in Kx), Kn the records of chunk
+  // n + 1 (= f).  A half-step runs chunk n, reads the taps of n + 1 into Xn
+  // and moves the records of n + 2 into Kx (free once chunk n has run).
+  auto half = [&](const GOps& X, GKeys& Kx, GOps& Xn, const GKeys& Kn) -> bool {
+    process(X, Kx);
+    if (!f.ok) return false;
+    gtaps(c, Kn, f, Xn);
     f = next_gchunk<S>(f, fw, s_end, c.lane);
-    if (f.ok) gkeys(c, f, bt, K);
+    if (f.ok) gkeys<BF16>(c, f, bt, Kx);
+    return true;
+  };
+  GKeys KA, KB;
+  GOps XA, XB;
+  gkeys<BF16>(c, f, bt, KA);
+  gtaps(c, KA, f, XA);
+  f = next_gchunk<S>(f, fw, s_end, c.lane);
+  if (f.ok) gkeys<BF16>(c, f, bt, KB);
+  while (half(XA, KA, XB, KB) && half(XB, KB, XA, KA)) {
   }
   f32x4 im;
 #pragma unroll
@@ -399,42 +409,88 @@ __global__ __launch_bounds__(64 * (LDS ? kLdsWaves : kWaves)) void grid_lp_kerne
   c.grp = lane >> 4;
   c.col8 = c.col << 3;
   c.ys = BF16 ? 1.f : ldexpf(1.f, 13 - exp_above(*a.vmax));
-  const int n_items = uniform((int)*a.nitems);
-  while (true) {
-    int it = 0;
-    if (lane == 0) it = (int)atomicAdd(a.qctr, 1u);
-    it = uniform(__shfl(it, 0, 64));
-    if (it >= n_items) break;
-    grid_lp_item<S, BF16>(a, c, it);
-  }
+  for_counter(a.qctr, (uint32_t)uniform((int)*a.nitems), lane,
+              [&](uint32_t it) { grid_lp_item<S, BF16>(a, c, (int)it); });
 }
 
 // ---------------------------------------------------------------- degridding
 
-// One chunk's operands: the record of slot c0 + col (loaded two chunks
-// ahead), the 16-bit taps 4 grp + m of that visibility (u for stage 1, v for
-// stage 2; BF16 high and low parts), and on a tile change the raw region
-// values R[y0 + col][x0 + 4 grp + m].
+// Degridding pipeline.  The kernel is bound by the texture-address unit,
+// which takes about 40 cycles per 64-lane vector-memory instruction whatever
+// its width (measured with the TA counters), so the pipeline keeps those
+// instructions few: slot records arrive 64 at a time in one coalesced 12-byte
+// load per lane and ds_bpermute hands each lane its chunk's record; a tile's
+// region takes two 16-byte loads per lane; and the results of four chunks are
+// moved by ds_bpermute into one 64-lane store.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+constexpr uint32_t kOob = 0x80000000u;   // byte offset past every buffer resource used here
+
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0,
+                                           (int)(bytes < 0x7FFFFFFF ? bytes : 0x7FFFFFFF),
+                                           0x00020000);
+}
+
+// One chunk's operands: the record (u base, v base, row-bin position) of slot
+// c0 + col and the 16-bit taps 4 grp + m of that visibility (u for stage 1,
+// v for stage 2; BF16 high and low parts).
 struct DOps {
-  SlotRec k;
+  u32x3 rec;
   u32x4 tu_h, tu_l, tv_h, tv_l;
-  float2 reg[4];
-  bool fresh;
 };
 
 struct DCtx {
+  __amdgpu_buffer_rsrc_t krs;   // tile slot records
+  __amdgpu_buffer_rsrc_t yrs;   // results (row-bin order)
   const uint32_t* tu;   // 16-bit padded tables (LDS or memory); BF16 low parts at + tab_len
   const uint32_t* tv;
   int tab_len;
-  int s_end, y0, gy, col, grp, lane;
+  int col, grp, lane;
+  int s0, last;
   float gs;             // FP16: scale of the region
   float back;           // 1 / gs
 };
 
+// Records of the item's slots, one slot per lane, in batches of 64 from the
+// item's first slot: batches a, a + 1 (arrived) and a + 2 (in flight).
+struct DBatch {
+  u32x3 ra, rb, rc;
+  int a;
+};
+
+__device__ __forceinline__ u32x3 batch_load(const DCtx& c, int j) {
+  return __builtin_amdgcn_raw_buffer_load_b96(c.krs, min(c.s0 + 64 * j + c.lane, c.last) * 12, 0, 0);
+}
+
+// Record of slot c0 + col of chunk k, moved from the batches by ds_bpermute.
+__device__ __forceinline__ u32x3 dkey(const DCtx& c, const ChunkPos& k, DBatch& bt) {
+  const int r = k.c0 - c.s0;
+  while ((r >> 6) > bt.a) {
+    bt.ra = bt.rb;
+    bt.rb = bt.rc;
+    bt.a += 1;
+    bt.rc = batch_load(c, bt.a + 2);
+  }
+  const int off = r & 63;   // the chunk is window [off, off + 16) of batches a, a + 1
+  u32x3 src = bt.ra;
+  if (off > 48) {
+    // the chunk reaches into batch a + 1: lanes below off hold its slots
+    const bool nb = c.lane < off;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) src[i] = nb ? bt.rb[i] : src[i];
+  }
+  const int addr = ((off + c.col) & 63) << 2;
+  u32x3 k3;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) k3[i] = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)src[i]);
+  return k3;
+}
+
 template <bool BF16>
 __device__ __forceinline__ void dtaps(const DCtx& c, DOps& B) {
-  const uint32_t* pu = c.tu + B.k.x + 4 * c.grp;
-  const uint32_t* pv = c.tv + B.k.y + 4 * c.grp;
+  const uint32_t* pu = c.tu + B.rec[0] + 4 * c.grp;
+  const uint32_t* pv = c.tv + B.rec[1] + 4 * c.grp;
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     B.tu_h[m] = pu[m];
@@ -446,22 +502,12 @@ __device__ __forceinline__ void dtaps(const DCtx& c, DOps& B) {
   }
 }
 
-// Region values of the tile at column tx for this lane's row (clamped, always
-// valid addresses; rows and columns outside the grid get factor 0 when the
-// region is converted).
-template <int S>
-__device__ inline void dregion(const float2* __restrict__ grid, int N, int tx, int gy, int grp,
-                               float2 (&r)[4]) {
-  constexpr int C = kRegion + 1 - S;
-  constexpr int H = S / 2;
-  const int64_t row = (int64_t)min(max(gy, 0), N - 1) * N;
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int gx = tx * C - H + 4 * grp + m;
-    r[m] = grid[row + min(max(gx, 0), N - 1)];
-  }
-}
-
+// Pipeline of a work item: chunk n runs while the taps of n + 1 are read
+// (its record moved one step earlier) and the record of n + 2 is moved from
+// the batches.  The region of a tile is loaded when its first chunk becomes
+// n + 2, into a two-entry queue, and converted to MFMA operands when that
+// chunk becomes n (after the step, before the next load is queued, so the
+// queue holds at most the tiles of n + 1 and n + 2).
 template <int S, bool BF16>
 __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, const DCtx& c0, int it) {
   constexpr int C = kRegion + 1 - S;
@@ -470,45 +516,114 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, const DCtx
   const int N = a.N;
   const int4 item = a.items[it];
   const int ty = uniform(item.x), s_end = uniform(item.z);
-  c.s_end = s_end;
-  c.y0 = ty * C - H;
-  c.gy = c.y0 + c.col;
-  const bool row_ok = c.gy >= 0 && c.gy < N;
+  c.s0 = uniform(item.y);
+  c.last = s_end - 1;
+  // the item's 16 grid rows as one buffer resource
+  const int y0 = ty * C - H;
+  const int rb0 = max(y0, 0);
+  const int nrows = min(y0 + 16, N) - rb0;
+  const __amdgpu_buffer_rsrc_t grs =
+      rsrc(a.grid + (int64_t)rb0 * N, (int64_t)nrows * N * (int64_t)sizeof(float2));
+  const int gy = y0 + c.col;
+  const bool row_ok = gy >= 0 && gy < N;
+  const int rowbase = (min(max(gy, rb0), rb0 + nrows - 1) - rb0) * N;   // clamped row
   const int sel = c.col & 3;                 // register of the lane's diagonal element
   const bool diag = c.grp == (c.col >> 2);   // the lane that holds W[col][col]
+  // lane holding V[col] of a chunk, for gathering four chunks' results
+  const int vsrc = (c.col + 16 * (c.col >> 2)) << 2;
   TileWalk tw;
   tw.start(a.tdesc + (int64_t)ty * a.ntx, a.ntx, uniform(item.w), c.lane);
   ChunkPos cur;
-  cur.c0 = uniform(item.y);
+  cur.c0 = c.s0;
   cur.pe = min(tw.padded_end(), s_end);
   cur.re = min(tw.real_end(), s_end);
   cur.tx = tw.tx;
   cur.ok = true;
   ChunkPos n1 = next_chunk(cur, tw, s_end, c.lane);
   ChunkPos n2 = next_chunk(n1, tw, s_end, c.lane);
-  Opnd ra, rb;   // region operands of the current tile: (Re R, Im R) and (Im R, -Re R)
 
-  // One pipeline step: chunk cur from X while the record of n2 goes into X.k
-  // and the taps (and on a tile change the region) of n1 into Y.
-  auto step = [&](DOps& X, DOps& Y) -> bool {
-    const SlotRec kc = X.k;
-    X.k = load_rec(a.krec + min(n2.c0 + c.col, n2.pe - 1));
-    dtaps<BF16>(c, Y);
-    if (X.fresh) {
-      // region operands: R (-1)^(x+y) times the scale, 0 outside the grid
-      const int gx0 = cur.tx * C - H + 4 * c.grp;
-      float f = BF16 ? 1.f : c.gs;
-      if (a.checker && ((gx0 + c.gy) & 1)) f = -f;
+  DBatch bt;
+  bt.a = 0;
+  bt.ra = batch_load(c, 0);
+  bt.rb = batch_load(c, 1);
+  bt.rc = batch_load(c, 2);
+
+  // raw region values R[gy][x0 + 4 grp + m] of a tile: two 16-byte loads
+  // inside the grid, clamped single loads at its edges (values outside the
+  // grid get factor 0 when converted)
+  auto load_region = [&](float2 (&g)[4], int tx) {
+    const int gx0 = tx * C - H + 4 * c.grp;
+    if (tx * C - H >= 0 && tx * C - H + 16 <= N) {
+      const uint32_t off = (uint32_t)(rowbase + gx0) * 8u;
+      const u32x4 v0 = __builtin_amdgcn_raw_buffer_load_b128(grs, off, 0, 0);
+      const u32x4 v1 = __builtin_amdgcn_raw_buffer_load_b128(grs, off + 16u, 0, 0);
+      g[0] = make_float2(__uint_as_float(v0[0]), __uint_as_float(v0[1]));
+      g[1] = make_float2(__uint_as_float(v0[2]), __uint_as_float(v0[3]));
+      g[2] = make_float2(__uint_as_float(v1[0]), __uint_as_float(v1[1]));
+      g[3] = make_float2(__uint_as_float(v1[2]), __uint_as_float(v1[3]));
+    } else {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        const int gx = gx0 + m;
-        const float fm = (row_ok && gx >= 0 && gx < N) ? f : 0.f;
-        set_pair<BF16>(ra, rb, m, X.reg[m].x * fm, X.reg[m].y * fm);
-        if (a.checker) f = -f;
+        const uint32_t off = (uint32_t)(rowbase + min(max(gx0 + m, 0), N - 1)) * 8u;
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(grs, off, 0, 0);
+        g[m] = make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
       }
     }
-    Y.fresh = n1.ok && n1.tx != cur.tx;
-    if (Y.fresh) dregion<S>(a.grid, N, n1.tx, c.gy, c.grp, Y.reg);
+  };
+  // region operands of the current tile: (Re R, Im R) and (Im R, -Re R)
+  Opnd ra, rb;
+  auto convert = [&](const float2 (&g)[4], int tx) {
+    // R (-1)^(x+y) times the scale, 0 outside the grid
+    const int gx0 = tx * C - H + 4 * c.grp;
+    float f = BF16 ? 1.f : c.gs;
+    if (a.checker && ((gx0 + gy) & 1)) f = -f;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int gx = gx0 + m;
+      const float fm = (row_ok && gx >= 0 && gx < N) ? f : 0.f;
+      set_pair<BF16>(ra, rb, m, g[m].x * fm, g[m].y * fm);
+      if (a.checker) f = -f;
+    }
+  };
+  // queue of raw regions: q1 (oldest), q2; nq entries, with their tile columns
+  float2 q1[4], q2[4];
+  int t1 = 0, t2 = 0, nq = 0;
+  auto push = [&](int tx) {
+    if (nq == 0) {
+      load_region(q1, tx);
+      t1 = tx;
+    } else {
+      load_region(q2, tx);
+      t2 = tx;
+    }
+    nq += 1;
+  };
+  auto pop = [&]() {
+    convert(q1, t1);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) q1[m] = q2[m];
+    t1 = t2;
+    nq -= 1;
+  };
+
+  // results of up to four chunks: lanes 16 j + col hold V[col] of chunk j of
+  // the group, stored with one instruction (offset kOob: nothing to store)
+  u32x2 res;
+  res[0] = 0u;
+  res[1] = 0u;
+  uint32_t roff = kOob;
+  int rj = 0;
+  auto flush = [&]() {
+    __builtin_amdgcn_raw_buffer_store_b64(res, c.yrs, roff, 0, 0);
+    roff = kOob;
+    rj = 0;
+  };
+
+  auto step = [&](DOps& X, DOps& Y, u32x3& K) -> bool {
+    // taps of n1 (record moved last step), then the record of n2
+    Y.rec = K;
+    dtaps<BF16>(c, Y);
+    K = dkey(c, n2, bt);
     // stage 1: Z = R conj(Tu)^T
     Opnd bu;
     bu.h = X.tu_h;
@@ -530,23 +645,41 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, const DCtx
       vr *= c.back;
       vi *= c.back;
     }
-    if (diag && cur.c0 + c.col < cur.re) a.yrow[rec_pos(kc)] = make_float2(vr, vi);
+    (void)diag;
+    // gather V[col] into lanes 16 rj + col
+    const uint32_t gr = (uint32_t)__builtin_amdgcn_ds_bpermute(vsrc, (int)__float_as_uint(vr));
+    const uint32_t gi = (uint32_t)__builtin_amdgcn_ds_bpermute(vsrc, (int)__float_as_uint(vi));
+    if (c.grp == rj) {
+      res[0] = gr;
+      res[1] = gi;
+      roff = cur.c0 + c.col < cur.re ? (X.rec[2] & 0x7FFFFFFFu) * 8u : kOob;
+    }
+    if (++rj == 4) flush();
     if (!n1.ok) return false;
+    const bool fresh = n1.tx != cur.tx;
     cur = n1;
     n1 = n2;
     n2 = next_chunk(n2, tw, s_end, c.lane);
+    if (fresh) pop();
+    if (n2.ok && n2.tx != n1.tx) push(n2.tx);
     return true;
   };
 
-  DOps A, B;
-  A.k = load_rec(a.krec + min(cur.c0 + c.col, cur.pe - 1));
-  dtaps<BF16>(c, A);
-  dregion<S>(a.grid, N, cur.tx, c.gy, c.grp, A.reg);
-  A.fresh = true;
-  B.k = load_rec(a.krec + min(n1.c0 + c.col, n1.pe - 1));
-  B.fresh = false;
-  while (step(A, B) && step(B, A)) {
+  // the first tile's region is converted at once; later ones come through the queue
+  {
+    float2 g[4];
+    load_region(g, cur.tx);
+    if (n1.ok && n1.tx != cur.tx) push(n1.tx);
+    if (n2.ok && n2.tx != n1.tx) push(n2.tx);
+    convert(g, cur.tx);
   }
+  DOps A, B;
+  A.rec = dkey(c, cur, bt);
+  dtaps<BF16>(c, A);
+  u32x3 K = dkey(c, n1, bt);
+  while (step(A, B, K) && step(B, A, K)) {
+  }
+  if (rj > 0) flush();
 }
 
 template <int S, bool BF16, bool LDS>
@@ -555,6 +688,8 @@ __global__ __launch_bounds__(64 * (LDS ? kLdsWaves : kWaves)) void degrid_lp_ker
   const int lane = threadIdx.x & 63;
   const int nt = BF16 ? 2 * a.tab_len : a.tab_len;   // dwords of one table (both parts)
   DCtx c;
+  c.krs = rsrc(a.krec, a.nslots * (int64_t)sizeof(SlotRec));
+  c.yrs = rsrc(a.yrow, a.ycap * (int64_t)sizeof(float2));
   c.tu = a.lp_u;
   c.tv = a.lp_v;
   if constexpr (LDS) {

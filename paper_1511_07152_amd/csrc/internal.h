@@ -13,8 +13,8 @@ namespace sepw {
 constexpr uint32_t kDropped = 0xFFFFFFFFu;
 constexpr int kRegion = 16;        // MFMA tile region edge (cells): core + S - 1
 constexpr int kMaxSupport = 15;    // S <= kRegion - 1
-constexpr int kItemMaxVis = 1024;  // default slots per gridding work item (a slice of a tile row)
-constexpr int kDegridItemSlots = 448;  // default slots per degridding work item
+constexpr int kItemMaxVis = 2048;  // default slots per gridding work item (a slice of a tile row)
+constexpr int kDegridItemSlots = 224;  // default slots per degridding work item
 constexpr int kItemMinSlots = 64;  // range of the tunable item length
 constexpr int kItemMaxSlots = 8192;
 constexpr int kMaxRowBins = 4096;  // level-1 sort bins (rows of tiles, possibly grouped)
@@ -30,6 +30,7 @@ static_assert(((uint64_t)kMaxRowBins << kPlaceShift) < 0xFFFFFFFFull,
               "placement words must stay below kDropped");
 constexpr int kTargetRowBins = 2048;
 constexpr int kCorrMaxD = 64;      // correction table: max tap offset |d| (1/O_c cells) + 1
+constexpr int kCtrStride = 64;     // dwords between the 8 work-list counters (own cache lines)
 
 // Padded tables: row length L = 32 - S holds the S taps of a table row at
 // offsets c - 1 .. c - 2 + S (c = 17 - S is the tile size) and zeros around
@@ -139,7 +140,7 @@ struct Plan {
   uint2* tdesc = nullptr;       // [ntiles] (first slot, first slot + count) per tile
   float2* rot = nullptr;        // [nvis] facet phase rotation, caller order
   int r8 = 0;                   // rows of tiles per work list: ceil(nty / 8)
-  uint32_t* qctr = nullptr;     // [8] work-list counters of a launch
+  uint32_t* qctr = nullptr;     // [8 kCtrStride] work-list counters of a launch, kCtrStride apart
   uint32_t* lp_max = nullptr;   // [2] FP16 scales of the current call: max |Re, Im| of W V
                                 // (gridding) and of the grid (degridding), as float bits
   WorkList gl;                  // gridding work items
@@ -366,6 +367,8 @@ struct DegridArgsLp {
   int N, ntx;
   int checker;              // the grid comes from the centred FFT: region times (-1)^(x+y)
   float2* yrow;
+  int64_t nslots;           // tile slots of krec
+  int64_t ycap;             // entries of yrow
 };
 
 hipError_t launch_grid_fp32(int S, const GridArgs& a, int64_t max_items, hipStream_t s);
