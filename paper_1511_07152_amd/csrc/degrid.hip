@@ -100,9 +100,24 @@ struct DegridCtx {
   const DegridArgs* a;
   const float2* tu_tab;
   const float2* tv_tab;
-  int s_end, y0, gy, col, grp, lane;
+  int s_end, s0, last, y0, gy, col, grp, lane;
   uint32_t smask;   // kRecSign when the result takes the record's sign (-1)^(cu+cv)
 };
+
+// Results of up to four chunks: lane (col, grp) holds V[col] of chunk grp of
+// the group (every lane of a column has it after the cross-group sum), so the
+// group goes out with one store instruction.
+struct ResGroup {
+  float2 v;
+  int pos;    // row-bin position, -1: nothing to store
+  int j;      // chunks in the group
+};
+
+__device__ __forceinline__ void res_flush(const DegridArgs& a, ResGroup& g) {
+  if (g.pos >= 0) a.yrow[g.pos] = g.v;
+  g.pos = -1;
+  g.j = 0;
+}
 
 __device__ __forceinline__ void fetch_taps(const DegridCtx& c, ChunkBuf& B) {
 #pragma unroll
@@ -118,12 +133,12 @@ __device__ __forceinline__ void fetch_taps(const DegridCtx& c, ChunkBuf& B) {
 // region) of chunk n1 (record Y.k, loaded one step earlier) into Y.  Buffers
 // alternate between steps.  Returns false after the item's last chunk.
 template <int S>
-__device__ __forceinline__ bool degrid_step(const DegridCtx& c, TileWalk& tw, ChunkPos& cur,
-                                            ChunkPos& n1, ChunkPos& n2, ChunkBuf& X,
-                                            ChunkBuf& Y) {
+__device__ __forceinline__ bool degrid_step(const DegridCtx& c, TileWalk& tw, RecBatch& bt,
+                                            ResGroup& rg, ChunkPos& cur, ChunkPos& n1,
+                                            ChunkPos& n2, ChunkBuf& X, ChunkBuf& Y) {
   const DegridArgs& a = *c.a;
   const SlotRec kx = X.k;   // this chunk's record (row-bin position of the result)
-  X.k = load_rec(a.krec + min(n2.c0 + c.col, n2.pe - 1));
+  X.k = rec_key(bt, a.krec, c.s0, c.last, n2.c0, c.col, c.lane);
   fetch_taps(c, Y);
   if (X.fresh && X.edge) region_zero<S>(cur.tx, c.gy, c.grp, a.N, X.reg);
   Y.fresh = n1.ok && n1.tx != cur.tx;
@@ -158,11 +173,13 @@ __device__ __forceinline__ bool degrid_step(const DegridCtx& c, TileWalk& tw, Ch
   v_im += __shfl_xor(v_im, 16, 64);
   v_re += __shfl_xor(v_re, 32, 64);
   v_im += __shfl_xor(v_im, 32, 64);
-  if (c.grp == 0 && cur.c0 + c.col < cur.re) {
+  if (c.grp == rg.j) {
     const uint32_t sg = (uint32_t)kx.z & c.smask;
-    a.yrow[rec_pos(kx)] = make_float2(__uint_as_float(__float_as_uint(v_re) ^ sg),
-                                      __uint_as_float(__float_as_uint(v_im) ^ sg));
+    rg.v = make_float2(__uint_as_float(__float_as_uint(v_re) ^ sg),
+                       __uint_as_float(__float_as_uint(v_im) ^ sg));
+    rg.pos = cur.c0 + c.col < cur.re ? rec_pos(kx) : -1;
   }
+  if (++rg.j == 4) res_flush(a, rg);
 
   if (!n1.ok) return false;
   cur = n1;
@@ -184,6 +201,8 @@ __device__ __forceinline__ void degrid_item(const DegridArgs& a, const float2* t
   c.tu_tab = tu_tab;
   c.tv_tab = tv_tab;
   c.s_end = s_end;
+  c.s0 = uniform(item.y);
+  c.last = s_end - 1;
   c.y0 = ty * C - H;                // first grid row of the item's regions
   c.gy = c.y0 + col;                // grid row of this lane's A operand
   c.smask = a.checker ? kRecSign : 0u;
@@ -202,15 +221,23 @@ __device__ __forceinline__ void degrid_item(const DegridArgs& a, const float2* t
   ChunkPos n2 = next_chunk(n1, tw, s_end, lane);
 
   // prologue: chunk cur complete in A, record of chunk n1 in B
+  RecBatch bt;
+  rec_batch_start(bt, a.krec, c.s0, c.last, lane);
+  ResGroup rg;
+  rg.v = make_float2(0.f, 0.f);
+  rg.pos = -1;
+  rg.j = 0;
   ChunkBuf A, B;
-  A.k = load_rec(a.krec + min(cur.c0 + col, cur.pe - 1));
-  fetch_taps(c, A);
   A.edge = edge_region<S>(cur.tx, c.y0, a.N);
   load_region<S>(a.grid, a.N, cur.tx, c.gy, grp, A.edge, A.reg);
+  A.k = rec_key(bt, a.krec, c.s0, c.last, cur.c0, col, lane);
+  fetch_taps(c, A);
   A.fresh = true;
-  B.k = load_rec(a.krec + min(n1.c0 + col, n1.pe - 1));
-  while (degrid_step<S>(c, tw, cur, n1, n2, A, B) && degrid_step<S>(c, tw, cur, n1, n2, B, A)) {
+  B.k = rec_key(bt, a.krec, c.s0, c.last, n1.c0, col, lane);
+  while (degrid_step<S>(c, tw, bt, rg, cur, n1, n2, A, B) &&
+         degrid_step<S>(c, tw, bt, rg, cur, n1, n2, B, A)) {
   }
+  if (rg.j > 0) res_flush(a, rg);
 }
 
 // Tables staged in LDS (LDS = true, the workgroup owns a CU with 16 waves) or

@@ -137,6 +137,58 @@ __device__ inline void for_items(const uint32_t* __restrict__ lists, int r8,
   }
 }
 
+// Slot records of a work item, one slot per lane, in batches of 64 from the
+// item's first slot s0: batches a and a + 1 have arrived, a + 2 is in flight.
+// A batch is one coalesced 12-byte load per lane (one vector-memory
+// instruction for 64 records, instead of one per chunk; the texture-address
+// unit, which spends about the same time on any 64-lane instruction, bounds
+// the degridding kernels).  rec_key() hands each lane the record of slot
+// c0 + col of a chunk [c0, c0 + 16) with ds_bpermute.
+typedef int i32x3u __attribute__((ext_vector_type(3), aligned(4)));
+
+struct RecBatch {
+  SlotRec ra, rb, rc;
+  int a;
+};
+
+__device__ inline SlotRec rec_batch_load(const SlotRec* krec, int s0, int last, int j, int lane) {
+  const i32x3u v = __builtin_nontemporal_load(
+      reinterpret_cast<const i32x3u*>(krec + min(s0 + 64 * j + lane, last)));
+  return SlotRec{v[0], v[1], v[2]};
+}
+
+__device__ inline void rec_batch_start(RecBatch& bt, const SlotRec* krec, int s0, int last,
+                                       int lane) {
+  bt.a = 0;
+  bt.ra = rec_batch_load(krec, s0, last, 0, lane);
+  bt.rb = rec_batch_load(krec, s0, last, 1, lane);
+  bt.rc = rec_batch_load(krec, s0, last, 2, lane);
+}
+
+// Record of slot c0 + col (c0 >= s0, non-decreasing from call to call).
+__device__ inline SlotRec rec_key(RecBatch& bt, const SlotRec* krec, int s0, int last, int c0,
+                                  int col, int lane) {
+  const int r = c0 - s0;
+  while ((r >> 6) > bt.a) {
+    bt.ra = bt.rb;
+    bt.rb = bt.rc;
+    bt.a += 1;
+    bt.rc = rec_batch_load(krec, s0, last, bt.a + 2, lane);
+  }
+  const int off = r & 63;   // the chunk is window [off, off + 16) of batches a, a + 1
+  SlotRec src = bt.ra;
+  if (off > 48) {
+    // the chunk reaches into batch a + 1: lanes below off hold its slots
+    const bool nb = lane < off;
+    src.x = nb ? bt.rb.x : src.x;
+    src.y = nb ? bt.rb.y : src.y;
+    src.z = nb ? bt.rb.z : src.z;
+  }
+  const int addr = ((off + col) & 63) << 2;
+  return SlotRec{__builtin_amdgcn_ds_bpermute(addr, src.x), __builtin_amdgcn_ds_bpermute(addr, src.y),
+                 __builtin_amdgcn_ds_bpermute(addr, src.z)};
+}
+
 // Position of one chunk of at most 16 slots inside one tile of a work item.
 struct ChunkPos {
   int c0;    // first slot
