@@ -31,7 +31,11 @@
  *
  * Conventions (the paper leaves these open; the library fixes them):
  *   N     grid and image size, even.           fov  full image width in
- *   S     GCF support in cells, odd, 1..15.         direction cosines [rad].
+ *   S     GCF support in cells, odd, 1..31 and       direction cosines [rad].
+ *         at most N - 1.  Up to 15 the footprints are gridded as tiles on the
+ *         matrix cores (all precisions); 17..31 take a per-visibility FP32 path
+ *         on the vector unit (FP16/BF16 and the correction table are
+ *         SEPW_ERR_UNSUPPORTED there).
  *   O     oversampling factor, power of two, 1..128.
  *   P     number of w-planes, 1..65535, uniform on [w_lo, w_hi]; plane k
  *         stands for w_k = w_lo + (k + 1/2)(w_hi - w_lo)/P; a visibility goes
@@ -79,7 +83,7 @@ enum {
   SEPW_ERR_NO_DEVICE = -2,    /* no HIP device visible                         */
   SEPW_ERR_HIP = -3,          /* a HIP runtime or kernel error                 */
   SEPW_ERR_OOM = -4,          /* device allocation failed                      */
-  SEPW_ERR_UNSUPPORTED = -5,  /* valid but not implemented (e.g. S > 15)       */
+  SEPW_ERR_UNSUPPORTED = -5,  /* valid but not implemented (e.g. S > 31)       */
   SEPW_ERR_FFT = -6           /* hipFFT failure                                */
 };
 
@@ -158,8 +162,8 @@ int sepw_kernels_taper(sepw_kernels k, double* out, void* hip_stream);
  * Errors: SEPW_ERR_ARG (null k; support even, negative or above S; oversample
  * not a power of two or above O; support above S - 2 when 1 < oversample < O,
  * where the coarse cell can be the next one), SEPW_ERR_UNSUPPORTED (facet
- * kernels; a taper not symmetric about the image centre; (Sc/2) Oc + Oc/2
- * above 63), SEPW_ERR_OOM, SEPW_ERR_HIP. */
+ * kernels; kernels with S above 15; a taper not symmetric about the image
+ * centre; (Sc/2) Oc + Oc/2 above 63), SEPW_ERR_OOM, SEPW_ERR_HIP. */
 int sepw_kernels_set_correction(sepw_kernels k, int32_t support, int32_t oversample,
                                 void* hip_stream);
 /* Copy the attached correction table into a device buffer of P*Oc*Oc*Sc*Sc

@@ -154,7 +154,9 @@ int validate_params(const sepw_kernel_params* p) {
         !std::isfinite(p->b_v))
       return SEPW_ERR_ARG;
   }
-  if (p->support > kMaxSupport) return SEPW_ERR_UNSUPPORTED;
+  // above the MFMA region only the FP32 per-visibility path exists
+  if (p->support > kMaxWideSupport) return SEPW_ERR_UNSUPPORTED;
+  if (wide_support(p->support) && p->precision != SEPW_FP32) return SEPW_ERR_UNSUPPORTED;
   return SEPW_OK;
 }
 
@@ -247,7 +249,9 @@ hipError_t make_separable_tables(Kernels* K, hipStream_t s) {
   if (e == hipSuccess && K->tab_v != K->tab_u)
     e = launch_tables(K->c1, K->N, K->fov, K->P, K->O, K->S, K->w_lo, K->w_hi, K->a_v, K->b_v,
                       K->tab_v, s);
-  // kernel-side layouts: zero-padded rows (and the precision form's 16-bit tables)
+  // kernel-side layouts of the tiled path: zero-padded rows (and the
+  // precision form's 16-bit tables); the per-visibility path reads the raw tables
+  if (wide_support(K->S)) return e;
   if (e == hipSuccess) e = launch_pad_table(K->tab_u, nullptr, K->P, K->O, K->S, K->pad_u, s);
   if (e == hipSuccess && K->pad_v != K->pad_u)
     e = launch_pad_table(K->tab_v, nullptr, K->P, K->O, K->S, K->pad_v, s);
@@ -411,7 +415,7 @@ int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K) {
 int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
   P->K = K;
   P->capacity = capacity;
-  P->tile_c = kRegion + 1 - K->S;
+  P->tile_c = (wide_support(K->S) ? kWideRegion : kRegion) + 1 - K->S;
   P->ntx = (K->N + P->tile_c - 1) / P->tile_c;
   P->nty = P->ntx;
   P->ntiles = (int64_t)P->ntx * P->nty;
@@ -465,6 +469,11 @@ int alloc_plan(Kernels* K, int64_t capacity, Plan* P) {
   return SEPW_OK;
 }
 
+WideArgs wide_args(const Plan* p, int checker) {
+  const Kernels* K = p->K;
+  return WideArgs{p->qrec, p->rbin, K->tab_u, K->tab_v, p->rot, p->nvis, K->N, K->S, K->O, checker};
+}
+
 MoveArgs move_args(const Plan* p, const sepw_c64* vis, const float* weight) {
   MoveArgs m;
   m.vis = reinterpret_cast<const float2*>(vis);
@@ -509,7 +518,7 @@ int set_list_slots(Plan* p, WorkList& l, int32_t slots, hipStream_t s) {
     l.max_items = need;
   }
   l.slots = slots;
-  SEPW_TRY(build_list(p, l, s));
+  if (!wide_support(p->K->S)) SEPW_TRY(build_list(p, l, s));   // no tiles on the per-visibility path
   return SEPW_OK;
 }
 
@@ -541,6 +550,11 @@ int bin_plan(Plan* P, int64_t nvis, const Coords& src, hipStream_t s) {
     SEPW_TRY(launch_scan(P->rowpad, P->prowoff, P->nbins + 1, P->scan_tmp, s));
     SEPW_TRY(launch_row_scatter(P->rbin, P->qrec, nvis, P->nbins, P->chist, P->delta, P->rrec,
                                 P->place, s));
+    if (wide_support(K->S)) {
+      // the per-visibility path reads the packed bins in caller order
+      if (K->facet) SEPW_TRY(launch_rotation(src, nvis, g, P->rot, s));
+      return SEPW_OK;
+    }
     // padding slots point at yrow[capacity], which nothing writes: keep it 0
     SEPW_TRY(launch_zero_c64(P->yrow + P->capacity, 1, s));
     SEPW_TRY(launch_row_sort(P->rowcount, P->rowoff, P->prowoff, P->rrec, P->rshift, P->nbins,
@@ -1024,7 +1038,8 @@ int sepw_kernels_set_correction(sepw_kernels k, int32_t support, int32_t oversam
   // the footprint about the coarse cell (possibly the next cell) stays inside the separable one
   if (oversample != k->O && oversample != 1 && support > k->S - 2) return SEPW_ERR_ARG;
   if (corr_dmax(support, oversample) + 1 > kCorrMaxD) return SEPW_ERR_UNSUPPORTED;
-  if (k->facet) return SEPW_ERR_UNSUPPORTED;
+  // the correction passes run on the tiled path only
+  if (k->facet || wide_support(k->S)) return SEPW_ERR_UNSUPPORTED;
   // the generation folds the screen about the image centre: the taper must be symmetric
   const int N = k->N;
   std::vector<double> c1(N);
@@ -1152,6 +1167,18 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
   const int N = K->N;
   const bool grid_only = flags & SEPW_GRID_ONLY;
   if (p->generation != K->generation) return SEPW_ERR_ARG;
+  if (wide_support(K->S)) {
+    if (K->corr) return SEPW_ERR_UNSUPPORTED;
+    {
+      Stage st(SEPW_STAGE_FILL, s);
+      SEPW_TRY(launch_zero_c64(img, (int64_t)N * N, s));
+    }
+    {
+      Stage st(SEPW_STAGE_GRID, s);
+      SEPW_TRY(launch_grid_wide(wide_args(p, grid_only ? 0 : 1), reinterpret_cast<const float2*>(vis),
+                                weight, img, s));
+    }
+  } else {
   {
     Stage st(SEPW_STAGE_GATHER, s);
     MoveArgs m = move_args(p, vis, weight);
@@ -1187,6 +1214,7 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
   if (K->corr) {
     Stage st(SEPW_STAGE_CORR_APPLY, s);
     SEPW_TRY(launch_corr_grid(K->S, corr_args(p, p->gl, img, grid_only ? 0 : 1), p->gl.max_items, s));
+  }
   }
   if (grid_only) return SEPW_OK;
   {
@@ -1228,6 +1256,12 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
   }
   if (p->nvis == 0) return SEPW_OK;
   float2* vo = reinterpret_cast<float2*>(vis_out);
+  if (wide_support(K->S)) {
+    if (K->corr) return SEPW_ERR_UNSUPPORTED;
+    Stage st(SEPW_STAGE_DEGRID, s);
+    SEPW_TRY(launch_degrid_wide(wide_args(p, checker), src, vo, s));
+    return SEPW_OK;
+  }
   {
     Stage st(SEPW_STAGE_DEGRID, s);
     SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8 * kCtrStride, s));
@@ -1280,7 +1314,7 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
     if (plans[j]->generation != K->generation) return SEPW_ERR_ARG;
   }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (plans[0]->K->prm.precision != SEPW_FP32) {
+  if (plans[0]->K->prm.precision != SEPW_FP32 || wide_support(plans[0]->K->S)) {
     // the persistent launch is built for the FP32 path; other precisions go job by job
     for (int j = 0; j < njobs; ++j) {
       int rc = sepw_grid(plans[j], vis[j], weight ? weight[j] : nullptr, out[j], flags, hip_stream);
@@ -1374,7 +1408,7 @@ int sepw_grid_batched_noalloc(int32_t njobs, const sepw_plan* plans, const sepw_
     if (plans[j]->generation != K->generation) return SEPW_ERR_ARG;
   }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (plans[0]->K->prm.precision != SEPW_FP32) {
+  if (plans[0]->K->prm.precision != SEPW_FP32 || wide_support(plans[0]->K->S)) {
     // job by job, as sepw_grid_batched does (sepw_grid allocates nothing)
     for (int j = 0; j < njobs; ++j) {
       int rc = sepw_grid(plans[j], vis[j], weight ? weight[j] : nullptr, out[j], flags, hip_stream);
@@ -1651,7 +1685,7 @@ int sepw_wstack_degrid(sepw_wstack ws, const sepw_c64* image, sepw_c64* vis_out,
   if ((flags & ~SEPW_DIV_N) != 0) return SEPW_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   Kernels* K = ws->K;
-  if (K->prm.precision != SEPW_FP32 || ws->nimg < 2) {
+  if (K->prm.precision != SEPW_FP32 || ws->nimg < 2 || wide_support(K->S)) {
     for (int j = 0; j < ws->ns; ++j) {
       if (!ws->plans[j]) continue;
       {
@@ -1814,7 +1848,7 @@ int sepw_wsnap_degrid(sepw_wsnap ws, const sepw_c64* image, sepw_c64* vis_out, u
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const int N = K->N;
   const int npow = (flags & SEPW_DIV_N) ? -1 : 0;
-  if (K->prm.precision != SEPW_FP32 || ws->nimg < 2) {
+  if (K->prm.precision != SEPW_FP32 || ws->nimg < 2 || wide_support(K->S)) {
     for (int i = 0; i < ws->ns; ++i) {
       Plan* p = ws->plans[i];
       if (!p) continue;

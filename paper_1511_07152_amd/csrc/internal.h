@@ -12,7 +12,13 @@ namespace sepw {
 
 constexpr uint32_t kDropped = 0xFFFFFFFFu;
 constexpr int kRegion = 16;        // MFMA tile region edge (cells): core + S - 1
-constexpr int kMaxSupport = 15;    // S <= kRegion - 1
+constexpr int kMaxSupport = 15;    // S <= kRegion - 1 on the tiled MFMA path
+// Supports 15 < S <= kMaxWideSupport take the per-visibility path (wide.hip):
+// plans keep the quantiser and the level-1 row bins with tiles of
+// kWideRegion + 1 - S cells, but no tile slots or work lists.
+constexpr int kWideRegion = 32;
+constexpr int kMaxWideSupport = 31;
+__host__ __device__ inline bool wide_support(int S) { return S > kMaxSupport; }
 constexpr int kItemMaxVis = 2048;  // default slots per gridding work item (a slice of a tile row)
 constexpr int kDegridItemSlots = 224;  // default slots per degridding work item
 constexpr int kItemMinSlots = 64;  // range of the tunable item length
@@ -412,6 +418,25 @@ hipError_t launch_degrid_fp32(int S, const DegridArgs& a, int64_t max_items, int
 hipError_t launch_degrid_fp32_batched(int S, const DegridArgs* jobs, const uint32_t* first,
                                       int njobs, uint32_t* counter, int lds_bytes, int n_cu,
                                       hipStream_t s);
+
+// Per-visibility gridding and degridding for supports above the MFMA region
+// (wide.hip).  Inputs in caller order: packed bins and row bins of the plan
+// (kDropped: off the grid), raw tables [P][O][S].
+struct WideArgs {
+  const uint2* qrec;        // (cell_u | cell_v << 16, fi_u | fi_v << 8 | k << 16)
+  const uint32_t* rbin;     // kDropped for dropped visibilities
+  const float2* tab_u;
+  const float2* tab_v;
+  const float2* rot;        // facet rotation or null
+  int64_t nvis;
+  int N, S, O;
+  int checker;              // grid side of the centred FFT: (-1)^(x+y)
+};
+// grid += W V rot Tu Tv over each footprint (atomics)
+hipError_t launch_grid_wide(const WideArgs& a, const float2* vis, const float* weight,
+                            float2* grid, hipStream_t s);
+// out[i] = conj(rot) sum conj(Tv) conj(Tu) grid over the footprint, 0 when dropped
+hipError_t launch_degrid_wide(const WideArgs& a, const float2* grid, float2* out, hipStream_t s);
 
 // out[q][p] = in[q][p] (-1)^(p+q) n(l0 + l_p, m0 + m_q)^npow / (c1[p] c1[q])
 hipError_t launch_correct(const float2* in, float2* out, const double* c1, int N, double fov,

@@ -58,6 +58,8 @@ __device__ inline double block_sum(double v, double* sh) {
   return t;
 }
 
+// SMAX: taps held per thread (16 for the tiled path, 32 above it)
+template <int SMAX>
 __global__ __launch_bounds__(kTabThreads) void table_kernel(
     const double* __restrict__ c1, int N, double fov, int P, int O, int S, double w_lo,
     double w_hi, double a, double b, float2* __restrict__ out) {
@@ -68,9 +70,9 @@ __global__ __launch_bounds__(kTabThreads) void table_kernel(
   const int h = S / 2;
   const double wk = w_lo + ((double)k + 0.5) * (w_hi - w_lo) / (double)P;
   const int64_t period = (int64_t)O * N;
-  double acc_re[kMaxSupport], acc_im[kMaxSupport];
+  double acc_re[SMAX], acc_im[SMAX];
 #pragma unroll
-  for (int s = 0; s < kMaxSupport; ++s) acc_re[s] = acc_im[s] = 0.0;
+  for (int s = 0; s < SMAX; ++s) acc_re[s] = acc_im[s] = 0.0;
 
   for (int p = threadIdx.x; p < N; p += kTabThreads) {
     const double l = (double)(p - N / 2) * fov / (double)N;
@@ -93,7 +95,7 @@ __global__ __launch_bounds__(kTabThreads) void table_kernel(
     sincospi(-2.0 * (double)r0 / (double)period, &te, &tc);
     sincospi(-2.0 * (double)q / (double)N, &rs, &rc);
 #pragma unroll
-    for (int s = 0; s < kMaxSupport; ++s) {
+    for (int s = 0; s < SMAX; ++s) {
       if (s < S) {
         acc_re[s] += are * tc - aim * te;
         acc_im[s] += are * te + aim * tc;
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(kTabThreads) void table_kernel(
   }
   const double invN = 1.0 / (double)N;
 #pragma unroll
-  for (int s = 0; s < kMaxSupport; ++s) {
+  for (int s = 0; s < SMAX; ++s) {
     if (s < S) {
       double re = block_sum(acc_re[s], sh);
       double im = block_sum(acc_im[s], sh);
@@ -195,8 +197,13 @@ hipError_t launch_lp_table(const float2* tab, int P, int O, int S, int bf16, int
 
 hipError_t launch_tables(const double* c1, int N, double fov, int P, int O, int S, double w_lo,
                          double w_hi, double a, double b, float2* out, hipStream_t s) {
-  hipLaunchKernelGGL(table_kernel, dim3(P * O), dim3(kTabThreads), 0, s, c1, N, fov, P, O, S,
-                     w_lo, w_hi, a, b, out);
+  if (S <= 16) {
+    hipLaunchKernelGGL(table_kernel<16>, dim3(P * O), dim3(kTabThreads), 0, s, c1, N, fov, P, O, S,
+                       w_lo, w_hi, a, b, out);
+  } else {
+    hipLaunchKernelGGL(table_kernel<32>, dim3(P * O), dim3(kTabThreads), 0, s, c1, N, fov, P, O, S,
+                       w_lo, w_hi, a, b, out);
+  }
   return hipGetLastError();
 }
 

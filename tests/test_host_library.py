@@ -77,9 +77,24 @@ def test_invalid_kernel_params_rejected(lib, bad):
 
 
 def test_unsupported_support(lib):
-    p = _params(lib, support=17)
-    h = ctypes.c_void_p()
-    assert lib.sepw_make_kernels(ctypes.byref(p), None, ctypes.byref(h)) == -5
+    # above 31 cells, and above 15 for the 16-bit forms (the per-visibility
+    # path of wide supports is FP32 only)
+    for kw in (dict(support=33), dict(support=17, precision=1), dict(support=31, precision=2)):
+        p = _params(lib, **kw)
+        h = ctypes.c_void_p()
+        assert lib.sepw_make_kernels(ctypes.byref(p), None, ctypes.byref(h)) == -5, kw
+        assert not h.value
+
+
+def test_wide_support_passes_validation(lib):
+    # S = 17 .. 31 in FP32 is valid: without a device the call gets past the
+    # argument checks to the device lookup
+    if lib.sepw_device_count() > 0:
+        pytest.skip("a device is present")
+    for S in (17, 21, 31):
+        p = _params(lib, support=S)
+        h = ctypes.c_void_p()
+        assert lib.sepw_make_kernels(ctypes.byref(p), None, ctypes.byref(h)) == -2
 
 
 def test_no_device_reported_after_validation(lib):
