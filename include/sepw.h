@@ -53,10 +53,11 @@
  * library.  Every call is asynchronous on the given HIP stream (NULL = the
  * default stream) unless stated; a kernel failure surfaces as SEPW_ERR_HIP at
  * a later call.  A plan or kernels object must not be used by two calls that
- * overlap in time (its scratch and FFT plan are shared).  The batched calls
- * (sepw_grid_batched, sepw_autotune_batched and the W-stacking and W-snapshot
- * grid and degrid calls) share one job table and work counter per process:
- * calls of them that overlap in time on different streams race.
+ * overlap in time (its scratch and FFT plan are shared).  A batched call
+ * (sepw_grid_batched, sepw_autotune_batched) keeps its job table, work
+ * counter and launch width in its first plan, and the W-stacking and
+ * W-snapshot calls in their first plan: calls led by different plans share
+ * nothing and may overlap on different streams.
  *
  * Errors: every call returns SEPW_OK or a negative code; no exception crosses
  * the ABI.  Arguments are validated on the host before any device work, so a
@@ -323,8 +324,8 @@ int sepw_plan_set_degrid_item_slots(sepw_plan p, int32_t slots, void* hip_stream
  * SEPW_GRID_ONLY on these jobs (HIP events, one warm-up and two timed runs per
  * candidate) for every work-item length in {256, 512, 1024, 2048} and every
  * persistent launch width in {2, 4, 8} workgroups per compute unit, and keeps
- * the fastest pair: the plans keep that item length, and later batched calls
- * in this process use that width.  The pair is returned in *item_slots and
+ * the fastest pair: the plans keep that item length and that width (used by
+ * later batched calls that they lead).  The pair is returned in *item_slots and
  * *blocks_per_cu (either may be NULL).  out[] is overwritten.  Synchronous.
  * Errors: as sepw_grid_batched, and those of sepw_plan_set_item_slots. */
 int sepw_autotune_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* const* vis,

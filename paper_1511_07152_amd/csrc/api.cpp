@@ -53,6 +53,8 @@ struct sepw_wsnap_s {
 
 namespace {
 
+void release_batch(BatchScratch& b);
+
 int map_hip(hipError_t e) {
   if (e == hipSuccess) return SEPW_OK;
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SEPW_ERR_OOM;
@@ -209,6 +211,10 @@ void destroy_plan(Plan* p) {
   dfree(p->qctr);
   dfree(p->lp_max);
   dfree(p->scan_tmp);
+  if (p->batch) {
+    release_batch(*p->batch);
+    delete p->batch;
+  }
   delete static_cast<sepw_plan_s*>(p);
 }
 
@@ -576,10 +582,15 @@ int read_dropped(Plan* P, int64_t* n_dropped, hipStream_t s) {
   return SEPW_OK;
 }
 
-// Library-owned scratch of the batched launch: the job table (pinned host
-// copy and device copy), the per-job item prefix and the work counter.  One
-// per process, grown on demand; guarded so that a new call waits until the
-// previous call's job table has reached the device before overwriting it.
+}  // namespace
+
+namespace sepw {
+// Library-owned scratch of the batched launches: the job tables (pinned host
+// copies and device copies), the per-job item prefix and the work counter.
+// Each plan owns one, used by the batched calls it leads (as plans[0]), grown
+// on demand; a new call waits until the previous call's job table has reached
+// the device before overwriting it.  Calls led by different plans share
+// nothing, so they may overlap on different streams.
 struct BatchScratch {
   int cap = 0;
   int device = -1;
@@ -597,29 +608,34 @@ struct BatchScratch {
   hipEvent_t copied = nullptr;
   int n_cu = 0;
 };
-std::mutex g_bmx;
-BatchScratch g_batch;
-int g_blocks_per_cu = 8;   // persistent batched launch width (set by the autotuner)
+}  // namespace sepw
 
-int batch_scratch(int njobs, hipStream_t s, BatchScratch** out) {
-  std::lock_guard<std::mutex> lk(g_bmx);
-  BatchScratch& b = g_batch;
+namespace {
+
+void release_batch(BatchScratch& b) {
+  if (b.copied) (void)hipEventSynchronize(b.copied);
+  if (b.host) (void)hipHostFree(b.host);
+  if (b.mhost) (void)hipHostFree(b.mhost);
+  if (b.mfirst_host) (void)hipHostFree(b.mfirst_host);
+  if (b.dhost) (void)hipHostFree(b.dhost);
+  dfree(b.djobs);
+  dfree(b.jobs);
+  dfree(b.mjobs);
+  dfree(b.mfirst);
+  dfree(b.first);
+  dfree(b.counter);
+  if (b.copied) (void)hipEventDestroy(b.copied);
+  b = BatchScratch();
+}
+
+int batch_scratch(Plan* lead, int njobs, hipStream_t s, BatchScratch** out) {
+  if (!lead->batch) lead->batch = new BatchScratch();
+  BatchScratch& b = *lead->batch;
   int dev = 0;
   SEPW_TRY(hipGetDevice(&dev));
   if (b.copied) SEPW_TRY(hipEventSynchronize(b.copied));
   if (b.cap < njobs || b.device != dev) {
-    if (b.host) (void)hipHostFree(b.host);
-    if (b.mhost) (void)hipHostFree(b.mhost);
-    if (b.mfirst_host) (void)hipHostFree(b.mfirst_host);
-    if (b.dhost) (void)hipHostFree(b.dhost);
-    dfree(b.djobs);
-    dfree(b.jobs);
-    dfree(b.mjobs);
-    dfree(b.mfirst);
-    dfree(b.first);
-    dfree(b.counter);
-    if (b.copied) (void)hipEventDestroy(b.copied);
-    b = BatchScratch();
+    release_batch(b);
     const int cap = njobs < 64 ? 64 : njobs;
     SEPW_TRY(hipHostMalloc(reinterpret_cast<void**>(&b.host), sizeof(GridArgs) * (size_t)cap));
     SEPW_TRY(hipHostMalloc(reinterpret_cast<void**>(&b.mhost), sizeof(MoveArgs) * (size_t)cap));
@@ -640,7 +656,7 @@ int batch_scratch(int njobs, hipStream_t s, BatchScratch** out) {
     b.device = dev;
   }
   (void)s;
-  b.blocks = b.n_cu * g_blocks_per_cu;
+  b.blocks = b.n_cu * lead->blocks_per_cu;
   *out = &b;
   return SEPW_OK;
 }
@@ -664,7 +680,7 @@ int degrid_images_batched(Kernels* K, Plan* const* plans, int nj, float2* grids,
     if (rc != SEPW_OK) return rc;
   }
   BatchScratch* bs = nullptr;
-  int rc = batch_scratch(nj, s, &bs);
+  int rc = batch_scratch(plans[0], nj, s, &bs);
   if (rc != SEPW_OK) return rc;
   for (int j = 0; j < nj; ++j) {
     const Plan* p = plans[j];
@@ -1330,7 +1346,7 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return plans[a]->nvis > plans[b]->nvis; });
   BatchScratch* bs = nullptr;
-  int rc = batch_scratch(njobs, s, &bs);
+  int rc = batch_scratch(plans[0], njobs, s, &bs);
   if (rc != SEPW_OK) return rc;
   // one movement launch for all jobs (job table and workgroup prefix on the host)
   int64_t mtotal = 0;
@@ -1456,7 +1472,7 @@ int sepw_grid_batched_noalloc(int32_t njobs, const sepw_plan* plans, const sepw_
     SEPW_TRY(launch_zero_c64(reinterpret_cast<float2*>(out[j]), (int64_t)N * N, s));
   SEPW_TRY(launch_job_prefix(area->jobs, njobs, area->first, &area->counter, s));
   SEPW_TRY(launch_grid_fp32_batched(S, area->jobs, area->first, njobs, &area->counter,
-                                    plans[0]->K->n_cu * g_blocks_per_cu, s));
+                                    plans[0]->K->n_cu * plans[0]->blocks_per_cu, s));
   for (int j = 0; j < njobs; ++j) {
     Plan* p = plans[j];
     if (!p->K->corr) continue;
@@ -1507,10 +1523,7 @@ int sepw_autotune_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64*
     for (int j = 0; j < njobs && rc == SEPW_OK; ++j)
       rc = sepw_plan_set_item_slots(plans[j], kSlots[si], hip_stream);
     for (int wi = 0; wi < 3 && rc == SEPW_OK; ++wi) {
-      {
-        std::lock_guard<std::mutex> lk(g_bmx);
-        g_blocks_per_cu = kWidth[wi];
-      }
+      for (int j = 0; j < njobs; ++j) plans[j]->blocks_per_cu = kWidth[wi];
       rc = sepw_grid_batched(njobs, plans, vis, weight, out, SEPW_GRID_ONLY, hip_stream);
       if (rc != SEPW_OK) break;
       he = hipEventRecord(e0, s);
@@ -1530,10 +1543,7 @@ int sepw_autotune_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64*
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  {
-    std::lock_guard<std::mutex> lk(g_bmx);
-    g_blocks_per_cu = best_width;
-  }
+  for (int j = 0; j < njobs; ++j) plans[j]->blocks_per_cu = best_width;
   for (int j = 0; j < njobs && rc == SEPW_OK; ++j)
     rc = sepw_plan_set_item_slots(plans[j], best_slots, hip_stream);
   if (rc != SEPW_OK) return rc;

@@ -116,6 +116,8 @@ struct WorkList {
   int4* items = nullptr;       // [max_items] (tile row, first slot, end slot, tile column)
 };
 
+struct BatchScratch;   // job tables of the batched launches (api.cpp)
+
 struct Plan {
   Kernels* K = nullptr;
   uint64_t generation = 0;      // K->generation the bins were made for
@@ -153,6 +155,9 @@ struct Plan {
   WorkList dl;                  // degridding work items (shorter: fewer rows of results in flight)
   uint32_t* scan_tmp = nullptr; // block partials for the scans
   int64_t scan_tmp_len = 0;
+  // batched calls led by this plan (plans[0]) keep their job tables here
+  BatchScratch* batch = nullptr;
+  int blocks_per_cu = 8;        // persistent batched launch width (set by the autotuner)
 };
 
 // Workgroups of a launch are dispatched to the 8 XCDs in turn (workgroup b on

@@ -127,3 +127,30 @@ def test_autotuned_batch_equals_per_job(lib):
             assert np.abs(got).max() == 0.0
         else:
             assert rel_rms(got, single) <= 1e-6
+
+
+def test_batched_calls_led_by_different_plans_overlap(lib):
+    # each batched call keeps its job table in its first plan: two calls led
+    # by different plans, queued on two streams (default priority) without a
+    # wait between them, both match the per-plan results
+    N, fov, S, O, P = 128, math.radians(1.5), 11, 8, 8
+    groups = []
+    for g, counts in enumerate(([4000, 30, 900], [2500, 7000, 11, 60])):
+        jobs = _jobs(70 + g, len(counts), N, fov, counts)
+        Ks = [lib.Kernels(N, fov, S, O, P, -350.0, 350.0, facet=jb["facet"]) for jb in jobs]
+        plans = [lib.Plan(K, dev(jb["u"], torch.float64), dev(jb["v"], torch.float64),
+                          dev(jb["w"], torch.float64)) for K, jb in zip(Ks, jobs)]
+        vis = [dev(jb["V"], torch.complex64) for jb in jobs]
+        wts = [dev(jb["W"], torch.float32) for jb in jobs]
+        groups.append((Ks, plans, vis, wts))
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    for st, (Ks, plans, vis, wts) in zip(streams, groups):
+        with torch.cuda.stream(st):
+            outs.append(lib.grid_batched(plans, vis, wts, flags=lib.GRID_ONLY))
+    torch.cuda.synchronize()
+    for (Ks, plans, vis, wts), got in zip(groups, outs):
+        for p, v, w, g in zip(plans, vis, wts, got):
+            want = lib.grid(p, v, w, flags=lib.GRID_ONLY)
+            assert rel_rms(g.cpu().numpy(), want.cpu().numpy()) <= 1e-6
