@@ -231,6 +231,17 @@ int32_t sepw_plan_tile_size(sepw_plan p);
 int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* out,
               uint32_t flags, void* hip_stream);
 
+/* Non-finite values.  For S <= 15 the sums run over 16 x 16 cell regions
+ * (tile core plus footprint, zero taps outside the footprint), and 0 times
+ * NaN or Inf is NaN: a NaN or Inf in W V makes the whole region of its tile
+ * non-finite (cells within 16 of its own cell, a superset of its footprint),
+ * and a NaN or Inf grid cell makes non-finite every degridded visibility
+ * whose tile region holds it (cells past the grid edge read the edge cell
+ * times 0).  Other cells and visibilities are unaffected; the FP16 form's
+ * power-of-two scales are taken over finite values only.  For S = 17..31
+ * (per-visibility path) a non-finite value reaches its own footprint only.
+ * The images and predictions of the FFT passes spread it over the plane. */
+
 /* Degrid: V_i = sum_t conj(Tv[..][t]) sum_s conj(Tu[..][s]) Ghat[cv-S/2+t][cu-S/2+s],
  * the adjoint of sepw_grid.  Without SEPW_GRID_ONLY, Ghat = F-[X / (c1 c1)] with
  * X = image (or image / n with SEPW_DIV_N).  in: DEVICE complex64[N*N] (not

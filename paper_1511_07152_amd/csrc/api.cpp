@@ -55,8 +55,12 @@ namespace {
 
 void release_batch(BatchScratch& b);
 
+// Error code for a failed runtime call.  Also clears the thread's last-error
+// state, which a failed call (an allocation, say) leaves set: the next kernel
+// launch checks it and would otherwise report this failure again.
 int map_hip(hipError_t e) {
   if (e == hipSuccess) return SEPW_OK;
+  (void)hipGetLastError();
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SEPW_ERR_OOM;
   if (e == hipErrorNoDevice || e == hipErrorInvalidDevice) return SEPW_ERR_NO_DEVICE;
   return SEPW_ERR_HIP;

@@ -775,7 +775,7 @@ __device__ inline void to_rows_chunk(const MoveArgs& a, int64_t chunk, MoveLds& 
     wt[m] = (in && a.weight) ? __builtin_nontemporal_load(a.weight + i) : 1.f;
     ro[m] = (in && a.rot) ? a.rot[i] : make_float2(1.f, 0.f);
   }
-  float mx = 0.f;   // max |Re, Im| of the placed values (fmaxf skips NaN)
+  float mx = 0.f;   // max |Re, Im| over the finite parts of the placed values
 #pragma unroll
   for (int m = 0; m < kPerThread; ++m) {
     if (pl[m] == kDropped) continue;
@@ -784,7 +784,7 @@ __device__ inline void to_rows_chunk(const MoveArgs& a, int64_t chunk, MoveLds& 
     const uint32_t k = pl[m] & kPlaceMask;
     L.stage[k] = v;
     L.binof[k] = (uint16_t)(pl[m] >> kPlaceShift);
-    mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+    mx = finite_absmax(mx, v);
   }
   __syncthreads();
   const uint32_t kept = a.ckept[chunk];

@@ -143,10 +143,9 @@ __device__ __forceinline__ f32x4 mma(const Opnd& a, const Opnd& b, f32x4 c) {
   return L::mfma(a.h, b.h, c);
 }
 
-// Exponent e of the smallest power of two above m = max |Re, Im| (bits of a
-// non-negative float), clamped to [-100, 100]; 0 when m is 0 or not finite
-// (any scale then serves: the operands are all 0, or the sums are not finite
-// anyway).
+// Exponent e of the smallest power of two above m = max |Re, Im| over the
+// finite parts (bits of a non-negative float), clamped to [-100, 100]; 0 when
+// m is 0 (any scale then serves: the operands are all 0).
 __device__ inline int exp_above(uint32_t bits) {
   const float m = __uint_as_float(bits);
   if (!(m > 0.f) || !(m <= 3.0e38f)) return 0;
@@ -744,8 +743,7 @@ __global__ __launch_bounds__(256) void absmax_kernel(const float2* __restrict__ 
   __shared__ float sh[4];
   float mx = 0.f;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const float2 v = g[i];
-    mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+    mx = finite_absmax(mx, g[i]);
   }
   for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;

@@ -43,6 +43,16 @@ constexpr int kCtrStride = 64;     // dwords between the 8 work-list counters (o
 // them, so that tap index col - ox for col in [0, 16) and ox in [0, c) is
 // always a valid, predicate-free offset: padded[row][c - 1 + col - ox].
 __host__ __device__ inline int padded_len(int S) { return 32 - S; }
+
+// Running maximum of |Re| and |Im| over finite parts only, for the FP16
+// form's per-call power-of-two scale: a NaN or Inf value does not set the
+// scale (it stays non-finite in the products it enters).
+__device__ inline float finite_absmax(float mx, float2 v) {
+  const float a = fabsf(v.x), b = fabsf(v.y);
+  if (a <= 3.4028235e38f) mx = fmaxf(mx, a);
+  if (b <= 3.4028235e38f) mx = fmaxf(mx, b);
+  return mx;
+}
 constexpr int kMaxRowTiles = 16384; // tiles per level-1 bin (level-2 sort in LDS)
 
 // Geometry shared by the binning kernels; all FP64 values are used exactly as
