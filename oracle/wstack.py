@@ -27,24 +27,73 @@ Readings (the paper fixes none of these):
   [-h, h], h = (w_hi - w_lo) / (2 n_s), one table set shared by all slices;
 * n - 1 is evaluated as -(l^2 + m^2) / (1 + n), which equals it exactly and
   avoids the cancellation of n - 1 near the centre.
+
+Non-uniform slices (Section 4.3 suggests many narrow slices near w = 0 and
+wider ones at large |w|, slice widths adapted to the visibility density):
+
+* with increasing edges e_0 < ... < e_ns, slice s holds e_s <= w < e_{s+1}
+  (w below e_0 in slice 0, w at or above e_ns in the last slice, non-finite w
+  in slice 0), centre w_s = (e_s + e_{s+1}) / 2, and the residual planes are
+  P uniform planes on [-h, h] with h the largest half-width (e_{s+1} - e_s) / 2,
+  one table set for all slices;
+* density-adapted edges: the finite w are counted in nfine uniform bins of
+  [w_lo, w_hi] (bin index as the plane index); edge k (0 < k < ns) is the
+  first bin boundary j at which the count below reaches k n / ns (n finite
+  visibilities), kept strictly increasing and leaving one bin for each later
+  slice; e_k = w_lo + j d with d = (w_hi - w_lo) / nfine, e_0 = w_lo,
+  e_ns = w_hi.  Slices then hold about n / ns visibilities each, so they are
+  narrow where w is dense.
 """
 import numpy as np
 
 from . import geometry, gridder, imaging, quantise, tables
 
 
-def slice_of(w, n_slices, w_lo, w_hi):
+def slice_of(w, n_slices, w_lo, w_hi, edges=None):
     """Slice index, slice centres and residual w - w_s of each visibility
     (non-finite w goes to slice 0 with a non-finite residual, which the
-    plane quantiser then drops)."""
-    s, _ = quantise.plane_index(w, n_slices, w_lo, w_hi)
-    ws = tables.w_plane_centres(n_slices, w_lo, w_hi)
-    return s, ws, np.asarray(w, np.float64) - ws[s]
+    plane quantiser then drops).  edges: None for uniform slices on
+    [w_lo, w_hi], else the n_slices + 1 increasing slice edges."""
+    w = np.asarray(w, np.float64)
+    if edges is None:
+        s, _ = quantise.plane_index(w, n_slices, w_lo, w_hi)
+        ws = tables.w_plane_centres(n_slices, w_lo, w_hi)
+    else:
+        e = np.asarray(edges, np.float64)
+        s = np.clip(np.searchsorted(e, w, side='right') - 1, 0, n_slices - 1)
+        s = np.where(np.isfinite(w), s, 0)
+        ws = (e[:-1] + e[1:]) * 0.5
+    return s, ws, w - ws[s]
 
 
-def residual_range(n_slices, w_lo, w_hi):
-    h = (np.float64(w_hi) - np.float64(w_lo)) / (2 * n_slices)
+def residual_range(n_slices, w_lo, w_hi, edges=None):
+    if edges is None:
+        h = (np.float64(w_hi) - np.float64(w_lo)) / (2 * n_slices)
+    else:
+        h = np.max(np.diff(np.asarray(edges, np.float64))) * 0.5
     return -h, h
+
+
+def density_edges(w, n_slices, w_lo, w_hi, nfine=16384):
+    """Slice edges with about equal visibility counts per slice (see the
+    module docstring)."""
+    w = np.asarray(w, np.float64)
+    fin = np.isfinite(w)
+    j, _ = quantise.plane_index(w[fin], nfine, w_lo, w_hi)
+    counts = np.bincount(j, minlength=nfine)
+    below = np.concatenate([[0], np.cumsum(counts)])    # below[j]: count in bins < j
+    n = int(below[-1])
+    d = (np.float64(w_hi) - np.float64(w_lo)) / nfine
+    e = np.empty(n_slices + 1)
+    e[0], e[n_slices] = w_lo, w_hi
+    prev = 0
+    for k in range(1, n_slices):
+        # first j with below[j] * ns >= k n (integers)
+        jk = int(np.searchsorted(below * n_slices, k * n, side='left'))
+        jk = min(max(jk, prev + 1), nfine - (n_slices - k))
+        e[k] = np.float64(w_lo) + np.float64(jk) * d
+        prev = jk
+    return e
 
 
 def slice_phase(N, fov, w_s, sign):
@@ -59,17 +108,17 @@ def _bins(u, v, w, N, fov, O, S, P, w_lo, w_hi):
     return quantise.quantise(u, v, w, N, fov, O, S, P, w_lo, w_hi, 1)
 
 
-def residual_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a=0.5, b=5.0 / 24.0):
-    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi)
+def residual_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a=0.5, b=5.0 / 24.0, edges=None):
+    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi, edges)
     return tables.separable_table(tables.w_plane_centres(P, r_lo, r_hi), N, fov, S, O, c1, a=a, b=b)
 
 
 def image(u, v, w, y, N, fov, S, O, P, n_slices, w_lo, w_hi, c1, n_power=0, a=0.5,
-          b=5.0 / 24.0, bins=_bins, wrap=False):
+          b=5.0 / 24.0, bins=_bins, wrap=False, edges=None):
     """Sum over slices of exp(2 pi i w_s (n - 1)) times the slice's corrected image."""
-    s, ws, dw = slice_of(w, n_slices, w_lo, w_hi)
-    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi)
-    T = residual_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a, b)
+    s, ws, dw = slice_of(w, n_slices, w_lo, w_hi, edges)
+    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi, edges)
+    T = residual_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a, b, edges)
     D = np.zeros((N, N), dtype=np.complex128)
     for k in range(n_slices):
         idx = np.flatnonzero(s == k)
@@ -82,11 +131,11 @@ def image(u, v, w, y, N, fov, S, O, P, n_slices, w_lo, w_hi, c1, n_power=0, a=0.
 
 
 def predict(u, v, w, X, N, fov, S, O, P, n_slices, w_lo, w_hi, c1, n_power=0, a=0.5,
-            b=5.0 / 24.0, bins=_bins, wrap=False):
+            b=5.0 / 24.0, bins=_bins, wrap=False, edges=None):
     """Visibilities of model X: slice s degrids X exp(-2 pi i w_s (n - 1))."""
-    s, ws, dw = slice_of(w, n_slices, w_lo, w_hi)
-    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi)
-    T = residual_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a, b)
+    s, ws, dw = slice_of(w, n_slices, w_lo, w_hi, edges)
+    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi, edges)
+    T = residual_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a, b, edges)
     V = np.zeros(len(u), dtype=np.complex128)
     for k in range(n_slices):
         idx = np.flatnonzero(s == k)
@@ -98,8 +147,8 @@ def predict(u, v, w, X, N, fov, S, O, P, n_slices, w_lo, w_hi, c1, n_power=0, a=
     return V
 
 
-def bins(u, v, w, N, fov, O, S, P, n_slices, w_lo, w_hi):
+def bins(u, v, w, N, fov, O, S, P, n_slices, w_lo, w_hi, edges=None):
     """Bins of every visibility in caller order (residual w, residual planes)."""
-    _, _, dw = slice_of(w, n_slices, w_lo, w_hi)
-    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi)
+    _, _, dw = slice_of(w, n_slices, w_lo, w_hi, edges)
+    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi, edges)
     return quantise.quantise(u, v, dw, N, fov, O, S, P, r_lo, r_hi, 1)
