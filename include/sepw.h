@@ -299,6 +299,37 @@ int sepw_wstack_create(sepw_kernels k, int32_t n_slices, double w_lo, double w_h
                        const double* u, const double* v, const double* w, int64_t* n_dropped,
                        void* hip_stream, sepw_wstack* out);
 
+/* W-stacking with non-uniform slices (Section 4.3 suggests many narrow
+ * slices near w = 0 and wider ones at large |w|, adapted to the visibility
+ * density).  edges: HOST float64[n_slices + 1], finite and strictly
+ * increasing; slice s holds e_s <= w < e_{s+1} (w below e_0 in slice 0, w at
+ * or above e_ns in the last slice, non-finite w in slice 0 and dropped),
+ * centre w_s = (e_s + e_{s+1}) / 2.  k's planes must span exactly [-h, h]
+ * with h the largest half-width (e_{s+1} - e_s) / 2 (narrower slices use the
+ * middle planes of the same tables).  Everything else as sepw_wstack_create;
+ * the object is used with sepw_wstack_grid / _degrid / sepw_free_wstack.
+ * Errors: SEPW_ERR_ARG (null k, edges or out, facet kernels, n_slices outside
+ * [1, 4096], edges not finite and increasing, kernels' w range not [-h, h],
+ * nvis out of range), SEPW_ERR_OOM, SEPW_ERR_HIP. */
+int sepw_wstack_create_edges(sepw_kernels k, int32_t n_slices, const double* edges, int64_t nvis,
+                             const double* u, const double* v, const double* w,
+                             int64_t* n_dropped, void* hip_stream, sepw_wstack* out);
+
+/* Density-adapted slice edges (Section 4.3's adaptation of slice width to the
+ * visibility density): the finite w (DEVICE float64[nvis]) are counted in
+ * 16384 uniform bins of [w_lo, w_hi] (bin floor((w - w_lo) 16384 / (w_hi -
+ * w_lo)), clamped); edge k, 0 < k < n_slices, is w_lo + j d (d = (w_hi - w_lo)
+ * / 16384) for the first bin boundary j below which at least k n / n_slices of
+ * the n finite visibilities lie, raised to keep the edges increasing and
+ * lowered to leave one bin for each later slice; e_0 = w_lo,
+ * e_ns = w_hi.  Slices then hold about n / n_slices visibilities each.
+ * edges: HOST float64[n_slices + 1], written.  Synchronises the stream.
+ * Errors: SEPW_ERR_ARG (null edges, n_slices outside [1, 4096], w_lo >= w_hi
+ * or not finite, nvis out of range, null w with nvis > 0),
+ * SEPW_ERR_NO_DEVICE, SEPW_ERR_OOM, SEPW_ERR_HIP. */
+int sepw_wstack_density_edges(int64_t nvis, const double* w, int32_t n_slices, double w_lo,
+                              double w_hi, double* edges, void* hip_stream);
+
 /* Dirty image of the W-stacking hybrid: sum over slices of
  * exp(2 pi i w_s (n - 1)) times the slice's image (sepw_grid without
  * SEPW_GRID_ONLY, same flags SEPW_MUL_N / SEPW_DIV_N).  vis, weight: DEVICE,

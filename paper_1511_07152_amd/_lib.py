@@ -82,6 +82,10 @@ def load():
                                           P(c_void_p), c_void_p, P(c_int32), P(c_int32)]
     lib.sepw_wstack_create.argtypes = [c_void_p, c_int32, c_double, c_double, c_int64, c_void_p,
                                        c_void_p, c_void_p, P(c_int64), c_void_p, P(c_void_p)]
+    lib.sepw_wstack_create_edges.argtypes = [c_void_p, c_int32, P(c_double), c_int64, c_void_p,
+                                             c_void_p, c_void_p, P(c_int64), c_void_p, P(c_void_p)]
+    lib.sepw_wstack_density_edges.argtypes = [c_int64, c_void_p, c_int32, c_double, c_double,
+                                              P(c_double), c_void_p]
     lib.sepw_wstack_grid.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_uint32,
                                      c_void_p]
     lib.sepw_wstack_degrid.argtypes = [c_void_p, c_void_p, c_void_p, ctypes.c_uint32, c_void_p]
@@ -324,12 +328,26 @@ class Plan:
             pass
 
 
+def density_edges(w, n_slices, w_lo, w_hi):
+    """sepw_wstack_density_edges: n_slices + 1 slice edges (numpy float64)
+    with about equal visibility counts per slice."""
+    lib = load()
+    w = _dev(w, torch.float64, "w")
+    out = (c_double * (int(n_slices) + 1))()
+    _check(lib.sepw_wstack_density_edges(w.numel(), _ptr(w), int(n_slices), float(w_lo),
+                                         float(w_hi), out, _stream()), "sepw_wstack_density_edges")
+    import numpy as np
+    return np.array(out[:], dtype=np.float64)
+
+
 class WStack:
     """sepw_wstack_create: W-stacking hybrid over n_slices uniform w-slices on
     [w_lo, w_hi]; ``kernels`` hold the residual tables (planes on [-h, h],
-    h = (w_hi - w_lo) / (2 n_slices))."""
+    h = (w_hi - w_lo) / (2 n_slices)).  With ``edges`` (n_slices + 1
+    increasing values; w_lo, w_hi ignored) sepw_wstack_create_edges: slices
+    [e_s, e_{s+1}), h the largest half-width."""
 
-    def __init__(self, kernels, n_slices, w_lo, w_hi, u, v, w, count_dropped=True):
+    def __init__(self, kernels, n_slices, w_lo, w_hi, u, v, w, count_dropped=True, edges=None):
         lib = load()
         u = _dev(u, torch.float64, "u")
         v = _dev(v, torch.float64, "v")
@@ -340,10 +358,18 @@ class WStack:
         self.nvis = u.numel()
         nd = c_int64(-1)
         h = c_void_p()
-        _check(lib.sepw_wstack_create(kernels.handle, int(n_slices), float(w_lo), float(w_hi),
-                                      self.nvis, _ptr(u), _ptr(v), _ptr(w),
-                                      ctypes.byref(nd) if count_dropped else None, _stream(),
-                                      ctypes.byref(h)), "sepw_wstack_create")
+        pnd = ctypes.byref(nd) if count_dropped else None
+        if edges is None:
+            _check(lib.sepw_wstack_create(kernels.handle, int(n_slices), float(w_lo), float(w_hi),
+                                          self.nvis, _ptr(u), _ptr(v), _ptr(w), pnd, _stream(),
+                                          ctypes.byref(h)), "sepw_wstack_create")
+        else:
+            if len(edges) != int(n_slices) + 1:
+                raise ValueError("edges must hold n_slices + 1 values")
+            e = (c_double * len(edges))(*[float(x) for x in edges])
+            _check(lib.sepw_wstack_create_edges(kernels.handle, int(n_slices), e, self.nvis,
+                                                _ptr(u), _ptr(v), _ptr(w), pnd, _stream(),
+                                                ctypes.byref(h)), "sepw_wstack_create_edges")
         self._h = h
         self.n_dropped = nd.value if count_dropped else None
 

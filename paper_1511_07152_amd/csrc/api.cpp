@@ -734,14 +734,17 @@ void destroy_wstack(sepw_wstack_s* W) {
 
 // Partition into slices (count, offsets, scatter with residual w), one plan
 // per non-empty slice.  Synchronises the stream (slice sizes come to the host).
-int wstack_build(sepw_wstack_s* W, Kernels* K, int ns, double w_lo, double w_hi, int64_t nvis,
-                 const double* u, const double* v, const double* w, int64_t* n_dropped,
-                 hipStream_t s) {
+// edges: null for uniform slices on [w_lo, w_hi], else ns + 1 increasing
+// host values (slice s = [e_s, e_{s+1}), centre (e_s + e_{s+1}) / 2).
+int wstack_build(sepw_wstack_s* W, Kernels* K, int ns, double w_lo, double w_hi,
+                 const double* edges, int64_t nvis, const double* u, const double* v,
+                 const double* w, int64_t* n_dropped, hipStream_t s) {
   W->K = K;
   W->ns = ns;
   W->nvis = nvis;
   W->centre.resize(ns);
-  for (int j = 0; j < ns; ++j) W->centre[j] = w_lo + ((j + 0.5) * (w_hi - w_lo)) / ns;
+  for (int j = 0; j < ns; ++j)
+    W->centre[j] = edges ? (edges[j] + edges[j + 1]) * 0.5 : w_lo + ((j + 0.5) * (w_hi - w_lo)) / ns;
   const double inv_ds = (double)ns / (w_hi - w_lo);
   W->off.assign(ns + 1, 0);
   W->plans.assign(ns, nullptr);
@@ -750,10 +753,11 @@ int wstack_build(sepw_wstack_s* W, Kernels* K, int ns, double w_lo, double w_hi,
   W->nimg = batch_images(K->N, ns);
   SEPW_TRY(dalloc(&W->img, (int64_t)W->nimg * K->N * K->N));
   uint32_t* count = nullptr;
-  double *cdev = nullptr, *us = nullptr, *vs = nullptr, *wsr = nullptr;
+  double *cdev = nullptr, *edev = nullptr, *us = nullptr, *vs = nullptr, *wsr = nullptr;
   auto cleanup = [&]() {
     dfree(count);
     dfree(cdev);
+    dfree(edev);
     dfree(us);
     dfree(vs);
     dfree(wsr);
@@ -764,8 +768,12 @@ int wstack_build(sepw_wstack_s* W, Kernels* K, int ns, double w_lo, double w_hi,
     SEPW_TRY(dalloc(&us, std::max<int64_t>(nvis, 1)));
     SEPW_TRY(dalloc(&vs, std::max<int64_t>(nvis, 1)));
     SEPW_TRY(dalloc(&wsr, std::max<int64_t>(nvis, 1)));
+    if (edges) {
+      SEPW_TRY(dalloc(&edev, ns + 1));
+      SEPW_TRY(hipMemcpyAsync(edev, edges, sizeof(double) * (ns + 1), hipMemcpyHostToDevice, s));
+    }
     SEPW_TRY(launch_fill_u32(count, 0u, ns, s));
-    SEPW_TRY(launch_slice_count(w, nvis, w_lo, inv_ds, ns, count, s));
+    SEPW_TRY(launch_slice_count(w, nvis, w_lo, inv_ds, ns, edev, count, s));
     std::vector<uint32_t> hc(ns);
     SEPW_TRY(hipMemcpyAsync(hc.data(), count, sizeof(uint32_t) * ns, hipMemcpyDeviceToHost, s));
     SEPW_TRY(hipStreamSynchronize(s));
@@ -776,8 +784,8 @@ int wstack_build(sepw_wstack_s* W, Kernels* K, int ns, double w_lo, double w_hi,
     }
     SEPW_TRY(hipMemcpyAsync(count, cur.data(), sizeof(uint32_t) * ns, hipMemcpyHostToDevice, s));
     SEPW_TRY(hipMemcpyAsync(cdev, W->centre.data(), sizeof(double) * ns, hipMemcpyHostToDevice, s));
-    SEPW_TRY(launch_slice_scatter(u, v, w, nvis, w_lo, inv_ds, ns, cdev, count, W->order, us, vs,
-                                  wsr, s));
+    SEPW_TRY(launch_slice_scatter(u, v, w, nvis, w_lo, inv_ds, ns, edev, cdev, count, W->order,
+                                  us, vs, wsr, s));
     int64_t dropped = 0;
     for (int j = 0; j < ns; ++j) {
       const int64_t n = W->off[j + 1] - W->off[j];
@@ -1633,12 +1641,82 @@ int sepw_wstack_create(sepw_kernels k, int32_t n_slices, double w_lo, double w_h
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   sepw_wstack_s* W = new (std::nothrow) sepw_wstack_s();
   if (!W) return SEPW_ERR_OOM;
-  int rc = wstack_build(W, k, n_slices, w_lo, w_hi, nvis, u, v, w, n_dropped, s);
+  int rc = wstack_build(W, k, n_slices, w_lo, w_hi, nullptr, nvis, u, v, w, n_dropped, s);
   if (rc != SEPW_OK) {
     destroy_wstack(W);
     return rc;
   }
   *out = W;
+  return SEPW_OK;
+}
+
+int sepw_wstack_create_edges(sepw_kernels k, int32_t n_slices, const double* edges, int64_t nvis,
+                             const double* u, const double* v, const double* w,
+                             int64_t* n_dropped, void* hip_stream, sepw_wstack* out) {
+  if (!out) return SEPW_ERR_ARG;
+  *out = nullptr;
+  if (!k || k->facet || n_slices < 1 || n_slices > kMaxSlices || !edges) return SEPW_ERR_ARG;
+  if (nvis < 0 || nvis > 2147483646LL) return SEPW_ERR_ARG;
+  if (nvis > 0 && (!u || !v || !w)) return SEPW_ERR_ARG;
+  double h = 0.0;
+  for (int j = 0; j <= n_slices; ++j)
+    if (!std::isfinite(edges[j])) return SEPW_ERR_ARG;
+  for (int j = 0; j < n_slices; ++j) {
+    if (!(edges[j] < edges[j + 1])) return SEPW_ERR_ARG;
+    h = std::max(h, (edges[j + 1] - edges[j]) * 0.5);
+  }
+  // the kernels' planes must span the residual range [-h, h] of the widest slice
+  if (std::fabs(k->w_lo + h) > 1e-12 * h || std::fabs(k->w_hi - h) > 1e-12 * h) return SEPW_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  sepw_wstack_s* W = new (std::nothrow) sepw_wstack_s();
+  if (!W) return SEPW_ERR_OOM;
+  int rc = wstack_build(W, k, n_slices, edges[0], edges[n_slices], edges, nvis, u, v, w, n_dropped,
+                        s);
+  if (rc != SEPW_OK) {
+    destroy_wstack(W);
+    return rc;
+  }
+  *out = W;
+  return SEPW_OK;
+}
+
+int sepw_wstack_density_edges(int64_t nvis, const double* w, int32_t n_slices, double w_lo,
+                              double w_hi, double* edges, void* hip_stream) {
+  if (!edges || n_slices < 1 || n_slices > kMaxSlices) return SEPW_ERR_ARG;
+  if (!std::isfinite(w_lo) || !std::isfinite(w_hi) || !(w_lo < w_hi)) return SEPW_ERR_ARG;
+  if (nvis < 0 || nvis > 2147483646LL || (nvis > 0 && !w)) return SEPW_ERR_ARG;
+  if (device_count() < 1) return SEPW_ERR_NO_DEVICE;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int nfine = kDensityBins;
+  std::vector<uint32_t> hc(nfine);
+  uint32_t* counts = nullptr;
+  SEPW_TRY(dalloc(&counts, nfine));
+  auto run = [&]() -> int {
+    SEPW_TRY(launch_fill_u32(counts, 0u, nfine, s));
+    SEPW_TRY(launch_w_hist(w, nvis, w_lo, (double)nfine / (w_hi - w_lo), nfine, counts, s));
+    SEPW_TRY(hipMemcpyAsync(hc.data(), counts, sizeof(uint32_t) * nfine, hipMemcpyDeviceToHost, s));
+    SEPW_TRY(hipStreamSynchronize(s));
+    return SEPW_OK;
+  };
+  const int rc = run();
+  dfree(counts);
+  if (rc != SEPW_OK) return rc;
+  // below[j] = finite visibilities in bins < j; edge k at the first j with
+  // below[j] ns >= k n, kept increasing with one bin left for each later slice
+  std::vector<int64_t> below(nfine + 1, 0);
+  for (int j = 0; j < nfine; ++j) below[j + 1] = below[j] + hc[j];
+  const int64_t n = below[nfine];
+  const double d = (w_hi - w_lo) / nfine;
+  edges[0] = w_lo;
+  edges[n_slices] = w_hi;
+  int search = 0, prev = 0;
+  for (int k = 1; k < n_slices; ++k) {
+    while (search < nfine && below[search] * n_slices < (int64_t)k * n) ++search;
+    const int jk = std::min(std::max(search, prev + 1), nfine - (n_slices - k));
+    const double t = (double)jk * d;
+    edges[k] = w_lo + t;
+    prev = jk;
+  }
   return SEPW_OK;
 }
 

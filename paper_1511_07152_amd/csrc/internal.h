@@ -26,6 +26,7 @@ constexpr int kItemMaxSlots = 8192;
 constexpr int kMaxRowBins = 4096;  // level-1 sort bins (rows of tiles, possibly grouped)
 constexpr int kL1Chunk = 10240;    // visibilities per workgroup in the level-1 passes
 constexpr int kMaxSlices = 4096;   // w-slices of the W-stacking hybrid
+constexpr int kDensityBins = 16384; // fine w bins of the density-adapted slice edges
 constexpr int kGroupChunks = 8;    // level-1 chunks per group of the run-offset scan
 // placement word of a kept visibility: row bin << kPlaceShift | its position in
 // its chunk's bin-ordered staging (kDropped for dropped visibilities)
@@ -287,12 +288,16 @@ hipError_t launch_item_counts(const uint2* tdesc, int ntx, int nty, int r8, int 
 hipError_t launch_items(const uint2* tdesc, const uint32_t* itoff, int ntx, int nty, int r8,
                         int item_slots, int4* items, hipStream_t s);
 // W-stacking hybrid (wstack.hip): slice partition, movement and image phase
+// edges: null for uniform slices (w_lo, inv_ds), else ns + 1 increasing edges
 hipError_t launch_slice_count(const double* w, int64_t nvis, double w_lo, double inv_ds, int ns,
-                              uint32_t* count, hipStream_t s);
+                              const double* edges, uint32_t* count, hipStream_t s);
 hipError_t launch_slice_scatter(const double* u, const double* v, const double* w, int64_t nvis,
-                                double w_lo, double inv_ds, int ns, const double* centre,
-                                uint32_t* cursor, uint32_t* order, double* us, double* vs,
-                                double* ws, hipStream_t s);
+                                double w_lo, double inv_ds, int ns, const double* edges,
+                                const double* centre, uint32_t* cursor, uint32_t* order,
+                                double* us, double* vs, double* ws, hipStream_t s);
+// counts[b] += finite w in bin b of nfine (<= kDensityBins) uniform bins of [w_lo, w_hi]
+hipError_t launch_w_hist(const double* w, int64_t nvis, double w_lo, double inv, int nfine,
+                         uint32_t* counts, hipStream_t s);
 hipError_t launch_slice_gather(const float2* vis, const float* weight, const uint32_t* order,
                                int64_t nvis, float2* out, hipStream_t s);
 hipError_t launch_slice_return(const float2* in, const uint32_t* order, int64_t nvis, float2* out,

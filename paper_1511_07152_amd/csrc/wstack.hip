@@ -1,5 +1,5 @@
 // W-stacking hybrid (Section 4.3): the visibilities are partitioned into
-// uniform w-slices; each slice is imaged with the separable W-projection path
+// w-slices; each slice is imaged with the separable W-projection path
 // on its residual w - w_s, and its image is corrected by the exact phase of
 // the slice centre, exp(2 pi i w_s (n - 1)), before the slice images are
 // summed (prediction: the model is multiplied by exp(-2 pi i w_s (n - 1))
@@ -9,7 +9,11 @@
 // n_s / (w_hi - w_lo) computed once on the host, each FP64 operation an
 // explicitly rounded IEEE operation in this order (so that the partition is
 // reproducible bit for bit); centres w_s = w_lo + (s + 1/2)(w_hi - w_lo)/n_s
-// come from the host.  Non-finite w goes to slice 0 with a non-finite
+// come from the host.  Non-uniform slices (Section 4.3 suggests narrow
+// slices where w is dense) come as increasing edges e_0 < ... < e_ns: slice
+// s holds e_s <= w < e_{s+1} (w below e_0 in slice 0, at or above e_ns in the
+// last), found by binary search, with centre (e_s + e_{s+1}) / 2 from the
+// host.  Non-finite w goes to slice 0 with a non-finite
 // residual, which the plane quantiser then drops.  n - 1 is evaluated as
 // -(l^2 + m^2) / (1 + n), equal to it and free of the cancellation near the
 // centre; the phase is reduced to [-1/2, 1/2] cycles before the FP64 sincos.
@@ -28,7 +32,18 @@ inline dim3 grid_for(int64_t n) {
   return dim3((unsigned)b);
 }
 
-__device__ inline int slice_of(double w, double w_lo, double inv_ds, int ns) {
+__device__ inline int slice_of(double w, double w_lo, double inv_ds, int ns,
+                               const double* __restrict__ edges) {
+  if (edges) {
+    if (!isfinite(w)) return 0;
+    int lo = 0, hi = ns;   // edges[lo] <= w < edges[hi], the outer edges open
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (w >= edges[mid]) lo = mid;
+      else hi = mid;
+    }
+    return lo;
+  }
   const double t = floor(__dmul_rn(__dsub_rn(w, w_lo), inv_ds));
   if (!isfinite(t)) return 0;
   return t < 0.0 ? 0 : (t > (double)(ns - 1) ? ns - 1 : (int)t);
@@ -38,13 +53,14 @@ __device__ inline int slice_of(double w, double w_lo, double inv_ds, int ns) {
 __global__ __launch_bounds__(kThreads) void slice_count_kernel(const double* __restrict__ w,
                                                                int64_t nvis, double w_lo,
                                                                double inv_ds, int ns,
+                                                               const double* __restrict__ edges,
                                                                uint32_t* __restrict__ count) {
   __shared__ uint32_t hist[kMaxSlices];
   for (int s = threadIdx.x; s < ns; s += kThreads) hist[s] = 0u;
   __syncthreads();
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < nvis;
        i += (int64_t)gridDim.x * kThreads)
-    atomicAdd(&hist[slice_of(w[i], w_lo, inv_ds, ns)], 1u);
+    atomicAdd(&hist[slice_of(w[i], w_lo, inv_ds, ns, edges)], 1u);
   __syncthreads();
   for (int s = threadIdx.x; s < ns; s += kThreads)
     if (hist[s]) atomicAdd(&count[s], hist[s]);
@@ -59,8 +75,8 @@ __global__ __launch_bounds__(kThreads) void slice_count_kernel(const double* __r
 constexpr int kScatterChunk = 16 * kThreads;
 __global__ __launch_bounds__(kThreads) void slice_scatter_kernel(
     const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
-    int64_t nvis, double w_lo, double inv_ds, int ns, const double* __restrict__ centre,
-    uint32_t* __restrict__ cursor, uint32_t* __restrict__ order, double* __restrict__ us,
+    int64_t nvis, double w_lo, double inv_ds, int ns, const double* __restrict__ edges,
+    const double* __restrict__ centre, uint32_t* __restrict__ cursor, uint32_t* __restrict__ order, double* __restrict__ us,
     double* __restrict__ vs, double* __restrict__ ws) {
   __shared__ uint32_t cnt[kMaxSlices];
   const int64_t i0 = (int64_t)blockIdx.x * kScatterChunk;
@@ -68,14 +84,14 @@ __global__ __launch_bounds__(kThreads) void slice_scatter_kernel(
   for (int s = threadIdx.x; s < ns; s += kThreads) cnt[s] = 0u;
   __syncthreads();
   for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads)
-    atomicAdd(&cnt[slice_of(w[i], w_lo, inv_ds, ns)], 1u);
+    atomicAdd(&cnt[slice_of(w[i], w_lo, inv_ds, ns, edges)], 1u);
   __syncthreads();
   for (int s = threadIdx.x; s < ns; s += kThreads)
     if (cnt[s]) cnt[s] = atomicAdd(&cursor[s], cnt[s]);   // this chunk's first position
   __syncthreads();
   for (int64_t i = i0 + threadIdx.x; i < i1; i += kThreads) {
     const double wi = w[i];
-    const int s = slice_of(wi, w_lo, inv_ds, ns);
+    const int s = slice_of(wi, w_lo, inv_ds, ns, edges);
     const uint32_t j = atomicAdd(&cnt[s], 1u);
     order[j] = (uint32_t)i;
     us[j] = u[i];
@@ -136,24 +152,57 @@ __global__ void slice_phase_kernel(const float2* __restrict__ in, float2* __rest
   }
 }
 
+// Counts of the finite w in nfine uniform bins of [w_lo, w_hi] (bin index
+// floor((w - w_lo) inv) clamped, each FP64 operation rounded as written; a
+// non-finite index counts in bin 0).  counts must be zero on entry.
+__global__ __launch_bounds__(kThreads) void w_hist_kernel(const double* __restrict__ w,
+                                                          int64_t nvis, double w_lo, double inv,
+                                                          int nfine,
+                                                          uint32_t* __restrict__ counts) {
+  __shared__ uint32_t hist[kDensityBins];
+  for (int b = threadIdx.x; b < nfine; b += kThreads) hist[b] = 0u;
+  __syncthreads();
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < nvis;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double x = w[i];
+    if (!isfinite(x)) continue;
+    const double t = floor(__dmul_rn(__dsub_rn(x, w_lo), inv));
+    const int b = !isfinite(t) ? 0 : (t < 0.0 ? 0 : (t > (double)(nfine - 1) ? nfine - 1 : (int)t));
+    atomicAdd(&hist[b], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nfine; b += kThreads)
+    if (hist[b]) atomicAdd(&counts[b], hist[b]);
+}
+
 }  // namespace
 
+hipError_t launch_w_hist(const double* w, int64_t nvis, double w_lo, double inv, int nfine,
+                         uint32_t* counts, hipStream_t s) {
+  if (nvis == 0) return hipSuccess;
+  int64_t b = (nvis + kThreads - 1) / kThreads;
+  if (b > 2048) b = 2048;   // per-workgroup LDS histograms: few workgroups, many visibilities each
+  hipLaunchKernelGGL(w_hist_kernel, dim3((unsigned)b), dim3(kThreads), 0, s, w, nvis, w_lo, inv,
+                     nfine, counts);
+  return hipGetLastError();
+}
+
 hipError_t launch_slice_count(const double* w, int64_t nvis, double w_lo, double inv_ds, int ns,
-                              uint32_t* count, hipStream_t s) {
+                              const double* edges, uint32_t* count, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
   hipLaunchKernelGGL(slice_count_kernel, grid_for(nvis), dim3(kThreads), 0, s, w, nvis, w_lo, inv_ds,
-                     ns, count);
+                     ns, edges, count);
   return hipGetLastError();
 }
 
 hipError_t launch_slice_scatter(const double* u, const double* v, const double* w, int64_t nvis,
-                                double w_lo, double inv_ds, int ns, const double* centre,
-                                uint32_t* cursor, uint32_t* order, double* us, double* vs,
-                                double* ws, hipStream_t s) {
+                                double w_lo, double inv_ds, int ns, const double* edges,
+                                const double* centre, uint32_t* cursor, uint32_t* order,
+                                double* us, double* vs, double* ws, hipStream_t s) {
   if (nvis == 0) return hipSuccess;
   const int64_t nb = (nvis + kScatterChunk - 1) / kScatterChunk;
   hipLaunchKernelGGL(slice_scatter_kernel, dim3((unsigned)nb), dim3(kThreads), 0, s, u, v, w, nvis,
-                     w_lo, inv_ds, ns, centre, cursor, order, us, vs, ws);
+                     w_lo, inv_ds, ns, edges, centre, cursor, order, us, vs, ws);
   return hipGetLastError();
 }
 

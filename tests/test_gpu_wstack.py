@@ -114,3 +114,79 @@ def test_wstack_arguments_checked(lib):
     empty = lib.WStack(K, d["ns"], d["w_lo"], d["w_hi"], z, z, z)
     img = empty.grid(torch.zeros(0, dtype=torch.complex64, device="cuda"), None)
     assert float(img.abs().max()) == 0.0
+
+
+# ---- non-uniform slices (Section 4.3: narrow where w is dense)
+
+EDGES = np.array([-2000.0, -700.0, -150.0, 0.0, 100.0, 900.0, 2000.0])
+
+
+def _make_edges(lib, d, edges):
+    h = np.max(np.diff(edges)) * 0.5
+    K = lib.Kernels(d["N"], d["fov"], d["S"], d["O"], d["P"], -h, h)
+    ws = lib.WStack(K, len(edges) - 1, 0.0, 0.0, dev(d["u"], torch.float64),
+                    dev(d["v"], torch.float64), dev(d["w"], torch.float64), edges=edges)
+    return K, ws
+
+
+def _args_edges(d, edges):
+    c1 = oracle.pswf.taper_c1(d["N"], d["fov"], d["S"])
+    return (d["N"], d["fov"], d["S"], d["O"], d["P"], len(edges) - 1, edges[0], edges[-1], c1)
+
+
+def test_nonuniform_slices_match_oracle(lib):
+    rng, d = _case(83, cells=31)
+    d["w"][:50] = rng.uniform(-2500.0, 2500.0, 50)     # some beyond the outer edges
+    K, ws = _make_edges(lib, d, EDGES)
+    q = oracle.wstack.bins(d["u"], d["v"], d["w"], d["N"], d["fov"], d["O"], d["S"], d["P"],
+                           len(EDGES) - 1, EDGES[0], EDGES[-1], edges=EDGES)
+    assert ws.n_dropped == int(q["dropped"].sum()) and ws.n_dropped > 0
+    img = ws.grid(dev(d["V"], torch.complex64), dev(d["W"], torch.float32), flags=lib.MUL_N)
+    want = oracle.wstack.image(d["u"], d["v"], d["w"], d["V"] * d["W"], *_args_edges(d, EDGES),
+                               n_power=1, edges=EDGES)
+    assert rel_rms(inner(img.cpu().numpy()), inner(want)) <= 1e-5
+    N = d["N"]
+    X = np.zeros((N, N), complex)
+    s = slice(N // 4, 3 * N // 4)
+    X[s, s] = rng.standard_normal((N // 2, N // 2)) + 1j * rng.standard_normal((N // 2, N // 2))
+    V = ws.degrid(dev(X, torch.complex64), flags=lib.DIV_N).cpu().numpy()
+    wantv = oracle.wstack.predict(d["u"], d["v"], d["w"], X, *_args_edges(d, EDGES), n_power=-1,
+                                  edges=EDGES)
+    assert rel_rms(V, wantv) <= 1e-5
+    assert np.all(V[q["dropped"]] == 0)
+
+
+def test_uniform_edges_equal_uniform_slices(lib):
+    rng, d = _case(84)
+    K, ws = _make(lib, d)
+    e = d["w_lo"] + np.arange(d["ns"] + 1) * (d["w_hi"] - d["w_lo"]) / d["ns"]
+    K2, ws2 = _make_edges(lib, d, e)
+    a = ws.grid(dev(d["V"], torch.complex64), None).cpu().numpy()
+    b = ws2.grid(dev(d["V"], torch.complex64), None).cpu().numpy()
+    assert rel_rms(inner(b), inner(a)) <= 1e-6
+
+
+def test_density_edges_match_oracle(lib):
+    rng = np.random.default_rng(85)
+    w = np.r_[rng.laplace(0.0, 300.0, 300_000), rng.uniform(-6000, 6000, 1000), np.nan, np.inf,
+              -np.inf, 4999.999, -5000.0]
+    wd = dev(w, torch.float64)
+    for ns in (1, 2, 7, 64, 1000):
+        got = lib.density_edges(wd, ns, -5000.0, 5000.0)
+        want = oracle.wstack.density_edges(w, ns, -5000.0, 5000.0, nfine=16384)
+        assert np.array_equal(got, want), ns
+
+
+def test_density_sliced_wstack_matches_oracle(lib):
+    # core-heavy w: density-adapted slices are narrow near 0
+    rng, d = _case(86)
+    d["w"] = np.clip(rng.laplace(0.0, 150.0, len(d["w"])), -1999.0, 1999.0)
+    e = lib.density_edges(dev(d["w"], torch.float64), 6, d["w_lo"], d["w_hi"])
+    assert np.array_equal(e, oracle.wstack.density_edges(d["w"], 6, d["w_lo"], d["w_hi"],
+                                                         nfine=16384))
+    assert e[3] - e[2] < (e[1] - e[0]) / 4
+    K, ws = _make_edges(lib, d, e)
+    img = ws.grid(dev(d["V"], torch.complex64), dev(d["W"], torch.float32), flags=lib.MUL_N)
+    want = oracle.wstack.image(d["u"], d["v"], d["w"], d["V"] * d["W"], *_args_edges(d, e),
+                               n_power=1, edges=e)
+    assert rel_rms(inner(img.cpu().numpy()), inner(want)) <= 1e-5

@@ -132,3 +132,18 @@ def test_null_handles_rejected(lib):
     assert lib.sepw_free_wsnap(None) == -1
     assert lib.sepw_free_kernels(None) == -1 and lib.sepw_free_plan(None) == -1
     assert lib.sepw_strerror(-1) == b"invalid argument"
+
+
+def test_wstack_edges_arguments_rejected(lib):
+    h = ctypes.c_void_p()
+    E = ctypes.c_double * 4
+    assert lib.sepw_wstack_create_edges(None, 3, E(-1.0, 0.0, 0.5, 1.0), 10, None, None, None,
+                                        None, None, ctypes.byref(h)) == -1
+    out = E()
+    assert lib.sepw_wstack_density_edges(10, None, 3, -1.0, 1.0, out, None) == -1      # null w
+    assert lib.sepw_wstack_density_edges(0, None, 0, -1.0, 1.0, out, None) == -1       # no slices
+    assert lib.sepw_wstack_density_edges(0, None, 3, 1.0, -1.0, out, None) == -1       # range
+    assert lib.sepw_wstack_density_edges(0, None, 3, -1.0, float("inf"), out, None) == -1
+    assert lib.sepw_wstack_density_edges(0, None, 3, -1.0, 1.0, None, None) == -1      # null out
+    if lib.sepw_device_count() == 0:
+        assert lib.sepw_wstack_density_edges(0, None, 3, -1.0, 1.0, out, None) == -2
