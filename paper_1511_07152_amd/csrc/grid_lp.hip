@@ -72,6 +72,10 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kLdsWaves = 16;   // waves per workgroup of the LDS-table launches
+// BF16 gridding holds hi and lo operand parts: with 12 waves per CU it gets
+// 168 registers and no spills (16 waves: 128 registers, 11 spilled, 12 %
+// slower at array scale)
+constexpr int lds_waves_grid(bool bf16) { return bf16 ? 12 : kLdsWaves; }
 constexpr int kWaves = 4;       // waves per workgroup when the tables stay in memory
 
 template <bool BF16>
@@ -380,7 +384,7 @@ __device__ __forceinline__ void grid_lp_item(const GridArgsLp& a, const GCtx& c0
 }
 
 template <int S, bool BF16, bool LDS>
-__global__ __launch_bounds__(64 * (LDS ? kLdsWaves : kWaves)) void grid_lp_kernel(GridArgsLp a) {
+__global__ __launch_bounds__(64 * (LDS ? lds_waves_grid(BF16) : kWaves)) void grid_lp_kernel(GridArgsLp a) {
   extern __shared__ float2 smem[];
   const int lane = threadIdx.x & 63;
   GCtx c;
@@ -504,9 +508,11 @@ __device__ __forceinline__ void dtaps(const DCtx& c, DOps& B) {
 // Pipeline of a work item: chunk n runs while the taps of n + 1 are read
 // (its record moved one step earlier) and the record of n + 2 is moved from
 // the batches.  The region of a tile is loaded when its first chunk becomes
-// n + 2, into a two-entry queue, and converted to MFMA operands when that
-// chunk becomes n (after the step, before the next load is queued, so the
-// queue holds at most the tiles of n + 1 and n + 2).
+// n + 1 and converted to MFMA operands when that chunk becomes n, so one raw
+// region is in flight.  (A two-entry queue of raw regions, loaded two chunks
+// ahead, made the compiler address its entries through a pointer chosen at
+// run time, which put the queue in scratch memory: 5 GB of scratch writes
+// per call at array scale and a third more time.)
 template <int S, bool BF16>
 __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, const DCtx& c0, int it) {
   constexpr int C = kRegion + 1 - S;
@@ -584,26 +590,8 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, const DCtx
       if (a.checker) f = -f;
     }
   };
-  // queue of raw regions: q1 (oldest), q2; nq entries, with their tile columns
-  float2 q1[4], q2[4];
-  int t1 = 0, t2 = 0, nq = 0;
-  auto push = [&](int tx) {
-    if (nq == 0) {
-      load_region(q1, tx);
-      t1 = tx;
-    } else {
-      load_region(q2, tx);
-      t2 = tx;
-    }
-    nq += 1;
-  };
-  auto pop = [&]() {
-    convert(q1, t1);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) q1[m] = q2[m];
-    t1 = t2;
-    nq -= 1;
-  };
+  // raw region of the next tile, loaded one chunk ahead
+  float2 q[4];
 
   // results of up to four chunks: lanes 16 j + col hold V[col] of chunk j of
   // the group, stored with one instruction (offset kOob: nothing to store)
@@ -659,19 +647,15 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, const DCtx
     cur = n1;
     n1 = n2;
     n2 = next_chunk(n2, tw, s_end, c.lane);
-    if (fresh) pop();
-    if (n2.ok && n2.tx != n1.tx) push(n2.tx);
+    if (fresh) convert(q, cur.tx);
+    if (n1.ok && n1.tx != cur.tx) load_region(q, n1.tx);
     return true;
   };
 
-  // the first tile's region is converted at once; later ones come through the queue
-  {
-    float2 g[4];
-    load_region(g, cur.tx);
-    if (n1.ok && n1.tx != cur.tx) push(n1.tx);
-    if (n2.ok && n2.tx != n1.tx) push(n2.tx);
-    convert(g, cur.tx);
-  }
+  // the first tile's region is converted at once; later ones are loaded one chunk ahead
+  load_region(q, cur.tx);
+  convert(q, cur.tx);
+  if (n1.ok && n1.tx != cur.tx) load_region(q, n1.tx);
   DOps A, B;
   A.rec = dkey(c, cur, bt);
   dtaps<BF16>(c, A);
@@ -716,7 +700,7 @@ void launch_grid_s(const GridArgsLp& a, int lds_bytes, int n_cu, hipStream_t s) 
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&grid_lp_kernel<S, BF16, true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     hipLaunchKernelGGL((grid_lp_kernel<S, BF16, true>), dim3((unsigned)n_cu),
-                       dim3(64 * kLdsWaves), lds_bytes, s, a);
+                       dim3(64 * lds_waves_grid(BF16)), lds_bytes, s, a);
   } else {
     hipLaunchKernelGGL((grid_lp_kernel<S, BF16, false>), dim3((unsigned)(4 * n_cu)),
                        dim3(64 * kWaves), 0, s, a);
