@@ -44,7 +44,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_grid_degrid_array4096_fp32.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_grid_degrid_array4096.md")
 
 
 def measured_traffic(kernel):
