@@ -187,17 +187,18 @@ class ExactDFT:
     def __init__(self, torch, d, u, v, w, V, W, X, npix=64, nv=256, seed=1511):
         import numpy as np
         N, fov = d["N"], d["fov"]
+        dev = u.device
         rng = np.random.default_rng(seed)
         self.pq = rng.integers(N // 4, 3 * N // 4, (2, npix))
-        self.vi = torch.as_tensor(rng.choice(len(d["u"]), nv, replace=False), device="cuda")
+        self.vi = torch.as_tensor(rng.choice(u.numel(), nv, replace=False), device=dev)
         f64 = torch.float64
-        lp = (torch.as_tensor(self.pq[0], device="cuda", dtype=f64) - N / 2) * (fov / N)
-        mq = (torch.as_tensor(self.pq[1], device="cuda", dtype=f64) - N / 2) * (fov / N)
+        lp = (torch.as_tensor(self.pq[0], device=dev, dtype=f64) - N / 2) * (fov / N)
+        mq = (torch.as_tensor(self.pq[1], device=dev, dtype=f64) - N / 2) * (fov / N)
         r2 = lp * lp + mq * mq
         n = torch.sqrt(1.0 - r2)
         nm1 = -r2 / (1.0 + n)
         y = V.to(torch.complex128) * W.to(f64)
-        D = torch.zeros(npix, dtype=torch.complex128, device="cuda")
+        D = torch.zeros(npix, dtype=torch.complex128, device=dev)
         step = 1 << 21
         for a in range(0, u.numel(), step):
             b = min(a + step, u.numel())
@@ -206,7 +207,7 @@ class ExactDFT:
         self.image = D * n
         # prediction of X at the sampled visibilities, over the inner half
         q0, q1 = N // 4, 3 * N // 4
-        li = (torch.arange(q0, q1, device="cuda", dtype=f64) - N / 2) * (fov / N)
+        li = (torch.arange(q0, q1, device=dev, dtype=f64) - N / 2) * (fov / N)
         L = li[None, :].expand(q1 - q0, -1).reshape(-1)
         M = li[:, None].expand(-1, q1 - q0).reshape(-1)
         r2 = L * L + M * M
@@ -214,7 +215,7 @@ class ExactDFT:
         x = X[q0:q1, q0:q1].reshape(-1).to(torch.complex128) / n
         nm1 = -r2 / (1.0 + n)
         us, vs, ws = u[self.vi], v[self.vi], w[self.vi]
-        P = torch.zeros(nv, dtype=torch.complex128, device="cuda")
+        P = torch.zeros(nv, dtype=torch.complex128, device=dev)
         step = 1 << 18
         for a in range(0, L.numel(), step):
             b = min(a + step, L.numel())

@@ -152,7 +152,13 @@ def test_image_matches_oracle(lib, flags, npow):
     f = getattr(lib, flags) if flags else 0
     img = lib.grid(plan, dev(d["V"], torch.complex64), dev(d["W"], torch.float32), flags=f).cpu().numpy()
     want = _oracle(d, plan).image(d["V"], d["W"], n_power=npow)
-    assert rel_rms(inner(img), inner(want)) <= 1e-5
+    e_in = rel_rms(inner(img), inner(want))
+    # the full image as well: at the edges 1 / (c1 c1) lifts the FP32
+    # rounding of the grid far above the tapered signal, so only the inner
+    # half carries the 1e-5 bound; the full-image figure is reported
+    e_full = rel_rms(img, want)
+    print("image (%s): inner half %.2e, full image %.2e" % (flags or "plain", e_in, e_full))
+    assert e_in <= 1e-5 and np.isfinite(e_full)
 
 
 def test_image_tracks_dft(lib):
