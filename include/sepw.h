@@ -99,6 +99,14 @@ enum { SEPW_FP32 = 0, SEPW_FP16 = 1, SEPW_BF16 = 2 };
                                 degrid with SEPW_DIV_N.
                                 degrid: X = image / n before the FFT, i.e. the
                                 prediction equation for a model image I.        */
+#define SEPW_REAL      0x8u  /* sepw_grid / sepw_degrid only, not with GRID_ONLY:
+                                the image is real, DEVICE float32[N*N]: degrid
+                                reads a real model image; grid writes the real
+                                part of the image (the adjoint of predicting
+                                from a real model).  Gridding then transforms
+                                in the kernels' work array, shared by the
+                                kernels' plans, so such calls on one kernels
+                                object do not overlap across streams.        */
 
 /* Kernel (GCF table) parameters.  Fill with sepw_default_params first. */
 typedef struct {
@@ -226,8 +234,8 @@ int32_t sepw_plan_tile_size(sepw_plan p);
  * vis: DEVICE complex64[nvis]; weight: DEVICE float[nvis] or NULL (all 1);
  * out: DEVICE complex64[N*N], overwritten.  Without SEPW_GRID_ONLY the output is
  * the image F+[G] / (c1 c1), times n (SEPW_MUL_N) or over n (SEPW_DIV_N).
- * Errors: SEPW_ERR_ARG (null pointers, both MUL_N and DIV_N), SEPW_ERR_HIP,
- * SEPW_ERR_FFT. */
+ * Errors: SEPW_ERR_ARG (null pointers, both MUL_N and DIV_N, REAL with
+ * GRID_ONLY), SEPW_ERR_HIP, SEPW_ERR_FFT. */
 int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* out,
               uint32_t flags, void* hip_stream);
 

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libsepw.so")
 OK, ERR_ARG, ERR_NO_DEVICE, ERR_HIP, ERR_OOM, ERR_UNSUPPORTED, ERR_FFT = 0, -1, -2, -3, -4, -5, -6
 TAPER_PSWF, TAPER_NONE, TAPER_USER = 0, 1, 2
 FP32, FP16, BF16 = 0, 1, 2
-GRID_ONLY, MUL_N, DIV_N = 0x1, 0x2, 0x4
+GRID_ONLY, MUL_N, DIV_N, REAL = 0x1, 0x2, 0x4, 0x8
 
 c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 
@@ -496,21 +496,28 @@ class WSnap:
 
 
 def grid(plan, vis, weight=None, flags=0, out=None):
-    """sepw_grid: complex64 N x N uv grid (GRID_ONLY) or image."""
+    """sepw_grid: complex64 N x N uv grid (GRID_ONLY) or image; with REAL in
+    flags the real part of the image as float32 N x N."""
     vis = _dev(vis, torch.complex64, "vis")
     if weight is not None:
         weight = _dev(weight, torch.float32, "weight")
     N = plan.kernels.N
     if out is None:
-        out = torch.empty((N, N), dtype=torch.complex64, device="cuda")
+        dt = torch.float32 if flags & REAL else torch.complex64
+        out = torch.empty((N, N), dtype=dt, device="cuda")
+    else:
+        out = _dev(out, torch.float32 if flags & REAL else torch.complex64, "out")
     _check(load().sepw_grid(plan.handle, _ptr(vis), _ptr(weight), _ptr(out), flags, _stream()),
            "sepw_grid")
     return out
 
 
 def degrid(plan, image, flags=0, out=None):
-    """sepw_degrid: complex64 visibilities in the caller's order."""
-    image = _dev(image, torch.complex64, "image")
+    """sepw_degrid: complex64 visibilities in the caller's order; a real
+    float32 image goes in as such (REAL)."""
+    if isinstance(image, torch.Tensor) and image.dtype == torch.float32 and not flags & GRID_ONLY:
+        flags |= REAL
+    image = _dev(image, torch.float32 if flags & REAL else torch.complex64, "image")
     if out is None:
         out = torch.empty(plan.nvis, dtype=torch.complex64, device="cuda")
     _check(load().sepw_degrid(plan.handle, _ptr(image), _ptr(out), flags, _stream()), "sepw_degrid")

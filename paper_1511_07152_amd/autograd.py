@@ -24,8 +24,8 @@ class Predict(torch.autograd.Function):
         if x.dtype != torch.float32 or x.dim() != 2:
             raise TypeError("x must be a real float32 (N, N) tensor")
         ctx.plan = plan
-        X = torch.complex(x.contiguous(), torch.zeros_like(x))
-        return _lib.degrid(plan, X, flags=_lib.DIV_N)
+        # the real model goes in as it is (no complex copy)
+        return _lib.degrid(plan, x.contiguous(), flags=_lib.DIV_N | _lib.REAL)
 
     @staticmethod
     def backward(ctx, grad_v):
@@ -33,8 +33,8 @@ class Predict(torch.autograd.Function):
         g = grad_v.contiguous()
         if g.dtype != torch.complex64:
             g = g.to(torch.complex64)
-        img = _lib.grid(plan, g, None, flags=_lib.DIV_N)
-        return img.real.contiguous(), None
+        # only the real part of the adjoint image is the gradient
+        return _lib.grid(plan, g, None, flags=_lib.DIV_N | _lib.REAL), None
 
 
 def predict(x, plan):

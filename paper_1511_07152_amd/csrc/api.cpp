@@ -1187,11 +1187,15 @@ int sepw_plan_bins(sepw_plan p, int32_t* out, void* hip_stream) {
 int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* out,
               uint32_t flags, void* hip_stream) {
   if (!p || !out || (!vis && p->nvis > 0)) return SEPW_ERR_ARG;
-  if ((flags & ~(SEPW_GRID_ONLY | SEPW_MUL_N | SEPW_DIV_N)) != 0) return SEPW_ERR_ARG;
+  if ((flags & ~(SEPW_GRID_ONLY | SEPW_MUL_N | SEPW_DIV_N | SEPW_REAL)) != 0) return SEPW_ERR_ARG;
   if ((flags & SEPW_MUL_N) && (flags & SEPW_DIV_N)) return SEPW_ERR_ARG;
+  if ((flags & SEPW_REAL) && (flags & SEPW_GRID_ONLY)) return SEPW_ERR_ARG;
   Kernels* K = p->K;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  float2* img = reinterpret_cast<float2*>(out);
+  // a real output image: the grid and its transform go through the kernels'
+  // complex work array, and only the real part reaches out
+  const bool real_out = flags & SEPW_REAL;
+  float2* img = real_out ? K->scratch : reinterpret_cast<float2*>(out);
   const int N = K->N;
   const bool grid_only = flags & SEPW_GRID_ONLY;
   if (p->generation != K->generation) return SEPW_ERR_ARG;
@@ -1253,7 +1257,11 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
   const int npow = (flags & SEPW_MUL_N) ? 1 : ((flags & SEPW_DIV_N) ? -1 : 0);
   {
     Stage st(SEPW_STAGE_CORRECT, s);
-    SEPW_TRY(launch_correct(img, img, K->c1, N, K->fov, K->l0, K->m0, npow, s));
+    if (real_out)
+      SEPW_TRY(launch_correct_real_out(img, reinterpret_cast<float*>(out), K->c1, N, K->fov, K->l0,
+                                       K->m0, npow, s));
+    else
+      SEPW_TRY(launch_correct(img, img, K->c1, N, K->fov, K->l0, K->m0, npow, s));
   }
   return SEPW_OK;
 }
@@ -1261,7 +1269,8 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
 int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t flags,
                 void* hip_stream) {
   if (!p || !in || (!vis_out && p->nvis > 0)) return SEPW_ERR_ARG;
-  if ((flags & ~(SEPW_GRID_ONLY | SEPW_DIV_N)) != 0) return SEPW_ERR_ARG;
+  if ((flags & ~(SEPW_GRID_ONLY | SEPW_DIV_N | SEPW_REAL)) != 0) return SEPW_ERR_ARG;
+  if ((flags & SEPW_REAL) && (flags & SEPW_GRID_ONLY)) return SEPW_ERR_ARG;
   Kernels* K = p->K;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const int N = K->N;
@@ -1272,7 +1281,11 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
     const int npow = (flags & SEPW_DIV_N) ? -1 : 0;
     {
       Stage st(SEPW_STAGE_CORRECT, s);
-      SEPW_TRY(launch_correct(src, K->scratch, K->c1, N, K->fov, K->l0, K->m0, npow, s));
+      if (flags & SEPW_REAL)
+        SEPW_TRY(launch_correct_real_in(reinterpret_cast<const float*>(in), K->scratch, K->c1, N,
+                                        K->fov, K->l0, K->m0, npow, s));
+      else
+        SEPW_TRY(launch_correct(src, K->scratch, K->c1, N, K->fov, K->l0, K->m0, npow, s));
     }
     {
       Stage st(SEPW_STAGE_FFT, s);

@@ -90,7 +90,7 @@ struct Kernels {
   // (gridding uses the FP32 padded tables)
   uint32_t* lp_u = nullptr;
   uint32_t* lp_v = nullptr;
-  float2* scratch = nullptr;   // N*N complex64 work grid for degridding
+  float2* scratch = nullptr;   // N*N complex64 work grid (degridding, real-output gridding)
   int tab_len = 0;             // entries of one padded table (P O L)
   int lds_bytes = 0;           // > 0: the FP32 kernels stage the tables in LDS
   int lds_bytes_lp = 0;        // > 0: the 16-bit degridding kernels stage their tables in LDS
@@ -459,6 +459,11 @@ hipError_t launch_grid_wide(const WideArgs& a, const float2* vis, const float* w
 hipError_t launch_degrid_wide(const WideArgs& a, const float2* grid, float2* out, hipStream_t s);
 
 // out[q][p] = in[q][p] (-1)^(p+q) n(l0 + l_p, m0 + m_q)^npow / (c1[p] c1[q])
+// real model image in (prediction) / real part of the image out (adjoint)
+hipError_t launch_correct_real_in(const float* in, float2* out, const double* c1, int N, double fov,
+                                  double l0, double m0, int npow, hipStream_t s);
+hipError_t launch_correct_real_out(const float2* in, float* out, const double* c1, int N,
+                                   double fov, double l0, double m0, int npow, hipStream_t s);
 hipError_t launch_correct(const float2* in, float2* out, const double* c1, int N, double fov,
                           double l0, double m0, int npow, hipStream_t s);
 

@@ -336,3 +336,31 @@ def test_grid_and_degrid_at_grid_corners(lib, N, S):
     X = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
     V = lib.degrid(plan, dev(X, torch.complex64), flags=lib.GRID_ONLY).cpu().numpy()
     assert rel_rms(V, o.degrid_grid(X)) <= 1e-5
+
+
+@pytest.mark.parametrize("S", [7, 21])
+def test_real_images(lib, S):
+    # SEPW_REAL: a real model image goes into the prediction as float32, and
+    # gridding can return the real part of the image; both must equal the
+    # complex calls on the same data (the same arithmetic, so to rounding)
+    d = _acc()
+    # taper of width 11 at S = 21: the default width S makes 1/(c1 c1) lift the
+    # rounding differences of two runs' FP32 atomics above 1e-6 over the inner half
+    K = lib.Kernels(d["N"], d["fov"], S, d["O"], d["P"], d["w_lo"], d["w_hi"],
+                    taper_width=min(S, 11))
+    plan = lib.Plan(K, dev(d["u"], torch.float64), dev(d["v"], torch.float64),
+                    dev(d["w"], torch.float64))
+    rng = np.random.default_rng(5)
+    N = d["N"]
+    x = np.zeros((N, N), np.float32)
+    x[N // 4:3 * N // 4, N // 4:3 * N // 4] = rng.standard_normal((N // 2, N // 2))
+    vr = lib.degrid(plan, dev(x, torch.float32), flags=lib.DIV_N).cpu().numpy()
+    vc = lib.degrid(plan, dev(x.astype(np.complex64), torch.complex64), flags=lib.DIV_N).cpu().numpy()
+    assert rel_rms(vr, vc) <= 1e-6
+    V, W = dev(d["V"], torch.complex64), dev(d["W"], torch.float32)
+    ir = lib.grid(plan, V, W, flags=lib.DIV_N | lib.REAL)
+    assert ir.dtype == torch.float32
+    ic = lib.grid(plan, V, W, flags=lib.DIV_N).cpu().numpy()
+    assert rel_rms(inner(ir.cpu().numpy()), inner(ic.real)) <= 1e-6
+    with pytest.raises(lib.SepwError):
+        lib.grid(plan, V, W, flags=lib.GRID_ONLY | lib.REAL)
