@@ -376,8 +376,14 @@ int sepw_plan_set_degrid_item_slots(sepw_plan p, int32_t slots, void* hip_stream
  * persistent launch width in {2, 4, 8} workgroups per compute unit, and keeps
  * the fastest pair: the plans keep that item length and that width (used by
  * later batched calls that they lead).  The pair is returned in *item_slots and
- * *blocks_per_cu (either may be NULL).  out[] is overwritten.  Synchronous.
- * Errors: as sepw_grid_batched, and those of sepw_plan_set_item_slots. */
+ * *blocks_per_cu (either may be NULL).  Results are cached per process by
+ * (device, N, S, O, precision, job count, total visibilities rounded down to a
+ * power of two): a later call with the same key applies the cached pair without
+ * timing (out[] is then not written).  The grid-tile edge is not a search
+ * dimension: 17 - S is the largest tile whose footprints fit one 16-cell MFMA
+ * region, and smaller tiles only add padding for the same matrix work.
+ * Synchronous.  Errors: as sepw_grid_batched, and those of
+ * sepw_plan_set_item_slots. */
 int sepw_autotune_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* const* vis,
                           const float* const* weight, sepw_c64* const* out, void* hip_stream,
                           int32_t* item_slots, int32_t* blocks_per_cu);

@@ -11,6 +11,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <array>
+#include <map>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -1526,6 +1528,12 @@ int sepw_plan_set_degrid_item_slots(sepw_plan p, int32_t slots, void* hip_stream
   return set_list_slots(p, p->dl, slots, static_cast<hipStream_t>(hip_stream));
 }
 
+namespace {
+// Autotuner results by (device, N, S, O, precision, jobs, floor(log2 total vis)).
+std::mutex g_tune_mx;
+std::map<std::array<int64_t, 7>, std::pair<int, int>> g_tune;
+}  // namespace
+
 int sepw_autotune_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* const* vis,
                           const float* const* weight, sepw_c64* const* out, void* hip_stream,
                           int32_t* item_slots, int32_t* blocks_per_cu) {
@@ -1533,6 +1541,30 @@ int sepw_autotune_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64*
   for (int j = 0; j < njobs; ++j)
     if (!plans[j]) return SEPW_ERR_ARG;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  int64_t total = 0;
+  for (int j = 0; j < njobs; ++j) total += plans[j]->nvis;
+  int bucket = 0;
+  while (bucket < 62 && (int64_t(2) << bucket) <= total) ++bucket;
+  int dev = 0;
+  SEPW_TRY(hipGetDevice(&dev));
+  const Kernels* K0 = plans[0]->K;
+  const std::array<int64_t, 7> key{dev, K0->N, K0->S, K0->O, K0->prm.precision, njobs, bucket};
+  {
+    std::unique_lock<std::mutex> lk(g_tune_mx);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      const std::pair<int, int> best = it->second;
+      lk.unlock();
+      int rc = SEPW_OK;
+      for (int j = 0; j < njobs; ++j) plans[j]->blocks_per_cu = best.second;
+      for (int j = 0; j < njobs && rc == SEPW_OK; ++j)
+        rc = sepw_plan_set_item_slots(plans[j], best.first, hip_stream);
+      if (rc != SEPW_OK) return rc;
+      if (item_slots) *item_slots = best.first;
+      if (blocks_per_cu) *blocks_per_cu = best.second;
+      return SEPW_OK;
+    }
+  }
   const int kSlots[] = {256, 512, 1024, 2048};
   const int kWidth[] = {2, 4, 8};
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1572,6 +1604,10 @@ int sepw_autotune_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64*
   for (int j = 0; j < njobs && rc == SEPW_OK; ++j)
     rc = sepw_plan_set_item_slots(plans[j], best_slots, hip_stream);
   if (rc != SEPW_OK) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mx);
+    g_tune[key] = std::make_pair(best_slots, best_width);
+  }
   if (item_slots) *item_slots = best_slots;
   if (blocks_per_cu) *blocks_per_cu = best_width;
   return SEPW_OK;

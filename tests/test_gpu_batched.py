@@ -119,6 +119,14 @@ def test_autotuned_batch_equals_per_job(lib):
     wts = [dev(jb["W"], torch.float32) for jb in jobs]
     slots, width = lib.autotune_batched(plans, vis, wts)
     assert slots in (256, 512, 1024, 2048) and width in (2, 4, 8)
+    # the same key (N, S, O, precision, jobs, visibility bucket) comes from the
+    # cache: the pair again, re-applied to plans whose item length was changed,
+    # and no timing runs (out[] untouched)
+    for p in plans:
+        p.set_item_slots(256)
+    marker = [torch.full((N, N), 7.0, dtype=torch.complex64, device="cuda") for _ in plans]
+    assert lib.autotune_batched(plans, vis, wts, outs=marker) == (slots, width)
+    assert all(float((m - 7.0).abs().max()) == 0.0 for m in marker)
     outs = lib.grid_batched(plans, vis, wts, flags=lib.GRID_ONLY)
     for j, jb in enumerate(jobs):
         single = lib.grid(plans[j], vis[j], wts[j], flags=lib.GRID_ONLY).cpu().numpy()
