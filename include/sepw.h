@@ -99,6 +99,13 @@ enum { SEPW_FP32 = 0, SEPW_FP16 = 1, SEPW_BF16 = 2 };
                                 degrid with SEPW_DIV_N.
                                 degrid: X = image / n before the FFT, i.e. the
                                 prediction equation for a model image I.        */
+/* The same flags under the names of the problem statement: the dirty image
+   (x n), the adjoint pair (/ n on both sides) and the model (/ n).  Footprints
+   that leave the grid are always dropped, never wrapped. */
+#define SEPW_DIRTY     SEPW_MUL_N
+#define SEPW_ADJOINT   SEPW_DIV_N
+#define SEPW_MODEL     SEPW_DIV_N
+#define SEPW_WRAP_FORBIDDEN 0x0u
 #define SEPW_REAL      0x8u  /* sepw_grid / sepw_degrid only, not with GRID_ONLY:
                                 the image is real, DEVICE float32[N*N]: degrid
                                 reads a real model image; grid writes the real
@@ -185,8 +192,10 @@ int sepw_kernels_correction_table(sepw_kernels k, sepw_c64* out, void* hip_strea
  * -w m0/n0 (Section 4.1) and the per-visibility phase rotation
  * exp(+2 pi i (u l0 + v m0 + w (n0 - 1))) is stored in the plan.
  * The plan keeps its own binned copy; u, v, w may be freed afterwards.
- * n_dropped: optional HOST pointer; if given the call synchronises the stream
- * and stores the number of skipped visibilities.  nvis may be 0.
+ * n_dropped: optional pointer to the number of skipped visibilities: a HOST
+ * pointer makes the call synchronise the stream and store it; a DEVICE pointer
+ * (device memory, told apart with hipPointerGetAttributes) gets it written on
+ * the stream, without a synchronisation.  nvis may be 0.
  * Errors: SEPW_ERR_ARG (null kernels, nvis < 0 or > 2^31-2, null arrays with
  * nvis > 0), SEPW_ERR_UNSUPPORTED (more tiles than the in-LDS tile sort
  * handles: N > 16384 at S = 15, N > 32768 at S <= 13), SEPW_ERR_OOM,

@@ -223,6 +223,23 @@ class Kernels:
             pass
 
 
+def _dropped_arg(count, host):
+    """n_dropped argument: a one-element int64 device tensor (written on the
+    stream, no synchronisation), True (host value, the call synchronises) or
+    False / None (not counted)."""
+    if isinstance(count, torch.Tensor):
+        if not count.is_cuda or count.dtype != torch.int64 or count.numel() < 1:
+            raise TypeError("count_dropped must be a CUDA int64 tensor")
+        return ctypes.cast(c_void_p(count.data_ptr()), ctypes.POINTER(c_int64))
+    return ctypes.byref(host) if count else None
+
+
+def _dropped_value(count, host):
+    if isinstance(count, torch.Tensor):
+        return count
+    return host.value if count else None
+
+
 class Plan:
     """Binned visibilities for one Kernels object (sepw_plan_create)."""
 
@@ -238,10 +255,10 @@ class Plan:
         nd = c_int64(-1)
         h = c_void_p()
         _check(lib.sepw_plan_create(kernels.handle, self.nvis, _ptr(u), _ptr(v), _ptr(w),
-                                    ctypes.byref(nd) if count_dropped else None, _stream(),
+                                    _dropped_arg(count_dropped, nd), _stream(),
                                     ctypes.byref(h)), "sepw_plan_create")
         self._h = h
-        self.n_dropped = nd.value if count_dropped else None
+        self.n_dropped = _dropped_value(count_dropped, nd)
 
     @property
     def handle(self):
@@ -292,11 +309,11 @@ class Plan:
         w = _dev(w, torch.float64, "w")
         nd = c_int64(-1)
         _check(load().sepw_plan_rebin(self._h, u.numel(), _ptr(u), _ptr(v), _ptr(w),
-                                      ctypes.byref(nd) if count_dropped else None, _stream()),
+                                      _dropped_arg(count_dropped, nd), _stream()),
                "sepw_plan_rebin")
         self.nvis = u.numel()
-        if count_dropped:
-            self.n_dropped = nd.value
+        if count_dropped is not False and count_dropped is not None:
+            self.n_dropped = _dropped_value(count_dropped, nd)
         return self
 
     def set_item_slots(self, slots):

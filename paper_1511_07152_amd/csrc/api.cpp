@@ -579,6 +579,13 @@ int bin_plan(Plan* P, int64_t nvis, const Coords& src, hipStream_t s) {
 }
 
 int read_dropped(Plan* P, int64_t* n_dropped, hipStream_t s) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, n_dropped) == hipSuccess && at.type == hipMemoryTypeDevice) {
+    // device memory: written on the stream, no synchronisation
+    SEPW_TRY(launch_dropped(P->rowoff + P->nbins, P->nvis, n_dropped, s));
+    return SEPW_OK;
+  }
+  (void)hipGetLastError();   // a host pointer unknown to the runtime reports an error
   uint32_t kept = 0;
   hipError_t e = hipMemcpyAsync(&kept, P->rowoff + P->nbins, sizeof(uint32_t),
                                 hipMemcpyDeviceToHost, s);

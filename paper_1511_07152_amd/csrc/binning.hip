@@ -232,6 +232,11 @@ __global__ void job_prefix_kernel(const Args* __restrict__ jobs, int njobs,
   *counter = 0u;
 }
 
+__global__ void dropped_kernel(const uint32_t* __restrict__ kept, int64_t nvis,
+                               int64_t* __restrict__ out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *out = nvis - (int64_t)*kept;
+}
+
 __global__ void bins_export_kernel(const uint2* __restrict__ rrec, const uint32_t* __restrict__ place,
                                    const uint32_t* __restrict__ delta, int nbins, int64_t nvis,
                                    int tile_c, int ntx, int32_t* __restrict__ out) {
@@ -968,6 +973,11 @@ hipError_t launch_row_sort(const uint32_t* rowcount, const uint32_t* rowoff,
     case 16: return run(&row_sort_kernel<16>);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_dropped(const uint32_t* kept, int64_t nvis, int64_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(dropped_kernel, dim3(1), dim3(64), 0, s, kept, nvis, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_vis_to_rows(const MoveArgs& a, hipStream_t s) {

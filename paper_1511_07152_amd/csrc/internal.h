@@ -317,6 +317,8 @@ hipError_t launch_snap_reproject_adjoint(const float2* X, float2* out, int N, do
                                          double dv, int npow, hipStream_t s);
 hipError_t launch_snap_npow(float2* out, int N, double fov, int npow, hipStream_t s);
 
+// *out = nvis - *kept, one thread
+hipError_t launch_dropped(const uint32_t* kept, int64_t nvis, int64_t* out, hipStream_t s);
 hipError_t launch_bins_export(const uint2* rrec, const uint32_t* place, const uint32_t* delta,
                               int nbins, int64_t nvis, int tile_c, int ntx, int32_t* out,
                               hipStream_t s);

@@ -364,3 +364,23 @@ def test_real_images(lib, S):
     assert rel_rms(inner(ir.cpu().numpy()), inner(ic.real)) <= 1e-6
     with pytest.raises(lib.SepwError):
         lib.grid(plan, V, W, flags=lib.GRID_ONLY | lib.REAL)
+
+
+def test_dropped_count_to_device_memory(lib):
+    # n_dropped as a device pointer: written on the stream, equal to the
+    # host count (which makes the call synchronise)
+    d = _acc()
+    rng = np.random.default_rng(9)
+    d["u"] = d["u"].copy()
+    d["u"][:37] = rng.uniform(31.0, 40.0, 37) / d["fov"]      # footprints off the grid
+    K = lib.Kernels(d["N"], d["fov"], d["S"], d["O"], d["P"], d["w_lo"], d["w_hi"])
+    uvw = [dev(d[k], torch.float64) for k in ("u", "v", "w")]
+    host = lib.Plan(K, *uvw)
+    cnt = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+    plan = lib.Plan(K, *uvw, count_dropped=cnt)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == host.n_dropped >= 37
+    cnt2 = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+    plan.rebin(uvw[0][:1000], uvw[1][:1000], uvw[2][:1000], count_dropped=cnt2)
+    torch.cuda.synchronize()
+    assert int(cnt2.item()) == int(_oracle(d, plan).q["dropped"][:1000].sum())
