@@ -56,8 +56,9 @@
  * overlap in time (its scratch and FFT plan are shared).  A batched call
  * (sepw_grid_batched, sepw_autotune_batched) keeps its job table, work
  * counter and launch width in its first plan, and the W-stacking and
- * W-snapshot calls in their first plan: calls led by different plans share
- * nothing and may overlap on different streams.
+ * W-snapshot calls in their first plan: there is no process-wide batch state,
+ * so batched calls whose plans and kernels objects are distinct may overlap
+ * on different streams.
  *
  * Errors: every call returns SEPW_OK or a negative code; no exception crosses
  * the ABI.  Arguments are validated on the host before any device work, so a
