@@ -269,12 +269,14 @@ def wstack_form(_lib, torch, d, u, v, w, V, W, model, steps, exact):
     ws.close()
     K.close()
     # the same number of slices with density-adapted edges (about equal
-    # counts: narrow near w = 0, wide at large |w|), one residual table set
-    # over the widest slice
+    # counts: narrow near w = 0, wide at large |w|), each slice with residual
+    # tables on its own range (the kernels' w range is not used)
     edges = _lib.density_edges(w, ns, d["w_lo"], d["w_hi"])
-    hd = float(max(edges[1:] - edges[:-1])) * 0.5
-    K = _lib.Kernels(N, fov, S, O, P, -hd, hd)
+    K = _lib.Kernels(N, fov, S, O, P, d["w_lo"], d["w_hi"])
+    t = time.perf_counter()
     ws = _lib.WStack(K, ns, 0.0, 0.0, u, v, w, edges=edges)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t
     step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -286,6 +288,7 @@ def wstack_form(_lib, torch, d, u, v, w, V, W, model, steps, exact):
     res["density_edges"] = {
         "ms_per_step": round(ms, 3), "Mvis_per_s": round(ws.nvis / (ms * 1e-3) / 1e6, 2),
         "narrowest_slice": round(float(min(widths)), 1), "widest_slice": round(float(max(widths)), 1),
+        "create_s": round(t_create, 3),
         **exact.errors(torch, img, vis_out)}
     ws.close()
     K.close()

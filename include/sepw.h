@@ -322,13 +322,18 @@ int sepw_wstack_create(sepw_kernels k, int32_t n_slices, double w_lo, double w_h
  * density).  edges: HOST float64[n_slices + 1], finite and strictly
  * increasing; slice s holds e_s <= w < e_{s+1} (w below e_0 in slice 0, w at
  * or above e_ns in the last slice, non-finite w in slice 0 and dropped),
- * centre w_s = (e_s + e_{s+1}) / 2.  k's planes must span exactly [-h, h]
- * with h the largest half-width (e_{s+1} - e_s) / 2 (narrower slices use the
- * middle planes of the same tables).  Everything else as sepw_wstack_create;
- * the object is used with sepw_wstack_grid / _degrid / sepw_free_wstack.
+ * centre w_s = (e_s + e_{s+1}) / 2.  Each non-empty slice gets tables of its
+ * own: k's parameters (N, fov, S, O, P, taper, precision) with the w range
+ * [-h_s, h_s], h_s = (e_{s+1} - e_s) / 2, so a narrow slice has finely spaced
+ * planes; k's own w range is not used.  The object holds those kernels (each
+ * with its FFT plan and an N x N work array) besides the plans; in FP32 the
+ * slices are degridded in one batched launch that reads each slice's tables
+ * through the caches.  Everything else as sepw_wstack_create; the object is
+ * used with sepw_wstack_grid / _degrid / sepw_free_wstack.
  * Errors: SEPW_ERR_ARG (null k, edges or out, facet kernels, n_slices outside
- * [1, 4096], edges not finite and increasing, kernels' w range not [-h, h],
- * nvis out of range), SEPW_ERR_OOM, SEPW_ERR_HIP. */
+ * [1, 4096], edges not finite and increasing, nvis out of range),
+ * SEPW_ERR_UNSUPPORTED (k carries a correction table), SEPW_ERR_OOM,
+ * SEPW_ERR_HIP, SEPW_ERR_FFT. */
 int sepw_wstack_create_edges(sepw_kernels k, int32_t n_slices, const double* edges, int64_t nvis,
                              const double* u, const double* v, const double* w,
                              int64_t* n_dropped, void* hip_stream, sepw_wstack* out);

@@ -33,9 +33,9 @@ wider ones at large |w|, slice widths adapted to the visibility density):
 
 * with increasing edges e_0 < ... < e_ns, slice s holds e_s <= w < e_{s+1}
   (w below e_0 in slice 0, w at or above e_ns in the last slice, non-finite w
-  in slice 0), centre w_s = (e_s + e_{s+1}) / 2, and the residual planes are
-  P uniform planes on [-h, h] with h the largest half-width (e_{s+1} - e_s) / 2,
-  one table set for all slices;
+  in slice 0), centre w_s = (e_s + e_{s+1}) / 2, and its residual w goes to
+  P uniform planes on its own range [-h_s, h_s], h_s = (e_{s+1} - e_s) / 2,
+  with a table set per slice (a narrow slice gets finely spaced planes);
 * density-adapted edges: the finite w are counted in nfine uniform bins of
   [w_lo, w_hi] (bin index as the plane index); edge k (0 < k < ns) is the
   first bin boundary j at which the count below reaches k n / ns (n finite
@@ -66,11 +66,14 @@ def slice_of(w, n_slices, w_lo, w_hi, edges=None):
     return s, ws, w - ws[s]
 
 
-def residual_range(n_slices, w_lo, w_hi, edges=None):
+def residual_range(n_slices, w_lo, w_hi, edges=None, k=0):
+    """Residual range [-h, h] of slice k: h = (w_hi - w_lo) / (2 n_s) for
+    uniform slices (all alike), h_k = (e_{k+1} - e_k) / 2 with edges."""
     if edges is None:
         h = (np.float64(w_hi) - np.float64(w_lo)) / (2 * n_slices)
     else:
-        h = np.max(np.diff(np.asarray(edges, np.float64))) * 0.5
+        e = np.asarray(edges, np.float64)
+        h = (e[k + 1] - e[k]) * 0.5
     return -h, h
 
 
@@ -108,22 +111,35 @@ def _bins(u, v, w, N, fov, O, S, P, w_lo, w_hi):
     return quantise.quantise(u, v, w, N, fov, O, S, P, w_lo, w_hi, 1)
 
 
-def residual_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a=0.5, b=5.0 / 24.0, edges=None):
-    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi, edges)
+def residual_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a=0.5, b=5.0 / 24.0, edges=None,
+                    k=0):
+    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi, edges, k)
     return tables.separable_table(tables.w_plane_centres(P, r_lo, r_hi), N, fov, S, O, c1, a=a, b=b)
+
+
+def _slice_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a, b, edges):
+    """Per slice: residual range and tables (computed once for uniform slices)."""
+    out, cache = [], {}
+    for k in range(n_slices):
+        r = residual_range(n_slices, w_lo, w_hi, edges, k)
+        if r not in cache:
+            cache[r] = tables.separable_table(tables.w_plane_centres(P, r[0], r[1]), N, fov, S, O,
+                                              c1, a=a, b=b)
+        out.append((r, cache[r]))
+    return out
 
 
 def image(u, v, w, y, N, fov, S, O, P, n_slices, w_lo, w_hi, c1, n_power=0, a=0.5,
           b=5.0 / 24.0, bins=_bins, wrap=False, edges=None):
     """Sum over slices of exp(2 pi i w_s (n - 1)) times the slice's corrected image."""
     s, ws, dw = slice_of(w, n_slices, w_lo, w_hi, edges)
-    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi, edges)
-    T = residual_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a, b, edges)
+    st = _slice_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a, b, edges)
     D = np.zeros((N, N), dtype=np.complex128)
     for k in range(n_slices):
         idx = np.flatnonzero(s == k)
         if len(idx) == 0:
             continue
+        (r_lo, r_hi), T = st[k]
         q = bins(u[idx], v[idx], dw[idx], N, fov, O, S, P, r_lo, r_hi)
         G = gridder.grid_separable(q, y[idx], T, N, S, wrap=wrap)
         D += slice_phase(N, fov, ws[k], +1) * imaging.image_from_grid(G, c1, fov, n_power)
@@ -134,13 +150,13 @@ def predict(u, v, w, X, N, fov, S, O, P, n_slices, w_lo, w_hi, c1, n_power=0, a=
             b=5.0 / 24.0, bins=_bins, wrap=False, edges=None):
     """Visibilities of model X: slice s degrids X exp(-2 pi i w_s (n - 1))."""
     s, ws, dw = slice_of(w, n_slices, w_lo, w_hi, edges)
-    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi, edges)
-    T = residual_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a, b, edges)
+    st = _slice_tables(N, fov, S, O, P, n_slices, w_lo, w_hi, c1, a, b, edges)
     V = np.zeros(len(u), dtype=np.complex128)
     for k in range(n_slices):
         idx = np.flatnonzero(s == k)
         if len(idx) == 0:
             continue
+        (r_lo, r_hi), T = st[k]
         q = bins(u[idx], v[idx], dw[idx], N, fov, O, S, P, r_lo, r_hi)
         G = imaging.grid_from_image(X * slice_phase(N, fov, ws[k], -1), c1, fov, n_power)
         V[idx] = gridder.degrid_separable(q, G, T, N, S, wrap=wrap)
@@ -148,7 +164,21 @@ def predict(u, v, w, X, N, fov, S, O, P, n_slices, w_lo, w_hi, c1, n_power=0, a=
 
 
 def bins(u, v, w, N, fov, O, S, P, n_slices, w_lo, w_hi, edges=None):
-    """Bins of every visibility in caller order (residual w, residual planes)."""
-    _, _, dw = slice_of(w, n_slices, w_lo, w_hi, edges)
-    r_lo, r_hi = residual_range(n_slices, w_lo, w_hi, edges)
-    return quantise.quantise(u, v, dw, N, fov, O, S, P, r_lo, r_hi, 1)
+    """Bins of every visibility in caller order (residual w, planes of its
+    slice's residual range)."""
+    s, _, dw = slice_of(w, n_slices, w_lo, w_hi, edges)
+    if edges is None:
+        r_lo, r_hi = residual_range(n_slices, w_lo, w_hi)
+        return quantise.quantise(u, v, dw, N, fov, O, S, P, r_lo, r_hi, 1)
+    out = None
+    for k in range(n_slices):
+        idx = np.flatnonzero(s == k)
+        if len(idx) == 0:
+            continue
+        r_lo, r_hi = residual_range(n_slices, w_lo, w_hi, edges, k)
+        q = quantise.quantise(u[idx], v[idx], dw[idx], N, fov, O, S, P, r_lo, r_hi, 1)
+        if out is None:
+            out = {key: np.zeros(len(u), dtype=val.dtype) for key, val in q.items()}
+        for key, val in q.items():
+            out[key][idx] = val
+    return out

@@ -362,7 +362,8 @@ class WStack:
     [w_lo, w_hi]; ``kernels`` hold the residual tables (planes on [-h, h],
     h = (w_hi - w_lo) / (2 n_slices)).  With ``edges`` (n_slices + 1
     increasing values; w_lo, w_hi ignored) sepw_wstack_create_edges: slices
-    [e_s, e_{s+1}), h the largest half-width."""
+    [e_s, e_{s+1}), each with tables of its own on [-h_s, h_s],
+    h_s = (e_{s+1} - e_s) / 2 (the kernels' own w range is not used)."""
 
     def __init__(self, kernels, n_slices, w_lo, w_hi, u, v, w, count_dropped=True, edges=None):
         lib = load()

@@ -33,6 +33,7 @@ struct sepw_wstack_s {
   std::vector<double> centre;    // slice centres w_s
   std::vector<int64_t> off;      // [ns + 1] slice offsets in slice order
   std::vector<Plan*> plans;      // [ns], null for empty slices
+  std::vector<Kernels*> kern;    // non-uniform slices: tables per slice on its own residual range
   uint32_t* order = nullptr;     // [nvis] slice-ordered position -> caller index
   float2* vis = nullptr;         // [nvis] slice-ordered W V (gridding) or results (degridding)
   float2* img = nullptr;         // [nimg N N] slice images (gridded or degridded nimg at a time)
@@ -674,7 +675,8 @@ int batch_scratch(Plan* lead, int njobs, hipStream_t s, BatchScratch** out) {
   return SEPW_OK;
 }
 
-// Degridding of nj FP32 plans on the same kernels K from images held in
+// Degridding of nj FP32 plans (on kernels K, or on kernels of their own with
+// K's N, S, taper and no correction table) from images held in
 // grids (N x N each, consecutive): per plan the correction (times n^npow) and
 // the FFT in place, then ONE batched persistent degridding launch over the
 // plans' items, then per plan the correction-table pass and the move of its
@@ -695,11 +697,15 @@ int degrid_images_batched(Kernels* K, Plan* const* plans, int nj, float2* grids,
   BatchScratch* bs = nullptr;
   int rc = batch_scratch(plans[0], nj, s, &bs);
   if (rc != SEPW_OK) return rc;
+  // the tables stay in LDS when every job uses K's; jobs with tables of
+  // their own (non-uniform W-stacking slices) read them through the caches
+  bool shared = true;
   for (int j = 0; j < nj; ++j) {
     const Plan* p = plans[j];
+    shared = shared && p->K == K;
     bs->dhost[j] = DegridArgs{p->dl.items, p->dl.itoff + 8 * p->r8, p->dl.itoff, p->r8, p->qctr,
-                              p->tdesc, p->krec, grids + (int64_t)j * N * N, K->pad_su, K->pad_sv,
-                              K->tab_len, N, p->ntx, 1, p->yrow};
+                              p->tdesc, p->krec, grids + (int64_t)j * N * N, p->K->pad_su,
+                              p->K->pad_sv, p->K->tab_len, N, p->ntx, 1, p->yrow};
   }
   SEPW_TRY(hipMemcpyAsync(bs->djobs, bs->dhost, sizeof(DegridArgs) * (size_t)nj,
                           hipMemcpyHostToDevice, s));
@@ -707,8 +713,8 @@ int degrid_images_batched(Kernels* K, Plan* const* plans, int nj, float2* grids,
   {
     Stage st(SEPW_STAGE_DEGRID, s);
     SEPW_TRY(launch_job_prefix(bs->djobs, nj, bs->first, bs->counter, s));
-    SEPW_TRY(launch_degrid_fp32_batched(K->S, bs->djobs, bs->first, nj, bs->counter, K->lds_bytes,
-                                        K->n_cu, s));
+    SEPW_TRY(launch_degrid_fp32_batched(K->S, bs->djobs, bs->first, nj, bs->counter,
+                                        shared ? K->lds_bytes : 0, K->n_cu, s));
   }
   for (int j = 0; j < nj; ++j) {
     Plan* p = plans[j];
@@ -735,6 +741,7 @@ int batch_images(int N, int n) {
 void destroy_wstack(sepw_wstack_s* W) {
   if (!W) return;
   for (Plan* p : W->plans) destroy_plan(p);
+  for (Kernels* k : W->kern) destroy_kernels(k);
   dfree(W->order);
   dfree(W->vis);
   dfree(W->img);
@@ -799,10 +806,32 @@ int wstack_build(sepw_wstack_s* W, Kernels* K, int ns, double w_lo, double w_hi,
     for (int j = 0; j < ns; ++j) {
       const int64_t n = W->off[j + 1] - W->off[j];
       if (n == 0) continue;
+      Kernels* KS = K;
+      if (edges) {
+        // the slice's own residual range [-h_s, h_s]: k's parameters with that w range
+        sepw_kernels_s* k2 = new (std::nothrow) sepw_kernels_s();
+        if (!k2) return SEPW_ERR_OOM;
+        W->kern.push_back(k2);
+        sepw_kernel_params prm = K->prm;
+        const double hs = (edges[j + 1] - edges[j]) * 0.5;
+        prm.w_lo = -hs;
+        prm.w_hi = hs;
+        const bool user = prm.taper == SEPW_TAPER_USER;
+        if (user) prm.taper = SEPW_TAPER_NONE;   // K's taper samples are copied below
+        int rk = build_kernels(&prm, s, k2);
+        if (rk != SEPW_OK) return rk;
+        if (user) {
+          k2->prm.taper = SEPW_TAPER_USER;
+          SEPW_TRY(hipMemcpyAsync(k2->c1, K->c1, sizeof(double) * (size_t)K->N,
+                                  hipMemcpyDeviceToDevice, s));
+          SEPW_TRY(make_tables(k2, s));
+        }
+        KS = k2;
+      }
       sepw_plan_s* P = new (std::nothrow) sepw_plan_s();
       if (!P) return SEPW_ERR_OOM;
       W->plans[j] = P;
-      int rc = alloc_plan(K, n, P);
+      int rc = alloc_plan(KS, n, P);
       if (rc == SEPW_OK) rc = bin_plan(P, n, plain_coords(us + W->off[j], vs + W->off[j], wsr + W->off[j]), s);
       if (rc == SEPW_OK && n_dropped) {
         int64_t d = 0;
@@ -1714,15 +1743,12 @@ int sepw_wstack_create_edges(sepw_kernels k, int32_t n_slices, const double* edg
   if (!k || k->facet || n_slices < 1 || n_slices > kMaxSlices || !edges) return SEPW_ERR_ARG;
   if (nvis < 0 || nvis > 2147483646LL) return SEPW_ERR_ARG;
   if (nvis > 0 && (!u || !v || !w)) return SEPW_ERR_ARG;
-  double h = 0.0;
   for (int j = 0; j <= n_slices; ++j)
     if (!std::isfinite(edges[j])) return SEPW_ERR_ARG;
-  for (int j = 0; j < n_slices; ++j) {
+  for (int j = 0; j < n_slices; ++j)
     if (!(edges[j] < edges[j + 1])) return SEPW_ERR_ARG;
-    h = std::max(h, (edges[j + 1] - edges[j]) * 0.5);
-  }
-  // the kernels' planes must span the residual range [-h, h] of the widest slice
-  if (std::fabs(k->w_lo + h) > 1e-12 * h || std::fabs(k->w_hi - h) > 1e-12 * h) return SEPW_ERR_ARG;
+  // every slice gets tables of its own (k's parameters, the slice's w range)
+  if (k->corr) return SEPW_ERR_UNSUPPORTED;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   sepw_wstack_s* W = new (std::nothrow) sepw_wstack_s();
   if (!W) return SEPW_ERR_OOM;

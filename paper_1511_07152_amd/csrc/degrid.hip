@@ -265,8 +265,10 @@ __global__ __launch_bounds__(LDS ? 1024 : 256) void degrid_fp32_kernel(DegridArg
             [&](int it) { degrid_item<S>(a, tu_tab, tv_tab, it, lane, lane & 15, lane >> 4); });
 }
 
-// Many jobs with the same tables in one launch: a wave takes global item gi,
-// the item gi - first[job] of the job with first[job] <= gi < first[job + 1].
+// Many jobs in one launch: a wave takes global item gi, the item
+// gi - first[job] of the job with first[job] <= gi < first[job + 1].  With
+// LDS every job uses jobs[0]'s tables (staged once); without, each job reads
+// its own.
 template <int S, bool LDS>
 __global__ __launch_bounds__(LDS ? 1024 : 256) void degrid_fp32_batched_kernel(
     const DegridArgs* __restrict__ jobs, const uint32_t* __restrict__ first, int njobs,
@@ -292,7 +294,9 @@ __global__ __launch_bounds__(LDS ? 1024 : 256) void degrid_fp32_batched_kernel(
       if (first[mid] <= gi) lo = mid; else hi = mid - 1;
     }
     const int job = uniform(lo);
-    degrid_item<S>(jobs[job], tu_tab, tv_tab, (int)(gi - first[job]), lane, lane & 15, lane >> 4);
+    const DegridArgs& a = jobs[job];
+    degrid_item<S>(a, LDS ? tu_tab : a.tab_u, LDS ? tv_tab : a.tab_v, (int)(gi - first[job]), lane,
+                   lane & 15, lane >> 4);
   });
 }
 

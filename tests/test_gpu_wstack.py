@@ -121,9 +121,9 @@ def test_wstack_arguments_checked(lib):
 EDGES = np.array([-2000.0, -700.0, -150.0, 0.0, 100.0, 900.0, 2000.0])
 
 
-def _make_edges(lib, d, edges):
-    h = np.max(np.diff(edges)) * 0.5
-    K = lib.Kernels(d["N"], d["fov"], d["S"], d["O"], d["P"], -h, h)
+def _make_edges(lib, d, edges, **kw):
+    # the kernels' own w range is not used: every slice gets tables on its range
+    K = lib.Kernels(d["N"], d["fov"], d["S"], d["O"], d["P"], -1.0, 1.0, **kw)
     ws = lib.WStack(K, len(edges) - 1, 0.0, 0.0, dev(d["u"], torch.float64),
                     dev(d["v"], torch.float64), dev(d["w"], torch.float64), edges=edges)
     return K, ws
@@ -190,3 +190,24 @@ def test_density_sliced_wstack_matches_oracle(lib):
     want = oracle.wstack.image(d["u"], d["v"], d["w"], d["V"] * d["W"], *_args_edges(d, e),
                                n_power=1, edges=e)
     assert rel_rms(inner(img.cpu().numpy()), inner(want)) <= 1e-5
+
+
+def test_nonuniform_slices_with_user_taper(lib):
+    # a caller's taper samples reach every slice's tables and the corrections
+    rng, d = _case(87)
+    c1 = oracle.pswf.taper_c1(d["N"], d["fov"], 5)       # not the default width S = 7
+    K, ws = _make_edges(lib, d, EDGES, taper="user", taper_samples=c1)
+    img = ws.grid(dev(d["V"], torch.complex64), None)
+    args = (d["N"], d["fov"], d["S"], d["O"], d["P"], len(EDGES) - 1, EDGES[0], EDGES[-1], c1)
+    want = oracle.wstack.image(d["u"], d["v"], d["w"], d["V"], *args, edges=EDGES)
+    assert rel_rms(inner(img.cpu().numpy()), inner(want)) <= 1e-5
+
+
+def test_nonuniform_slices_reject_correction_tables(lib):
+    rng, d = _case(88, n=100)
+    K = lib.Kernels(d["N"], d["fov"], d["S"], d["O"], d["P"], -1.0, 1.0)
+    K.set_correction(5, 4)
+    with pytest.raises(lib.SepwError) as e:
+        lib.WStack(K, len(EDGES) - 1, 0.0, 0.0, dev(d["u"], torch.float64),
+                   dev(d["v"], torch.float64), dev(d["w"], torch.float64), edges=EDGES)
+    assert e.value.code == -5

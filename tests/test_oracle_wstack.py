@@ -138,7 +138,7 @@ def test_nonuniform_slice_centred_full_support_equals_exact_dft():
     assert _close(D, ref, c1)
 
 
-def test_nonuniform_residual_planes_use_the_widest_slice():
+def test_nonuniform_residual_planes_use_each_slices_range():
     N, O, P, fov = 16, 4, 3, math.radians(8.0)
     ns = len(EDGES) - 1
     rng, u, v, y = _vis(59, N, fov, 80, N / 2 - 1)
@@ -146,9 +146,9 @@ def test_nonuniform_residual_planes_use_the_widest_slice():
     c1 = pswf.taper_c1(N, fov, 6.0)
     D = wstack.image(u, v, w, y, N, fov, N, O, P, ns, EDGES[0], EDGES[-1], c1, bins=_full_bins,
                      wrap=True, edges=EDGES)
-    # reference: the widest slice (-1500 .. -400) sets the residual planes
-    h = 550.0
-    wc = tables.w_plane_centres(P, -h, h)
+    # reference: per slice, the exact phase of its centre times the
+    # separable-screen DFT at the centre of its residual plane, the planes
+    # spanning that slice's own half-width
     exact = dft.phase_screen(N, fov, 'exact')
     sep = dft.phase_screen(N, fov, 'sep')
     ref = np.zeros((N, N), complex)
@@ -156,6 +156,8 @@ def test_nonuniform_residual_planes_use_the_widest_slice():
         lo = -np.inf if s == 0 else EDGES[s]
         hi = np.inf if s == ns - 1 else EDGES[s + 1]
         ws = (EDGES[s] + EDGES[s + 1]) / 2
+        h = (EDGES[s + 1] - EDGES[s]) / 2
+        wc = tables.w_plane_centres(P, -h, h)
         m = (w >= lo) & (w < hi)
         q = _full_bins(u[m], v[m], w[m] - ws, N, fov, O, N, P, -h, h)
         uh, vh = quantise.dequantised(q, N, fov, O)
