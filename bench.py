@@ -297,8 +297,11 @@ def wstack_form(_lib, torch, d, u, v, w, V, W, model, steps, exact):
 
 def correction_form(_lib, torch, d, u, v, w, V, W, model, steps, Sc=13, Oc=8):
     """The correction table F_w - F~_w (Section 6) attached to the array-scale
-    kernels (S_c = 13, O_c = 8): its FP64 generation for the 128 planes, then
-    grid (x n) + degrid (/ n) per step with the correction passes."""
+    kernels (S_c = 13, O_c = 8): its FP64 generation for the 128 planes (and
+    its factoring into separable terms), then grid (x n) + degrid (/ n) per
+    step with the correction run as those terms on the matrix-core kernels;
+    then the same step with the passes that walk the table, and the relative
+    difference of the two forms' images and visibilities."""
     N, fov, S, O, P = d["N"], d["fov"], d["S"], d["O"], d["P"]
     K = _lib.Kernels(N, fov, S, O, P, d["w_lo"], d["w_hi"])
     torch.cuda.synchronize()
@@ -327,9 +330,22 @@ def correction_form(_lib, torch, d, u, v, w, V, W, model, steps, Sc=13, Oc=8):
     st = _lib.timing_collect()
     res = {"workload": "array-scale, correction S_c=%d O_c=%d beside S=%d O=%d, %d planes"
                        % (Sc, Oc, S, O, P),
-           "table_generation_ms": round(table_ms, 2), "ms_per_step": round(ms, 3),
-           "Mvis_per_s": round(plan.nvis / (ms * 1e-3) / 1e6, 2),
+           "table_generation_ms": round(table_ms, 2), "separable_terms": K.correction_rank(),
+           "ms_per_step": round(ms, 3), "Mvis_per_s": round(plan.nvis / (ms * 1e-3) / 1e6, 2),
            "stages_ms_per_step": {k: round(v_ / steps, 4) for k, (v_, n) in st.items() if n}}
+    img_t, vis_t = img.clone(), vis_out.clone()
+    K.correction_terms(False)
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms_w = (time.perf_counter() - t0) * 1e3 / steps
+    res["table_walk"] = {
+        "ms_per_step": round(ms_w, 3),
+        "rel_diff_terms_vs_walk": {"image_inner_half": rel_diff(torch, img_t, img, inner=True),
+                                   "vis": rel_diff(torch, vis_t, vis_out)}}
     plan.close()
     K.close()
     return res

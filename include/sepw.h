@@ -174,8 +174,17 @@ int sepw_kernels_taper(sepw_kernels k, double* out, void* hip_stream);
  * cu + (fi_u - O/2)/O, ties upwards (cu_c is cu or cu + 1).  With Sc = S and
  * Oc = O gridding is then exactly gridding with the exact 2D GCF.  The table
  * is generated now (FP64, stored complex64) and again by
- * sepw_kernels_set_wrange; existing plans stay valid.  Synchronises the
- * stream once (taper check).
+ * sepw_kernels_set_wrange; existing plans stay valid.  For FP32 kernels the
+ * table is then also factored, per plane, into at most 8 separable terms
+ * sum_r a_r[fu][su] b_r[fv][sv] with every entry of the difference within
+ * 1e-6 of the table's largest entry (cross approximation with complete
+ * pivoting; the table's exponent gap is a short polynomial in l^2 and m^2, so
+ * few terms suffice: 3 at 3 degrees), and grid / degrid run the separable
+ * matrix-core kernels once per term instead of walking the table; otherwise
+ * (16-bit kernels, more terms needed, or a table above 2^24 entries) the
+ * correction passes walk the table.  Both give the same footprint sums.
+ * Synchronises the stream (taper check; the factoring, here and in
+ * sepw_kernels_set_wrange, copies the table to the host).
  * Errors: SEPW_ERR_ARG (null k; support even, negative or above S; oversample
  * not a power of two or above O; support above S - 2 when 1 < oversample < O,
  * where the coarse cell can be the next one), SEPW_ERR_UNSUPPORTED (facet
@@ -187,6 +196,16 @@ int sepw_kernels_set_correction(sepw_kernels k, int32_t support, int32_t oversam
  * complex64, layout [k][fu][fv][sv][su] (su fastest).
  * Errors: SEPW_ERR_ARG (null pointers, no correction attached), SEPW_ERR_HIP. */
 int sepw_kernels_correction_table(sepw_kernels k, sepw_c64* out, void* hip_stream);
+/* Choose how corrections of k run: enable = 1 (the default) factors the
+ * table into separable terms where it can (see sepw_kernels_set_correction),
+ * 0 makes grid / degrid walk the table itself.  Applies to the attached table
+ * (factoring it now synchronises the stream) and to later ones.
+ * Errors: SEPW_ERR_ARG (null k, enable not 0 or 1), SEPW_ERR_OOM, SEPW_ERR_HIP. */
+int sepw_kernels_correction_terms(sepw_kernels k, int32_t enable, void* hip_stream);
+/* Number of separable terms the attached correction runs as (*rank >= 0; 0
+ * for an all-zero table), or -1 when the correction passes walk the table.
+ * Errors: SEPW_ERR_ARG (null pointers, no correction attached). */
+int sepw_kernels_correction_rank(sepw_kernels k, int32_t* rank);
 
 /* Quantise and bin nvis visibilities (u, v, w: DEVICE float64 arrays in
  * wavelengths, caller order).  In facet mode u, v are shifted by -w l0/n0,

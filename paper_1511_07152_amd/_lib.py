@@ -58,6 +58,8 @@ def load():
     lib.sepw_kernels_taper.argtypes = [c_void_p, c_void_p, c_void_p]
     lib.sepw_kernels_set_correction.argtypes = [c_void_p, c_int32, c_int32, c_void_p]
     lib.sepw_kernels_correction_table.argtypes = [c_void_p, c_void_p, c_void_p]
+    lib.sepw_kernels_correction_rank.argtypes = [c_void_p, P(c_int32)]
+    lib.sepw_kernels_correction_terms.argtypes = [c_void_p, c_int32, c_void_p]
     lib.sepw_plan_create.argtypes = [c_void_p, c_int64, c_void_p, c_void_p, c_void_p,
                                      P(c_int64), c_void_p, P(c_void_p)]
     lib.sepw_plan_bins.argtypes = [c_void_p, c_void_p, c_void_p]
@@ -109,7 +111,9 @@ def load():
                  "sepw_timing_collect", "sepw_plan_set_item_slots", "sepw_plan_set_degrid_item_slots",
                  "sepw_autotune_batched", "sepw_wstack_create", "sepw_wstack_grid",
                  "sepw_wstack_degrid", "sepw_free_wstack", "sepw_kernels_set_correction",
-                 "sepw_kernels_correction_table", "sepw_plan_create_channels",
+                 "sepw_kernels_correction_table", "sepw_kernels_correction_rank",
+                 "sepw_kernels_correction_terms",
+                 "sepw_plan_create_channels",
                  "sepw_plan_rebin_channels", "sepw_wsnap_create", "sepw_wsnap_grid",
                  "sepw_wsnap_degrid", "sepw_wsnap_plane", "sepw_free_wsnap"):
         getattr(lib, name).restype = c_int32
@@ -195,6 +199,20 @@ class Kernels:
         _check(load().sepw_kernels_set_correction(self._h, int(support), int(oversample), _stream()),
                "sepw_kernels_set_correction")
         self.corr = (int(support), int(oversample)) if support else None
+
+    def correction_terms(self, enable):
+        """sepw_kernels_correction_terms: run corrections as separable terms
+        (True, the default) or by walking the table (False)."""
+        _check(load().sepw_kernels_correction_terms(self._h, 1 if enable else 0, _stream()),
+               "sepw_kernels_correction_terms")
+
+    def correction_rank(self):
+        """sepw_kernels_correction_rank: separable terms the correction runs as
+        (-1: the correction passes walk the table)."""
+        r = ctypes.c_int32(0)
+        _check(load().sepw_kernels_correction_rank(self._h, ctypes.byref(r)),
+               "sepw_kernels_correction_rank")
+        return r.value
 
     def correction_table(self):
         """The attached correction table, [P][Oc][Oc][Sc(v)][Sc(u)] complex64."""

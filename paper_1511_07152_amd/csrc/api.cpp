@@ -169,6 +169,8 @@ int validate_params(const sepw_kernel_params* p) {
   return SEPW_OK;
 }
 
+void free_corr_terms(Kernels* K);
+
 void destroy_kernels(Kernels* k) {
   if (!k) return;
   if (k->tab_v && k->tab_v != k->tab_u) dfree(k->tab_v);
@@ -187,6 +189,7 @@ void destroy_kernels(Kernels* k) {
   dfree(k->lp_u);
   dfree(k->corr);
   dfree(k->corr_tmp);
+  free_corr_terms(k);
   if (k->fft_ok) hipfftDestroy(k->fft);
   delete static_cast<sepw_kernels_s*>(k);
 }
@@ -280,11 +283,90 @@ hipError_t make_separable_tables(Kernels* K, hipStream_t s) {
   return e;
 }
 
+void free_corr_terms(Kernels* K) {
+  for (int r = 0; r < kMaxCorrRank; ++r) {
+    if (K->ck_v[r] == K->ck_u[r]) K->ck_v[r] = nullptr;
+    if (K->ck_sv[r] == K->ck_su[r]) K->ck_sv[r] = nullptr;
+    dfree(K->ck_u[r]);
+    dfree(K->ck_v[r]);
+    dfree(K->ck_su[r]);
+    dfree(K->ck_sv[r]);
+  }
+  K->corr_rank = -1;
+  K->ck_lds = 0;
+}
+
+// Correction tables of the FP32 tiled path as separable terms (at most
+// kMaxCorrRank, every residual entry within 1e-6 of the table's largest): the
+// table comes to the host (the stream is synchronised), and the terms' padded
+// tables go back.  Otherwise corr_rank stays -1 and the correction passes
+// walk the table.
+hipError_t factor_corr(Kernels* K, hipStream_t s) {
+  K->corr_rank = -1;
+  if (!K->corr_terms || K->prm.precision != SEPW_FP32 || wide_support(K->S)) return hipSuccess;
+  const int64_t nC = (int64_t)K->P * K->corr_O * K->corr_O * K->corr_S * K->corr_S;
+  if (nC > ((int64_t)1 << 24)) return hipSuccess;   // host copy above 128 MiB: keep the passes
+  std::vector<float2> C((size_t)nC);
+  hipError_t e = hipMemcpyAsync(C.data(), K->corr, sizeof(float2) * nC, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  std::vector<float2> tu, tv;
+  bool shared = false;
+  const int rank = factor_corr_table(C.data(), K->P, K->O, K->S, K->corr_O, K->corr_S,
+                                     kMaxCorrRank, 1e-6, &tu, &tv, &shared);
+  if (rank < 0) return hipSuccess;
+  // the tables of earlier terms are rewritten in place (stream order); a
+  // shared u / v table and a separate pair are not interchangeable
+  for (int r = 0; r < kMaxCorrRank; ++r)
+    if (K->ck_u[r] && (K->ck_v[r] == K->ck_u[r]) != shared) {
+      e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return e;
+      free_corr_terms(K);
+      break;
+    }
+  const int64_t one = (int64_t)K->P * K->O * K->S;
+  float2* dev = nullptr;
+  if (rank > 0) e = dalloc(&dev, 2 * rank * one);
+  for (int r = 0; r < rank && e == hipSuccess; ++r) {
+    float2* du = dev + (int64_t)r * one;
+    float2* dv = dev + (int64_t)(rank + r) * one;
+    e = hipMemcpyAsync(du, tu.data() + (size_t)r * one, sizeof(float2) * one, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !shared)
+      e = hipMemcpyAsync(dv, tv.data() + (size_t)r * one, sizeof(float2) * one, hipMemcpyHostToDevice, s);
+    float2** dst[4] = {&K->ck_u[r], &K->ck_su[r], &K->ck_v[r], &K->ck_sv[r]};
+    for (int t = 0; t < (shared ? 2 : 4) && e == hipSuccess; ++t)
+      if (!*dst[t]) e = dalloc(dst[t], (int64_t)K->tab_len);
+    if (shared) {
+      K->ck_v[r] = K->ck_u[r];
+      K->ck_sv[r] = K->ck_su[r];
+    }
+    if (e == hipSuccess) e = launch_pad_table(du, nullptr, K->P, K->O, K->S, K->ck_u[r], s);
+    if (e == hipSuccess) e = launch_pad_table(du, nullptr, K->P, K->O, K->S, K->ck_su[r], s, true);
+    if (e == hipSuccess && !shared) e = launch_pad_table(dv, nullptr, K->P, K->O, K->S, K->ck_v[r], s);
+    if (e == hipSuccess && !shared)
+      e = launch_pad_table(dv, nullptr, K->P, K->O, K->S, K->ck_sv[r], s, true);
+  }
+  // the host tables must outlive the copies
+  if (dev) {
+    const hipError_t e2 = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = e2;
+    dfree(dev);
+  }
+  if (e != hipSuccess) return e;
+  const int64_t bytes = (int64_t)sizeof(float2) * (shared ? 1 : 2) * K->tab_len;
+  K->ck_lds = bytes <= (int64_t)K->lds_max ? (int)bytes : 0;
+  K->corr_rank = rank;
+  return hipSuccess;
+}
+
 hipError_t make_corr_table(Kernels* K, hipStream_t s) {
   if (!K->corr) return hipSuccess;
   Stage st(SEPW_STAGE_CORR_TABLE, s);
-  return launch_corr_tables(K->c1, K->N, K->fov, K->P, K->w_lo, K->w_hi, K->a_u, K->b_u, K->a_v,
-                            K->b_v, K->corr_S, K->corr_O, K->corr_nkb, K->corr_tmp, K->corr, s);
+  hipError_t e = launch_corr_tables(K->c1, K->N, K->fov, K->P, K->w_lo, K->w_hi, K->a_u, K->b_u,
+                                    K->a_v, K->b_v, K->corr_S, K->corr_O, K->corr_nkb,
+                                    K->corr_tmp, K->corr, s);
+  if (e == hipSuccess) e = factor_corr(K, s);
+  return e;
 }
 
 // every table of the kernel set for its current w range
@@ -325,6 +407,51 @@ CorrArgs corr_args(const Plan* p, const WorkList& l, float2* grid, int checker) 
   a.checker = checker;
   a.grid = grid;
   return a;
+}
+
+// The correction beside a plan's separable pass (nothing without a table):
+// factored, the separable kernels once per term with the term's tables
+// (gridding adds into the grid; degridding adds into the results the
+// separable pass left in row-bin order); otherwise the passes that walk the
+// table itself.
+int corr_grid_pass(Plan* p, float2* grid, int checker, hipStream_t s) {
+  const Kernels* K = p->K;
+  if (!K->corr) return SEPW_OK;
+  Stage st(SEPW_STAGE_CORR_APPLY, s);
+  if (K->corr_rank < 0) {
+    SEPW_TRY(launch_corr_grid(K->S, corr_args(p, p->gl, grid, checker), p->gl.max_items, s));
+    return SEPW_OK;
+  }
+  for (int r = 0; r < K->corr_rank; ++r) {
+    GridArgs a{p->gl.items, p->gl.itoff + 8 * p->r8, p->gl.itoff, p->r8, p->qctr, p->tdesc, p->krec,
+               p->yrow, K->ck_u[r], K->ck_v[r], K->tab_len, K->N, p->ntx, checker, grid};
+    if (K->ck_lds > 0) {
+      SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8 * kCtrStride, s));
+      SEPW_TRY(launch_grid_fp32_lds(K->S, a, K->ck_lds, K->n_cu, s));
+    } else {
+      SEPW_TRY(launch_grid_fp32(K->S, a, p->gl.max_items, s));
+    }
+  }
+  return SEPW_OK;
+}
+
+int corr_degrid_pass(Plan* p, const float2* grid, int checker, hipStream_t s) {
+  const Kernels* K = p->K;
+  if (!K->corr) return SEPW_OK;
+  Stage st(SEPW_STAGE_CORR_APPLY, s);
+  if (K->corr_rank < 0) {
+    SEPW_TRY(launch_corr_degrid(K->S, corr_args(p, p->dl, const_cast<float2*>(grid), checker),
+                                p->dl.max_items, s));
+    return SEPW_OK;
+  }
+  for (int r = 0; r < K->corr_rank; ++r) {
+    DegridArgs a{p->dl.items, p->dl.itoff + 8 * p->r8, p->dl.itoff, p->r8, p->qctr, p->tdesc, p->krec,
+                 grid, checker ? K->ck_su[r] : K->ck_u[r], checker ? K->ck_sv[r] : K->ck_v[r],
+                 K->tab_len, K->N, p->ntx, checker, p->yrow, 1};
+    SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8 * kCtrStride, s));
+    SEPW_TRY(launch_degrid_fp32(K->S, a, p->dl.max_items, K->ck_lds, K->n_cu, s));
+  }
+  return SEPW_OK;
 }
 
 int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K) {
@@ -416,6 +543,7 @@ int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K) {
     SEPW_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     const int64_t bytes = (int64_t)sizeof(float2) * npad * (shared_axes ? 1 : 2);
     K->n_cu = ncu > 0 ? ncu : 1;
+    K->lds_max = max_lds;
     K->lds_bytes = bytes <= (int64_t)max_lds ? (int)bytes : 0;
     const int64_t lp_bytes = (int64_t)sizeof(uint32_t) * nlp * (shared_axes ? 1 : 2);
     K->lds_bytes_lp = lp_bytes <= (int64_t)max_lds ? (int)lp_bytes : 0;
@@ -718,11 +846,8 @@ int degrid_images_batched(Kernels* K, Plan* const* plans, int nj, float2* grids,
   }
   for (int j = 0; j < nj; ++j) {
     Plan* p = plans[j];
-    if (K->corr) {
-      Stage st(SEPW_STAGE_CORR_APPLY, s);
-      SEPW_TRY(launch_corr_degrid(K->S, corr_args(p, p->dl, grids + (int64_t)j * N * N, 1),
-                                  p->dl.max_items, s));
-    }
+    int rc2 = corr_degrid_pass(p, grids + (int64_t)j * N * N, 1, s);
+    if (rc2 != SEPW_OK) return rc2;
     Stage st(SEPW_STAGE_GATHER, s);
     SEPW_TRY(launch_vis_from_rows(p->yrow, p->rot, p->place, p->delta, p->ckept, p->nvis,
                                   p->nbins, vis[j], s));
@@ -1096,6 +1221,7 @@ int sepw_kernels_set_correction(sepw_kernels k, int32_t support, int32_t oversam
     if (k->corr) SEPW_TRY(hipStreamSynchronize(s));
     dfree(k->corr);
     dfree(k->corr_tmp);
+    free_corr_terms(k);
     k->corr_S = k->corr_O = k->corr_nkb = 0;
     return SEPW_OK;
   }
@@ -1113,8 +1239,10 @@ int sepw_kernels_set_correction(sepw_kernels k, int32_t support, int32_t oversam
   SEPW_TRY(hipStreamSynchronize(s));
   for (int c = 1; c < N / 2; ++c)
     if (c1[N / 2 + c] != c1[N / 2 - c]) return SEPW_ERR_UNSUPPORTED;
+  SEPW_TRY(hipStreamSynchronize(s));
   dfree(k->corr);
   dfree(k->corr_tmp);
+  free_corr_terms(k);
   k->corr_S = k->corr_O = k->corr_nkb = 0;
   // planes per generation batch: FP64 work space of at most 2^25 doubles beyond the weights
   const int64_t one = corr_tmp_doubles(N, support, oversample, 1) - corr_tmp_doubles(N, support, oversample, 0);
@@ -1138,6 +1266,26 @@ int sepw_kernels_correction_table(sepw_kernels k, sepw_c64* out, void* hip_strea
   const size_t n = (size_t)k->P * k->corr_O * k->corr_O * k->corr_S * k->corr_S;
   SEPW_TRY(hipMemcpyAsync(out, k->corr, sizeof(float2) * n, hipMemcpyDeviceToDevice,
                           static_cast<hipStream_t>(hip_stream)));
+  return SEPW_OK;
+}
+
+int sepw_kernels_correction_terms(sepw_kernels k, int32_t enable, void* hip_stream) {
+  if (!k || (enable != 0 && enable != 1)) return SEPW_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  k->corr_terms = enable != 0;
+  if (!k->corr) return SEPW_OK;
+  if (enable) {
+    if (k->corr_rank < 0) SEPW_TRY(factor_corr(k, s));
+  } else {
+    SEPW_TRY(hipStreamSynchronize(s));   // calls in flight may still read the term tables
+    free_corr_terms(k);
+  }
+  return SEPW_OK;
+}
+
+int sepw_kernels_correction_rank(sepw_kernels k, int32_t* rank) {
+  if (!k || !rank || !k->corr) return SEPW_ERR_ARG;
+  *rank = k->corr_rank;
   return SEPW_OK;
 }
 
@@ -1281,9 +1429,9 @@ int sepw_grid(sepw_plan p, const sepw_c64* vis, const float* weight, sepw_c64* o
       SEPW_TRY(launch_grid_lp(K->S, K->prm.precision == SEPW_BF16, a, K->lds_bytes, K->n_cu, s));
     }
   }
-  if (K->corr) {
-    Stage st(SEPW_STAGE_CORR_APPLY, s);
-    SEPW_TRY(launch_corr_grid(K->S, corr_args(p, p->gl, img, grid_only ? 0 : 1), p->gl.max_items, s));
+  {
+    int rc = corr_grid_pass(p, img, grid_only ? 0 : 1, s);
+    if (rc != SEPW_OK) return rc;
   }
   }
   if (grid_only) return SEPW_OK;
@@ -1366,10 +1514,9 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
       SEPW_TRY(launch_degrid_lp(K->S, bf16, a, K->lds_bytes_lp, K->n_cu, s));
     }
   }
-  if (K->corr) {
-    Stage st(SEPW_STAGE_CORR_APPLY, s);
-    SEPW_TRY(launch_corr_degrid(K->S, corr_args(p, p->dl, const_cast<float2*>(src), checker),
-                                p->dl.max_items, s));
+  {
+    int rc = corr_degrid_pass(p, src, checker, s);
+    if (rc != SEPW_OK) return rc;
   }
   {
     Stage st(SEPW_STAGE_GATHER, s);
@@ -1450,11 +1597,8 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
     SEPW_TRY(launch_grid_fp32_batched(S, bs->jobs, bs->first, njobs, bs->counter, bs->blocks, s));
   }
   for (int j = 0; j < njobs; ++j) {
-    Plan* p = plans[j];
-    if (!p->K->corr) continue;
-    Stage st(SEPW_STAGE_CORR_APPLY, s);
-    SEPW_TRY(launch_corr_grid(S, corr_args(p, p->gl, reinterpret_cast<float2*>(out[j]), grid_only ? 0 : 1),
-                              p->gl.max_items, s));
+    rc = corr_grid_pass(plans[j], reinterpret_cast<float2*>(out[j]), grid_only ? 0 : 1, s);
+    if (rc != SEPW_OK) return rc;
   }
   if (grid_only) return SEPW_OK;
   const int npow = (flags & SEPW_MUL_N) ? 1 : ((flags & SEPW_DIV_N) ? -1 : 0);
@@ -1537,10 +1681,8 @@ int sepw_grid_batched_noalloc(int32_t njobs, const sepw_plan* plans, const sepw_
   SEPW_TRY(launch_grid_fp32_batched(S, area->jobs, area->first, njobs, &area->counter,
                                     plans[0]->K->n_cu * plans[0]->blocks_per_cu, s));
   for (int j = 0; j < njobs; ++j) {
-    Plan* p = plans[j];
-    if (!p->K->corr) continue;
-    SEPW_TRY(launch_corr_grid(S, corr_args(p, p->gl, reinterpret_cast<float2*>(out[j]), grid_only ? 0 : 1),
-                              p->gl.max_items, s));
+    rc = corr_grid_pass(plans[j], reinterpret_cast<float2*>(out[j]), grid_only ? 0 : 1, s);
+    if (rc != SEPW_OK) return rc;
   }
   if (grid_only) return SEPW_OK;
   const int npow = (flags & SEPW_MUL_N) ? 1 : ((flags & SEPW_DIV_N) ? -1 : 0);

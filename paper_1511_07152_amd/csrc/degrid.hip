@@ -114,7 +114,15 @@ struct ResGroup {
 };
 
 __device__ __forceinline__ void res_flush(const DegridArgs& a, ResGroup& g) {
-  if (g.pos >= 0) a.yrow[g.pos] = g.v;
+  if (g.pos >= 0) {
+    float2 v = g.v;
+    if (a.accum) {
+      const float2 o = a.yrow[g.pos];
+      v.x += o.x;
+      v.y += o.y;
+    }
+    a.yrow[g.pos] = v;
+  }
   g.pos = -1;
   g.j = 0;
 }

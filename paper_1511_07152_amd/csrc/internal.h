@@ -6,6 +6,8 @@
 #include <hipfft/hipfft.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "sepw.h"
 
 namespace sepw {
@@ -13,6 +15,7 @@ namespace sepw {
 constexpr uint32_t kDropped = 0xFFFFFFFFu;
 constexpr int kRegion = 16;        // MFMA tile region edge (cells): core + S - 1
 constexpr int kMaxSupport = 15;    // S <= kRegion - 1 on the tiled MFMA path
+constexpr int kMaxCorrRank = 8;    // separable terms of a factored correction table
 // Supports 15 < S <= kMaxWideSupport take the per-visibility path (wide.hip):
 // plans keep the quantiser and the level-1 row bins with tiles of
 // kWideRegion + 1 - S cells, but no tile slots or work lists.
@@ -103,6 +106,17 @@ struct Kernels {
   int corr_S = 0, corr_O = 0, corr_nkb = 0;
   float2* corr = nullptr;
   double* corr_tmp = nullptr;
+  // the same correction as corr_rank separable terms (FP32 kernels; -1: the
+  // correction passes walk the table itself): padded u / v tables of term r,
+  // plain and with tap signs (-1)^s, and the LDS bytes of one term's pair
+  bool corr_terms = true;      // factor the table when it is (re)generated
+  int corr_rank = -1;
+  float2* ck_u[kMaxCorrRank] = {};
+  float2* ck_v[kMaxCorrRank] = {};
+  float2* ck_su[kMaxCorrRank] = {};
+  float2* ck_sv[kMaxCorrRank] = {};
+  int ck_lds = 0;
+  int lds_max = 0;             // LDS bytes one workgroup may use
 };
 
 // Tile slot record: padded-table bases of the visibility's u and v taps (tap
@@ -186,6 +200,17 @@ __host__ __device__ inline uint2 pack_rec(int cu, int fu, int cv, int fv, int k)
   return make_uint2((uint32_t)cu | ((uint32_t)cv << 16),
                     (uint32_t)fu | ((uint32_t)fv << 8) | ((uint32_t)k << 16));
 }
+
+// ---- correction table as separable terms (corr_factor.cpp) ----
+// Factors C [P][Oc][Oc][Sc][Sc] (FP32) into at most max_rank separable terms
+// per plane with every residual entry within tol_rel of C's largest entry and
+// writes the terms' u and v tables ([rank][P][O][S] complex64, zero rows for
+// planes of lower rank; *shared: the terms are symmetric and tv equals tu).
+// Returns the rank (0 for an all-zero table), or -1 when max_rank terms do
+// not reach the tolerance.
+int factor_corr_table(const float2* C, int P, int O, int S, int Oc, int Sc, int max_rank,
+                      double tol_rel, std::vector<float2>* tu, std::vector<float2>* tv,
+                      bool* shared);
 
 // ---- host-side PSWF (pswf.cpp) ----
 // Legendre coefficients d_j (degree 2j, normalised Legendre basis) of psi_0(c, x)
@@ -359,6 +384,7 @@ struct DegridArgs {
   int N, ntx;
   int checker;              // the grid comes from the centred FFT: results times (-1)^(cu+cv)
   float2* yrow;             // results in row-bin order (padding slots are not written)
+  int accum = 0;            // add the results to yrow instead of storing them
 };
 
 // Precision form (FP16 / BF16).  Gridding reads the FP32 padded tables;

@@ -46,9 +46,14 @@ def _case(seed, N, S, O, P, n=2500, wmax=200.0, fov=1.0, spread=None):
     return rng, d
 
 
-def _make(lib, d, Sc, Oc, **kw):
+def _make(lib, d, Sc, Oc, form="terms", **kw):
     K = lib.Kernels(d["N"], d["fov"], d["S"], d["O"], d["P"], d["w_lo"], d["w_hi"], **kw)
     K.set_correction(Sc, Oc)
+    if form == "table":
+        K.correction_terms(False)
+        assert K.correction_rank() == -1
+    elif kw.get("precision", "fp32") == "fp32":
+        assert 1 <= K.correction_rank() <= 8
     plan = lib.Plan(K, dev(d["u"], torch.float64), dev(d["v"], torch.float64), dev(d["w"], torch.float64))
     return K, plan
 
@@ -114,10 +119,11 @@ APPLY_CASES = [
 ]
 
 
+@pytest.mark.parametrize("form", ["terms", "table"])
 @pytest.mark.parametrize("N,S,O,P,Sc,Oc", APPLY_CASES)
-def test_corrected_grid_matches_oracle(lib, N, S, O, P, Sc, Oc):
+def test_corrected_grid_matches_oracle(lib, N, S, O, P, Sc, Oc, form):
     _, d = _case(10 + Sc * Oc, N, S, O, P)
-    K, plan = _make(lib, d, Sc, Oc)
+    K, plan = _make(lib, d, Sc, Oc, form)
     G = lib.grid(plan, dev(d["V"], torch.complex64), dev(d["W"], torch.float32),
                  flags=lib.GRID_ONLY).cpu().numpy()
     o = OracleSetup(d["u"], d["v"], d["w"], N, d["fov"], S, O, P, d["w_lo"], d["w_hi"], plan.tile_size)
@@ -129,10 +135,11 @@ def test_corrected_grid_matches_oracle(lib, N, S, O, P, Sc, Oc):
     assert rel_rms(plain, want) > 1e3 * max(rel_rms(G, want), 1e-9)
 
 
+@pytest.mark.parametrize("form", ["terms", "table"])
 @pytest.mark.parametrize("N,S,O,P,Sc,Oc", APPLY_CASES)
-def test_corrected_degrid_matches_oracle(lib, N, S, O, P, Sc, Oc):
+def test_corrected_degrid_matches_oracle(lib, N, S, O, P, Sc, Oc, form):
     rng, d = _case(20 + Sc * Oc, N, S, O, P)
-    K, plan = _make(lib, d, Sc, Oc)
+    K, plan = _make(lib, d, Sc, Oc, form)
     G = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
     V = lib.degrid(plan, dev(G, torch.complex64), flags=lib.GRID_ONLY).cpu().numpy()
     o = OracleSetup(d["u"], d["v"], d["w"], N, d["fov"], S, O, P, d["w_lo"], d["w_hi"], plan.tile_size)
@@ -140,9 +147,10 @@ def test_corrected_degrid_matches_oracle(lib, N, S, O, P, Sc, Oc):
     assert rel_rms(V, oracle.correction.degrid(o.q, G, o.Tu, C, N, S, O, Sc, Oc)) <= 1e-5
 
 
-def test_corrected_image_and_prediction(lib):
+@pytest.mark.parametrize("form", ["terms", "table"])
+def test_corrected_image_and_prediction(lib, form):
     rng, d = _case(31, 64, 9, 8, 4)
-    K, plan = _make(lib, d, 7, 8)
+    K, plan = _make(lib, d, 7, 8, form)
     o = OracleSetup(d["u"], d["v"], d["w"], 64, d["fov"], 9, 8, 4, d["w_lo"], d["w_hi"], plan.tile_size)
     C = _oracle_table(d, 7, 8, o.c1)
     img = lib.grid(plan, dev(d["V"], torch.complex64), dev(d["W"], torch.float32),
@@ -224,3 +232,44 @@ def test_correction_argument_checks(lib):
     assert e.value.code == lib.ERR_UNSUPPORTED
     with pytest.raises(ValueError):
         Ku.correction_table()
+
+
+def test_correction_terms_at_three_degrees(lib):
+    # at a 3 degree field the exponent gap is l^2 m^2 and the two fourth
+    # powers: three separable terms per plane
+    fov = math.radians(3.0)
+    K = lib.Kernels(256, fov, 15, 8, 8, -28000.0, 28000.0)
+    K.set_correction(13, 8)
+    assert K.correction_rank() == 3
+    K.correction_terms(False)
+    assert K.correction_rank() == -1
+    K.correction_terms(True)
+    assert K.correction_rank() == 3
+    # a plane at w = 0 has no correction: no terms
+    Z = lib.Kernels(32, 0.3, 7, 8, 1, -5.0, 5.0)
+    Z.set_correction(5, 4)
+    assert Z.correction_rank() == 0
+    # the 16-bit kernels walk the table
+    H = lib.Kernels(64, 1.0, 7, 8, 4, -200.0, 200.0, precision="fp16")
+    H.set_correction(5, 8)
+    assert H.correction_rank() == -1
+
+
+@pytest.mark.parametrize("form", ["terms", "table"])
+def test_corrected_step_at_three_degrees(lib, form):
+    # the terms reproduce the table's footprints where the correction is tiny
+    # (about 1e-7 of the separable kernel): both forms equal the oracle
+    rng = np.random.default_rng(71)
+    N, fov, S, O, P = 256, math.radians(3.0), 15, 8, 8
+    n = 4000
+    d = dict(u=rng.uniform(-120, 120, n) / fov, v=rng.uniform(-120, 120, n) / fov,
+             w=rng.uniform(-28000.0, 28000.0, n),
+             V=rng.standard_normal(n) + 1j * rng.standard_normal(n), W=rng.uniform(0.5, 2.0, n),
+             N=N, fov=fov, S=S, O=O, P=P, w_lo=-28000.0, w_hi=28000.0)
+    K, plan = _make(lib, d, 13, 8, form)
+    G = lib.grid(plan, dev(d["V"], torch.complex64), dev(d["W"], torch.float32),
+                 flags=lib.GRID_ONLY).cpu().numpy()
+    o = OracleSetup(d["u"], d["v"], d["w"], N, fov, S, O, P, d["w_lo"], d["w_hi"], plan.tile_size)
+    C = _oracle_table(d, 13, 8, o.c1)
+    want = oracle.correction.grid(o.q, d["V"] * d["W"], o.Tu, C, N, S, O, 13, 8)
+    assert rel_rms(G, want) <= 1e-5

@@ -123,6 +123,9 @@ def test_null_handles_rejected(lib):
     assert lib.sepw_kernels_set_correction(None, 5, 8, None) == -1
     assert lib.sepw_kernels_set_correction(None, 0, 0, None) == -1
     assert lib.sepw_kernels_correction_table(None, None, None) == -1
+    assert lib.sepw_kernels_correction_terms(None, 1, None) == -1
+    rank = ctypes.c_int32(0)
+    assert lib.sepw_kernels_correction_rank(None, ctypes.byref(rank)) == -1
     assert lib.sepw_plan_create_channels(None, 10, 4, None, None, None, None, ctypes.byref(h)) == -1
     assert lib.sepw_plan_rebin_channels(None, 10, 4, None, None, None, None) == -1
     assert lib.sepw_wsnap_create(None, 2, None, None, None, None, None, None, ctypes.byref(h)) == -1
