@@ -273,3 +273,31 @@ def test_corrected_step_at_three_degrees(lib, form):
     C = _oracle_table(d, 13, 8, o.c1)
     want = oracle.correction.grid(o.q, d["V"] * d["W"], o.Tu, C, N, S, O, 13, 8)
     assert rel_rms(G, want) <= 1e-5
+
+
+@pytest.mark.parametrize("P", [4, 80])
+def test_corrected_asymmetric_axes(lib, P):
+    # screens that differ per axis: the terms take the general (two-table)
+    # form; at 80 planes a term's two tables no longer fit LDS together
+    ax = dict(a=0.43, b=0.1, a_v=0.61, b_v=0.3)
+    rng, d = _case(81 + P, 64, 7, 8, P)
+    K, plan = _make(lib, d, 5, 8, **ax)
+    assert 1 <= K.correction_rank() <= 8
+    o = OracleSetup(d["u"], d["v"], d["w"], 64, d["fov"], 7, 8, P, d["w_lo"], d["w_hi"],
+                    plan.tile_size)
+    wc = oracle.tables.w_plane_centres(P, d["w_lo"], d["w_hi"])
+    Tu = oracle.tables.separable_table(wc, 64, d["fov"], 7, 8, o.c1, a=ax["a"], b=ax["b"])
+    Tv = oracle.tables.separable_table(wc, 64, d["fov"], 7, 8, o.c1, a=ax["a_v"], b=ax["b_v"])
+    C = _oracle_table(d, 5, 8, o.c1, **ax)
+    qc = oracle.correction.coarse_bins(o.q, 8, 8)
+    y = d["V"] * d["W"]
+    want = (oracle.gridder.grid_separable(o.q, y, Tu, 64, 7, Tv=Tv)
+            + oracle.gridder.grid_exact(qc, y, C, 64, 5))
+    G = lib.grid(plan, dev(d["V"], torch.complex64), dev(d["W"], torch.float32),
+                 flags=lib.GRID_ONLY).cpu().numpy()
+    assert rel_rms(G, want) <= 1e-5
+    X = rng.standard_normal((64, 64)) + 1j * rng.standard_normal((64, 64))
+    wantv = (oracle.gridder.degrid_separable(o.q, X, Tu, 64, 7, Tv=Tv)
+             + oracle.gridder.degrid_exact(qc, X, C, 64, 5))
+    V = lib.degrid(plan, dev(X, torch.complex64), flags=lib.GRID_ONLY).cpu().numpy()
+    assert rel_rms(V, wantv) <= 1e-5
