@@ -344,10 +344,10 @@ int sepw_wstack_create(sepw_kernels k, int32_t n_slices, double w_lo, double w_h
  * centre w_s = (e_s + e_{s+1}) / 2.  Each non-empty slice gets tables of its
  * own: k's parameters (N, fov, S, O, P, taper, precision) with the w range
  * [-h_s, h_s], h_s = (e_{s+1} - e_s) / 2, so a narrow slice has finely spaced
- * planes; k's own w range is not used.  The object holds those kernels (each
- * with its FFT plan and an N x N work array) besides the plans; in FP32 the
- * slices are degridded in one batched launch that reads each slice's tables
- * through the caches.  Everything else as sepw_wstack_create; the object is
+ * planes; k's own w range is not used.  The object holds those slices'
+ * tables (with k's taper, FFT plan and work array) besides the plans; in
+ * FP32 the slices are degridded in one batched launch that reads each slice's
+ * tables through the caches.  Everything else as sepw_wstack_create; the object is
  * used with sepw_wstack_grid / _degrid / sepw_free_wstack.
  * Errors: SEPW_ERR_ARG (null k, edges or out, facet kernels, n_slices outside
  * [1, 4096], edges not finite and increasing, nvis out of range),

@@ -177,7 +177,7 @@ void destroy_kernels(Kernels* k) {
   k->tab_v = nullptr;
   dfree(k->tab_u);
   dfree(k->c1);
-  dfree(k->scratch);
+  if (!k->borrowed) dfree(k->scratch);
   if (k->pad_v && k->pad_v != k->pad_u) dfree(k->pad_v);
   k->pad_v = nullptr;
   dfree(k->pad_u);
@@ -190,7 +190,7 @@ void destroy_kernels(Kernels* k) {
   dfree(k->corr);
   dfree(k->corr_tmp);
   free_corr_terms(k);
-  if (k->fft_ok) hipfftDestroy(k->fft);
+  if (k->fft_ok && !k->borrowed) hipfftDestroy(k->fft);
   delete static_cast<sepw_kernels_s*>(k);
 }
 
@@ -454,7 +454,11 @@ int corr_degrid_pass(Plan* p, const float2* grid, int checker, hipStream_t s) {
   return SEPW_OK;
 }
 
-int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K) {
+// share: null, or a kernels object with the same N, fov and taper whose taper
+// samples are copied and whose FFT plan and work grid are used, not made (the
+// tables of W-stacking slices; share outlives K).
+int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K,
+                  const Kernels* share = nullptr) {
   K->prm = *p;
   K->prm.taper_samples = nullptr;
   K->N = p->grid_size;
@@ -485,7 +489,9 @@ int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K) {
 
   const int N = K->N;
   SEPW_TRY(dalloc(&K->c1, N));
-  if (p->taper == SEPW_TAPER_NONE) {
+  if (share) {
+    SEPW_TRY(hipMemcpyAsync(K->c1, share->c1, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  } else if (p->taper == SEPW_TAPER_NONE) {
     SEPW_TRY(launch_ones(K->c1, N, s));
   } else if (p->taper == SEPW_TAPER_USER) {
     SEPW_TRY(hipMemcpyAsync(K->c1, p->taper_samples, sizeof(double) * N, hipMemcpyHostToDevice, s));
@@ -534,7 +540,12 @@ int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K) {
     }
   }
   SEPW_TRY(make_tables(K, s));
-  SEPW_TRY(dalloc(&K->scratch, (int64_t)N * N));
+  if (share) {
+    K->scratch = share->scratch;
+    K->borrowed = true;
+  } else {
+    SEPW_TRY(dalloc(&K->scratch, (int64_t)N * N));
+  }
   // stage the FP32 tables in LDS when both fit in one workgroup's share
   {
     int dev = 0, max_lds = 0, ncu = 0;
@@ -548,7 +559,11 @@ int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K) {
     const int64_t lp_bytes = (int64_t)sizeof(uint32_t) * nlp * (shared_axes ? 1 : 2);
     K->lds_bytes_lp = lp_bytes <= (int64_t)max_lds ? (int)lp_bytes : 0;
   }
-  if (hipfftPlan2d(&K->fft, N, N, HIPFFT_C2C) != HIPFFT_SUCCESS) return SEPW_ERR_FFT;
+  if (share) {
+    K->fft = share->fft;
+  } else if (hipfftPlan2d(&K->fft, N, N, HIPFFT_C2C) != HIPFFT_SUCCESS) {
+    return SEPW_ERR_FFT;
+  }
   K->fft_ok = true;
   return SEPW_OK;
 }
@@ -937,20 +952,13 @@ int wstack_build(sepw_wstack_s* W, Kernels* K, int ns, double w_lo, double w_hi,
         sepw_kernels_s* k2 = new (std::nothrow) sepw_kernels_s();
         if (!k2) return SEPW_ERR_OOM;
         W->kern.push_back(k2);
+        // (K's taper samples, FFT plan and work grid)
         sepw_kernel_params prm = K->prm;
         const double hs = (edges[j + 1] - edges[j]) * 0.5;
         prm.w_lo = -hs;
         prm.w_hi = hs;
-        const bool user = prm.taper == SEPW_TAPER_USER;
-        if (user) prm.taper = SEPW_TAPER_NONE;   // K's taper samples are copied below
-        int rk = build_kernels(&prm, s, k2);
+        int rk = build_kernels(&prm, s, k2, K);
         if (rk != SEPW_OK) return rk;
-        if (user) {
-          k2->prm.taper = SEPW_TAPER_USER;
-          SEPW_TRY(hipMemcpyAsync(k2->c1, K->c1, sizeof(double) * (size_t)K->N,
-                                  hipMemcpyDeviceToDevice, s));
-          SEPW_TRY(make_tables(k2, s));
-        }
         KS = k2;
       }
       sepw_plan_s* P = new (std::nothrow) sepw_plan_s();

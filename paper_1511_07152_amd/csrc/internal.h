@@ -100,6 +100,7 @@ struct Kernels {
   int n_cu = 0;                // compute units of the device
   hipfftHandle fft = 0;
   bool fft_ok = false;
+  bool borrowed = false;       // fft and scratch belong to another kernels object
   uint64_t generation = 0;     // bumped when the tables are regenerated
   // correction table F_w - F~_w (0 support = none): [P][Oc][Oc][Sc][Sc] complex64,
   // taps (sv, su) with su fastest; corr_tmp = FP64 work space of its generation
