@@ -837,15 +837,29 @@ int degrid_images_batched(Kernels* K, Plan* const* plans, int nj, float2* grids,
     int rc = fft_exec(K, g, HIPFFT_FORWARD, s);
     if (rc != SEPW_OK) return rc;
   }
+  bool shared = true;
+  for (int j = 0; j < nj; ++j) shared = shared && plans[j]->K == K;
+  if (!shared && K->lds_bytes > 0) {
+    // jobs with tables of their own (non-uniform W-stacking slices): one
+    // launch per job, each with its tables in LDS (measured faster than one
+    // persistent launch reading every job's tables through the caches)
+    Stage st(SEPW_STAGE_DEGRID, s);
+    for (int j = 0; j < nj; ++j) {
+      const Plan* p = plans[j];
+      const DegridArgs a{p->dl.items, p->dl.itoff + 8 * p->r8, p->dl.itoff, p->r8, p->qctr,
+                         p->tdesc, p->krec, grids + (int64_t)j * N * N, p->K->pad_su,
+                         p->K->pad_sv, p->K->tab_len, N, p->ntx, 1, p->yrow};
+      SEPW_TRY(launch_fill_u32(p->qctr, 0u, 8 * kCtrStride, s));
+      SEPW_TRY(launch_degrid_fp32(K->S, a, p->dl.max_items, p->K->lds_bytes, K->n_cu, s));
+    }
+  } else {
   BatchScratch* bs = nullptr;
   int rc = batch_scratch(plans[0], nj, s, &bs);
   if (rc != SEPW_OK) return rc;
-  // the tables stay in LDS when every job uses K's; jobs with tables of
-  // their own (non-uniform W-stacking slices) read them through the caches
-  bool shared = true;
+  // the tables stay in LDS when every job uses K's; otherwise (tables too
+  // large for LDS) the jobs read them through the caches
   for (int j = 0; j < nj; ++j) {
     const Plan* p = plans[j];
-    shared = shared && p->K == K;
     bs->dhost[j] = DegridArgs{p->dl.items, p->dl.itoff + 8 * p->r8, p->dl.itoff, p->r8, p->qctr,
                               p->tdesc, p->krec, grids + (int64_t)j * N * N, p->K->pad_su,
                               p->K->pad_sv, p->K->tab_len, N, p->ntx, 1, p->yrow};
@@ -858,6 +872,7 @@ int degrid_images_batched(Kernels* K, Plan* const* plans, int nj, float2* grids,
     SEPW_TRY(launch_job_prefix(bs->djobs, nj, bs->first, bs->counter, s));
     SEPW_TRY(launch_degrid_fp32_batched(K->S, bs->djobs, bs->first, nj, bs->counter,
                                         shared ? K->lds_bytes : 0, K->n_cu, s));
+  }
   }
   for (int j = 0; j < nj; ++j) {
     Plan* p = plans[j];
