@@ -761,7 +761,7 @@ struct BatchScratch {
   DegridArgs* dhost = nullptr;  // pinned degridding job table
   DegridArgs* djobs = nullptr;  // device
   uint32_t* first = nullptr;    // device [cap + 1]
-  uint32_t* counter = nullptr;  // device
+  uint32_t* counter = nullptr;  // device [8 kCtrStride]: the launch's work counters
   hipEvent_t copied = nullptr;
   int n_cu = 0;
 };
@@ -804,7 +804,7 @@ int batch_scratch(Plan* lead, int njobs, hipStream_t s, BatchScratch** out) {
     SEPW_TRY(dalloc(&b.mjobs, cap));
     SEPW_TRY(dalloc(&b.mfirst, cap + 1));
     SEPW_TRY(dalloc(&b.first, cap + 1));
-    SEPW_TRY(dalloc(&b.counter, 1));
+    SEPW_TRY(dalloc(&b.counter, 8 * kCtrStride));
     SEPW_TRY(hipEventCreateWithFlags(&b.copied, hipEventDisableTiming));
     hipDeviceProp_t prop;
     SEPW_TRY(hipGetDeviceProperties(&prop, dev));
@@ -1104,7 +1104,8 @@ struct NoAllocArea {
   MoveArgs mjobs[kNoAllocMaxJobs];     // movement jobs, caller order
   uint32_t first[kNoAllocMaxJobs + 1];   // prefix of work items per job
   uint32_t mfirst[kNoAllocMaxJobs + 1];  // first movement workgroup per job
-  alignas(256) uint32_t counter;       // work counter of the persistent launch (own cache line)
+  alignas(256) uint32_t counter[8 * kCtrStride];   // work counters of the persistent launch
+                                                   // (eight, each in a cache line of its own)
 };
 
 }  // namespace
@@ -1700,8 +1701,8 @@ int sepw_grid_batched_noalloc(int32_t njobs, const sepw_plan* plans, const sepw_
   SEPW_TRY(launch_vis_to_rows_batched(area->mjobs, area->mfirst, njobs, mtotal, s));
   for (int j = 0; j < njobs; ++j)
     SEPW_TRY(launch_zero_c64(reinterpret_cast<float2*>(out[j]), (int64_t)N * N, s));
-  SEPW_TRY(launch_job_prefix(area->jobs, njobs, area->first, &area->counter, s));
-  SEPW_TRY(launch_grid_fp32_batched(S, area->jobs, area->first, njobs, &area->counter,
+  SEPW_TRY(launch_job_prefix(area->jobs, njobs, area->first, area->counter, s));
+  SEPW_TRY(launch_grid_fp32_batched(S, area->jobs, area->first, njobs, area->counter,
                                     plans[0]->K->n_cu * plans[0]->blocks_per_cu, s));
   for (int j = 0; j < njobs; ++j) {
     rc = corr_grid_pass(plans[j], reinterpret_cast<float2*>(out[j]), grid_only ? 0 : 1, s);

@@ -229,7 +229,7 @@ __global__ void job_prefix_kernel(const Args* __restrict__ jobs, int njobs,
     acc += *jobs[j].nitems;
     first[j + 1] = acc;
   }
-  *counter = 0u;
+  for (int q = 0; q < 8; ++q) counter[q * kCtrStride] = 0u;
 }
 
 __global__ void dropped_kernel(const uint32_t* __restrict__ kept, int64_t nvis,

@@ -295,7 +295,7 @@ __global__ __launch_bounds__(LDS ? 1024 : 256) void degrid_fp32_batched_kernel(
     tu_tab = smem;
   }
   const int lane = threadIdx.x & 63;
-  for_counter(counter, first[njobs], lane, [&](uint32_t gi) {
+  for_blocks8(counter, first[njobs], lane, [&](uint32_t gi) {
     int lo = 0, hi = njobs - 1;   // last job with first[job] <= gi
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;

@@ -250,9 +250,9 @@ __global__ __launch_bounds__(64 * kWaves) void grid_fp32_kernel(GridArgs a) {
 }
 
 // Persistent launch over the work items of many jobs (facets, snapshots):
-// waves take (job, item) pairs from one atomic counter over the concatenated
-// item lists (jobs ordered by decreasing size on the host), so uneven jobs
-// share the GPU without a launch per job.
+// waves take (job, item) pairs from the concatenated item lists (jobs ordered
+// by decreasing size on the host) through eight block counters, so uneven
+// jobs share the GPU without a launch per job.
 template <int S>
 __global__ __launch_bounds__(64 * kWaves) void grid_fp32_batched_kernel(
     const GridArgs* __restrict__ jobs, const uint32_t* __restrict__ first, int njobs,
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(64 * kWaves) void grid_fp32_batched_kernel(
   const int lane = threadIdx.x & 63;
   float* ring = rings + (threadIdx.x >> 6) * kRingFloats;
   for (int i = lane; i < kRingFloats; i += 64) ring[i] = 0.f;
-  for_counter(counter, first[njobs], lane, [&](uint32_t gi) {
+  for_blocks8(counter, first[njobs], lane, [&](uint32_t gi) {
     int lo = 0, hi = njobs - 1;   // last job with first[job] <= gi
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;

@@ -432,10 +432,11 @@ hipError_t launch_grid_fp32(int S, const GridArgs& a, int64_t max_items, hipStre
 hipError_t launch_grid_fp32_lds(int S, const GridArgs& a, int lds_bytes, int n_cu,
                                 hipStream_t s);
 // persistent launch over the items of njobs jobs; first[njobs + 1] = prefix of
-// per-job item counts (device), counter = zeroed device word
+// per-job item counts (device), counter = 8 zeroed counters kCtrStride apart
 hipError_t launch_grid_fp32_batched(int S, const GridArgs* jobs, const uint32_t* first, int njobs,
                                     uint32_t* counter, int blocks, hipStream_t s);
-// first[j + 1] = first[j] + *jobs[j].nitems, first[0] = 0; counter = 0
+// first[j + 1] = first[j] + *jobs[j].nitems, first[0] = 0; the 8 counters
+// (kCtrStride apart) = 0
 hipError_t launch_job_prefix(const GridArgs* jobs, int njobs, uint32_t* first, uint32_t* counter,
                              hipStream_t s);
 hipError_t launch_job_prefix(const DegridArgs* jobs, int njobs, uint32_t* first, uint32_t* counter,

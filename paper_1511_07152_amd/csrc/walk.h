@@ -116,6 +116,32 @@ __device__ inline void for_counter(uint32_t* __restrict__ ctr, uint32_t n, int l
   }
 }
 
+// Items [0, n) in eight contiguous blocks, block q claimed through counter q
+// (kCtrStride dwords apart, all zero at launch): a wave takes the block of
+// its XCD first, then the others in turn, so the claims of a launch spread
+// over eight cache lines and each XCD works on consecutive items while its
+// block lasts.  Every item is taken exactly once.
+template <class F>
+__device__ inline void for_blocks8(uint32_t* __restrict__ ctr, uint32_t n, int lane, F&& body) {
+  const int x = uniform(xcd_id());
+  const uint32_t per = (n + 7) / 8;
+  for (int l = 0; l < 8; ++l) {
+    const int q = (x + l) & 7;
+    uint32_t* c = ctr + q * kCtrStride;
+    const uint32_t lo = min((uint32_t)q * per, n), hi = min(lo + per, n);
+    // a plain read first: blocks that are already used up cost no atomic
+    if (lo + __atomic_load_n(c, __ATOMIC_RELAXED) >= hi) continue;
+    while (true) {
+      uint32_t k = 0;
+      if (lane == 0) k = atomicAdd(c, (uint32_t)kClaim);
+      k = (uint32_t)uniform((int)__shfl((int)k, 0, 64));
+      if (lo + k >= hi) break;
+      const uint32_t e = min(lo + k + (uint32_t)kClaim, hi);
+      for (uint32_t i = lo + k; i < e; ++i) body(i);
+    }
+  }
+}
+
 template <class F>
 __device__ inline void for_items(const uint32_t* __restrict__ lists, int r8,
                                  uint32_t* __restrict__ ctr, int lane, F&& body) {
