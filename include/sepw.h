@@ -302,8 +302,8 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
 /* sepw_grid_batched for callers that cannot allocate memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid allocation): the
  * same jobs, flags, output and errors, but the job tables, the per-job work
- * prefix and the work counter live in one static device array of the library
- * (about 48 KB; each GPU the library runs on holds its own copy until the
+ * prefix and the work counters live in one static device array of the library
+ * (about 51 KB; each GPU the library runs on holds its own copy until the
  * process ends), written by a small kernel from kernel arguments, so the call
  * makes no hipMalloc, hipFree, pinned-host or other allocating call.  At most
  * 256 jobs: njobs > 256 returns SEPW_ERR_UNSUPPORTED with no device work.
