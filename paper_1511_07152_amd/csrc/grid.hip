@@ -508,7 +508,7 @@ __global__ __launch_bounds__(64 * kLdsWaves) void grid_fp32_lds_kernel(GridArgs 
   const char* tu = reinterpret_cast<const char*>(smem);
   const char* tv = reinterpret_cast<const char*>(two ? smem + n : smem);
   const int lane = threadIdx.x & 63;
-  for_counter(a.qctr, (uint32_t)uniform((int)*a.nitems), lane,
+  for_blocks8(a.qctr, (uint32_t)uniform((int)*a.nitems), lane,
               [&](uint32_t it) { grid_item_lds<S>(a, tu, tv, (int)it, lane); });
 }
 

@@ -412,7 +412,7 @@ __global__ __launch_bounds__(64 * (LDS ? lds_waves_grid(BF16) : kWaves)) void gr
   c.grp = lane >> 4;
   c.col8 = c.col << 3;
   c.ys = BF16 ? 1.f : ldexpf(1.f, 13 - exp_above(*a.vmax));
-  for_counter(a.qctr, (uint32_t)uniform((int)*a.nitems), lane,
+  for_blocks8(a.qctr, (uint32_t)uniform((int)*a.nitems), lane,
               [&](uint32_t it) { grid_lp_item<S, BF16>(a, c, (int)it); });
 }
 
