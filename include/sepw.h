@@ -392,7 +392,7 @@ int sepw_wstack_degrid(sepw_wstack ws, const sepw_c64* image, sepw_c64* vis_out,
 
 /* Length of the plan's gridding work items: the number of tile slots
  * (visibilities, each tile padded to whole groups of 4) of one row of tiles
- * that one wave processes in order.  Default 2048; must be a multiple of 4 in
+ * that one wave processes in order.  Default 1024; must be a multiple of 4 in
  * [64, 8192].  Rebuilds the plan's gridding work list asynchronously on the
  * stream (it waits for the stream once when the list has to grow); later
  * rebins keep the length.  Used by sepw_grid and sepw_grid_batched.

@@ -22,7 +22,7 @@ constexpr int kMaxCorrRank = 8;    // separable terms of a factored correction t
 constexpr int kWideRegion = 32;
 constexpr int kMaxWideSupport = 31;
 __host__ __device__ inline bool wide_support(int S) { return S > kMaxSupport; }
-constexpr int kItemMaxVis = 2048;  // default slots per gridding work item (a slice of a tile row)
+constexpr int kItemMaxVis = 1024;  // default slots per gridding work item (a slice of a tile row)
 constexpr int kDegridItemSlots = 224;  // default slots per degridding work item
 constexpr int kItemMinSlots = 64;  // range of the tunable item length
 constexpr int kItemMaxSlots = 8192;
