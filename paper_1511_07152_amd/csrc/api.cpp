@@ -177,7 +177,10 @@ void destroy_kernels(Kernels* k) {
   k->tab_v = nullptr;
   dfree(k->tab_u);
   dfree(k->c1);
-  if (!k->borrowed) dfree(k->scratch);
+  if (!k->borrowed) {
+    dfree(k->scratch);
+    dfree(k->g16);
+  }
   if (k->pad_v && k->pad_v != k->pad_u) dfree(k->pad_v);
   k->pad_v = nullptr;
   dfree(k->pad_u);
@@ -542,9 +545,16 @@ int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K,
   SEPW_TRY(make_tables(K, s));
   if (share) {
     K->scratch = share->scratch;
+    K->g16 = share->g16;
     K->borrowed = true;
   } else {
     SEPW_TRY(dalloc(&K->scratch, (int64_t)N * N));
+    if (p->precision == SEPW_FP16 && !wide_support(K->S)) {
+      // the FP16 degridding operand grid; its border stays zero
+      const int64_t pitch = N + 2 * kG16Border;
+      SEPW_TRY(dalloc(&K->g16, pitch * pitch));
+      SEPW_TRY(launch_fill_u32(K->g16, 0u, pitch * pitch, s));
+    }
   }
   // stage the FP32 tables in LDS when both fit in one workgroup's share
   {
@@ -1535,6 +1545,11 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
       DegridArgsLp a{p->dl.items, p->dl.itoff, p->r8, p->qctr, p->tdesc, p->krec, src, K->lp_u,
                      K->lp_v, K->tab_len, p->lp_max + 1, N, p->ntx, checker, p->yrow,
                      p->pcap, p->capacity + 1};
+      if (!bf16) {
+        if (!K->g16) return SEPW_ERR_UNSUPPORTED;   // FP16 kernels always hold it
+        SEPW_TRY(launch_f16_grid(src, N, p->lp_max + 1, checker, K->g16, s));
+        a.g16 = K->g16;
+      }
       SEPW_TRY(launch_degrid_lp(K->S, bf16, a, K->lds_bytes_lp, K->n_cu, s));
     }
   }

@@ -50,7 +50,10 @@
 // Lane (c, g) holds W[4 g + r][c], so the diagonal W[c][c] sits in lane
 // (c, c / 4), register c % 4.  With the grid from the centred FFT the region
 // carries (-1)^(x+y) itself (applied with the scale when it is converted),
-// so the tables are the plain ones.
+// so the tables are the plain ones.  FP16 takes A1 from an operand grid
+// converted once per call (scale, sign and rounding as the per-region
+// conversion, a zero border instead of bounds checks); BF16 converts each
+// region's FP32 values (high and low parts) when it is used.
 //
 // Layout of v_mfma_f32_16x16x32: lane l supplies A[l % 16][8 (l / 16) + i]
 // and B[8 (l / 16) + i][l % 16], i = 0..7, two 16-bit values per dword (low
@@ -590,8 +593,33 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, const DCtx
       if (a.checker) f = -f;
     }
   };
-  // raw region of the next tile, loaded one chunk ahead
+  // FP16: the region comes ready from the operand grid (scaled, signed, a
+  // zero border around the grid): one 16-byte load per lane, always in
+  // bounds, and (Im, -Re) by a half swap and a sign flip
+  const int pitch = a.N + 2 * kG16Border;
+  const __amdgpu_buffer_rsrc_t g16rs =
+      BF16 ? grs
+           : rsrc(a.g16 + (int64_t)(y0 + kG16Border) * pitch, (int64_t)16 * pitch * 4);
+  auto load16 = [&](u32x4& g, int tx) {
+    const uint32_t off = (uint32_t)(c.col * pitch + tx * C - H + 4 * c.grp + kG16Border) * 4u;
+    g = __builtin_amdgcn_raw_buffer_load_b128(g16rs, off, 0, 0);
+  };
+  auto take16 = [&](const u32x4& g) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      ra.h[m] = g[m];
+      rb.h[m] = ((g[m] >> 16) | (g[m] << 16)) ^ 0x80000000u;
+    }
+  };
+  // region of the next tile, loaded one chunk ahead (raw FP32 for BF16)
   float2 q[4];
+  u32x4 q16;
+  auto load_next = [&](int tx) {
+    if constexpr (BF16) load_region(q, tx); else load16(q16, tx);
+  };
+  auto use_next = [&](int tx) {
+    if constexpr (BF16) convert(q, tx); else take16(q16);
+  };
 
   // results of up to four chunks: lanes 16 j + col hold V[col] of chunk j of
   // the group, stored with one instruction (offset kOob: nothing to store)
@@ -647,15 +675,15 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, const DCtx
     cur = n1;
     n1 = n2;
     n2 = next_chunk(n2, tw, s_end, c.lane);
-    if (fresh) convert(q, cur.tx);
-    if (n1.ok && n1.tx != cur.tx) load_region(q, n1.tx);
+    if (fresh) use_next(cur.tx);
+    if (n1.ok && n1.tx != cur.tx) load_next(n1.tx);
     return true;
   };
 
-  // the first tile's region is converted at once; later ones are loaded one chunk ahead
-  load_region(q, cur.tx);
-  convert(q, cur.tx);
-  if (n1.ok && n1.tx != cur.tx) load_region(q, n1.tx);
+  // the first tile's region is taken at once; later ones are loaded one chunk ahead
+  load_next(cur.tx);
+  use_next(cur.tx);
+  if (n1.ok && n1.tx != cur.tx) load_next(n1.tx);
   DOps A, B;
   A.rec = dkey(c, cur, bt);
   dtaps<BF16>(c, A);
@@ -738,6 +766,23 @@ __global__ __launch_bounds__(256) void absmax_kernel(const float2* __restrict__ 
   }
 }
 
+// FP16 degridding operands of a whole grid (see launch_f16_grid): the same
+// products and rounding as the kernel's own conversion of a region.
+__global__ __launch_bounds__(256) void f16_grid_kernel(const float2* __restrict__ g, int N,
+                                                       const uint32_t* __restrict__ gmax,
+                                                       int checker, uint32_t* __restrict__ out) {
+  const int e = exp_above(*gmax);
+  const float gs = ldexpf(1.f, 9 - e);
+  const int64_t pitch = N + 2 * kG16Border;
+  const int64_t n = (int64_t)N * N;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int64_t y = i / N, x = i - y * N;
+    const float f = (checker && ((x + y) & 1)) ? -gs : gs;
+    const float2 v = g[i];
+    out[(y + kG16Border) * pitch + x + kG16Border] = Lp<false>::pack(v.x * f, v.y * f);
+  }
+}
+
 }  // namespace
 
 #define SEPW_LP_CASES(F, B, ...)                                \
@@ -774,6 +819,15 @@ hipError_t launch_degrid_lp(int S, bool bf16, const DegridArgsLp& a, int lds_byt
 }
 
 #undef SEPW_LP_CASES
+
+hipError_t launch_f16_grid(const float2* g, int N, const uint32_t* gmax, int checker,
+                           uint32_t* out, hipStream_t s) {
+  int64_t b = ((int64_t)N * N + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(f16_grid_kernel, dim3((unsigned)b), dim3(256), 0, s, g, N, gmax, checker, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_absmax(const float2* g, int64_t n, uint32_t* out, hipStream_t s) {
   int64_t b = (n + 255) / 256;

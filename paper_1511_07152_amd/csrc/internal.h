@@ -16,6 +16,7 @@ constexpr uint32_t kDropped = 0xFFFFFFFFu;
 constexpr int kRegion = 16;        // MFMA tile region edge (cells): core + S - 1
 constexpr int kMaxSupport = 15;    // S <= kRegion - 1 on the tiled MFMA path
 constexpr int kMaxCorrRank = 8;    // separable terms of a factored correction table
+constexpr int kG16Border = 16;     // zero border (cells) of the FP16 degridding operand grid
 // Supports 15 < S <= kMaxWideSupport take the per-visibility path (wide.hip):
 // plans keep the quantiser and the level-1 row bins with tiles of
 // kWideRegion + 1 - S cells, but no tile slots or work lists.
@@ -93,6 +94,9 @@ struct Kernels {
   // (gridding uses the FP32 padded tables)
   uint32_t* lp_u = nullptr;
   uint32_t* lp_v = nullptr;
+  // FP16 degridding: the grid as MFMA operands, (N + 2 kG16Border)^2 FP16
+  // (Re, Im) pairs with a zero border
+  uint32_t* g16 = nullptr;
   float2* scratch = nullptr;   // N*N complex64 work grid (degridding, real-output gridding)
   int tab_len = 0;             // entries of one padded table (P O L)
   int lds_bytes = 0;           // > 0: the FP32 kernels stage the tables in LDS
@@ -424,6 +428,7 @@ struct DegridArgsLp {
   float2* yrow;
   int64_t nslots;           // tile slots of krec
   int64_t ycap;             // entries of yrow
+  const uint32_t* g16 = nullptr;   // FP16: the grid as operands (launch_f16_grid), else null
 };
 
 hipError_t launch_grid_fp32(int S, const GridArgs& a, int64_t max_items, hipStream_t s);
@@ -450,6 +455,12 @@ hipError_t launch_degrid_lp(int S, bool bf16, const DegridArgsLp& a, int lds_byt
                             hipStream_t s);
 // atomic maximum of max |Re, Im| over n complex values into *out (float bits)
 hipError_t launch_absmax(const float2* g, int64_t n, uint32_t* out, hipStream_t s);
+// FP16 degridding operands of an N x N grid: cell (x, y) times the call's
+// scale 2^(9 - e) (e from *gmax as in the degridding kernel) and, with
+// checker, (-1)^(x + y), rounded to an FP16 (Re, Im) pair at (x + B, y + B)
+// of out (pitch N + 2B, B = kG16Border; the border is left as it is: zero)
+hipError_t launch_f16_grid(const float2* g, int N, const uint32_t* gmax, int checker,
+                           uint32_t* out, hipStream_t s);
 // zero-padded FP32 tables: out[k][fi][c - 1 + s] = tab[k][fi][s] * (scale ? scale[k] : 1),
 // times (-1)^s when alternate
 hipError_t launch_pad_table(const float2* tab, const float* scale, int P, int O, int S, float2* out,
