@@ -549,11 +549,12 @@ int build_kernels(const sepw_kernel_params* p, hipStream_t s, Kernels* K,
     K->borrowed = true;
   } else {
     SEPW_TRY(dalloc(&K->scratch, (int64_t)N * N));
-    if (p->precision == SEPW_FP16 && !wide_support(K->S)) {
-      // the FP16 degridding operand grid; its border stays zero
+    if (p->precision != SEPW_FP32 && !wide_support(K->S)) {
+      // the 16-bit degridding operand grid (BF16: two planes); its border stays zero
       const int64_t pitch = N + 2 * kG16Border;
-      SEPW_TRY(dalloc(&K->g16, pitch * pitch));
-      SEPW_TRY(launch_fill_u32(K->g16, 0u, pitch * pitch, s));
+      const int64_t n = pitch * pitch * (p->precision == SEPW_BF16 ? 2 : 1);
+      SEPW_TRY(dalloc(&K->g16, n));
+      SEPW_TRY(launch_fill_u32(K->g16, 0u, n, s));
     }
   }
   // stage the FP32 tables in LDS when both fit in one workgroup's share
@@ -1545,11 +1546,9 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
       DegridArgsLp a{p->dl.items, p->dl.itoff, p->r8, p->qctr, p->tdesc, p->krec, src, K->lp_u,
                      K->lp_v, K->tab_len, p->lp_max + 1, N, p->ntx, checker, p->yrow,
                      p->pcap, p->capacity + 1};
-      if (!bf16) {
-        if (!K->g16) return SEPW_ERR_UNSUPPORTED;   // FP16 kernels always hold it
-        SEPW_TRY(launch_f16_grid(src, N, p->lp_max + 1, checker, K->g16, s));
-        a.g16 = K->g16;
-      }
+      if (!K->g16) return SEPW_ERR_UNSUPPORTED;   // 16-bit kernels always hold it
+      SEPW_TRY(launch_lp_grid(src, N, bf16, p->lp_max + 1, checker, K->g16, s));
+      a.g16 = K->g16;
       SEPW_TRY(launch_degrid_lp(K->S, bf16, a, K->lds_bytes_lp, K->n_cu, s));
     }
   }

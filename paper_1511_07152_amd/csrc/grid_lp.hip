@@ -52,8 +52,8 @@
 // carries (-1)^(x+y) itself (applied with the scale when it is converted),
 // so the tables are the plain ones.  FP16 takes A1 from an operand grid
 // converted once per call (scale, sign and rounding as the per-region
-// conversion, a zero border instead of bounds checks); BF16 converts each
-// region's FP32 values (high and low parts) when it is used.
+// conversion, a zero border instead of bounds checks), BF16 its high and
+// low parts from two such planes.
 //
 // Layout of v_mfma_f32_16x16x32: lane l supplies A[l % 16][8 (l / 16) + i]
 // and B[8 (l / 16) + i][l % 16], i = 0..7, two 16-bit values per dword (low
@@ -454,7 +454,6 @@ struct DCtx {
   int tab_len;
   int col, grp, lane;
   int s0, last;
-  float gs;             // FP16: scale of the region
   float back;           // 1 / gs
 };
 
@@ -526,15 +525,7 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, const DCtx
   const int ty = uniform(item.x), s_end = uniform(item.z);
   c.s0 = uniform(item.y);
   c.last = s_end - 1;
-  // the item's 16 grid rows as one buffer resource
-  const int y0 = ty * C - H;
-  const int rb0 = max(y0, 0);
-  const int nrows = min(y0 + 16, N) - rb0;
-  const __amdgpu_buffer_rsrc_t grs =
-      rsrc(a.grid + (int64_t)rb0 * N, (int64_t)nrows * N * (int64_t)sizeof(float2));
-  const int gy = y0 + c.col;
-  const bool row_ok = gy >= 0 && gy < N;
-  const int rowbase = (min(max(gy, rb0), rb0 + nrows - 1) - rb0) * N;   // clamped row
+  const int y0 = ty * C - H;   // first grid row of the item's regions
   const int sel = c.col & 3;                 // register of the lane's diagonal element
   const bool diag = c.grp == (c.col >> 2);   // the lane that holds W[col][col]
   // lane holding V[col] of a chunk, for gathering four chunks' results
@@ -556,70 +547,38 @@ __device__ __forceinline__ void degrid_lp_item(const DegridArgsLp& a, const DCtx
   bt.rb = batch_load(c, 1);
   bt.rc = batch_load(c, 2);
 
-  // raw region values R[gy][x0 + 4 grp + m] of a tile: two 16-byte loads
-  // inside the grid, clamped single loads at its edges (values outside the
-  // grid get factor 0 when converted)
-  auto load_region = [&](float2 (&g)[4], int tx) {
-    const int gx0 = tx * C - H + 4 * c.grp;
-    if (tx * C - H >= 0 && tx * C - H + 16 <= N) {
-      const uint32_t off = (uint32_t)(rowbase + gx0) * 8u;
-      const u32x4 v0 = __builtin_amdgcn_raw_buffer_load_b128(grs, off, 0, 0);
-      const u32x4 v1 = __builtin_amdgcn_raw_buffer_load_b128(grs, off + 16u, 0, 0);
-      g[0] = make_float2(__uint_as_float(v0[0]), __uint_as_float(v0[1]));
-      g[1] = make_float2(__uint_as_float(v0[2]), __uint_as_float(v0[3]));
-      g[2] = make_float2(__uint_as_float(v1[0]), __uint_as_float(v1[1]));
-      g[3] = make_float2(__uint_as_float(v1[2]), __uint_as_float(v1[3]));
-    } else {
+  // region operands of the current tile: (Re R, Im R) and (Im R, -Re R)
+  Opnd ra, rb;
+  // The region comes from the operand grid (a.g16: scaled, signed, rounded,
+  // a zero border around the grid): one in-bounds 16-byte load per lane (two
+  // for BF16: high parts, then low parts one plane further), and (Im, -Re)
+  // a half swap and a sign flip of each pair
+  const int pitch = a.N + 2 * kG16Border;
+  const int64_t plane = (int64_t)pitch * pitch;
+  const uint32_t* g16row = a.g16 + (int64_t)(y0 + kG16Border) * pitch;
+  const __amdgpu_buffer_rsrc_t g16h = rsrc(g16row, (int64_t)16 * pitch * 4);
+  const __amdgpu_buffer_rsrc_t g16l = BF16 ? rsrc(g16row + plane, (int64_t)16 * pitch * 4) : g16h;
+  auto load16 = [&](u32x4& gh, u32x4& gl, int tx) {
+    const uint32_t off = (uint32_t)(c.col * pitch + tx * C - H + 4 * c.grp + kG16Border) * 4u;
+    gh = __builtin_amdgcn_raw_buffer_load_b128(g16h, off, 0, 0);
+    if constexpr (BF16) gl = __builtin_amdgcn_raw_buffer_load_b128(g16l, off, 0, 0);
+  };
+  auto swapneg = [](uint32_t v) { return ((v >> 16) | (v << 16)) ^ 0x80000000u; };
+  auto take16 = [&](const u32x4& gh, const u32x4& gl) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const uint32_t off = (uint32_t)(rowbase + min(max(gx0 + m, 0), N - 1)) * 8u;
-        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(grs, off, 0, 0);
-        g[m] = make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+    for (int m = 0; m < 4; ++m) {
+      ra.h[m] = gh[m];
+      rb.h[m] = swapneg(gh[m]);
+      if constexpr (BF16) {
+        ra.l[m] = gl[m];
+        rb.l[m] = swapneg(gl[m]);
       }
     }
   };
-  // region operands of the current tile: (Re R, Im R) and (Im R, -Re R)
-  Opnd ra, rb;
-  auto convert = [&](const float2 (&g)[4], int tx) {
-    // R (-1)^(x+y) times the scale, 0 outside the grid
-    const int gx0 = tx * C - H + 4 * c.grp;
-    float f = BF16 ? 1.f : c.gs;
-    if (a.checker && ((gx0 + gy) & 1)) f = -f;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int gx = gx0 + m;
-      const float fm = (row_ok && gx >= 0 && gx < N) ? f : 0.f;
-      set_pair<BF16>(ra, rb, m, g[m].x * fm, g[m].y * fm);
-      if (a.checker) f = -f;
-    }
-  };
-  // FP16: the region comes ready from the operand grid (scaled, signed, a
-  // zero border around the grid): one 16-byte load per lane, always in
-  // bounds, and (Im, -Re) by a half swap and a sign flip
-  const int pitch = a.N + 2 * kG16Border;
-  const __amdgpu_buffer_rsrc_t g16rs =
-      BF16 ? grs
-           : rsrc(a.g16 + (int64_t)(y0 + kG16Border) * pitch, (int64_t)16 * pitch * 4);
-  auto load16 = [&](u32x4& g, int tx) {
-    const uint32_t off = (uint32_t)(c.col * pitch + tx * C - H + 4 * c.grp + kG16Border) * 4u;
-    g = __builtin_amdgcn_raw_buffer_load_b128(g16rs, off, 0, 0);
-  };
-  auto take16 = [&](const u32x4& g) {
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      ra.h[m] = g[m];
-      rb.h[m] = ((g[m] >> 16) | (g[m] << 16)) ^ 0x80000000u;
-    }
-  };
-  // region of the next tile, loaded one chunk ahead (raw FP32 for BF16)
-  float2 q[4];
-  u32x4 q16;
-  auto load_next = [&](int tx) {
-    if constexpr (BF16) load_region(q, tx); else load16(q16, tx);
-  };
-  auto use_next = [&](int tx) {
-    if constexpr (BF16) convert(q, tx); else take16(q16);
-  };
+  // region of the next tile, loaded one chunk ahead
+  u32x4 qh, ql;
+  auto load_next = [&](int tx) { load16(qh, ql, tx); };
+  auto use_next = [&](int) { take16(qh, ql); };
 
   // results of up to four chunks: lanes 16 j + col hold V[col] of chunk j of
   // the group, stored with one instruction (offset kOob: nothing to store)
@@ -717,7 +676,6 @@ __global__ __launch_bounds__(64 * (LDS ? kLdsWaves : kWaves)) void degrid_lp_ker
   c.col = lane & 15;
   c.grp = lane >> 4;
   const int e = BF16 ? 0 : exp_above(*a.gmax);
-  c.gs = ldexpf(1.f, 9 - e);
   c.back = ldexpf(1.f, e - 9);
   for_items(a.lists, a.r8, a.qctr, lane, [&](int it) { degrid_lp_item<S, BF16>(a, c, it); });
 }
@@ -766,20 +724,26 @@ __global__ __launch_bounds__(256) void absmax_kernel(const float2* __restrict__ 
   }
 }
 
-// FP16 degridding operands of a whole grid (see launch_f16_grid): the same
-// products and rounding as the kernel's own conversion of a region.
-__global__ __launch_bounds__(256) void f16_grid_kernel(const float2* __restrict__ g, int N,
-                                                       const uint32_t* __restrict__ gmax,
-                                                       int checker, uint32_t* __restrict__ out) {
-  const int e = exp_above(*gmax);
-  const float gs = ldexpf(1.f, 9 - e);
+// 16-bit degridding operands of a whole grid (see launch_lp_grid): the same
+// products, rounding and (BF16) high / low split as the kernel's own
+// conversion of a region.
+template <bool BF16>
+__global__ __launch_bounds__(256) void lp_grid_kernel(const float2* __restrict__ g, int N,
+                                                      const uint32_t* __restrict__ gmax,
+                                                      int checker, uint32_t* __restrict__ out) {
+  typedef Lp<BF16> L;
+  const float gs = BF16 ? 1.f : ldexpf(1.f, 9 - exp_above(*gmax));
   const int64_t pitch = N + 2 * kG16Border;
   const int64_t n = (int64_t)N * N;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     const int64_t y = i / N, x = i - y * N;
     const float f = (checker && ((x + y) & 1)) ? -gs : gs;
     const float2 v = g[i];
-    out[(y + kG16Border) * pitch + x + kG16Border] = Lp<false>::pack(v.x * f, v.y * f);
+    const float a = v.x * f, b = v.y * f;
+    const int64_t o = (y + kG16Border) * pitch + x + kG16Border;
+    const uint32_t h = L::pack(a, b);
+    out[o] = h;
+    if constexpr (BF16) out[o + pitch * pitch] = L::pack(a - L::low(h), b - L::high(h));
   }
 }
 
@@ -820,12 +784,17 @@ hipError_t launch_degrid_lp(int S, bool bf16, const DegridArgsLp& a, int lds_byt
 
 #undef SEPW_LP_CASES
 
-hipError_t launch_f16_grid(const float2* g, int N, const uint32_t* gmax, int checker,
-                           uint32_t* out, hipStream_t s) {
+hipError_t launch_lp_grid(const float2* g, int N, bool bf16, const uint32_t* gmax, int checker,
+                          uint32_t* out, hipStream_t s) {
   int64_t b = ((int64_t)N * N + 255) / 256;
   if (b > 8192) b = 8192;
   if (b < 1) b = 1;
-  hipLaunchKernelGGL(f16_grid_kernel, dim3((unsigned)b), dim3(256), 0, s, g, N, gmax, checker, out);
+  if (bf16)
+    hipLaunchKernelGGL(lp_grid_kernel<true>, dim3((unsigned)b), dim3(256), 0, s, g, N, gmax,
+                       checker, out);
+  else
+    hipLaunchKernelGGL(lp_grid_kernel<false>, dim3((unsigned)b), dim3(256), 0, s, g, N, gmax,
+                       checker, out);
   return hipGetLastError();
 }
 

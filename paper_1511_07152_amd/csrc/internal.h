@@ -94,8 +94,8 @@ struct Kernels {
   // (gridding uses the FP32 padded tables)
   uint32_t* lp_u = nullptr;
   uint32_t* lp_v = nullptr;
-  // FP16 degridding: the grid as MFMA operands, (N + 2 kG16Border)^2 FP16
-  // (Re, Im) pairs with a zero border
+  // 16-bit degridding: the grid as MFMA operands, (N + 2 kG16Border)^2 16-bit
+  // (Re, Im) pairs with a zero border (BF16: high parts, then low parts)
   uint32_t* g16 = nullptr;
   float2* scratch = nullptr;   // N*N complex64 work grid (degridding, real-output gridding)
   int tab_len = 0;             // entries of one padded table (P O L)
@@ -418,7 +418,7 @@ struct DegridArgsLp {
   uint32_t* qctr;           // list counters, zero at launch
   const uint2* tdesc;
   const SlotRec* krec;
-  const float2* grid;
+  const float2* grid;       // the FP32 grid (the kernel reads g16, made from it)
   const uint32_t* lp_u;     // 16-bit padded tables
   const uint32_t* lp_v;
   int tab_len;
@@ -428,7 +428,7 @@ struct DegridArgsLp {
   float2* yrow;
   int64_t nslots;           // tile slots of krec
   int64_t ycap;             // entries of yrow
-  const uint32_t* g16 = nullptr;   // FP16: the grid as operands (launch_f16_grid), else null
+  const uint32_t* g16 = nullptr;   // the grid as operands (launch_lp_grid)
 };
 
 hipError_t launch_grid_fp32(int S, const GridArgs& a, int64_t max_items, hipStream_t s);
@@ -455,12 +455,13 @@ hipError_t launch_degrid_lp(int S, bool bf16, const DegridArgsLp& a, int lds_byt
                             hipStream_t s);
 // atomic maximum of max |Re, Im| over n complex values into *out (float bits)
 hipError_t launch_absmax(const float2* g, int64_t n, uint32_t* out, hipStream_t s);
-// FP16 degridding operands of an N x N grid: cell (x, y) times the call's
-// scale 2^(9 - e) (e from *gmax as in the degridding kernel) and, with
-// checker, (-1)^(x + y), rounded to an FP16 (Re, Im) pair at (x + B, y + B)
-// of out (pitch N + 2B, B = kG16Border; the border is left as it is: zero)
-hipError_t launch_f16_grid(const float2* g, int N, const uint32_t* gmax, int checker,
-                           uint32_t* out, hipStream_t s);
+// 16-bit degridding operands of an N x N grid: cell (x, y) times (FP16) the
+// call's scale 2^(9 - e) (e from *gmax as in the degridding kernel) and,
+// with checker, (-1)^(x + y), rounded to a 16-bit (Re, Im) pair at
+// (x + B, y + B) of out (pitch N + 2B, B = kG16Border; the border is left as
+// it is: zero); BF16 writes the low parts one plane ((N + 2B)^2) further
+hipError_t launch_lp_grid(const float2* g, int N, bool bf16, const uint32_t* gmax, int checker,
+                          uint32_t* out, hipStream_t s);
 // zero-padded FP32 tables: out[k][fi][c - 1 + s] = tab[k][fi][s] * (scale ? scale[k] : 1),
 // times (-1)^s when alternate
 hipError_t launch_pad_table(const float2* tab, const float* scale, int P, int O, int S, float2* out,
