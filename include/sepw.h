@@ -147,6 +147,9 @@ void sepw_default_params(sepw_kernel_params* p);
  * facet != 0 the axis coefficients are 1/2 (1/n0 + l0^2/n0^3) and
  * 1/2 (1/n0 + m0^2/n0^3) with b = 0 (Section 4.1).  c1 is the zeroth prolate
  * spheroidal wave function psi_0(pi W / 2, 2 l / fov), normalised to c1(0) = 1.
+ * Besides the tables the object holds an N x N complex64 work grid, a hipFFT
+ * plan and, for FP16 / BF16 kernels with S <= 15, the degridding operand grid
+ * ((N + 32)^2 dwords, two such planes for BF16; 68 MB at N = 4096).
  * Synchronises the stream once (host set-up of the taper coefficients).
  * Errors: SEPW_ERR_ARG for any out-of-range field, SEPW_ERR_NO_DEVICE,
  * SEPW_ERR_OOM, SEPW_ERR_HIP, SEPW_ERR_FFT.  *out is NULL on error. */
