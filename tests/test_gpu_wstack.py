@@ -211,3 +211,42 @@ def test_nonuniform_slices_reject_correction_tables(lib):
         lib.WStack(K, len(EDGES) - 1, 0.0, 0.0, dev(d["u"], torch.float64),
                    dev(d["v"], torch.float64), dev(d["w"], torch.float64), edges=EDGES)
     assert e.value.code == -5
+
+
+def test_wstack_with_correction_equals_its_slices(lib):
+    # the batched W-stacking launches with the correction (run as separable
+    # terms) give what single-plan calls give slice by slice
+    rng = np.random.default_rng(89)
+    N, fov, S, O, P, ns, wmax, n = 64, 1.0, 7, 8, 4, 3, 600.0, 3000
+    u = rng.uniform(-28, 28, n) / fov
+    v = rng.uniform(-28, 28, n) / fov
+    w = rng.uniform(-wmax, wmax, n)
+    V = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    h = wmax / ns
+    K = lib.Kernels(N, fov, S, O, P, -h, h)
+    K.set_correction(5, 8)
+    assert K.correction_rank() >= 1
+    ws = lib.WStack(K, ns, -wmax, wmax, dev(u, torch.float64), dev(v, torch.float64),
+                    dev(w, torch.float64))
+    s, ws_c, dw = oracle.wstack.slice_of(w, ns, -wmax, wmax)
+    X = np.zeros((N, N), complex)
+    X[N // 4:3 * N // 4, N // 4:3 * N // 4] = rng.standard_normal((N // 2, N // 2))
+    img = np.zeros((N, N), complex)
+    Vs = np.zeros(n, complex)
+    for k in range(ns):
+        idx = np.flatnonzero(s == k)
+        p = lib.Plan(K, dev(u[idx], torch.float64), dev(v[idx], torch.float64),
+                     dev(dw[idx], torch.float64))
+        g = lib.grid(p, dev(V[idx], torch.complex64), None, flags=lib.MUL_N).cpu().numpy()
+        img += oracle.wstack.slice_phase(N, fov, ws_c[k], +1) * g
+        Xk = X * oracle.wstack.slice_phase(N, fov, ws_c[k], -1)
+        Vs[idx] = lib.degrid(p, dev(Xk, torch.complex64), flags=lib.DIV_N).cpu().numpy()
+    got = ws.grid(dev(V, torch.complex64), None, flags=lib.MUL_N).cpu().numpy()
+    assert rel_rms(inner(got), inner(img)) <= 1e-5
+    gotv = ws.degrid(dev(X, torch.complex64), flags=lib.DIV_N).cpu().numpy()
+    assert rel_rms(gotv, Vs) <= 1e-5
+    # the correction is there: without it the prediction differs far more
+    K.set_correction(0, 0)
+    bare = lib.WStack(K, ns, -wmax, wmax, dev(u, torch.float64), dev(v, torch.float64),
+                      dev(w, torch.float64)).degrid(dev(X, torch.complex64), flags=lib.DIV_N)
+    assert rel_rms(bare.cpu().numpy(), Vs) > 1e-3
