@@ -109,11 +109,13 @@ __global__ __launch_bounds__(kThreads) void snap_residual_kernel(
   }
 }
 
-__device__ inline double keys(double t) {
-  t = fabs(t);
-  if (t <= 1.0) return (1.5 * t - 2.5) * t * t + 1.0;
-  if (t < 2.0) return ((-0.5 * t + 2.5) * t - 4.0) * t + 2.0;
-  return 0.0;
+// Keys' cubic convolution kernel (a = -1/2) at distance t, in FP32: the
+// weights are FP32 anyway, and t, at most 2 pixels, is formed in FP64 first.
+__device__ inline float keys(float t) {
+  t = fabsf(t);
+  if (t <= 1.f) return (1.5f * t - 2.5f) * t * t + 1.f;
+  if (t < 2.f) return ((-0.5f * t + 2.5f) * t - 4.f) * t + 2.f;
+  return 0.f;
 }
 
 struct Taps {
@@ -126,11 +128,12 @@ __device__ inline Taps taps(double x, int N) {
   const double x0 = floor(x);
   const double f = x - x0;
   t.i0 = (int)x0 - 1;
-  const double wd[4] = {keys(1.0 + f), keys(f), keys(1.0 - f), keys(2.0 - f)};
+  const float wd[4] = {keys((float)(1.0 + f)), keys((float)f), keys((float)(1.0 - f)),
+                        keys((float)(2.0 - f))};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int i = t.i0 + k;
-    t.wt[k] = (i >= 0 && i < N) ? (float)wd[k] : 0.f;
+    t.wt[k] = (i >= 0 && i < N) ? wd[k] : 0.f;
   }
   return t;
 }
@@ -310,7 +313,7 @@ __global__ __launch_bounds__(kGTile * kGTile) void snap_adjoint_gather_kernel(
       const int e = qq * kGBox + pp;
       const double dx = sx[e] - (double)jx, dy = sy[e] - (double)jy;
       if (fabs(dx) < 2.0 && fabs(dy) < 2.0) {
-        const float wgt = (float)keys(dy) * (float)keys(dx);
+        const float wgt = keys((float)dy) * keys((float)dx);
         ar += wgt * sv[e].x;
         ai += wgt * sv[e].y;
       }
