@@ -428,8 +428,11 @@ int sepw_autotune_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64*
 /* Regenerate the tables of k for a new w range (same P), asynchronously on
  * the stream: the per-batch form of table generation when the w-planes span
  * the batch's own +/- max|w|.  Plans created for the old range become invalid:
- * sepw_grid / sepw_degrid on them return SEPW_ERR_ARG.
- * Errors: SEPW_ERR_ARG (null k, non-finite or empty range), SEPW_ERR_HIP. */
+ * sepw_grid / sepw_degrid on them return SEPW_ERR_ARG.  With a correction
+ * table attached to FP32 kernels, factoring it into separable terms
+ * synchronises the stream.
+ * Errors: SEPW_ERR_ARG (null k, non-finite or empty range), SEPW_ERR_OOM,
+ * SEPW_ERR_HIP. */
 int sepw_kernels_set_wrange(sepw_kernels k, double w_lo, double w_hi, void* hip_stream);
 
 /* Optional per-stage timing for benchmarking: while enabled, every kernel the
