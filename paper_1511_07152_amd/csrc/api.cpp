@@ -831,16 +831,17 @@ int batch_scratch(Plan* lead, int njobs, hipStream_t s, BatchScratch** out) {
 
 // Degridding of nj FP32 plans (on kernels K, or on kernels of their own with
 // K's N, S, taper and no correction table) from images held in
-// grids (N x N each, consecutive): per plan the correction (times n^npow) and
-// the FFT in place, then ONE batched persistent degridding launch over the
-// plans' items, then per plan the correction-table pass and the move of its
-// results into vis[j] (its caller order).
+// grids (N x N each, consecutive): per plan the correction (times n^npow;
+// skipped when the images come corrected) and the FFT in place, then the
+// degridding launch(es) over the plans' items, then per plan the
+// correction-table pass and the move of its results into vis[j] (its caller
+// order).
 int degrid_images_batched(Kernels* K, Plan* const* plans, int nj, float2* grids, int npow,
-                          float2* const* vis, hipStream_t s) {
+                          float2* const* vis, hipStream_t s, bool corrected = false) {
   const int N = K->N;
   for (int j = 0; j < nj; ++j) {
     float2* g = grids + (int64_t)j * N * N;
-    {
+    if (!corrected) {
       Stage st(SEPW_STAGE_CORRECT, s);
       SEPW_TRY(launch_correct(g, g, K->c1, N, K->fov, K->l0, K->m0, npow, s));
     }
@@ -1564,6 +1565,13 @@ int sepw_degrid(sepw_plan p, const sepw_c64* in, sepw_c64* vis_out, uint32_t fla
   return SEPW_OK;
 }
 
+// Internal flag of grid_batched: grids as for a transform (the centred FFT's
+// checkerboard included) but no FFT and no correction (FP32 tiled jobs only).
+constexpr uint32_t kGridNoTransform = 0x40000000u;
+
+int grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* const* vis,
+                 const float* const* weight, sepw_c64* const* out, uint32_t flags, hipStream_t s);
+
 int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* const* vis,
                       const float* const* weight, sepw_c64* const* out, uint32_t flags,
                       void* hip_stream) {
@@ -1577,8 +1585,15 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
     if (K->N != K0->N || K->S != K0->S || K->prm.precision != K0->prm.precision) return SEPW_ERR_ARG;
     if (plans[j]->generation != K->generation) return SEPW_ERR_ARG;
   }
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  return grid_batched(njobs, plans, vis, weight, out, flags, static_cast<hipStream_t>(hip_stream));
+}
+
+// sepw_grid_batched after argument checks (flags may add kGridNoTransform)
+int grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* const* vis,
+                 const float* const* weight, sepw_c64* const* out, uint32_t flags, hipStream_t s) {
+  void* hip_stream = s;
   if (plans[0]->K->prm.precision != SEPW_FP32 || wide_support(plans[0]->K->S)) {
+    if (flags & kGridNoTransform) return SEPW_ERR_UNSUPPORTED;
     // the persistent launch is built for the FP32 path; other precisions go job by job
     for (int j = 0; j < njobs; ++j) {
       int rc = sepw_grid(plans[j], vis[j], weight ? weight[j] : nullptr, out[j], flags, hip_stream);
@@ -1638,7 +1653,7 @@ int sepw_grid_batched(int32_t njobs, const sepw_plan* plans, const sepw_c64* con
     rc = corr_grid_pass(plans[j], reinterpret_cast<float2*>(out[j]), grid_only ? 0 : 1, s);
     if (rc != SEPW_OK) return rc;
   }
-  if (grid_only) return SEPW_OK;
+  if (grid_only || (flags & kGridNoTransform)) return SEPW_OK;
   const int npow = (flags & SEPW_MUL_N) ? 1 : ((flags & SEPW_DIV_N) ? -1 : 0);
   for (int j = 0; j < njobs; ++j) {
     Kernels* K = plans[j]->K;
@@ -2019,13 +2034,25 @@ int sepw_wstack_grid(sepw_wstack ws, const sepw_c64* vis, const float* weight, s
       idx.push_back(j0);
     }
     if (idx.empty()) break;
-    int rc = sepw_grid_batched((int32_t)idx.size(), plans.data(), vs.data(), wts.data(),
-                               imgs.data(), flags, hip_stream);
+    // FP32 tiled: grids only, then per slice the FFT and one pass for the
+    // correction and the slice phase; otherwise images, then the phase
+    const bool fused = K->prm.precision == SEPW_FP32 && !wide_support(K->S);
+    const int npow = (flags & SEPW_MUL_N) ? 1 : ((flags & SEPW_DIV_N) ? -1 : 0);
+    int rc = fused ? grid_batched((int32_t)idx.size(), plans.data(), vs.data(), wts.data(),
+                                  imgs.data(), kGridNoTransform, s)
+                   : sepw_grid_batched((int32_t)idx.size(), plans.data(), vs.data(), wts.data(),
+                                       imgs.data(), flags, hip_stream);
     if (rc != SEPW_OK) return rc;
-    Stage st(SEPW_STAGE_CORRECT, s);
     for (size_t k = 0; k < idx.size(); ++k) {
-      SEPW_TRY(launch_slice_phase(reinterpret_cast<const float2*>(imgs[k]), out, K->N, K->fov,
-                                  ws->centre[idx[k]], +1, !first, s));
+      float2* img = reinterpret_cast<float2*>(imgs[k]);
+      if (fused) {
+        Stage st(SEPW_STAGE_FFT, s);
+        rc = fft_exec(static_cast<Plan*>(plans[k])->K, img, HIPFFT_BACKWARD, s);
+        if (rc != SEPW_OK) return rc;
+      }
+      Stage st(SEPW_STAGE_CORRECT, s);
+      SEPW_TRY(launch_slice_phase(img, out, K->N, K->fov, ws->centre[idx[k]], +1, !first,
+                                  fused ? K->c1 : nullptr, npow, s));
       first = false;
     }
   }
@@ -2045,7 +2072,7 @@ int sepw_wstack_degrid(sepw_wstack ws, const sepw_c64* image, sepw_c64* vis_out,
       {
         Stage st(SEPW_STAGE_CORRECT, s);
         SEPW_TRY(launch_slice_phase(reinterpret_cast<const float2*>(image), ws->img, K->N, K->fov,
-                                    ws->centre[j], -1, false, s));
+                                    ws->centre[j], -1, false, nullptr, 0, s));
       }
       int rc = sepw_degrid(static_cast<sepw_plan_s*>(ws->plans[j]),
                            reinterpret_cast<const sepw_c64*>(ws->img),
@@ -2053,8 +2080,8 @@ int sepw_wstack_degrid(sepw_wstack ws, const sepw_c64* image, sepw_c64* vis_out,
       if (rc != SEPW_OK) return rc;
     }
   } else {
-    // FP32: per slice the phase correction into its own image, then the
-    // slices' degridding in batches of up to nimg
+    // FP32: per slice one pass for the slice phase and the correction into
+    // its own image, then the slices' degridding in batches of up to nimg
     const int64_t nn = (int64_t)K->N * K->N;
     const int npow = (flags & SEPW_DIV_N) ? -1 : 0;
     std::vector<Plan*> plans;
@@ -2067,13 +2094,13 @@ int sepw_wstack_degrid(sepw_wstack ws, const sepw_c64* image, sepw_c64* vis_out,
         Stage st(SEPW_STAGE_CORRECT, s);
         SEPW_TRY(launch_slice_phase(reinterpret_cast<const float2*>(image),
                                     ws->img + (int64_t)plans.size() * nn, K->N, K->fov,
-                                    ws->centre[j0], -1, false, s));
+                                    ws->centre[j0], -1, false, K->c1, npow, s));
         plans.push_back(ws->plans[j0]);
         outs.push_back(ws->vis + ws->off[j0]);
       }
       if (plans.empty()) break;
       int rc = degrid_images_batched(K, plans.data(), (int)plans.size(), ws->img, npow,
-                                     outs.data(), s);
+                                     outs.data(), s, true);
       if (rc != SEPW_OK) return rc;
     }
   }

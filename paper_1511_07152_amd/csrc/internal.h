@@ -332,9 +332,11 @@ hipError_t launch_slice_gather(const float2* vis, const float* weight, const uin
                                int64_t nvis, float2* out, hipStream_t s);
 hipError_t launch_slice_return(const float2* in, const uint32_t* order, int64_t nvis, float2* out,
                                hipStream_t s);
-// out (+)= in exp(sign 2 pi i w_s (n - 1)) over the N x N pixels
+// out (+)= in exp(sign 2 pi i w_s (n - 1)) over the N x N pixels, times the
+// image correction (-1)^(p+q) n^npow / (c1[p] c1[q]) when c1 is not null
 hipError_t launch_slice_phase(const float2* in, float2* out, int N, double fov, double w_s,
-                              int sign, bool accumulate, hipStream_t s);
+                              int sign, bool accumulate, const double* c1, int npow,
+                              hipStream_t s);
 
 // W snapshots (wsnap.hip): plane fit and residual w, reprojection and its transpose
 hipError_t launch_snap_fit(const double* u, const double* v, const double* w, const int64_t* range,

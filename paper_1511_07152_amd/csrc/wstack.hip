@@ -125,8 +125,12 @@ __global__ void slice_return_kernel(const float2* __restrict__ in, const uint32_
 }
 
 // out = in exp(sign 2 pi i w_s (n - 1)) (accumulate: out += ...)
+// With c1, the pass also applies the image correction of the separable path
+// (the centred transform's (-1)^(p+q), n^npow and 1 / (c1[p] c1[q])), formed
+// in FP64 with the phase.
 __global__ void slice_phase_kernel(const float2* __restrict__ in, float2* __restrict__ out, int N,
-                                   double fov, double w_s, int sign, int accumulate) {
+                                   double fov, double w_s, int sign, int accumulate,
+                                   const double* __restrict__ c1, int npow) {
   const int64_t total = (int64_t)N * N;
   const double step = fov / (double)N;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
@@ -141,6 +145,13 @@ __global__ void slice_phase_kernel(const float2* __restrict__ in, float2* __rest
     const double frac = cyc - rint(cyc);
     double sn, cs;
     sincospi(2.0 * (double)sign * frac, &sn, &cs);
+    if (c1) {
+      double f = 1.0 / (c1[p] * c1[q]);
+      if (npow != 0) f = npow > 0 ? f * n : f / n;
+      if ((p + q) & 1) f = -f;
+      sn *= f;
+      cs *= f;
+    }
     const float2 a = in[i];
     const float re = (float)(a.x * cs - a.y * sn), im = (float)(a.x * sn + a.y * cs);
     if (accumulate) {
@@ -222,9 +233,10 @@ hipError_t launch_slice_return(const float2* in, const uint32_t* order, int64_t 
 }
 
 hipError_t launch_slice_phase(const float2* in, float2* out, int N, double fov, double w_s,
-                              int sign, bool accumulate, hipStream_t s) {
+                              int sign, bool accumulate, const double* c1, int npow,
+                              hipStream_t s) {
   hipLaunchKernelGGL(slice_phase_kernel, grid_for((int64_t)N * N), dim3(kThreads), 0, s, in, out, N,
-                     fov, w_s, sign, accumulate ? 1 : 0);
+                     fov, w_s, sign, accumulate ? 1 : 0, c1, npow);
   return hipGetLastError();
 }
 
