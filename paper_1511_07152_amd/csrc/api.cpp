@@ -2237,7 +2237,7 @@ int sepw_wsnap_degrid(sepw_wsnap ws, const sepw_c64* image, sepw_c64* vis_out, u
         Stage st(SEPW_STAGE_CORRECT, s);
         SEPW_TRY(launch_snap_reproject_adjoint(reinterpret_cast<const float2*>(image), ws->img, N,
                                                K->fov, ws->d0[2 * (size_t)i],
-                                               ws->d0[2 * (size_t)i + 1], npow, s));
+                                               ws->d0[2 * (size_t)i + 1], npow, nullptr, s));
       }
       int rc = sepw_degrid(static_cast<sepw_plan>(p), reinterpret_cast<const sepw_c64*>(ws->img),
                            vis_out + ws->off[i], 0u, hip_stream);
@@ -2245,8 +2245,9 @@ int sepw_wsnap_degrid(sepw_wsnap ws, const sepw_c64* image, sepw_c64* vis_out, u
     }
     return SEPW_OK;
   }
-  // FP32: per snapshot the transposed reprojection into its own image, then
-  // the snapshots' degridding in batches of up to nimg
+  // FP32: per snapshot the transposed reprojection into its own image (with
+  // the image correction in the same pass), then the snapshots' degridding in
+  // batches of up to nimg
   std::vector<int> idx;
   std::vector<Plan*> plans;
   std::vector<float2*> outs;
@@ -2263,11 +2264,12 @@ int sepw_wsnap_degrid(sepw_wsnap ws, const sepw_c64* image, sepw_c64* vis_out, u
       SEPW_TRY(launch_snap_reproject_adjoint(reinterpret_cast<const float2*>(image),
                                              ws->img + (int64_t)j * N * N, N, K->fov,
                                              ws->d0[2 * (size_t)i], ws->d0[2 * (size_t)i + 1],
-                                             npow, s));
+                                             npow, K->c1, s));
       plans.push_back(ws->plans[i]);
       outs.push_back(reinterpret_cast<float2*>(vis_out + ws->off[i]));
     }
-    int rc = degrid_images_batched(K, plans.data(), (int)idx.size(), ws->img, 0, outs.data(), s);
+    int rc = degrid_images_batched(K, plans.data(), (int)idx.size(), ws->img, 0, outs.data(), s,
+                                   true);
     if (rc != SEPW_OK) return rc;
   }
   return SEPW_OK;

@@ -344,9 +344,11 @@ hipError_t launch_snap_fit(const double* u, const double* v, const double* w, co
                            double2* d0, double* wr, unsigned long long* maxbits, hipStream_t s);
 hipError_t launch_snap_reproject(const float2* in, float2* out, int N, double fov, double du,
                                  double dv, bool accumulate, hipStream_t s);
-// out = the transposed reprojection of X n^npow (written in full)
+// out = the transposed reprojection of X n^npow (written in full), then,
+// when c1 is not null, times the image correction before the FFT,
+// (-1)^(p+q) / (c1[p] c1[q])
 hipError_t launch_snap_reproject_adjoint(const float2* X, float2* out, int N, double fov, double du,
-                                         double dv, int npow, hipStream_t s);
+                                         double dv, int npow, const double* c1, hipStream_t s);
 hipError_t launch_snap_npow(float2* out, int N, double fov, int npow, hipStream_t s);
 
 // *out = nvis - *kept, one thread

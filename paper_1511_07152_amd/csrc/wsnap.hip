@@ -257,7 +257,7 @@ __device__ inline void warp_at(double p, double q, int N, double fov, double du,
 
 __global__ __launch_bounds__(kGTile * kGTile) void snap_adjoint_gather_kernel(
     const float2* __restrict__ X, float2* __restrict__ out, int N, double fov, double du, double dv,
-    int npow) {
+    int npow, const double* __restrict__ c1) {
   __shared__ double sx[kGBox * kGBox], sy[kGBox * kGBox];
   __shared__ float2 sv[kGBox * kGBox];
   const int tx0 = blockIdx.x * kGTile, ty0 = blockIdx.y * kGTile;
@@ -319,6 +319,14 @@ __global__ __launch_bounds__(kGTile * kGTile) void snap_adjoint_gather_kernel(
       }
     }
   }
+  if (c1) {
+    // the snapshot image's correction before its FFT, as the separate pass
+    // would apply it: (-1)^(p+q) / (c1[p] c1[q]) in FP64
+    double f = 1.0 / (c1[jx] * c1[jy]);
+    if ((jx + jy) & 1) f = -f;
+    ar = (float)(ar * f);
+    ai = (float)(ai * f);
+  }
   out[(int64_t)jy * N + jx] = make_float2(ar, ai);
 }
 
@@ -365,19 +373,22 @@ hipError_t launch_snap_reproject(const float2* in, float2* out, int N, double fo
 }
 
 hipError_t launch_snap_reproject_adjoint(const float2* X, float2* out, int N, double fov, double du,
-                                         double dv, int npow, hipStream_t s) {
+                                         double dv, int npow, const double* c1, hipStream_t s) {
   // bound on the warp's deviation from the identity: max |d| (|l| + |m|) / n
   // over the image, |l|, |m| <= fov / 2
   const double eps = std::max(std::fabs(du), std::fabs(dv)) * fov / std::sqrt(1.0 - 0.5 * fov * fov);
   if (eps <= 0.1) {
     const unsigned nt = (unsigned)((N + kGTile - 1) / kGTile);
     hipLaunchKernelGGL(snap_adjoint_gather_kernel, dim3(nt, nt), dim3(kGTile * kGTile), 0, s, X, out,
-                       N, fov, du, dv, npow);
+                       N, fov, du, dv, npow, c1);
   } else {
     hipError_t e = launch_zero_c64(out, (int64_t)N * N, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(snap_reproject_adjoint_kernel, grid_for((int64_t)N * N), dim3(kThreads), 0, s,
                        X, out, N, fov, du, dv, npow);
+    e = hipGetLastError();
+    if (e == hipSuccess && c1) e = launch_correct(out, out, c1, N, fov, 0.0, 0.0, 0, s);
+    return e;
   }
   return hipGetLastError();
 }
