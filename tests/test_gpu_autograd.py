@@ -60,7 +60,7 @@ def test_gradient_matches_oracle_adjoint(mods):
     inner = (slice(N // 4, 3 * N // 4),) * 2
     err = np.linalg.norm((got - want)[inner]) / np.linalg.norm(want[inner])
     assert err <= 1e-5
-    assert float(loss) == pytest.approx(oracle.chi2.chi2(op, d["x"], d["Vt"], d["W"]), rel=1e-5)
+    assert float(loss.detach()) == pytest.approx(oracle.chi2.chi2(op, d["x"], d["Vt"], d["W"]), rel=1e-5)
 
 
 def test_gradient_matches_central_differences(mods):
