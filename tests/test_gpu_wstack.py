@@ -250,3 +250,23 @@ def test_wstack_with_correction_equals_its_slices(lib):
     bare = lib.WStack(K, ns, -wmax, wmax, dev(u, torch.float64), dev(v, torch.float64),
                       dev(w, torch.float64)).degrid(dev(X, torch.complex64), flags=lib.DIV_N)
     assert rel_rms(bare.cpu().numpy(), Vs) > 1e-3
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_nonuniform_slices_in_16bit(lib, precision):
+    # slice tables of the 16-bit forms (they use the caller kernels' operand
+    # grid, FFT plan and work grid): within the 16-bit bound of the oracle
+    rng, d = _case(90)
+    K, ws = _make_edges(lib, d, EDGES, precision=precision)
+    img = ws.grid(dev(d["V"], torch.complex64), dev(d["W"], torch.float32), flags=lib.MUL_N)
+    want = oracle.wstack.image(d["u"], d["v"], d["w"], d["V"] * d["W"], *_args_edges(d, EDGES),
+                               n_power=1, edges=EDGES)
+    assert rel_rms(inner(img.cpu().numpy()), inner(want)) <= 3e-3
+    N = d["N"]
+    X = np.zeros((N, N), complex)
+    s = slice(N // 4, 3 * N // 4)
+    X[s, s] = rng.standard_normal((N // 2, N // 2)) + 1j * rng.standard_normal((N // 2, N // 2))
+    V = ws.degrid(dev(X, torch.complex64), flags=lib.DIV_N).cpu().numpy()
+    wantv = oracle.wstack.predict(d["u"], d["v"], d["w"], X, *_args_edges(d, EDGES), n_power=-1,
+                                  edges=EDGES)
+    assert rel_rms(V, wantv) <= 3e-3
