@@ -132,3 +132,21 @@ def test_wsnap_argument_checks(lib):
         ws.grid(dev(d["V"], torch.complex64), flags=lib.GRID_ONLY)
     with pytest.raises(lib.SepwError):
         ws.degrid(torch.zeros((d["N"], d["N"]), dtype=torch.complex64, device="cuda"), flags=lib.MUL_N)
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_wsnap_in_16bit(lib, precision):
+    # the 16-bit forms go snapshot by snapshot through the single-plan calls
+    # (the transposed reprojection, then the 16-bit degridder's operand grid)
+    rng, d = _case(77, **GEOMETRIES["gather"])
+    K = lib.Kernels(d["N"], d["fov"], d["S"], d["O"], d["P"], -1.0, 1.0, precision=precision)
+    ws = lib.WSnap(K, d["offs"], dev(d["u"], torch.float64), dev(d["v"], torch.float64),
+                   dev(d["w"], torch.float64))
+    img = ws.grid(dev(d["V"], torch.complex64), dev(d["W"], torch.float32)).cpu().numpy()
+    want = oracle.wsnap.image(d["u"], d["v"], d["w"], d["V"] * d["W"], *_args(d))
+    assert rel_rms(inner(img), inner(want)) <= 3e-3
+    N = d["N"]
+    X = np.zeros((N, N), complex)
+    X[N // 4:3 * N // 4, N // 4:3 * N // 4] = rng.standard_normal((N // 2, N // 2))
+    V = ws.degrid(dev(X, torch.complex64), flags=lib.DIV_N).cpu().numpy()
+    assert rel_rms(V, oracle.wsnap.predict(d["u"], d["v"], d["w"], X, *_args(d), n_power=-1)) <= 3e-3
