@@ -649,9 +649,13 @@ def main():
             # errors of this step's outputs relative to the FP32 step's, on
             # the same array-scale data (FP32 is within 1e-6 of the FP64
             # reference there, so these are the 16-bit forms' own errors)
+            g_ms = st["grid"][0] / max(st["grid"][1], 1)
+            d_ms = st["degrid"][0] / max(st["degrid"][1], 1)
             forms[prec] = {"value": round(nvis / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 3),
-                           "grid_ms": round(st["grid"][0] / max(st["grid"][1], 1), 4),
-                           "degrid_ms": round(st["degrid"][0] / max(st["degrid"][1], 1), 4),
+                           "grid_ms": round(g_ms, 4), "degrid_ms": round(d_ms, 4),
+                           # grid + degrid kernel time of the FP32 step over this form's
+                           "kernels_speedup_vs_fp32": round(
+                               (per_launch["grid"] + per_launch["degrid"]) / (g_ms + d_ms), 3),
                            "rel_rms_err_vs_fp32": {
                                "image_inner_half": rel_diff(torch, img, ref_img, inner=True),
                                "image_full": rel_diff(torch, img, ref_img),
